@@ -1,0 +1,44 @@
+"""Gate matrices used by the oracle (its own table; the HIP path has another).
+
+Matrix convention: U[row][col] = <row|U|col>, i.e. psi_U(b', b) = U[b'][b] in
+the notation of Sec. III.B (row = the bit after the gate).
+
+* H: psi_H(1,1) = -1/sqrt(2), other entries +1/sqrt(2) (Sec. III.B and the
+  Hadamard table of App. D).
+* T = diag(1, e^{i pi/4}) (Sec. II, gate list).
+* X^1/2, Y^1/2: pi/2 rotations about X and Y (Sec. II).  The paper fixes them
+  only up to a global phase; App. F, Eq. (phX) fixes the relative phases
+  (no-flip/flip ratio i for X^1/2; only <0|Y^1/2|1> negative).  The reading
+  used here is RX(pi/2) = (1/sqrt2)[[1,-i],[-i,1]] and
+  RY(pi/2) = (1/sqrt2)[[1,-1],[1,1]].
+* CZ = diag(1,1,1,-1): psi_CZ(1,1) = -1, others 1 (Sec. III.B, App. D table).
+* U / UD: the value is read from gate_vals[slot].
+"""
+import numpy as np
+
+KIND_H, KIND_T, KIND_XH, KIND_YH, KIND_CZ, KIND_U, KIND_UD = 0, 1, 2, 3, 4, 5, 6
+
+_R2 = 1.0 / np.sqrt(2.0)
+_FIXED = {
+    KIND_H: np.array([[_R2, _R2], [_R2, -_R2]], dtype=np.complex128),
+    KIND_T: np.array([[1, 0], [0, np.exp(1j * np.pi / 4)]], dtype=np.complex128),
+    KIND_XH: np.array([[_R2, -1j * _R2], [-1j * _R2, _R2]], dtype=np.complex128),
+    KIND_YH: np.array([[_R2, -_R2], [_R2, _R2]], dtype=np.complex128),
+}
+
+
+def gate_matrix(kind: int, slot: int, gate_vals) -> np.ndarray:
+    """2x2 complex128 matrix of a single-qubit gate."""
+    kind = int(kind)
+    if kind in _FIXED:
+        return _FIXED[kind].copy()
+    if kind in (KIND_U, KIND_UD):
+        m = np.asarray(gate_vals[int(slot)], dtype=np.complex128).reshape(2, 2)
+        if kind == KIND_UD:
+            m = np.diag(np.diag(m))
+        return m.copy()
+    raise ValueError(f"gate kind {kind} is not a single-qubit gate")
+
+
+def is_diagonal_kind(kind: int) -> bool:
+    return int(kind) in (KIND_T, KIND_CZ, KIND_UD)

@@ -1,0 +1,158 @@
+/*
+ * qgm.h -- C ABI of the MI355X amplitude engine for random grid circuits
+ * viewed as complex undirected graphical models (arXiv:1712.05384).
+ *
+ * The library computes output amplitudes <x|U|0...0> of a circuit built from
+ * single-qubit gates and CZ gates (Sec. III.A, Eq. (fpath)), for a batch of
+ * output bitstrings x, by variable elimination on the graphical model of
+ * Sec. III.B (Eq. (psi_x)): one Boolean variable per qubit per non-diagonal
+ * gate, complex factors per gate, eliminated in the vertical (worldline by
+ * worldline) order of Sec. IV.A.  Leaving some output deltas out of Eq. (psi_x)
+ * gives sets of amplitudes at once (the "open" qubits below).
+ *
+ * Conventions (all entry points)
+ *  - Qubit (r, c) of a rows x cols lattice has index q = r*cols + c; n <= 64.
+ *  - A bitstring is a uint64_t whose bit q is the output bit of qubit q.  Bits
+ *    at positions >= n and bits on open qubits are ignored.
+ *  - Complex numbers are interleaved (re, im): complex64 = 2 floats,
+ *    complex128 = 2 doubles.  A 2x2 gate matrix is stored row-major with
+ *    element [row][col] = <row|U|col> (row = the state after the gate).
+ *  - Every entry point returns a qgm_status; on failure qgm_last_error()
+ *    returns a message (thread-local, valid until the next call on the same
+ *    thread).  Arguments are validated before anything is launched.
+ *  - Device pointers are HIP device pointers on the current device; `stream`
+ *    is a hipStream_t passed as void* (NULL = the default stream).  All device
+ *    work is enqueued asynchronously on that stream; HIP errors raised by the
+ *    kernels surface as QGM_E_HIP at the next call or at qgm_sync_check().
+ *  - The caller owns every buffer passed in; the library never frees them and
+ *    never allocates device memory on the amplitude path except the one-time
+ *    per-device upload of a plan's constant tables (see qgm_amplitudes).
+ */
+#ifndef QGM_API_H_
+#define QGM_API_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QGM_OK = 0,
+    QGM_E_INVALID = -1,      /* malformed circuit, options or arguments */
+    QGM_E_UNSUPPORTED = -2,  /* valid input outside what the kernels handle */
+    QGM_E_OOM = -3,          /* plan cannot fit the memory budget / workspace too small */
+    QGM_E_HIP = -4,          /* a HIP runtime call failed */
+    QGM_E_INTERNAL = -5
+} qgm_status;
+
+/* Gate kinds (Sec. II: H, X^1/2, Y^1/2, T, CZ; plus value-slot gates).
+ *  QGM_H  = (1/sqrt2)[[1,1],[1,-1]]              (table of App. D)
+ *  QGM_T  = diag(1, e^{i pi/4})                   (Sec. II)
+ *  QGM_XH = RX(pi/2) = (1/sqrt2)[[1,-i],[-i,1]]   (Sec. II; phases of App. F Eq. (phX))
+ *  QGM_YH = RY(pi/2) = (1/sqrt2)[[1,-1],[1,1]]    (Sec. II; phases of App. F Eq. (phX))
+ *  QGM_CZ = diag(1,1,1,-1) on (q0, q1)            (Sec. III.B)
+ *  QGM_U  = general 2x2 read from gate_vals[slot]; non-diagonal, so it opens a
+ *           new worldline variable (Sec. III.A)
+ *  QGM_UD = diagonal 2x2 read from the diagonal of gate_vals[slot]; like T it
+ *           adds no variable (Sec. III.A) */
+typedef enum { QGM_H = 0, QGM_T = 1, QGM_XH = 2, QGM_YH = 3, QGM_CZ = 4, QGM_U = 5, QGM_UD = 6 } qgm_kind;
+
+typedef struct {
+    int32_t kind;    /* qgm_kind */
+    int32_t cycle;   /* clock cycle >= 0; gates apply in (cycle, list index) order */
+    int32_t q0;      /* qubit */
+    int32_t q1;      /* second qubit of a CZ, -1 otherwise */
+    int32_t slot;    /* index into gate_vals for QGM_U / QGM_UD, -1 otherwise */
+} qgm_gate;
+
+typedef struct {
+    int32_t rows, cols;      /* lattice; n = rows*cols qubits, 1 <= n <= 64 */
+    int32_t n_gates;
+    int32_t n_slots;         /* number of 2x2 values gate_vals must hold */
+    const qgm_gate* gates;   /* host array [n_gates]; a qubit is used at most once per cycle */
+} qgm_circuit;
+
+typedef struct {
+    int32_t ordering;          /* 0 = vertical order of Sec. IV.A (qubits along the shorter side first) */
+    int32_t precision;         /* 0 = complex64 with FP32 arithmetic */
+    int32_t max_group_bits;    /* reserved, 0 */
+    int32_t min_sliced_vars;   /* slice at least this many variables (Sec. V outlook: space-time tradeoffs) */
+    int32_t out_c128;          /* 1: amplitudes are written as complex128, 0: complex64 */
+    int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor has rank <= max_rank */
+    int32_t reserved[2];
+} qgm_plan_opts;
+
+typedef struct qgm_plan_s qgm_plan_t;
+
+/* Fills *opts with the defaults (all zero: vertical order, complex64 out). */
+void qgm_default_opts(qgm_plan_opts* opts);
+
+/* Builds a contraction plan on the host (no device call).  The plan depends on
+ * which gates are diagonal and on the open qubits, not on gate values or
+ * bitstrings, so one plan serves any batch of bitstrings and any gate_vals.
+ *  open_qubits: host array [n_open] of distinct qubits whose output bit is left
+ *               free (the delta of Eq. (psi_x) omitted); output index bit i
+ *               corresponds to open_qubits[i].  May be NULL when n_open = 0.
+ *  opts:        may be NULL for the defaults.
+ *  *out:        receives the plan; free it with qgm_plan_destroy.
+ * Errors: QGM_E_INVALID for a malformed circuit (qubit out of range, CZ with
+ * q0 == q1, a qubit used twice in one cycle, unknown kind, slot out of range),
+ * duplicate or out-of-range open qubits; QGM_E_UNSUPPORTED when a step would
+ * exceed the kernels' limits. */
+qgm_status qgm_plan(const qgm_circuit* circuit, const int32_t* open_qubits, int32_t n_open,
+                    const qgm_plan_opts* opts, qgm_plan_t** out);
+
+/* Writes a JSON description of the plan into json[0..cap) (NUL-terminated) and
+ * the size it needs (including the NUL) into *needed (may be NULL).  detail 0:
+ * summary and per-step sizes; detail 1: also the axis layouts and the factor
+ * programs of every step.  Returns QGM_E_INVALID if cap is too small (json may
+ * be NULL to query the size). */
+qgm_status qgm_plan_info(const qgm_plan_t* plan, int32_t detail, char* json, size_t cap, size_t* needed);
+
+/* Device workspace (bytes) that qgm_amplitudes needs for a batch of B bitstrings. */
+qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);
+
+/* Computes out[b][o] = <x_b with the open bits set to o | U | 0...0> for
+ * b < B and o < 2^n_open (Eq. (psi_x) with the deltas of the open qubits
+ * left out), by the plan's elimination steps on the device.
+ *  gate_vals: device complex64 [n_slots][2][2]; may be NULL when n_slots = 0.
+ *  bits:      device uint64 [B].
+ *  out:       device complex64 or complex128 (opts.out_c128) [B][2^n_open].
+ *  workspace: device buffer of at least qgm_workspace_bytes(plan, B) bytes,
+ *             256-byte aligned; its contents are scratch.
+ * The first call of a plan on a device uploads the plan's constant tables
+ * (a synchronous hipMalloc + hipMemcpy, kept until qgm_plan_destroy).
+ * Sums over sliced variables are done in FP64.  Calls that share a workspace
+ * must be ordered on one stream. */
+qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
+                          void* out, void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Per-phase timing of qgm_amplitudes (hipEvents recorded on the call's
+ * stream; instrumentation for the benchmark, off by default).  enable = 1
+ * starts recording and clears the totals; 0 stops.  While enabled each call
+ * records 5 events: before the boundary kernel, after it, after the G
+ * builder, after the last elimination step, after the output stage. */
+qgm_status qgm_plan_set_timing(qgm_plan_t* plan, int32_t enable);
+
+/* Synchronises the recorded events and returns the accumulated times (ms) of
+ * the phases [0] boundary, [1] G build, [2] elimination steps, [3] output
+ * stage into ms[4], and the number of timed calls into *n_calls.  The step
+ * phase holds n_steps kernel launches per call. */
+qgm_status qgm_plan_timings(qgm_plan_t* plan, double* ms, int64_t* n_calls);
+
+/* Destroys a plan and frees its device tables (NULL is ignored). */
+void qgm_plan_destroy(qgm_plan_t* plan);
+
+/* Last error message of the calling thread ("" if none). */
+const char* qgm_last_error(void);
+
+/* Synchronises `stream` and reports any pending HIP error as QGM_E_HIP. */
+qgm_status qgm_sync_check(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QGM_API_H_ */

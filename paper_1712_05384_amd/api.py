@@ -1,0 +1,128 @@
+"""Python binding of the C ABI (argument marshalling only; every step of the
+amplitude path runs in the HIP kernels of libqgm.so)."""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import numpy as np
+
+from . import _native as N
+
+
+def _circuit_struct(rows: int, cols: int, gates: np.ndarray, n_slots: int):
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 5))
+    arr = (N.QgmGate * max(1, len(g)))()
+    ctypes.memmove(arr, g.ctypes.data, g.nbytes)
+    c = N.QgmCircuit(rows, cols, len(g), n_slots, ctypes.cast(arr, ctypes.POINTER(N.QgmGate)))
+    return c, arr
+
+
+class Plan:
+    """A contraction plan (qgm_plan).  `circuit` is anything with rows, cols,
+    gates (int32 [n_gates, 5]: kind, cycle, q0, q1, slot) and n_slots."""
+
+    def __init__(self, circuit, open_qubits=(), *, min_sliced_vars: int = 0, max_rank: int = 0,
+                 out_c128: bool = False):
+        L = N.lib()
+        self._lib = L
+        self._h = None
+        self.n = int(circuit.rows * circuit.cols)
+        self.n_slots = int(getattr(circuit, "n_slots", 0))
+        self.open_qubits = [int(q) for q in open_qubits]
+        self.out_c128 = bool(out_c128)
+        cs, self._keep = _circuit_struct(circuit.rows, circuit.cols, circuit.gates, self.n_slots)
+        opts = N.QgmPlanOpts()
+        L.qgm_default_opts(ctypes.byref(opts))
+        opts.min_sliced_vars = int(min_sliced_vars)
+        opts.max_rank = int(max_rank)
+        opts.out_c128 = 1 if out_c128 else 0
+        op = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
+        h = ctypes.c_void_p()
+        N.check(L.qgm_plan(ctypes.byref(cs), op, len(self.open_qubits), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def info(self, detail: int = 0) -> dict:
+        need = ctypes.c_size_t()
+        self._lib.qgm_plan_info(self._h, detail, None, 0, ctypes.byref(need))
+        buf = ctypes.create_string_buffer(need.value)
+        N.check(self._lib.qgm_plan_info(self._h, detail, buf, need.value, None))
+        return json.loads(buf.value.decode())
+
+    def workspace_bytes(self, B: int) -> int:
+        out = ctypes.c_uint64()
+        N.check(self._lib.qgm_workspace_bytes(self._h, int(B), ctypes.byref(out)))
+        return int(out.value)
+
+    def amplitudes(self, bits, gate_vals=None, *, out=None, workspace=None, stream=None):
+        """Amplitudes for a batch of bitstrings on the current CUDA/HIP device.
+
+        bits: torch tensor (int64 or uint64 bit patterns) or numpy uint64 array.
+        gate_vals: complex64 tensor [n_slots, 2, 2] (moved to the device), or None.
+        Returns complex64 (or complex128) tensor [B, 2^n_open]."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if isinstance(bits, np.ndarray):
+            bits = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint64).view(np.int64))
+        if bits.dtype not in (torch.int64, torch.uint64):
+            raise TypeError("bits must be a 64-bit integer tensor")
+        bits = bits.to(dev).contiguous()
+        B = int(bits.shape[0])
+        n_out = 1 << len(self.open_qubits)
+        odt = torch.complex128 if self.out_c128 else torch.complex64
+        if out is None:
+            out = torch.empty((B, n_out), dtype=odt, device=dev)
+        elif out.dtype != odt or tuple(out.shape) != (B, n_out) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, shape or layout")
+        gv = None
+        if self.n_slots:
+            if gate_vals is None:
+                raise ValueError("this circuit reads gate_vals")
+            gv = torch.as_tensor(gate_vals).to(dev, torch.complex64).contiguous()
+            if tuple(gv.shape) != (self.n_slots, 2, 2):
+                raise ValueError("gate_vals must be [n_slots, 2, 2]")
+        need = self.workspace_bytes(B)
+        if workspace is None:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        if workspace.numel() < need:
+            raise ValueError("workspace too small")
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self._lib.qgm_amplitudes(self._h, None if gv is None else gv.data_ptr(), bits.data_ptr(), B,
+                                         out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                         ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def set_timing(self, enable: bool) -> None:
+        N.check(self._lib.qgm_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timings(self) -> tuple[list[float], int]:
+        """Accumulated ms of [boundary, G build, elimination steps, output] and the call count."""
+        ms = (ctypes.c_double * 4)()
+        n = ctypes.c_int64()
+        N.check(self._lib.qgm_plan_timings(self._h, ms, ctypes.byref(n)))
+        return list(ms), int(n.value)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.qgm_plan_destroy(self._h)
+            self._h = None
+
+
+def plan(circuit, open_qubits=(), **opts) -> Plan:
+    return Plan(circuit, open_qubits, **opts)
+
+
+def amplitudes(p: Plan, bits, gate_vals=None, **kw):
+    return p.amplitudes(bits, gate_vals, **kw)
+
+
+def sync_check(stream=None) -> None:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    N.check(N.lib().qgm_sync_check(ctypes.c_void_p(stream.cuda_stream)))

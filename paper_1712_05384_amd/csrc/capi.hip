@@ -1,0 +1,289 @@
+// C ABI of libqgm: plan construction (host), device table upload, and the
+// amplitude executor that enqueues the step kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "qgm.h"
+
+struct qgm_plan_s {
+    qgm::Plan p;
+    uint32_t max_g_entries = 0;
+    // offsets (bytes) of the constant tables inside each device copy
+    size_t off_fixed = 0, off_steps = 0, off_ops = 0, off_sig = 0, off_final = 0, total = 0;
+    // optional per-phase timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;   // 5 per timed call
+    size_t events_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+qgm_status fail(qgm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+qgm_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return QGM_E_HIP;
+}
+
+// The fixed single-qubit gates of Sec. II, row = the state after the gate.
+// H: the table of App. D; T = diag(1, e^{i pi/4}); X^1/2 = RX(pi/2) and
+// Y^1/2 = RY(pi/2), whose relative phases are those of App. F, Eq. (phX).
+void fixed_matrices(double2 m[qgm::kFixedMats * 4]) {
+    const double r = 1.0 / std::sqrt(2.0);
+    const double2 H[4] = {{r, 0}, {r, 0}, {r, 0}, {-r, 0}};
+    const double2 T[4] = {{1, 0}, {0, 0}, {0, 0}, {std::cos(M_PI / 4), std::sin(M_PI / 4)}};
+    const double2 X[4] = {{r, 0}, {0, -r}, {0, -r}, {r, 0}};
+    const double2 Y[4] = {{r, 0}, {-r, 0}, {r, 0}, {r, 0}};
+    for (int i = 0; i < 4; ++i) {
+        m[0 * 4 + i] = H[i];
+        m[1 * 4 + i] = T[i];
+        m[2 * 4 + i] = X[i];
+        m[3 * 4 + i] = Y[i];
+    }
+}
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+void layout_tables(qgm_plan_t* P) {
+    const qgm::Plan& p = P->p;
+    size_t n_sig = 0;
+    for (auto& st : p.steps) n_sig += st.sig_src.size();
+    P->off_fixed = 0;
+    P->off_steps = al(sizeof(double2) * qgm::kFixedMats * 4);
+    P->off_ops = P->off_steps + al(sizeof(qgm::StepTab) * p.steps.size());
+    P->off_sig = P->off_ops + al(sizeof(qgm::GOp) * size_t(p.n_ops_total));
+    P->off_final = P->off_sig + al(sizeof(int32_t) * (n_sig + 1));
+    P->total = P->off_final + al(sizeof(int32_t) * (p.final_pos.size() + 1));
+    P->max_g_entries = 0;
+    for (auto& st : p.steps) P->max_g_entries = std::max<uint32_t>(P->max_g_entries, uint32_t(st.g_entries()));
+}
+
+// Returns the device copy of the plan's constant tables for the current
+// device, uploading it on first use.
+qgm_status device_tables(qgm_plan_t* P, char** base) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (auto& d : P->p.dev)
+        if (d.device == dev) { *base = static_cast<char*>(d.base); return QGM_OK; }
+    const qgm::Plan& p = P->p;
+    std::string host(P->total, '\0');
+    char* h = &host[0];
+    fixed_matrices(reinterpret_cast<double2*>(h + P->off_fixed));
+    auto* tabs = reinterpret_cast<qgm::StepTab*>(h + P->off_steps);
+    auto* ops = reinterpret_cast<qgm::GOp*>(h + P->off_ops);
+    auto* sig = reinterpret_cast<int32_t*>(h + P->off_sig);
+    auto* fin = reinterpret_cast<int32_t*>(h + P->off_final);
+    int32_t ops_off = 0, sig_off = 0;
+    for (size_t s = 0; s < p.steps.size(); ++s) {
+        const qgm::Step& st = p.steps[s];
+        qgm::StepTab t{};
+        t.vb = st.vb; t.kb = st.kb; t.nb = st.nb; t.sb = st.sb;
+        t.ops_off = ops_off; t.n_ops = int32_t(st.ops.size());
+        t.sig_off = sig_off; t.g_off = st.g_off;
+        tabs[s] = t;
+        for (auto& op : st.ops) ops[ops_off++] = op;
+        for (int x : st.sig_src) sig[sig_off++] = x;
+    }
+    for (size_t i = 0; i < p.final_pos.size(); ++i) fin[i] = p.final_pos[i];
+    void* d = nullptr;
+    e = hipMalloc(&d, P->total);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
+    e = hipMemcpy(d, h, P->total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "hipMemcpy(plan tables)"); }
+    P->p.dev.push_back({dev, d});
+    *base = static_cast<char*>(d);
+    return QGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qgm_default_opts(qgm_plan_opts* opts) {
+    if (opts) std::memset(opts, 0, sizeof *opts);
+}
+
+qgm_status qgm_plan(const qgm_circuit* circuit, const int32_t* open_qubits, int32_t n_open,
+                    const qgm_plan_opts* opts_in, qgm_plan_t** out) {
+    g_err.clear();
+    if (!out) return fail(QGM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    qgm_plan_opts opts;
+    qgm_default_opts(&opts);
+    if (opts_in) opts = *opts_in;
+    auto* P = new (std::nothrow) qgm_plan_t;
+    if (!P) return fail(QGM_E_OOM, "out of host memory");
+    std::string err;
+    qgm_status st;
+    try {
+        st = qgm::build_plan(circuit, open_qubits, n_open, opts, P->p, &err);
+    } catch (const std::bad_alloc&) {
+        st = QGM_E_OOM;
+        err = "out of host memory while planning";
+    } catch (...) {
+        st = QGM_E_INTERNAL;
+        err = "unexpected exception while planning";
+    }
+    if (st != QGM_OK) {
+        delete P;
+        return fail(st, err);
+    }
+    layout_tables(P);
+    *out = P;
+    return QGM_OK;
+}
+
+qgm_status qgm_plan_info(const qgm_plan_t* plan, int32_t detail, char* json, size_t cap, size_t* needed) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    std::string s;
+    try {
+        s = qgm::plan_json(plan->p, detail);
+    } catch (...) {
+        return fail(QGM_E_OOM, "out of host memory");
+    }
+    if (needed) *needed = s.size() + 1;
+    if (!json || cap < s.size() + 1) return fail(QGM_E_INVALID, "buffer too small");
+    std::memcpy(json, s.c_str(), s.size() + 1);
+    return QGM_OK;
+}
+
+qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes) {
+    g_err.clear();
+    if (!plan || !bytes) return fail(QGM_E_INVALID, "plan or bytes is NULL");
+    if (B < 0) return fail(QGM_E_INVALID, "B < 0");
+    *bytes = qgm::workspace_layout(plan->p, B).total;
+    return QGM_OK;
+}
+
+qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
+                          void* workspace, uint64_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    if (B < 0) return fail(QGM_E_INVALID, "B < 0");
+    if (B == 0) return QGM_OK;
+    const qgm::Plan& p = plan->p;
+    if (!bits || !out || !workspace) return fail(QGM_E_INVALID, "bits, out and workspace must be device pointers");
+    if (p.n_slots > 0 && !gate_vals) return fail(QGM_E_INVALID, "the circuit reads gate_vals but it is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
+    const int64_t B_pad = qgm::padded_batch(B);
+    const int64_t B_eff = qgm::batch_eff(p, B);
+    if (B_eff > (int64_t(1) << 26)) return fail(QGM_E_UNSUPPORTED, "batch times slice count exceeds 2^26");
+    if ((int64_t(1) << p.r_max) * (B_eff / 64) > (int64_t(1) << 31))
+        return fail(QGM_E_UNSUPPORTED, "frontier rows times batch blocks exceed 2^31");
+    const qgm::WsLayout w = qgm::workspace_layout(p, B);
+    if (ws_bytes < w.total)
+        return fail(QGM_E_OOM, "workspace too small: need " + std::to_string(w.total) + " bytes");
+    char* tables = nullptr;
+    qgm_status st = device_tables(plan, &tables);
+    if (st != QGM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    float2* F[2] = {reinterpret_cast<float2*>(ws + w.f0), reinterpret_cast<float2*>(ws + w.f1)};
+    auto* vids = reinterpret_cast<uint16_t*>(ws + w.var_ids);
+    auto* gtab = reinterpret_cast<float2*>(ws + w.g);
+    const auto* tabs = reinterpret_cast<const qgm::StepTab*>(tables + plan->off_steps);
+    const int n_steps = int(p.steps.size());
+    hipEvent_t ev[5] = {};
+    if (plan->timing) {
+        while (plan->events.size() < plan->events_used + 5) {
+            hipEvent_t e = nullptr;
+            hipError_t he = hipEventCreate(&e);
+            if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+            plan->events.push_back(e);
+        }
+        for (int i = 0; i < 5; ++i) ev[i] = plan->events[plan->events_used + i];
+        plan->events_used += 5;
+    }
+    auto mark = [&](int i) { if (plan->timing) (void)hipEventRecord(ev[i], s); };
+    mark(0);
+    qgm::launch_boundary(bits, B, uint32_t(B_pad), uint32_t(B_eff), n_steps, tabs,
+                         reinterpret_cast<const int32_t*>(tables + plan->off_sig), vids, s);
+    mark(1);
+    qgm::launch_build_g(tabs, n_steps, plan->max_g_entries, reinterpret_cast<const qgm::GOp*>(tables + plan->off_ops),
+                        reinterpret_cast<const double2*>(tables + plan->off_fixed),
+                        static_cast<const float2*>(gate_vals), gtab, s);
+    mark(2);
+    for (int i = 0; i < n_steps; ++i) {
+        const qgm::Step& stp = p.steps[i];
+        qgm::StepParams sp{};
+        sp.kb = stp.kb; sp.vb = stp.vb; sp.nb = stp.nb; sp.sb = stp.sb;
+        sp.row_bits = stp.r_in - stp.kb;
+        sp.input_is_one = stp.input_is_one ? 1 : 0;
+        for (int j = 0; j < stp.kb; ++j) sp.kpos[j] = stp.kpos[j];
+        for (int j = 0; j < stp.vb; ++j) sp.vpos[j] = stp.vpos[j];
+        sp.g_off = stp.g_off;
+        qgm::launch_step(sp, F[i & 1], F[(i + 1) & 1], vids + size_t(i) * size_t(B_eff), gtab, uint32_t(B_eff), s);
+    }
+    mark(3);
+    qgm::launch_finalize(F[n_steps & 1], uint32_t(B_eff), uint32_t(B_pad), B, int(1 << p.sliced.size()), p.n_open,
+                         reinterpret_cast<const int32_t*>(tables + plan->off_final), out, p.opts.out_c128 != 0, s);
+    mark(4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
+qgm_status qgm_plan_set_timing(qgm_plan_t* plan, int32_t enable) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    plan->timing = enable != 0;
+    plan->events_used = 0;
+    return QGM_OK;
+}
+
+qgm_status qgm_plan_timings(qgm_plan_t* plan, double* ms, int64_t* n_calls) {
+    g_err.clear();
+    if (!plan || !ms || !n_calls) return fail(QGM_E_INVALID, "NULL argument");
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+    *n_calls = int64_t(plan->events_used / 5);
+    for (size_t c = 0; c + 5 <= plan->events_used; c += 5) {
+        hipError_t e = hipEventSynchronize(plan->events[c + 4]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        for (int i = 0; i < 4; ++i) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, plan->events[c + i], plan->events[c + i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            ms[i] += double(t);
+        }
+    }
+    return QGM_OK;
+}
+
+void qgm_plan_destroy(qgm_plan_t* plan) {
+    if (!plan) return;
+    for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
+    int cur = 0;
+    bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto& d : plan->p.dev) {
+        if (hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.base);
+    }
+    if (have_cur) (void)hipSetDevice(cur);
+    delete plan;
+}
+
+const char* qgm_last_error(void) { return g_err.c_str(); }
+
+qgm_status qgm_sync_check(void* stream) {
+    g_err.clear();
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending HIP error");
+    return QGM_OK;
+}
+
+}  // extern "C"

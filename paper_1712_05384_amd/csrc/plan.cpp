@@ -1,0 +1,432 @@
+// Host-side planner: worldline variables and factors (Sec. III.A-B), the
+// vertical elimination order (Sec. IV.A), grouped bucket elimination (App. A)
+// with one step per worldline, and variable slicing.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <set>
+#include <sstream>
+
+namespace qgm {
+
+namespace {
+
+bool is_diag_kind(int k) { return k == QGM_T || k == QGM_UD || k == QGM_CZ; }
+
+int mat_index(int kind, int slot) {
+    switch (kind) {
+        case QGM_H: return 0;
+        case QGM_T: return 1;
+        case QGM_XH: return 2;
+        case QGM_YH: return 3;
+        default: return kFixedMats + slot;   // QGM_U, QGM_UD
+    }
+}
+
+// The vertical order of Sec. IV.A: whole worldlines one qubit at a time, with
+// qubits taken first along the shorter lattice side.
+std::vector<int> vertical_order(int rows, int cols) {
+    std::vector<int> o;
+    if (rows <= cols) {
+        for (int c = 0; c < cols; ++c)
+            for (int r = 0; r < rows; ++r) o.push_back(r * cols + c);
+    } else {
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) o.push_back(r * cols + c);
+    }
+    return o;
+}
+
+struct Src { uint8_t src = SRC_ZERO; uint8_t bit = 0; };
+
+}  // namespace
+
+int64_t padded_batch(int64_t B) { return (B + 63) / 64 * 64; }
+
+double Step::bytes_per_b() const {
+    double in = input_is_one ? 0.0 : 8.0 * double(int64_t(1) << r_in);
+    return in + 8.0 * double(int64_t(1) << r_out) + 2.0;
+}
+
+double Step::flops_per_b() const {
+    // rows * K * N complex multiply-adds, 8 real flops each
+    return 8.0 * double(int64_t(1) << (r_in - kb)) * double(int64_t(1) << kb) * double(int64_t(1) << nb);
+}
+
+static qgm_status validate(const qgm_circuit* c, const int32_t* open, int32_t n_open, std::string* err) {
+    if (!c) { *err = "circuit is NULL"; return QGM_E_INVALID; }
+    if (c->rows < 1 || c->cols < 1 || int64_t(c->rows) * c->cols > 64) {
+        *err = "rows and cols must be >= 1 with rows*cols <= 64"; return QGM_E_INVALID;
+    }
+    if (c->n_gates < 0 || (c->n_gates > 0 && !c->gates)) { *err = "bad gate array"; return QGM_E_INVALID; }
+    if (c->n_slots < 0) { *err = "n_slots < 0"; return QGM_E_INVALID; }
+    const int n = c->rows * c->cols;
+    std::set<std::pair<int, int>> used;   // (cycle, qubit)
+    for (int i = 0; i < c->n_gates; ++i) {
+        const qgm_gate& g = c->gates[i];
+        char buf[160];
+        if (g.kind < QGM_H || g.kind > QGM_UD) {
+            snprintf(buf, sizeof buf, "gate %d: unknown kind %d", i, g.kind); *err = buf; return QGM_E_INVALID;
+        }
+        if (g.cycle < 0) { snprintf(buf, sizeof buf, "gate %d: negative cycle", i); *err = buf; return QGM_E_INVALID; }
+        if (g.q0 < 0 || g.q0 >= n) {
+            snprintf(buf, sizeof buf, "gate %d: qubit %d out of range", i, g.q0); *err = buf; return QGM_E_INVALID;
+        }
+        if (g.kind == QGM_CZ) {
+            if (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0) {
+                snprintf(buf, sizeof buf, "gate %d: CZ needs two distinct qubits in range", i); *err = buf;
+                return QGM_E_INVALID;
+            }
+        } else if (g.q1 != -1) {
+            snprintf(buf, sizeof buf, "gate %d: single-qubit gate must have q1 = -1", i); *err = buf;
+            return QGM_E_INVALID;
+        }
+        if (g.kind == QGM_U || g.kind == QGM_UD) {
+            if (g.slot < 0 || g.slot >= c->n_slots) {
+                snprintf(buf, sizeof buf, "gate %d: slot %d out of range [0, %d)", i, g.slot, c->n_slots);
+                *err = buf; return QGM_E_INVALID;
+            }
+        }
+        for (int q : {g.q0, g.kind == QGM_CZ ? g.q1 : -1}) {
+            if (q < 0) continue;
+            if (!used.insert({g.cycle, q}).second) {
+                snprintf(buf, sizeof buf, "gate %d: qubit %d used twice in cycle %d", i, q, g.cycle);
+                *err = buf; return QGM_E_INVALID;
+            }
+        }
+    }
+    if (n_open < 0 || n_open > n || (n_open > 0 && !open)) { *err = "bad open qubit list"; return QGM_E_INVALID; }
+    std::set<int> seen;
+    for (int i = 0; i < n_open; ++i) {
+        if (open[i] < 0 || open[i] >= n || !seen.insert(open[i]).second) {
+            *err = "open qubits must be distinct and in range"; return QGM_E_INVALID;
+        }
+    }
+    return QGM_OK;
+}
+
+// Builds steps for the current slicing; returns the peak rank.
+static qgm_status build_steps(Plan& p, std::string* err) {
+    p.steps.clear();
+    const int n = p.n;
+    std::vector<int> pos(n);
+    for (int i = 0; i < n; ++i) pos[p.order[i]] = i;
+    // owner step of each gate: the earliest qubit in the order among its qubits
+    std::vector<std::vector<int>> owned(n);
+    for (int r = 0; r < int(p.recs.size()); ++r) {
+        const GateRec& g = p.recs[r];
+        int owner = g.q0;
+        if (g.type == 2 && pos[g.q1] < pos[g.q0]) owner = g.q1;
+        owned[owner].push_back(r);
+    }
+    auto fixed_src = [&](int v, Src& s) -> bool {
+        const VarInfo& vi = p.vars[v];
+        if (vi.slice_idx >= 0) { s.src = SRC_SIG; return true; }
+        if (vi.is_final && vi.open_idx < 0) { s.src = SRC_SIG; return true; }
+        if (vi.is_c0 && vi.open_idx < 0) { s.src = SRC_ZERO; s.bit = 0; return true; }
+        return false;
+    };
+    std::vector<int> S;   // frontier layout: variable at each position
+    int r_peak = 0;
+    int64_t g_off = 0;
+    for (int si = 0; si < n; ++si) {
+        const int q = p.order[si];
+        Step st;
+        st.qubit = q;
+        st.input_is_one = (si == 0);
+        st.in_axes = S;
+        st.r_in = int(S.size());
+        std::map<int, int> inpos;
+        for (int i = 0; i < int(S.size()); ++i) inpos[S[i]] = i;
+        // local variables of this step, in order of first use
+        std::vector<int> local;
+        std::set<int> local_set;
+        auto touch = [&](int v) { if (v >= 0 && local_set.insert(v).second) local.push_back(v); };
+        for (int v : p.chain[q]) touch(v);
+        for (int r : owned[q]) { touch(p.recs[r].var0); touch(p.recs[r].var1); }
+        std::map<int, Src> src;
+        std::map<long long, int> sig_bit;   // key: qubit (>=0) or -(1+slice) -> bit
+        auto sig_of = [&](int v) -> int {
+            const VarInfo& vi = p.vars[v];
+            long long key = vi.slice_idx >= 0 ? -(1LL + vi.slice_idx) : (long long)vi.qubit;
+            auto it = sig_bit.find(key);
+            if (it != sig_bit.end()) return it->second;
+            int b = int(st.sig_src.size());
+            st.sig_src.push_back(int(key));
+            sig_bit[key] = b;
+            return b;
+        };
+        for (int v : local) {
+            Src s;
+            const VarInfo& vi = p.vars[v];
+            const bool own = (vi.qubit == q);
+            const bool open_final = vi.is_final && vi.open_idx >= 0;
+            if (fixed_src(v, s)) {
+                if (s.src == SRC_SIG) s.bit = uint8_t(sig_of(v));
+            } else if (inpos.count(v)) {
+                if (own && !open_final) st.k_vars.push_back(v);
+                else st.v_vars.push_back(v);
+                s.src = (own && !open_final) ? SRC_K : SRC_V;
+            } else {
+                if (own && !open_final) s.src = SRC_INT;
+                else { s.src = SRC_N; s.bit = uint8_t(st.n_vars.size()); st.n_vars.push_back(v); }
+            }
+            src[v] = s;
+        }
+        // a frontier variable of this qubit that the step does not touch cannot occur:
+        // every worldline variable is touched by its gates.
+        for (int v : S)
+            if (p.vars[v].qubit == q && !src.count(v)) { *err = "internal: untouched frontier variable"; return QGM_E_INTERNAL; }
+        // K bits in ascending input position
+        std::sort(st.k_vars.begin(), st.k_vars.end(), [&](int a, int b) { return inpos[a] < inpos[b]; });
+        for (int i = 0; i < int(st.k_vars.size()); ++i) {
+            src[st.k_vars[i]].bit = uint8_t(i);
+            st.kpos.push_back(inpos[st.k_vars[i]]);
+        }
+        // output layout: input axes without K (order kept), then N axes
+        std::set<int> kset(st.k_vars.begin(), st.k_vars.end());
+        for (int v : S) if (!kset.count(v)) st.out_axes.push_back(v);
+        const int row_bits = int(st.out_axes.size());
+        for (int v : st.n_vars) st.out_axes.push_back(v);
+        std::map<int, int> outpos;
+        for (int i = 0; i < int(st.out_axes.size()); ++i) outpos[st.out_axes[i]] = i;
+        std::sort(st.v_vars.begin(), st.v_vars.end(), [&](int a, int b) { return outpos[a] < outpos[b]; });
+        for (int i = 0; i < int(st.v_vars.size()); ++i) {
+            src[st.v_vars[i]].bit = uint8_t(i);
+            st.vpos.push_back(outpos[st.v_vars[i]]);
+        }
+        st.kb = int(st.k_vars.size());
+        st.vb = int(st.v_vars.size());
+        st.nb = int(st.n_vars.size());
+        st.sb = int(st.sig_src.size());
+        st.r_out = int(st.out_axes.size());
+        (void)row_bits;
+        if (st.kb > kMaxKB || st.vb > kMaxBits || st.sb > kMaxBits + 4 || st.nb > kMaxNB ||
+            st.r_out > kMaxRank || st.r_in > kMaxRank) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "step for qubit %d exceeds kernel limits (K=%d V=%d N=%d sigma=%d rank %d->%d)",
+                     q, st.kb, st.vb, st.nb, st.sb, st.r_in, st.r_out);
+            *err = buf;
+            return QGM_E_UNSUPPORTED;
+        }
+        // factor program along the worldline of q (time order)
+        auto emit = [&](uint8_t type, int v, int mat) {
+            GOp op{};
+            op.type = type;
+            op.mat = mat;
+            if (v >= 0) { op.src = src[v].src; op.bit = src[v].bit; }
+            st.ops.push_back(op);
+        };
+        {
+            int c0 = p.chain[q][0];
+            if (src[c0].src != SRC_ZERO && src[c0].src != SRC_INT) emit(GOP_PROJECT, c0, -1);
+        }
+        for (int r : owned[q]) {
+            const GateRec& g = p.recs[r];
+            if (g.type == 0) {
+                emit(GOP_MAT, -1, g.mat);
+                if (src[g.var0].src != SRC_INT) emit(GOP_PROJECT, g.var0, -1);
+            } else if (g.type == 1) {
+                emit(GOP_DIAG, -1, g.mat);
+            } else {
+                int partner = (g.q0 == q) ? g.var1 : g.var0;
+                if (src[partner].src == SRC_ZERO) continue;   // (-1)^{b*0} = 1
+                emit(GOP_CZ, partner, -1);
+            }
+        }
+        emit(GOP_END, p.chain[q].back(), -1);
+        if (src[p.chain[q].back()].src == SRC_INT) { *err = "internal: final variable summed"; return QGM_E_INTERNAL; }
+        st.g_off = g_off;
+        g_off += st.g_entries();
+        r_peak = std::max(r_peak, std::max(st.r_in, st.r_out));
+        S = st.out_axes;
+        p.steps.push_back(std::move(st));
+    }
+    // the last frontier holds exactly the open variables
+    if (int(S.size()) != p.n_open) { *err = "internal: final frontier is not the open set"; return QGM_E_INTERNAL; }
+    p.final_pos.assign(p.n_open, -1);
+    for (int i = 0; i < int(S.size()); ++i) p.final_pos[p.vars[S[i]].open_idx] = i;
+    p.g_total = g_off;
+    p.r_max = r_peak;
+    p.n_ops_total = 0;
+    for (auto& st : p.steps) p.n_ops_total += int64_t(st.ops.size());
+    return QGM_OK;
+}
+
+// Picks the next variable to slice: among the non-open variables of the
+// largest frontier, the one alive in the frontier for the most steps.
+static int pick_slice_var(const Plan& p) {
+    int peak = -1, best_step = -1;
+    bool out_side = false;
+    for (int i = 0; i < int(p.steps.size()); ++i) {
+        if (p.steps[i].r_in > peak) { peak = p.steps[i].r_in; best_step = i; out_side = false; }
+        if (p.steps[i].r_out > peak) { peak = p.steps[i].r_out; best_step = i; out_side = true; }
+    }
+    if (best_step < 0) return -1;
+    const auto& axes = out_side ? p.steps[best_step].out_axes : p.steps[best_step].in_axes;
+    std::map<int, int> life;
+    for (auto& st : p.steps)
+        for (int v : st.in_axes) life[v]++;
+    int best = -1, best_life = -1;
+    for (int v : axes) {
+        if (p.vars[v].open_idx >= 0) continue;
+        if (life[v] > best_life) { best_life = life[v]; best = v; }
+    }
+    return best;
+}
+
+qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
+                      const qgm_plan_opts& opts, Plan& p, std::string* err) {
+    qgm_status st = validate(c, open, n_open, err);
+    if (st != QGM_OK) return st;
+    if (opts.ordering != 0 || opts.precision != 0 || opts.max_group_bits != 0) {
+        *err = "only ordering 0, precision 0 and max_group_bits 0 are implemented";
+        return QGM_E_UNSUPPORTED;
+    }
+    if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
+        *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
+    }
+    p.opts = opts;
+    p.rows = c->rows;
+    p.cols = c->cols;
+    p.n = c->rows * c->cols;
+    p.n_slots = c->n_slots;
+    p.n_open = n_open;
+    p.open_qubits.assign(open, open + n_open);
+    const int n = p.n;
+    // time order: (cycle, list index)
+    std::vector<int> idx(c->n_gates);
+    for (int i = 0; i < c->n_gates; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c->gates[a].cycle < c->gates[b].cycle; });
+    // worldline variables: b_q^0 for every qubit, then one per non-diagonal gate
+    p.vars.clear();
+    p.chain.assign(n, {});
+    for (int q = 0; q < n; ++q) {
+        VarInfo v; v.qubit = q; v.k = 0; v.is_c0 = true;
+        p.vars.push_back(v);
+        p.chain[q].push_back(q);
+    }
+    p.recs.clear();
+    p.n_diag_gates = p.n_nondiag_gates = p.n_cz = 0;
+    for (int i : idx) {
+        const qgm_gate& g = c->gates[i];
+        GateRec r;
+        r.gate_index = i;
+        r.q0 = g.q0;
+        if (g.kind == QGM_CZ) {
+            r.type = 2; r.q1 = g.q1;
+            r.var0 = p.chain[g.q0].back(); r.var1 = p.chain[g.q1].back();
+            p.n_cz++;
+        } else if (is_diag_kind(g.kind)) {
+            r.type = 1; r.var0 = p.chain[g.q0].back(); r.mat = mat_index(g.kind, g.slot);
+            p.n_diag_gates++;
+        } else {
+            r.type = 0; r.mat = mat_index(g.kind, g.slot);
+            VarInfo v; v.qubit = g.q0; v.k = int(p.chain[g.q0].size());
+            int id = int(p.vars.size());
+            p.vars.push_back(v);
+            r.var1 = p.chain[g.q0].back();
+            r.var0 = id;
+            p.chain[g.q0].push_back(id);
+            p.n_nondiag_gates++;
+        }
+        p.recs.push_back(r);
+    }
+    for (int q = 0; q < n; ++q) p.vars[p.chain[q].back()].is_final = true;
+    for (int i = 0; i < n_open; ++i) p.vars[p.chain[open[i]].back()].open_idx = i;
+    p.order = vertical_order(p.rows, p.cols);
+    p.sliced.clear();
+    st = build_steps(p, err);
+    if (st != QGM_OK) return st;
+    while ((opts.max_rank > 0 && p.r_max > opts.max_rank) || int(p.sliced.size()) < opts.min_sliced_vars) {
+        if (p.sliced.size() >= 12) { *err = "max_rank needs more than 12 sliced variables"; return QGM_E_OOM; }
+        int v = pick_slice_var(p);
+        if (v < 0) {
+            if (opts.max_rank > 0 && p.r_max > opts.max_rank) { *err = "no variable left to slice"; return QGM_E_OOM; }
+            break;
+        }
+        p.vars[v].slice_idx = int(p.sliced.size());
+        p.sliced.push_back(v);
+        st = build_steps(p, err);
+        if (st != QGM_OK) return st;
+    }
+    return QGM_OK;
+}
+
+WsLayout workspace_layout(const Plan& p, int64_t B) {
+    auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+    WsLayout w;
+    const uint64_t be = uint64_t(batch_eff(p, B));
+    const uint64_t fbytes = al((uint64_t(1) << p.r_max) * be * 8);
+    w.f0 = 0;
+    w.f1 = fbytes;
+    w.var_ids = 2 * fbytes;
+    w.g = w.var_ids + al(uint64_t(p.steps.size()) * be * 2);
+    w.total = w.g + al(uint64_t(p.g_total) * 8);
+    return w;
+}
+
+static void json_ints(std::ostringstream& o, const std::vector<int>& v) {
+    o << "[";
+    for (size_t i = 0; i < v.size(); ++i) o << (i ? "," : "") << v[i];
+    o << "]";
+}
+
+std::string plan_json(const Plan& p, int detail) {
+    std::ostringstream o;
+    o.precision(17);
+    double bytes = 0, flops = 0;
+    for (auto& st : p.steps) { bytes += st.bytes_per_b(); flops += st.flops_per_b(); }
+    o << "{\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols << ",\"n_vars\":" << p.vars.size()
+      << ",\"n_open\":" << p.n_open << ",\"n_slots\":" << p.n_slots << ",\"n_steps\":" << p.steps.size()
+      << ",\"max_rank\":" << p.r_max << ",\"n_sliced\":" << p.sliced.size()
+      << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
+      << ",\"g_entries\":" << p.g_total
+      << ",\"bytes_per_amp\":" << bytes * double(int64_t(1) << p.sliced.size())
+      << ",\"flops_per_amp\":" << flops * double(int64_t(1) << p.sliced.size());
+    o << ",\"open_qubits\":"; json_ints(o, p.open_qubits);
+    o << ",\"order\":"; json_ints(o, p.order);
+    o << ",\"final_pos\":"; json_ints(o, p.final_pos);
+    std::vector<int> sl_q, sl_k;
+    for (int v : p.sliced) { sl_q.push_back(p.vars[v].qubit); sl_k.push_back(p.vars[v].k); }
+    o << ",\"sliced_qubit\":"; json_ints(o, sl_q);
+    o << ",\"sliced_k\":"; json_ints(o, sl_k);
+    o << ",\"steps\":[";
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        const Step& st = p.steps[i];
+        o << (i ? "," : "") << "{\"qubit\":" << st.qubit << ",\"r_in\":" << st.r_in << ",\"r_out\":" << st.r_out
+          << ",\"kb\":" << st.kb << ",\"vb\":" << st.vb << ",\"nb\":" << st.nb << ",\"sb\":" << st.sb
+          << ",\"input_is_one\":" << (st.input_is_one ? 1 : 0) << ",\"g_off\":" << st.g_off
+          << ",\"bytes_per_b\":" << st.bytes_per_b() << ",\"flops_per_b\":" << st.flops_per_b();
+        if (detail >= 1) {
+            o << ",\"kpos\":"; json_ints(o, st.kpos);
+            o << ",\"vpos\":"; json_ints(o, st.vpos);
+            o << ",\"sig_src\":"; json_ints(o, st.sig_src);
+            o << ",\"in_axes\":"; json_ints(o, st.in_axes);
+            o << ",\"out_axes\":"; json_ints(o, st.out_axes);
+            o << ",\"ops\":[";
+            for (size_t j = 0; j < st.ops.size(); ++j) {
+                const GOp& g = st.ops[j];
+                o << (j ? "," : "") << "[" << int(g.type) << "," << int(g.src) << "," << int(g.bit) << "," << g.mat << "]";
+            }
+            o << "]";
+        }
+        o << "}";
+    }
+    o << "]";
+    if (detail >= 1) {
+        o << ",\"vars\":[";
+        for (size_t i = 0; i < p.vars.size(); ++i) {
+            const VarInfo& v = p.vars[i];
+            o << (i ? "," : "") << "[" << v.qubit << "," << v.k << "," << (v.is_c0 ? 1 : 0) << ","
+              << (v.is_final ? 1 : 0) << "," << v.open_idx << "," << v.slice_idx << "]";
+        }
+        o << "]";
+    }
+    o << "}";
+    return o.str();
+}
+
+}  // namespace qgm

@@ -1,0 +1,53 @@
+// Step program records shared by the host planner and the device kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace qgm {
+
+// Sources of a variable's value inside one step's factor program.
+enum : uint8_t {
+    SRC_ZERO = 0,  // constant 0 (input delta of Eq. (psi_x))
+    SRC_K = 1,     // bit of the contracted index K
+    SRC_V = 2,     // bit of the kept shared index V
+    SRC_N = 3,     // bit of the new index N
+    SRC_SIG = 4,   // bit of the per-bitstring variant sigma (output bit or slice bit)
+    SRC_INT = 5    // summed inside G (internal worldline variable)
+};
+
+// Factor-program operations.  The program walks one qubit's worldline in time
+// order with a 2-vector s over the current worldline variable, starting from
+// s = (1, 0) (the input delta b_q^0 = 0).
+enum : uint8_t {
+    GOP_PROJECT = 0,  // the current variable takes the value of (src, bit): zero the other entry
+    GOP_MAT = 1,      // non-diagonal gate: s <- M[mat] s (sums out the previous variable)
+    GOP_DIAG = 2,     // diagonal gate on the current variable: s[c] *= M[mat][c][c]
+    GOP_CZ = 3,       // CZ with a partner variable of value p = (src, bit): s[1] *= (-1)^p
+    GOP_END = 4       // result = s[value of (src, bit)] (the last worldline variable)
+};
+
+struct GOp {
+    uint8_t type;
+    uint8_t src;
+    uint8_t bit;
+    uint8_t pad;
+    int32_t mat;
+};
+
+constexpr int kFixedMats = 4;       // H, T, X^1/2, Y^1/2; slot s is matrix kFixedMats + s
+constexpr int kMaxKB = 6;           // K bits handled with the contracted slice in registers
+constexpr int kMaxBits = 8;         // per-step bound on V bits, on sigma bits
+constexpr int kMaxNB = 10;
+constexpr int kMaxRank = 31;
+
+// Per-step launch parameters (passed by value to the step kernel).
+struct StepParams {
+    int32_t kb, vb, nb, sb;
+    int32_t row_bits;       // r_in - kb = number of bits of a row (M and V axes)
+    int32_t input_is_one;
+    int32_t kpos[kMaxKB];
+    int32_t vpos[kMaxBits];
+    int64_t g_off;
+};
+
+}  // namespace qgm

@@ -1,0 +1,148 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance for complex64 amplitudes: max |A_gpu - A_oracle| <= 1e-5 * 2^{-n/2}
+(amplitudes of random circuits have magnitude ~2^{-n/2}; the paper reports
+relative errors below 1e-5 in single precision).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_05384_amd import circuits as C
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _plan(c, open_qubits=(), **kw):
+    import paper_1712_05384_amd as Q
+    return Q.plan(c, open_qubits, **kw)
+
+
+def _gpu_amps(p, bits, gate_vals=None):
+    out = p.amplitudes(bits, gate_vals)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _oracle_open(c, bits, open_qubits):
+    cols = []
+    for o in range(1 << len(open_qubits)):
+        xb = bits.copy()
+        for i, q in enumerate(open_qubits):
+            xb = (xb & ~np.uint64(1 << q)) | np.uint64(((o >> i) & 1) << q)
+        cols.append(oracle.sv_amplitudes(c.n, c.gates, c.gate_vals, xb))
+    return np.stack(cols, axis=1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_app_d_on_gpu():
+    d = C.example_app_d()
+    got = _gpu_amps(_plan(d), np.arange(4, dtype=np.uint64))[:, 0]
+    assert np.allclose(got, [0.5, 0.5, 0.5, -0.5], atol=1e-7)
+
+
+def test_c1_full_batch():
+    """4x4 depth 16, 64 bitstrings: every amplitude against the 2^16 state vector."""
+    c, bits = C.workload("c1_4x4_d16")
+    _say("case c1_4x4_d16 B=64")
+    got = _gpu_amps(_plan(c), bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    err = np.abs(got - ref).max()
+    assert err <= TOL * 2 ** (-c.n / 2), err
+
+
+@pytest.mark.parametrize("B", [1, 5, 63, 64, 65, 130])
+def test_ragged_batches(B):
+    c = C.random_grid_circuit(3, 4, 12, 7)
+    bits = C.random_bitstrings(c.n, B, 7)
+    _say("case 3x4_d12 B=%d" % B)
+    got = _gpu_amps(_plan(c), bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(1, 1, 3, 1), (2, 2, 1, 2), (1, 5, 12, 3), (4, 4, 24, 4),
+                                                  (3, 5, 20, 5), (4, 5, 16, 6)])
+def test_random_circuits(rows, cols, depth, seed):
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 256, seed)
+    _say("case %s B=256" % c.name)
+    got = _gpu_amps(_plan(c), bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_parameterised_gate_values():
+    c = C.parameterised_circuit(4, 4, 14, 8)
+    bits = C.random_bitstrings(c.n, 128, 8)
+    _say("case %s B=128 (gate_vals)" % c.name)
+    got = _gpu_amps(_plan(c), bits, torch.tensor(c.gate_vals.astype(np.complex64)))[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, c.gate_vals.astype(np.complex64).astype(np.complex128), bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("open_qubits", [(0,), (5, 2), (11, 3, 7)])
+def test_open_qubits_on_gpu(open_qubits):
+    c = C.random_grid_circuit(3, 4, 12, 9)
+    bits = C.random_bitstrings(c.n, 70, 9)
+    _say("case 3x4_d12 open=%s" % (open_qubits,))
+    got = _gpu_amps(_plan(c, open_qubits), bits)
+    ref = _oracle_open(c, bits, open_qubits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("nsl", [1, 3])
+def test_sliced_fp64_sum(nsl):
+    """Slices summed in FP64 on the GPU equal the unsliced amplitudes."""
+    c = C.random_grid_circuit(4, 4, 16, 10)
+    bits = C.random_bitstrings(c.n, 128, 10)
+    _say("case 4x4_d16 slices=%d" % nsl)
+    p = _plan(c, min_sliced_vars=nsl, out_c128=True)
+    got = _gpu_amps(p, bits)[:, 0]
+    assert got.dtype == np.complex128
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_clifford_probabilities_dyadic_36_qubits():
+    """6x6 depth 12 with T replaced by S: no state vector fits a test, but a
+    Clifford circuit's probabilities are 0 or 2^-k (App. F, end)."""
+    c = C.clifford_variant(C.random_grid_circuit(6, 6, 12, 11))
+    bits = C.random_bitstrings(c.n, 256, 11)
+    _say("case clifford 6x6_d12")
+    got = _gpu_amps(_plan(c), bits, torch.tensor(c.gate_vals.astype(np.complex64)))[:, 0]
+    p = np.abs(got) ** 2
+    nz = p[p > 2.0 ** (-c.n - 8)]
+    assert len(nz) > 0
+    k = np.log2(1 / nz)
+    assert np.abs(k - np.round(k)).max() < 1e-4
+
+
+def test_c2_full_size():
+    """5x5 depth 25, 1024 bitstrings (the benchmark workload) against the 2^25
+    state vector, element by element."""
+    c, bits = C.workload("c2_5x5_d25")
+    _say("case c2_5x5_d25 B=1024")
+    got = _gpu_amps(_plan(c), bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    err = np.abs(got - ref).max()
+    _say("c2 max err * 2^(n/2) = %.3g" % (err * 2 ** (c.n / 2)))
+    assert err <= TOL * 2 ** (-c.n / 2), err
+
+
+def test_repeat_calls_bitwise_identical():
+    c, bits = C.workload("c1_4x4_d16")
+    p = _plan(c)
+    a = _gpu_amps(p, bits)
+    for _ in range(3):
+        assert np.array_equal(_gpu_amps(p, bits), a)

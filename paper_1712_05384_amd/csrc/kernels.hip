@@ -13,7 +13,7 @@
 
 namespace qgm {
 
-__device__ __forceinline__ uint32_t src_value(uint8_t src, uint8_t bit, uint32_t k, uint32_t v, uint32_t n, uint32_t sig) {
+__device__ __forceinline__ uint32_t src_value(int32_t src, int32_t bit, uint32_t k, uint32_t v, uint32_t n, uint32_t sig) {
     switch (src) {
         case SRC_K: return (k >> bit) & 1u;
         case SRC_V: return (v >> bit) & 1u;

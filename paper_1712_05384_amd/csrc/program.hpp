@@ -26,11 +26,13 @@ enum : uint8_t {
     GOP_END = 4       // result = s[value of (src, bit)] (the last worldline variable)
 };
 
+// All fields are 32-bit so that every field sits at a dword-aligned offset:
+// the kernels read the program with scalar loads, and a scalar load whose
+// base register is not dword aligned silently drops the low address bits.
 struct GOp {
-    uint8_t type;
-    uint8_t src;
-    uint8_t bit;
-    uint8_t pad;
+    int32_t type;
+    int32_t src;
+    int32_t bit;
     int32_t mat;
 };
 

@@ -34,6 +34,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_5x5_d25")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--kernel-policy", type=int, default=0,
+                    help="0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -50,7 +52,7 @@ def main() -> int:
     c, bits = C.workload(args.workload)
     B = len(bits)
     t0 = time.perf_counter()
-    p = Q.plan(c)
+    p = Q.plan(c, kernel_policy=args.kernel_policy)
     plan_s = time.perf_counter() - t0
     info = p.info(0)
     print(f"# plan: n={c.n} steps={info['n_steps']} max_rank={info['max_rank']} "
@@ -100,7 +102,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{c.name}: {c.rows}x{c.cols} grid, depth {c.depth()}, {B} uniform bitstrings, "
                                f"complex64, one plan for the batch", "global_batch": B,
-                   "qubits": c.n, "max_rank": info["max_rank"], "sliced_vars": info["n_sliced"]},
+                   "qubits": c.n, "max_rank": info["max_rank"], "sliced_vars": info["n_sliced"],
+                   "kernel_policy": args.kernel_policy},
         "phases_ms_per_step": {k: round(v / max(ncalls, 1), 5) for k, v in
                                zip(("boundary", "g_build", "elimination", "output"), phases)},
         "plan_seconds": round(plan_s, 4),

@@ -77,7 +77,11 @@ typedef struct {
 typedef struct {
     int32_t ordering;          /* 0 = vertical order of Sec. IV.A (qubits along the shorter side first) */
     int32_t precision;         /* 0 = complex64 with FP32 arithmetic */
-    int32_t max_group_bits;    /* reserved, 0 */
+    int32_t kernel_policy;     /* 0 = auto (the vector-ALU kernel, one row per thread); 1 = the same;
+                                  2 = FP32 matrix-core kernel for every step it supports (K and N of
+                                      2^3..2^5), the vector-ALU kernel elsewhere;
+                                  3 = vector-ALU kernel with two rows per thread on dense steps
+                                      (|K|+|N| >= 8 bits) */
     int32_t min_sliced_vars;   /* slice at least this many variables (Sec. V outlook: space-time tradeoffs) */
     int32_t out_c128;          /* 1: amplitudes are written as complex128, 0: complex64 */
     int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor has rank <= max_rank */

@@ -27,7 +27,7 @@ class QgmCircuit(ctypes.Structure):
 
 
 class QgmPlanOpts(ctypes.Structure):
-    _fields_ = [("ordering", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_group_bits", ctypes.c_int32),
+    _fields_ = [("ordering", ctypes.c_int32), ("precision", ctypes.c_int32), ("kernel_policy", ctypes.c_int32),
                 ("min_sliced_vars", ctypes.c_int32), ("out_c128", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
 

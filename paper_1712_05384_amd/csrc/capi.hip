@@ -226,7 +226,19 @@ qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_
         for (int j = 0; j < stp.kb; ++j) sp.kpos[j] = stp.kpos[j];
         for (int j = 0; j < stp.vb; ++j) sp.vpos[j] = stp.vpos[j];
         sp.g_off = stp.g_off;
-        qgm::launch_step(sp, F[i & 1], F[(i + 1) & 1], vids + size_t(i) * size_t(B_eff), gtab, uint32_t(B_eff), s);
+        sp.pair_bit = stp.pair_bit;
+        sp.pair_in = stp.pair_in;
+        const uint16_t* vs = vids + size_t(i) * size_t(B_eff);
+        if (stp.kclass == 1) {
+            qgm::DenseParams dp{};
+            dp.sp = sp;
+            for (int j = 0; j < 4; ++j) dp.inner_pos[j] = stp.inner_pos[j];
+            dp.n_outer = int32_t(stp.outer_pos.size());
+            for (int j = 0; j < dp.n_outer; ++j) dp.outer_pos[j] = stp.outer_pos[j];
+            qgm::launch_dense(dp, F[i & 1], F[(i + 1) & 1], vs, gtab, uint32_t(B_eff), s);
+        } else {
+            qgm::launch_step(sp, F[i & 1], F[(i + 1) & 1], vs, gtab, uint32_t(B_eff), s);
+        }
     }
     mark(3);
     qgm::launch_finalize(F[n_steps & 1], uint32_t(B_eff), uint32_t(B_pad), B, int(1 << p.sliced.size()), p.n_open,

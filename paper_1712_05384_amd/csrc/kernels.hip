@@ -101,12 +101,17 @@ __global__ void __launch_bounds__(256) k_build_g(const StepTab* __restrict__ ste
 
 // One elimination step (bucket processing of App. A for one worldline):
 //   F'[row, n] = sum_k F[row (+) k, ...] * G_sigma(b)[v(row), k, n]
-// Each wave owns 64 consecutive batch entries of one output row: it loads
-// the 2^KB contracted inputs of that row into registers, then streams over
-// the 2^nb outputs in chunks of NCH.  G sits in LDS (or is read through the
-// cache when large) with sigma as the fastest index, so lanes whose
-// bitstrings select different variants read neighbouring banks.
-template <int KB, int NCH, bool USE_LDS>
+// Each wave owns 64 consecutive batch entries of R output rows (R = 2 pairs
+// rows that differ in one non-V bit, so they share v and sigma): it loads the
+// 2^KB contracted inputs of those rows into registers, then streams over the
+// 2^nb outputs in chunks of NCH.  G is staged in LDS transposed as
+// [v][sigma][n][k], the sigma pitch padded by one element: a lane's base depends
+// only on (v, sigma), so every read of the unrolled k, j loops uses an
+// immediate offset (no address arithmetic per multiply-add), and lanes whose
+// bitstrings select different variants hit different banks.  Large G is read
+// through the cache in its [v][k][n][sigma] order instead.  R = 2 (two rows
+// per thread that share v and sigma) lets one G read feed two multiply-adds.
+template <int KB, int NCH, bool USE_LDS, int R>
 __global__ void __launch_bounds__(256) k_step(StepParams sp, const float2* __restrict__ fin,
                                               float2* __restrict__ fout, const uint16_t* __restrict__ vids,
                                               const float2* __restrict__ gtab, uint32_t B_eff, uint32_t nbb,
@@ -116,11 +121,17 @@ __global__ void __launch_bounds__(256) k_step(StepParams sp, const float2* __res
     const int nb = sp.nb, sb = sp.sb;
     const int N = 1 << nb;
     const float2* __restrict__ G = gtab + sp.g_off;
+    const uint32_t SS = (uint32_t(K) << nb) + 1u;   // LDS pitch of one variant (padded)
     if constexpr (USE_LDS) {
-        const int total = 1 << (sp.vb + KB + nb + sb);
-        for (int i = threadIdx.x; i < total; i += 256) glds[i] = G[i];
+        const uint32_t total = 1u << (sp.vb + KB + nb + sb);
+        for (uint32_t e = threadIdx.x; e < total; e += 256) {
+            const uint32_t sg = e & ((1u << sb) - 1u);
+            const uint32_t n = (e >> sb) & ((1u << nb) - 1u);
+            const uint32_t k = (e >> (sb + nb)) & uint32_t(K - 1);
+            const uint32_t v = e >> (sb + nb + KB);
+            glds[((v << sb) + sg) * SS + (n << KB) + k] = G[e];
+        }
         __syncthreads();
-        G = glds;
     }
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
@@ -133,8 +144,13 @@ __global__ void __launch_bounds__(256) k_step(StepParams sp, const float2* __res
         koff[k] = o;
     }
     for (uint32_t unit = blockIdx.x * 4u + wave; unit < n_units; unit += gridDim.x * 4u) {
-        const uint32_t row = unit / nbb;
-        const uint32_t b = (unit - row * nbb) * 64u + lane;
+        const uint32_t urow = unit / nbb;
+        const uint32_t b = (unit - urow * nbb) * 64u + lane;
+        uint32_t row = urow;
+        if constexpr (R == 2) {
+            const uint32_t p = uint32_t(sp.pair_bit);
+            row = ((urow >> p) << (p + 1)) | (urow & ((1u << p) - 1u));
+        }
         const uint32_t sig = vids[b];
         uint32_t inrow = row;
 #pragma unroll
@@ -144,34 +160,51 @@ __global__ void __launch_bounds__(256) k_step(StepParams sp, const float2* __res
         }
         uint32_t v = 0;
         for (int i = 0; i < sp.vb; ++i) v |= ((row >> sp.vpos[i]) & 1u) << i;
-        float2 a[K];
+        float2 a[R][K];
         if (sp.input_is_one) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) a[k] = make_float2(k == 0 ? 1.f : 0.f, 0.f);
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < K; ++k) a[r][k] = make_float2(k == 0 ? 1.f : 0.f, 0.f);
         } else {
 #pragma unroll
-            for (int k = 0; k < K; ++k) a[k] = fin[size_t(inrow + koff[k]) * B_eff + b];
+            for (int r = 0; r < R; ++r) {
+                const uint32_t ir = inrow + (r ? uint32_t(sp.pair_in) : 0u);
+#pragma unroll
+                for (int k = 0; k < K; ++k) a[r][k] = fin[size_t(ir + koff[k]) * B_eff + b];
+            }
         }
         const uint32_t gv = (v << KB);
+        const float2* gl = glds + ((v << sb) + sig) * SS;
         for (int nc = 0; nc < N; nc += NCH) {
-            float2 acc[NCH];
+            float2 acc[R][NCH];
 #pragma unroll
-            for (int j = 0; j < NCH; ++j) acc[j] = make_float2(0.f, 0.f);
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < NCH; ++j) acc[r][j] = make_float2(0.f, 0.f);
+            const float2* gc = gl + (uint32_t(nc) << KB);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const uint32_t gbase = (((gv + k) << nb) + nc) << sb;
 #pragma unroll
                 for (int j = 0; j < NCH; ++j) {
-                    const float2 g = G[gbase + (uint32_t(j) << sb) + sig];
-                    acc[j].x = fmaf(a[k].x, g.x, acc[j].x);
-                    acc[j].x = fmaf(-a[k].y, g.y, acc[j].x);
-                    acc[j].y = fmaf(a[k].x, g.y, acc[j].y);
-                    acc[j].y = fmaf(a[k].y, g.x, acc[j].y);
+                    const float2 g = USE_LDS ? gc[j * K + k] : G[gbase + (uint32_t(j) << sb) + sig];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        acc[r][j].x = fmaf(a[r][k].x, g.x, acc[r][j].x);
+                        acc[r][j].x = fmaf(-a[r][k].y, g.y, acc[r][j].x);
+                        acc[r][j].y = fmaf(a[r][k].x, g.y, acc[r][j].y);
+                        acc[r][j].y = fmaf(a[r][k].y, g.x, acc[r][j].y);
+                    }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < NCH; ++j)
-                fout[size_t(row + (uint32_t(nc + j) << sp.row_bits)) * B_eff + b] = acc[j];
+            for (int r = 0; r < R; ++r) {
+                const uint32_t orow = row + (r ? (1u << sp.pair_bit) : 0u);
+#pragma unroll
+                for (int j = 0; j < NCH; ++j)
+                    fout[size_t(orow + (uint32_t(nc + j) << sp.row_bits)) * B_eff + b] = acc[r][j];
+            }
         }
     }
 }
@@ -202,54 +235,63 @@ __global__ void __launch_bounds__(256) k_finalize(const float2* __restrict__ f, 
 // ---------------------------------------------------------------------------
 // launch helpers
 
-template <int KB, int NCH, bool L>
+template <int KB, int NCH, bool L, int R>
 static void launch_step_t(const StepParams& sp, const float2* fin, float2* fout, const uint16_t* vids,
                           const float2* gtab, uint32_t B_eff, uint32_t nbb, uint32_t n_units, size_t lds,
                           hipStream_t stream) {
     uint32_t grid = (n_units + 3) / 4;
     if (grid > kStepMaxGrid) grid = kStepMaxGrid;
-    hipLaunchKernelGGL((k_step<KB, NCH, L>), dim3(grid), dim3(256), L ? lds : 0, stream, sp, fin, fout, vids, gtab,
-                       B_eff, nbb, n_units);
+    hipLaunchKernelGGL((k_step<KB, NCH, L, R>), dim3(grid), dim3(256), L ? lds : 0, stream, sp, fin, fout, vids,
+                       gtab, B_eff, nbb, n_units);
 }
 
-template <int KB, bool L>
+template <int KB, bool L, int R>
 static void launch_step_nch(int nch, const StepParams& sp, const float2* fin, float2* fout, const uint16_t* vids,
                             const float2* gtab, uint32_t B_eff, uint32_t nbb, uint32_t n_units, size_t lds,
                             hipStream_t stream) {
     switch (nch) {
-        case 1: launch_step_t<KB, 1, L>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 2: launch_step_t<KB, 2, L>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 4: launch_step_t<KB, 4, L>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        default: launch_step_t<KB, 8, L>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 1: launch_step_t<KB, 1, L, R>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 2: launch_step_t<KB, 2, L, R>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 4: launch_step_t<KB, 4, L, R>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        default: launch_step_t<KB, 8, L, R>(sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
     }
 }
 
 template <bool L>
-static void launch_step_kb(int kb, int nch, const StepParams& sp, const float2* fin, float2* fout,
+static void launch_step_kb(int kb, bool pair, int nch, const StepParams& sp, const float2* fin, float2* fout,
                            const uint16_t* vids, const float2* gtab, uint32_t B_eff, uint32_t nbb,
                            uint32_t n_units, size_t lds, hipStream_t stream) {
+    if (pair) {   // row pairs: dense steps (K of 2^3..2^5)
+        switch (kb) {
+            case 3: launch_step_nch<3, L, 2>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+            case 4: launch_step_nch<4, L, 2>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+            default: launch_step_nch<5, L, 2>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        }
+        return;
+    }
     switch (kb) {
-        case 0: launch_step_nch<0, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 1: launch_step_nch<1, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 2: launch_step_nch<2, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 3: launch_step_nch<3, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 4: launch_step_nch<4, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        case 5: launch_step_nch<5, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
-        default: launch_step_nch<6, L>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 0: launch_step_nch<0, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 1: launch_step_nch<1, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 2: launch_step_nch<2, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 3: launch_step_nch<3, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 4: launch_step_nch<4, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        case 5: launch_step_nch<5, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
+        default: launch_step_nch<6, L, 1>(nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds, stream); break;
     }
 }
 
 void launch_step(const StepParams& sp, const float2* fin, float2* fout, const uint16_t* vids, const float2* gtab,
                  uint32_t B_eff, hipStream_t stream) {
     const uint32_t nbb = B_eff / 64;
-    const uint32_t n_units = (1u << sp.row_bits) * nbb;
+    const bool pair = sp.pair_bit >= 0;
+    const uint32_t n_units = (1u << (sp.row_bits - (pair ? 1 : 0))) * nbb;
     const int N = 1 << sp.nb;
     const int nch = N >= 8 ? 8 : N;
-    const size_t g_bytes = size_t(8) << (sp.vb + sp.kb + sp.nb + sp.sb);
-    if (g_bytes <= kStepLdsBytes)
-        launch_step_kb<true>(sp.kb, nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, g_bytes, stream);
+    const size_t lds_bytes = size_t(8) * ((size_t(1) << (sp.vb + sp.sb)) * ((size_t(1) << (sp.kb + sp.nb)) + 1));
+    if (lds_bytes <= kStepLdsBytes)
+        launch_step_kb<true>(sp.kb, pair, nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, lds_bytes, stream);
     else
-        launch_step_kb<false>(sp.kb, nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, 0, stream);
+        launch_step_kb<false>(sp.kb, pair, nch, sp, fin, fout, vids, gtab, B_eff, nbb, n_units, 0, stream);
 }
 
 void launch_boundary(const uint64_t* bits, int64_t B, uint32_t B_pad, uint32_t B_eff, int n_steps,

@@ -15,8 +15,17 @@ struct StepTab {
     int64_t g_off;
 };
 
+// Launch parameters of the matrix-core step kernel.
+struct DenseParams {
+    StepParams sp;
+    int32_t inner_pos[4];
+    int32_t outer_pos[kMaxRank];
+    int32_t n_outer;
+};
+
 constexpr uint32_t kStepMaxGrid = 8192;           // work-groups of the step kernel (grid-stride beyond)
-constexpr size_t kStepLdsBytes = 32 * 1024;       // G up to this size is staged in LDS
+constexpr uint32_t kDenseMaxGrid = 4096;          // work-groups of the matrix-core step kernel
+constexpr size_t kStepLdsBytes = 48 * 1024;       // G up to this size is staged in LDS
 
 void launch_boundary(const uint64_t* bits, int64_t B, uint32_t B_pad, uint32_t B_eff, int n_steps,
                      const StepTab* steps, const int32_t* sig_src, uint16_t* vids, hipStream_t stream);
@@ -24,6 +33,8 @@ void launch_build_g(const StepTab* steps, int n_steps, uint32_t max_entries, con
                     const float2* slots, float2* gtab, hipStream_t stream);
 void launch_step(const StepParams& sp, const float2* fin, float2* fout, const uint16_t* vids, const float2* gtab,
                  uint32_t B_eff, hipStream_t stream);
+void launch_dense(const DenseParams& dp, const float2* fin, float2* fout, const uint16_t* vids, const float2* gtab,
+                  uint32_t B_eff, hipStream_t stream);
 void launch_finalize(const float2* f, uint32_t B_eff, uint32_t B_pad, int64_t B, int n_slices, int n_open,
                      const int32_t* final_pos, void* out, bool c128, hipStream_t stream);
 

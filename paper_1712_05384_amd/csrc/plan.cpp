@@ -107,6 +107,45 @@ static qgm_status validate(const qgm_circuit* c, const int32_t* open, int32_t n_
     return QGM_OK;
 }
 
+// Chooses the kernel of a step.
+//  * kernel_policy 0/1: the vector-ALU kernel, one row per thread.
+//  * kernel_policy 2: every step the matrix-core kernel supports (K and N of
+//    2^3..2^5, 4 non-V row bits for a 16-row tile, <= 16 variants) runs on it.
+//  * kernel_policy 3: dense steps (|K| + |N| >= 8 bits, K of 2^3..2^5) run the
+//    vector-ALU kernel with two rows per thread that differ in a non-V bit
+//    (same v, same sigma), so every G read feeds two multiply-adds.
+static void classify_step(const Plan& p, Step& st) {
+    st.kclass = 0;
+    st.pair_bit = -1;
+    st.pair_in = 0;
+    st.inner_pos.clear();
+    st.outer_pos.clear();
+    const int row_bits = st.r_in - st.kb;
+    std::set<int> vset(st.vpos.begin(), st.vpos.end());
+    const bool mfma_ok = !st.input_is_one && st.kb >= 3 && st.kb <= 5 && st.nb >= 3 && st.nb <= 5 &&
+                         row_bits - st.vb >= 4 && (1 << st.sb) <= kDenseMaxVariants;
+    if (p.opts.kernel_policy == 2 && mfma_ok) {
+        for (int pos = 0; pos < row_bits; ++pos) {
+            if (int(st.inner_pos.size()) < 4 && !vset.count(pos)) st.inner_pos.push_back(pos);
+            else st.outer_pos.push_back(pos);
+        }
+        st.kclass = 1;
+        return;
+    }
+    if (p.opts.kernel_policy != 3) return;
+    const bool dense = st.kb >= 3 && st.kb <= 5 && st.kb + st.nb >= 8 && row_bits - st.vb >= 1;
+    if (!dense) return;
+    for (int pos = 0; pos < row_bits; ++pos) {
+        if (vset.count(pos)) continue;
+        st.pair_bit = pos;
+        // input position of that row bit: the input axes are the output row axes with K inserted
+        const int var = st.out_axes[pos];
+        for (int i = 0; i < int(st.in_axes.size()); ++i)
+            if (st.in_axes[i] == var) st.pair_in = 1 << i;
+        break;
+    }
+}
+
 // Builds steps for the current slicing; returns the peak rank.
 static qgm_status build_steps(Plan& p, std::string* err) {
     p.steps.clear();
@@ -240,6 +279,7 @@ static qgm_status build_steps(Plan& p, std::string* err) {
         if (src[p.chain[q].back()].src == SRC_INT) { *err = "internal: final variable summed"; return QGM_E_INTERNAL; }
         st.g_off = g_off;
         g_off += st.g_entries();
+        classify_step(p, st);
         r_peak = std::max(r_peak, std::max(st.r_in, st.r_out));
         S = st.out_axes;
         p.steps.push_back(std::move(st));
@@ -281,10 +321,11 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
                       const qgm_plan_opts& opts, Plan& p, std::string* err) {
     qgm_status st = validate(c, open, n_open, err);
     if (st != QGM_OK) return st;
-    if (opts.ordering != 0 || opts.precision != 0 || opts.max_group_bits != 0) {
-        *err = "only ordering 0, precision 0 and max_group_bits 0 are implemented";
+    if (opts.ordering != 0 || opts.precision != 0) {
+        *err = "only ordering 0 and precision 0 are implemented";
         return QGM_E_UNSUPPORTED;
     }
+    if (opts.kernel_policy < 0 || opts.kernel_policy > 3) { *err = "kernel_policy must be 0..3"; return QGM_E_INVALID; }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }
@@ -399,6 +440,7 @@ std::string plan_json(const Plan& p, int detail) {
         o << (i ? "," : "") << "{\"qubit\":" << st.qubit << ",\"r_in\":" << st.r_in << ",\"r_out\":" << st.r_out
           << ",\"kb\":" << st.kb << ",\"vb\":" << st.vb << ",\"nb\":" << st.nb << ",\"sb\":" << st.sb
           << ",\"input_is_one\":" << (st.input_is_one ? 1 : 0) << ",\"g_off\":" << st.g_off
+          << ",\"kernel\":\"" << (st.kclass == 1 ? "mfma_f32" : (st.pair_bit >= 0 ? "valu_pair" : "valu")) << "\""
           << ",\"bytes_per_b\":" << st.bytes_per_b() << ",\"flops_per_b\":" << st.flops_per_b();
         if (detail >= 1) {
             o << ",\"kpos\":"; json_ints(o, st.kpos);

@@ -41,6 +41,7 @@ constexpr int kMaxKB = 6;           // K bits handled with the contracted slice 
 constexpr int kMaxBits = 8;         // per-step bound on V bits, on sigma bits
 constexpr int kMaxNB = 10;
 constexpr int kMaxRank = 31;
+constexpr int kDenseMaxVariants = 16;  // matrix-core kernel: at most 2^4 operand variants per step
 
 // Per-step launch parameters (passed by value to the step kernel).
 struct StepParams {
@@ -49,6 +50,8 @@ struct StepParams {
     int32_t input_is_one;
     int32_t kpos[kMaxKB];
     int32_t vpos[kMaxBits];
+    int32_t pair_bit;       // >= 0: each thread also handles row | (1 << pair_bit) (a non-V row bit)
+    int32_t pair_in;        // input-tensor offset of that bit
     int64_t g_off;
 };
 

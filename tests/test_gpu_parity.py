@@ -146,3 +146,39 @@ def test_repeat_calls_bitwise_identical():
     a = _gpu_amps(p, bits)
     for _ in range(3):
         assert np.array_equal(_gpu_amps(p, bits), a)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(4, 4, 24, 4), (4, 4, 30, 12), (5, 4, 24, 13), (4, 5, 24, 14)])
+def test_matrix_core_steps(rows, cols, depth, seed):
+    """Every step the FP32 MFMA kernel supports runs on it (kernel_policy 2);
+    the amplitudes still match the oracle, including ragged batch padding."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 200, seed)
+    p = _plan(c, kernel_policy=2)
+    kinds = [s["kernel"] for s in p.info(0)["steps"]]
+    assert "mfma_f32" in kinds
+    _say("case %s mfma steps=%d" % (c.name, kinds.count("mfma_f32")))
+    got = _gpu_amps(p, bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_matrix_core_with_gate_values_and_slices():
+    c = C.parameterised_circuit(4, 4, 24, 15)
+    bits = C.random_bitstrings(c.n, 64, 15)
+    p = _plan(c, kernel_policy=2, min_sliced_vars=1)
+    _say("case %s mfma + slice" % c.name)
+    got = _gpu_amps(p, bits, torch.tensor(c.gate_vals.astype(np.complex64)))[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, c.gate_vals.astype(np.complex64).astype(np.complex128), bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("policy", [2, 3])
+def test_c2_kernel_policies(policy):
+    """Matrix-core steps (policy 2) and row-paired vector-ALU steps (policy 3) on the
+    benchmark workload, against the 2^25 state vector."""
+    c, bits = C.workload("c2_5x5_d25")
+    _say("case c2 policy %d" % policy)
+    got = _gpu_amps(_plan(c, kernel_policy=policy), bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)

@@ -157,3 +157,19 @@ def test_null_arguments_and_small_workspace():
     st = L.qgm_amplitudes(pc.handle, None, ctypes.c_void_p(256), 64, ctypes.c_void_p(256),
                           ctypes.c_void_p(256), 1 << 40, None)
     assert st == N.QGM_E_INVALID
+
+
+def test_kernel_classification():
+    """Policy 0 (and 1) keep every step on the vector-ALU kernel with one row per thread;
+    policy 2 puts every step the matrix-core kernel supports on it; policy 3 pairs rows
+    on dense steps (|K| + |N| >= 8 bits, K of 2^3..2^5)."""
+    c, _ = C.workload("c2_5x5_d25")
+    for pol in (0, 1):
+        assert all(s["kernel"] == "valu" for s in Q.plan(c, kernel_policy=pol).info(0)["steps"])
+    for s in Q.plan(c, kernel_policy=3).info(0)["steps"]:
+        assert (s["kernel"] == "valu_pair") == (3 <= s["kb"] <= 5 and s["kb"] + s["nb"] >= 8)
+    forced = Q.plan(c, kernel_policy=2).info(0)["steps"]
+    for s in forced:
+        ok = 3 <= s["kb"] <= 5 and 3 <= s["nb"] <= 5 and s["r_in"] - s["kb"] - s["vb"] >= 4 and s["sb"] <= 4
+        assert (s["kernel"] == "mfma_f32") == (ok and not s["input_is_one"])
+    assert any(s["kernel"] == "mfma_f32" for s in forced)

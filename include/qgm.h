@@ -85,7 +85,8 @@ typedef struct {
     int32_t min_sliced_vars;   /* slice at least this many variables (Sec. V outlook: space-time tradeoffs) */
     int32_t out_c128;          /* 1: amplitudes are written as complex128, 0: complex64 */
     int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor has rank <= max_rank */
-    int32_t reserved[2];
+    int32_t checkpoint_every;  /* qgm_backward keeps every c-th frontier (0 = ceil(sqrt(steps))) */
+    int32_t reserved;
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;
@@ -132,6 +133,28 @@ qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* byte
  * must be ordered on one stream. */
 qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
                           void* out, void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Device workspace (bytes) that qgm_backward needs for a batch of B bitstrings. */
+qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);
+
+/* Gradient of a real loss with respect to the gate values (the gate
+ * environments), by the adjoint of the elimination steps.  Runs the forward
+ * pass itself, keeping every c-th frontier (opts.checkpoint_every, default
+ * ceil(sqrt(steps))) and recomputing each segment during the reverse sweep.
+ *  grad_amps:  device complex64 [B][2^n_open], dL/dRe A + i dL/dIm A for each
+ *              amplitude (the torch convention).
+ *  amps_out:   device [B][2^n_open] (complex64 or complex128 per opts.out_c128),
+ *              receives the amplitudes of the forward pass; may be NULL.
+ *  gate_grads: device complex64 [n_slots][2][2], receives
+ *              dL/dRe U + i dL/dIm U summed over the gates that read each slot
+ *              (for QGM_UD slots only the diagonal is written non-zero).  May be
+ *              NULL when n_slots = 0.
+ *  workspace:  at least qgm_backward_workspace_bytes(plan, B) bytes, 256-byte aligned.
+ * With L = sum_x log |A_x|^2 (grad_amps = 2 / conj(A)) this is the gradient of
+ * m times the cross-entropy estimator of App. B, Eq. (cee). */
+qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
+                        const void* grad_amps, void* amps_out, void* gate_grads, void* workspace, uint64_t ws_bytes,
+                        void* stream);
 
 /* Per-phase timing of qgm_amplitudes (hipEvents recorded on the call's
  * stream; instrumentation for the benchmark, off by default).  enable = 1

@@ -13,7 +13,8 @@ STATUS_NAMES = {0: "QGM_OK", -1: "QGM_E_INVALID", -2: "QGM_E_UNSUPPORTED", -3: "
 
 # Every symbol include/qgm.h declares.
 EXPORTED = ("qgm_default_opts", "qgm_plan", "qgm_plan_info", "qgm_workspace_bytes", "qgm_amplitudes",
-            "qgm_plan_set_timing", "qgm_plan_timings", "qgm_plan_destroy", "qgm_last_error", "qgm_sync_check")
+            "qgm_backward_workspace_bytes", "qgm_backward", "qgm_plan_set_timing", "qgm_plan_timings",
+            "qgm_plan_destroy", "qgm_last_error", "qgm_sync_check")
 
 
 class QgmGate(ctypes.Structure):
@@ -29,7 +30,7 @@ class QgmCircuit(ctypes.Structure):
 class QgmPlanOpts(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int32), ("precision", ctypes.c_int32), ("kernel_policy", ctypes.c_int32),
                 ("min_sliced_vars", ctypes.c_int32), ("out_c128", ctypes.c_int32), ("max_rank", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("checkpoint_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class QgmError(RuntimeError):
@@ -57,6 +58,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_size_t)]
         L.qgm_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
         L.qgm_amplitudes.argtypes = [P, P, P, ctypes.c_int64, P, P, ctypes.c_uint64, P]
+        L.qgm_backward_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
+        L.qgm_backward.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_uint64, P]
         L.qgm_plan_set_timing.argtypes = [P, ctypes.c_int32]
         L.qgm_plan_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.qgm_plan_destroy.argtypes = [P]
@@ -65,7 +68,7 @@ def lib():
         L.qgm_last_error.restype = ctypes.c_char_p
         L.qgm_sync_check.argtypes = [P]
         for f in (L.qgm_plan, L.qgm_plan_info, L.qgm_workspace_bytes, L.qgm_amplitudes, L.qgm_sync_check,
-                  L.qgm_plan_set_timing, L.qgm_plan_timings):
+                  L.qgm_plan_set_timing, L.qgm_plan_timings, L.qgm_backward_workspace_bytes, L.qgm_backward):
             f.restype = ctypes.c_int
         _lib = L
     return _lib

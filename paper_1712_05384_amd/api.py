@@ -23,7 +23,7 @@ class Plan:
     gates (int32 [n_gates, 5]: kind, cycle, q0, q1, slot) and n_slots."""
 
     def __init__(self, circuit, open_qubits=(), *, min_sliced_vars: int = 0, max_rank: int = 0,
-                 out_c128: bool = False, kernel_policy: int = 0):
+                 out_c128: bool = False, kernel_policy: int = 0, checkpoint_every: int = 0):
         L = N.lib()
         self._lib = L
         self._h = None
@@ -38,6 +38,7 @@ class Plan:
         opts.max_rank = int(max_rank)
         opts.out_c128 = 1 if out_c128 else 0
         opts.kernel_policy = int(kernel_policy)
+        opts.checkpoint_every = int(checkpoint_every)
         op = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         h = ctypes.c_void_p()
         N.check(L.qgm_plan(ctypes.byref(cs), op, len(self.open_qubits), ctypes.byref(opts), ctypes.byref(h)))
@@ -98,6 +99,46 @@ class Plan:
                                          ctypes.c_void_p(stream.cuda_stream)))
         return out
 
+    def backward_workspace_bytes(self, B: int) -> int:
+        out = ctypes.c_uint64()
+        N.check(self._lib.qgm_backward_workspace_bytes(self._h, int(B), ctypes.byref(out)))
+        return int(out.value)
+
+    def backward(self, bits, grad_amps, gate_vals=None, *, workspace=None, stream=None, want_amps=True):
+        """Gradient with respect to gate_vals of a real loss whose torch gradient
+        with respect to the amplitudes is grad_amps ([B, 2^n_open] complex).
+        Returns (amps or None, gate_grads [n_slots, 2, 2] complex64)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if isinstance(bits, np.ndarray):
+            bits = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint64).view(np.int64))
+        bits = bits.to(dev).contiguous()
+        B = int(bits.shape[0])
+        n_out = 1 << len(self.open_qubits)
+        g = torch.as_tensor(grad_amps).to(dev, torch.complex64).reshape(B, n_out).contiguous()
+        gv = None
+        if self.n_slots:
+            if gate_vals is None:
+                raise ValueError("this circuit reads gate_vals")
+            gv = torch.as_tensor(gate_vals).to(dev, torch.complex64).contiguous()
+            if tuple(gv.shape) != (self.n_slots, 2, 2):
+                raise ValueError("gate_vals must be [n_slots, 2, 2]")
+        grads = torch.zeros((max(self.n_slots, 1), 2, 2), dtype=torch.complex64, device=dev)
+        odt = torch.complex128 if self.out_c128 else torch.complex64
+        amps = torch.empty((B, n_out), dtype=odt, device=dev) if want_amps else None
+        need = self.backward_workspace_bytes(B)
+        if workspace is None:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        if workspace.numel() < need:
+            raise ValueError("workspace too small")
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self._lib.qgm_backward(self._h, None if gv is None else gv.data_ptr(), bits.data_ptr(), B,
+                                       g.data_ptr(), None if amps is None else amps.data_ptr(),
+                                       grads.data_ptr() if self.n_slots else None,
+                                       workspace.data_ptr(), workspace.numel(), ctypes.c_void_p(stream.cuda_stream)))
+        return amps, grads[:self.n_slots]
+
     def set_timing(self, enable: bool) -> None:
         N.check(self._lib.qgm_plan_set_timing(self._h, 1 if enable else 0))
 
@@ -127,3 +168,38 @@ def sync_check(stream=None) -> None:
     if stream is None:
         stream = torch.cuda.current_stream()
     N.check(N.lib().qgm_sync_check(ctypes.c_void_p(stream.cuda_stream)))
+
+
+def _autograd_function():
+    import torch
+
+    class QGMAmplitudes(torch.autograd.Function):
+        """amps = QGMAmplitudes.apply(gate_vals, bits, plan): complex64 [B, 2^n_open]
+        differentiable with respect to gate_vals [n_slots, 2, 2] (complex64).
+        The backward pass calls qgm_backward, which recomputes the forward with
+        checkpoints instead of keeping the frontier tensors alive in between."""
+
+        @staticmethod
+        def forward(ctx, gate_vals, bits, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(gate_vals, bits)
+            return plan.amplitudes(bits, gate_vals.detach())
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            gate_vals, bits = ctx.saved_tensors
+            _, grads = ctx.plan.backward(bits, grad_out, gate_vals.detach(), want_amps=False)
+            return grads.to(gate_vals.dtype), None, None
+
+    return QGMAmplitudes
+
+
+_QGM_FN = None
+
+
+def amplitudes_autograd(gate_vals, bits, p: Plan):
+    """Differentiable amplitudes (see QGMAmplitudes)."""
+    global _QGM_FN
+    if _QGM_FN is None:
+        _QGM_FN = _autograd_function()
+    return _QGM_FN.apply(gate_vals, bits, p)

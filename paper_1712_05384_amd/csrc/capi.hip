@@ -2,6 +2,7 @@
 // amplitude executor that enqueues the step kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -17,6 +18,12 @@ struct qgm_plan_s {
     uint32_t max_g_entries = 0;
     // offsets (bytes) of the constant tables inside each device copy
     size_t off_fixed = 0, off_steps = 0, off_ops = 0, off_sig = 0, off_final = 0, total = 0;
+    // adjoint tables: per-step wave offsets of the G-entry waves, per-slot (step, op) lists
+    size_t off_wave_base = 0, off_step_waves = 0, off_slot_off = 0, off_slot_ops = 0;
+    std::vector<int64_t> wave_base;
+    std::vector<int32_t> step_waves, slot_off, slot_ops;
+    int64_t total_waves = 0;
+    int max_ops = 1;
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -65,7 +72,36 @@ void layout_tables(qgm_plan_t* P) {
     P->off_ops = P->off_steps + al(sizeof(qgm::StepTab) * p.steps.size());
     P->off_sig = P->off_ops + al(sizeof(qgm::GOp) * size_t(p.n_ops_total));
     P->off_final = P->off_sig + al(sizeof(int32_t) * (n_sig + 1));
-    P->total = P->off_final + al(sizeof(int32_t) * (p.final_pos.size() + 1));
+    // adjoint tables
+    P->wave_base.clear();
+    P->step_waves.clear();
+    P->total_waves = 0;
+    P->max_ops = 1;
+    std::vector<std::vector<int32_t>> per_slot(std::max(p.n_slots, 0));
+    for (size_t s = 0; s < p.steps.size(); ++s) {
+        const qgm::Step& st = p.steps[s];
+        const int64_t waves = (st.g_entries() + 63) / 64;
+        P->wave_base.push_back(P->total_waves);
+        P->step_waves.push_back(int32_t(waves));
+        P->total_waves += waves;
+        P->max_ops = std::max(P->max_ops, int(st.ops.size()));
+        for (size_t i = 0; i < st.ops.size(); ++i) {
+            const qgm::GOp& op = st.ops[i];
+            if ((op.type == qgm::GOP_MAT || op.type == qgm::GOP_DIAG) && op.mat >= qgm::kFixedMats)
+                per_slot[op.mat - qgm::kFixedMats].push_back(int32_t(s << 16) | int32_t(i));
+        }
+    }
+    P->slot_off.assign(1, 0);
+    P->slot_ops.clear();
+    for (auto& v : per_slot) {
+        for (int32_t x : v) P->slot_ops.push_back(x);
+        P->slot_off.push_back(int32_t(P->slot_ops.size()));
+    }
+    P->off_wave_base = P->off_final + al(sizeof(int32_t) * (p.final_pos.size() + 1));
+    P->off_step_waves = P->off_wave_base + al(sizeof(int64_t) * (P->wave_base.size() + 1));
+    P->off_slot_off = P->off_step_waves + al(sizeof(int32_t) * (P->step_waves.size() + 1));
+    P->off_slot_ops = P->off_slot_off + al(sizeof(int32_t) * (P->slot_off.size() + 1));
+    P->total = P->off_slot_ops + al(sizeof(int32_t) * (P->slot_ops.size() + 1));
     P->max_g_entries = 0;
     for (auto& st : p.steps) P->max_g_entries = std::max<uint32_t>(P->max_g_entries, uint32_t(st.g_entries()));
 }
@@ -98,6 +134,10 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
         for (int x : st.sig_src) sig[sig_off++] = x;
     }
     for (size_t i = 0; i < p.final_pos.size(); ++i) fin[i] = p.final_pos[i];
+    std::memcpy(h + P->off_wave_base, P->wave_base.data(), sizeof(int64_t) * P->wave_base.size());
+    std::memcpy(h + P->off_step_waves, P->step_waves.data(), sizeof(int32_t) * P->step_waves.size());
+    std::memcpy(h + P->off_slot_off, P->slot_off.data(), sizeof(int32_t) * P->slot_off.size());
+    std::memcpy(h + P->off_slot_ops, P->slot_ops.data(), sizeof(int32_t) * P->slot_ops.size());
     void* d = nullptr;
     e = hipMalloc(&d, P->total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
@@ -106,6 +146,91 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     P->p.dev.push_back({dev, d});
     *base = static_cast<char*>(d);
     return QGM_OK;
+}
+
+qgm::StepParams step_params(const qgm::Step& stp) {
+    qgm::StepParams sp{};
+    sp.kb = stp.kb; sp.vb = stp.vb; sp.nb = stp.nb; sp.sb = stp.sb;
+    sp.row_bits = stp.r_in - stp.kb;
+    sp.input_is_one = stp.input_is_one ? 1 : 0;
+    for (int j = 0; j < stp.kb; ++j) sp.kpos[j] = stp.kpos[j];
+    for (int j = 0; j < stp.vb; ++j) sp.vpos[j] = stp.vpos[j];
+    sp.g_off = stp.g_off;
+    sp.pair_bit = stp.pair_bit;
+    sp.pair_in = stp.pair_in;
+    return sp;
+}
+
+// Enqueues forward step i reading fin and writing fout.
+void forward_step(const qgm::Step& stp, const float2* fin, float2* fout, const uint16_t* vs, const float2* gtab,
+                  uint32_t B_eff, hipStream_t s) {
+    const qgm::StepParams sp = step_params(stp);
+    if (stp.kclass == 1) {
+        qgm::DenseParams dp{};
+        dp.sp = sp;
+        for (int j = 0; j < 4; ++j) dp.inner_pos[j] = stp.inner_pos[j];
+        dp.n_outer = int32_t(stp.outer_pos.size());
+        for (int j = 0; j < dp.n_outer; ++j) dp.outer_pos[j] = stp.outer_pos[j];
+        qgm::launch_dense(dp, fin, fout, vs, gtab, B_eff, s);
+    } else {
+        qgm::launch_step(sp, fin, fout, vs, gtab, B_eff, s);
+    }
+}
+
+// Gbar work split for one step at batch B_eff: 8-wide k and n slices, and
+// row chunks so that the partial-product kernel has about 2^18 threads.
+qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
+    qgm::GbarParams gp{};
+    gp.sp = step_params(stp);
+    const int K = 1 << stp.kb, N = 1 << stp.nb;
+    gp.kw = std::min(K, 8);
+    gp.nw = std::min(N, 8);
+    gp.n_kc = K / gp.kw;
+    gp.n_nc = N / gp.nw;
+    std::vector<int> vp(stp.vpos.begin(), stp.vpos.end());
+    const int row_bits = stp.r_in - stp.kb;
+    gp.n_free = 0;
+    for (int pos = 0; pos < row_bits; ++pos)
+        if (std::find(vp.begin(), vp.end(), pos) == vp.end()) gp.free_pos[gp.n_free++] = pos;
+    const int64_t base_units = int64_t(gp.n_kc) * gp.n_nc << stp.vb;
+    int64_t n_rc = 1;
+    while (n_rc * 2 <= (int64_t(1) << gp.n_free) && base_units * n_rc * 2 * B_eff <= (int64_t(1) << 18) &&
+           base_units * n_rc * 2 <= 65535)
+        n_rc *= 2;
+    gp.n_rc = int32_t(n_rc);
+    gp.rc_rows = int32_t((int64_t(1) << gp.n_free) / n_rc);
+    return gp;
+}
+
+struct BwdLayout {
+    uint64_t frame = 0;
+    int c = 1, n_ck = 0;
+    uint64_t frames = 0, vids = 0, g = 0, gbar = 0, part = 0, wpart = 0, total = 0;
+};
+
+BwdLayout backward_layout(const qgm_plan_t* P, int64_t B) {
+    const qgm::Plan& p = P->p;
+    BwdLayout L;
+    const int S = int(p.steps.size());
+    const uint64_t be = uint64_t(qgm::batch_eff(p, B));
+    L.frame = al((uint64_t(1) << p.r_max) * be * 8);
+    L.c = p.opts.checkpoint_every > 0 ? p.opts.checkpoint_every : std::max(1, int(std::ceil(std::sqrt(double(S)))));
+    L.n_ck = (S - 1) / L.c;
+    const uint64_t n_frames = 4 + uint64_t(L.n_ck) + uint64_t(L.c - 1);
+    L.frames = 0;
+    L.vids = n_frames * L.frame;
+    L.g = L.vids + al(uint64_t(S) * be * 2);
+    L.gbar = L.g + al(uint64_t(p.g_total) * 8);
+    L.part = L.gbar + al(uint64_t(p.g_total) * 16);
+    uint64_t part_bytes = 0;
+    for (auto& st : p.steps) {
+        const qgm::GbarParams gp = gbar_params(st, uint32_t(be));
+        const uint64_t units = uint64_t(gp.n_nc) * gp.n_kc * gp.n_rc << st.vb;
+        part_bytes = std::max(part_bytes, units * 64 * be * 8);
+    }
+    L.wpart = L.part + al(part_bytes);
+    L.total = L.wpart + al(uint64_t(P->total_waves) * uint64_t(P->max_ops) * 4 * 16);
+    return L;
 }
 
 }  // namespace
@@ -217,33 +342,107 @@ qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_
                         reinterpret_cast<const double2*>(tables + plan->off_fixed),
                         static_cast<const float2*>(gate_vals), gtab, s);
     mark(2);
-    for (int i = 0; i < n_steps; ++i) {
-        const qgm::Step& stp = p.steps[i];
-        qgm::StepParams sp{};
-        sp.kb = stp.kb; sp.vb = stp.vb; sp.nb = stp.nb; sp.sb = stp.sb;
-        sp.row_bits = stp.r_in - stp.kb;
-        sp.input_is_one = stp.input_is_one ? 1 : 0;
-        for (int j = 0; j < stp.kb; ++j) sp.kpos[j] = stp.kpos[j];
-        for (int j = 0; j < stp.vb; ++j) sp.vpos[j] = stp.vpos[j];
-        sp.g_off = stp.g_off;
-        sp.pair_bit = stp.pair_bit;
-        sp.pair_in = stp.pair_in;
-        const uint16_t* vs = vids + size_t(i) * size_t(B_eff);
-        if (stp.kclass == 1) {
-            qgm::DenseParams dp{};
-            dp.sp = sp;
-            for (int j = 0; j < 4; ++j) dp.inner_pos[j] = stp.inner_pos[j];
-            dp.n_outer = int32_t(stp.outer_pos.size());
-            for (int j = 0; j < dp.n_outer; ++j) dp.outer_pos[j] = stp.outer_pos[j];
-            qgm::launch_dense(dp, F[i & 1], F[(i + 1) & 1], vs, gtab, uint32_t(B_eff), s);
-        } else {
-            qgm::launch_step(sp, F[i & 1], F[(i + 1) & 1], vs, gtab, uint32_t(B_eff), s);
-        }
-    }
+    for (int i = 0; i < n_steps; ++i)
+        forward_step(p.steps[i], F[i & 1], F[(i + 1) & 1], vids + size_t(i) * size_t(B_eff), gtab, uint32_t(B_eff), s);
     mark(3);
     qgm::launch_finalize(F[n_steps & 1], uint32_t(B_eff), uint32_t(B_pad), B, int(1 << p.sliced.size()), p.n_open,
                          reinterpret_cast<const int32_t*>(tables + plan->off_final), out, p.opts.out_c128 != 0, s);
     mark(4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
+qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes) {
+    g_err.clear();
+    if (!plan || !bytes) return fail(QGM_E_INVALID, "plan or bytes is NULL");
+    if (B < 0) return fail(QGM_E_INVALID, "B < 0");
+    *bytes = backward_layout(plan, B).total;
+    return QGM_OK;
+}
+
+qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
+                        const void* grad_amps, void* amps_out, void* gate_grads, void* workspace, uint64_t ws_bytes,
+                        void* stream) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    if (B < 0) return fail(QGM_E_INVALID, "B < 0");
+    const qgm::Plan& p = plan->p;
+    if (B == 0) return QGM_OK;
+    if (!bits || !grad_amps || !workspace || (p.n_slots > 0 && (!gate_vals || !gate_grads)))
+        return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "
+                                   "must be device pointers");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
+    if (p.n_open > 16) return fail(QGM_E_UNSUPPORTED, "qgm_backward supports at most 16 open qubits");
+    const int64_t B_pad = qgm::padded_batch(B);
+    const int64_t B_eff = qgm::batch_eff(p, B);
+    if (B_eff > (int64_t(1) << 26)) return fail(QGM_E_UNSUPPORTED, "batch times slice count exceeds 2^26");
+    if ((int64_t(1) << p.r_max) * (B_eff / 64) > (int64_t(1) << 31))
+        return fail(QGM_E_UNSUPPORTED, "frontier rows times batch blocks exceed 2^31");
+    const BwdLayout L = backward_layout(plan, B);
+    if (ws_bytes < L.total) return fail(QGM_E_OOM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    char* tables = nullptr;
+    qgm_status st = device_tables(plan, &tables);
+    if (st != QGM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    auto frame = [&](uint64_t i) { return reinterpret_cast<float2*>(ws + L.frames + i * L.frame); };
+    float2* fwd[2] = {frame(0), frame(1)};
+    float2* adj[2] = {frame(2), frame(3)};
+    auto ck = [&](int i) { return frame(4 + uint64_t(i)); };              // holds F_{(i+1)c}
+    auto seg = [&](int j) { return frame(4 + uint64_t(L.n_ck) + uint64_t(j)); };
+    auto* vids = reinterpret_cast<uint16_t*>(ws + L.vids);
+    auto* gtab = reinterpret_cast<float2*>(ws + L.g);
+    auto* gbar = reinterpret_cast<double2*>(ws + L.gbar);
+    auto* part = reinterpret_cast<float2*>(ws + L.part);
+    auto* wpart = reinterpret_cast<double2*>(ws + L.wpart);
+    const auto* tabs = reinterpret_cast<const qgm::StepTab*>(tables + plan->off_steps);
+    const int S = int(p.steps.size());
+    const int c = L.c;
+    const uint32_t be = uint32_t(B_eff);
+    auto vs = [&](int i) { return vids + size_t(i) * size_t(B_eff); };
+    qgm::launch_boundary(bits, B, uint32_t(B_pad), be, S, tabs, reinterpret_cast<const int32_t*>(tables + plan->off_sig),
+                         vids, s);
+    qgm::launch_build_g(tabs, S, plan->max_g_entries, reinterpret_cast<const qgm::GOp*>(tables + plan->off_ops),
+                        reinterpret_cast<const double2*>(tables + plan->off_fixed),
+                        static_cast<const float2*>(gate_vals), gtab, s);
+    // forward, keeping F_s for s = c, 2c, ... (< S)
+    auto loc = [&](int i) -> float2* {   // where F_i lives after the forward (i >= 1)
+        if (i < S && i % c == 0) return ck(i / c - 1);
+        return fwd[i & 1];
+    };
+    for (int i = 0; i < S; ++i)
+        forward_step(p.steps[i], i == 0 ? fwd[0] : loc(i), loc(i + 1), vs(i), gtab, be, s);
+    if (amps_out)
+        qgm::launch_finalize(loc(S), be, uint32_t(B_pad), B, int(1 << p.sliced.size()), p.n_open,
+                             reinterpret_cast<const int32_t*>(tables + plan->off_final), amps_out,
+                             p.opts.out_c128 != 0, s);
+    // seed: Fbar_S = conj(grad_amps) on every slice copy
+    qgm::launch_seed(static_cast<const float2*>(grad_amps), be, uint32_t(B_pad), B, p.n_open,
+                     reinterpret_cast<const int32_t*>(tables + plan->off_final), adj[S & 1], s);
+    // backward over checkpoint segments [a, e)
+    for (int a = ((S - 1) / c) * c; a >= 0; a -= c) {
+        const int e = std::min(a + c, S);
+        const float2* fa = a == 0 ? fwd[0] : ck(a / c - 1);
+        for (int i = a; i + 1 < e; ++i)   // recompute F_{a+1} .. F_{e-1}
+            forward_step(p.steps[i], i == a ? fa : seg(i - a - 1), seg(i - a), vs(i), gtab, be, s);
+        for (int i = e - 1; i >= a; --i) {
+            const float2* fin = i == a ? fa : seg(i - a - 1);
+            const qgm::GbarParams gp = gbar_params(p.steps[i], be);
+            qgm::launch_gbar(gp, fin, adj[(i + 1) & 1], part, vs(i), be, gbar, s);
+            if (i > 0) qgm::launch_step_t(step_params(p.steps[i]), adj[(i + 1) & 1], adj[i & 1], vs(i), gtab, be, s);
+        }
+    }
+    if (p.n_slots > 0) {
+        qgm::launch_gadj(tabs, S, plan->max_g_entries, reinterpret_cast<const qgm::GOp*>(tables + plan->off_ops),
+                         reinterpret_cast<const double2*>(tables + plan->off_fixed), static_cast<const float2*>(gate_vals),
+                         gbar, reinterpret_cast<const int64_t*>(tables + plan->off_wave_base), wpart, plan->max_ops, s);
+        qgm::launch_slot_grads(reinterpret_cast<const int32_t*>(tables + plan->off_slot_off),
+                               reinterpret_cast<const int32_t*>(tables + plan->off_slot_ops),
+                               reinterpret_cast<const int64_t*>(tables + plan->off_wave_base),
+                               reinterpret_cast<const int32_t*>(tables + plan->off_step_waves), wpart, plan->max_ops,
+                               p.n_slots, static_cast<float2*>(gate_grads), s);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return QGM_OK;

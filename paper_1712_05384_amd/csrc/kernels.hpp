@@ -23,6 +23,16 @@ struct DenseParams {
     int32_t n_outer;
 };
 
+// Launch parameters of the Gbar partial-product kernel.
+struct GbarParams {
+    StepParams sp;
+    int32_t kw, nw;             // widths of the k and n slices (<= 8)
+    int32_t n_kc, n_nc, n_rc;   // number of k slices, n slices, row chunks
+    int32_t rc_rows;            // rows per chunk
+    int32_t n_free;             // row bits that are not V bits
+    int32_t free_pos[kMaxRank];
+};
+
 constexpr uint32_t kStepMaxGrid = 8192;           // work-groups of the step kernel (grid-stride beyond)
 constexpr uint32_t kDenseMaxGrid = 4096;          // work-groups of the matrix-core step kernel
 constexpr size_t kStepLdsBytes = 48 * 1024;       // G up to this size is staged in LDS
@@ -35,6 +45,18 @@ void launch_step(const StepParams& sp, const float2* fin, float2* fout, const ui
                  uint32_t B_eff, hipStream_t stream);
 void launch_dense(const DenseParams& dp, const float2* fin, float2* fout, const uint16_t* vids, const float2* gtab,
                   uint32_t B_eff, hipStream_t stream);
+void launch_step_t(const StepParams& sp, const float2* cbar, float2* abar, const uint16_t* vids, const float2* gtab,
+                   uint32_t B_eff, hipStream_t stream);
+void launch_gbar(const GbarParams& gp, const float2* a, const float2* cbar, float2* part, const uint16_t* vids,
+                 uint32_t B_eff, double2* gbar, hipStream_t stream);
+void launch_gadj(const StepTab* steps, int n_steps, uint32_t max_entries, const GOp* ops, const double2* fixed,
+                 const float2* slots, const double2* gbar, const int64_t* wave_base, double2* wpart, int max_ops,
+                 hipStream_t stream);
+void launch_slot_grads(const int32_t* slot_ops_off, const int32_t* slot_ops, const int64_t* wave_base,
+                       const int32_t* step_waves, const double2* wpart, int max_ops, int n_slots, float2* grads,
+                       hipStream_t stream);
+void launch_seed(const float2* g, uint32_t B_eff, uint32_t B_pad, int64_t B, int n_open, const int32_t* final_pos,
+                 float2* fbar, hipStream_t stream);
 void launch_finalize(const float2* f, uint32_t B_eff, uint32_t B_pad, int64_t B, int n_slices, int n_open,
                      const int32_t* final_pos, void* out, bool c128, hipStream_t stream);
 

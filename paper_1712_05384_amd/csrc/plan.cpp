@@ -276,6 +276,10 @@ static qgm_status build_steps(Plan& p, std::string* err) {
             }
         }
         emit(GOP_END, p.chain[q].back(), -1);
+        if (int(st.ops.size()) > kMaxOps) {
+            *err = "factor program of qubit " + std::to_string(q) + " is longer than " + std::to_string(kMaxOps) + " ops";
+            return QGM_E_UNSUPPORTED;
+        }
         if (src[p.chain[q].back()].src == SRC_INT) { *err = "internal: final variable summed"; return QGM_E_INTERNAL; }
         st.g_off = g_off;
         g_off += st.g_entries();

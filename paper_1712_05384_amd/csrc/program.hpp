@@ -42,6 +42,7 @@ constexpr int kMaxBits = 8;         // per-step bound on V bits, on sigma bits
 constexpr int kMaxNB = 10;
 constexpr int kMaxRank = 31;
 constexpr int kDenseMaxVariants = 16;  // matrix-core kernel: at most 2^4 operand variants per step
+constexpr int kMaxOps = 128;           // factor-program length per step (the G builder's adjoint keeps each state)
 
 // Per-step launch parameters (passed by value to the step kernel).
 struct StepParams {

@@ -1,0 +1,89 @@
+"""GPU gradients (adjoint of the elimination steps) against the FP64 oracle's
+adjoint-state gradient, the exact per-gate scaling identity, and finite
+differences.  Loss: L = sum_x log |A_x|^2 (m times the negative cross-entropy
+estimator of App. B, Eq. (cee)); torch convention dL/dRe U + i dL/dIm U."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_05384_amd import circuits as C
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GTOL = 1e-4   # relative Frobenius error over all gates
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_grad(c, bits, **kw):
+    import paper_1712_05384_amd as Q
+    p = Q.plan(c, **kw)
+    gv = torch.tensor(c.gate_vals.astype(np.complex64), device="cuda")
+    amps = p.amplitudes(bits, gv)
+    g_amps = 2.0 / torch.conj(amps)
+    a2, grads = p.backward(bits, g_amps, gv)
+    torch.cuda.synchronize()
+    return amps.cpu().numpy()[:, 0], a2.cpu().numpy()[:, 0], grads.cpu().numpy()
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,kw", [
+    (2, 2, 6, 1, {}), (3, 3, 10, 2, {}), (3, 4, 12, 3, {"checkpoint_every": 2}),
+    (4, 4, 12, 4, {"checkpoint_every": 1}), (3, 4, 10, 5, {"min_sliced_vars": 2}),
+    (4, 4, 16, 6, {"kernel_policy": 2}), (4, 3, 14, 7, {})])
+def test_gradient_matches_oracle(rows, cols, depth, seed, kw):
+    c = C.parameterised_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 100, seed)
+    _say("case %s %s" % (c.name, kw))
+    amps, amps2, got = _gpu_grad(c, bits, **kw)
+    vals = c.gate_vals.astype(np.complex64).astype(np.complex128)
+    _, ref = oracle.sv_log_prob_gradient(c.n, c.gates, vals, bits)
+    assert np.array_equal(amps, amps2)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say("  rel frobenius err %.3g" % rel)
+    assert rel <= GTOL
+    # exact identity: sum_ab U[a,b] conj(G[a,b]) = 2m for every gate (A is linear in U)
+    ident = np.einsum("sab,sab->s", vals, got.conj())
+    assert np.abs(ident - 2 * len(bits)).max() <= 1e-3 * 2 * len(bits)
+
+
+def test_c4_workload_gradient():
+    """5x5 depth 20, every single-qubit gate U(theta, n), 256 bitstrings."""
+    c, bits = C.workload("c4_5x5_d20_U")
+    _say("case c4 5x5 d20 B=256")
+    amps, _, got = _gpu_grad(c, bits)
+    vals = c.gate_vals.astype(np.complex64).astype(np.complex128)
+    ref_amps, ref = oracle.sv_log_prob_gradient(c.n, c.gates, vals, bits)
+    assert np.abs(amps - ref_amps).max() <= 1e-5 * 2 ** (-c.n / 2)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say("  c4 rel frobenius err %.3g" % rel)
+    assert rel <= GTOL
+
+
+def test_autograd_function_and_finite_difference():
+    import paper_1712_05384_amd as Q
+    c = C.parameterised_circuit(3, 3, 10, 9)
+    bits = torch.from_numpy(C.random_bitstrings(c.n, 64, 9).view(np.int64)).cuda()
+    p = Q.plan(c)
+    gv = torch.tensor(c.gate_vals.astype(np.complex64), device="cuda", requires_grad=True)
+    amps = Q.amplitudes_autograd(gv, bits, p)
+    loss = torch.log(amps.abs() ** 2).sum()
+    loss.backward()
+    g = gv.grad.detach().cpu().numpy()
+    # coarse finite difference in complex64 (smoke level, h = 1e-2)
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        s, a, b = rng.integers(0, c.n_slots), rng.integers(0, 2), rng.integers(0, 2)
+        for unit in (1.0, 1j):
+            vp = gv.detach().clone(); vp[s, a, b] += 1e-2 * unit
+            vm = gv.detach().clone(); vm[s, a, b] -= 1e-2 * unit
+            lp = torch.log(p.amplitudes(bits, vp).abs() ** 2).sum().item()
+            lm = torch.log(p.amplitudes(bits, vm).abs() ** 2).sum().item()
+            fd = (lp - lm) / 2e-2
+            an = g[s, a, b].real if unit == 1.0 else g[s, a, b].imag
+            assert abs(fd - an) <= 0.05 * max(1.0, abs(an)), (s, a, b, unit, fd, an)

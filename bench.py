@@ -34,6 +34,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_5x5_d25")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary workloads (C4 gradients, C3 sliced, C5 four-circuit graph)")
     ap.add_argument("--kernel-policy", type=int, default=0,
                     help="0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
     args = ap.parse_args()
@@ -110,6 +112,24 @@ def main() -> int:
         "roofline": roofline,
     }
 
+    # the same call replayed from a HIP graph (no per-launch host work)
+    g = Q.Graph([p], [bits_d], [gv])
+    for _ in range(args.warmup):
+        g.launch(stream)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g.launch(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    result["graph_ms_per_step"] = round(ev0.elapsed_time(ev1) / args.steps, 5)
+    result["graph_amplitudes_per_sec"] = round(B / (result["graph_ms_per_step"] / 1e3), 1)
+    assert torch.equal(g.outs[0], out), "graph replay differs from the eager call"
+    del g
+
+    if not args.no_extras:
+        result["extras"] = extras(Q, C, torch, np, stream, args)
+
     if not args.no_cpu_baseline and c.n <= 30:
         import oracle
         got = out.cpu().numpy()[:, 0]
@@ -135,6 +155,65 @@ def main() -> int:
         result["tolerance_x_2^(n/2)"] = 1e-5
     print(json.dumps(result), flush=True)
     return 0
+
+
+def _time(fn, reps, stream, torch):
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras(Q, C, torch, np, stream, args):
+    """Secondary workloads, timed the same way (inputs resident, HIP events)."""
+    out = {}
+    dev = torch.device("cuda", 0)
+    # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2
+    c, bits = C.workload("c4_5x5_d20_U")
+    p = Q.plan(c)
+    gv = torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
+    bd = torch.from_numpy(bits.view(np.int64)).to(dev)
+    amps = p.amplitudes(bd, gv)
+    gamps = (2.0 / torch.conj(amps)).contiguous()
+    ws = torch.empty(p.backward_workspace_bytes(len(bits)), dtype=torch.uint8, device=dev)
+    ms = _time(lambda: p.backward(bd, gamps, gv, workspace=ws, stream=stream), 10, stream, torch)
+    msf = _time(lambda: p.amplitudes(bd, gv, stream=stream), 10, stream, torch)
+    out["c4_grad"] = {"workload": "5x5 depth 20, every 1q gate U(theta, n), 256 bitstrings, d(sum log p)/dU for "
+                                  f"{c.n_slots} gate tensors, checkpointed", "grad_evals_per_sec": round(1e3 / ms, 2),
+                      "ms_per_grad_eval": round(ms, 4), "ms_forward_only": round(msf, 4)}
+    print(f"# c4 gradient: {ms:.3f} ms per evaluation (forward alone {msf:.3f} ms)", file=sys.stderr, flush=True)
+    del ws
+    # 5x6 depth 30, 2 sliced variables, FP64 slice sum
+    c, bits = C.workload("c3_5x6_d30")
+    p = Q.plan(c, min_sliced_vars=2, out_c128=True)
+    bd = torch.from_numpy(bits.view(np.int64)).to(dev)
+    g = Q.Graph([p], [bd])
+    ms = _time(lambda: g.launch(stream), 5, stream, torch)
+    out["c3_sliced"] = {"workload": "5x6 depth 30, 1024 bitstrings, 2 sliced variables, FP64 slice sum",
+                        "amplitudes_per_sec": round(len(bits) / (ms / 1e3), 1), "ms_per_call": round(ms, 4),
+                        "bytes_per_amp": p.info(0)["bytes_per_amp"]}
+    print(f"# c3 sliced: {ms:.3f} ms per 1024 amplitudes", file=sys.stderr, flush=True)
+    del g
+    # uneven batch: 4x5 d20, 5x5 d24, 6x6 d24, 6x7 d27, 1024 bitstrings each, one graph
+    names = ("c5_4x5_d20", "c5_5x5_d24", "c5_6x6_d24", "c5_6x7_d27")
+    cs, bs = zip(*[C.workload(nm) for nm in names])
+    plans = [Q.plan(ci) for ci in cs]
+    g = Q.Graph(plans, list(bs))
+    ms = _time(lambda: g.launch(stream), 3, stream, torch)
+    total = sum(len(b) for b in bs)
+    out["c5_graph"] = {"workload": "4x5 d20 + 5x5 d24 + 6x6 d24 + 6x7 d27, 1024 bitstrings each, one HIP graph "
+                                   "with one branch per circuit", "amplitudes_per_sec": round(total / (ms / 1e3), 1),
+                       "ms_per_launch": round(ms, 4)}
+    print(f"# c5 graph: {ms:.3f} ms per launch ({total} amplitudes)", file=sys.stderr, flush=True)
+    del g
+    return out
 
 
 if __name__ == "__main__":

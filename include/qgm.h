@@ -169,6 +169,26 @@ qgm_status qgm_plan_set_timing(qgm_plan_t* plan, int32_t enable);
  * phase holds n_steps kernel launches per call. */
 qgm_status qgm_plan_timings(qgm_plan_t* plan, double* ms, int64_t* n_calls);
 
+/* ---- Multi-circuit batches: one HIP graph for several plans ---------------
+ * qgm_graph_create records the complete qgm_amplitudes launch sequence of
+ * n_circ independent (plan, batch) pairs into one HIP graph, one branch per
+ * circuit (the branches fork from and join back to a common node, so the
+ * device may run small circuits beside large ones), and instantiates it.
+ * The buffers are fixed at creation: every later qgm_graph_launch recomputes
+ * out[i] from the current contents of bits[i] and gate_vals[i].  All arrays
+ * are host arrays of length n_circ; the pointers they hold follow the rules of
+ * qgm_amplitudes (workspaces must not be shared between circuits).  Creation
+ * uploads missing plan tables first and captures on private streams; it does
+ * not launch anything.  A graph must not outlive its plans or buffers. */
+typedef struct qgm_graph_s qgm_graph_t;
+qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void* const* gate_vals,
+                            const uint64_t* const* bits, const int64_t* B, void* const* out,
+                            void* const* workspace, const uint64_t* ws_bytes, qgm_graph_t** graph);
+/* Enqueues one replay of the graph on `stream`. */
+qgm_status qgm_graph_launch(qgm_graph_t* graph, void* stream);
+/* Destroys the graph (NULL is ignored). */
+void qgm_graph_destroy(qgm_graph_t* graph);
+
 /* Destroys a plan and frees its device tables (NULL is ignored). */
 void qgm_plan_destroy(qgm_plan_t* plan);
 

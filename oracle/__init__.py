@@ -10,7 +10,9 @@ Contents
                   over the C library sv_oracle.c
   brute_force.py  tiny exhaustive sums: Eq. (psi_x) over all worldline
                   variables, and the Ising-phase form of App. F
+  bucket.py       bucket elimination of App. A in FP64 (for n > 30)
 """
 from .gates import gate_matrix, KIND_H, KIND_T, KIND_XH, KIND_YH, KIND_CZ, KIND_U, KIND_UD  # noqa: F401
 from .statevector import sv_state, sv_amplitudes, sv_vjp, sv_log_prob_gradient, build_library  # noqa: F401
 from .brute_force import path_sum_amplitude, ising_amplitude  # noqa: F401
+from .bucket import bucket_amplitude, bucket_amplitudes  # noqa: F401

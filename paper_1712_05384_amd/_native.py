@@ -13,8 +13,9 @@ STATUS_NAMES = {0: "QGM_OK", -1: "QGM_E_INVALID", -2: "QGM_E_UNSUPPORTED", -3: "
 
 # Every symbol include/qgm.h declares.
 EXPORTED = ("qgm_default_opts", "qgm_plan", "qgm_plan_info", "qgm_workspace_bytes", "qgm_amplitudes",
-            "qgm_backward_workspace_bytes", "qgm_backward", "qgm_plan_set_timing", "qgm_plan_timings",
-            "qgm_plan_destroy", "qgm_last_error", "qgm_sync_check")
+            "qgm_backward_workspace_bytes", "qgm_backward", "qgm_graph_create", "qgm_graph_launch",
+            "qgm_graph_destroy", "qgm_plan_set_timing", "qgm_plan_timings", "qgm_plan_destroy", "qgm_last_error",
+            "qgm_sync_check")
 
 
 class QgmGate(ctypes.Structure):
@@ -60,6 +61,12 @@ def lib():
         L.qgm_amplitudes.argtypes = [P, P, P, ctypes.c_int64, P, P, ctypes.c_uint64, P]
         L.qgm_backward_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
         L.qgm_backward.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_uint64, P]
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.qgm_graph_create.argtypes = [ctypes.c_int32, PP, PP, PP, ctypes.POINTER(ctypes.c_int64), PP, PP,
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(P)]
+        L.qgm_graph_launch.argtypes = [P, P]
+        L.qgm_graph_destroy.argtypes = [P]
+        L.qgm_graph_destroy.restype = None
         L.qgm_plan_set_timing.argtypes = [P, ctypes.c_int32]
         L.qgm_plan_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.qgm_plan_destroy.argtypes = [P]
@@ -68,7 +75,8 @@ def lib():
         L.qgm_last_error.restype = ctypes.c_char_p
         L.qgm_sync_check.argtypes = [P]
         for f in (L.qgm_plan, L.qgm_plan_info, L.qgm_workspace_bytes, L.qgm_amplitudes, L.qgm_sync_check,
-                  L.qgm_plan_set_timing, L.qgm_plan_timings, L.qgm_backward_workspace_bytes, L.qgm_backward):
+                  L.qgm_plan_set_timing, L.qgm_plan_timings, L.qgm_backward_workspace_bytes, L.qgm_backward,
+                  L.qgm_graph_create, L.qgm_graph_launch):
             f.restype = ctypes.c_int
         _lib = L
     return _lib

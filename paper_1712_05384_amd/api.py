@@ -155,6 +155,58 @@ class Plan:
             self._h = None
 
 
+class Graph:
+    """One HIP graph replaying the amplitude computation of several
+    (plan, bits, gate_vals) batches, one concurrent branch per circuit
+    (qgm_graph_create).  Buffers are allocated here and fixed for the graph's
+    life; launch() recomputes self.outs[i] from self.bits[i]."""
+
+    def __init__(self, plans, bits_list, gate_vals_list=None):
+        import torch
+        self._lib = N.lib()
+        self._h = None
+        dev = torch.device("cuda", torch.cuda.current_device())
+        n = len(plans)
+        self.plans = list(plans)
+        self.bits, self.outs, self.workspaces, self.gate_vals = [], [], [], []
+        for i, p in enumerate(self.plans):
+            b = bits_list[i]
+            if isinstance(b, np.ndarray):
+                b = torch.from_numpy(np.ascontiguousarray(b, dtype=np.uint64).view(np.int64))
+            b = b.to(dev).contiguous()
+            self.bits.append(b)
+            B = int(b.shape[0])
+            odt = torch.complex128 if p.out_c128 else torch.complex64
+            self.outs.append(torch.empty((B, 1 << len(p.open_qubits)), dtype=odt, device=dev))
+            self.workspaces.append(torch.empty(max(p.workspace_bytes(B), 256), dtype=torch.uint8, device=dev))
+            gv = None if gate_vals_list is None else gate_vals_list[i]
+            self.gate_vals.append(None if gv is None else torch.as_tensor(gv).to(dev, torch.complex64).contiguous())
+        VP = ctypes.c_void_p * n
+        ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        hp = VP(*[p.handle.value for p in self.plans])
+        gp = VP(*[ptr(g) for g in self.gate_vals])
+        bp = VP(*[ptr(b) for b in self.bits])
+        Bs = (ctypes.c_int64 * n)(*[int(b.shape[0]) for b in self.bits])
+        op = VP(*[ptr(o) for o in self.outs])
+        wp = VP(*[ptr(w) for w in self.workspaces])
+        wb = (ctypes.c_uint64 * n)(*[w.numel() for w in self.workspaces])
+        h = ctypes.c_void_p()
+        N.check(self._lib.qgm_graph_create(n, hp, gp, bp, Bs, op, wp, wb, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        N.check(self._lib.qgm_graph_launch(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        return self.outs
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.qgm_graph_destroy(self._h)
+            self._h = None
+
+
 def plan(circuit, open_qubits=(), **opts) -> Plan:
     return Plan(circuit, open_qubits, **opts)
 

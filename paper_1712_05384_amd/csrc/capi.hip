@@ -13,6 +13,11 @@
 #include "plan.hpp"
 #include "qgm.h"
 
+struct qgm_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct qgm_plan_s {
     qgm::Plan p;
     uint32_t max_g_entries = 0;
@@ -446,6 +451,84 @@ qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return QGM_OK;
+}
+
+qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void* const* gate_vals,
+                            const uint64_t* const* bits, const int64_t* B, void* const* out,
+                            void* const* workspace, const uint64_t* ws_bytes, qgm_graph_t** graph) {
+    g_err.clear();
+    if (!graph) return fail(QGM_E_INVALID, "graph is NULL");
+    *graph = nullptr;
+    if (n_circ < 1 || !plans || !bits || !B || !out || !workspace || !ws_bytes)
+        return fail(QGM_E_INVALID, "n_circ >= 1 and every array must be given");
+    for (int i = 0; i < n_circ; ++i) {
+        if (!plans[i]) return fail(QGM_E_INVALID, "plan " + std::to_string(i) + " is NULL");
+        if (plans[i]->p.n_slots > 0 && (!gate_vals || !gate_vals[i]))
+            return fail(QGM_E_INVALID, "circuit " + std::to_string(i) + " reads gate_vals but it is NULL");
+        const qgm::WsLayout w = qgm::workspace_layout(plans[i]->p, B[i]);
+        if (ws_bytes[i] < w.total) return fail(QGM_E_OOM, "workspace of circuit " + std::to_string(i) + " too small");
+        for (int j = 0; j < i; ++j)
+            if (workspace[j] == workspace[i]) return fail(QGM_E_INVALID, "circuits must not share a workspace");
+        char* t = nullptr;
+        qgm_status st = device_tables(plans[i], &t);   // no allocation may happen during capture
+        if (st != QGM_OK) return st;
+    }
+    std::vector<hipStream_t> streams(n_circ + 1, nullptr);
+    std::vector<hipEvent_t> events(n_circ + 1, nullptr);
+    qgm_status result = QGM_OK;
+    hipGraph_t g = nullptr;
+    auto cleanup = [&]() {
+        for (auto e : events) if (e) (void)hipEventDestroy(e);
+        for (auto s : streams) if (s) (void)hipStreamDestroy(s);
+    };
+    for (int i = 0; i <= n_circ; ++i) {
+        hipError_t e = hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&events[i], hipEventDisableTiming);
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "stream/event creation"); }
+    }
+    std::vector<bool> timing(n_circ);
+    for (int i = 0; i < n_circ; ++i) { timing[i] = plans[i]->timing; plans[i]->timing = false; }
+    hipError_t e = hipStreamBeginCapture(streams[0], hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipStreamBeginCapture"); }
+    (void)hipEventRecord(events[0], streams[0]);
+    for (int i = 0; i < n_circ && result == QGM_OK; ++i) {
+        (void)hipStreamWaitEvent(streams[i + 1], events[0], 0);
+        result = qgm_amplitudes(plans[i], gate_vals ? gate_vals[i] : nullptr, bits[i], B[i], out[i], workspace[i],
+                                ws_bytes[i], streams[i + 1]);
+        (void)hipEventRecord(events[i + 1], streams[i + 1]);
+        (void)hipStreamWaitEvent(streams[0], events[i + 1], 0);
+    }
+    e = hipStreamEndCapture(streams[0], &g);
+    for (int i = 0; i < n_circ; ++i) plans[i]->timing = timing[i];
+    const std::string amp_err = g_err;
+    cleanup();
+    if (result != QGM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(result, amp_err);
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    auto* G = new (std::nothrow) qgm_graph_t;
+    if (!G) { (void)hipGraphDestroy(g); return fail(QGM_E_OOM, "out of host memory"); }
+    G->graph = g;
+    e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); delete G; return hip_fail(e, "hipGraphInstantiate"); }
+    *graph = G;
+    return QGM_OK;
+}
+
+qgm_status qgm_graph_launch(qgm_graph_t* graph, void* stream) {
+    g_err.clear();
+    if (!graph || !graph->exec) return fail(QGM_E_INVALID, "graph is NULL");
+    hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return QGM_OK;
+}
+
+void qgm_graph_destroy(qgm_graph_t* graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 qgm_status qgm_plan_set_timing(qgm_plan_t* plan, int32_t enable) {

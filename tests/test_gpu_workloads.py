@@ -1,0 +1,110 @@
+"""Full-size workloads on the GPU: the 5x6 depth-30 circuit (sliced, FP64 slice
+sum) against stored oracle amplitudes, and the uneven four-circuit batch run
+as one HIP graph, against the state vector (n <= 25) or the FP64 bucket
+elimination oracle (n = 36, 42) plus Porter-Thomas statistics."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_05384_amd import circuits as C
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EULER_GAMMA = 0.5772156649015329
+C5 = ("c5_4x5_d20", "c5_5x5_d24", "c5_6x6_d24", "c5_6x7_d27")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_c3_sliced_against_stored_oracle():
+    """5x6 depth 30, 1024 bitstrings, 2 sliced variables summed in FP64 on the
+    GPU, complex128 output; the stored values come from the FP64 state vector
+    (tests/golden/make_golden.py)."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c3_5x6_d30")
+    ref = np.load(os.path.join(GOLDEN, "c3_5x6_d30_amps.npy"), allow_pickle=False)
+    _say("case c3 5x6 d30 B=1024 slices=2")
+    p = Q.plan(c, min_sliced_vars=2, out_c128=True)
+    assert p.info(0)["n_sliced"] == 2
+    got = p.amplitudes(bits).cpu().numpy()[:, 0]
+    err = np.abs(got - ref).max()
+    _say("  c3 max err * 2^(n/2) = %.3g" % (err * 2 ** (c.n / 2)))
+    assert err <= TOL * 2 ** (-c.n / 2)
+    # unsliced plan agrees with the sliced one to rounding
+    got0 = Q.plan(c).amplitudes(bits).cpu().numpy()[:, 0]
+    assert np.abs(got0 - got).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_graph_replays_match_eager():
+    """Several circuits in one graph; every replay (with eager work and
+    synchronisation in between) equals the eager result bit for bit."""
+    import paper_1712_05384_amd as Q
+    circs = [C.random_grid_circuit(3, 4, 12, 1), C.random_grid_circuit(4, 4, 16, 2),
+             C.parameterised_circuit(3, 3, 10, 3), C.random_grid_circuit(2, 3, 8, 4)]
+    opens = [(), (1, 5), (), (0,)]
+    plans = [Q.plan(c, o) for c, o in zip(circs, opens)]
+    bits = [C.random_bitstrings(c.n, B, i) for i, (c, B) in enumerate(zip(circs, (64, 130, 50, 1)))]
+    gvs = [None if c.gate_vals is None else c.gate_vals.astype(np.complex64) for c in circs]
+    eager = [p.amplitudes(b, g).cpu().numpy() for p, b, g in zip(plans, bits, gvs)]
+    g = Q.Graph(plans, bits, gvs)
+    for rep in range(3):
+        outs = [o.cpu().numpy() for o in g.launch()]
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert np.array_equal(o, e), rep
+        plans[1].amplitudes(bits[1])          # eager work between replays
+        torch.cuda.synchronize()
+
+
+def _pt_checks(amps, n):
+    m = len(amps)
+    Np = (2.0 ** n) * np.abs(amps) ** 2
+    assert abs(Np.mean() - 1) <= 5 / np.sqrt(m)
+    assert abs((Np ** 2).mean() - 2) <= 5 * 4.47 / np.sqrt(m)
+    assert abs(np.log(Np).mean() + EULER_GAMMA) <= 5 * 1.28 / np.sqrt(m)
+
+
+def test_c5_uneven_batch_in_one_graph():
+    """4x5 d20, 5x5 d24, 6x6 d24, 6x7 d27 with 1024 bitstrings each, one graph."""
+    import paper_1712_05384_amd as Q
+    cs, bs = zip(*[C.workload(nm) for nm in C5])
+    plans = [Q.plan(c) for c in cs]
+    _say("case c5 graph of 4 circuits x 1024")
+    g = Q.Graph(plans, list(bs))
+    outs = [o.cpu().numpy()[:, 0] for o in g.launch()]
+    torch.cuda.synchronize()
+    for nm, c, b, a in zip(C5, cs, bs, outs):
+        if c.n <= 25:
+            ref = oracle.sv_amplitudes(c.n, c.gates, None, b)
+            err = np.abs(a - ref).max()
+        else:
+            idx = np.arange(0, len(b), len(b) // 8)[:8]
+            ref = oracle.bucket_amplitudes(c.n, c.gates, None, b[idx])
+            err = np.abs(a[idx] - ref).max()
+        _say("  %s n=%d max err * 2^(n/2) = %.3g" % (nm, c.n, err * 2 ** (c.n / 2)))
+        assert err <= TOL * 2 ** (-c.n / 2)
+        _pt_checks(a, c.n)
+
+
+def test_clifford_42_qubits_dyadic():
+    """6x7 depth 27 with T -> S: same plan structure as the benchmark circuit,
+    probabilities are 0 or 2^-k (App. F, end)."""
+    import paper_1712_05384_amd as Q
+    c, b = C.workload("c5_6x7_d27")
+    k = C.clifford_variant(c)
+    _say("case clifford 6x7 d27")
+    a = Q.plan(k).amplitudes(b[:256], k.gate_vals.astype(np.complex64)).cpu().numpy()[:, 0]
+    p = np.abs(a) ** 2
+    nz = p[p > 2.0 ** (-k.n - 10)]
+    assert len(nz) > 0
+    e = np.log2(1 / nz)
+    assert np.abs(e - np.round(e)).max() < 1e-3

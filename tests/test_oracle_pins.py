@@ -208,3 +208,23 @@ def test_cycle0_input_column_is_zero():
     for i, row in enumerate(c.gates):
         if row[1] == 0:
             assert np.abs(per_gate[i][:, 1]).max() < 1e-14
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(3, 3, 12, 91), (4, 4, 16, 92), (3, 5, 20, 93)])
+def test_bucket_elimination_matches_state_vector(rows, cols, depth, seed):
+    """App. A bucket elimination (own min-degree order) equals the state vector."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 6, seed)
+    a = oracle.bucket_amplitudes(c.n, c.gates, None, bits)
+    b = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(a - b).max() < 1e-14
+    cp = C.parameterised_circuit(3, 3, 8, seed)
+    a = oracle.bucket_amplitudes(cp.n, cp.gates, cp.gate_vals, bits % (1 << cp.n))
+    b = oracle.sv_amplitudes(cp.n, cp.gates, cp.gate_vals, bits % (1 << cp.n))
+    assert np.abs(a - b).max() < 1e-14
+
+
+def test_bucket_elimination_app_d():
+    g = json.load(open(os.path.join(GOLDEN, "app_d.json")))
+    for x, (re, im) in g["amplitudes"].items():
+        assert abs(oracle.bucket_amplitude(2, np.array(g["gates"]), None, int(x)) - complex(re, im)) < 1e-15

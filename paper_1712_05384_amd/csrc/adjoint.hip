@@ -172,32 +172,61 @@ __global__ void __launch_bounds__(256) k_gbar(GbarParams gp, const float2* __res
 }
 
 // Gbar[v][k][n][sigma] (complex128) = sum over row chunks and over the b with
-// sigma(b) = sigma of the partials, in a fixed order.
+// sigma(b) = sigma of the partials.  One work-group per (v, k, n): each thread
+// walks its bitstrings (b = tid, tid + 256, ...) over all row chunks, adding
+// into one of 16 register accumulators selected by sigma (a chunk of 16
+// variants per pass), then the work-group sums each accumulator with a fixed
+// LDS tree: the result does not depend on scheduling.
 __global__ void __launch_bounds__(256) k_gbar_reduce(GbarParams gp, const float2* __restrict__ part,
                                                      const uint16_t* __restrict__ vids, uint32_t B_eff,
                                                      double2* __restrict__ gbar) {
+    __shared__ double red[256][2];
     const StepParams& sp = gp.sp;
-    const uint32_t total = 1u << (sp.vb + sp.kb + sp.nb + sp.sb);
-    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-    if (e >= total) return;
-    const uint32_t sig = e & ((1u << sp.sb) - 1u);
-    const uint32_t n = (e >> sp.sb) & ((1u << sp.nb) - 1u);
-    const uint32_t k = (e >> (sp.sb + sp.nb)) & ((1u << sp.kb) - 1u);
-    const uint32_t v = e >> (sp.sb + sp.nb + sp.kb);
+    const uint32_t vkn = blockIdx.x;                 // (v, k, n) without sigma
+    const uint32_t n = vkn & ((1u << sp.nb) - 1u);
+    const uint32_t k = (vkn >> sp.nb) & ((1u << sp.kb) - 1u);
+    const uint32_t v = vkn >> (sp.nb + sp.kb);
     const uint32_t kc = k / uint32_t(gp.kw), ki = k % uint32_t(gp.kw);
     const uint32_t nc = n / uint32_t(gp.nw), nj = n % uint32_t(gp.nw);
-    double re = 0.0, im = 0.0;
-    for (uint32_t rc = 0; rc < gp.n_rc; ++rc) {
-        const uint32_t unit = ((v * gp.n_rc + rc) * gp.n_kc + kc) * gp.n_nc + nc;
-        const float2* p = part + (size_t(unit) * 64 + ki * 8 + nj) * B_eff;
-        for (uint32_t b = 0; b < B_eff; ++b) {
-            if (vids[b] != sig) continue;
-            const float2 x = p[b];
-            re += double(x.x);
-            im += double(x.y);
+    const uint32_t S = 1u << sp.sb;
+    const int tid = threadIdx.x;
+    for (uint32_t s0 = 0; s0 < S; s0 += 16) {
+        double re[16], im[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) { re[q] = 0.0; im[q] = 0.0; }
+        for (uint32_t b = uint32_t(tid); b < B_eff; b += 256) {
+            const uint32_t sg = uint32_t(vids[b]) - s0;
+            if (sg >= 16u) continue;
+            double xr = 0.0, xi = 0.0;
+            for (uint32_t rc = 0; rc < uint32_t(gp.n_rc); ++rc) {
+                const uint32_t unit = ((v * gp.n_rc + rc) * gp.n_kc + kc) * gp.n_nc + nc;
+                const float2 x = part[(size_t(unit) * 64 + ki * 8 + nj) * B_eff + b];
+                xr += double(x.x);
+                xi += double(x.y);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const bool hit = sg == uint32_t(q);
+                re[q] += hit ? xr : 0.0;
+                im[q] += hit ? xi : 0.0;
+            }
+        }
+        const uint32_t nq = S - s0 < 16u ? S - s0 : 16u;
+        for (uint32_t q = 0; q < nq; ++q) {
+            double r = 0.0, i = 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) if (uint32_t(t) == q) { r = re[t]; i = im[t]; }
+            red[tid][0] = r;
+            red[tid][1] = i;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if (tid < w) { red[tid][0] += red[tid + w][0]; red[tid][1] += red[tid + w][1]; }
+                __syncthreads();
+            }
+            if (tid == 0) gbar[sp.g_off + (size_t(vkn) << sp.sb) + s0 + q] = make_double2(red[0][0], red[0][1]);
+            __syncthreads();
         }
     }
-    gbar[sp.g_off + e] = make_double2(re, im);
 }
 
 // Gate environments of every step: thread per (step, G entry); per-wave sums of
@@ -384,8 +413,8 @@ void launch_gbar(const GbarParams& gp, const float2* a, const float2* cbar, floa
                  uint32_t B_eff, double2* gbar, hipStream_t stream) {
     const uint32_t units = uint32_t(gp.n_nc) * gp.n_kc * gp.n_rc * (1u << gp.sp.vb);
     hipLaunchKernelGGL(k_gbar, dim3((B_eff + 255) / 256, units), dim3(256), 0, stream, gp, a, cbar, part, B_eff);
-    const uint32_t total = 1u << (gp.sp.vb + gp.sp.kb + gp.sp.nb + gp.sp.sb);
-    hipLaunchKernelGGL(k_gbar_reduce, dim3((total + 255) / 256), dim3(256), 0, stream, gp, part, vids, B_eff, gbar);
+    const uint32_t vkn = 1u << (gp.sp.vb + gp.sp.kb + gp.sp.nb);
+    hipLaunchKernelGGL(k_gbar_reduce, dim3(vkn), dim3(256), 0, stream, gp, part, vids, B_eff, gbar);
 }
 
 void launch_gadj(const StepTab* steps, int n_steps, uint32_t max_entries, const GOp* ops, const double2* fixed,

@@ -183,7 +183,7 @@ void forward_step(const qgm::Step& stp, const float2* fin, float2* fout, const u
 }
 
 // Gbar work split for one step at batch B_eff: 8-wide k and n slices, and
-// row chunks so that the partial-product kernel has about 2^18 threads.
+// row chunks so that the partial-product kernel has about 2^16 threads.
 qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
     qgm::GbarParams gp{};
     gp.sp = step_params(stp);
@@ -199,7 +199,7 @@ qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
         if (std::find(vp.begin(), vp.end(), pos) == vp.end()) gp.free_pos[gp.n_free++] = pos;
     const int64_t base_units = int64_t(gp.n_kc) * gp.n_nc << stp.vb;
     int64_t n_rc = 1;
-    while (n_rc * 2 <= (int64_t(1) << gp.n_free) && base_units * n_rc * 2 * B_eff <= (int64_t(1) << 18) &&
+    while (n_rc * 2 <= (int64_t(1) << gp.n_free) && base_units * n_rc * 2 * B_eff <= (int64_t(1) << 16) &&
            base_units * n_rc * 2 <= 65535)
         n_rc *= 2;
     gp.n_rc = int32_t(n_rc);

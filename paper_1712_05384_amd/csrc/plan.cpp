@@ -300,8 +300,10 @@ static qgm_status build_steps(Plan& p, std::string* err) {
 }
 
 // Picks the next variable to slice: among the non-open variables of the
-// largest frontier, the one alive in the frontier for the most steps.
-static int pick_slice_var(const Plan& p) {
+// largest frontier, the one whose sliced plan moves the fewest bytes in total
+// (every slice copy repeats the steps where the variable is not alive, so a
+// short-lived variable costs more than it saves); ties go to the lower peak.
+static int pick_slice_var(Plan& p, std::string* err) {
     int peak = -1, best_step = -1;
     bool out_side = false;
     for (int i = 0; i < int(p.steps.size()); ++i) {
@@ -309,15 +311,26 @@ static int pick_slice_var(const Plan& p) {
         if (p.steps[i].r_out > peak) { peak = p.steps[i].r_out; best_step = i; out_side = true; }
     }
     if (best_step < 0) return -1;
-    const auto& axes = out_side ? p.steps[best_step].out_axes : p.steps[best_step].in_axes;
-    std::map<int, int> life;
-    for (auto& st : p.steps)
-        for (int v : st.in_axes) life[v]++;
-    int best = -1, best_life = -1;
+    const std::vector<int> axes = out_side ? p.steps[best_step].out_axes : p.steps[best_step].in_axes;
+    int best = -1, best_peak = 1 << 30;
+    double best_bytes = 0;
+    const int slice_idx = int(p.sliced.size());
     for (int v : axes) {
         if (p.vars[v].open_idx >= 0) continue;
-        if (life[v] > best_life) { best_life = life[v]; best = v; }
+        p.vars[v].slice_idx = slice_idx;
+        std::string e;
+        if (build_steps(p, &e) == QGM_OK) {
+            double bytes = 0;
+            for (auto& st : p.steps) bytes += st.bytes_per_b();
+            if (best < 0 || bytes < best_bytes || (bytes == best_bytes && p.r_max < best_peak)) {
+                best = v;
+                best_bytes = bytes;
+                best_peak = p.r_max;
+            }
+        }
+        p.vars[v].slice_idx = -1;
     }
+    if (best < 0) { *err = "no slicing candidate yields a valid plan"; return -1; }
     return best;
 }
 
@@ -387,7 +400,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     if (st != QGM_OK) return st;
     while ((opts.max_rank > 0 && p.r_max > opts.max_rank) || int(p.sliced.size()) < opts.min_sliced_vars) {
         if (p.sliced.size() >= 12) { *err = "max_rank needs more than 12 sliced variables"; return QGM_E_OOM; }
-        int v = pick_slice_var(p);
+        int v = pick_slice_var(p, err);
         if (v < 0) {
             if (opts.max_rank > 0 && p.r_max > opts.max_rank) { *err = "no variable left to slice"; return QGM_E_OOM; }
             break;

@@ -23,6 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per elimination-step launch on the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
+# plain 1 GiB copy gives), valid for the step-kernel source with this hash.
+MEASURED_TRAFFIC = {"c2_5x5_d25": {"bytes_per_launch": 226794653.4, "kernels_sha256_16": "a72736aaae65f038"}}
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
 
 
@@ -36,6 +40,8 @@ def main() -> int:
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary workloads (C4 gradients, C3 sliced, C5 four-circuit graph)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     ap.add_argument("--kernel-policy", type=int, default=0,
                     help="0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
     args = ap.parse_args()
@@ -46,6 +52,14 @@ def main() -> int:
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 3}))
+        return 0
     import paper_1712_05384_amd as Q
     from paper_1712_05384_amd import circuits as C
 
@@ -92,8 +106,16 @@ def main() -> int:
     n_launch = info["n_steps"]
     step_ms = phases[2] / max(ncalls, 1)
     achieved = step_bytes / (step_ms / 1e3) / 1e9
+    traffic = None
+    rec = MEASURED_TRAFFIC.get(args.workload)
+    if rec and args.kernel_policy == 0:
+        import hashlib
+        src = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", "kernels.hip")
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == rec["kernels_sha256_16"]:
+            traffic = round(rec["bytes_per_launch"] / (step_ms / n_launch / 1e3) / 1e9, 1)   # GB/s of HBM traffic
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
                 "kernel": "k_step (elimination step)", "bytes_per_launch": step_bytes / n_launch,
                 "launch_ms": step_ms / n_launch, "launches_per_step": n_launch}
 

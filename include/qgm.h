@@ -81,7 +81,9 @@ typedef struct {
                                   2 = FP32 matrix-core kernel for every step it supports (K and N of
                                       2^3..2^5), the vector-ALU kernel elsewhere;
                                   3 = vector-ALU kernel with two rows per thread on dense steps
-                                      (|K|+|N| >= 8 bits) */
+                                      (|K|+|N| >= 8 bits);
+                                  4 = as 2 with BF16x3 split-precision matrix cores (bf16 hi+lo
+                                      operands, three products, FP32 accumulation) */
     int32_t min_sliced_vars;   /* slice at least this many variables (Sec. V outlook: space-time tradeoffs) */
     int32_t out_c128;          /* 1: amplitudes are written as complex128, 0: complex64 */
     int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor has rank <= max_rank */

@@ -170,9 +170,10 @@ qgm::StepParams step_params(const qgm::Step& stp) {
 void forward_step(const qgm::Step& stp, const float2* fin, float2* fout, const uint16_t* vs, const float2* gtab,
                   uint32_t B_eff, hipStream_t s) {
     const qgm::StepParams sp = step_params(stp);
-    if (stp.kclass == 1) {
+    if (stp.kclass == 1 || stp.kclass == 2) {
         qgm::DenseParams dp{};
         dp.sp = sp;
+        dp.bf16x3 = stp.kclass == 2 ? 1 : 0;
         for (int j = 0; j < 4; ++j) dp.inner_pos[j] = stp.inner_pos[j];
         dp.n_outer = int32_t(stp.outer_pos.size());
         for (int j = 0; j < dp.n_outer; ++j) dp.outer_pos[j] = stp.outer_pos[j];

@@ -1,4 +1,5 @@
-// Dense elimination step on the matrix cores (FP32 MFMA, gfx950).
+// Dense elimination step on the matrix cores (FP32 MFMA, or BF16x3 split
+// precision with FP32 accumulation, gfx950).
 //
 // Same contraction as k_step, F'[row, n] = sum_k F[row (+) k] G_sigma(b)[v, k, n],
 // for steps whose K and N are both large (2^3..2^5): there the VALU kernel is
@@ -24,6 +25,10 @@
 // the V bits change; per bitstring it issues (2K/4) x (2N/16)
 // v_mfma_f32_16x16x4_f32 and writes C back over A in LDS, from where the tile
 // is stored with the same 128-byte accesses.
+//
+// BF16x3: the same tile, with every FP32 operand split into bf16 hi + lo and
+// three v_mfma_f32_16x16x16_bf16 (hi*hi + hi*lo + lo*hi) per 16-deep k-step,
+// accumulated in FP32: 3 * (2K/16) * (2N/16) instructions per bitstring.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -31,6 +36,19 @@
 namespace qgm {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// BF16x3 split of an FP32 value: hi = bf16(x) rounded to nearest even, lo =
+// bf16(x - hi); a*b is then hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo*lo term,
+// ~2^-16 relative, is dropped) with FP32 accumulation.
+__device__ __forceinline__ void split_bf16(float x, short& hi, short& lo) {
+    uint32_t u = __float_as_uint(x);
+    uint32_t h = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    hi = short(h >> 16);
+    const float r = x - __uint_as_float(h);
+    uint32_t v = __float_as_uint(r);
+    lo = short((v + 0x7fffu + ((v >> 16) & 1u)) >> 16);
+}
 
 __device__ __forceinline__ uint32_t deposit_bits(uint32_t x, const int32_t* pos, int nbits) {
     uint32_t r = 0;
@@ -38,7 +56,7 @@ __device__ __forceinline__ uint32_t deposit_bits(uint32_t x, const int32_t* pos,
     return r;
 }
 
-template <int KB, int NB>
+template <int KB, int NB, bool B3>
 __global__ void __launch_bounds__(256, 2) k_dense(DenseParams dp, const float2* __restrict__ fin,
                                                   float2* __restrict__ fout, const uint16_t* __restrict__ vids,
                                                   const float2* __restrict__ gtab, uint32_t B_eff,
@@ -53,6 +71,7 @@ __global__ void __launch_bounds__(256, 2) k_dense(DenseParams dp, const float2* 
     // under the two-work-groups-per-CU register budget.  Otherwise the second
     // work-group on the CU overlaps one tile's loads with the other's MFMAs.
     constexpr bool PREFETCH = (KS * NBLK + 2 * K) <= 96;
+    constexpr int KS3 = (2 * K) / 16;     // BF16x3: 16x16x16 k-steps over the real K
     __shared__ float tile[16 * BS];
     __shared__ uint32_t sigs[16], pin[16], pout[16];
     __shared__ int order[16];
@@ -110,7 +129,8 @@ __global__ void __launch_bounds__(256, 2) k_dense(DenseParams dp, const float2* 
     const int n_var = 1 << sp.sb;
     // waves per variant (n_var < 4) or variants per wave (n_var >= 4)
     const int wpv = n_var < 4 ? 4 / n_var : 1;
-    float gf[KS][NBLK];
+    float gf[B3 ? 1 : KS][NBLK];
+    v4s gh[B3 ? KS3 : 1][NBLK], gl3[B3 ? KS3 : 1][NBLK];
     for (; T < n_tiles; T += gridDim.x) {
         uint32_t base_row, base_in, b0;
         tile_base(T, base_row, base_in, b0);
@@ -147,16 +167,39 @@ __global__ void __launch_bounds__(256, 2) k_dense(DenseParams dp, const float2* 
             if (uint32_t(sig) != cur_sig || v != cur_v) {
                 cur_sig = uint32_t(sig);
                 cur_v = v;
+                if constexpr (!B3) {
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int kr = 4 * s + (lane >> 4);
-                    const int k = kr >> 1, cp = kr & 1;
+                    for (int s = 0; s < KS; ++s) {
+                        const int kr = 4 * s + (lane >> 4);
+                        const int k = kr >> 1, cp = kr & 1;
 #pragma unroll
-                    for (int nb = 0; nb < NBLK; ++nb) {
-                        const int nr = 16 * nb + (lane & 15);
-                        const int n = nr >> 1, c = nr & 1;
-                        const float2 g = G[(((v * K + uint32_t(k)) * N + uint32_t(n)) << sp.sb) + uint32_t(sig)];
-                        gf[s][nb] = cp == 0 ? (c == 0 ? g.x : g.y) : (c == 0 ? -g.y : g.x);
+                        for (int nb = 0; nb < NBLK; ++nb) {
+                            const int nr = 16 * nb + (lane & 15);
+                            const int n = nr >> 1, c = nr & 1;
+                            const float2 g = G[(((v * K + uint32_t(k)) * N + uint32_t(n)) << sp.sb) + uint32_t(sig)];
+                            gf[s][nb] = cp == 0 ? (c == 0 ? g.x : g.y) : (c == 0 ? -g.y : g.x);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < KS3; ++s) {
+#pragma unroll
+                        for (int nb = 0; nb < NBLK; ++nb) {
+                            const int nr = 16 * nb + (lane & 15);
+                            const int n = nr >> 1, c = nr & 1;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int kr = 16 * s + 4 * (lane >> 4) + j;
+                                const int k = kr >> 1, cp = kr & 1;
+                                const float2 g =
+                                    G[(((v * K + uint32_t(k)) * N + uint32_t(n)) << sp.sb) + uint32_t(sig)];
+                                const float x = cp == 0 ? (c == 0 ? g.x : g.y) : (c == 0 ? -g.y : g.x);
+                                short h, l;
+                                split_bf16(x, h, l);
+                                gh[s][nb][j] = h;
+                                gl3[s][nb][j] = l;
+                            }
+                        }
                     }
                 }
             }
@@ -165,13 +208,34 @@ __global__ void __launch_bounds__(256, 2) k_dense(DenseParams dp, const float2* 
                 v4f acc[NBLK];
 #pragma unroll
                 for (int nb = 0; nb < NBLK; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
-                const float* arow = &tile[b_l * BS + (lane & 15) * RS + (lane >> 4)];
+                if constexpr (!B3) {
+                    const float* arow = &tile[b_l * BS + (lane & 15) * RS + (lane >> 4)];
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const float a = arow[4 * s];
+                    for (int s = 0; s < KS; ++s) {
+                        const float a = arow[4 * s];
 #pragma unroll
-                    for (int nb = 0; nb < NBLK; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gf[s][nb], acc[nb], 0, 0, 0);
+                        for (int nb = 0; nb < NBLK; ++nb)
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, gf[s][nb], acc[nb], 0, 0, 0);
+                    }
+                } else {
+                    const float* arow = &tile[b_l * BS + (lane & 15) * RS + 4 * (lane >> 4)];
+#pragma unroll
+                    for (int s = 0; s < KS3; ++s) {
+                        const float2 x01 = *reinterpret_cast<const float2*>(arow + 16 * s);
+                        const float2 x23 = *reinterpret_cast<const float2*>(arow + 16 * s + 2);
+                        v4s ah, al;
+                        short h, l;
+                        split_bf16(x01.x, h, l); ah[0] = h; al[0] = l;
+                        split_bf16(x01.y, h, l); ah[1] = h; al[1] = l;
+                        split_bf16(x23.x, h, l); ah[2] = h; al[2] = l;
+                        split_bf16(x23.y, h, l); ah[3] = h; al[3] = l;
+#pragma unroll
+                        for (int nb = 0; nb < NBLK; ++nb) {
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, gh[s][nb], acc[nb], 0, 0, 0);
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, gl3[s][nb], acc[nb], 0, 0, 0);
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, gh[s][nb], acc[nb], 0, 0, 0);
+                        }
+                    }
                 }
 #pragma unroll
                 for (int nb = 0; nb < NBLK; ++nb) {
@@ -200,7 +264,12 @@ static void launch_dense_t(const DenseParams& dp, const float2* fin, float2* fou
                            const float2* gtab, uint32_t B_eff, hipStream_t stream) {
     const uint32_t n_tiles = (1u << dp.n_outer) * (B_eff / 16);
     uint32_t grid = n_tiles < kDenseMaxGrid ? n_tiles : kDenseMaxGrid;
-    hipLaunchKernelGGL((k_dense<KB, NB>), dim3(grid), dim3(256), 0, stream, dp, fin, fout, vids, gtab, B_eff, n_tiles);
+    if (dp.bf16x3)
+        hipLaunchKernelGGL((k_dense<KB, NB, true>), dim3(grid), dim3(256), 0, stream, dp, fin, fout, vids, gtab, B_eff,
+                           n_tiles);
+    else
+        hipLaunchKernelGGL((k_dense<KB, NB, false>), dim3(grid), dim3(256), 0, stream, dp, fin, fout, vids, gtab, B_eff,
+                           n_tiles);
 }
 
 template <int KB>

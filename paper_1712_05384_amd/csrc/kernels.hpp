@@ -21,6 +21,7 @@ struct DenseParams {
     int32_t inner_pos[4];
     int32_t outer_pos[kMaxRank];
     int32_t n_outer;
+    int32_t bf16x3;           // 1: BF16x3 split-precision matrix cores, 0: FP32 matrix cores
 };
 
 // Launch parameters of the Gbar partial-product kernel.

@@ -111,6 +111,7 @@ static qgm_status validate(const qgm_circuit* c, const int32_t* open, int32_t n_
 //  * kernel_policy 0/1: the vector-ALU kernel, one row per thread.
 //  * kernel_policy 2: every step the matrix-core kernel supports (K and N of
 //    2^3..2^5, 4 non-V row bits for a 16-row tile, <= 16 variants) runs on it.
+//  * kernel_policy 4: the same steps on the BF16x3 split-precision matrix cores.
 //  * kernel_policy 3: dense steps (|K| + |N| >= 8 bits, K of 2^3..2^5) run the
 //    vector-ALU kernel with two rows per thread that differ in a non-V bit
 //    (same v, same sigma), so every G read feeds two multiply-adds.
@@ -124,12 +125,12 @@ static void classify_step(const Plan& p, Step& st) {
     std::set<int> vset(st.vpos.begin(), st.vpos.end());
     const bool mfma_ok = !st.input_is_one && st.kb >= 3 && st.kb <= 5 && st.nb >= 3 && st.nb <= 5 &&
                          row_bits - st.vb >= 4 && (1 << st.sb) <= kDenseMaxVariants;
-    if (p.opts.kernel_policy == 2 && mfma_ok) {
+    if ((p.opts.kernel_policy == 2 || p.opts.kernel_policy == 4) && mfma_ok) {
         for (int pos = 0; pos < row_bits; ++pos) {
             if (int(st.inner_pos.size()) < 4 && !vset.count(pos)) st.inner_pos.push_back(pos);
             else st.outer_pos.push_back(pos);
         }
-        st.kclass = 1;
+        st.kclass = p.opts.kernel_policy == 4 ? 2 : 1;
         return;
     }
     if (p.opts.kernel_policy != 3) return;
@@ -342,7 +343,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         *err = "only ordering 0 and precision 0 are implemented";
         return QGM_E_UNSUPPORTED;
     }
-    if (opts.kernel_policy < 0 || opts.kernel_policy > 3) { *err = "kernel_policy must be 0..3"; return QGM_E_INVALID; }
+    if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }
@@ -426,6 +427,12 @@ WsLayout workspace_layout(const Plan& p, int64_t B) {
     return w;
 }
 
+static const char* kernel_name(const Step& st) {
+    if (st.kclass == 1) return "mfma_f32";
+    if (st.kclass == 2) return "mfma_bf16x3";
+    return st.pair_bit >= 0 ? "valu_pair" : "valu";
+}
+
 static void json_ints(std::ostringstream& o, const std::vector<int>& v) {
     o << "[";
     for (size_t i = 0; i < v.size(); ++i) o << (i ? "," : "") << v[i];
@@ -457,7 +464,7 @@ std::string plan_json(const Plan& p, int detail) {
         o << (i ? "," : "") << "{\"qubit\":" << st.qubit << ",\"r_in\":" << st.r_in << ",\"r_out\":" << st.r_out
           << ",\"kb\":" << st.kb << ",\"vb\":" << st.vb << ",\"nb\":" << st.nb << ",\"sb\":" << st.sb
           << ",\"input_is_one\":" << (st.input_is_one ? 1 : 0) << ",\"g_off\":" << st.g_off
-          << ",\"kernel\":\"" << (st.kclass == 1 ? "mfma_f32" : (st.pair_bit >= 0 ? "valu_pair" : "valu")) << "\""
+          << ",\"kernel\":\"" << kernel_name(st) << "\""
           << ",\"bytes_per_b\":" << st.bytes_per_b() << ",\"flops_per_b\":" << st.flops_per_b();
         if (detail >= 1) {
             o << ",\"kpos\":"; json_ints(o, st.kpos);

@@ -47,7 +47,7 @@ struct Step {
     std::vector<int> sig_src;           // variant bit i: qubit q (>= 0) or -(1 + slice index)
     std::vector<GOp> ops;               // factor program evaluated by the G builder
     int64_t g_off = 0;                  // complex offset of this step's G in the G table
-    int kclass = 0;                     // 0 = vector-ALU kernel, 1 = FP32 MFMA kernel
+    int kclass = 0;                     // 0 = vector-ALU kernel, 1 = FP32 MFMA kernel, 2 = BF16x3 MFMA kernel
     int pair_bit = -1;                  // vector-ALU kernel: rows paired on this row bit (-1: no pairing)
     int pair_in = 0;                    // input-tensor offset of the paired bit
     std::vector<int> inner_pos;         // MFMA tile: the 4 row positions inside a tile (no V axes)

@@ -182,3 +182,23 @@ def test_c2_kernel_policies(policy):
     got = _gpu_amps(_plan(c, kernel_policy=policy), bits)[:, 0]
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+BF16X3_TOL = 2e-3   # BF16x3: per-product relative error ~2^-16 (dropped lo*lo and lo rounding)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(4, 4, 24, 4), (4, 4, 30, 12)])
+def test_bf16x3_steps(rows, cols, depth, seed):
+    """Matrix-core steps in BF16x3 split precision, within 2e-3 * 2^-n/2 of the oracle
+    (and visibly less exact than FP32, so the split path really runs)."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 200, seed)
+    p = _plan(c, kernel_policy=4)
+    kinds = [s["kernel"] for s in p.info(0)["steps"]]
+    assert "mfma_bf16x3" in kinds
+    _say("case %s bf16x3 steps=%d" % (c.name, kinds.count("mfma_bf16x3")))
+    got = _gpu_amps(p, bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    err = np.abs(got - ref).max() * 2 ** (c.n / 2)
+    _say("  bf16x3 max err * 2^(n/2) = %.3g" % err)
+    assert err <= BF16X3_TOL

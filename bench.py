@@ -42,6 +42,7 @@ def main() -> int:
                     help="skip the secondary workloads (C4 gradients, C3 sliced, C5 four-circuit graph)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the policy's kernels instead of timing them")
     ap.add_argument("--kernel-policy", type=int, default=0,
                     help="0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
     args = ap.parse_args()
@@ -79,6 +80,10 @@ def main() -> int:
     out = torch.empty((B, 1), dtype=torch.complex64, device=dev)
     ws = torch.empty(p.workspace_bytes(B), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
+    kernels = None
+    if not args.no_autotune:
+        kernels = p.autotune(bits_d, gv, stream=stream)   # per-step kernel by measurement (complex64 kernels only)
+        info = p.info(0)
 
     for _ in range(args.warmup):
         p.amplitudes(bits_d, gv, out=out, workspace=ws, stream=stream)
@@ -108,7 +113,7 @@ def main() -> int:
     achieved = step_bytes / (step_ms / 1e3) / 1e9
     traffic = None
     rec = MEASURED_TRAFFIC.get(args.workload)
-    if rec and args.kernel_policy == 0:
+    if rec and args.kernel_policy == 0 and args.no_autotune:
         import hashlib
         src = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", "kernels.hip")
         if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == rec["kernels_sha256_16"]:
@@ -127,7 +132,9 @@ def main() -> int:
         "config": {"workload": f"{c.name}: {c.rows}x{c.cols} grid, depth {c.depth()}, {B} uniform bitstrings, "
                                f"complex64, one plan for the batch", "global_batch": B,
                    "qubits": c.n, "max_rank": info["max_rank"], "sliced_vars": info["n_sliced"],
-                   "kernel_policy": args.kernel_policy},
+                   "kernel_policy": args.kernel_policy, "autotuned": not args.no_autotune,
+                   "step_kernels": {k: (kernels or [st["kernel"] for st in info["steps"]]).count(k)
+                                    for k in ("valu", "valu_pair", "mfma_f32", "mfma_bf16x3")}},
         "phases_ms_per_step": {k: round(v / max(ncalls, 1), 5) for k, v in
                                zip(("boundary", "g_build", "elimination", "output"), phases)},
         "plan_seconds": round(plan_s, 4),

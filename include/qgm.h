@@ -158,6 +158,19 @@ qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
                         const void* grad_amps, void* amps_out, void* gate_grads, void* workspace, uint64_t ws_bytes,
                         void* stream);
 
+/* Chooses the kernel of every elimination step by measurement on the current
+ * device (the cGEMM-shape autotuner): for each step it times the vector-ALU
+ * kernel with one and with two rows per thread, the FP32 matrix-core kernel
+ * and, if allow_bf16x3, the BF16x3 matrix-core kernel (each where the step's
+ * shape allows it) on the given batch, and keeps the fastest.  Timings are
+ * cached in a text file keyed by (arch, K, V, N, sigma bits, rank, batch,
+ * kernel): cache_path, or $QGM_TUNE_CACHE when cache_path is NULL, or no cache.
+ * Runs one qgm_amplitudes call first (out may be NULL only here: the call's
+ * output is not written), uses `workspace` as scratch and synchronises
+ * `stream`.  The choice is stored in the plan (see qgm_plan_info). */
+qgm_status qgm_autotune(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* workspace,
+                        uint64_t ws_bytes, void* stream, int32_t allow_bf16x3, const char* cache_path);
+
 /* Per-phase timing of qgm_amplitudes (hipEvents recorded on the call's
  * stream; instrumentation for the benchmark, off by default).  enable = 1
  * starts recording and clears the totals; 0 stops.  While enabled each call

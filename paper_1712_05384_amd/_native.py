@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "QGM_OK", -1: "QGM_E_INVALID", -2: "QGM_E_UNSUPPORTED", -3: "
 # Every symbol include/qgm.h declares.
 EXPORTED = ("qgm_default_opts", "qgm_plan", "qgm_plan_info", "qgm_workspace_bytes", "qgm_amplitudes",
             "qgm_backward_workspace_bytes", "qgm_backward", "qgm_graph_create", "qgm_graph_launch",
-            "qgm_graph_destroy", "qgm_plan_set_timing", "qgm_plan_timings", "qgm_plan_destroy", "qgm_last_error",
+            "qgm_graph_destroy", "qgm_autotune", "qgm_plan_set_timing", "qgm_plan_timings", "qgm_plan_destroy", "qgm_last_error",
             "qgm_sync_check")
 
 
@@ -67,6 +67,7 @@ def lib():
         L.qgm_graph_launch.argtypes = [P, P]
         L.qgm_graph_destroy.argtypes = [P]
         L.qgm_graph_destroy.restype = None
+        L.qgm_autotune.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_uint64, P, ctypes.c_int32, ctypes.c_char_p]
         L.qgm_plan_set_timing.argtypes = [P, ctypes.c_int32]
         L.qgm_plan_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.qgm_plan_destroy.argtypes = [P]
@@ -76,7 +77,7 @@ def lib():
         L.qgm_sync_check.argtypes = [P]
         for f in (L.qgm_plan, L.qgm_plan_info, L.qgm_workspace_bytes, L.qgm_amplitudes, L.qgm_sync_check,
                   L.qgm_plan_set_timing, L.qgm_plan_timings, L.qgm_backward_workspace_bytes, L.qgm_backward,
-                  L.qgm_graph_create, L.qgm_graph_launch):
+                  L.qgm_graph_create, L.qgm_graph_launch, L.qgm_autotune):
             f.restype = ctypes.c_int
         _lib = L
     return _lib

@@ -139,6 +139,27 @@ class Plan:
                                        workspace.data_ptr(), workspace.numel(), ctypes.c_void_p(stream.cuda_stream)))
         return amps, grads[:self.n_slots]
 
+    def autotune(self, bits, gate_vals=None, *, allow_bf16x3: bool = False, cache_path=None, stream=None):
+        """Times the candidate kernels of every step on this device and keeps
+        the fastest (qgm_autotune).  Returns the per-step kernel names."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if isinstance(bits, np.ndarray):
+            bits = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint64).view(np.int64))
+        bits = bits.to(dev).contiguous()
+        B = int(bits.shape[0])
+        gv = None
+        if self.n_slots:
+            gv = torch.as_tensor(gate_vals).to(dev, torch.complex64).contiguous()
+        ws = torch.empty(max(self.workspace_bytes(B), 256), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self._lib.qgm_autotune(self._h, None if gv is None else gv.data_ptr(), bits.data_ptr(), B,
+                                       ws.data_ptr(), ws.numel(), ctypes.c_void_p(stream.cuda_stream),
+                                       1 if allow_bf16x3 else 0,
+                                       None if cache_path is None else str(cache_path).encode()))
+        return [s["kernel"] for s in self.info(0)["steps"]]
+
     def set_timing(self, enable: bool) -> None:
         N.check(self._lib.qgm_plan_set_timing(self._h, 1 if enable else 0))
 

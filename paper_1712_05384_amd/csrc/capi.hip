@@ -4,7 +4,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -300,14 +305,19 @@ qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* byte
     return QGM_OK;
 }
 
-qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
-                          void* workspace, uint64_t ws_bytes, void* stream) {
+}  // extern "C"
+
+// The amplitude call; with out == nullptr and allow_no_out the output stage is
+// skipped (the autotuner only needs the frontier buffers filled).
+static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
+                                  void* workspace, uint64_t ws_bytes, void* stream, bool allow_no_out) {
     g_err.clear();
     if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
     if (B < 0) return fail(QGM_E_INVALID, "B < 0");
     if (B == 0) return QGM_OK;
     const qgm::Plan& p = plan->p;
-    if (!bits || !out || !workspace) return fail(QGM_E_INVALID, "bits, out and workspace must be device pointers");
+    if (!bits || (!out && !allow_no_out) || !workspace)
+        return fail(QGM_E_INVALID, "bits, out and workspace must be device pointers");
     if (p.n_slots > 0 && !gate_vals) return fail(QGM_E_INVALID, "the circuit reads gate_vals but it is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
     const int64_t B_pad = qgm::padded_batch(B);
@@ -351,12 +361,20 @@ qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_
     for (int i = 0; i < n_steps; ++i)
         forward_step(p.steps[i], F[i & 1], F[(i + 1) & 1], vids + size_t(i) * size_t(B_eff), gtab, uint32_t(B_eff), s);
     mark(3);
-    qgm::launch_finalize(F[n_steps & 1], uint32_t(B_eff), uint32_t(B_pad), B, int(1 << p.sliced.size()), p.n_open,
-                         reinterpret_cast<const int32_t*>(tables + plan->off_final), out, p.opts.out_c128 != 0, s);
+    if (out)
+        qgm::launch_finalize(F[n_steps & 1], uint32_t(B_eff), uint32_t(B_pad), B, int(1 << p.sliced.size()), p.n_open,
+                             reinterpret_cast<const int32_t*>(tables + plan->off_final), out, p.opts.out_c128 != 0, s);
     mark(4);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return QGM_OK;
+}
+
+extern "C" {
+
+qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
+                          void* workspace, uint64_t ws_bytes, void* stream) {
+    return amplitudes_impl(plan, gate_vals, bits, B, out, workspace, ws_bytes, stream, false);
 }
 
 qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes) {
@@ -530,6 +548,105 @@ void qgm_graph_destroy(qgm_graph_t* graph) {
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     if (graph->graph) (void)hipGraphDestroy(graph->graph);
     delete graph;
+}
+
+qgm_status qgm_autotune(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* workspace,
+                        uint64_t ws_bytes, void* stream, int32_t allow_bf16x3, const char* cache_path) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    if (B <= 0) return fail(QGM_E_INVALID, "B must be > 0");
+    // a full call first: validates the arguments, uploads tables, fills the frontier buffers
+    qgm_status st = amplitudes_impl(plan, gate_vals, bits, B, nullptr, workspace, ws_bytes, stream, true);
+    if (st != QGM_OK) return st;
+    qgm::Plan& p = plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "device properties");
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty() && std::getenv("QGM_TUNE_CACHE")) path = std::getenv("QGM_TUNE_CACHE");
+    std::map<std::string, double> cache;
+    if (!path.empty()) {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string a;
+            int kb, vb, nb, sb, r, c;
+            long long be;
+            double ms;
+            if (ls >> a >> kb >> vb >> nb >> sb >> r >> be >> c >> ms) {
+                std::ostringstream k;
+                k << a << ' ' << kb << ' ' << vb << ' ' << nb << ' ' << sb << ' ' << r << ' ' << be << ' ' << c;
+                cache[k.str()] = ms;
+            }
+        }
+    }
+    const qgm::WsLayout w = qgm::workspace_layout(p, B);
+    const int64_t B_eff = qgm::batch_eff(p, B);
+    char* ws = static_cast<char*>(workspace);
+    float2* F[2] = {reinterpret_cast<float2*>(ws + w.f0), reinterpret_cast<float2*>(ws + w.f1)};
+    auto* vids = reinterpret_cast<uint16_t*>(ws + w.var_ids);
+    auto* gtab = reinterpret_cast<float2*>(ws + w.g);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    std::vector<std::string> fresh;
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        qgm::Step& stp = p.steps[i];
+        int best = qgm::KC_VALU;
+        double best_ms = 1e300;
+        for (int cand = qgm::KC_VALU; cand <= qgm::KC_MFMA_BF16X3; ++cand) {
+            if (!qgm::step_supports(stp, cand)) continue;
+            if (cand == qgm::KC_MFMA_BF16X3 && !allow_bf16x3) continue;
+            std::ostringstream k;
+            k << arch << ' ' << stp.kb << ' ' << stp.vb << ' ' << stp.nb << ' ' << stp.sb << ' ' << stp.r_in << ' '
+              << B_eff << ' ' << cand;
+            double ms;
+            auto it = cache.find(k.str());
+            if (it != cache.end()) {
+                ms = it->second;
+            } else {
+                qgm::configure_step(stp, cand);
+                const uint16_t* vs = vids + size_t(i) * size_t(B_eff);
+                forward_step(stp, F[i & 1], F[(i + 1) & 1], vs, gtab, uint32_t(B_eff), s);
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < 3; ++r) forward_step(stp, F[i & 1], F[(i + 1) & 1], vs, gtab, uint32_t(B_eff), s);
+                (void)hipEventRecord(e1, s);
+                e = hipEventSynchronize(e1);
+                float t = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+                if (e != hipSuccess) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return hip_fail(e, "timing a step");
+                }
+                ms = double(t) / 3.0;
+                cache[k.str()] = ms;
+                std::ostringstream line;
+                line.precision(6);
+                line << k.str() << ' ' << ms;
+                fresh.push_back(line.str());
+            }
+            if (ms < best_ms) { best_ms = ms; best = cand; }
+        }
+        qgm::configure_step(stp, best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!path.empty() && !fresh.empty()) {
+        std::ofstream out(path, std::ios::app);
+        for (auto& l : fresh) out << l << '\n';
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "autotune launches");
+    return QGM_OK;
 }
 
 qgm_status qgm_plan_set_timing(qgm_plan_t* plan, int32_t enable) {

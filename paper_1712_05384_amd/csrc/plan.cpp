@@ -107,15 +107,31 @@ static qgm_status validate(const qgm_circuit* c, const int32_t* open, int32_t n_
     return QGM_OK;
 }
 
-// Chooses the kernel of a step.
-//  * kernel_policy 0/1: the vector-ALU kernel, one row per thread.
-//  * kernel_policy 2: every step the matrix-core kernel supports (K and N of
-//    2^3..2^5, 4 non-V row bits for a 16-row tile, <= 16 variants) runs on it.
-//  * kernel_policy 4: the same steps on the BF16x3 split-precision matrix cores.
-//  * kernel_policy 3: dense steps (|K| + |N| >= 8 bits, K of 2^3..2^5) run the
-//    vector-ALU kernel with two rows per thread that differ in a non-V bit
-//    (same v, same sigma), so every G read feeds two multiply-adds.
-static void classify_step(const Plan& p, Step& st) {
+// Kernel candidates of a step (see configure_step).
+bool step_supports(const Step& st, int cand) {
+    const int row_bits = st.r_in - st.kb;
+    switch (cand) {
+        case KC_VALU: return true;
+        case KC_VALU_PAIR: {
+            if (!(st.kb >= 3 && st.kb <= 5 && row_bits - st.vb >= 1)) return false;
+            return true;
+        }
+        case KC_MFMA_F32:
+        case KC_MFMA_BF16X3:
+            return !st.input_is_one && st.kb >= 3 && st.kb <= 5 && st.nb >= 3 && st.nb <= 5 &&
+                   row_bits - st.vb >= 4 && (1 << st.sb) <= kDenseMaxVariants;
+        default: return false;
+    }
+}
+
+// Sets the kernel of a step:
+//  * KC_VALU: the vector-ALU kernel, one row per thread;
+//  * KC_VALU_PAIR: the vector-ALU kernel with two rows per thread that differ
+//    in a non-V bit (same v, same sigma), so every G read feeds two
+//    multiply-adds;
+//  * KC_MFMA_F32 / KC_MFMA_BF16X3: the matrix-core kernel (16-row tiles over 4
+//    non-V row bits), FP32 or BF16x3 split precision.
+void configure_step(Step& st, int cand) {
     st.kclass = 0;
     st.pair_bit = -1;
     st.pair_in = 0;
@@ -123,28 +139,31 @@ static void classify_step(const Plan& p, Step& st) {
     st.outer_pos.clear();
     const int row_bits = st.r_in - st.kb;
     std::set<int> vset(st.vpos.begin(), st.vpos.end());
-    const bool mfma_ok = !st.input_is_one && st.kb >= 3 && st.kb <= 5 && st.nb >= 3 && st.nb <= 5 &&
-                         row_bits - st.vb >= 4 && (1 << st.sb) <= kDenseMaxVariants;
-    if ((p.opts.kernel_policy == 2 || p.opts.kernel_policy == 4) && mfma_ok) {
+    if (cand == KC_MFMA_F32 || cand == KC_MFMA_BF16X3) {
         for (int pos = 0; pos < row_bits; ++pos) {
             if (int(st.inner_pos.size()) < 4 && !vset.count(pos)) st.inner_pos.push_back(pos);
             else st.outer_pos.push_back(pos);
         }
-        st.kclass = p.opts.kernel_policy == 4 ? 2 : 1;
-        return;
+        st.kclass = cand == KC_MFMA_BF16X3 ? 2 : 1;
+    } else if (cand == KC_VALU_PAIR) {
+        for (int pos = 0; pos < row_bits; ++pos) {
+            if (vset.count(pos)) continue;
+            st.pair_bit = pos;
+            const int var = st.out_axes[pos];
+            for (int i = 0; i < int(st.in_axes.size()); ++i)
+                if (st.in_axes[i] == var) st.pair_in = 1 << i;
+            break;
+        }
     }
-    if (p.opts.kernel_policy != 3) return;
-    const bool dense = st.kb >= 3 && st.kb <= 5 && st.kb + st.nb >= 8 && row_bits - st.vb >= 1;
-    if (!dense) return;
-    for (int pos = 0; pos < row_bits; ++pos) {
-        if (vset.count(pos)) continue;
-        st.pair_bit = pos;
-        // input position of that row bit: the input axes are the output row axes with K inserted
-        const int var = st.out_axes[pos];
-        for (int i = 0; i < int(st.in_axes.size()); ++i)
-            if (st.in_axes[i] == var) st.pair_in = 1 << i;
-        break;
-    }
+}
+
+// Kernel of a step under a kernel_policy (autotuning may change it later).
+static void classify_step(const Plan& p, Step& st) {
+    int cand = KC_VALU;
+    const int pol = p.opts.kernel_policy;
+    if ((pol == 2 || pol == 4) && step_supports(st, KC_MFMA_F32)) cand = pol == 4 ? KC_MFMA_BF16X3 : KC_MFMA_F32;
+    else if (pol == 3 && st.kb + st.nb >= 8 && step_supports(st, KC_VALU_PAIR)) cand = KC_VALU_PAIR;
+    configure_step(st, cand);
 }
 
 // Builds steps for the current slicing; returns the peak rank.

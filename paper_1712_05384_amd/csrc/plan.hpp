@@ -78,6 +78,11 @@ struct Plan {
     std::vector<DevTables> dev;
 };
 
+// Kernel candidates of an elimination step.
+enum { KC_VALU = 0, KC_VALU_PAIR = 1, KC_MFMA_F32 = 2, KC_MFMA_BF16X3 = 3 };
+bool step_supports(const Step& st, int cand);
+void configure_step(Step& st, int cand);
+
 // Builds the plan; returns QGM_OK or an error code with a message in *err.
 qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
                       const qgm_plan_opts& opts, Plan& p, std::string* err);

@@ -202,3 +202,21 @@ def test_bf16x3_steps(rows, cols, depth, seed):
     err = np.abs(got - ref).max() * 2 ** (c.n / 2)
     _say("  bf16x3 max err * 2^(n/2) = %.3g" % err)
     assert err <= BF16X3_TOL
+
+
+def test_autotune_choices_and_cache(tmp_path):
+    """The autotuner keeps, per step, a kernel the step supports; results still
+    match the oracle; the timing cache is written once and reused."""
+    c, bits = C.workload("c2_5x5_d25")
+    p = _plan(c)
+    cache = tmp_path / "tune.txt"
+    kinds = p.autotune(bits, cache_path=cache)
+    assert set(kinds) <= {"valu", "valu_pair", "mfma_f32"}
+    n_lines = len(cache.read_text().splitlines())
+    assert n_lines >= len(kinds)
+    kinds2 = p.autotune(bits, cache_path=cache)
+    assert kinds2 == kinds and len(cache.read_text().splitlines()) == n_lines
+    _say("autotuned kernels: %s" % kinds)
+    got = _gpu_amps(p, bits)[:, 0]
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)

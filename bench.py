@@ -219,6 +219,17 @@ def extras(Q, C, torch, np, stream, args):
                       "ms_per_grad_eval": round(ms, 4), "ms_forward_only": round(msf, 4)}
     print(f"# c4 gradient: {ms:.3f} ms per evaluation (forward alone {msf:.3f} ms)", file=sys.stderr, flush=True)
     del ws
+    # plain per-bitstring baseline: the default workload's plan called with B = 1
+    # in a host loop (no graph, no autotuning; B is padded to one 64-wide wave)
+    c, bits = C.workload(args.workload)
+    p = Q.plan(c)
+    one = [torch.from_numpy(bits[i:i + 1].view(np.int64)).to(dev) for i in range(64)]
+    o1 = torch.empty((1, 1), dtype=torch.complex64, device=dev)
+    w1 = torch.empty(p.workspace_bytes(1), dtype=torch.uint8, device=dev)
+    ms = _time(lambda: [p.amplitudes(b1, None, out=o1, workspace=w1, stream=stream) for b1 in one], 3, stream, torch)
+    out["per_bitstring_baseline"] = {"workload": f"{c.name}, same plan, B = 1 per call, 64 calls",
+                                     "amplitudes_per_sec": round(64 / (ms / 1e3), 1), "ms_per_amplitude": round(ms / 64, 4)}
+    print(f"# per-bitstring baseline: {ms / 64:.3f} ms per amplitude", file=sys.stderr, flush=True)
     # 5x6 depth 30, 2 sliced variables, FP64 slice sum
     c, bits = C.workload("c3_5x6_d30")
     p = Q.plan(c, min_sliced_vars=2, out_c128=True)

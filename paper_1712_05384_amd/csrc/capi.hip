@@ -34,6 +34,10 @@ struct qgm_plan_s {
     std::vector<int32_t> step_waves, slot_off, slot_ops;
     int64_t total_waves = 0;
     int max_ops = 1;
+    // tree plans (ordering 1): offsets of the bucket records, factor tables, phase and final rows
+    size_t off_tsteps = 0, off_tgtab = 0, off_tfac = 0, off_tphase = 0, off_tfinal = 0;
+    int n_gtabs = 0;
+    uint32_t max_tree_g = 0;
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -73,8 +77,93 @@ void fixed_matrices(double2 m[qgm::kFixedMats * 4]) {
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+void layout_tree_tables(qgm_plan_t* P) {
+    const qgm::TreePlan& t = P->p.tree;
+    size_t n_fac = 0;
+    P->n_gtabs = 0;
+    P->max_tree_g = 0;
+    for (auto& st : t.steps)
+        if (!st.factors.empty()) {
+            n_fac += st.factors.size();
+            P->n_gtabs++;
+            P->max_tree_g = std::max<uint32_t>(P->max_tree_g, uint32_t(st.g_entries()));
+        }
+    P->off_fixed = 0;
+    P->off_tsteps = al(sizeof(double2) * qgm::kFixedMats * 4);
+    P->off_tgtab = P->off_tsteps + al(sizeof(qgm::TreeStepDev) * (t.steps.size() + 1));
+    P->off_tfac = P->off_tgtab + al(sizeof(qgm::TreeGTab) * (size_t(P->n_gtabs) + 1));
+    P->off_tphase = P->off_tfac + al(sizeof(qgm::TFactor) * (n_fac + 1));
+    P->off_tfinal = P->off_tphase + al(sizeof(qgm::TFactor) * (t.phase.size() + 1));
+    P->total = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
+}
+
+// Device record of bucket st (index arithmetic of Sec. IV's bucket product).
+qgm::TreeStepDev tree_step_dev(const qgm::TreePlan& t, const qgm::TreeStep& st) {
+    qgm::TreeStepDev d{};
+    const int r = int(st.out_axes.size());
+    d.r_out = r;
+    d.n_in = int32_t(st.in_tensors.size());
+    d.sb = st.sb();
+    d.oc_bits = std::min(r, qgm::kTreeOcBits);
+    d.has_g = st.factors.empty() ? 0 : 1;
+    d.n_chunks = int64_t(1) << (r - d.oc_bits);
+    d.g_off = st.g_off;
+    d.out_row = t.tensor_row[st.out_tensor];
+    for (int i = 0; i < d.n_in; ++i) {
+        const int tid = st.in_tensors[i];
+        d.in_row[i] = t.tensor_row[tid];
+        const std::vector<int>& ax = t.tensor_axes[tid];
+        for (int a = 0; a < int(ax.size()); ++a) {
+            if (ax[a] == st.var) { d.in_v[i] = 1 << a; continue; }
+            for (int j = 0; j < r; ++j)
+                if (st.out_axes[j] == ax[a]) d.in_str[i][j] = 1 << a;
+        }
+        int low = 0;
+        for (int j = 0; j < qgm::kTreeOcBits; ++j) {
+            d.in_inc[i][j] = d.in_str[i][j] - low;
+            low += d.in_str[i][j];
+        }
+    }
+    for (int j = 0; j < r; ++j)
+        for (int g = 0; g < st.gb(); ++g)
+            if (st.out_axes[j] == st.gvars[g]) d.g_str[j] = 1 << g;
+    int low = 0;
+    for (int j = 0; j < qgm::kTreeOcBits; ++j) {
+        d.g_inc[j] = d.g_str[j] - low;
+        low += d.g_str[j];
+    }
+    for (int i = 0; i < st.sb(); ++i) d.sig_q[i] = st.sig_q[i];
+    return d;
+}
+
+void fill_tree_tables(const qgm_plan_t* P, char* h) {
+    const qgm::TreePlan& t = P->p.tree;
+    auto* sd = reinterpret_cast<qgm::TreeStepDev*>(h + P->off_tsteps);
+    auto* gt = reinterpret_cast<qgm::TreeGTab*>(h + P->off_tgtab);
+    auto* fac = reinterpret_cast<qgm::TFactor*>(h + P->off_tfac);
+    int n_g = 0, n_fac = 0;
+    for (size_t i = 0; i < t.steps.size(); ++i) {
+        const qgm::TreeStep& st = t.steps[i];
+        sd[i] = tree_step_dev(t, st);
+        if (st.factors.empty()) continue;
+        qgm::TreeGTab g{};
+        g.gb = st.gb();
+        g.sb = st.sb();
+        g.fac_off = n_fac;
+        g.n_fac = int32_t(st.factors.size());
+        g.g_off = st.g_off;
+        gt[n_g++] = g;
+        for (auto& f : st.factors) fac[n_fac++] = f;
+    }
+    auto* ph = reinterpret_cast<qgm::TFactor*>(h + P->off_tphase);
+    for (size_t i = 0; i < t.phase.size(); ++i) ph[i] = t.phase[i];
+    auto* fr = reinterpret_cast<int64_t*>(h + P->off_tfinal);
+    for (size_t i = 0; i < t.finals.size(); ++i) fr[i] = t.tensor_row[t.finals[i]];
+}
+
 void layout_tables(qgm_plan_t* P) {
     const qgm::Plan& p = P->p;
+    if (p.is_tree) { layout_tree_tables(P); return; }
     size_t n_sig = 0;
     for (auto& st : p.steps) n_sig += st.sig_src.size();
     P->off_fixed = 0;
@@ -116,18 +205,8 @@ void layout_tables(qgm_plan_t* P) {
     for (auto& st : p.steps) P->max_g_entries = std::max<uint32_t>(P->max_g_entries, uint32_t(st.g_entries()));
 }
 
-// Returns the device copy of the plan's constant tables for the current
-// device, uploading it on first use.
-qgm_status device_tables(qgm_plan_t* P, char** base) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    for (auto& d : P->p.dev)
-        if (d.device == dev) { *base = static_cast<char*>(d.base); return QGM_OK; }
+void fill_step_tables(const qgm_plan_t* P, char* h) {
     const qgm::Plan& p = P->p;
-    std::string host(P->total, '\0');
-    char* h = &host[0];
-    fixed_matrices(reinterpret_cast<double2*>(h + P->off_fixed));
     auto* tabs = reinterpret_cast<qgm::StepTab*>(h + P->off_steps);
     auto* ops = reinterpret_cast<qgm::GOp*>(h + P->off_ops);
     auto* sig = reinterpret_cast<int32_t*>(h + P->off_sig);
@@ -148,6 +227,21 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     std::memcpy(h + P->off_step_waves, P->step_waves.data(), sizeof(int32_t) * P->step_waves.size());
     std::memcpy(h + P->off_slot_off, P->slot_off.data(), sizeof(int32_t) * P->slot_off.size());
     std::memcpy(h + P->off_slot_ops, P->slot_ops.data(), sizeof(int32_t) * P->slot_ops.size());
+}
+
+// Returns the device copy of the plan's constant tables for the current
+// device, uploading it on first use.
+qgm_status device_tables(qgm_plan_t* P, char** base) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (auto& d : P->p.dev)
+        if (d.device == dev) { *base = static_cast<char*>(d.base); return QGM_OK; }
+    std::string host(P->total, '\0');
+    char* h = &host[0];
+    fixed_matrices(reinterpret_cast<double2*>(h + P->off_fixed));
+    if (P->p.is_tree) fill_tree_tables(P, h);
+    else fill_step_tables(P, h);
     void* d = nullptr;
     e = hipMalloc(&d, P->total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
@@ -323,7 +417,7 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     const int64_t B_pad = qgm::padded_batch(B);
     const int64_t B_eff = qgm::batch_eff(p, B);
     if (B_eff > (int64_t(1) << 26)) return fail(QGM_E_UNSUPPORTED, "batch times slice count exceeds 2^26");
-    if ((int64_t(1) << p.r_max) * (B_eff / 64) > (int64_t(1) << 31))
+    if ((int64_t(1) << p.r_max) * (B_eff / 64) >= (int64_t(1) << 31))
         return fail(QGM_E_UNSUPPORTED, "frontier rows times batch blocks exceed 2^31");
     const qgm::WsLayout w = qgm::workspace_layout(p, B);
     if (ws_bytes < w.total)
@@ -351,6 +445,46 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     }
     auto mark = [&](int i) { if (plan->timing) (void)hipEventRecord(ev[i], s); };
     mark(0);
+    if (p.is_tree) {
+        // bucket elimination: factor tables, one launch per tree level, FP64 product
+        const qgm::TreePlan& t = p.tree;
+        float2* arena = reinterpret_cast<float2*>(ws + w.f0);
+        float2* gt = reinterpret_cast<float2*>(ws + w.g);
+        const auto* fixed = reinterpret_cast<const double2*>(tables + plan->off_fixed);
+        const auto* slots = static_cast<const float2*>(gate_vals);
+        const auto* sd = reinterpret_cast<const qgm::TreeStepDev*>(tables + plan->off_tsteps);
+        mark(1);
+        qgm::launch_tree_g(reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab), plan->n_gtabs,
+                           plan->max_tree_g, reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tfac), fixed,
+                           slots, gt, s);
+        mark(2);
+        const int64_t n_bg = B_eff / 64;
+        for (const auto& lvl : t.levels) {
+            qgm::TreeLevel L{};
+            for (int sid : lvl) {
+                const int r = int(t.steps[sid].out_axes.size());
+                const int64_t units = (int64_t(1) << (r - std::min(r, qgm::kTreeOcBits))) * n_bg;
+                if (L.n == qgm::kTreeLevelSlots || int64_t(L.unit_start[L.n]) + units >= (int64_t(1) << 31)) {
+                    qgm::launch_tree_level(L, sd, arena, gt, bits, B, uint32_t(B_eff), s);
+                    L = qgm::TreeLevel{};
+                }
+                L.step[L.n] = sid;
+                L.unit_start[L.n + 1] = int32_t(L.unit_start[L.n] + units);
+                L.n++;
+            }
+            if (L.n > 0) qgm::launch_tree_level(L, sd, arena, gt, bits, B, uint32_t(B_eff), s);
+        }
+        mark(3);
+        if (out)
+            qgm::launch_tree_final(reinterpret_cast<const int64_t*>(tables + plan->off_tfinal), int(t.finals.size()),
+                                   reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tphase),
+                                   int(t.phase.size()), fixed, slots, arena, bits, B, uint32_t(B_eff), out,
+                                   p.opts.out_c128 != 0, s);
+        mark(4);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return QGM_OK;
+    }
     qgm::launch_boundary(bits, B, uint32_t(B_pad), uint32_t(B_eff), n_steps, tabs,
                          reinterpret_cast<const int32_t*>(tables + plan->off_sig), vids, s);
     mark(1);
@@ -381,6 +515,7 @@ qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint6
     g_err.clear();
     if (!plan || !bytes) return fail(QGM_E_INVALID, "plan or bytes is NULL");
     if (B < 0) return fail(QGM_E_INVALID, "B < 0");
+    if (plan->p.is_tree) return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a plan with ordering 0");
     *bytes = backward_layout(plan, B).total;
     return QGM_OK;
 }
@@ -392,6 +527,7 @@ qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
     if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
     if (B < 0) return fail(QGM_E_INVALID, "B < 0");
     const qgm::Plan& p = plan->p;
+    if (p.is_tree) return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a plan with ordering 0");
     if (B == 0) return QGM_OK;
     if (!bits || !grad_amps || !workspace || (p.n_slots > 0 && (!gate_vals || !gate_grads)))
         return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "
@@ -559,6 +695,7 @@ qgm_status qgm_autotune(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
     qgm_status st = amplitudes_impl(plan, gate_vals, bits, B, nullptr, workspace, ws_bytes, stream, true);
     if (st != QGM_OK) return st;
     qgm::Plan& p = plan->p;
+    if (p.is_tree) return QGM_OK;   // one bucket kernel: nothing to choose
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
     hipDeviceProp_t prop;

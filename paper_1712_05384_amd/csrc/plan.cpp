@@ -358,8 +358,8 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
                       const qgm_plan_opts& opts, Plan& p, std::string* err) {
     qgm_status st = validate(c, open, n_open, err);
     if (st != QGM_OK) return st;
-    if (opts.ordering != 0 || opts.precision != 0) {
-        *err = "only ordering 0 and precision 0 are implemented";
+    if ((opts.ordering != 0 && opts.ordering != 1) || opts.precision != 0) {
+        *err = "ordering must be 0 or 1 and precision 0";
         return QGM_E_UNSUPPORTED;
     }
     if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
@@ -414,8 +414,19 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     }
     for (int q = 0; q < n; ++q) p.vars[p.chain[q].back()].is_final = true;
     for (int i = 0; i < n_open; ++i) p.vars[p.chain[open[i]].back()].open_idx = i;
-    p.order = vertical_order(p.rows, p.cols);
     p.sliced.clear();
+    p.is_tree = opts.ordering == 1;
+    if (p.is_tree) {
+        st = build_tree_plan(p, p.tree, err);
+        if (st != QGM_OK) return st;
+        p.steps.clear();
+        p.order.clear();
+        p.final_pos.clear();
+        p.r_max = p.tree.max_rank;
+        p.g_total = p.tree.g_total;
+        return QGM_OK;
+    }
+    p.order = vertical_order(p.rows, p.cols);
     st = build_steps(p, err);
     if (st != QGM_OK) return st;
     while ((opts.max_rank > 0 && p.r_max > opts.max_rank) || int(p.sliced.size()) < opts.min_sliced_vars) {
@@ -437,6 +448,12 @@ WsLayout workspace_layout(const Plan& p, int64_t B) {
     auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
     WsLayout w;
     const uint64_t be = uint64_t(batch_eff(p, B));
+    if (p.is_tree) {
+        w.f0 = w.f1 = w.var_ids = 0;
+        w.g = al(uint64_t(p.tree.arena_rows) * be * 8);
+        w.total = w.g + al(uint64_t(p.tree.g_total) * 8);
+        return w;
+    }
     const uint64_t fbytes = al((uint64_t(1) << p.r_max) * be * 8);
     w.f0 = 0;
     w.f1 = fbytes;
@@ -458,12 +475,68 @@ static void json_ints(std::ostringstream& o, const std::vector<int>& v) {
     o << "]";
 }
 
+static void json_factor(std::ostringstream& o, const TFactor& f) {
+    o << "[" << f.type << "," << f.mat << "," << f.src0 << "," << f.bit0 << "," << f.src1 << "," << f.bit1 << "]";
+}
+
+static std::string tree_json(const Plan& p, int detail) {
+    const TreePlan& t = p.tree;
+    std::ostringstream o;
+    o.precision(17);
+    o << "{\"ordering\":1,\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols
+      << ",\"n_vars\":" << p.vars.size() << ",\"n_free\":" << t.n_free << ",\"n_open\":0,\"n_slots\":" << p.n_slots
+      << ",\"n_steps\":0,\"n_buckets\":" << t.steps.size() << ",\"n_levels\":" << t.levels.size()
+      << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
+      << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
+      << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
+      << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
+      << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size();
+    o << ",\"order\":"; json_ints(o, t.order);
+    o << ",\"finals\":"; json_ints(o, t.finals);
+    o << ",\"steps\":[],\"buckets\":[";
+    for (size_t i = 0; i < t.steps.size(); ++i) {
+        const TreeStep& st = t.steps[i];
+        o << (i ? "," : "") << "{\"var\":" << st.var << ",\"qubit\":" << p.vars[st.var].qubit
+          << ",\"k\":" << p.vars[st.var].k << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
+          << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
+          << ",\"n_factors\":" << st.factors.size() << ",\"g_off\":" << st.g_off
+          << ",\"bytes_per_b\":" << tree_step_bytes(t, st);
+        if (detail >= 1) {
+            o << ",\"out_tensor\":" << st.out_tensor;
+            o << ",\"out_axes\":"; json_ints(o, st.out_axes);
+            o << ",\"in_tensors\":"; json_ints(o, st.in_tensors);
+            o << ",\"gvars\":"; json_ints(o, st.gvars);
+            o << ",\"sig_q\":"; json_ints(o, st.sig_q);
+            o << ",\"factors\":[";
+            for (size_t j = 0; j < st.factors.size(); ++j) { if (j) o << ","; json_factor(o, st.factors[j]); }
+            o << "]";
+        }
+        o << "}";
+    }
+    o << "]";
+    if (detail >= 1) {
+        o << ",\"tensors\":[";
+        for (size_t i = 0; i < t.tensor_axes.size(); ++i) {
+            o << (i ? "," : "") << "{\"axes\":";
+            json_ints(o, t.tensor_axes[i]);
+            o << ",\"made\":" << t.tensor_made[i] << ",\"used\":" << t.tensor_used[i] << ",\"row\":" << t.tensor_row[i]
+              << "}";
+        }
+        o << "],\"phase\":[";
+        for (size_t j = 0; j < t.phase.size(); ++j) { if (j) o << ","; json_factor(o, t.phase[j]); }
+        o << "]";
+    }
+    o << "}";
+    return o.str();
+}
+
 std::string plan_json(const Plan& p, int detail) {
+    if (p.is_tree) return tree_json(p, detail);
     std::ostringstream o;
     o.precision(17);
     double bytes = 0, flops = 0;
     for (auto& st : p.steps) { bytes += st.bytes_per_b(); flops += st.flops_per_b(); }
-    o << "{\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols << ",\"n_vars\":" << p.vars.size()
+    o << "{\"ordering\":0,\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols << ",\"n_vars\":" << p.vars.size()
       << ",\"n_open\":" << p.n_open << ",\"n_slots\":" << p.n_slots << ",\"n_steps\":" << p.steps.size()
       << ",\"max_rank\":" << p.r_max << ",\"n_sliced\":" << p.sliced.size()
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates

@@ -8,6 +8,7 @@
 
 #include "qgm.h"
 #include "program.hpp"
+#include "tree.hpp"
 
 namespace qgm {
 
@@ -65,7 +66,7 @@ struct Plan {
     std::vector<VarInfo> vars;
     std::vector<std::vector<int>> chain;     // chain[q] = worldline variables of qubit q
     std::vector<GateRec> recs;               // time-ordered gates
-    std::vector<int> order;                  // elimination order of qubits
+    std::vector<int> order;                  // elimination order of qubits (ordering 0)
     std::vector<Step> steps;
     std::vector<int> sliced;                 // sliced variable ids
     std::vector<int> final_pos;              // output bit i -> position in the last frontier
@@ -73,6 +74,8 @@ struct Plan {
     int64_t g_total = 0;
     int64_t n_ops_total = 0;
     int n_diag_gates = 0, n_nondiag_gates = 0, n_cz = 0;
+    bool is_tree = false;                    // ordering 1: bucket elimination with a greedy order
+    TreePlan tree;
     // Device copies of the constant tables, one per device ordinal.
     struct DevTables { int device = -1; void* base = nullptr; };
     std::vector<DevTables> dev;
@@ -93,6 +96,9 @@ std::string plan_json(const Plan& p, int detail);
 int64_t padded_batch(int64_t B);
 inline int64_t batch_eff(const Plan& p, int64_t B) { return padded_batch(B) << p.sliced.size(); }
 
+// Workspace of a call.  Ordering 0: two frontier buffers, the variant ids
+// and the G table.  Ordering 1: the arena of bucket results (f0) and the
+// factor tables (g).
 struct WsLayout {
     uint64_t f0 = 0, f1 = 0, var_ids = 0, g = 0, total = 0;
 };

@@ -1,0 +1,366 @@
+// Bucket-elimination planner (ordering 1): greedy treewidth orders, bucket
+// steps, elimination-tree levels and the arena of intermediate results.
+#include "tree.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <limits>
+#include <map>
+#include <set>
+
+#include "plan.hpp"
+
+namespace qgm {
+
+namespace {
+
+// splitmix64 (Steele, Lea, Flood 2014): seeds the randomised tie breaks.
+struct SplitMix {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+enum { VK_FREE = 0, VK_ZERO = 1, VK_SIG = 2 };
+
+struct RawFactor {
+    int type, mat;
+    int v[2];
+    int nv;
+    std::vector<int> free;   // free-variable indices (fi) it touches, distinct
+};
+
+struct Model {
+    std::vector<int> kind;        // per variable id: VK_*
+    std::vector<int> fi;          // per variable id: free index or -1
+    std::vector<int> free_var;    // free index -> variable id
+    std::vector<RawFactor> facs;  // factors with at least one free variable
+    std::vector<TFactor> phase;
+};
+
+TFactor fixed_factor(const Plan& p, const Model& m, const RawFactor& f) {
+    TFactor t{};
+    t.type = f.type;
+    t.mat = f.mat;
+    int* srcs[2][2] = {{&t.src0, &t.bit0}, {&t.src1, &t.bit1}};
+    for (int i = 0; i < f.nv; ++i) {
+        const int v = f.v[i];
+        if (m.kind[v] == VK_SIG) { *srcs[i][0] = TS_SIG; *srcs[i][1] = p.vars[v].qubit; }
+        else { *srcs[i][0] = TS_ZERO; *srcs[i][1] = 0; }
+    }
+    return t;
+}
+
+// Greedy elimination order on the graph of free variables.  crit 0 picks the
+// variable of fewest alive neighbours (min-degree), crit 1 the one whose
+// elimination adds the fewest fill edges (min-fill, ties by degree); ties
+// left after that go to a per-variable priority (random or the index).
+std::vector<int> greedy_order(int nF, const std::vector<uint8_t>& adj0, int crit, uint64_t seed) {
+    std::vector<uint8_t> adj = adj0;
+    std::vector<int> deg(nF, 0), alive(nF, 1), score(nF, 0);
+    std::vector<uint64_t> prio(nF);
+    SplitMix rng{seed};
+    for (int i = 0; i < nF; ++i) prio[i] = seed ? rng.next() : uint64_t(i);
+    for (int i = 0; i < nF; ++i)
+        for (int j = 0; j < nF; ++j) deg[i] += adj[size_t(i) * nF + j];
+    auto nbrs = [&](int u, std::vector<int>& out) {
+        out.clear();
+        const uint8_t* row = &adj[size_t(u) * nF];
+        for (int j = 0; j < nF; ++j)
+            if (row[j] && alive[j]) out.push_back(j);
+    };
+    std::vector<int> nb, nb2;
+    auto fill_of = [&](int u) {
+        nbrs(u, nb2);
+        int f = 0;
+        for (size_t a = 0; a < nb2.size(); ++a)
+            for (size_t b = a + 1; b < nb2.size(); ++b) f += adj[size_t(nb2[a]) * nF + nb2[b]] ? 0 : 1;
+        return f;
+    };
+    if (crit == 1)
+        for (int i = 0; i < nF; ++i) score[i] = fill_of(i);
+    std::vector<int> order;
+    order.reserve(nF);
+    std::vector<uint8_t> dirty(nF, 0);
+    for (int it = 0; it < nF; ++it) {
+        int best = -1;
+        for (int u = 0; u < nF; ++u) {
+            if (!alive[u]) continue;
+            if (best < 0) { best = u; continue; }
+            const int su = crit == 1 ? score[u] : deg[u], sb = crit == 1 ? score[best] : deg[best];
+            if (su < sb || (su == sb && (deg[u] < deg[best] || (deg[u] == deg[best] && prio[u] < prio[best]))))
+                best = u;
+        }
+        nbrs(best, nb);
+        alive[best] = 0;
+        order.push_back(best);
+        for (int a : nb) deg[a] -= 1;
+        for (size_t a = 0; a < nb.size(); ++a)
+            for (size_t b = a + 1; b < nb.size(); ++b) {
+                uint8_t& e = adj[size_t(nb[a]) * nF + nb[b]];
+                if (!e) {
+                    e = 1;
+                    adj[size_t(nb[b]) * nF + nb[a]] = 1;
+                    deg[nb[a]] += 1;
+                    deg[nb[b]] += 1;
+                }
+            }
+        if (crit == 1) {
+            // fill counts change only within distance two of the eliminated variable
+            std::vector<int> touched;
+            for (int a : nb) {
+                if (!dirty[a]) { dirty[a] = 1; touched.push_back(a); }
+                nbrs(a, nb2);
+                for (int c : nb2)
+                    if (!dirty[c]) { dirty[c] = 1; touched.push_back(c); }
+            }
+            for (int u : touched) { score[u] = fill_of(u); dirty[u] = 0; }
+        }
+    }
+    return order;
+}
+
+struct SimOut {
+    bool ok = false;
+    double bytes = 0, flops = 0;
+    int levels = 0, max_rank = 0, max_in = 0;
+    std::string why;
+};
+
+// Runs bucket elimination over the structure for an order (free indices);
+// with `t` set, also records the steps.
+SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, TreePlan* t) {
+    SimOut r;
+    const int nF = int(order.size());
+    std::vector<int> pos(nF);
+    for (int i = 0; i < nF; ++i) pos[order[i]] = i;
+    std::vector<std::vector<int>> bfac(nF), bten(nF);
+    for (int f = 0; f < int(m.facs.size()); ++f) {
+        int e = nF;
+        for (int u : m.facs[f].free) e = std::min(e, pos[u]);
+        bfac[e].push_back(f);
+    }
+    std::vector<std::vector<int>> taxes;   // result axes (free indices, position ascending)
+    std::vector<int> tmade;
+    std::vector<int> finals;
+    for (int i = 0; i < nF; ++i) {
+        const int v = order[i];
+        std::set<int> A;
+        int level = 0;
+        for (int tid : bten[i]) {
+            for (int u : taxes[tid]) A.insert(u);
+            level = std::max(level, tmade[tid] + 1);
+        }
+        std::set<int> gset;
+        std::vector<int> sigq;
+        for (int f : bfac[i]) {
+            const RawFactor& rf = m.facs[f];
+            for (int u : rf.free) { A.insert(u); if (u != v) gset.insert(u); }
+            for (int k = 0; k < rf.nv; ++k)
+                if (m.kind[rf.v[k]] == VK_SIG) {
+                    const int q = p.vars[rf.v[k]].qubit;
+                    if (std::find(sigq.begin(), sigq.end(), q) == sigq.end()) sigq.push_back(q);
+                }
+        }
+        if (!A.count(v)) { r.why = "internal: variable missing from its bucket"; return r; }
+        std::vector<int> out;
+        for (int u : A) if (u != v) out.push_back(u);
+        std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+        const int n_in = int(bten[i].size());
+        if (int(out.size()) > kTreeMaxRank || n_in > kTreeMaxIn || int(gset.size()) > kTreeMaxGBits ||
+            int(sigq.size()) > kTreeMaxSig || int(gset.size()) + 1 + int(sigq.size()) > kTreeMaxGIndex) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "bucket exceeds kernel limits (rank %d, inputs %d, table bits %d, output bits %d)",
+                     int(out.size()), n_in, int(gset.size()), int(sigq.size()));
+            r.why = buf;
+            return r;
+        }
+        const bool has_g = !bfac[i].empty();
+        const double rows = double(int64_t(1) << out.size());
+        double bytes = 8.0 * rows;
+        for (int tid : bten[i]) bytes += 8.0 * double(int64_t(1) << taxes[tid].size());
+        const int mult = n_in + (has_g ? 1 : 0);
+        r.bytes += bytes;
+        r.flops += 2.0 * rows * (6.0 * std::max(mult - 1, 0) + 2.0);
+        r.levels = std::max(r.levels, level + 1);
+        r.max_rank = std::max(r.max_rank, int(out.size()));
+        r.max_in = std::max(r.max_in, n_in);
+        const int tid = int(taxes.size());
+        taxes.push_back(out);
+        tmade.push_back(level);
+        if (out.empty()) finals.push_back(tid);
+        else bten[pos[out[0]]].push_back(tid);
+        if (t) {
+            TreeStep st;
+            st.var = m.free_var[v];
+            st.level = level;
+            st.out_tensor = tid;
+            for (int u : out) st.out_axes.push_back(m.free_var[u]);
+            st.in_tensors = bten[i];
+            std::vector<int> g(gset.begin(), gset.end());
+            std::sort(g.begin(), g.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+            for (int u : g) st.gvars.push_back(m.free_var[u]);
+            st.sig_q = sigq;
+            for (int f : bfac[i]) {
+                const RawFactor& rf = m.facs[f];
+                TFactor tf{};
+                tf.type = rf.type;
+                tf.mat = rf.mat;
+                int* srcs[2][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}};
+                for (int k = 0; k < rf.nv; ++k) {
+                    const int var = rf.v[k];
+                    if (m.kind[var] == VK_FREE) {
+                        const int u = m.fi[var];
+                        *srcs[k][0] = TS_G;
+                        *srcs[k][1] = u == v ? 0 : 1 + int(std::find(g.begin(), g.end(), u) - g.begin());
+                    } else if (m.kind[var] == VK_SIG) {
+                        *srcs[k][0] = TS_SIG;
+                        *srcs[k][1] = int(std::find(sigq.begin(), sigq.end(), p.vars[var].qubit) - sigq.begin());
+                    } else {
+                        *srcs[k][0] = TS_ZERO;
+                        *srcs[k][1] = 0;
+                    }
+                }
+                st.factors.push_back(tf);
+            }
+            t->steps.push_back(std::move(st));
+        }
+    }
+    if (t) {
+        t->tensor_axes.clear();
+        for (auto& a : taxes) {
+            std::vector<int> ax;
+            for (int u : a) ax.push_back(m.free_var[u]);
+            t->tensor_axes.push_back(ax);
+        }
+        t->tensor_made = tmade;
+        t->finals = finals;
+    }
+    r.ok = true;
+    return r;
+}
+
+}  // namespace
+
+double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
+    double b = 8.0 * double(int64_t(1) << st.out_axes.size());
+    for (int tid : st.in_tensors) b += 8.0 * double(int64_t(1) << t.tensor_axes[tid].size());
+    return b;
+}
+
+qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
+    t = TreePlan{};
+    if (p.n_open != 0) { *err = "ordering 1 supports no open qubits"; return QGM_E_UNSUPPORTED; }
+    if (p.opts.min_sliced_vars != 0 || p.opts.max_rank != 0) {
+        *err = "ordering 1 does not slice (min_sliced_vars and max_rank must be 0)";
+        return QGM_E_UNSUPPORTED;
+    }
+    Model m;
+    const int nv = int(p.vars.size());
+    m.kind.assign(nv, VK_FREE);
+    m.fi.assign(nv, -1);
+    for (int v = 0; v < nv; ++v) {
+        const VarInfo& vi = p.vars[v];
+        if (vi.is_c0) {
+            m.kind[v] = VK_ZERO;
+            if (vi.is_final) {   // a worldline without non-diagonal gates: b = 0 must equal x_q
+                TFactor d{};
+                d.type = TF_DELTA0;
+                d.src0 = TS_SIG;
+                d.bit0 = vi.qubit;
+                m.phase.push_back(d);
+            }
+        } else if (vi.is_final) {
+            m.kind[v] = VK_SIG;
+        } else {
+            m.fi[v] = int(m.free_var.size());
+            m.free_var.push_back(v);
+        }
+    }
+    const int nF = int(m.free_var.size());
+    for (const GateRec& g : p.recs) {
+        RawFactor f{};
+        f.mat = g.mat;
+        if (g.type == 0) { f.type = TF_MAT; f.v[0] = g.var0; f.v[1] = g.var1; f.nv = 2; }
+        else if (g.type == 1) { f.type = TF_DIAG; f.v[0] = g.var0; f.v[1] = -1; f.nv = 1; }
+        else { f.type = TF_CZ; f.mat = -1; f.v[0] = g.var0; f.v[1] = g.var1; f.nv = 2; }
+        for (int k = 0; k < f.nv; ++k) {
+            const int u = m.fi[f.v[k]];
+            if (u >= 0 && std::find(f.free.begin(), f.free.end(), u) == f.free.end()) f.free.push_back(u);
+        }
+        if (f.free.empty()) m.phase.push_back(fixed_factor(p, m, f));
+        else m.facs.push_back(f);
+    }
+    t.phase = m.phase;
+    t.n_free = nF;
+    std::vector<uint8_t> adj(size_t(nF) * nF, 0);
+    for (auto& f : m.facs)
+        if (f.free.size() == 2) {
+            adj[size_t(f.free[0]) * nF + f.free[1]] = 1;
+            adj[size_t(f.free[1]) * nF + f.free[0]] = 1;
+        }
+    // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks
+    const int restarts = nF > 1500 ? 1 : (nF > 600 ? 4 : 16);
+    std::vector<int> best;
+    SimOut best_r;
+    double best_cost = std::numeric_limits<double>::infinity();
+    std::string last_why;
+    for (int crit = 0; crit < 2; ++crit)
+        for (int rs = 0; rs <= restarts; ++rs) {
+            std::vector<int> ord = greedy_order(nF, adj, crit, rs == 0 ? 0 : 0x5EED0000ull + uint64_t(rs) * 131 + crit);
+            SimOut r = simulate(p, m, ord, nullptr);
+            ++t.n_candidates;
+            if (!r.ok) { last_why = r.why; continue; }
+            // a level costs about one launch: weigh it as 4 KiB per bitstring
+            const double cost = r.bytes + 4096.0 * r.levels;
+            if (cost < best_cost) { best_cost = cost; best = ord; best_r = r; }
+        }
+    if (best.empty() && nF > 0) { *err = "no elimination order fits the kernels: " + last_why; return QGM_E_UNSUPPORTED; }
+    SimOut r = simulate(p, m, best, &t);
+    if (!r.ok) { *err = r.why; return QGM_E_INTERNAL; }
+    for (int u : best) t.order.push_back(m.free_var[u]);
+    t.max_rank = r.max_rank;
+    t.max_in = r.max_in;
+    t.bytes_per_b = r.bytes;
+    t.flops_per_b = r.flops;
+    const int n_levels = r.levels;
+    t.levels.assign(n_levels, {});
+    for (int s = 0; s < int(t.steps.size()); ++s) t.levels[t.steps[s].level].push_back(s);
+    // last level reading each result (the final product counts as level n_levels)
+    const int T = int(t.tensor_axes.size());
+    t.tensor_used.assign(T, n_levels);
+    for (auto& st : t.steps)
+        for (int tid : st.in_tensors) t.tensor_used[tid] = st.level;
+    // arena: results whose level intervals overlap get disjoint rows
+    std::vector<int> idx(T);
+    for (int i = 0; i < T; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return t.tensor_axes[a].size() > t.tensor_axes[b].size(); });
+    t.tensor_row.assign(T, -1);
+    std::vector<int> placed;
+    for (int a : idx) {
+        const int64_t size = int64_t(1) << t.tensor_axes[a].size();
+        std::vector<std::pair<int64_t, int64_t>> busy;
+        for (int b : placed)
+            if (!(t.tensor_used[b] < t.tensor_made[a] || t.tensor_used[a] < t.tensor_made[b]))
+                busy.push_back({t.tensor_row[b], t.tensor_row[b] + (int64_t(1) << t.tensor_axes[b].size())});
+        std::sort(busy.begin(), busy.end());
+        int64_t off = 0;
+        for (auto& iv : busy) {
+            if (off + size <= iv.first) break;
+            off = std::max(off, iv.second);
+        }
+        t.tensor_row[a] = off;
+        t.arena_rows = std::max(t.arena_rows, off + size);
+        placed.push_back(a);
+    }
+    int64_t g = 0;
+    for (auto& st : t.steps) { st.g_off = g; g += st.g_entries(); }
+    t.g_total = g;
+    return QGM_OK;
+}
+
+}  // namespace qgm

@@ -1,0 +1,170 @@
+"""GPU parity of the bucket-elimination path (ordering 1: greedy treewidth
+order, one launch per elimination-tree level) against the FP64 oracle.
+
+Same tolerance as the vertical path: max |A_gpu - A_oracle| <= 1e-5 * 2^{-n/2}.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_05384_amd import circuits as C
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _tree(c, **kw):
+    import paper_1712_05384_amd as Q
+    return Q.plan(c, ordering=1, **kw)
+
+
+def _amps(p, bits, gate_vals=None):
+    out = p.amplitudes(bits, gate_vals)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[:, 0]
+
+
+def test_app_d_tree():
+    d = C.example_app_d()
+    got = _amps(_tree(d), np.arange(4, dtype=np.uint64))
+    assert np.allclose(got, [0.5, 0.5, 0.5, -0.5], atol=1e-7)
+
+
+def test_tree_c1_full_batch():
+    c, bits = C.workload("c1_4x4_d16")
+    _say("case tree c1_4x4_d16 B=64")
+    got = _amps(_tree(c), bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("B", [1, 5, 63, 64, 65, 130])
+def test_tree_ragged_batches(B):
+    c = C.random_grid_circuit(3, 4, 12, 7)
+    bits = C.random_bitstrings(c.n, B, 7)
+    _say("case tree 3x4_d12 B=%d" % B)
+    got = _amps(_tree(c), bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(1, 1, 3, 1), (2, 2, 1, 2), (1, 5, 12, 3), (4, 4, 24, 4),
+                                                  (3, 5, 20, 5), (4, 5, 16, 6), (5, 4, 30, 16)])
+def test_tree_random_circuits(rows, cols, depth, seed):
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 256, seed)
+    _say("case tree %s B=256" % c.name)
+    got = _amps(_tree(c), bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_gate_values_and_c128():
+    c = C.parameterised_circuit(4, 4, 14, 8)
+    bits = C.random_bitstrings(c.n, 128, 8)
+    gv = c.gate_vals.astype(np.complex64)
+    _say("case tree %s B=128 (gate_vals, complex128 out)" % c.name)
+    got = _amps(_tree(c, out_c128=True), bits, torch.tensor(gv))
+    assert got.dtype == np.complex128
+    ref = oracle.sv_amplitudes(c.n, c.gates, gv.astype(np.complex128), bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_qubit_without_non_diagonal_gates():
+    """b^0 = b^d = 0 on a worldline without non-diagonal gates: amplitude 0 when x_q = 1."""
+    g = np.array([(C.H, 0, 0, -1, -1), (C.CZ, 1, 0, 1, -1), (C.T, 2, 1, -1, -1), (C.H, 3, 0, -1, -1),
+                  (C.H, 0, 2, -1, -1), (C.CZ, 4, 1, 2, -1), (C.XH, 5, 2, -1, -1)])
+    c = C.Circuit(1, 3, g)
+    bits = np.arange(8, dtype=np.uint64)
+    got = _amps(_tree(c), bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() <= 1e-7
+
+
+def test_tree_clifford_probabilities_dyadic_36_qubits():
+    c = C.clifford_variant(C.random_grid_circuit(6, 6, 12, 11))
+    bits = C.random_bitstrings(c.n, 256, 11)
+    _say("case tree clifford 6x6_d12")
+    got = _amps(_tree(c), bits, torch.tensor(c.gate_vals.astype(np.complex64)))
+    p = np.abs(got) ** 2
+    nz = p[p > 2.0 ** (-c.n - 8)]
+    assert len(nz) > 0
+    k = np.log2(1 / nz)
+    assert np.abs(k - np.round(k)).max() < 1e-4
+
+
+def test_tree_c2_full_size_and_vertical_agreement():
+    """5x5 depth 25, 1024 bitstrings: the bucket path against the 2^25 state
+    vector, and against the vertical path."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c2_5x5_d25")
+    _say("case tree c2_5x5_d25 B=1024")
+    got = _amps(_tree(c), bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    err = np.abs(got - ref).max()
+    _say("  tree c2 max err * 2^(n/2) = %.3g" % (err * 2 ** (c.n / 2)))
+    assert err <= TOL * 2 ** (-c.n / 2)
+    vert = _amps(Q.plan(c), bits)
+    assert np.abs(vert - got).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_c3_against_stored_oracle():
+    """5x6 depth 30, 1024 bitstrings, no slicing needed (largest bucket result
+    rank 16), complex128 output, against the stored FP64 state-vector values."""
+    c, bits = C.workload("c3_5x6_d30")
+    ref = np.load(os.path.join(GOLDEN, "c3_5x6_d30_amps.npy"), allow_pickle=False)
+    _say("case tree c3 5x6 d30 B=1024")
+    got = _amps(_tree(c, out_c128=True), bits)
+    err = np.abs(got - ref).max()
+    _say("  tree c3 max err * 2^(n/2) = %.3g" % (err * 2 ** (c.n / 2)))
+    assert err <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_c4_parameterised_workload():
+    c, bits = C.workload("c4_5x5_d20_U")
+    gv = c.gate_vals.astype(np.complex64)
+    _say("case tree c4 5x5 d20 U B=256")
+    got = _amps(_tree(c), bits, torch.tensor(gv))
+    ref = oracle.sv_amplitudes(c.n, c.gates, gv.astype(np.complex128), bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_repeat_calls_bitwise_identical():
+    c, bits = C.workload("c1_4x4_d16")
+    p = _tree(c)
+    a = _amps(p, bits)
+    for _ in range(3):
+        assert np.array_equal(_amps(p, bits), a)
+
+
+def test_tree_graph_mixed_with_vertical():
+    """A HIP graph holding a bucket plan and a vertical plan replays to the eager results."""
+    import paper_1712_05384_amd as Q
+    c1 = C.random_grid_circuit(4, 4, 16, 2)
+    c2 = C.parameterised_circuit(3, 3, 10, 3)
+    plans = [_tree(c1), Q.plan(c2), _tree(c2)]
+    bits = [C.random_bitstrings(c1.n, 130, 1), C.random_bitstrings(c2.n, 64, 2), C.random_bitstrings(c2.n, 64, 2)]
+    gv2 = c2.gate_vals.astype(np.complex64)
+    gvs = [None, gv2, gv2]
+    eager = [p.amplitudes(b, g).cpu().numpy() for p, b, g in zip(plans, bits, gvs)]
+    g = Q.Graph(plans, bits, gvs)
+    for rep in range(3):
+        outs = [o.cpu().numpy() for o in g.launch()]
+        torch.cuda.synchronize()
+        for a, b in zip(outs, eager):
+            assert np.array_equal(a, b), rep
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+    ref = oracle.sv_amplitudes(c1.n, c1.gates, None, bits[0])
+    assert np.abs(eager[0][:, 0] - ref).max() <= TOL * 2 ** (-c1.n / 2)
+    assert np.abs(eager[2] - eager[1]).max() <= TOL * 2 ** (-c2.n / 2)

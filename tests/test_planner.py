@@ -173,3 +173,90 @@ def test_kernel_classification():
         ok = 3 <= s["kb"] <= 5 and 3 <= s["nb"] <= 5 and s["r_in"] - s["kb"] - s["vb"] >= 4 and s["sb"] <= 4
         assert (s["kernel"] == "mfma_f32") == (ok and not s["input_is_one"])
     assert any(s["kernel"] == "mfma_f32" for s in forced)
+
+
+# --- bucket-elimination plans (ordering 1) -------------------------------------------------
+
+from tree_interp import run_tree_plan  # noqa: E402
+
+
+def _check_tree(c, bits, ref=None, **opts):
+    info = Q.plan(c, ordering=1, **opts).info(1)
+    got = run_tree_plan(info, c.gate_vals, bits)
+    if ref is None:
+        ref = oracle.sv_amplitudes(c.n, c.gates, c.gate_vals, bits)
+    assert np.abs(got - ref).max() < 1e-12 * max(1.0, 2 ** (-c.n / 2) * 1e3), c.name
+    return info
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(1, 1, 5, 1), (1, 3, 8, 2), (2, 2, 1, 3), (2, 2, 2, 4),
+                                                  (3, 3, 12, 5), (2, 4, 16, 6), (4, 2, 16, 7), (3, 4, 10, 8)])
+def test_tree_plan_matches_oracle(rows, cols, depth, seed):
+    """Bucket elimination of App. A along the planner's greedy order, run by the
+    CPU interpreter with arena-overlap checks, equals the state vector."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    _check_tree(c, C.random_bitstrings(c.n, 40, seed))
+
+
+def test_tree_plan_parameterised_clifford_and_bare_qubit():
+    c = C.parameterised_circuit(3, 3, 9, 11)
+    _check_tree(c, C.random_bitstrings(c.n, 20, 11))
+    k = C.clifford_variant(C.random_grid_circuit(3, 3, 10, 12))
+    _check_tree(k, C.random_bitstrings(k.n, 20, 12))
+    g = np.array([(C.H, 0, 0, -1, -1), (C.CZ, 1, 0, 1, -1), (C.T, 2, 1, -1, -1), (C.H, 3, 0, -1, -1)])
+    info = _check_tree(C.Circuit(1, 3, g), np.arange(8, dtype=np.uint64))
+    assert any(f[0] == 3 for f in info["phase"])   # the x_q = 0 delta of the bare worldline
+
+
+@pytest.mark.parametrize("name", ["c1_4x4_d16", "c2_5x5_d25", "c4_5x5_d20_U"])
+def test_tree_plan_workloads_against_bucket_oracle(name):
+    c, bits = C.workload(name)
+    bits = bits[:6]
+    ref = oracle.bucket_amplitudes(c.n, c.gates, c.gate_vals, bits)
+    info = _check_tree(c, bits, ref)
+    assert info["n_levels"] <= info["n_buckets"]
+
+
+def test_tree_orders_beat_vertical():
+    """Greedy treewidth orders need far less traffic than the vertical order
+    (Sec. IV.B: heuristic orders beat the vertical one)."""
+    for name, factor in (("c2_5x5_d25", 10), ("c3_5x6_d30", 8), ("c5_6x6_d24", 30)):
+        c, _ = C.workload(name)
+        t = Q.plan(c, ordering=1).info(0)
+        v = Q.plan(c).info(0)
+        assert t["bytes_per_amp"] * factor < v["bytes_per_amp"], (name, t["bytes_per_amp"], v["bytes_per_amp"])
+        assert t["max_rank"] < v["max_rank"]
+
+
+def test_tree_plan_is_deterministic_and_consistent():
+    c, _ = C.workload("c2_5x5_d25")
+    a = Q.plan(c, ordering=1).info(1)
+    b = Q.plan(c, ordering=1).info(1)
+    assert a == b
+    assert sorted(a["order"]) == sorted(s["var"] for s in a["buckets"])
+    assert a["n_free"] == len(a["order"])
+    assert abs(sum(s["bytes_per_b"] for s in a["buckets"]) - a["bytes_per_amp"]) < 1e-6 * a["bytes_per_amp"]
+    # every result is read by exactly one later bucket or by the final product
+    readers = [0] * len(a["tensors"])
+    for s in a["buckets"]:
+        for t in s["in_tensors"]:
+            readers[t] += 1
+            assert a["tensors"][t]["made"] < s["level"]
+    for t in a["finals"]:
+        readers[t] += 1
+    assert readers == [1] * len(a["tensors"])
+
+
+def test_tree_plan_rejects_open_qubits_slicing_and_backward():
+    c = C.random_grid_circuit(3, 3, 8, 1)
+    for kw in (dict(open_qubits=(0,)), dict(min_sliced_vars=1), dict(max_rank=3)):
+        oq = kw.pop("open_qubits", ())
+        with pytest.raises(N.QgmError) as e:
+            Q.plan(c, oq, ordering=1, **kw)
+        assert e.value.status == N.QGM_E_UNSUPPORTED
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(c, ordering=2)
+    assert e.value.status == N.QGM_E_UNSUPPORTED
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(c, ordering=1).backward_workspace_bytes(64)
+    assert e.value.status == N.QGM_E_UNSUPPORTED

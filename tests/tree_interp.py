@@ -1,0 +1,116 @@
+"""CPU interpreter of a bucket-elimination plan (ordering 1), complex128.
+
+It executes the planner's output -- bucket factor lists, axis layouts,
+variant bits, tree levels and arena rows -- with the semantics the HIP bucket
+kernels implement, so the planner can be checked against the oracle without a
+GPU.  Results live in a simulated arena: every row remembers which result
+wrote it, a read checks that the row still holds that result, and a level's
+writes may not land on rows of a result that the level (or a later one) still
+reads.  It is neither the oracle nor a fallback of the product path.
+"""
+import numpy as np
+
+from oracle.gates import gate_matrix
+
+TS_ZERO, TS_G, TS_SIG = 0, 1, 2
+TF_MAT, TF_DIAG, TF_CZ, TF_DELTA0 = 0, 1, 2, 3
+
+
+def _mat(idx, gate_vals):
+    if idx < 4:
+        return gate_matrix(idx, -1, None)
+    return np.asarray(gate_vals[idx - 4], dtype=np.complex128).reshape(2, 2)
+
+
+def _factor(f, a, b, gate_vals):
+    typ, mat = f[0], f[1]
+    if typ == TF_MAT:
+        return _mat(mat, gate_vals)[a, b]
+    if typ == TF_DIAG:
+        return _mat(mat, gate_vals)[a, a]
+    if typ == TF_CZ:
+        return np.where((a & b) == 1, -1.0, 1.0)
+    return np.where(a == 1, 0.0, 1.0)
+
+
+def bucket_table(st, gate_vals):
+    """G of a bucket as [2^(gb+1) (index c = (g << 1) | v), 2^sb]."""
+    gb, sb = st["gb"], st["sb"]
+    c = np.arange(1 << (gb + 1))[:, None]
+    sig = np.arange(1 << sb)[None, :]
+    acc = np.ones((1 << (gb + 1), 1 << sb), dtype=np.complex128)
+
+    def val(src, bit):
+        if src == TS_G:
+            return ((c >> bit) & 1) + 0 * sig
+        if src == TS_SIG:
+            return ((sig >> bit) & 1) + 0 * c
+        return np.zeros_like(c + sig)
+
+    for f in st["factors"]:
+        acc = acc * _factor(f, val(f[2], f[3]), val(f[4], f[5]), gate_vals)
+    return acc
+
+
+def run_tree_plan(info, gate_vals, bits):
+    """Executes a detail-1 tree plan for uint64 bitstrings; returns complex128 [B]."""
+    bits = np.asarray(bits, dtype=np.uint64)
+    B = len(bits)
+    tensors = info["tensors"]
+    arena = np.zeros((max(info["arena_rows"], 1), B), dtype=np.complex128)
+    owner = np.full(max(info["arena_rows"], 1), -1)
+    xb = lambda q: ((bits >> np.uint64(q)) & np.uint64(1)).astype(np.int64)
+
+    def read(tid):
+        t = tensors[tid]
+        rows = slice(t["row"], t["row"] + (1 << len(t["axes"])))
+        assert (owner[rows] == tid).all(), f"result {tid} was overwritten before it was read"
+        return arena[rows]
+
+    levels = {}
+    for st in info["buckets"]:
+        levels.setdefault(st["level"], []).append(st)
+    for L in sorted(levels):
+        pending = []
+        for st in levels[L]:
+            v = st["var"]
+            out_axes = st["out_axes"]
+            r = len(out_axes)
+            o = np.arange(1 << r)
+            bit_of = {ax: (o >> j) & 1 for j, ax in enumerate(out_axes)}
+            sig = np.zeros(B, dtype=np.int64)
+            for i, q in enumerate(st["sig_q"]):
+                sig |= xb(q) << i
+            acc = np.zeros((1 << r, B), dtype=np.complex128)
+            for vv in (0, 1):
+                term = np.ones((1 << r, B), dtype=np.complex128)
+                if st["factors"]:
+                    G = bucket_table(st, gate_vals)
+                    g = np.zeros(1 << r, dtype=np.int64)
+                    for j, gv in enumerate(st["gvars"]):
+                        g |= bit_of[gv] << j
+                    term *= G[(g << 1) | vv][:, sig]
+                for tid in st["in_tensors"]:
+                    T = read(tid)
+                    idx = np.zeros(1 << r, dtype=np.int64)
+                    for a, ax in enumerate(tensors[tid]["axes"]):
+                        idx |= (vv if ax == v else bit_of[ax]) << a
+                    term *= T[idx]
+                acc += term
+            pending.append((st["out_tensor"], acc))
+        for tid, acc in pending:
+            t = tensors[tid]
+            rows = np.arange(t["row"], t["row"] + (1 << len(t["axes"])))
+            for rr in rows:
+                prev = owner[rr]
+                assert prev < 0 or tensors[prev]["used"] < L, f"level {L} overwrites result {prev} still in use"
+            arena[rows] = acc
+            owner[rows] = tid
+    amp = np.ones(B, dtype=np.complex128)
+    for f in info["phase"]:
+        a = xb(f[3]) if f[2] == TS_SIG else np.zeros(B, dtype=np.int64)
+        b = xb(f[5]) if f[4] == TS_SIG else np.zeros(B, dtype=np.int64)
+        amp = amp * _factor(f, a, b, gate_vals)
+    for tid in info["finals"]:
+        amp = amp * read(tid)[0]
+    return amp

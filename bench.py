@@ -1,17 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the amplitude path on one MI355X.
 
-A "step" is one qgm_amplitudes call over the whole batch: boundary kernel,
-G build, every elimination step and the FP64 output stage, with bitstrings,
+A "step" is one qgm_amplitudes call over the whole batch, with bitstrings,
 workspace and output already resident in HBM.  Default workload: the 5x5
-depth-25 random grid circuit (seed 201) with 1024 uniform bitstrings.
+depth-25 random grid circuit (seed 201) with 1024 uniform bitstrings, planned
+with ordering 1 (bucket elimination along a greedy treewidth order): the
+prologue kernel (factor tables, sigma rows), one bucket-kernel launch per
+elimination-tree level and the FP64 output product.  --ordering 0 times the
+vertical-order path instead (worldline steps, autotuned kernels).
 
 Prints one JSON line.  The roofline object is for the dominant kernel (the
-elimination-step kernel): algorithmic bytes per launch (read F + write F' +
-variant ids, from the plan) over its average launch duration, timed with HIP
-events on the stream the kernels run on.  The cpu_baseline leg times the FP64
-state-vector oracle on the host cores over the same circuit and bitstrings,
-and its amplitudes give the max error of the GPU result.
+bucket kernel, or the worldline-step kernel for ordering 0): algorithmic bytes
+per launch (every input result read once, every result written once, from
+the plan) over its average launch duration, timed with HIP events on the
+stream the kernels run on.  The cpu_baseline leg times the FP64 state-vector
+oracle on the host cores over the same circuit and bitstrings, and its
+amplitudes give the max error of the GPU result.
 """
 import argparse
 import json
@@ -23,10 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per elimination-step launch on the default workload, from two
+# HBM bytes per dominant-kernel launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
-# plain 1 GiB copy gives), valid for the step-kernel source with this hash.
-MEASURED_TRAFFIC = {"c2_5x5_d25": {"bytes_per_launch": 226794653.4, "kernels_sha256_16": "a72736aaae65f038"}}
+# plain 1 GiB copy gives), valid for the kernel source with this hash.
+MEASURED_TRAFFIC = {
+    ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
+}
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
 
 
@@ -42,9 +48,11 @@ def main() -> int:
                     help="skip the secondary workloads (C4 gradients, C3 sliced, C5 four-circuit graph)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the policy's kernels instead of timing them")
+    ap.add_argument("--ordering", type=int, default=1,
+                    help="1 bucket elimination along a greedy treewidth order (default), 0 vertical order")
+    ap.add_argument("--no-autotune", action="store_true", help="ordering 0: keep the policy's kernels")
     ap.add_argument("--kernel-policy", type=int, default=0,
-                    help="0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
+                    help="ordering 0: 0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -69,10 +77,10 @@ def main() -> int:
     c, bits = C.workload(args.workload)
     B = len(bits)
     t0 = time.perf_counter()
-    p = Q.plan(c, kernel_policy=args.kernel_policy)
+    p = Q.plan(c, kernel_policy=args.kernel_policy, ordering=args.ordering)
     plan_s = time.perf_counter() - t0
     info = p.info(0)
-    print(f"# plan: n={c.n} steps={info['n_steps']} max_rank={info['max_rank']} "
+    print(f"# plan: n={c.n} ordering={args.ordering} max_rank={info['max_rank']} "
           f"bytes/amp={info['bytes_per_amp']:.3g} flops/amp={info['flops_per_amp']:.3g} plan_s={plan_s:.3f}",
           file=sys.stderr, flush=True)
     gv = None if c.gate_vals is None else torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
@@ -81,23 +89,27 @@ def main() -> int:
     ws = torch.empty(p.workspace_bytes(B), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
     kernels = None
-    if not args.no_autotune:
+    if args.ordering == 0 and not args.no_autotune:
         kernels = p.autotune(bits_d, gv, stream=stream)   # per-step kernel by measurement (complex64 kernels only)
         info = p.info(0)
 
     for _ in range(args.warmup):
         p.amplitudes(bits_d, gv, out=out, workspace=ws, stream=stream)
     torch.cuda.synchronize()
-    p.set_timing(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
         p.amplitudes(bits_d, gv, out=out, workspace=ws, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
+    # phase split from separate calls with the plan's own HIP events between
+    # the phases (each event adds a few microseconds, so not in the timed loop)
+    p.set_timing(True)
+    for _ in range(args.steps):
+        p.amplitudes(bits_d, gv, out=out, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
     phases, ncalls = p.timings()
     p.set_timing(False)
     ms_per_step = total_ms / args.steps
@@ -105,38 +117,17 @@ def main() -> int:
     print(f"# timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.4g} amplitudes/s", file=sys.stderr,
           flush=True)
 
-    # dominant kernel: the elimination steps
-    B_eff = ((B + 63) // 64 * 64) << info["n_sliced"]
-    step_bytes = B_eff * sum(s["bytes_per_b"] for s in info["steps"])
-    n_launch = info["n_steps"]
-    step_ms = phases[2] / max(ncalls, 1)
-    achieved = step_bytes / (step_ms / 1e3) / 1e9
-    traffic = None
-    rec = MEASURED_TRAFFIC.get(args.workload)
-    if rec and args.kernel_policy == 0 and args.no_autotune:
-        import hashlib
-        src = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", "kernels.hip")
-        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == rec["kernels_sha256_16"]:
-            traffic = round(rec["bytes_per_launch"] / (step_ms / n_launch / 1e3) / 1e9, 1)   # GB/s of HBM traffic
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_bytes_per_launch": rec["bytes_per_launch"] if traffic is not None else None,
-                "kernel": "k_step (elimination step)", "bytes_per_launch": step_bytes / n_launch,
-                "launch_ms": step_ms / n_launch, "launches_per_step": n_launch}
-
+    roofline, cfg = dominant_kernel(args, p, info, B, phases[2] / max(ncalls, 1), kernels)
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": f"{c.name}: {c.rows}x{c.cols} grid, depth {c.depth()}, {B} uniform bitstrings, "
-                               f"complex64, one plan for the batch", "global_batch": B,
-                   "qubits": c.n, "max_rank": info["max_rank"], "sliced_vars": info["n_sliced"],
-                   "kernel_policy": args.kernel_policy, "autotuned": not args.no_autotune,
-                   "step_kernels": {k: (kernels or [st["kernel"] for st in info["steps"]]).count(k)
-                                    for k in ("valu", "valu_pair", "mfma_f32", "mfma_bf16x3")}},
-        "phases_ms_per_step": {k: round(v / max(ncalls, 1), 5) for k, v in
-                               zip(("boundary", "g_build", "elimination", "output"), phases)},
+        "config": dict({"workload": f"{c.name}: {c.rows}x{c.cols} grid, depth {c.depth()}, {B} uniform bitstrings, "
+                                    f"complex64, one plan for the batch", "global_batch": B,
+                        "qubits": c.n, "ordering": args.ordering, "max_rank": info["max_rank"]}, **cfg),
+        "phases_ms_per_call_with_events": {k: round(v / max(ncalls, 1), 5) for k, v in
+                                           zip(("boundary", "tables", "elimination", "output"), phases)},
         "plan_seconds": round(plan_s, 4),
         "roofline": roofline,
     }
@@ -186,6 +177,50 @@ def main() -> int:
     return 0
 
 
+def dominant_kernel(args, p, info, B, elim_ms, kernels):
+    """Roofline object of the dominant kernel and its config keys.  elim_ms is
+    the per-call time of all its launches (HIP events around them)."""
+    B_eff = ((B + 63) // 64 * 64) << info["n_sliced"]
+    if info["ordering"] == 1:
+        kernel = "k_tree_level (bucket elimination, one launch per elimination-tree level)"
+        n_launch = info["n_levels"]
+        alg_bytes = B_eff * sum(s["bytes_per_b"] for s in info["buckets"])
+        # loads the kernel issues (cache-served re-reads of broadcast inputs, padding rows included)
+        lv_in, lv_k = {}, {}
+        for s in info["buckets"]:
+            lv_in[s["level"]] = max(lv_in.get(s["level"], 0), s["n_in"])
+            lv_k[s["level"]] = max(lv_k.get(s["level"], 1), s["kg"])
+        issued = sum(8 * max(2 ** s["r_out"], 8) * (2 ** lv_k[s["level"]] * (lv_in[s["level"]] + 1) + 1)
+                     for s in info["buckets"]) * B_eff
+        cfg = {"buckets": info["n_buckets"], "tree_levels": n_launch, "bytes_per_amp": info["bytes_per_amp"]}
+        extra = {"issued_load_store_bytes_per_launch": issued / n_launch}
+        src = "tree.hip"
+    else:
+        kernel = "k_step (worldline elimination step)"
+        n_launch = info["n_steps"]
+        alg_bytes = B_eff * sum(s["bytes_per_b"] for s in info["steps"])
+        cfg = {"sliced_vars": info["n_sliced"], "kernel_policy": args.kernel_policy,
+               "autotuned": not args.no_autotune,
+               "step_kernels": {k: (kernels or [st["kernel"] for st in info["steps"]]).count(k)
+                                for k in ("valu", "valu_pair", "mfma_f32", "mfma_bf16x3")}}
+        extra = {}
+        src = "kernels.hip"
+    achieved = alg_bytes / (elim_ms / 1e3) / 1e9
+    traffic, tb = None, None
+    rec = MEASURED_TRAFFIC.get((args.workload, info["ordering"]))
+    if rec and args.kernel_policy == 0 and (info["ordering"] == 1 or args.no_autotune):
+        import hashlib
+        path = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", rec["source"])
+        if rec["source"] == src and hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == rec["sha256_16"]:
+            tb = rec["bytes_per_launch"]
+            traffic = round(tb / (elim_ms / n_launch / 1e3) / 1e9, 1)   # GB/s of HBM traffic
+    roofline = dict({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_bytes_per_launch": tb, "kernel": kernel, "bytes_per_launch": alg_bytes / n_launch,
+                     "launch_ms": elim_ms / n_launch, "launches_per_step": n_launch}, **extra)
+    return roofline, cfg
+
+
 def _time(fn, reps, stream, torch):
     for _ in range(2):
         fn()
@@ -200,11 +235,45 @@ def _time(fn, reps, stream, torch):
     return e0.elapsed_time(e1) / reps
 
 
+def _amps_per_sec(Q, C, torch, np, stream, name, reps=5, **plan_kw):
+    """Eager amplitudes/s of one workload with inputs resident; returns (value, plan, ms)."""
+    dev = torch.device("cuda", 0)
+    c, bits = C.workload(name)
+    p = Q.plan(c, **plan_kw)
+    gv = None if c.gate_vals is None else torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
+    bd = torch.from_numpy(bits.view(np.int64)).to(dev)
+    o = torch.empty((len(bits), 1), dtype=torch.complex128 if plan_kw.get("out_c128") else torch.complex64,
+                    device=dev)
+    w = torch.empty(max(p.workspace_bytes(len(bits)), 256), dtype=torch.uint8, device=dev)
+    if plan_kw.get("ordering", 0) == 0:
+        p.autotune(bd, gv, stream=stream)
+    ms = _time(lambda: p.amplitudes(bd, gv, out=o, workspace=w, stream=stream), reps, stream, torch)
+    return len(bits) / (ms / 1e3), p, ms
+
+
 def extras(Q, C, torch, np, stream, args):
     """Secondary workloads, timed the same way (inputs resident, HIP events)."""
     out = {}
     dev = torch.device("cuda", 0)
-    # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2
+    # the other elimination order on the default workload
+    other = 1 - args.ordering
+    v, p, ms = _amps_per_sec(Q, C, torch, np, stream, args.workload, 10, ordering=other)
+    info = p.info(0)
+    p.set_timing(True)
+    c, bits = C.workload(args.workload)
+    bd = torch.from_numpy(bits.view(np.int64)).to(dev)
+    for _ in range(5):
+        p.amplitudes(bd, None, stream=stream)
+    torch.cuda.synchronize()
+    ph, nc = p.timings()
+    p.set_timing(False)
+    rf, _ = dominant_kernel(argparse.Namespace(workload=args.workload, kernel_policy=0, no_autotune=False), p, info,
+                            len(bits), ph[2] / max(nc, 1), None)
+    out["ordering_%d" % other] = {"workload": args.workload, "amplitudes_per_sec": round(v, 1),
+                                  "ms_per_call": round(ms, 4), "bytes_per_amp": info["bytes_per_amp"],
+                                  "max_rank": info["max_rank"], "roofline": rf}
+    print(f"# ordering {other}: {ms:.3f} ms per call, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
+    # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2 (vertical order)
     c, bits = C.workload("c4_5x5_d20_U")
     p = Q.plan(c)
     gv = torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
@@ -220,9 +289,9 @@ def extras(Q, C, torch, np, stream, args):
     print(f"# c4 gradient: {ms:.3f} ms per evaluation (forward alone {msf:.3f} ms)", file=sys.stderr, flush=True)
     del ws
     # plain per-bitstring baseline: the default workload's plan called with B = 1
-    # in a host loop (no graph, no autotuning; B is padded to one 64-wide wave)
+    # in a host loop (no graph; B is padded to one 64-wide wave)
     c, bits = C.workload(args.workload)
-    p = Q.plan(c)
+    p = Q.plan(c, ordering=args.ordering)
     one = [torch.from_numpy(bits[i:i + 1].view(np.int64)).to(dev) for i in range(64)]
     o1 = torch.empty((1, 1), dtype=torch.complex64, device=dev)
     w1 = torch.empty(p.workspace_bytes(1), dtype=torch.uint8, device=dev)
@@ -230,29 +299,32 @@ def extras(Q, C, torch, np, stream, args):
     out["per_bitstring_baseline"] = {"workload": f"{c.name}, same plan, B = 1 per call, 64 calls",
                                      "amplitudes_per_sec": round(64 / (ms / 1e3), 1), "ms_per_amplitude": round(ms / 64, 4)}
     print(f"# per-bitstring baseline: {ms / 64:.3f} ms per amplitude", file=sys.stderr, flush=True)
-    # 5x6 depth 30, 2 sliced variables, FP64 slice sum
-    c, bits = C.workload("c3_5x6_d30")
-    p = Q.plan(c, min_sliced_vars=2, out_c128=True)
-    bd = torch.from_numpy(bits.view(np.int64)).to(dev)
-    g = Q.Graph([p], [bd])
-    ms = _time(lambda: g.launch(stream), 5, stream, torch)
-    out["c3_sliced"] = {"workload": "5x6 depth 30, 1024 bitstrings, 2 sliced variables, FP64 slice sum",
-                        "amplitudes_per_sec": round(len(bits) / (ms / 1e3), 1), "ms_per_call": round(ms, 4),
-                        "bytes_per_amp": p.info(0)["bytes_per_amp"]}
-    print(f"# c3 sliced: {ms:.3f} ms per 1024 amplitudes", file=sys.stderr, flush=True)
-    del g
+    # 5x6 depth 30: bucket path (no slicing needed) and vertical path with 2 sliced variables, FP64 slice sum
+    v1, p1, ms1 = _amps_per_sec(Q, C, torch, np, stream, "c3_5x6_d30", 5, ordering=1, out_c128=True)
+    v0, p0, ms0 = _amps_per_sec(Q, C, torch, np, stream, "c3_5x6_d30", 3, ordering=0, min_sliced_vars=2,
+                                out_c128=True)
+    out["c3"] = {"workload": "5x6 depth 30, 1024 bitstrings, complex128 output",
+                 "ordering_1": {"amplitudes_per_sec": round(v1, 1), "ms_per_call": round(ms1, 4),
+                                "bytes_per_amp": p1.info(0)["bytes_per_amp"]},
+                 "ordering_0_sliced_2": {"amplitudes_per_sec": round(v0, 1), "ms_per_call": round(ms0, 4),
+                                         "bytes_per_amp": p0.info(0)["bytes_per_amp"]}}
+    print(f"# c3: bucket {ms1:.3f} ms, vertical sliced {ms0:.3f} ms per 1024 amplitudes", file=sys.stderr,
+          flush=True)
     # uneven batch: 4x5 d20, 5x5 d24, 6x6 d24, 6x7 d27, 1024 bitstrings each, one graph
     names = ("c5_4x5_d20", "c5_5x5_d24", "c5_6x6_d24", "c5_6x7_d27")
     cs, bs = zip(*[C.workload(nm) for nm in names])
-    plans = [Q.plan(ci) for ci in cs]
-    g = Q.Graph(plans, list(bs))
-    ms = _time(lambda: g.launch(stream), 3, stream, torch)
     total = sum(len(b) for b in bs)
     out["c5_graph"] = {"workload": "4x5 d20 + 5x5 d24 + 6x6 d24 + 6x7 d27, 1024 bitstrings each, one HIP graph "
-                                   "with one branch per circuit", "amplitudes_per_sec": round(total / (ms / 1e3), 1),
-                       "ms_per_launch": round(ms, 4)}
-    print(f"# c5 graph: {ms:.3f} ms per launch ({total} amplitudes)", file=sys.stderr, flush=True)
-    del g
+                                   "with one branch per circuit"}
+    for ordering in (1, 0):
+        plans = [Q.plan(ci, ordering=ordering) for ci in cs]
+        g = Q.Graph(plans, list(bs))
+        ms = _time(lambda: g.launch(stream), 3, stream, torch)
+        out["c5_graph"]["ordering_%d" % ordering] = {"amplitudes_per_sec": round(total / (ms / 1e3), 1),
+                                                     "ms_per_launch": round(ms, 4)}
+        print(f"# c5 graph ordering {ordering}: {ms:.3f} ms per launch ({total} amplitudes)", file=sys.stderr,
+              flush=True)
+        del g
     return out
 
 

@@ -75,7 +75,10 @@ typedef struct {
 } qgm_circuit;
 
 typedef struct {
-    int32_t ordering;          /* 0 = vertical order of Sec. IV.A (qubits along the shorter side first) */
+    int32_t ordering;          /* 0 = vertical order of Sec. IV.A (qubits along the shorter side first);
+                                  1 = bucket elimination (App. A) along a greedy treewidth order (min-degree /
+                                      min-fill with randomised tie breaks, the cheapest of several; Sec. IV.B),
+                                      forward amplitudes only: no open qubits, no slicing, no qgm_backward */
     int32_t precision;         /* 0 = complex64 with FP32 arithmetic */
     int32_t kernel_policy;     /* 0 = auto (the vector-ALU kernel, one row per thread); 1 = the same;
                                   2 = FP32 matrix-core kernel for every step it supports (K and N of
@@ -88,7 +91,9 @@ typedef struct {
     int32_t out_c128;          /* 1: amplitudes are written as complex128, 0: complex64 */
     int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor has rank <= max_rank */
     int32_t checkpoint_every;  /* qgm_backward keeps every c-th frontier (0 = ceil(sqrt(steps))) */
-    int32_t reserved;
+    int32_t no_chain_merge;    /* ordering 1 only: 1 = one variable per bucket step; 0 = a bucket whose only
+                                  input is an earlier bucket's result absorbs that bucket when the merged
+                                  index space grows by at most one bit (up to 3 summed variables) */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;

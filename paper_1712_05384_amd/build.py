@@ -7,6 +7,7 @@ paper_1712_05384_amd/libqgm.so.  hipcc cross-compiles, so no GPU is needed.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import shutil
@@ -40,16 +41,24 @@ def build(verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-result"]
     device = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-munsafe-fp-atomics"]
+    cmds = []
     for src in sources():
         obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
         if src.endswith(".hip"):
-            cmd = [hipcc(), "-x", "hip", *device, *common, "-c", src, "-o", obj]
+            cmds.append([hipcc(), "-x", "hip", *device, *common, "-c", src, "-o", obj])
         else:
-            cmd = [hipcc(), *common, "-c", src, "-o", obj]
+            cmds.append([hipcc(), *common, "-c", src, "-o", obj])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1), 8))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for f in [pool.submit(run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

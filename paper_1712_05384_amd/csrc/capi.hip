@@ -35,7 +35,7 @@ struct qgm_plan_s {
     int64_t total_waves = 0;
     int max_ops = 1;
     // tree plans (ordering 1): offsets of the bucket records, factor tables, phase and final rows
-    size_t off_tsteps = 0, off_tgtab = 0, off_tfac = 0, off_tphase = 0, off_tfinal = 0;
+    size_t off_tsteps = 0, off_ttasks = 0, off_tgtab = 0, off_tfac = 0, off_tsig = 0, off_tphase = 0, off_tfinal = 0;
     int n_gtabs = 0;
     uint32_t max_tree_g = 0;
     // optional per-phase timing
@@ -82,77 +82,108 @@ void layout_tree_tables(qgm_plan_t* P) {
     size_t n_fac = 0;
     P->n_gtabs = 0;
     P->max_tree_g = 0;
-    for (auto& st : t.steps)
-        if (!st.factors.empty()) {
-            n_fac += st.factors.size();
-            P->n_gtabs++;
-            P->max_tree_g = std::max<uint32_t>(P->max_tree_g, uint32_t(st.g_entries()));
-        }
+    P->n_gtabs = int(t.steps.size());
+    P->max_tree_g = 1;
+    for (auto& st : t.steps) {
+        n_fac += st.factors.size();
+        P->max_tree_g = std::max<uint32_t>(P->max_tree_g, uint32_t(st.g_entries()));
+    }
     P->off_fixed = 0;
     P->off_tsteps = al(sizeof(double2) * qgm::kFixedMats * 4);
-    P->off_tgtab = P->off_tsteps + al(sizeof(qgm::TreeStepDev) * (t.steps.size() + 1));
+    P->off_ttasks = P->off_tsteps + al(sizeof(qgm::TreeStepDev) * (t.steps.size() + 1));
+    P->off_tgtab = P->off_ttasks + al(sizeof(qgm::TreeTask) * size_t(t.n_tasks + 1));
     P->off_tfac = P->off_tgtab + al(sizeof(qgm::TreeGTab) * (size_t(P->n_gtabs) + 1));
-    P->off_tphase = P->off_tfac + al(sizeof(qgm::TFactor) * (n_fac + 1));
+    P->off_tsig = P->off_tfac + al(sizeof(qgm::TFactor) * (n_fac + 1));
+    P->off_tphase = P->off_tsig + al(sizeof(qgm::TreeSigTab) * (size_t(t.n_sig_rows) + 1));
     P->off_tfinal = P->off_tphase + al(sizeof(qgm::TFactor) * (t.phase.size() + 1));
     P->total = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
 }
 
-// Device record of bucket st (index arithmetic of Sec. IV's bucket product).
-qgm::TreeStepDev tree_step_dev(const qgm::TreePlan& t, const qgm::TreeStep& st) {
-    qgm::TreeStepDev d{};
-    const int r = int(st.out_axes.size());
-    d.r_out = r;
-    d.n_in = int32_t(st.in_tensors.size());
-    d.sb = st.sb();
-    d.oc_bits = std::min(r, qgm::kTreeOcBits);
-    d.has_g = st.factors.empty() ? 0 : 1;
-    d.n_chunks = int64_t(1) << (r - d.oc_bits);
-    d.g_off = st.g_off;
-    d.out_row = t.tensor_row[st.out_tensor];
-    for (int i = 0; i < d.n_in; ++i) {
-        const int tid = st.in_tensors[i];
-        d.in_row[i] = t.tensor_row[tid];
-        const std::vector<int>& ax = t.tensor_axes[tid];
-        for (int a = 0; a < int(ax.size()); ++a) {
-            if (ax[a] == st.var) { d.in_v[i] = 1 << a; continue; }
-            for (int j = 0; j < r; ++j)
-                if (st.out_axes[j] == ax[a]) d.in_str[i][j] = 1 << a;
-        }
-        int low = 0;
-        for (int j = 0; j < qgm::kTreeOcBits; ++j) {
-            d.in_inc[i][j] = d.in_str[i][j] - low;
-            low += d.in_str[i][j];
-        }
-    }
-    for (int j = 0; j < r; ++j)
-        for (int g = 0; g < st.gb(); ++g)
-            if (st.out_axes[j] == st.gvars[g]) d.g_str[j] = 1 << g;
-    int low = 0;
-    for (int j = 0; j < qgm::kTreeOcBits; ++j) {
-        d.g_inc[j] = d.g_str[j] - low;
-        low += d.g_str[j];
-    }
-    for (int i = 0; i < st.sb(); ++i) d.sig_q[i] = st.sig_q[i];
-    return d;
-}
-
+// Device records of a bucket: the row stride of every result bit in every
+// input (the index arithmetic of the bucket product), split into the
+// per-bucket record and one task record per chunk of 2^oc_bits result rows.
 void fill_tree_tables(const qgm_plan_t* P, char* h) {
     const qgm::TreePlan& t = P->p.tree;
     auto* sd = reinterpret_cast<qgm::TreeStepDev*>(h + P->off_tsteps);
+    auto* tasks = reinterpret_cast<qgm::TreeTask*>(h + P->off_ttasks);
     auto* gt = reinterpret_cast<qgm::TreeGTab*>(h + P->off_tgtab);
     auto* fac = reinterpret_cast<qgm::TFactor*>(h + P->off_tfac);
-    int n_g = 0, n_fac = 0;
+    auto* sg = reinterpret_cast<qgm::TreeSigTab*>(h + P->off_tsig);
+    int n_fac = 0;
+    const int zero_sig = t.n_sig_rows - 1;
+    sg[zero_sig] = qgm::TreeSigTab{};
     for (size_t i = 0; i < t.steps.size(); ++i) {
         const qgm::TreeStep& st = t.steps[i];
-        sd[i] = tree_step_dev(t, st);
-        if (st.factors.empty()) continue;
+        const int r = int(st.out_axes.size());
+        const int n_in = int(st.in_tensors.size());
+        qgm::TreeStepDev d{};
+        d.n_in = n_in;
+        d.sb = st.sb();
+        d.sig_row = st.sig_row >= 0 ? st.sig_row : zero_sig;
+        d.gshift = st.kg + st.sb();
+        std::vector<std::vector<int64_t>> str(n_in, std::vector<int64_t>(r, 0));
+        std::vector<int64_t> gstr(r, 0);
+        for (int k = 0; k < n_in; ++k) {
+            const std::vector<int>& ax = t.tensor_axes[st.in_tensors[k]];
+            for (int a = 0; a < int(ax.size()); ++a) {
+                for (size_t i = 0; i < st.vars.size(); ++i)
+                    if (ax[a] == st.vars[i]) d.in_vs[k][i] = 1 << a;
+                for (int j = 0; j < r; ++j)
+                    if (st.out_axes[j] == ax[a]) str[k][j] = int64_t(1) << a;
+            }
+            int64_t low = 0;
+            for (int j = 0; j < qgm::kTreeOcBits; ++j) {
+                const int64_t sj = j < r ? str[k][j] : 0;
+                d.in_inc[k][j] = int32_t(sj - low);
+                low += sj;
+            }
+        }
+        for (int j = 0; j < r; ++j)
+            for (int g = 0; g < st.gb(); ++g)
+                if (st.out_axes[j] == st.gvars[g]) gstr[j] = int64_t(1) << g;
+        int64_t low = 0;
+        for (int j = 0; j < qgm::kTreeOcBits; ++j) {
+            const int64_t sj = j < r ? gstr[j] : 0;
+            d.g_inc[j] = int32_t(sj - low);
+            low += sj;
+        }
+        sd[i] = d;
+        // tasks: chunk c covers result rows [c << ocb, (c << ocb) + n_oc)
+        const int ocb = st.oc_bits();
+        const int64_t n_ch = st.n_tasks();
+        for (int64_t c = 0; c < n_ch; ++c) {
+            const int64_t o0 = c << ocb;
+            qgm::TreeTask tk{};
+            tk.step = int32_t(i);
+            tk.out_row = int32_t(t.tensor_row[st.out_tensor] + o0);
+            int64_t g0 = 0;
+            for (int j = 0; j < r; ++j)
+                if ((o0 >> j) & 1) g0 += gstr[j];
+            tk.g_ent = int32_t(st.g_off + (g0 << d.gshift));
+            for (int k = 0; k < qgm::kTreeMaxIn; ++k) {
+                if (k >= n_in) { tk.in_row[k] = int32_t(t.ones_row); continue; }
+                int64_t row = t.tensor_row[st.in_tensors[k]];
+                for (int j = 0; j < r; ++j)
+                    if ((o0 >> j) & 1) row += str[k][j];
+                tk.in_row[k] = int32_t(row);
+            }
+            tasks[st.task_off + c] = tk;
+        }
+        if (st.sig_row >= 0) {
+            qgm::TreeSigTab q{};
+            q.sb = st.sb();
+            for (int b = 0; b < st.sb(); ++b) q.q[b] = st.sig_q[b];
+            sg[st.sig_row] = q;
+        }
         qgm::TreeGTab g{};
         g.gb = st.gb();
         g.sb = st.sb();
+        g.k = int32_t(st.vars.size());
+        g.kg = st.kg;
         g.fac_off = n_fac;
         g.n_fac = int32_t(st.factors.size());
         g.g_off = st.g_off;
-        gt[n_g++] = g;
+        gt[i] = g;
         for (auto& f : st.factors) fac[n_fac++] = f;
     }
     auto* ph = reinterpret_cast<qgm::TFactor*>(h + P->off_tphase);
@@ -446,33 +477,26 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     auto mark = [&](int i) { if (plan->timing) (void)hipEventRecord(ev[i], s); };
     mark(0);
     if (p.is_tree) {
-        // bucket elimination: factor tables, one launch per tree level, FP64 product
+        // bucket elimination: prologue (factor tables, sigma rows), one launch per tree level, FP64 product
         const qgm::TreePlan& t = p.tree;
         float2* arena = reinterpret_cast<float2*>(ws + w.f0);
         float2* gt = reinterpret_cast<float2*>(ws + w.g);
+        auto* sigs = reinterpret_cast<uint16_t*>(ws + w.var_ids);
         const auto* fixed = reinterpret_cast<const double2*>(tables + plan->off_fixed);
         const auto* slots = static_cast<const float2*>(gate_vals);
         const auto* sd = reinterpret_cast<const qgm::TreeStepDev*>(tables + plan->off_tsteps);
+        const auto* tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks);
         mark(1);
-        qgm::launch_tree_g(reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab), plan->n_gtabs,
-                           plan->max_tree_g, reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tfac), fixed,
-                           slots, gt, s);
+        qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab), plan->n_gtabs,
+                                  plan->max_tree_g, reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tfac),
+                                  fixed, slots, gt, reinterpret_cast<const qgm::TreeSigTab*>(tables + plan->off_tsig),
+                                  t.n_sig_rows, bits, B, uint32_t(B_eff), sigs,
+                                  arena + t.ones_row * B_eff, s);
         mark(2);
-        const int64_t n_bg = B_eff / 64;
-        for (const auto& lvl : t.levels) {
-            qgm::TreeLevel L{};
-            for (int sid : lvl) {
-                const int r = int(t.steps[sid].out_axes.size());
-                const int64_t units = (int64_t(1) << (r - std::min(r, qgm::kTreeOcBits))) * n_bg;
-                if (L.n == qgm::kTreeLevelSlots || int64_t(L.unit_start[L.n]) + units >= (int64_t(1) << 31)) {
-                    qgm::launch_tree_level(L, sd, arena, gt, bits, B, uint32_t(B_eff), s);
-                    L = qgm::TreeLevel{};
-                }
-                L.step[L.n] = sid;
-                L.unit_start[L.n + 1] = int32_t(L.unit_start[L.n] + units);
-                L.n++;
-            }
-            if (L.n > 0) qgm::launch_tree_level(L, sd, arena, gt, bits, B, uint32_t(B_eff), s);
+        for (size_t L = 0; L < t.levels.size(); ++L) {
+            const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
+            qgm::launch_tree_level(t.level_max_in[L], t.level_k[L], tasks + t0, int32_t(t1 - t0), sd, arena, arena,
+                                   gt, sigs, uint32_t(B_eff), s);
         }
         mark(3);
         if (out)

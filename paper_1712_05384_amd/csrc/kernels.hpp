@@ -36,33 +36,41 @@ struct GbarParams {
 };
 
 // Device record of one bucket of a tree plan (read with scalar loads: every
-// field is 32- or 64-bit at its natural alignment).
+// field is 32-bit).
 struct TreeStepDev {
-    int32_t r_out, n_in, sb, oc_bits;     // result rank, inputs, output bits, log2(o per wave unit)
-    int32_t has_g, pad0;
-    int64_t n_chunks;                     // 2^(r_out - oc_bits)
-    int64_t g_off;                        // factor table: entry (((g << 1) | v) << sb) | sigma
-    int64_t out_row;                      // arena row of the result
-    int64_t in_row[kTreeMaxIn];           // arena row of each input
-    int32_t in_v[kTreeMaxIn];             // row stride of v in input t (0: v is not an axis of t)
-    int32_t in_str[kTreeMaxIn][kTreeMaxRank];   // row stride of result bit j in input t
+    int32_t n_in, sb, sig_row, gshift;          // inputs, output bits, row of the sigma table, kg + sb
+    int32_t in_vs[kTreeMaxIn][kTreeMaxSum];     // row stride of summed variable i in input t (0: not an axis
+                                                //   of t, or t is a constant-1 pad beyond the bucket's inputs)
     int32_t in_inc[kTreeMaxIn][kTreeOcBits];    // row change of input t when o -> o + 1 with ctz(o + 1) = j
-    int32_t g_str[kTreeMaxRank];                // factor-table g stride of result bit j
-    int32_t g_inc[kTreeOcBits];
-    int32_t sig_q[kTreeMaxSig];                 // sigma bit i = bit sig_q[i] of the bitstring
+    int32_t g_inc[kTreeOcBits];                 // factor-table g change for the same steps
+    int32_t pad;
 };
 
-// Factor-table record of one bucket (G builder).
+// One wave task: a chunk of 2^kTreeOcBits consecutive result rows of a
+// bucket (times the 64-bitstring groups of the batch).  A result of rank
+// below kTreeOcBits has one chunk whose rows wrap around its index space; the
+// arena reserves 2^kTreeOcBits rows for it, so all rows of the chunk are
+// stored and only the first 2^rank are read.
+struct TreeTask {
+    int32_t step;                               // bucket
+    int32_t pad;
+    int32_t out_row;                            // arena row of the chunk's first result row
+    int32_t g_ent;                              // factor-table entry of (g(o0), w = 0, sigma = 0)
+    int32_t in_row[kTreeMaxIn];                 // arena row of input t at (o0, v = 0)
+};
+
+// Factor-table record of one bucket (prologue kernel).
 struct TreeGTab {
-    int32_t gb, sb, fac_off, n_fac;
+    int32_t gb, sb, k, kg;                      // entry e = (((g << kg) | w) << sb) | sigma; w >= 2^k gives 0
+    int32_t fac_off, n_fac;
     int64_t g_off;
 };
 
-// Buckets of one level launch; bucket k owns wave units [unit_start[k], unit_start[k + 1]).
-struct TreeLevel {
-    int32_t n;
-    int32_t step[kTreeLevelSlots];
-    int32_t unit_start[kTreeLevelSlots + 1];
+// Sigma-table record of one bucket: sigma bit i = bit q[i] of the bitstring.
+struct TreeSigTab {
+    int32_t sb;
+    int32_t q[kTreeMaxSig];
+    int32_t pad[3];
 };
 
 constexpr uint32_t kStepMaxGrid = 8192;           // work-groups of the step kernel (grid-stride beyond)
@@ -92,10 +100,13 @@ void launch_seed(const float2* g, uint32_t B_eff, uint32_t B_pad, int64_t B, int
 void launch_finalize(const float2* f, uint32_t B_eff, uint32_t B_pad, int64_t B, int n_slices, int n_open,
                      const int32_t* final_pos, void* out, bool c128, hipStream_t stream);
 
-void launch_tree_g(const TreeGTab* tabs, int n_tabs, uint32_t max_entries, const TFactor* facs, const double2* fixed,
-                   const float2* slots, float2* gtab, hipStream_t stream);
-void launch_tree_level(const TreeLevel& lv, const TreeStepDev* steps, float2* arena, const float2* gtab,
-                       const uint64_t* bits, int64_t B, uint32_t B_eff, hipStream_t stream);
+void launch_tree_prologue(const TreeGTab* gtabs, int n_gtabs, uint32_t max_entries, const TFactor* facs,
+                          const double2* fixed, const float2* slots, float2* gtab, const TreeSigTab* sigtabs,
+                          int n_sig, const uint64_t* bits, int64_t B, uint32_t B_eff, uint16_t* sigs, float2* ones,
+                          hipStream_t stream);
+void launch_tree_level(int nin, int k, const TreeTask* tasks, int32_t n_tasks, const TreeStepDev* steps,
+                       const float2* ain, float2* aout, const float2* gtab, const uint16_t* sigs, uint32_t B_eff,
+                       hipStream_t stream);
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                        const float2* slots, const float2* arena, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        void* out, bool c128, hipStream_t stream);

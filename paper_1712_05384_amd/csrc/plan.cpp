@@ -451,7 +451,8 @@ WsLayout workspace_layout(const Plan& p, int64_t B) {
     if (p.is_tree) {
         w.f0 = w.f1 = w.var_ids = 0;
         w.g = al(uint64_t(p.tree.arena_rows) * be * 8);
-        w.total = w.g + al(uint64_t(p.tree.g_total) * 8);
+        w.var_ids = w.g + al(uint64_t(p.tree.g_total) * 8);
+        w.total = w.var_ids + al(uint64_t(p.tree.n_sig_rows) * be * 2);
         return w;
     }
     const uint64_t fbytes = al((uint64_t(1) << p.r_max) * be * 8);
@@ -487,6 +488,7 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"n_vars\":" << p.vars.size() << ",\"n_free\":" << t.n_free << ",\"n_open\":0,\"n_slots\":" << p.n_slots
       << ",\"n_steps\":0,\"n_buckets\":" << t.steps.size() << ",\"n_levels\":" << t.levels.size()
       << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
+      << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
@@ -496,8 +498,9 @@ static std::string tree_json(const Plan& p, int detail) {
     o << ",\"steps\":[],\"buckets\":[";
     for (size_t i = 0; i < t.steps.size(); ++i) {
         const TreeStep& st = t.steps[i];
-        o << (i ? "," : "") << "{\"var\":" << st.var << ",\"qubit\":" << p.vars[st.var].qubit
-          << ",\"k\":" << p.vars[st.var].k << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
+        o << (i ? "," : "") << "{\"vars\":";
+        json_ints(o, st.vars);
+        o << ",\"kg\":" << st.kg << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.factors.size() << ",\"g_off\":" << st.g_off
           << ",\"bytes_per_b\":" << tree_step_bytes(t, st);
@@ -520,7 +523,7 @@ static std::string tree_json(const Plan& p, int detail) {
             o << (i ? "," : "") << "{\"axes\":";
             json_ints(o, t.tensor_axes[i]);
             o << ",\"made\":" << t.tensor_made[i] << ",\"used\":" << t.tensor_used[i] << ",\"row\":" << t.tensor_row[i]
-              << "}";
+              << ",\"alloc_rows\":" << (int64_t(1) << std::max(int(t.tensor_axes[i].size()), kTreeOcBits)) << "}";
         }
         o << "],\"phase\":[";
         for (size_t j = 0; j < t.phase.size(); ++j) { if (j) o << ","; json_factor(o, t.phase[j]); }

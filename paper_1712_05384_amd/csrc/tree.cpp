@@ -131,9 +131,49 @@ struct SimOut {
     std::string why;
 };
 
-// Runs bucket elimination over the structure for an order (free indices);
-// with `t` set, also records the steps.
-SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, TreePlan* t) {
+// A bucket step in free-variable indices, before merging and encoding.
+struct RStep {
+    std::vector<int> vars;   // summed variables (the bucket's variable first)
+    std::vector<int> out;    // result axes, elimination position ascending
+    std::vector<int> ins;    // input results
+    std::vector<int> facs;   // gate factors (indices into Model::facs)
+    int out_tensor = -1;
+    bool alive = true;
+};
+
+struct RTensor {
+    std::vector<int> axes;
+    int producer = -1;
+};
+
+// Factor-table variables (besides the summed ones) and output bits of a set of factors.
+void table_vars(const Plan& p, const Model& m, const std::vector<int>& facs, const std::vector<int>& summed,
+                std::set<int>& gset, std::vector<int>& sigq) {
+    gset.clear();
+    sigq.clear();
+    for (int f : facs) {
+        const RawFactor& rf = m.facs[f];
+        for (int u : rf.free)
+            if (std::find(summed.begin(), summed.end(), u) == summed.end()) gset.insert(u);
+        for (int k = 0; k < rf.nv; ++k)
+            if (m.kind[rf.v[k]] == VK_SIG) {
+                const int q = p.vars[rf.v[k]].qubit;
+                if (std::find(sigq.begin(), sigq.end(), q) == sigq.end()) sigq.push_back(q);
+            }
+    }
+}
+
+bool fits(int rank, int n_in, int gb, int k, int sb) {
+    return rank <= kTreeMaxRank && n_in <= kTreeMaxIn && gb <= kTreeMaxGBits && sb <= kTreeMaxSig &&
+           k <= kTreeMaxSum && gb + k + sb <= kTreeMaxGIndex;
+}
+
+// Runs bucket elimination over the structure for an order (free indices):
+// bucket i multiplies the results and factors whose earliest variable is
+// order[i] and sums that variable out.  With `steps`/`tens` set, also
+// records the steps.
+SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, std::vector<RStep>* steps,
+                std::vector<RTensor>* tens) {
     SimOut r;
     const int nF = int(order.size());
     std::vector<int> pos(nF);
@@ -144,9 +184,10 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, Tr
         for (int u : m.facs[f].free) e = std::min(e, pos[u]);
         bfac[e].push_back(f);
     }
-    std::vector<std::vector<int>> taxes;   // result axes (free indices, position ascending)
+    std::vector<std::vector<int>> taxes;
     std::vector<int> tmade;
-    std::vector<int> finals;
+    std::set<int> gset;
+    std::vector<int> sigq;
     for (int i = 0; i < nF; ++i) {
         const int v = order[i];
         std::set<int> A;
@@ -155,35 +196,25 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, Tr
             for (int u : taxes[tid]) A.insert(u);
             level = std::max(level, tmade[tid] + 1);
         }
-        std::set<int> gset;
-        std::vector<int> sigq;
-        for (int f : bfac[i]) {
-            const RawFactor& rf = m.facs[f];
-            for (int u : rf.free) { A.insert(u); if (u != v) gset.insert(u); }
-            for (int k = 0; k < rf.nv; ++k)
-                if (m.kind[rf.v[k]] == VK_SIG) {
-                    const int q = p.vars[rf.v[k]].qubit;
-                    if (std::find(sigq.begin(), sigq.end(), q) == sigq.end()) sigq.push_back(q);
-                }
-        }
+        for (int f : bfac[i])
+            for (int u : m.facs[f].free) A.insert(u);
         if (!A.count(v)) { r.why = "internal: variable missing from its bucket"; return r; }
+        table_vars(p, m, bfac[i], {v}, gset, sigq);
         std::vector<int> out;
         for (int u : A) if (u != v) out.push_back(u);
         std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
         const int n_in = int(bten[i].size());
-        if (int(out.size()) > kTreeMaxRank || n_in > kTreeMaxIn || int(gset.size()) > kTreeMaxGBits ||
-            int(sigq.size()) > kTreeMaxSig || int(gset.size()) + 1 + int(sigq.size()) > kTreeMaxGIndex) {
+        if (!fits(int(out.size()), n_in, int(gset.size()), 1, int(sigq.size()))) {
             char buf[200];
             snprintf(buf, sizeof buf, "bucket exceeds kernel limits (rank %d, inputs %d, table bits %d, output bits %d)",
                      int(out.size()), n_in, int(gset.size()), int(sigq.size()));
             r.why = buf;
             return r;
         }
-        const bool has_g = !bfac[i].empty();
         const double rows = double(int64_t(1) << out.size());
         double bytes = 8.0 * rows;
         for (int tid : bten[i]) bytes += 8.0 * double(int64_t(1) << taxes[tid].size());
-        const int mult = n_in + (has_g ? 1 : 0);
+        const int mult = n_in + (bfac[i].empty() ? 0 : 1);
         r.bytes += bytes;
         r.flops += 2.0 * rows * (6.0 * std::max(mult - 1, 0) + 2.0);
         r.levels = std::max(r.levels, level + 1);
@@ -192,58 +223,163 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, Tr
         const int tid = int(taxes.size());
         taxes.push_back(out);
         tmade.push_back(level);
-        if (out.empty()) finals.push_back(tid);
-        else bten[pos[out[0]]].push_back(tid);
-        if (t) {
-            TreeStep st;
-            st.var = m.free_var[v];
-            st.level = level;
+        if (!out.empty()) bten[pos[out[0]]].push_back(tid);
+        if (steps) {
+            RStep st;
+            st.vars = {v};
+            st.out = out;
+            st.ins = bten[i];
+            st.facs = bfac[i];
             st.out_tensor = tid;
-            for (int u : out) st.out_axes.push_back(m.free_var[u]);
-            st.in_tensors = bten[i];
-            std::vector<int> g(gset.begin(), gset.end());
-            std::sort(g.begin(), g.end(), [&](int a, int b) { return pos[a] < pos[b]; });
-            for (int u : g) st.gvars.push_back(m.free_var[u]);
-            st.sig_q = sigq;
-            for (int f : bfac[i]) {
-                const RawFactor& rf = m.facs[f];
-                TFactor tf{};
-                tf.type = rf.type;
-                tf.mat = rf.mat;
-                int* srcs[2][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}};
-                for (int k = 0; k < rf.nv; ++k) {
-                    const int var = rf.v[k];
-                    if (m.kind[var] == VK_FREE) {
-                        const int u = m.fi[var];
-                        *srcs[k][0] = TS_G;
-                        *srcs[k][1] = u == v ? 0 : 1 + int(std::find(g.begin(), g.end(), u) - g.begin());
-                    } else if (m.kind[var] == VK_SIG) {
-                        *srcs[k][0] = TS_SIG;
-                        *srcs[k][1] = int(std::find(sigq.begin(), sigq.end(), p.vars[var].qubit) - sigq.begin());
-                    } else {
-                        *srcs[k][0] = TS_ZERO;
-                        *srcs[k][1] = 0;
-                    }
-                }
-                st.factors.push_back(tf);
-            }
-            t->steps.push_back(std::move(st));
+            RTensor rt;
+            rt.axes = out;
+            rt.producer = int(steps->size());
+            tens->push_back(rt);
+            steps->push_back(st);
         }
-    }
-    if (t) {
-        t->tensor_axes.clear();
-        for (auto& a : taxes) {
-            std::vector<int> ax;
-            for (int u : a) ax.push_back(m.free_var[u]);
-            t->tensor_axes.push_back(ax);
-        }
-        t->tensor_made = tmade;
-        t->finals = finals;
     }
     r.ok = true;
     return r;
 }
 
+// Merges chain links: a bucket whose only input is the result of one earlier
+// bucket absorbs that bucket (both summed variables at once) when the merged
+// index space grows by at most one bit, so the intermediate result is never
+// written and the elimination tree loses a level.
+void merge_chains(const Plan& p, const Model& m, std::vector<RStep>& steps, std::vector<RTensor>& tens) {
+    std::set<int> gset;
+    std::vector<int> sigq;
+    for (size_t i = 0; i < steps.size(); ++i) {
+        RStep& par = steps[i];
+        if (par.ins.size() != 1) continue;
+        const int tid = par.ins[0];
+        RStep& ch = steps[tens[tid].producer];
+        std::vector<int> V = ch.vars;
+        V.insert(V.end(), par.vars.begin(), par.vars.end());
+        std::vector<int> facs = ch.facs;
+        facs.insert(facs.end(), par.facs.begin(), par.facs.end());
+        table_vars(p, m, facs, V, gset, sigq);
+        if (!fits(int(par.out.size()), int(ch.ins.size()), int(gset.size()), int(V.size()), int(sigq.size()))) continue;
+        const int64_t work_m = int64_t(1) << (par.out.size() + V.size());
+        const int64_t work_c = int64_t(1) << (ch.out.size() + ch.vars.size());
+        const int64_t work_p = int64_t(1) << (par.out.size() + par.vars.size());
+        if (work_m > 2 * std::max(work_c, work_p)) continue;
+        par.vars = V;
+        par.facs = facs;
+        par.ins = ch.ins;
+        ch.alive = false;
+        tens[tid].producer = -2;   // never materialised
+    }
+}
+
+}  // namespace
+
+// Turns the merged raw steps into the plan: compact result ids, levels,
+// factor tables (index c = (g << kg) | w, kg = most summed variables of the
+// level), arena rows, sigma rows and wave tasks.
+static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector<int>& order,
+                                const std::vector<RStep>& rs, const std::vector<RTensor>& rt, TreePlan& t,
+                                std::string* err) {
+    const int nF = int(order.size());
+    std::vector<int> pos(nF);
+    for (int i = 0; i < nF; ++i) pos[order[i]] = i;
+    std::vector<int> tmap(rt.size(), -1);
+    t.tensor_axes.clear();
+    for (const RStep& st : rs) {
+        if (!st.alive) continue;
+        tmap[st.out_tensor] = int(t.tensor_axes.size());
+        std::vector<int> ax;
+        for (int u : st.out) ax.push_back(m.free_var[u]);
+        t.tensor_axes.push_back(ax);
+    }
+    const int T = int(t.tensor_axes.size());
+    t.tensor_made.assign(T, 0);
+    t.steps.clear();
+    t.finals.clear();
+    std::set<int> gset;
+    std::vector<int> sigq;
+    std::vector<std::vector<int>> step_facs;
+    double bytes = 0, flops = 0;
+    for (const RStep& st : rs) {
+        if (!st.alive) continue;
+        TreeStep ts;
+        for (int u : st.vars) ts.vars.push_back(m.free_var[u]);
+        ts.out_tensor = tmap[st.out_tensor];
+        for (int u : st.out) ts.out_axes.push_back(m.free_var[u]);
+        int level = 0;
+        for (int in : st.ins) {
+            const int ti = tmap[in];
+            if (ti < 0) { *err = "internal: merged result still read"; return QGM_E_INTERNAL; }
+            ts.in_tensors.push_back(ti);
+            level = std::max(level, t.tensor_made[ti] + 1);
+        }
+        ts.level = level;
+        t.tensor_made[ts.out_tensor] = level;
+        table_vars(p, m, st.facs, st.vars, gset, sigq);
+        std::vector<int> g(gset.begin(), gset.end());
+        std::sort(g.begin(), g.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+        for (int u : g) ts.gvars.push_back(m.free_var[u]);
+        ts.sig_q = sigq;
+        step_facs.push_back(st.facs);
+        if (ts.out_axes.empty()) t.finals.push_back(ts.out_tensor);
+        const double rows = double(int64_t(1) << ts.out_axes.size());
+        double b = 8.0 * rows;
+        for (int ti : ts.in_tensors) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
+        bytes += b;
+        const int mult = int(ts.in_tensors.size()) + (st.facs.empty() ? 0 : 1);
+        flops += rows * double(int64_t(1) << ts.vars.size()) * (6.0 * std::max(mult - 1, 0) + 2.0);
+        t.steps.push_back(std::move(ts));
+    }
+    t.bytes_per_b = bytes;
+    t.flops_per_b = flops;
+    int n_levels = 0;
+    for (auto& st : t.steps) n_levels = std::max(n_levels, st.level + 1);
+    t.levels.assign(n_levels, {});
+    t.level_k.assign(n_levels, 1);
+    for (int s = 0; s < int(t.steps.size()); ++s) {
+        t.levels[t.steps[s].level].push_back(s);
+        t.level_k[t.steps[s].level] = std::max(t.level_k[t.steps[s].level], int(t.steps[s].vars.size()));
+    }
+    // factor encoding: summed variable i is index bit i, table variable j is bit kg + j
+    t.max_rank = 0;
+    t.max_in = 0;
+    for (size_t si = 0; si < t.steps.size(); ++si) {
+        TreeStep& st = t.steps[si];
+        st.kg = t.level_k[st.level];
+        if (st.gb() + st.kg + st.sb() > kTreeMaxGIndex) {
+            *err = "bucket factor table exceeds the kernel limit";
+            return QGM_E_UNSUPPORTED;
+        }
+        t.max_rank = std::max(t.max_rank, int(st.out_axes.size()));
+        t.max_in = std::max(t.max_in, int(st.in_tensors.size()));
+        for (int f : step_facs[si]) {
+            const RawFactor& rf = m.facs[f];
+            TFactor tf{};
+            tf.type = rf.type;
+            tf.mat = rf.mat;
+            int* srcs[2][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}};
+            for (int k = 0; k < rf.nv; ++k) {
+                const int var = rf.v[k];
+                if (m.kind[var] == VK_FREE) {
+                    *srcs[k][0] = TS_G;
+                    auto it = std::find(st.vars.begin(), st.vars.end(), var);
+                    if (it != st.vars.end()) *srcs[k][1] = int(it - st.vars.begin());
+                    else *srcs[k][1] = st.kg + int(std::find(st.gvars.begin(), st.gvars.end(), var) - st.gvars.begin());
+                } else if (m.kind[var] == VK_SIG) {
+                    *srcs[k][0] = TS_SIG;
+                    *srcs[k][1] = int(std::find(st.sig_q.begin(), st.sig_q.end(), p.vars[var].qubit) - st.sig_q.begin());
+                } else {
+                    *srcs[k][0] = TS_ZERO;
+                    *srcs[k][1] = 0;
+                }
+            }
+            st.factors.push_back(tf);
+        }
+    }
+    return QGM_OK;
+}
+
+namespace {
 }  // namespace
 
 double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
@@ -306,30 +442,28 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks
     const int restarts = nF > 1500 ? 1 : (nF > 600 ? 4 : 16);
     std::vector<int> best;
-    SimOut best_r;
     double best_cost = std::numeric_limits<double>::infinity();
     std::string last_why;
     for (int crit = 0; crit < 2; ++crit)
         for (int rs = 0; rs <= restarts; ++rs) {
             std::vector<int> ord = greedy_order(nF, adj, crit, rs == 0 ? 0 : 0x5EED0000ull + uint64_t(rs) * 131 + crit);
-            SimOut r = simulate(p, m, ord, nullptr);
+            SimOut r = simulate(p, m, ord, nullptr, nullptr);
             ++t.n_candidates;
             if (!r.ok) { last_why = r.why; continue; }
             // a level costs about one launch: weigh it as 4 KiB per bitstring
             const double cost = r.bytes + 4096.0 * r.levels;
-            if (cost < best_cost) { best_cost = cost; best = ord; best_r = r; }
+            if (cost < best_cost) { best_cost = cost; best = ord; }
         }
     if (best.empty() && nF > 0) { *err = "no elimination order fits the kernels: " + last_why; return QGM_E_UNSUPPORTED; }
-    SimOut r = simulate(p, m, best, &t);
+    std::vector<RStep> rs;
+    std::vector<RTensor> rt;
+    SimOut r = simulate(p, m, best, &rs, &rt);
     if (!r.ok) { *err = r.why; return QGM_E_INTERNAL; }
+    if (p.opts.no_chain_merge == 0) merge_chains(p, m, rs, rt);
+    qgm_status fst = finalize_tree(p, m, best, rs, rt, t, err);
+    if (fst != QGM_OK) return fst;
     for (int u : best) t.order.push_back(m.free_var[u]);
-    t.max_rank = r.max_rank;
-    t.max_in = r.max_in;
-    t.bytes_per_b = r.bytes;
-    t.flops_per_b = r.flops;
-    const int n_levels = r.levels;
-    t.levels.assign(n_levels, {});
-    for (int s = 0; s < int(t.steps.size()); ++s) t.levels[t.steps[s].level].push_back(s);
+    const int n_levels = int(t.levels.size());
     // last level reading each result (the final product counts as level n_levels)
     const int T = int(t.tensor_axes.size());
     t.tensor_used.assign(T, n_levels);
@@ -341,12 +475,14 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return t.tensor_axes[a].size() > t.tensor_axes[b].size(); });
     t.tensor_row.assign(T, -1);
     std::vector<int> placed;
+    // a result holds at least 2^kTreeOcBits rows: a wave task writes that many
+    auto alloc_rows = [&](int tid) { return int64_t(1) << std::max(int(t.tensor_axes[tid].size()), kTreeOcBits); };
     for (int a : idx) {
-        const int64_t size = int64_t(1) << t.tensor_axes[a].size();
+        const int64_t size = alloc_rows(a);
         std::vector<std::pair<int64_t, int64_t>> busy;
         for (int b : placed)
             if (!(t.tensor_used[b] < t.tensor_made[a] || t.tensor_used[a] < t.tensor_made[b]))
-                busy.push_back({t.tensor_row[b], t.tensor_row[b] + (int64_t(1) << t.tensor_axes[b].size())});
+                busy.push_back({t.tensor_row[b], t.tensor_row[b] + alloc_rows(b)});
         std::sort(busy.begin(), busy.end());
         int64_t off = 0;
         for (auto& iv : busy) {
@@ -358,8 +494,33 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         placed.push_back(a);
     }
     int64_t g = 0;
-    for (auto& st : t.steps) { st.g_off = g; g += st.g_entries(); }
+    for (auto& st : t.steps) {
+        st.g_off = g;
+        g += st.g_entries();
+        st.sig_row = st.sb() > 0 ? t.n_sig_rows++ : -1;
+    }
     t.g_total = g;
+    t.ones_row = t.arena_rows;    // constant-1 input row for buckets with fewer inputs than their launch
+    t.arena_rows += 1;
+    t.n_sig_rows += 1;            // all-zero sigma row for buckets that read no output bit
+    // wave tasks grouped by level (a level is one launch)
+    t.level_task_off.assign(1, 0);
+    t.level_max_in.clear();
+    for (auto& lvl : t.levels) {
+        int mi = 0;
+        for (int sid : lvl) {
+            TreeStep& st = t.steps[sid];
+            st.task_off = t.n_tasks;
+            t.n_tasks += st.n_tasks();
+            mi = std::max(mi, int(st.in_tensors.size()));
+        }
+        t.level_task_off.push_back(t.n_tasks);
+        t.level_max_in.push_back(mi);
+    }
+    if (t.n_tasks > kTreeMaxTasks || t.arena_rows >= (int64_t(1) << 31) || t.g_total >= (int64_t(1) << 31)) {
+        *err = "bucket plan too large for the device tables (results of rank > 24)";
+        return QGM_E_UNSUPPORTED;
+    }
     return QGM_OK;
 }
 

@@ -233,7 +233,7 @@ def test_tree_plan_is_deterministic_and_consistent():
     a = Q.plan(c, ordering=1).info(1)
     b = Q.plan(c, ordering=1).info(1)
     assert a == b
-    assert sorted(a["order"]) == sorted(s["var"] for s in a["buckets"])
+    assert sorted(a["order"]) == sorted(v for s in a["buckets"] for v in s["vars"])
     assert a["n_free"] == len(a["order"])
     assert abs(sum(s["bytes_per_b"] for s in a["buckets"]) - a["bytes_per_amp"]) < 1e-6 * a["bytes_per_amp"]
     # every result is read by exactly one later bucket or by the final product
@@ -260,3 +260,26 @@ def test_tree_plan_rejects_open_qubits_slicing_and_backward():
     with pytest.raises(N.QgmError) as e:
         Q.plan(c, ordering=1).backward_workspace_bytes(64)
     assert e.value.status == N.QGM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(3, 3, 12, 5), (2, 4, 16, 6), (3, 4, 10, 8)])
+def test_tree_plan_without_chain_merge(rows, cols, depth, seed):
+    """One variable per bucket (no merged chains) gives the same amplitudes."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    info = _check_tree(c, C.random_bitstrings(c.n, 20, seed), chain_merge=False)
+    assert all(len(s["vars"]) == 1 for s in info["buckets"])
+
+
+def test_chain_merge_shortens_the_tree():
+    """Merged chains sum up to three variables per bucket: fewer levels, fewer
+    buckets and less traffic, the same elimination order."""
+    for name in ("c2_5x5_d25", "c3_5x6_d30"):
+        c, _ = C.workload(name)
+        a = Q.plan(c, ordering=1, chain_merge=False).info(0)
+        b = Q.plan(c, ordering=1).info(1)
+        assert b["order"] == a["order"]
+        assert b["n_levels"] < a["n_levels"] and b["n_buckets"] < a["n_buckets"]
+        assert b["bytes_per_amp"] < a["bytes_per_amp"]
+        assert max(len(s["vars"]) for s in b["buckets"]) <= 3
+        for s in b["buckets"]:
+            assert s["kg"] >= len(s["vars"])

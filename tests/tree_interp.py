@@ -1,8 +1,8 @@
 """CPU interpreter of a bucket-elimination plan (ordering 1), complex128.
 
-It executes the planner's output -- bucket factor lists, axis layouts,
-variant bits, tree levels and arena rows -- with the semantics the HIP bucket
-kernels implement, so the planner can be checked against the oracle without a
+It executes the planner's output -- bucket factor lists, summed variables
+(several for a merged chain), axis layouts, variant bits, tree levels and
+arena rows -- with the semantics the HIP bucket kernels implement, so the planner can be checked against the oracle without a
 GPU.  Results live in a simulated arena: every row remembers which result
 wrote it, a read checks that the row still holds that result, and a level's
 writes may not land on rows of a result that the level (or a later one) still
@@ -34,11 +34,13 @@ def _factor(f, a, b, gate_vals):
 
 
 def bucket_table(st, gate_vals):
-    """G of a bucket as [2^(gb+1) (index c = (g << 1) | v), 2^sb]."""
-    gb, sb = st["gb"], st["sb"]
-    c = np.arange(1 << (gb + 1))[:, None]
+    """G of a bucket as [2^(gb+kg) (index c = (g << kg) | w), 2^sb]; entries
+    whose w has bits beyond the bucket's k summed variables are 0."""
+    gb, sb, kg, k = st["gb"], st["sb"], st["kg"], len(st["vars"])
+    c = np.arange(1 << (gb + kg))[:, None]
     sig = np.arange(1 << sb)[None, :]
-    acc = np.ones((1 << (gb + 1), 1 << sb), dtype=np.complex128)
+    acc = np.ones((1 << (gb + kg), 1 << sb), dtype=np.complex128)
+    acc[((c[:, 0] & ((1 << kg) - 1)) >> k) != 0] = 0
 
     def val(src, bit):
         if src == TS_G:
@@ -73,7 +75,8 @@ def run_tree_plan(info, gate_vals, bits):
     for L in sorted(levels):
         pending = []
         for st in levels[L]:
-            v = st["var"]
+            summed = st["vars"]
+            kg = st["kg"]
             out_axes = st["out_axes"]
             r = len(out_axes)
             o = np.arange(1 << r)
@@ -82,29 +85,31 @@ def run_tree_plan(info, gate_vals, bits):
             for i, q in enumerate(st["sig_q"]):
                 sig |= xb(q) << i
             acc = np.zeros((1 << r, B), dtype=np.complex128)
-            for vv in (0, 1):
-                term = np.ones((1 << r, B), dtype=np.complex128)
-                if st["factors"]:
-                    G = bucket_table(st, gate_vals)
-                    g = np.zeros(1 << r, dtype=np.int64)
-                    for j, gv in enumerate(st["gvars"]):
-                        g |= bit_of[gv] << j
-                    term *= G[(g << 1) | vv][:, sig]
+            G = bucket_table(st, gate_vals)
+            g = np.zeros(1 << r, dtype=np.int64)
+            for j, gv in enumerate(st["gvars"]):
+                g |= bit_of[gv] << j
+            for w in range(1 << len(summed)):
+                val = {var: (w >> i) & 1 for i, var in enumerate(summed)}
+                term = np.array(G[(g << kg) | w][:, sig])
                 for tid in st["in_tensors"]:
                     T = read(tid)
                     idx = np.zeros(1 << r, dtype=np.int64)
                     for a, ax in enumerate(tensors[tid]["axes"]):
-                        idx |= (vv if ax == v else bit_of[ax]) << a
+                        idx |= (val[ax] if ax in val else bit_of[ax]) << a
                     term *= T[idx]
                 acc += term
             pending.append((st["out_tensor"], acc))
         for tid, acc in pending:
             t = tensors[tid]
-            rows = np.arange(t["row"], t["row"] + (1 << len(t["axes"])))
+            # the device writes every reserved row (rows beyond 2^rank repeat the first ones)
+            rows = np.arange(t["row"], t["row"] + t["alloc_rows"])
+            assert t["row"] + t["alloc_rows"] <= info["arena_rows"]
             for rr in rows:
                 prev = owner[rr]
-                assert prev < 0 or tensors[prev]["used"] < L, f"level {L} overwrites result {prev} still in use"
-            arena[rows] = acc
+                assert prev < 0 or prev == tid or tensors[prev]["used"] < L, \
+                    f"level {L} overwrites result {prev} still in use"
+            arena[rows] = np.tile(acc, (len(rows) // len(acc), 1))
             owner[rows] = tid
     amp = np.ones(B, dtype=np.complex128)
     for f in info["phase"]:

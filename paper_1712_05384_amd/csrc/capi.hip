@@ -35,9 +35,10 @@ struct qgm_plan_s {
     int64_t total_waves = 0;
     int max_ops = 1;
     // tree plans (ordering 1): offsets of the bucket records, factor tables, phase and final rows
-    size_t off_tsteps = 0, off_ttasks = 0, off_tgtab = 0, off_tfac = 0, off_tsig = 0, off_tphase = 0, off_tfinal = 0;
+    size_t off_ttasks = 0, off_tgtab = 0, off_tgroup = 0, off_tfac = 0, off_ttail = 0, off_tphase = 0, off_tfinal = 0;
     int n_gtabs = 0;
-    uint32_t max_tree_g = 0;
+    size_t off_tpro = 0, off_tg = 0;   // prologue block list; factor tables of a plan without gate values
+    int n_pro_blocks = 0;
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -79,89 +80,102 @@ size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 void layout_tree_tables(qgm_plan_t* P) {
     const qgm::TreePlan& t = P->p.tree;
-    size_t n_fac = 0;
-    P->n_gtabs = 0;
-    P->max_tree_g = 0;
+    size_t n_fac = 0, n_groups = 0;
     P->n_gtabs = int(t.steps.size());
-    P->max_tree_g = 1;
+    P->n_pro_blocks = 0;
     for (auto& st : t.steps) {
-        n_fac += st.factors.size();
-        P->max_tree_g = std::max<uint32_t>(P->max_tree_g, uint32_t(st.g_entries()));
+        n_fac += size_t(st.n_factors());
+        n_groups += st.groups.size();
+        P->n_pro_blocks += int((st.g_entries() + 255) / 256);
     }
+    const size_t n_tail = t.levels.size() - size_t(t.tail_start);
     P->off_fixed = 0;
-    P->off_tsteps = al(sizeof(double2) * qgm::kFixedMats * 4);
-    P->off_ttasks = P->off_tsteps + al(sizeof(qgm::TreeStepDev) * (t.steps.size() + 1));
+    P->off_ttasks = al(sizeof(double2) * qgm::kFixedMats * 4);
     P->off_tgtab = P->off_ttasks + al(sizeof(qgm::TreeTask) * size_t(t.n_tasks + 1));
-    P->off_tfac = P->off_tgtab + al(sizeof(qgm::TreeGTab) * (size_t(P->n_gtabs) + 1));
-    P->off_tsig = P->off_tfac + al(sizeof(qgm::TFactor) * (n_fac + 1));
-    P->off_tphase = P->off_tsig + al(sizeof(qgm::TreeSigTab) * (size_t(t.n_sig_rows) + 1));
+    P->off_tgroup = P->off_tgtab + al(sizeof(qgm::TreeGTab) * (size_t(P->n_gtabs) + 1));
+    P->off_tfac = P->off_tgroup + al(sizeof(qgm::TreeGroup) * (n_groups + 1));
+    P->off_ttail = P->off_tfac + al(sizeof(qgm::TFactor) * (n_fac + 1));
+    P->off_tphase = P->off_ttail + al(sizeof(qgm::TreeTailLevel) * (n_tail + 1));
     P->off_tfinal = P->off_tphase + al(sizeof(qgm::TFactor) * (t.phase.size() + 1));
-    P->total = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
+    P->off_tpro = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
+    P->off_tg = P->off_tpro + al(sizeof(qgm::TreeProBlock) * size_t(P->n_pro_blocks + 1));
+    P->total = P->off_tg + (P->p.n_slots == 0 ? al(sizeof(float2) * size_t(t.g_total)) : 0);
 }
 
-// Device records of a bucket: the row stride of every result bit in every
-// input (the index arithmetic of the bucket product), split into the
-// per-bucket record and one task record per chunk of 2^oc_bits result rows.
+// Device records of the buckets: the row stride of every result bit and
+// every summed variable in every input (the index arithmetic of the bucket
+// product), one task record per wave unit of result rows, the factor tables'
+// groups and factors, the tail levels and the prologue's block list.
 void fill_tree_tables(const qgm_plan_t* P, char* h) {
     const qgm::TreePlan& t = P->p.tree;
-    auto* sd = reinterpret_cast<qgm::TreeStepDev*>(h + P->off_tsteps);
     auto* tasks = reinterpret_cast<qgm::TreeTask*>(h + P->off_ttasks);
     auto* gt = reinterpret_cast<qgm::TreeGTab*>(h + P->off_tgtab);
+    auto* grp = reinterpret_cast<qgm::TreeGroup*>(h + P->off_tgroup);
     auto* fac = reinterpret_cast<qgm::TFactor*>(h + P->off_tfac);
-    auto* sg = reinterpret_cast<qgm::TreeSigTab*>(h + P->off_tsig);
-    int n_fac = 0;
-    const int zero_sig = t.n_sig_rows - 1;
-    sg[zero_sig] = qgm::TreeSigTab{};
+    auto* pro = reinterpret_cast<qgm::TreeProBlock*>(h + P->off_tpro);
+    int n_fac = 0, n_grp = 0, n_pro = 0;
     for (size_t i = 0; i < t.steps.size(); ++i) {
         const qgm::TreeStep& st = t.steps[i];
         const int r = int(st.out_axes.size());
+        qgm::TreeGTab g{};
+        g.gb = st.gb();
+        g.sb = st.sb();
+        g.k = st.kg;
+        g.n_groups = int32_t(st.groups.size());
+        g.group_off = n_grp;
+        g.n_fac = st.n_factors();
+        g.g_off = st.g_off;
+        for (auto& gr : st.groups) {
+            grp[n_grp++] = {n_fac, int32_t(gr.factors.size()), gr.k_int, 0};
+            for (auto& f : gr.factors) fac[n_fac++] = f;
+        }
+        for (int64_t sub = 0; sub < (st.g_entries() + 255) / 256; ++sub) pro[n_pro++] = {int32_t(i), int32_t(sub)};
+        gt[i] = g;
         const int n_in = int(st.in_tensors.size());
-        qgm::TreeStepDev d{};
-        d.n_in = n_in;
-        d.sb = st.sb();
-        d.sig_row = st.sig_row >= 0 ? st.sig_row : zero_sig;
-        d.gshift = st.kg + st.sb();
+        qgm::TreeTask base{};
+        base.k = st.kg;
+        base.n_sig = st.sb();
+        base.sb = st.sb();
+        base.gshift = st.kg + st.sb();
+        for (int b = 0; b < st.sb(); ++b) base.sig_q[b] = st.sig_q[b];
         std::vector<std::vector<int64_t>> str(n_in, std::vector<int64_t>(r, 0));
         std::vector<int64_t> gstr(r, 0);
         for (int k = 0; k < n_in; ++k) {
             const std::vector<int>& ax = t.tensor_axes[st.in_tensors[k]];
             for (int a = 0; a < int(ax.size()); ++a) {
-                for (size_t i = 0; i < st.vars.size(); ++i)
-                    if (ax[a] == st.vars[i]) d.in_vs[k][i] = 1 << a;
+                for (size_t v = 0; v < st.vars.size(); ++v)
+                    if (ax[a] == st.vars[v]) base.in_vs[k][v] = 1 << a;
                 for (int j = 0; j < r; ++j)
                     if (st.out_axes[j] == ax[a]) str[k][j] = int64_t(1) << a;
             }
             int64_t low = 0;
-            for (int j = 0; j < qgm::kTreeOcBits; ++j) {
+            for (int j = 0; j < qgm::kTreeOcBits; ++j) {   // wrapped beyond the result's rank
                 const int64_t sj = j < r ? str[k][j] : 0;
-                d.in_inc[k][j] = int32_t(sj - low);
+                base.in_inc[k][j] = int32_t(sj - low);
                 low += sj;
             }
         }
         for (int j = 0; j < r; ++j)
-            for (int g = 0; g < st.gb(); ++g)
-                if (st.out_axes[j] == st.gvars[g]) gstr[j] = int64_t(1) << g;
+            for (int gi = 0; gi < st.gb(); ++gi)
+                if (st.out_axes[j] == st.gvars[gi]) gstr[j] = int64_t(1) << gi;
         int64_t low = 0;
         for (int j = 0; j < qgm::kTreeOcBits; ++j) {
             const int64_t sj = j < r ? gstr[j] : 0;
-            d.g_inc[j] = int32_t(sj - low);
+            base.g_inc[j] = int32_t(sj - low);
             low += sj;
         }
-        sd[i] = d;
-        // tasks: chunk c covers result rows [c << ocb, (c << ocb) + n_oc)
-        const int ocb = st.oc_bits();
+        // task c covers result rows [c * unit_rows, (c + 1) * unit_rows), wrapping for small results
         const int64_t n_ch = st.n_tasks();
         for (int64_t c = 0; c < n_ch; ++c) {
-            const int64_t o0 = c << ocb;
-            qgm::TreeTask tk{};
-            tk.step = int32_t(i);
+            const int64_t o0 = c * st.unit_rows;
+            qgm::TreeTask tk = base;
             tk.out_row = int32_t(t.tensor_row[st.out_tensor] + o0);
             int64_t g0 = 0;
             for (int j = 0; j < r; ++j)
                 if ((o0 >> j) & 1) g0 += gstr[j];
-            tk.g_ent = int32_t(st.g_off + (g0 << d.gshift));
+            tk.g_ent = int32_t(st.g_off + (g0 << base.gshift));
             for (int k = 0; k < qgm::kTreeMaxIn; ++k) {
-                if (k >= n_in) { tk.in_row[k] = int32_t(t.ones_row); continue; }
+                if (k >= n_in) { tk.in_row[k] = -1; continue; }
                 int64_t row = t.tensor_row[st.in_tensors[k]];
                 for (int j = 0; j < r; ++j)
                     if ((o0 >> j) & 1) row += str[k][j];
@@ -169,22 +183,14 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
             }
             tasks[st.task_off + c] = tk;
         }
-        if (st.sig_row >= 0) {
-            qgm::TreeSigTab q{};
-            q.sb = st.sb();
-            for (int b = 0; b < st.sb(); ++b) q.q[b] = st.sig_q[b];
-            sg[st.sig_row] = q;
-        }
-        qgm::TreeGTab g{};
-        g.gb = st.gb();
-        g.sb = st.sb();
-        g.k = int32_t(st.vars.size());
-        g.kg = st.kg;
-        g.fac_off = n_fac;
-        g.n_fac = int32_t(st.factors.size());
-        g.g_off = st.g_off;
-        gt[i] = g;
-        for (auto& f : st.factors) fac[n_fac++] = f;
+    }
+    auto* tl = reinterpret_cast<qgm::TreeTailLevel*>(h + P->off_ttail);
+    for (size_t L = size_t(t.tail_start); L < t.levels.size(); ++L) {
+        qgm::TreeTailLevel x{};
+        x.task_off = int32_t(t.level_task_off[L]);
+        x.n_tasks = int32_t(t.level_task_off[L + 1] - t.level_task_off[L]);
+        x.nin = qgm::launch_inputs(t.level_max_in[L]);
+        tl[L - size_t(t.tail_start)] = x;
     }
     auto* ph = reinterpret_cast<qgm::TFactor*>(h + P->off_tphase);
     for (size_t i = 0; i < t.phase.size(); ++i) ph[i] = t.phase[i];
@@ -278,6 +284,19 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
     e = hipMemcpy(d, h, P->total, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "hipMemcpy(plan tables)"); }
+    if (P->p.is_tree && P->p.n_slots == 0) {
+        // the factor tables of a circuit without gate values depend only on the plan: build them once
+        char* b = static_cast<char*>(d);
+        qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeProBlock*>(b + P->off_tpro), P->n_pro_blocks,
+                                  reinterpret_cast<const qgm::TreeGTab*>(b + P->off_tgtab),
+                                  reinterpret_cast<const qgm::TreeGroup*>(b + P->off_tgroup),
+                                  reinterpret_cast<const qgm::TFactor*>(b + P->off_tfac),
+                                  reinterpret_cast<const double2*>(b + P->off_fixed), nullptr,
+                                  reinterpret_cast<float2*>(b + P->off_tg), P->p.tree.ones_g, nullptr);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "building the plan's factor tables"); }
+    }
     P->p.dev.push_back({dev, d});
     *base = static_cast<char*>(d);
     return QGM_OK;
@@ -477,33 +496,44 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     auto mark = [&](int i) { if (plan->timing) (void)hipEventRecord(ev[i], s); };
     mark(0);
     if (p.is_tree) {
-        // bucket elimination: prologue (factor tables, sigma rows), one launch per tree level, FP64 product
+        // bucket elimination: factor tables (only for a circuit with gate values), one launch per tree level,
+        // the tail
+        // levels and the FP64 product in one launch
         const qgm::TreePlan& t = p.tree;
         float2* arena = reinterpret_cast<float2*>(ws + w.f0);
-        float2* gt = reinterpret_cast<float2*>(ws + w.g);
-        auto* sigs = reinterpret_cast<uint16_t*>(ws + w.var_ids);
+        float2* gt = p.n_slots > 0 ? reinterpret_cast<float2*>(ws + w.g) : reinterpret_cast<float2*>(tables + plan->off_tg);
         const auto* fixed = reinterpret_cast<const double2*>(tables + plan->off_fixed);
         const auto* slots = static_cast<const float2*>(gate_vals);
-        const auto* sd = reinterpret_cast<const qgm::TreeStepDev*>(tables + plan->off_tsteps);
         const auto* tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks);
+        const auto* facs = reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tfac);
+        const auto* phase = reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tphase);
+        const auto* finals = reinterpret_cast<const int64_t*>(tables + plan->off_tfinal);
         mark(1);
-        qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab), plan->n_gtabs,
-                                  plan->max_tree_g, reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tfac),
-                                  fixed, slots, gt, reinterpret_cast<const qgm::TreeSigTab*>(tables + plan->off_tsig),
-                                  t.n_sig_rows, bits, B, uint32_t(B_eff), sigs,
-                                  arena + t.ones_row * B_eff, s);
+        if (p.n_slots > 0)   // factor tables from this call's gate values
+            qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeProBlock*>(tables + plan->off_tpro),
+                                      plan->n_pro_blocks,
+                                      reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab),
+                                      reinterpret_cast<const qgm::TreeGroup*>(tables + plan->off_tgroup), facs, fixed,
+                                      slots, gt, t.ones_g, s);
         mark(2);
-        for (size_t L = 0; L < t.levels.size(); ++L) {
+        for (int L = t.first_level; L < t.tail_start; ++L) {
             const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
-            qgm::launch_tree_level(t.level_max_in[L], t.level_k[L], tasks + t0, int32_t(t1 - t0), sd, arena, arena,
-                                   gt, sigs, uint32_t(B_eff), s);
+            qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
+                                   B, uint32_t(B_eff), s);
         }
-        mark(3);
-        if (out)
-            qgm::launch_tree_final(reinterpret_cast<const int64_t*>(tables + plan->off_tfinal), int(t.finals.size()),
-                                   reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tphase),
-                                   int(t.phase.size()), fixed, slots, arena, bits, B, uint32_t(B_eff), out,
-                                   p.opts.out_c128 != 0, s);
+        const int n_tail = int(t.levels.size()) - t.tail_start;
+        if (n_tail > 0) {
+            if (out)
+                qgm::launch_tree_tail(reinterpret_cast<const qgm::TreeTailLevel*>(tables + plan->off_ttail), n_tail,
+                                      tasks, arena, gt, t.ones_g, finals, int(t.finals.size()), phase, int(t.phase.size()),
+                                      fixed, slots, bits, B, uint32_t(B_eff), out, p.opts.out_c128 != 0, s);
+            mark(3);
+        } else {
+            mark(3);
+            if (out)
+                qgm::launch_tree_final(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed, slots, arena,
+                                       bits, B, uint32_t(B_eff), out, p.opts.out_c128 != 0, s);
+        }
         mark(4);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");

@@ -35,42 +35,52 @@ struct GbarParams {
     int32_t free_pos[kMaxRank];
 };
 
-// Device record of one bucket of a tree plan (read with scalar loads: every
-// field is 32-bit).
-struct TreeStepDev {
-    int32_t n_in, sb, sig_row, gshift;          // inputs, output bits, row of the sigma table, kg + sb
-    int32_t in_vs[kTreeMaxIn][kTreeMaxSum];     // row stride of summed variable i in input t (0: not an axis
-                                                //   of t, or t is a constant-1 pad beyond the bucket's inputs)
+// Records of a tree plan's device tables (read with scalar loads: every
+// field is 32- or 64-bit at its natural alignment).
+
+// One wave task of a bucket with inputs: tree_unit_rows(launch inputs, k)
+// consecutive result rows (times the 64-bitstring groups of the batch), with
+// everything the unit needs about its bucket, so a wave reads one record.  A
+// result with fewer rows has one task whose rows wrap around its index space;
+// the arena reserves 2^kTreeOcBits rows for every result, so all rows of the
+// task are stored and only the first 2^rank are read.
+struct TreeTask {
+    int32_t k;                                  // summed variables (1 .. kTreeMaxSum)
+    int32_t n_sig, sb, gshift;                  // output bits read by the factors; gshift = k + sb
+    int32_t out_row;                            // arena row of the task's first result row
+    int32_t g_ent;                              // factor-table entry of (g(o0), w = 0, sigma = 0)
+    int32_t pad0, pad1;
+    int32_t in_row[kTreeMaxIn];                 // arena row of input t at (o0, w = 0); -1 for t beyond the
+                                                //   bucket's inputs (the wave reads the constant 1 instead)
+    int32_t sig_q[kTreeMaxSig];                 // sigma bit i = bit sig_q[i] of the bitstring
+    int32_t in_vs[kTreeMaxIn][kTreeMaxSum];     // row stride of summed variable i in input t (0: not an axis)
     int32_t in_inc[kTreeMaxIn][kTreeOcBits];    // row change of input t when o -> o + 1 with ctz(o + 1) = j
     int32_t g_inc[kTreeOcBits];                 // factor-table g change for the same steps
-    int32_t pad;
+    int32_t pad2;
 };
 
-// One wave task: a chunk of 2^kTreeOcBits consecutive result rows of a
-// bucket (times the 64-bitstring groups of the batch).  A result of rank
-// below kTreeOcBits has one chunk whose rows wrap around its index space; the
-// arena reserves 2^kTreeOcBits rows for it, so all rows of the chunk are
-// stored and only the first 2^rank are read.
-struct TreeTask {
-    int32_t step;                               // bucket
-    int32_t pad;
-    int32_t out_row;                            // arena row of the chunk's first result row
-    int32_t g_ent;                              // factor-table entry of (g(o0), w = 0, sigma = 0)
-    int32_t in_row[kTreeMaxIn];                 // arena row of input t at (o0, v = 0)
-};
-
-// Factor-table record of one bucket (prologue kernel).
+// Factor table of a bucket (prologue kernel): entry e = (((g << k) | w) << sb)
+// | sigma is the product over the bucket's factor groups of (prod_f f), or of
+// (sum over the group's own 2^k_int values of prod_f f).
 struct TreeGTab {
-    int32_t gb, sb, k, kg;                      // entry e = (((g << kg) | w) << sb) | sigma; w >= 2^k gives 0
-    int32_t fac_off, n_fac;
+    int32_t gb, sb, k, n_groups;
+    int32_t group_off, n_fac;                   // first group record; factors of all groups
     int64_t g_off;
 };
 
-// Sigma-table record of one bucket: sigma bit i = bit q[i] of the bitstring.
-struct TreeSigTab {
-    int32_t sb;
-    int32_t q[kTreeMaxSig];
-    int32_t pad[3];
+struct TreeGroup {
+    int32_t fac_off, n_fac, k_int, pad;
+};
+
+// One block of the prologue: what it computes.
+struct TreeProBlock {
+    int32_t idx;       // factor table
+    int32_t sub;       // block within the table (256 entries)
+};
+
+// A level run by the tail kernel (one work-group per 64-bitstring group).
+struct TreeTailLevel {
+    int32_t task_off, n_tasks, nin, pad;
 };
 
 constexpr uint32_t kStepMaxGrid = 8192;           // work-groups of the step kernel (grid-stride beyond)
@@ -100,13 +110,16 @@ void launch_seed(const float2* g, uint32_t B_eff, uint32_t B_pad, int64_t B, int
 void launch_finalize(const float2* f, uint32_t B_eff, uint32_t B_pad, int64_t B, int n_slices, int n_open,
                      const int32_t* final_pos, void* out, bool c128, hipStream_t stream);
 
-void launch_tree_prologue(const TreeGTab* gtabs, int n_gtabs, uint32_t max_entries, const TFactor* facs,
-                          const double2* fixed, const float2* slots, float2* gtab, const TreeSigTab* sigtabs,
-                          int n_sig, const uint64_t* bits, int64_t B, uint32_t B_eff, uint16_t* sigs, float2* ones,
-                          hipStream_t stream);
-void launch_tree_level(int nin, int k, const TreeTask* tasks, int32_t n_tasks, const TreeStepDev* steps,
-                       const float2* ain, float2* aout, const float2* gtab, const uint16_t* sigs, uint32_t B_eff,
+void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
+                          const TFactor* facs, const double2* fixed, const float2* slots, float2* gtab,
+                          int64_t ones_g, hipStream_t stream);
+void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
+                       const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        hipStream_t stream);
+void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask* tasks, float2* arena,
+                      const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,
+                      int n_phase, const double2* fixed, const float2* slots, const uint64_t* bits, int64_t B,
+                      uint32_t B_eff, void* out, bool c128, hipStream_t stream);
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                        const float2* slots, const float2* arena, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        void* out, bool c128, hipStream_t stream);

@@ -450,9 +450,11 @@ WsLayout workspace_layout(const Plan& p, int64_t B) {
     const uint64_t be = uint64_t(batch_eff(p, B));
     if (p.is_tree) {
         w.f0 = w.f1 = w.var_ids = 0;
+        // factor tables live in the workspace only when the circuit reads gate values (otherwise the
+        // plan's device tables hold them, built once)
         w.g = al(uint64_t(p.tree.arena_rows) * be * 8);
-        w.var_ids = w.g + al(uint64_t(p.tree.g_total) * 8);
-        w.total = w.var_ids + al(uint64_t(p.tree.n_sig_rows) * be * 2);
+        w.var_ids = w.g + (p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0);
+        w.total = w.var_ids;
         return w;
     }
     const uint64_t fbytes = al((uint64_t(1) << p.r_max) * be * 8);
@@ -489,6 +491,8 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"n_steps\":0,\"n_buckets\":" << t.steps.size() << ",\"n_levels\":" << t.levels.size()
       << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
+      << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
+      << ",\"launches\":" << (1 + std::max(t.tail_start - t.first_level, 0) + 1)
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
@@ -502,7 +506,7 @@ static std::string tree_json(const Plan& p, int detail) {
         json_ints(o, st.vars);
         o << ",\"kg\":" << st.kg << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
-          << ",\"n_factors\":" << st.factors.size() << ",\"g_off\":" << st.g_off
+          << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
           << ",\"bytes_per_b\":" << tree_step_bytes(t, st);
         if (detail >= 1) {
             o << ",\"out_tensor\":" << st.out_tensor;
@@ -510,8 +514,17 @@ static std::string tree_json(const Plan& p, int detail) {
             o << ",\"in_tensors\":"; json_ints(o, st.in_tensors);
             o << ",\"gvars\":"; json_ints(o, st.gvars);
             o << ",\"sig_q\":"; json_ints(o, st.sig_q);
-            o << ",\"factors\":[";
-            for (size_t j = 0; j < st.factors.size(); ++j) { if (j) o << ","; json_factor(o, st.factors[j]); }
+            o << ",\"groups\":[";
+            for (size_t gi = 0; gi < st.groups.size(); ++gi) {
+                o << (gi ? "," : "") << "{\"k\":" << st.groups[gi].k_int << ",\"vars\":";
+                json_ints(o, st.groups[gi].vars);
+                o << ",\"factors\":[";
+                for (size_t j = 0; j < st.groups[gi].factors.size(); ++j) {
+                    if (j) o << ",";
+                    json_factor(o, st.groups[gi].factors[j]);
+                }
+                o << "]}";
+            }
             o << "]";
         }
         o << "}";

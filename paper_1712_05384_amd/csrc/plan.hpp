@@ -97,8 +97,8 @@ int64_t padded_batch(int64_t B);
 inline int64_t batch_eff(const Plan& p, int64_t B) { return padded_batch(B) << p.sliced.size(); }
 
 // Workspace of a call.  Ordering 0: two frontier buffers, the variant ids
-// and the G table.  Ordering 1: the arena of bucket results (f0), the factor
-// tables (g) and the per-bucket sigma rows (var_ids).
+// and the G table.  Ordering 1: the arena of bucket results (f0) and, when
+// the circuit reads gate values, the factor tables (g).
 struct WsLayout {
     uint64_t f0 = 0, f1 = 0, var_ids = 0, g = 0, total = 0;
 };

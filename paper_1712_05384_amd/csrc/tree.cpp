@@ -137,6 +137,7 @@ struct RStep {
     std::vector<int> out;    // result axes, elimination position ascending
     std::vector<int> ins;    // input results
     std::vector<int> facs;   // gate factors (indices into Model::facs)
+    std::vector<std::pair<std::vector<int>, std::vector<int>>> absorbed;   // (variables, factors) of folded buckets
     int out_tensor = -1;
     bool alive = true;
 };
@@ -161,6 +162,17 @@ void table_vars(const Plan& p, const Model& m, const std::vector<int>& facs, con
                 if (std::find(sigq.begin(), sigq.end(), q) == sigq.end()) sigq.push_back(q);
             }
     }
+}
+
+// Table variables and output bits of a bucket with absorbed groups: every
+// free variable of any factor that is neither summed by the bucket nor a
+// group's own variable.
+void group_table_vars(const Plan& p, const Model& m, const RStep& st, std::set<int>& gset, std::vector<int>& sigq) {
+    std::vector<int> excl = st.vars;
+    for (auto& a : st.absorbed) excl.insert(excl.end(), a.first.begin(), a.first.end());
+    std::vector<int> facs = st.facs;
+    for (auto& a : st.absorbed) facs.insert(facs.end(), a.second.begin(), a.second.end());
+    table_vars(p, m, facs, excl, gset, sigq);
 }
 
 bool fits(int rank, int n_in, int gb, int k, int sb) {
@@ -272,6 +284,38 @@ void merge_chains(const Plan& p, const Model& m, std::vector<RStep>& steps, std:
     }
 }
 
+// Folds every bucket without inputs into the factor table of the bucket that
+// reads its result: that bucket's table gets one more factor group, the sum
+// over the folded bucket's variables of its factors' product.  The folded
+// result is never materialised and level 0 of the tree (if every such bucket
+// has a reader and the tables stay within the limits) needs no launch.
+int absorb_leaves(const Plan& p, const Model& m, std::vector<RStep>& steps, std::vector<RTensor>& tens) {
+    std::vector<int> reader(tens.size(), -1);
+    for (size_t i = 0; i < steps.size(); ++i)
+        if (steps[i].alive)
+            for (int t : steps[i].ins) reader[t] = int(i);
+    std::set<int> gset;
+    std::vector<int> sigq;
+    int n = 0;
+    for (size_t i = 0; i < steps.size(); ++i) {
+        RStep& lf = steps[i];
+        if (!lf.alive || !lf.ins.empty() || !lf.absorbed.empty() || reader[lf.out_tensor] < 0) continue;
+        RStep& par = steps[reader[lf.out_tensor]];
+        par.absorbed.push_back({lf.vars, lf.facs});
+        group_table_vars(p, m, par, gset, sigq);
+        const int n_in = int(par.ins.size()) - 1;
+        if (!fits(int(par.out.size()), n_in, int(gset.size()), int(par.vars.size()), int(sigq.size()))) {
+            par.absorbed.pop_back();
+            continue;
+        }
+        par.ins.erase(std::find(par.ins.begin(), par.ins.end(), lf.out_tensor));
+        lf.alive = false;
+        tens[lf.out_tensor].producer = -2;   // never materialised
+        ++n;
+    }
+    return n;
+}
+
 }  // namespace
 
 // Turns the merged raw steps into the plan: compact result ids, levels,
@@ -298,7 +342,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     t.finals.clear();
     std::set<int> gset;
     std::vector<int> sigq;
-    std::vector<std::vector<int>> step_facs;
+    std::vector<std::vector<std::pair<std::vector<int>, std::vector<int>>>> step_groups;   // (own vars, factors)
     double bytes = 0, flops = 0;
     for (const RStep& st : rs) {
         if (!st.alive) continue;
@@ -315,18 +359,19 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         }
         ts.level = level;
         t.tensor_made[ts.out_tensor] = level;
-        table_vars(p, m, st.facs, st.vars, gset, sigq);
+        group_table_vars(p, m, st, gset, sigq);
         std::vector<int> g(gset.begin(), gset.end());
         std::sort(g.begin(), g.end(), [&](int a, int b) { return pos[a] < pos[b]; });
         for (int u : g) ts.gvars.push_back(m.free_var[u]);
         ts.sig_q = sigq;
-        step_facs.push_back(st.facs);
+        step_groups.push_back({{std::vector<int>{}, st.facs}});
+        for (auto& a : st.absorbed) step_groups.back().push_back(a);
         if (ts.out_axes.empty()) t.finals.push_back(ts.out_tensor);
         const double rows = double(int64_t(1) << ts.out_axes.size());
         double b = 8.0 * rows;
         for (int ti : ts.in_tensors) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
         bytes += b;
-        const int mult = int(ts.in_tensors.size()) + (st.facs.empty() ? 0 : 1);
+        const int mult = int(ts.in_tensors.size()) + 1;
         flops += rows * double(int64_t(1) << ts.vars.size()) * (6.0 * std::max(mult - 1, 0) + 2.0);
         t.steps.push_back(std::move(ts));
     }
@@ -335,45 +380,56 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     int n_levels = 0;
     for (auto& st : t.steps) n_levels = std::max(n_levels, st.level + 1);
     t.levels.assign(n_levels, {});
-    t.level_k.assign(n_levels, 1);
-    for (int s = 0; s < int(t.steps.size()); ++s) {
-        t.levels[t.steps[s].level].push_back(s);
-        t.level_k[t.steps[s].level] = std::max(t.level_k[t.steps[s].level], int(t.steps[s].vars.size()));
-    }
+    for (int s = 0; s < int(t.steps.size()); ++s) t.levels[t.steps[s].level].push_back(s);
     // factor encoding: summed variable i is index bit i, table variable j is bit kg + j
     t.max_rank = 0;
     t.max_in = 0;
     for (size_t si = 0; si < t.steps.size(); ++si) {
         TreeStep& st = t.steps[si];
-        st.kg = t.level_k[st.level];
+        st.kg = int(st.vars.size());
         if (st.gb() + st.kg + st.sb() > kTreeMaxGIndex) {
             *err = "bucket factor table exceeds the kernel limit";
             return QGM_E_UNSUPPORTED;
         }
         t.max_rank = std::max(t.max_rank, int(st.out_axes.size()));
         t.max_in = std::max(t.max_in, int(st.in_tensors.size()));
-        for (int f : step_facs[si]) {
-            const RawFactor& rf = m.facs[f];
-            TFactor tf{};
-            tf.type = rf.type;
-            tf.mat = rf.mat;
-            int* srcs[2][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}};
-            for (int k = 0; k < rf.nv; ++k) {
-                const int var = rf.v[k];
-                if (m.kind[var] == VK_FREE) {
-                    *srcs[k][0] = TS_G;
-                    auto it = std::find(st.vars.begin(), st.vars.end(), var);
-                    if (it != st.vars.end()) *srcs[k][1] = int(it - st.vars.begin());
-                    else *srcs[k][1] = st.kg + int(std::find(st.gvars.begin(), st.gvars.end(), var) - st.gvars.begin());
-                } else if (m.kind[var] == VK_SIG) {
-                    *srcs[k][0] = TS_SIG;
-                    *srcs[k][1] = int(std::find(st.sig_q.begin(), st.sig_q.end(), p.vars[var].qubit) - st.sig_q.begin());
-                } else {
-                    *srcs[k][0] = TS_ZERO;
-                    *srcs[k][1] = 0;
+        for (auto& grp : step_groups[si]) {
+            TGroup tg;
+            tg.k_int = int(grp.first.size());
+            for (int u : grp.first) tg.vars.push_back(m.free_var[u]);
+            for (int f : grp.second) {
+                const RawFactor& rf = m.facs[f];
+                TFactor tf{};
+                tf.type = rf.type;
+                tf.mat = rf.mat;
+                int* srcs[2][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}};
+                for (int k = 0; k < rf.nv; ++k) {
+                    const int var = rf.v[k];
+                    if (m.kind[var] == VK_FREE) {
+                        const int u = m.fi[var];
+                        auto own = std::find(grp.first.begin(), grp.first.end(), u);
+                        auto it = std::find(st.vars.begin(), st.vars.end(), var);
+                        if (own != grp.first.end()) {
+                            *srcs[k][0] = TS_INT;
+                            *srcs[k][1] = int(own - grp.first.begin());
+                        } else if (it != st.vars.end()) {
+                            *srcs[k][0] = TS_G;
+                            *srcs[k][1] = int(it - st.vars.begin());
+                        } else {
+                            *srcs[k][0] = TS_G;
+                            *srcs[k][1] = st.kg + int(std::find(st.gvars.begin(), st.gvars.end(), var) - st.gvars.begin());
+                        }
+                    } else if (m.kind[var] == VK_SIG) {
+                        *srcs[k][0] = TS_SIG;
+                        *srcs[k][1] = int(std::find(st.sig_q.begin(), st.sig_q.end(), p.vars[var].qubit) - st.sig_q.begin());
+                    } else {
+                        *srcs[k][0] = TS_ZERO;
+                        *srcs[k][1] = 0;
+                    }
                 }
+                tg.factors.push_back(tf);
             }
-            st.factors.push_back(tf);
+            st.groups.push_back(std::move(tg));
         }
     }
     return QGM_OK;
@@ -460,6 +516,7 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     SimOut r = simulate(p, m, best, &rs, &rt);
     if (!r.ok) { *err = r.why; return QGM_E_INTERNAL; }
     if (p.opts.no_chain_merge == 0) merge_chains(p, m, rs, rt);
+    t.n_absorbed = absorb_leaves(p, m, rs, rt);
     qgm_status fst = finalize_tree(p, m, best, rs, rt, t, err);
     if (fst != QGM_OK) return fst;
     for (int u : best) t.order.push_back(m.free_var[u]);
@@ -493,29 +550,39 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         t.arena_rows = std::max(t.arena_rows, off + size);
         placed.push_back(a);
     }
+    // factor tables of every bucket
     int64_t g = 0;
     for (auto& st : t.steps) {
         st.g_off = g;
         g += st.g_entries();
-        st.sig_row = st.sb() > 0 ? t.n_sig_rows++ : -1;
     }
-    t.g_total = g;
-    t.ones_row = t.arena_rows;    // constant-1 input row for buckets with fewer inputs than their launch
-    t.arena_rows += 1;
-    t.n_sig_rows += 1;            // all-zero sigma row for buckets that read no output bit
-    // wave tasks grouped by level (a level is one launch)
+    t.ones_g = g;                 // constant 1 read for inputs a bucket does not have
+    t.g_total = g + 1;
+    // wave tasks of the buckets with inputs, grouped by level (a level is one launch)
     t.level_task_off.assign(1, 0);
     t.level_max_in.clear();
-    for (auto& lvl : t.levels) {
+    for (size_t L = 0; L < t.levels.size(); ++L) {
         int mi = 0;
-        for (int sid : lvl) {
+        for (int sid : t.levels[L]) mi = std::max(mi, int(t.steps[sid].in_tensors.size()));
+        const int nin = launch_inputs(mi);
+        for (int sid : t.levels[L]) {
             TreeStep& st = t.steps[sid];
+            st.unit_rows = tree_unit_rows(nin, st.kg);
             st.task_off = t.n_tasks;
             t.n_tasks += st.n_tasks();
-            mi = std::max(mi, int(st.in_tensors.size()));
         }
         t.level_task_off.push_back(t.n_tasks);
         t.level_max_in.push_back(mi);
+    }
+    // tail: the longest run of last levels with few tasks and few inputs
+    t.first_level = 0;
+    while (t.first_level < int(t.levels.size()) && t.levels[t.first_level].empty()) ++t.first_level;
+    t.tail_start = int(t.levels.size());
+    while (t.tail_start > std::max(t.first_level, 1)) {
+        const int L = t.tail_start - 1;
+        const int64_t nt = t.level_task_off[L + 1] - t.level_task_off[L];
+        if (nt > kTreeTailTasks || launch_inputs(t.level_max_in[L]) > kTreeTailInputs) break;
+        t.tail_start = L;
     }
     if (t.n_tasks > kTreeMaxTasks || t.arena_rows >= (int64_t(1) << 31) || t.g_total >= (int64_t(1) << 31)) {
         *err = "bucket plan too large for the device tables (results of rank > 24)";

@@ -44,202 +44,249 @@ __device__ __forceinline__ double2 factor_value(const TFactor& f, uint32_t a, ui
 }  // namespace
 
 constexpr int kTreeMaxPrologueFactors = 64;
+constexpr int kTreeMaxPhaseLds = 512;
 
-// Prologue of a call: the factor table of every bucket (blockIdx.y <
-// n_gtabs; a bucket without factors has a table of ones), the sigma rows
-// (n_gtabs <= blockIdx.y < n_gtabs + n_sig) and the arena's constant-1 row
-// (last blockIdx.y).  Table entry e = (c << sb) | sigma with
-// c = (g << 1) | v holds the product of the bucket's gate factors (Sec. III.B)
-// for those variable values, in FP64 rounded once to complex64; entries of
-// summed-variable values w >= 2^k (a bucket summing fewer variables than its
-// launch) are 0.
-__global__ void __launch_bounds__(256) k_tree_prologue(const TreeGTab* __restrict__ gtabs, int n_gtabs,
+// The four values of up to kTreeMaxPrologueFactors factors, and the sources
+// of their variables, staged in LDS by the whole block.
+struct FactorLds {
+    double2 v[kTreeMaxPrologueFactors][4];
+    int32_t s[kTreeMaxPrologueFactors][4];
+};
+
+__device__ __forceinline__ int stage_factors(FactorLds& L, const TFactor* __restrict__ facs, int n_fac,
+                                             const double2* __restrict__ fixed, const float2* __restrict__ slots) {
+    const int nf = n_fac < kTreeMaxPrologueFactors ? n_fac : kTreeMaxPrologueFactors;
+    for (int i = threadIdx.x; i < nf * 4; i += blockDim.x) {
+        const TFactor f = facs[i >> 2];
+        L.v[i >> 2][i & 3] = factor_value(f, (i >> 1) & 1u, i & 1u, fixed, slots);
+        if ((i & 3) == 0) {
+            L.s[i >> 2][0] = f.src0;
+            L.s[i >> 2][1] = f.bit0;
+            L.s[i >> 2][2] = f.src1;
+            L.s[i >> 2][3] = f.bit1;
+        }
+    }
+    __syncthreads();
+    return nf;
+}
+
+// Product of factors [f0, f1) of a table for index c, output bits sig and a
+// group's own summed value iv (FP64).
+__device__ __forceinline__ double2 factor_product(const FactorLds& L, int nf, const TFactor* __restrict__ facs,
+                                                  int f0, int f1, const double2* __restrict__ fixed,
+                                                  const float2* __restrict__ slots, uint32_t c, uint32_t sig,
+                                                  uint32_t iv) {
+    auto val = [&](int32_t src, int32_t bit) -> uint32_t {
+        switch (src) {
+            case TS_G: return (c >> bit) & 1u;
+            case TS_SIG: return (sig >> bit) & 1u;
+            case TS_INT: return (iv >> bit) & 1u;
+            default: return 0u;
+        }
+    };
+    double2 acc = make_double2(1.0, 0.0);
+    for (int i = f0; i < f1; ++i) {
+        if (i < nf) {
+            acc = cmuld(acc, L.v[i][val(L.s[i][0], L.s[i][1]) * 2u + val(L.s[i][2], L.s[i][3])]);
+        } else {   // beyond the LDS copy: read the record directly
+            const TFactor f = facs[i];
+            acc = cmuld(acc, factor_value(f, val(f.src0, f.bit0), val(f.src1, f.bit1), fixed, slots));
+        }
+    }
+    return acc;
+}
+
+__device__ __forceinline__ uint32_t gather_sigma(uint64_t x, const int32_t* q, int n) {
+    uint32_t sig = 0;
+#pragma unroll
+    for (int i = 0; i < kTreeMaxSig; ++i)
+        if (i < n) sig |= uint32_t((x >> q[i]) & 1ull) << i;
+    return sig;
+}
+
+// Factor tables (one launch; block i does 256 entries of table blocks[i].idx;
+// block 0 also writes the constant 1): entry e = (c << sb) | sigma with
+// c = (g << k) | w is the product over the bucket's factor groups (its own
+// gate factors, Sec. III.B; then each absorbed bucket's factors summed over
+// that bucket's variables) for those variable values, in FP64 rounded once to
+// complex64.  A plan whose circuit reads no gate values runs this once, into
+// its own device tables; otherwise every call runs it into the workspace.
+__global__ void __launch_bounds__(256) k_tree_prologue(const TreeProBlock* __restrict__ blocks,
+                                                       const TreeGTab* __restrict__ gtabs,
+                                                       const TreeGroup* __restrict__ groups,
                                                        const TFactor* __restrict__ facs,
                                                        const double2* __restrict__ fixed,
                                                        const float2* __restrict__ slots, float2* __restrict__ gtab,
-                                                       const TreeSigTab* __restrict__ sigtabs, int n_sig,
-                                                       const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
-                                                       uint16_t* __restrict__ sigs, float2* __restrict__ ones) {
-    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-    if (int(blockIdx.y) < n_gtabs) {
-        // the four values of every factor of this bucket, and the index bits
-        // feeding its variables, staged in LDS once per block
-        __shared__ double2 fv[kTreeMaxPrologueFactors][4];
-        __shared__ int32_t fs[kTreeMaxPrologueFactors][4];
-        const TreeGTab t = gtabs[blockIdx.y];
-        const uint32_t total = 1u << (t.gb + t.kg + t.sb);
-        if (blockIdx.x * 256u >= total) return;   // whole block beyond this table (uniform)
-        const int nf = t.n_fac < kTreeMaxPrologueFactors ? t.n_fac : kTreeMaxPrologueFactors;
-        for (int i = threadIdx.x; i < nf * 4; i += 256) {
-            const TFactor f = facs[t.fac_off + (i >> 2)];
-            fv[i >> 2][i & 3] = factor_value(f, (i >> 1) & 1u, i & 1u, fixed, slots);
-            if ((i & 3) == 0) {
-                fs[i >> 2][0] = f.src0;
-                fs[i >> 2][1] = f.bit0;
-                fs[i >> 2][2] = f.src1;
-                fs[i >> 2][3] = f.bit1;
-            }
+                                                       int64_t ones_g) {
+    __shared__ FactorLds L;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gtab[ones_g] = make_float2(1.f, 0.f);
+    const TreeProBlock blk = blocks[blockIdx.x];
+    const TreeGTab t = gtabs[blk.idx];
+    const TreeGroup* __restrict__ gr = groups + t.group_off;
+    const TFactor* __restrict__ tf = facs + gr[0].fac_off;   // the groups' factors are contiguous
+    const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);
+    const int64_t e = int64_t(blk.sub) * 256 + threadIdx.x;
+    if (e >= (int64_t(1) << (t.gb + t.k + t.sb))) return;
+    const uint32_t sig = uint32_t(e) & ((1u << t.sb) - 1u);
+    const uint32_t c = uint32_t(e) >> t.sb;
+    double2 acc = make_double2(1.0, 0.0);
+    for (int q = 0; q < t.n_groups; ++q) {
+        const TreeGroup g = gr[q];
+        const int f0 = g.fac_off - gr[0].fac_off, f1 = f0 + g.n_fac;
+        double2 sum = make_double2(0.0, 0.0);
+        for (uint32_t iv = 0; iv < (1u << g.k_int); ++iv) {
+            const double2 v = factor_product(L, nf, tf, f0, f1, fixed, slots, c, sig, iv);
+            sum.x += v.x;
+            sum.y += v.y;
         }
-        __syncthreads();
-        if (e >= total) return;
-        const uint32_t sig = e & ((1u << t.sb) - 1u);
-        const uint32_t c = e >> t.sb;
-        if (((c & ((1u << t.kg) - 1u)) >> t.k) != 0u) {   // summed-variable slots the bucket does not have
-            gtab[t.g_off + e] = make_float2(0.f, 0.f);
-            return;
-        }
-        auto val = [&](int32_t src, int32_t bit) -> uint32_t {
-            return src == TS_G ? (c >> bit) & 1u : (src == TS_SIG ? (sig >> bit) & 1u : 0u);
-        };
-        double2 acc = make_double2(1.0, 0.0);
-        for (int i = 0; i < nf; ++i) acc = cmuld(acc, fv[i][val(fs[i][0], fs[i][1]) * 2u + val(fs[i][2], fs[i][3])]);
-        for (int i = nf; i < t.n_fac; ++i) {   // beyond the LDS copy: read the records directly
-            const TFactor f = facs[t.fac_off + i];
-            acc = cmuld(acc, factor_value(f, val(f.src0, f.bit0), val(f.src1, f.bit1), fixed, slots));
-        }
-        gtab[t.g_off + e] = make_float2(float(acc.x), float(acc.y));
-        return;
+        acc = cmuld(acc, sum);
     }
-    if (e >= B_eff) return;
-    const int r = int(blockIdx.y) - n_gtabs;
-    if (r == n_sig) {   // the arena's constant-1 row
-        ones[e] = make_float2(1.f, 0.f);
-        return;
-    }
-    const TreeSigTab st = sigtabs[r];
-    const uint64_t x = int64_t(e) < B ? bits[e] : 0ull;
-    uint32_t sig = 0;
-    for (int i = 0; i < st.sb; ++i) sig |= uint32_t((x >> st.q[i]) & 1ull) << i;
-    sigs[size_t(r) * B_eff + e] = uint16_t(sig);
+    gtab[t.g_off + e] = make_float2(float(acc.x), float(acc.y));
 }
 
-// One level of the elimination tree.  Wave unit u handles task u / n_bg
-// (2^kTreeOcBits consecutive result rows of one bucket) for the 64
-// bitstrings of group u % n_bg:
+// One wave unit of a bucket with inputs: the task's rows for the 64
+// bitstrings b of one group,
 //   R[o][b] = sum_{w < 2^K} G[g(o), w, sigma(b)] * prod_t T_t[idx_t(o) + off_t(w)][b],
-// w running over the values of the bucket's summed variables (one, or up to
-// three for a merged chain).  The code has no data-dependent branch: a
-// bucket with fewer inputs than NIN multiplies the arena's constant-1 row,
-// one summing fewer variables than K has zeros in its table at the extra w,
-// one without output bits reads the all-zero sigma row, and the chunk of a
-// result with fewer than 2^kTreeOcBits rows wraps onto valid rows and stores
-// into rows the arena reserves for it.  Inputs (ain) and results (aout) are
-// views of one arena that a level never reads and writes at the same rows, so
-// the loads of a batch of rows can all be in flight at once.
+// w running over the values of the bucket's K summed variables (one, or up to
+// three for a merged chain).  No data-dependent branch: a bucket with fewer
+// inputs than NIN multiplies a constant 1 (one address for all lanes, chosen
+// per wave), and the task of a result with fewer rows than a unit wraps onto
+// valid rows and stores into rows the arena reserves for it.  Inputs (ain) and results (aout) are views
+// of one arena whose rows a level never both reads and writes, so all loads
+// of a unit can be in flight at once.
 template <int NIN, int K>
-__global__ void __launch_bounds__(256) k_tree_level(const TreeTask* __restrict__ tasks, uint32_t n_units,
-                                                    const TreeStepDev* __restrict__ steps,
-                                                    const float2* __restrict__ ain, float2* __restrict__ aout,
-                                                    const float2* __restrict__ gtab, const uint16_t* __restrict__ sigs,
-                                                    uint32_t B_eff, uint32_t n_bg) {
-    constexpr int OC = 1 << kTreeOcBits;
+__device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __restrict__ ain,
+                                          float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
+                                          int64_t sig, uint32_t b, int64_t be) {
     constexpr int W = 1 << K;
     constexpr int WC = W < 8 ? W : 8;          // summed-variable values per load batch
-    constexpr int LPB = (NIN + 1) * WC;         // loads per row and batch
-    // rows whose loads are issued together: up to about 64 loads in flight per wave
-    constexpr int OB = LPB <= 8 ? OC : (LPB <= 16 ? OC / 2 : (LPB <= 32 ? OC / 4 : OC / 8));
+    constexpr int OB = tree_unit_rows(NIN, K);
+    // input rows and factor-table entry of the unit's rows, and the offset of
+    // each summed value w in each input (scalar)
+    int64_t row[OB][NIN], gent[OB], off[NIN][W];
+#pragma unroll
+    for (int t = 0; t < NIN; ++t) {
+        row[0][t] = tk.in_row[t];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            int64_t o = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if ((w >> i) & 1) o += tk.in_vs[t][i];
+            off[t][w] = o * be;
+        }
+    }
+    gent[0] = tk.g_ent;
+#pragma unroll
+    for (int oi = 1; oi < OB; ++oi) {
+        const int j = __builtin_ctz(uint32_t(oi));
+#pragma unroll
+        for (int t = 0; t < NIN; ++t) row[oi][t] = row[oi - 1][t] + tk.in_inc[t][j];
+        gent[oi] = gent[oi - 1] + (int64_t(tk.g_inc[j]) << tk.gshift);
+    }
+    float2 acc[OB];
+#pragma unroll
+    for (int i = 0; i < OB; ++i) acc[i] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w0 = 0; w0 < W; w0 += WC) {
+        float2 a[OB][NIN][WC], q[OB][WC];
+#pragma unroll
+        for (int i = 0; i < OB; ++i)
+#pragma unroll
+            for (int t = 0; t < NIN; ++t) {
+                // an input the bucket does not have reads the constant 1 (same address in every lane)
+                const float2* __restrict__ src = tk.in_row[t] >= 0 ? ain + row[i][t] * be + b : gtab + ones_g;
+#pragma unroll
+                for (int w = 0; w < WC; ++w) a[i][t][w] = src[off[t][w0 + w]];
+            }
+#pragma unroll
+        for (int i = 0; i < OB; ++i)
+#pragma unroll
+            for (int w = 0; w < WC; ++w) q[i][w] = gtab[gent[i] + (int64_t(w0 + w) << tk.sb) + sig];
+#pragma unroll
+        for (int i = 0; i < OB; ++i)
+#pragma unroll
+            for (int w = 0; w < WC; ++w) {
+                float2 pw = q[i][w];
+#pragma unroll
+                for (int t = 0; t < NIN; ++t) pw = cmulf(pw, a[i][t][w]);
+                acc[i].x += pw.x;
+                acc[i].y += pw.y;
+            }
+    }
+    float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b;
+#pragma unroll
+    for (int i = 0; i < OB; ++i) out[int64_t(i) * be] = acc[i];
+}
+
+// A unit of task tk for bitstring group bg (x = the lane's bitstring).
+template <int NIN>
+__device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const float2* __restrict__ ain,
+                                          float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
+                                          uint32_t b, int64_t be) {
+    static_assert(kTreeMaxSum == 3, "tasks sum 1, 2 or 3 variables");
+    const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
+    if (tk.k == 1) tree_unit<NIN, 1>(tk, ain, aout, gtab, ones_g, sig, b, be);
+    else if (tk.k == 2) tree_unit<NIN, 2>(tk, ain, aout, gtab, ones_g, sig, b, be);
+    else tree_unit<NIN, 3>(tk, ain, aout, gtab, ones_g, sig, b, be);
+}
+
+// One level of the elimination tree: wave unit u handles task u / n_bg for
+// the 64 bitstrings of group u % n_bg.  The bitstring is loaded before the
+// task record arrives, so the unit waits on two memory round trips (task and
+// bitstring together, then inputs and factor table together) before its
+// stores.
+template <int NIN>
+__global__ void __launch_bounds__(256) k_tree_level(const TreeTask* __restrict__ tasks, uint32_t n_units,
+                                                    const float2* __restrict__ ain, float2* __restrict__ aout,
+                                                    const float2* __restrict__ gtab, int64_t ones_g,
+                                                    const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                    uint32_t n_bg) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t be = int64_t(B_eff);
     for (uint32_t u = blockIdx.x * 4u + wave; u < n_units; u += gridDim.x * 4u) {
         const uint32_t ti = u / n_bg;
         const uint32_t bg = u - ti * n_bg;
-        const TreeTask tk = tasks[ti];
-        const TreeStepDev sd = steps[tk.step];
         const uint32_t b = bg * 64u + lane;
-        const int64_t sig = sigs[int64_t(sd.sig_row) * be + b];
-        // input rows and factor-table entry of every row of the chunk, and the
-        // row offset of each summed-variable value w in each input (scalar)
-        int64_t row[OC][NIN], gent[OC], off[NIN][W];
-#pragma unroll
-        for (int t = 0; t < NIN; ++t) {
-            row[0][t] = tk.in_row[t];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                int64_t o = 0;
-#pragma unroll
-                for (int i = 0; i < K; ++i)
-                    if ((w >> i) & 1) o += sd.in_vs[t][i];
-                off[t][w] = o * be;
-            }
-        }
-        gent[0] = tk.g_ent;
-#pragma unroll
-        for (int oi = 1; oi < OC; ++oi) {
-            const int j = __builtin_ctz(uint32_t(oi));
-#pragma unroll
-            for (int t = 0; t < NIN; ++t) row[oi][t] = row[oi - 1][t] + sd.in_inc[t][j];
-            gent[oi] = gent[oi - 1] + (int64_t(sd.g_inc[j]) << sd.gshift);
-        }
-        float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b;
-#pragma unroll
-        for (int o0 = 0; o0 < OC; o0 += OB) {
-            float2 acc[OB];
-#pragma unroll
-            for (int i = 0; i < OB; ++i) acc[i] = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int w0 = 0; w0 < W; w0 += WC) {
-                float2 a[OB][NIN][WC], q[OB][WC];
-#pragma unroll
-                for (int i = 0; i < OB; ++i)
-#pragma unroll
-                    for (int t = 0; t < NIN; ++t) {
-                        const float2* __restrict__ src = ain + row[o0 + i][t] * be + b;
-#pragma unroll
-                        for (int w = 0; w < WC; ++w) a[i][t][w] = src[off[t][w0 + w]];
-                    }
-#pragma unroll
-                for (int i = 0; i < OB; ++i)
-#pragma unroll
-                    for (int w = 0; w < WC; ++w) q[i][w] = gtab[gent[o0 + i] + (int64_t(w0 + w) << sd.sb) + sig];
-#pragma unroll
-                for (int i = 0; i < OB; ++i)
-#pragma unroll
-                    for (int w = 0; w < WC; ++w) {
-                        float2 pw = q[i][w];
-#pragma unroll
-                        for (int t = 0; t < NIN; ++t) pw = cmulf(pw, a[i][t][w]);
-                        acc[i].x += pw.x;
-                        acc[i].y += pw.y;
-                    }
-            }
-#pragma unroll
-            for (int i = 0; i < OB; ++i) out[int64_t(o0 + i) * be] = acc[i];
-        }
+        const uint64_t x = int64_t(b) < B ? bits[b] : 0ull;
+        const TreeTask tk = tasks[ti];
+        tree_task<NIN>(tk, x, ain, aout, gtab, ones_g, b, be);
     }
 }
 
-// Amplitude of every bitstring: the phase of the factors without free
-// variables times the rank-0 bucket results, multiplied in FP64.  The phase
-// factors and their four values each are staged in LDS once per block.
-constexpr int kTreeMaxPhaseLds = 512;
+// Phase of the factors without free variables for bitstring x (FP64), from
+// values staged in LDS by stage_phase.
+struct PhaseLds {
+    double2 v[kTreeMaxPhaseLds][4];
+    int32_t q[kTreeMaxPhaseLds][2];   // bit of x feeding each variable (-1: fixed 0)
+};
 
-__global__ void __launch_bounds__(256) k_tree_final(const int64_t* __restrict__ final_rows, int n_final,
-                                                    const TFactor* __restrict__ phase, int n_phase,
-                                                    const double2* __restrict__ fixed, const float2* __restrict__ slots,
-                                                    const float2* __restrict__ arena, const uint64_t* __restrict__ bits,
-                                                    int64_t B, uint32_t B_eff, void* __restrict__ out, int c128) {
-    __shared__ double2 pv[kTreeMaxPhaseLds][4];
-    __shared__ int32_t pq[kTreeMaxPhaseLds][2];   // bit of x feeding each variable (-1: fixed 0)
+__device__ __forceinline__ int stage_phase(PhaseLds& P, const TFactor* __restrict__ phase, int n_phase,
+                                           const double2* __restrict__ fixed, const float2* __restrict__ slots) {
     const int n_lds = n_phase < kTreeMaxPhaseLds ? n_phase : kTreeMaxPhaseLds;
-    for (int i = threadIdx.x; i < n_lds * 4; i += 256) {
+    for (int i = threadIdx.x; i < n_lds * 4; i += blockDim.x) {
         const TFactor f = phase[i >> 2];
-        const uint32_t a = (i >> 1) & 1, c = i & 1;
-        pv[i >> 2][i & 3] = factor_value(f, a, c, fixed, slots);
+        P.v[i >> 2][i & 3] = factor_value(f, (i >> 1) & 1u, i & 1u, fixed, slots);
         if ((i & 3) == 0) {
-            pq[i >> 2][0] = f.src0 == TS_SIG ? f.bit0 : -1;
-            pq[i >> 2][1] = f.src1 == TS_SIG ? f.bit1 : -1;
+            P.q[i >> 2][0] = f.src0 == TS_SIG ? f.bit0 : -1;
+            P.q[i >> 2][1] = f.src1 == TS_SIG ? f.bit1 : -1;
         }
     }
-    __syncthreads();
-    const uint32_t b = blockIdx.x * 256u + threadIdx.x;
-    if (int64_t(b) >= B) return;
-    const uint64_t x = bits[b];
+    return n_lds;
+}
+
+// Amplitude = phase x product of the rank-0 results (FP64), written as complex64 or complex128.
+__device__ __forceinline__ void write_amplitude(const PhaseLds& P, int n_lds, const TFactor* __restrict__ phase,
+                                                int n_phase, const double2* __restrict__ fixed,
+                                                const float2* __restrict__ slots, const int64_t* __restrict__ final_rows,
+                                                int n_final, const float2* __restrict__ arena, uint64_t x, uint32_t b,
+                                                uint32_t B_eff, void* __restrict__ out, int c128) {
     double2 acc = make_double2(1.0, 0.0);
     for (int i = 0; i < n_lds; ++i) {
-        const uint32_t a = pq[i][0] >= 0 ? uint32_t((x >> pq[i][0]) & 1ull) : 0u;
-        const uint32_t c = pq[i][1] >= 0 ? uint32_t((x >> pq[i][1]) & 1ull) : 0u;
-        acc = cmuld(acc, pv[i][a * 2 + c]);
+        const uint32_t a = P.q[i][0] >= 0 ? uint32_t((x >> P.q[i][0]) & 1ull) : 0u;
+        const uint32_t c = P.q[i][1] >= 0 ? uint32_t((x >> P.q[i][1]) & 1ull) : 0u;
+        acc = cmuld(acc, P.v[i][a * 2 + c]);
     }
     for (int i = n_lds; i < n_phase; ++i) {   // beyond the LDS copy: read the records directly
         const TFactor f = phase[i];
@@ -255,52 +302,102 @@ __global__ void __launch_bounds__(256) k_tree_final(const int64_t* __restrict__ 
     else static_cast<float2*>(out)[b] = make_float2(float(acc.x), float(acc.y));
 }
 
-void launch_tree_prologue(const TreeGTab* gtabs, int n_gtabs, uint32_t max_entries, const TFactor* facs,
-                          const double2* fixed, const float2* slots, float2* gtab, const TreeSigTab* sigtabs,
-                          int n_sig, const uint64_t* bits, int64_t B, uint32_t B_eff, uint16_t* sigs, float2* ones,
-                          hipStream_t stream) {
-    const uint32_t ny = uint32_t(n_gtabs + n_sig + 1);
-    const uint32_t nx = std::max<uint32_t>(n_gtabs > 0 ? (max_entries + 255) / 256 : 1, (B_eff + 255) / 256);
-    hipLaunchKernelGGL(k_tree_prologue, dim3(nx, ny), dim3(256), 0, stream, gtabs, n_gtabs, facs, fixed, slots, gtab,
-                       sigtabs, n_sig, bits, B, B_eff, sigs, ones);
+// The last levels of the tree, whose buckets have few rows, in one launch:
+// work-group g owns the 64 bitstrings of group g and runs every task of
+// every tail level for them, its four waves taking the tasks of a level in
+// turn, with a block barrier between levels (a level reads only results of
+// earlier levels, written by waves of the same work-group).  Then the
+// amplitudes: phase x rank-0 results in FP64.
+__global__ void __launch_bounds__(256) k_tree_tail(const TreeTailLevel* __restrict__ levels, int n_levels,
+                                                   const TreeTask* __restrict__ tasks, float2* __restrict__ arena,
+                                                   const float2* __restrict__ gtab, int64_t ones_g,
+                                                   const int64_t* __restrict__ final_rows, int n_final,
+                                                   const TFactor* __restrict__ phase, int n_phase,
+                                                   const double2* __restrict__ fixed, const float2* __restrict__ slots,
+                                                   const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                   void* __restrict__ out, int c128) {
+    __shared__ PhaseLds P;
+    const int n_lds = stage_phase(P, phase, n_phase, fixed, slots);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t be = int64_t(B_eff);
+    const uint32_t b = blockIdx.x * 64u + lane;
+    const uint64_t x = int64_t(b) < B ? bits[b] : 0ull;
+    for (int l = 0; l < n_levels; ++l) {
+        const TreeTailLevel lv = levels[l];
+        for (int t = int(wave); t < lv.n_tasks; t += 4) {
+            const TreeTask tk = tasks[lv.task_off + t];
+            // arena is read and written through the same pointer here: a task
+            // reads only rows of earlier levels, which no task of this level writes
+            if (lv.nin <= 1) tree_task<1>(tk, x, arena, arena, gtab, ones_g, b, be);
+            else if (lv.nin == 2) tree_task<2>(tk, x, arena, arena, gtab, ones_g, b, be);
+            else if (lv.nin == 3) tree_task<3>(tk, x, arena, arena, gtab, ones_g, b, be);
+            else tree_task<4>(tk, x, arena, arena, gtab, ones_g, b, be);
+        }
+        __syncthreads();
+    }
+    if (wave == 0 && int64_t(b) < B)
+        write_amplitude(P, n_lds, phase, n_phase, fixed, slots, final_rows, n_final, arena, x, b, B_eff, out, c128);
 }
 
-template <int NIN, int K>
-static void launch_level_nk(uint32_t grid, hipStream_t stream, const TreeTask* tk, uint32_t n_units,
-                            const TreeStepDev* steps, const float2* ain, float2* aout, const float2* gtab,
-                            const uint16_t* sigs, uint32_t B_eff, uint32_t n_bg) {
-    hipLaunchKernelGGL((k_tree_level<NIN, K>), dim3(grid), dim3(256), 0, stream, tk, n_units, steps, ain, aout, gtab,
-                       sigs, B_eff, n_bg);
+// The amplitudes when the tree has no tail levels.
+__global__ void __launch_bounds__(256) k_tree_final(const int64_t* __restrict__ final_rows, int n_final,
+                                                    const TFactor* __restrict__ phase, int n_phase,
+                                                    const double2* __restrict__ fixed, const float2* __restrict__ slots,
+                                                    const float2* __restrict__ arena, const uint64_t* __restrict__ bits,
+                                                    int64_t B, uint32_t B_eff, void* __restrict__ out, int c128) {
+    __shared__ PhaseLds P;
+    const int n_lds = stage_phase(P, phase, n_phase, fixed, slots);
+    __syncthreads();
+    const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+    if (int64_t(b) >= B) return;
+    write_amplitude(P, n_lds, phase, n_phase, fixed, slots, final_rows, n_final, arena, bits[b], b, B_eff, out, c128);
 }
 
-static_assert(kTreeMaxSum == 3, "launch_tree_level dispatches K = 1 .. 3");
-
-template <int K>
-static void launch_level_k(int nin, uint32_t grid, hipStream_t stream, const TreeTask* tk, uint32_t n_units,
-                           const TreeStepDev* steps, const float2* ain, float2* aout, const float2* gtab,
-                           const uint16_t* sigs, uint32_t B_eff, uint32_t n_bg) {
-    if (nin <= 1) launch_level_nk<1, K>(grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
-    else if (nin == 2) launch_level_nk<2, K>(grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
-    else if (nin == 3) launch_level_nk<3, K>(grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
-    else if (nin == 4) launch_level_nk<4, K>(grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
-    else launch_level_nk<kTreeMaxIn, K>(grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
+void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
+                          const TFactor* facs, const double2* fixed, const float2* slots, float2* gtab,
+                          int64_t ones_g, hipStream_t stream) {
+    if (n_blocks <= 0) return;   // a plan without buckets reads no table
+    hipLaunchKernelGGL(k_tree_prologue, dim3(uint32_t(n_blocks)), dim3(256), 0, stream, blocks, gtabs, groups, facs,
+                       fixed, slots, gtab, ones_g);
 }
 
-void launch_tree_level(int nin, int k, const TreeTask* tasks, int32_t n_tasks, const TreeStepDev* steps,
-                       const float2* ain, float2* aout, const float2* gtab, const uint16_t* sigs, uint32_t B_eff,
-                       hipStream_t stream) {
-    const uint32_t n_bg = B_eff / 64u;
+template <int NIN>
+static void launch_level_n(hipStream_t stream, const TreeTask* tasks, int64_t n_tasks, const float2* ain,
+                           float2* aout, const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B,
+                           uint32_t B_eff, uint32_t n_bg) {
     // launches of at most 2^31 wave units (tasks of one level are independent)
-    const int64_t per = std::max<int64_t>(1, (int64_t(1) << 31) / n_bg);
+    const int64_t per = std::max<int64_t>(1, (int64_t(1) << 31) / int64_t(n_bg));
     for (int64_t t0 = 0; t0 < n_tasks; t0 += per) {
         const int64_t nt = std::min<int64_t>(per, n_tasks - t0);
         const uint32_t n_units = uint32_t(nt * n_bg);
         const uint32_t grid = uint32_t(std::min<int64_t>((int64_t(n_units) + 3) / 4, kStepMaxGrid));
-        const TreeTask* tk = tasks + t0;
-        if (k <= 1) launch_level_k<1>(nin, grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
-        else if (k == 2) launch_level_k<2>(nin, grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
-        else launch_level_k<3>(nin, grid, stream, tk, n_units, steps, ain, aout, gtab, sigs, B_eff, n_bg);
+        hipLaunchKernelGGL(k_tree_level<NIN>, dim3(grid), dim3(256), 0, stream, tasks + t0, n_units, ain, aout, gtab,
+                           ones_g, bits, B, B_eff, n_bg);
     }
+}
+
+void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
+                       const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
+                       hipStream_t stream) {
+    const uint32_t n_bg = B_eff / 64u;
+    if (n_tasks <= 0) return;
+    switch (launch_inputs(nin)) {
+        case 1: launch_level_n<1>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
+        case 2: launch_level_n<2>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
+        case 3: launch_level_n<3>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
+        case 4: launch_level_n<4>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
+        default: launch_level_n<kTreeMaxIn>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg);
+    }
+}
+
+void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask* tasks, float2* arena,
+                      const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,
+                      int n_phase, const double2* fixed, const float2* slots, const uint64_t* bits, int64_t B,
+                      uint32_t B_eff, void* out, bool c128, hipStream_t stream) {
+    hipLaunchKernelGGL(k_tree_tail, dim3(B_eff / 64u), dim3(256), 0, stream, levels, n_levels, tasks, arena, gtab,
+                       ones_g, final_rows, n_final, phase, n_phase, fixed, slots, bits, B, B_eff, out, c128 ? 1 : 0);
 }
 
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,

@@ -17,7 +17,10 @@
 // planner).  Factors without any free
 // variable form a per-bitstring phase, evaluated in FP64 with the final
 // product of the rank-0 results.  Buckets whose inputs are ready run in the
-// same launch (one launch per level of the elimination tree).
+// same launch (one launch per level of the elimination tree); a bucket
+// without inputs is folded into the factor table of the bucket that reads its
+// result, and the last levels, whose buckets have few rows, run in one tail
+// launch with the final product.
 #pragma once
 
 #include <algorithm>
@@ -35,17 +38,33 @@ constexpr int kTreeMaxRank = 28;    // rank of a bucket result
 constexpr int kTreeMaxIn = 8;       // earlier results multiplied in one bucket
 constexpr int kTreeMaxSig = 12;     // output bits read by one bucket's factors
 constexpr int kTreeMaxGBits = 10;   // variables of a bucket's factor table besides v
-constexpr int kTreeMaxGIndex = 20;  // gb + kg + sb
+constexpr int kTreeMaxGIndex = 20;  // gb + k + sb
 constexpr int kTreeMaxSum = 3;      // variables summed by one (merged) bucket: beyond 3 the
                                     // serial load batches of a wave outweigh the saved launch
+constexpr int kTreeTailTasks = 8;   // tail levels: at most this many wave tasks per bitstring group
+constexpr int kTreeTailInputs = 4;  // ... and at most this many inputs per bucket
 constexpr int kTreeOcBits = 3;      // a wave unit covers up to 2^kTreeOcBits consecutive result rows
 constexpr int64_t kTreeMaxTasks = int64_t(1) << 22;   // (bucket, row chunk) records of a plan
+
+// Result rows of one wave unit of a bucket with k summed variables in a
+// launch whose buckets have at most nin inputs: the loads of those rows are
+// issued together (about 64 at most).
+constexpr int tree_unit_rows(int nin, int k) {
+    const int lpb = (nin + 1) * ((1 << k) < 8 ? (1 << k) : 8);   // loads per row and batch of summed values
+    return lpb <= 8 ? 8 : (lpb <= 16 ? 4 : (lpb <= 32 ? 2 : 1));
+}
+static_assert(tree_unit_rows(1, 1) == (1 << kTreeOcBits), "a unit never exceeds the rows reserved per result");
+
+// Inputs of the bucket-kernel variant that runs a level whose buckets have at
+// most n inputs (variants exist for 1, 2, 3, 4 and kTreeMaxIn inputs).
+constexpr int launch_inputs(int n) { return n <= 1 ? 1 : (n <= 4 ? n : 8); }
 
 // Sources of a variable inside a factor of the tree plan.
 enum : int32_t {
     TS_ZERO = 0,   // fixed to 0 (input delta)
     TS_G = 1,      // bit `bit` of the factor-table index c = (g << kg) | w (w: the summed variables)
-    TS_SIG = 2     // output bit: bit `bit` of sigma (bucket factors) or qubit `bit` of x (phase)
+    TS_SIG = 2,    // output bit: bit `bit` of sigma (bucket factors) or qubit `bit` of x (phase)
+    TS_INT = 3     // bit `bit` of a factor group's own summed value (an absorbed bucket's variables)
 };
 
 // Factor types of the tree plan.
@@ -62,21 +81,39 @@ struct TFactor {
     int32_t src1, bit1;
 };
 
+// A group of factors of a bucket's factor table: the table entry is the
+// product over groups of (prod_f f) for k_int = 0, or of
+// (sum over the 2^k_int values of the group's own variables of prod_f f) --
+// a bucket without inputs whose result only one later bucket reads is folded
+// into that bucket's table this way.
+struct TGroup {
+    int k_int = 0;
+    std::vector<int> vars;              // the group's own summed variables (ids), k_int of them
+    std::vector<TFactor> factors;
+};
+
 struct TreeStep {
     std::vector<int> vars;              // variables summed out (a merged chain sums up to kTreeMaxSum)
-    int kg = 1;                         // summed-variable bits of the table index: the level's most
+    int kg = 1;                         // summed-variable bits of the table index (= vars.size())
     int level = 0;                      // level in the elimination tree (0: no earlier result)
     int out_tensor = -1;                // id of the result
     std::vector<int> out_axes;          // result axes (variables), elimination position ascending
     std::vector<int> in_tensors;        // earlier results multiplied in
     std::vector<int> gvars;             // factor-table variables besides the summed ones (index bits kg..)
     std::vector<int> sig_q;             // sigma bit i = output bit of qubit sig_q[i]
-    std::vector<TFactor> factors;       // gate factors of the bucket (none: G = 1)
+    std::vector<TGroup> groups;         // factor groups: [0] the bucket's own gate factors, then absorbed buckets
+    int n_factors() const {
+        int n = 0;
+        for (auto& g : groups) n += int(g.factors.size());
+        return n;
+    }
     int64_t g_off = 0;                  // complex offset in the factor-table area
-    int sig_row = -1;                   // row of the per-call sigma table (-1: reads no output bit)
-    int64_t task_off = 0;               // first wave task (row chunk) of this bucket
-    int oc_bits() const { return std::min(int(out_axes.size()), kTreeOcBits); }
-    int64_t n_tasks() const { return int64_t(1) << (int(out_axes.size()) - oc_bits()); }
+    int64_t task_off = 0;               // first wave task of this bucket
+    int unit_rows = 1;                  // result rows per wave task (tree_unit_rows of its launch)
+    int64_t n_tasks() const {
+        const int64_t rows = int64_t(1) << out_axes.size();
+        return rows <= unit_rows ? 1 : rows / unit_rows;
+    }
     int gb() const { return int(gvars.size()); }
     int sb() const { return int(sig_q.size()); }
     int64_t g_entries() const { return int64_t(1) << (gb() + kg + sb()); }
@@ -94,9 +131,12 @@ struct TreePlan {
     std::vector<int64_t> level_task_off;         // wave tasks of level L: [off[L], off[L + 1])
     std::vector<int> level_max_in;               // most inputs of a bucket in level L
     int64_t n_tasks = 0;
-    int n_sig_rows = 0;                          // sigma rows, the last one all zero (buckets without output bits)
-    int64_t ones_row = 0;                        // arena row of constant 1 (inputs a bucket does not have)
-    std::vector<int> level_k;                    // most summed variables of a bucket in level L
+    int64_t ones_g = 0;                          // factor-table entry holding the constant 1 that a wave reads
+                                                 //   (lane stride 0) for inputs its bucket does not have
+    int n_absorbed = 0;                          // buckets without inputs folded into a later bucket's table
+    int first_level = 1;                         // first level with buckets (0 unless every level-0 bucket
+                                                 //   was absorbed)
+    int tail_start = 0;                          // levels [tail_start, n_levels) run in the tail kernel
     int64_t arena_rows = 0;
     int64_t g_total = 0;
     int max_rank = 0;

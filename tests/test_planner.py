@@ -233,7 +233,10 @@ def test_tree_plan_is_deterministic_and_consistent():
     a = Q.plan(c, ordering=1).info(1)
     b = Q.plan(c, ordering=1).info(1)
     assert a == b
-    assert sorted(a["order"]) == sorted(v for s in a["buckets"] for v in s["vars"])
+    summed = [v for s in a["buckets"] for v in s["vars"]]
+    summed += [v for s in a["buckets"] for g in s["groups"] for v in g["vars"]]   # absorbed buckets
+    assert sorted(a["order"]) == sorted(summed)
+    assert a["absorbed_buckets"] == sum(len(s["groups"]) - 1 for s in a["buckets"]) > 0
     assert a["n_free"] == len(a["order"])
     assert abs(sum(s["bytes_per_b"] for s in a["buckets"]) - a["bytes_per_amp"]) < 1e-6 * a["bytes_per_amp"]
     # every result is read by exactly one later bucket or by the final product
@@ -282,4 +285,4 @@ def test_chain_merge_shortens_the_tree():
         assert b["bytes_per_amp"] < a["bytes_per_amp"]
         assert max(len(s["vars"]) for s in b["buckets"]) <= 3
         for s in b["buckets"]:
-            assert s["kg"] >= len(s["vars"])
+            assert s["kg"] == len(s["vars"])

@@ -1,8 +1,9 @@
 """CPU interpreter of a bucket-elimination plan (ordering 1), complex128.
 
-It executes the planner's output -- bucket factor lists, summed variables
-(several for a merged chain), axis layouts, variant bits, tree levels and
-arena rows -- with the semantics the HIP bucket kernels implement, so the planner can be checked against the oracle without a
+It executes the planner's output -- bucket factor groups (a bucket without
+inputs folded into its reader's table), summed variables (several for a
+merged chain), axis layouts, variant bits, tree levels and arena rows -- with
+the semantics the HIP bucket kernels implement, so the planner can be checked against the oracle without a
 GPU.  Results live in a simulated arena: every row remembers which result
 wrote it, a read checks that the row still holds that result, and a level's
 writes may not land on rows of a result that the level (or a later one) still
@@ -12,7 +13,7 @@ import numpy as np
 
 from oracle.gates import gate_matrix
 
-TS_ZERO, TS_G, TS_SIG = 0, 1, 2
+TS_ZERO, TS_G, TS_SIG, TS_INT = 0, 1, 2, 3
 TF_MAT, TF_DIAG, TF_CZ, TF_DELTA0 = 0, 1, 2, 3
 
 
@@ -34,23 +35,31 @@ def _factor(f, a, b, gate_vals):
 
 
 def bucket_table(st, gate_vals):
-    """G of a bucket as [2^(gb+kg) (index c = (g << kg) | w), 2^sb]; entries
-    whose w has bits beyond the bucket's k summed variables are 0."""
-    gb, sb, kg, k = st["gb"], st["sb"], st["kg"], len(st["vars"])
+    """G of a bucket as [2^(gb+kg) (index c = (g << kg) | w), 2^sb]: the product
+    over its factor groups of (product of the group's factors), summed over the
+    group's own variables (TS_INT) for an absorbed bucket."""
+    gb, sb, kg = st["gb"], st["sb"], st["kg"]
     c = np.arange(1 << (gb + kg))[:, None]
     sig = np.arange(1 << sb)[None, :]
     acc = np.ones((1 << (gb + kg), 1 << sb), dtype=np.complex128)
-    acc[((c[:, 0] & ((1 << kg) - 1)) >> k) != 0] = 0
 
-    def val(src, bit):
+    def val(src, bit, iv):
         if src == TS_G:
             return ((c >> bit) & 1) + 0 * sig
         if src == TS_SIG:
             return ((sig >> bit) & 1) + 0 * c
+        if src == TS_INT:
+            return ((iv >> bit) & 1) + 0 * (c + sig)
         return np.zeros_like(c + sig)
 
-    for f in st["factors"]:
-        acc = acc * _factor(f, val(f[2], f[3]), val(f[4], f[5]), gate_vals)
+    for grp in st["groups"]:
+        total = np.zeros_like(acc)
+        for iv in range(1 << grp["k"]):
+            term = np.ones_like(acc)
+            for f in grp["factors"]:
+                term = term * _factor(f, val(f[2], f[3], iv), val(f[4], f[5], iv), gate_vals)
+            total += term
+        acc = acc * total
     return acc
 
 

@@ -492,7 +492,8 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
       << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
-      << ",\"launches\":" << (1 + std::max(t.tail_start - t.first_level, 0) + 1)
+      << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start
+      << ",\"level_launches\":" << (std::max(t.tail_start - t.first_level, 0) + (t.tail_start < int(t.levels.size()) ? 1 : 0))
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b

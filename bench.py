@@ -281,21 +281,52 @@ def extras(Q, C, torch, np, stream, args):
                                   "ms_per_call": round(ms, 4), "bytes_per_amp": info["bytes_per_amp"],
                                   "max_rank": info["max_rank"], "roofline": rf}
     print(f"# ordering {other}: {ms:.3f} ms per call, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
-    # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2 (vertical order)
+    # batch scaling of the bucket path on the default circuit: larger batches give the level kernels
+    # enough wave units to approach the HBM roof
+    c, _ = C.workload(args.workload)
+    p = Q.plan(c, ordering=1)
+    info = p.info(0)
+    scale = {}
+    for Bs in (4096, 16384, 65536):
+        bs = C.random_bitstrings(c.n, Bs, 77)
+        bd = torch.from_numpy(bs.view(np.int64)).to(dev)
+        o = torch.empty((Bs, 1), dtype=torch.complex64, device=dev)
+        w = torch.empty(p.workspace_bytes(Bs), dtype=torch.uint8, device=dev)
+        g = Q.Graph([p], [bd])
+        ms = _time(lambda: g.launch(stream), 10, stream, torch)
+        p.set_timing(True)
+        for _ in range(5):
+            p.amplitudes(bd, None, out=o, workspace=w, stream=stream)
+        torch.cuda.synchronize()
+        ph, nc = p.timings()
+        p.set_timing(False)
+        rf, _ = dominant_kernel(argparse.Namespace(workload="", kernel_policy=0, no_autotune=True), p, info, Bs,
+                                ph[2] / max(nc, 1), None)
+        scale[str(Bs)] = {"amplitudes_per_sec": round(Bs / (ms / 1e3), 1), "ms_per_call": round(ms, 4),
+                          "roofline_frac": rf["frac"], "achieved_GBps": rf["achieved"]}
+        print(f"# ordering 1 B={Bs}: {ms:.3f} ms, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
+        del g, w, o
+    out["ordering_1_batch_scaling"] = {"workload": f"{args.workload} with B uniform bitstrings (seed 77), graph replay",
+                                       **scale}
+    # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2
     c, bits = C.workload("c4_5x5_d20_U")
-    p = Q.plan(c)
     gv = torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
     bd = torch.from_numpy(bits.view(np.int64)).to(dev)
-    amps = p.amplitudes(bd, gv)
-    gamps = (2.0 / torch.conj(amps)).contiguous()
-    ws = torch.empty(p.backward_workspace_bytes(len(bits)), dtype=torch.uint8, device=dev)
-    ms = _time(lambda: p.backward(bd, gamps, gv, workspace=ws, stream=stream), 10, stream, torch)
-    msf = _time(lambda: p.amplitudes(bd, gv, stream=stream), 10, stream, torch)
     out["c4_grad"] = {"workload": "5x5 depth 20, every 1q gate U(theta, n), 256 bitstrings, d(sum log p)/dU for "
-                                  f"{c.n_slots} gate tensors, checkpointed", "grad_evals_per_sec": round(1e3 / ms, 2),
-                      "ms_per_grad_eval": round(ms, 4), "ms_forward_only": round(msf, 4)}
-    print(f"# c4 gradient: {ms:.3f} ms per evaluation (forward alone {msf:.3f} ms)", file=sys.stderr, flush=True)
-    del ws
+                                  f"{c.n_slots} gate tensors (one backward call: forward, seed, adjoint)"}
+    for ordering in (1, 0):
+        p = Q.plan(c, ordering=ordering)
+        amps = p.amplitudes(bd, gv)
+        gamps = (2.0 / torch.conj(amps)).contiguous()
+        ws = torch.empty(p.backward_workspace_bytes(len(bits)), dtype=torch.uint8, device=dev)
+        ms = _time(lambda: p.backward(bd, gamps, gv, workspace=ws, stream=stream), 10, stream, torch)
+        msf = _time(lambda: p.amplitudes(bd, gv, stream=stream), 10, stream, torch)
+        out["c4_grad"]["ordering_%d" % ordering] = {"grad_evals_per_sec": round(1e3 / ms, 2),
+                                                    "ms_per_grad_eval": round(ms, 4),
+                                                    "ms_forward_only": round(msf, 4)}
+        print(f"# c4 gradient ordering {ordering}: {ms:.3f} ms per evaluation (forward alone {msf:.3f} ms)",
+              file=sys.stderr, flush=True)
+        del ws
     # plain per-bitstring baseline: the default workload's plan called with B = 1
     # in a host loop (no graph; B is padded to one 64-wide wave)
     c, bits = C.workload(args.workload)

@@ -39,6 +39,14 @@ struct qgm_plan_s {
     int n_gtabs = 0;
     size_t off_tpro = 0, off_tg = 0;   // prologue block list; factor tables of a plan without gate values
     int n_pro_blocks = 0;
+    // tree plans, adjoint: keep-all tasks and final rows, per-bucket records, per-level item lists, slot lists
+    size_t off_ttasks_all = 0, off_tfinal_all = 0, off_tbwd = 0, off_tbwdin = 0, off_tbwdg = 0, off_titems = 0;
+    size_t off_tslot_off = 0, off_tslot_occ = 0;
+    struct LevelItems { int off = 0, n = 0; int64_t rows = 0; };
+    std::vector<LevelItems> lv_exp, lv_in, lv_g;
+    std::vector<qgm::TreeBwdItem> items;
+    std::vector<int32_t> slot_off_t, slot_occ_t;
+    int64_t n_fbar = 0;
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -99,7 +107,157 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tfinal = P->off_tphase + al(sizeof(qgm::TFactor) * (t.phase.size() + 1));
     P->off_tpro = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
     P->off_tg = P->off_tpro + al(sizeof(qgm::TreeProBlock) * size_t(P->n_pro_blocks + 1));
-    P->total = P->off_tg + (P->p.n_slots == 0 ? al(sizeof(float2) * size_t(t.g_total)) : 0);
+    // adjoint records and item lists (level by level: expansion, input adjoints, table adjoints)
+    size_t n_in_total = 0;
+    for (auto& st : t.steps) n_in_total += st.in_tensors.size();
+    P->items.clear();
+    P->lv_exp.assign(t.levels.size(), {});
+    P->lv_in.assign(t.levels.size(), {});
+    P->lv_g.assign(t.levels.size(), {});
+    {
+        int in_idx = 0;
+        std::vector<int> in_base(t.steps.size(), 0);
+        for (size_t s = 0; s < t.steps.size(); ++s) { in_base[s] = in_idx; in_idx += int(t.steps[s].in_tensors.size()); }
+        for (size_t L = 0; L < t.levels.size(); ++L) {
+            auto add = [&](qgm_plan_s::LevelItems& li, int idx, int64_t rows) {
+                if (li.n == 0) li.off = int(P->items.size());
+                P->items.push_back({idx, int32_t(li.rows)});
+                li.rows += rows;
+                li.n++;
+            };
+            for (int sid : t.levels[L]) {
+                const qgm::TreeStep& st = t.steps[sid];
+                add(P->lv_exp[L], sid, int64_t(1) << (st.out_axes.size() + st.vars.size()));
+            }
+            for (int sid : t.levels[L]) {
+                const qgm::TreeStep& st = t.steps[sid];
+                for (size_t k = 0; k < st.in_tensors.size(); ++k)
+                    add(P->lv_in[L], in_base[sid] + int(k), int64_t(1) << t.tensor_axes[st.in_tensors[k]].size());
+            }
+            for (int sid : t.levels[L]) {
+                const qgm::TreeStep& st = t.steps[sid];
+                add(P->lv_g[L], sid, int64_t(1) << (st.gb() + st.kg));
+            }
+        }
+    }
+    // gate-slot occurrences among the table factors and the phase factors
+    {
+        std::vector<std::vector<int32_t>> occ(std::max(P->p.n_slots, 0));
+        int gi = 0;
+        auto note = [&](const qgm::TFactor& f, int index) {
+            if ((f.type == qgm::TF_MAT || f.type == qgm::TF_DIAG) && f.mat >= qgm::kFixedMats)
+                occ[f.mat - qgm::kFixedMats].push_back(int32_t(index) * 2 + (f.type == qgm::TF_DIAG ? 1 : 0));
+        };
+        for (auto& st : t.steps)
+            for (auto& g : st.groups)
+                for (auto& f : g.factors) note(f, gi++);
+        P->n_fbar = gi + int64_t(t.phase.size());
+        for (size_t i = 0; i < t.phase.size(); ++i) note(t.phase[i], gi + int(i));
+        P->slot_off_t.assign(1, 0);
+        P->slot_occ_t.clear();
+        for (auto& v : occ) {
+            for (int32_t x : v) P->slot_occ_t.push_back(x);
+            P->slot_off_t.push_back(int32_t(P->slot_occ_t.size()));
+        }
+    }
+    const size_t g_bytes = P->p.n_slots == 0 ? al(sizeof(float2) * size_t(t.g_total)) : 0;
+    P->off_ttasks_all = P->off_tg + g_bytes;
+    P->off_tfinal_all = P->off_ttasks_all + al(sizeof(qgm::TreeTask) * size_t(t.n_tasks + 1));
+    P->off_tbwd = P->off_tfinal_all + al(sizeof(int64_t) * (t.finals.size() + 1));
+    P->off_tbwdin = P->off_tbwd + al(sizeof(qgm::TreeBwd) * (t.steps.size() + 1));
+    P->off_tbwdg = P->off_tbwdin + al(sizeof(qgm::TreeBwdIn) * (n_in_total + 1));
+    P->off_titems = P->off_tbwdg + al(sizeof(qgm::TreeBwdG) * (t.steps.size() + 1));
+    P->off_tslot_off = P->off_titems + al(sizeof(qgm::TreeBwdItem) * (P->items.size() + 1));
+    P->off_tslot_occ = P->off_tslot_off + al(sizeof(int32_t) * (P->slot_off_t.size() + 1));
+    P->total = P->off_tslot_occ + al(sizeof(int32_t) * (P->slot_occ_t.size() + 1));
+}
+
+// Adjoint tables: the forward tasks with every result at its own rows
+// (keep-all layout), the per-bucket expansion records, the input-adjoint and
+// table-adjoint records, the level item lists and the gate-slot lists.
+void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
+    const qgm::TreePlan& t = P->p.tree;
+    const auto* tasks = reinterpret_cast<const qgm::TreeTask*>(h + P->off_ttasks);
+    auto* tasks_all = reinterpret_cast<qgm::TreeTask*>(h + P->off_ttasks_all);
+    // keep-all rows: every row of the forward layout is relocated by its tensor
+    std::vector<int64_t> shift(t.tensor_axes.size());
+    for (size_t i = 0; i < shift.size(); ++i) shift[i] = t.tensor_row_all[i] - t.tensor_row[i];
+    for (size_t sid = 0; sid < t.steps.size(); ++sid) {
+        const qgm::TreeStep& st = t.steps[sid];
+        for (int64_t c = 0; c < st.n_tasks(); ++c) {
+            qgm::TreeTask tk = tasks[st.task_off + c];
+            tk.out_row = int32_t(tk.out_row + shift[st.out_tensor]);
+            for (size_t k = 0; k < st.in_tensors.size(); ++k)
+                tk.in_row[k] = int32_t(tk.in_row[k] + shift[st.in_tensors[k]]);
+            tasks_all[st.task_off + c] = tk;
+        }
+    }
+    auto* fa = reinterpret_cast<int64_t*>(h + P->off_tfinal_all);
+    for (size_t i = 0; i < t.finals.size(); ++i) fa[i] = t.tensor_row_all[t.finals[i]];
+    auto* bw = reinterpret_cast<qgm::TreeBwd*>(h + P->off_tbwd);
+    auto* bi = reinterpret_cast<qgm::TreeBwdIn*>(h + P->off_tbwdin);
+    auto* bg = reinterpret_cast<qgm::TreeBwdG*>(h + P->off_tbwdg);
+    int in_idx = 0;
+    for (size_t sid = 0; sid < t.steps.size(); ++sid) {
+        const qgm::TreeStep& st = t.steps[sid];
+        const int r = int(st.out_axes.size()), k = st.kg;
+        // a-bit of a variable: summed variable i -> i, result axis j -> k + j
+        auto abit = [&](int var) {
+            for (int i = 0; i < k; ++i) if (st.vars[i] == var) return i;
+            for (int j = 0; j < r; ++j) if (st.out_axes[j] == var) return k + j;
+            return -1;
+        };
+        qgm::TreeBwd d{};
+        d.n_in = int32_t(st.in_tensors.size());
+        d.k = k;
+        d.r = r;
+        d.sb = st.sb();
+        d.a_bits = r + k;
+        d.out_row = int32_t(t.tensor_row_all[st.out_tensor]);
+        d.scratch_row = t.scratch_row[sid];
+        d.g_off = st.g_off;
+        for (int b = 0; b < st.sb(); ++b) d.sig_q[b] = st.sig_q[b];
+        for (int i = 0; i < k; ++i) d.g_str[i] = 1 << i;
+        for (int j = 0; j < r; ++j)
+            for (int p = 0; p < st.gb(); ++p)
+                if (st.out_axes[j] == st.gvars[p]) d.g_str[k + j] = 1 << (k + p);
+        const int64_t arows = int64_t(1) << d.a_bits;
+        for (int ti = 0; ti < d.n_in; ++ti) {
+            const int tid = st.in_tensors[ti];
+            const std::vector<int>& ax = t.tensor_axes[tid];
+            d.in_row[ti] = int32_t(t.tensor_row_all[tid]);
+            qgm::TreeBwdIn e{};
+            e.r_t = int32_t(ax.size());
+            e.dst_row = int32_t(t.tensor_row_all[tid]);
+            e.q_row = d.scratch_row + (1 + ti) * arows;
+            std::vector<bool> used(d.a_bits, false);
+            for (int p = 0; p < int(ax.size()); ++p) {
+                const int ab = abit(ax[p]);
+                d.in_str[ti][ab] = 1 << p;
+                e.pos[p] = ab;
+                used[ab] = true;
+            }
+            for (int i = 0; i < d.a_bits; ++i)
+                if (!used[i]) e.free_bits[e.n_free++] = i;
+            bi[in_idx++] = e;
+        }
+        bw[sid] = d;
+        qgm::TreeBwdG g{};
+        g.c_bits = st.gb() + k;
+        g.sb = st.sb();
+        g.h_row = d.scratch_row;
+        g.g_off = st.g_off;
+        for (int b = 0; b < st.sb(); ++b) g.sig_q[b] = st.sig_q[b];
+        for (int i = 0; i < k; ++i) g.cpos[i] = i;
+        for (int p = 0; p < st.gb(); ++p) g.cpos[k + p] = abit(st.gvars[p]);
+        for (int j = 0; j < r; ++j)
+            if (std::find(st.gvars.begin(), st.gvars.end(), st.out_axes[j]) == st.gvars.end())
+                g.free_bits[g.n_free++] = k + j;
+        bg[sid] = g;
+    }
+    std::memcpy(h + P->off_titems, P->items.data(), sizeof(qgm::TreeBwdItem) * P->items.size());
+    std::memcpy(h + P->off_tslot_off, P->slot_off_t.data(), sizeof(int32_t) * P->slot_off_t.size());
+    std::memcpy(h + P->off_tslot_occ, P->slot_occ_t.data(), sizeof(int32_t) * P->slot_occ_t.size());
 }
 
 // Device records of the buckets: the row stride of every result bit and
@@ -184,6 +342,7 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
             tasks[st.task_off + c] = tk;
         }
     }
+    fill_tree_adjoint_tables(P, h);
     auto* tl = reinterpret_cast<qgm::TreeTailLevel*>(h + P->off_ttail);
     for (size_t L = size_t(t.tail_start); L < t.levels.size(); ++L) {
         qgm::TreeTailLevel x{};
@@ -355,6 +514,27 @@ qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
     gp.n_rc = int32_t(n_rc);
     gp.rc_rows = int32_t((int64_t(1) << gp.n_free) / n_rc);
     return gp;
+}
+
+// Workspace of qgm_backward for a tree plan: the keep-all arena, the adjoint
+// arena, the factor tables (circuits with gate values), the expansion
+// scratch, the table adjoints (FP64) and the factor adjoints (FP64).
+struct TreeBwdLayout {
+    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, gbar = 0, fbar = 0, total = 0;
+};
+
+TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
+    const qgm::TreePlan& t = P->p.tree;
+    const uint64_t be = uint64_t(qgm::padded_batch(B));
+    TreeBwdLayout L;
+    L.arena = 0;
+    L.adj = al(uint64_t(t.arena_rows_all) * be * 8);
+    L.g = 2 * L.adj;
+    L.scratch = L.g + (P->p.n_slots > 0 ? al(uint64_t(t.g_total) * 8) : 0);
+    L.gbar = L.scratch + al(uint64_t(t.scratch_rows) * be * 8);
+    L.fbar = L.gbar + al(uint64_t(t.g_total) * 16);
+    L.total = L.fbar + al(uint64_t(P->n_fbar) * 4 * 16 + 16);
+    return L;
 }
 
 struct BwdLayout {
@@ -558,6 +738,76 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     return QGM_OK;
 }
 
+// qgm_backward for a tree plan: forward with every result kept, seed, then
+// the buckets' adjoints level by level in reverse, then the gate gradients.
+static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
+                                const void* grad_amps, void* amps_out, void* gate_grads, void* workspace,
+                                uint64_t ws_bytes, void* stream) {
+    const qgm::Plan& p = plan->p;
+    const qgm::TreePlan& t = p.tree;
+    if (B == 0) return QGM_OK;
+    if (!bits || !grad_amps || !workspace || (p.n_slots > 0 && (!gate_vals || !gate_grads)))
+        return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "
+                                   "must be device pointers");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
+    const int64_t B_eff = qgm::padded_batch(B);
+    if (B_eff > (int64_t(1) << 26)) return fail(QGM_E_UNSUPPORTED, "batch exceeds 2^26");
+    const TreeBwdLayout L = tree_backward_layout(plan, B);
+    if (ws_bytes < L.total) return fail(QGM_E_OOM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    char* tables = nullptr;
+    qgm_status st = device_tables(plan, &tables);
+    if (st != QGM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    auto* arena = reinterpret_cast<float2*>(ws + L.arena);
+    auto* adj = reinterpret_cast<float2*>(ws + L.adj);
+    auto* scratch = reinterpret_cast<float2*>(ws + L.scratch);
+    auto* gbar = reinterpret_cast<double2*>(ws + L.gbar);
+    auto* fbar = reinterpret_cast<double2*>(ws + L.fbar);
+    float2* gt = p.n_slots > 0 ? reinterpret_cast<float2*>(ws + L.g) : reinterpret_cast<float2*>(tables + plan->off_tg);
+    const auto* fixed = reinterpret_cast<const double2*>(tables + plan->off_fixed);
+    const auto* slots = static_cast<const float2*>(gate_vals);
+    const auto* facs = reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tfac);
+    const auto* pro = reinterpret_cast<const qgm::TreeProBlock*>(tables + plan->off_tpro);
+    const auto* gtabs = reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab);
+    const auto* groups = reinterpret_cast<const qgm::TreeGroup*>(tables + plan->off_tgroup);
+    const auto* tasks_all = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks_all);
+    const auto* items = reinterpret_cast<const qgm::TreeBwdItem*>(tables + plan->off_titems);
+    const uint32_t be = uint32_t(B_eff);
+    if (p.n_slots > 0) qgm::launch_tree_prologue(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gt, t.ones_g, s);
+    for (int Lv = t.first_level; Lv < int(t.levels.size()); ++Lv) {
+        const int64_t t0 = t.level_task_off[Lv], t1 = t.level_task_off[Lv + 1];
+        qgm::launch_tree_level(t.level_max_in[Lv], tasks_all + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
+                               B, be, s);
+    }
+    const int64_t n_fbar4 = plan->n_fbar * 4;
+    qgm::launch_tb_zero(fbar, n_fbar4, s);
+    qgm::launch_tb_seed(reinterpret_cast<const int64_t*>(tables + plan->off_tfinal_all), int(t.finals.size()),
+                        reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tphase), int(t.phase.size()), fixed,
+                        slots, arena, adj, bits, B, be, static_cast<const float2*>(grad_amps), amps_out,
+                        p.opts.out_c128 != 0, fbar + (plan->n_fbar - int64_t(t.phase.size())) * 4, s);
+    const auto* bwd = reinterpret_cast<const qgm::TreeBwd*>(tables + plan->off_tbwd);
+    const auto* bin = reinterpret_cast<const qgm::TreeBwdIn*>(tables + plan->off_tbwdin);
+    const auto* bgd = reinterpret_cast<const qgm::TreeBwdG*>(tables + plan->off_tbwdg);
+    for (int Lv = int(t.levels.size()) - 1; Lv >= t.first_level; --Lv) {
+        const auto& ex = plan->lv_exp[Lv];
+        const auto& in = plan->lv_in[Lv];
+        const auto& gg = plan->lv_g[Lv];
+        qgm::launch_tb_expand(items + ex.off, ex.n, ex.rows, bwd, arena, adj, gt, scratch, bits, B, be, s);
+        if (in.n > 0) qgm::launch_tb_reduce_in(items + in.off, in.n, in.rows, bin, scratch, adj, be, s);
+        if (p.n_slots > 0) qgm::launch_tb_gbar(items + gg.off, gg.n, gg.rows, bgd, scratch, bits, B, be, gbar, s);
+    }
+    if (p.n_slots > 0) {
+        qgm::launch_tb_gadj(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gbar, fbar, s);
+        qgm::launch_tb_slots(reinterpret_cast<const int32_t*>(tables + plan->off_tslot_off),
+                             reinterpret_cast<const int32_t*>(tables + plan->off_tslot_occ), p.n_slots, fbar,
+                             static_cast<float2*>(gate_grads), s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
 extern "C" {
 
 qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
@@ -569,8 +819,7 @@ qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint6
     g_err.clear();
     if (!plan || !bytes) return fail(QGM_E_INVALID, "plan or bytes is NULL");
     if (B < 0) return fail(QGM_E_INVALID, "B < 0");
-    if (plan->p.is_tree) return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a plan with ordering 0");
-    *bytes = backward_layout(plan, B).total;
+    *bytes = plan->p.is_tree ? tree_backward_layout(plan, B).total : backward_layout(plan, B).total;
     return QGM_OK;
 }
 
@@ -581,7 +830,8 @@ qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
     if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
     if (B < 0) return fail(QGM_E_INVALID, "B < 0");
     const qgm::Plan& p = plan->p;
-    if (p.is_tree) return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a plan with ordering 0");
+    if (p.is_tree) return tree_backward(plan, gate_vals, bits, B, grad_amps, amps_out, gate_grads, workspace, ws_bytes,
+                                        stream);
     if (B == 0) return QGM_OK;
     if (!bits || !grad_amps || !workspace || (p.n_slots > 0 && (!gate_vals || !gate_grads)))
         return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "

@@ -83,6 +83,52 @@ struct TreeTailLevel {
     int32_t task_off, n_tasks, nin, pad;
 };
 
+// ---- adjoint of a bucket plan (qgm_backward with ordering 1) ----
+// The adjoint keeps every forward result (each result at its own rows of a
+// "keep-all" arena) and writes each result's adjoint at the same rows of an
+// adjoint arena.  A bucket's index space is a = (o << k) | w: its result bits o
+// and its summed bits w.
+constexpr int kTreeMaxABits = 31;
+
+struct TreeBwd {
+    int32_t n_in, k, r, sb;
+    int32_t a_bits, pad0;
+    int32_t out_row;                            // keep-all row of the result and of its adjoint
+    int32_t pad1;
+    int64_t scratch_row;                        // H at [row, row + 2^a_bits), then Q_t for each input t
+    int64_t g_off;                              // factor table base entry
+    int32_t sig_q[kTreeMaxSig];
+    int32_t in_row[kTreeMaxIn];                 // keep-all rows of the inputs
+    int32_t in_str[kTreeMaxIn][32];             // row stride of a-bit i in input t
+    int32_t g_str[32];                          // factor-table index stride of a-bit i (c units)
+};
+
+// Adjoint of input t of a bucket: the sum over the a-bits that are not axes of t.
+struct TreeBwdIn {
+    int32_t r_t, n_free;
+    int32_t dst_row;                            // keep-all adjoint row of input t
+    int32_t pad;
+    int64_t q_row;                              // scratch row of Q_t
+    int32_t pos[32];                            // a-bit of t's axis p
+    int32_t free_bits[32];                      // a-bits that are not axes of t
+};
+
+// Adjoint of a bucket's factor table, one table row c per block.
+struct TreeBwdG {
+    int32_t c_bits, n_free, sb, pad;            // c_bits = gb + k
+    int64_t h_row;                              // scratch row of H
+    int64_t g_off;                              // table base entry (the table adjoint has the same layout)
+    int32_t sig_q[kTreeMaxSig];
+    int32_t cpos[32];                           // a-bit of table-index bit i
+    int32_t free_bits[32];                      // a-bits outside the table index
+};
+
+// A list entry of one adjoint launch: descriptor index and its first row.
+struct TreeBwdItem {
+    int32_t idx;
+    int32_t row0;
+};
+
 constexpr uint32_t kStepMaxGrid = 8192;           // work-groups of the step kernel (grid-stride beyond)
 constexpr uint32_t kDenseMaxGrid = 4096;          // work-groups of the matrix-core step kernel
 constexpr size_t kStepLdsBytes = 48 * 1024;       // G up to this size is staged in LDS
@@ -120,6 +166,24 @@ void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask*
                       const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,
                       int n_phase, const double2* fixed, const float2* slots, const uint64_t* bits, int64_t B,
                       uint32_t B_eff, void* out, bool c128, hipStream_t stream);
+void launch_tb_zero(double2* p, int64_t n, hipStream_t stream);
+void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
+                    const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,
+                    uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* fbar_phase,
+                    hipStream_t stream);
+void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwd* bwd,
+                      const float2* arena, const float2* adj, const float2* gtab, float2* scratch,
+                      const uint64_t* bits, int64_t B, uint32_t B_eff, hipStream_t stream);
+void launch_tb_reduce_in(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
+                         const float2* scratch, float2* adj, uint32_t B_eff, hipStream_t stream);
+void launch_tb_gbar(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg,
+                    const float2* scratch, const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar,
+                    hipStream_t stream);
+void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
+                    const TFactor* facs, const double2* fixed, const float2* slots, const double2* gbar,
+                    double2* fbar, hipStream_t stream);
+void launch_tb_slots(const int32_t* slot_off, const int32_t* slot_occ, int n_slots, const double2* fbar,
+                     float2* grads, hipStream_t stream);
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                        const float2* slots, const float2* arena, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        void* out, bool c128, hipStream_t stream);

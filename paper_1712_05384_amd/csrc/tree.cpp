@@ -301,6 +301,7 @@ int absorb_leaves(const Plan& p, const Model& m, std::vector<RStep>& steps, std:
         RStep& lf = steps[i];
         if (!lf.alive || !lf.ins.empty() || !lf.absorbed.empty() || reader[lf.out_tensor] < 0) continue;
         RStep& par = steps[reader[lf.out_tensor]];
+        if (par.absorbed.size() >= 15) continue;   // a table has at most 16 factor groups
         par.absorbed.push_back({lf.vars, lf.facs});
         group_table_vars(p, m, par, gset, sigq);
         const int n_in = int(par.ins.size()) - 1;
@@ -584,7 +585,28 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         if (nt > kTreeTailTasks || launch_inputs(t.level_max_in[L]) > kTreeTailInputs) break;
         t.tail_start = L;
     }
-    if (t.n_tasks > kTreeMaxTasks || t.arena_rows >= (int64_t(1) << 31) || t.g_total >= (int64_t(1) << 31)) {
+    // adjoint layout: each result at its own rows; per level, the expansion scratch of its buckets
+    t.tensor_row_all.assign(T, 0);
+    t.arena_rows_all = 0;
+    for (int i = 0; i < T; ++i) {
+        t.tensor_row_all[i] = t.arena_rows_all;
+        t.arena_rows_all += alloc_rows(i);
+    }
+    t.scratch_row.assign(t.steps.size(), 0);
+    t.scratch_rows = 0;
+    for (auto& lvl : t.levels) {
+        int64_t rows = 0;
+        for (int sid : lvl) {
+            const TreeStep& st = t.steps[sid];
+            t.scratch_row[sid] = rows;
+            rows += int64_t(st.in_tensors.size() + 1) << (st.out_axes.size() + st.vars.size());
+        }
+        t.scratch_rows = std::max(t.scratch_rows, rows);
+    }
+    for (auto& st : t.steps)
+        if (st.groups.size() > 16) { *err = "internal: more than 16 factor groups"; return QGM_E_INTERNAL; }
+    if (t.n_tasks > kTreeMaxTasks || t.arena_rows >= (int64_t(1) << 31) || t.g_total >= (int64_t(1) << 31) ||
+        t.arena_rows_all >= (int64_t(1) << 31)) {
         *err = "bucket plan too large for the device tables (results of rank > 24)";
         return QGM_E_UNSUPPORTED;
     }

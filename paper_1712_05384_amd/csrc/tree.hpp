@@ -131,6 +131,12 @@ struct TreePlan {
     std::vector<int64_t> level_task_off;         // wave tasks of level L: [off[L], off[L + 1])
     std::vector<int> level_max_in;               // most inputs of a bucket in level L
     int64_t n_tasks = 0;
+    // adjoint (qgm_backward): every result at its own rows, and per level the
+    // scratch rows of the expansion (H and one Q per input for each bucket)
+    std::vector<int64_t> tensor_row_all;
+    int64_t arena_rows_all = 0;
+    std::vector<int64_t> scratch_row;            // per step, within its level's scratch
+    int64_t scratch_rows = 0;                    // the largest level's scratch
     int64_t ones_g = 0;                          // factor-table entry holding the constant 1 that a wave reads
                                                  //   (lane stride 0) for inputs its bucket does not have
     int n_absorbed = 0;                          // buckets without inputs folded into a later bucket's table

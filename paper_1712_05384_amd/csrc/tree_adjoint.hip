@@ -1,0 +1,396 @@
+// Adjoint of the bucket-elimination path (qgm_backward with ordering 1, gfx950).
+//
+// Holomorphic adjoints are propagated through the buckets in reverse level
+// order.  For bucket s with result R[o] = sum_w G[c(o, w), sigma] prod_t T_t[idx_t(o, w)]
+// and index space a = (o << k) | w:
+//   T_t-bar[j] = sum_{a : idx_t(a) = j} R-bar[o(a)] G[c(a), sigma] prod_{t' != t} T_t'[idx_t'(a)]
+//   G-bar[c][sigma] = sum_b [sigma(b) = sigma] sum_{a : c(a) = c} R-bar[o(a)] prod_t T_t[idx_t(a)]
+// computed in two passes: an expansion over the whole index space (writing
+// H = R-bar prod_t T_t and Q_t = R-bar G prod_{t' != t} T_t' per row a), then
+// reductions over the a-bits that an input (or the table index) does not
+// carry.  The table adjoints then flow through the factor groups to every gate
+// factor (product rule; an absorbed bucket's group is a sum over its own
+// variables), and the factors of each gate slot are summed into its gradient.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "tree_dev.hpp"
+
+namespace qgm {
+
+using namespace tree_dev;
+
+namespace {
+
+constexpr int kTbMaxGroups = 16;    // factor groups of one table (the planner keeps them below this)
+constexpr int kTbGbarLds = 1 << kTreeMaxSig;
+
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+__device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
+    atomicAdd(&p->x, v.x);
+    atomicAdd(&p->y, v.y);
+}
+
+__device__ __forceinline__ bool slot_factor(const TFactor& f) {
+    return (f.type == TF_MAT || f.type == TF_DIAG) && f.mat >= kFixedMats;
+}
+
+// Entry of an item list whose rows cover `row` (items sorted by row0).
+__device__ __forceinline__ TreeBwdItem find_item(const TreeBwdItem* __restrict__ items, int n_items, int64_t row) {
+    int k = 0;
+    while (k + 1 < n_items && int64_t(items[k + 1].row0) <= row) ++k;
+    return items[k];
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_tb_zero(double2* __restrict__ p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        p[i] = make_double2(0.0, 0.0);
+}
+
+// Seed: A = phase x prod of the rank-0 results (FP64), A-bar = conj(grad_amps);
+// the adjoint of every rank-0 result, and the phase factors' share of the
+// gate-slot gradients.  Padded bitstrings (b >= B) get zero adjoints.
+__global__ void __launch_bounds__(256) k_tb_seed(const int64_t* __restrict__ final_rows, int n_final,
+                                                 const TFactor* __restrict__ phase, int n_phase,
+                                                 const double2* __restrict__ fixed, const float2* __restrict__ slots,
+                                                 const float2* __restrict__ arena, float2* __restrict__ adj,
+                                                 const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                 const float2* __restrict__ grad_amps, void* __restrict__ amps_out,
+                                                 int c128, double2* __restrict__ fbar_phase) {
+    const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+    if (b >= B_eff) return;
+    const bool live = int64_t(b) < B;
+    const uint64_t x = live ? bits[b] : 0ull;
+    auto phase_value = [&](int i) {
+        const TFactor f = phase[i];
+        const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
+        const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
+        return factor_value(f, a, c, fixed, slots);
+    };
+    double2 phi = make_double2(1.0, 0.0);
+    for (int i = 0; i < n_phase; ++i) phi = cmuld(phi, phase_value(i));
+    double2 prod = make_double2(1.0, 0.0);
+    for (int f = 0; f < n_final; ++f) {
+        const float2 r = arena[final_rows[f] * int64_t(B_eff) + b];
+        prod = cmuld(prod, make_double2(r.x, r.y));
+    }
+    const double2 amp = cmuld(phi, prod);
+    if (live && amps_out) {
+        if (c128) static_cast<double2*>(amps_out)[b] = amp;
+        else static_cast<float2*>(amps_out)[b] = make_float2(float(amp.x), float(amp.y));
+    }
+    double2 abar = make_double2(0.0, 0.0);
+    if (live) {
+        const float2 g = grad_amps[b];
+        abar = make_double2(g.x, -g.y);
+    }
+    for (int f = 0; f < n_final; ++f) {
+        double2 v = cmuld(abar, phi);
+        for (int f2 = 0; f2 < n_final; ++f2) {
+            if (f2 == f) continue;
+            const float2 r = arena[final_rows[f2] * int64_t(B_eff) + b];
+            v = cmuld(v, make_double2(r.x, r.y));
+        }
+        adj[final_rows[f] * int64_t(B_eff) + b] = make_float2(float(v.x), float(v.y));
+    }
+    if (!live) return;
+    const double2 phibar = cmuld(abar, prod);
+    for (int i = 0; i < n_phase; ++i) {
+        const TFactor f = phase[i];
+        if (!slot_factor(f)) continue;
+        double2 v = phibar;
+        for (int j = 0; j < n_phase; ++j)
+            if (j != i) v = cmuld(v, phase_value(j));
+        const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
+        const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
+        atomic_add_c(fbar_phase + size_t(i) * 4 + a * 2 + c, v);
+    }
+}
+
+// Expansion over a bucket's index space: wave unit u handles row a of one
+// bucket of the level for 64 bitstrings, writing H[a] and every Q_t[a].
+__global__ void __launch_bounds__(256) k_tb_expand(const TreeBwdItem* __restrict__ items, int n_items,
+                                                   int64_t n_units, const TreeBwd* __restrict__ bwd,
+                                                   const float2* __restrict__ arena, const float2* __restrict__ adj,
+                                                   const float2* __restrict__ gtab, float2* __restrict__ scratch,
+                                                   const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t be = int64_t(B_eff);
+    const uint32_t n_bg = B_eff / 64u;
+    for (int64_t u = int64_t(blockIdx.x) * 4 + wave; u < n_units; u += int64_t(gridDim.x) * 4) {
+        const int64_t R = u / n_bg;
+        const uint32_t bg = uint32_t(u - R * n_bg);
+        const TreeBwdItem it = find_item(items, n_items, R);
+        const TreeBwd* __restrict__ d = bwd + it.idx;
+        const uint32_t a = uint32_t(R - it.row0);
+        const uint32_t b = bg * 64u + lane;
+        const uint64_t x = int64_t(b) < B ? bits[b] : 0ull;
+        const int n_in = d->n_in;
+        const uint32_t sig = gather_sigma(x, d->sig_q, d->sb);
+        int64_t idx[kTreeMaxIn];
+#pragma unroll
+        for (int t = 0; t < kTreeMaxIn; ++t) idx[t] = t < n_in ? int64_t(d->in_row[t]) : 0;
+        int64_t c = 0;
+        for (uint32_t m = a; m; m &= m - 1u) {
+            const int i = __builtin_ctz(m);
+#pragma unroll
+            for (int t = 0; t < kTreeMaxIn; ++t)
+                if (t < n_in) idx[t] += d->in_str[t][i];
+            c += d->g_str[i];
+        }
+        const float2 rb = adj[(int64_t(d->out_row) + (a >> d->k)) * be + b];
+        const float2 gv = gtab[d->g_off + (c << d->sb) + sig];
+        float2 T[kTreeMaxIn];
+#pragma unroll
+        for (int t = 0; t < kTreeMaxIn; ++t) T[t] = t < n_in ? arena[idx[t] * be + b] : make_float2(1.f, 0.f);
+        float2 h = rb;
+#pragma unroll
+        for (int t = 0; t < kTreeMaxIn; ++t) h = cmulf(h, T[t]);
+        const int64_t rows = int64_t(1) << d->a_bits;
+        scratch[(d->scratch_row + a) * be + b] = h;
+        const float2 base = cmulf(rb, gv);
+#pragma unroll
+        for (int t = 0; t < kTreeMaxIn; ++t) {
+            if (t >= n_in) break;
+            float2 q = base;
+#pragma unroll
+            for (int t2 = 0; t2 < kTreeMaxIn; ++t2)
+                if (t2 != t) q = cmulf(q, T[t2]);
+            scratch[(d->scratch_row + (1 + t) * rows + a) * be + b] = q;
+        }
+    }
+}
+
+// Input adjoints: block (row j of one input adjoint, 64-bitstring group); its
+// four waves sum interleaved quarters of the rows a that map to j.
+__global__ void __launch_bounds__(256) k_tb_reduce_in(const TreeBwdItem* __restrict__ items, int n_items,
+                                                      const TreeBwdIn* __restrict__ bin,
+                                                      const float2* __restrict__ scratch, float2* __restrict__ adj,
+                                                      uint32_t B_eff) {
+    __shared__ float2 part[4][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const int64_t be = int64_t(B_eff);
+    const uint32_t n_bg = B_eff / 64u;
+    const int64_t R = int64_t(blockIdx.x) / n_bg;
+    const uint32_t bg = uint32_t(int64_t(blockIdx.x) - R * n_bg);
+    const TreeBwdItem it = find_item(items, n_items, R);
+    const TreeBwdIn* __restrict__ d = bin + it.idx;
+    const uint32_t j = uint32_t(R - it.row0);
+    const uint32_t b = bg * 64u + lane;
+    uint32_t a0 = 0;
+    for (int p = 0; p < d->r_t; ++p) a0 |= ((j >> p) & 1u) << d->pos[p];
+    const uint32_t n_comb = 1u << d->n_free;
+    float2 acc = make_float2(0.f, 0.f);
+    for (uint32_t f = wave; f < n_comb; f += 4u) {
+        uint32_t a = a0;
+        for (uint32_t m = f; m; m &= m - 1u) a |= 1u << d->free_bits[__builtin_ctz(m)];
+        const float2 v = scratch[(d->q_row + a) * be + b];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+        float2 s = part[0][lane];
+        for (int w = 1; w < 4; ++w) {
+            s.x += part[w][lane].x;
+            s.y += part[w][lane].y;
+        }
+        adj[(int64_t(d->dst_row) + j) * be + b] = s;
+    }
+}
+
+// Factor-table adjoint: block = one table row c; every thread sums H over the
+// rows of class c for its bitstrings and adds the result to the bin of its
+// bitstring's output bits (LDS, FP64); the block then writes the row.
+__global__ void __launch_bounds__(256) k_tb_gbar(const TreeBwdItem* __restrict__ items, int n_items,
+                                                 const TreeBwdG* __restrict__ bgd, const float2* __restrict__ scratch,
+                                                 const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                 double2* __restrict__ gbar) {
+    __shared__ double2 bins[kTbGbarLds];
+    const int64_t be = int64_t(B_eff);
+    const TreeBwdItem it = find_item(items, n_items, blockIdx.x);
+    const TreeBwdG* __restrict__ d = bgd + it.idx;
+    const uint32_t c = uint32_t(int64_t(blockIdx.x) - it.row0);
+    const int sb = d->sb;
+    for (int i = threadIdx.x; i < (1 << sb); i += 256) bins[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    uint32_t ac = 0;
+    for (int i = 0; i < d->c_bits; ++i) ac |= ((c >> i) & 1u) << d->cpos[i];
+    const uint32_t n_comb = 1u << d->n_free;
+    for (int64_t b = threadIdx.x; b < B; b += 256) {
+        double2 h = make_double2(0.0, 0.0);
+        for (uint32_t f = 0; f < n_comb; ++f) {
+            uint32_t a = ac;
+            for (uint32_t m = f; m; m &= m - 1u) a |= 1u << d->free_bits[__builtin_ctz(m)];
+            const float2 v = scratch[(d->h_row + a) * be + b];
+            h.x += v.x;
+            h.y += v.y;
+        }
+        const uint32_t sig = gather_sigma(bits[b], d->sig_q, sb);
+        atomicAdd(&bins[sig].x, h.x);
+        atomicAdd(&bins[sig].y, h.y);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (1 << sb); i += 256) gbar[d->g_off + (int64_t(c) << sb) + i] = bins[i];
+}
+
+// Factor adjoints from the table adjoints: per table entry e (blocks as in
+// the factor-table build), for every group q and value iv of its own
+// variables, each gate-slot factor f of q receives
+//   G-bar[e] * prod_{q' != q} S_q' * prod_{f' in q, f' != f} f'
+// at the entry of its table that (c, sigma, iv) selects.
+__global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict__ blocks,
+                                                 const TreeGTab* __restrict__ gtabs,
+                                                 const TreeGroup* __restrict__ groups,
+                                                 const TFactor* __restrict__ facs, const double2* __restrict__ fixed,
+                                                 const float2* __restrict__ slots, const double2* __restrict__ gbar,
+                                                 double2* __restrict__ fbar) {
+    __shared__ FactorLds L;
+    const TreeProBlock blk = blocks[blockIdx.x];
+    const TreeGTab t = gtabs[blk.idx];
+    const TreeGroup* __restrict__ gr = groups + t.group_off;
+    const int fac0 = gr[0].fac_off;
+    const TFactor* __restrict__ tf = facs + fac0;
+    const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);
+    const int64_t e = int64_t(blk.sub) * 256 + threadIdx.x;
+    if (e >= (int64_t(1) << (t.gb + t.k + t.sb))) return;
+    const double2 gb = gbar[t.g_off + e];
+    if (gb.x == 0.0 && gb.y == 0.0) return;
+    const uint32_t sig = uint32_t(e) & ((1u << t.sb) - 1u);
+    const uint32_t c = uint32_t(e) >> t.sb;
+    double2 S[kTbMaxGroups];
+#pragma unroll
+    for (int q = 0; q < kTbMaxGroups; ++q) {
+        S[q] = make_double2(1.0, 0.0);
+        if (q < t.n_groups) {
+            const TreeGroup g = gr[q];
+            const int f0 = g.fac_off - fac0, f1 = f0 + g.n_fac;
+            double2 sum = make_double2(0.0, 0.0);
+            for (uint32_t iv = 0; iv < (1u << g.k_int); ++iv) {
+                const double2 v = factor_product(L, nf, tf, f0, f1, fixed, slots, c, sig, iv);
+                sum.x += v.x;
+                sum.y += v.y;
+            }
+            S[q] = sum;
+        }
+    }
+    auto val = [&](int32_t src, int32_t bit, uint32_t iv) -> uint32_t {
+        switch (src) {
+            case TS_G: return (c >> bit) & 1u;
+            case TS_SIG: return (sig >> bit) & 1u;
+            case TS_INT: return (iv >> bit) & 1u;
+            default: return 0u;
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < kTbMaxGroups; ++q) {
+        if (q >= t.n_groups) break;
+        double2 pq = gb;
+#pragma unroll
+        for (int q2 = 0; q2 < kTbMaxGroups; ++q2)
+            if (q2 != q && q2 < t.n_groups) pq = cmuld(pq, S[q2]);
+        const TreeGroup g = gr[q];
+        const int f0 = g.fac_off - fac0, f1 = f0 + g.n_fac;
+        for (int i = f0; i < f1; ++i) {
+            const TFactor f = tf[i];
+            if (!slot_factor(f)) continue;
+            for (uint32_t iv = 0; iv < (1u << g.k_int); ++iv) {
+                double2 v = pq;
+                for (int i2 = f0; i2 < f1; ++i2)
+                    if (i2 != i) v = cmuld(v, factor_product(L, nf, tf, i2, i2 + 1, fixed, slots, c, sig, iv));
+                const uint32_t args = val(f.src0, f.bit0, iv) * 2u + val(f.src1, f.bit1, iv);
+                atomic_add_c(fbar + size_t(fac0 + i) * 4 + args, v);
+            }
+        }
+    }
+}
+
+// Gradient of every gate slot: the sum of its factors' adjoints (a diagonal
+// gate's factor value at (a, c) is the slot entry (a, a)), conjugated for the
+// torch convention.
+__global__ void __launch_bounds__(256) k_tb_slots(const int32_t* __restrict__ slot_off,
+                                                  const int32_t* __restrict__ slot_occ, int n_slots,
+                                                  const double2* __restrict__ fbar, float2* __restrict__ grads) {
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= n_slots * 4) return;
+    const int s = id >> 2, el = id & 3;
+    const int ra = el >> 1, rc = el & 1;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int o = slot_off[s]; o < slot_off[s + 1]; ++o) {
+        const int32_t occ = slot_occ[o];
+        const double2* fb = fbar + size_t(occ >> 1) * 4;
+        if (occ & 1) {   // diagonal gate: entries (a, 0) and (a, 1) of the factor both hold M[a][a]
+            if (ra == rc) {
+                acc.x += fb[ra * 2].x + fb[ra * 2 + 1].x;
+                acc.y += fb[ra * 2].y + fb[ra * 2 + 1].y;
+            }
+        } else {
+            acc.x += fb[el].x;
+            acc.y += fb[el].y;
+        }
+    }
+    grads[id] = conjf2(make_float2(float(acc.x), float(acc.y)));
+}
+
+void launch_tb_zero(double2* p, int64_t n, hipStream_t stream) {
+    if (n <= 0) return;
+    const uint32_t grid = uint32_t(std::min<int64_t>((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_tb_zero, dim3(grid), dim3(256), 0, stream, p, n);
+}
+
+void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
+                    const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,
+                    uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* fbar_phase,
+                    hipStream_t stream) {
+    hipLaunchKernelGGL(k_tb_seed, dim3((B_eff + 255) / 256), dim3(256), 0, stream, final_rows, n_final, phase, n_phase,
+                       fixed, slots, arena, adj, bits, B, B_eff, grad_amps, amps_out, c128 ? 1 : 0, fbar_phase);
+}
+
+void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwd* bwd,
+                      const float2* arena, const float2* adj, const float2* gtab, float2* scratch,
+                      const uint64_t* bits, int64_t B, uint32_t B_eff, hipStream_t stream) {
+    const int64_t n_units = total_rows * (B_eff / 64u);
+    if (n_units <= 0) return;
+    const uint32_t grid = uint32_t(std::min<int64_t>((n_units + 3) / 4, kStepMaxGrid));
+    hipLaunchKernelGGL(k_tb_expand, dim3(grid), dim3(256), 0, stream, items, n_items, n_units, bwd, arena, adj, gtab,
+                       scratch, bits, B, B_eff);
+}
+
+void launch_tb_reduce_in(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
+                         const float2* scratch, float2* adj, uint32_t B_eff, hipStream_t stream) {
+    const int64_t blocks = total_rows * (B_eff / 64u);
+    if (blocks <= 0) return;
+    hipLaunchKernelGGL(k_tb_reduce_in, dim3(uint32_t(blocks)), dim3(256), 0, stream, items, n_items, bin, scratch, adj,
+                       B_eff);
+}
+
+void launch_tb_gbar(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg,
+                    const float2* scratch, const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar,
+                    hipStream_t stream) {
+    if (total_rows <= 0) return;
+    hipLaunchKernelGGL(k_tb_gbar, dim3(uint32_t(total_rows)), dim3(256), 0, stream, items, n_items, bg, scratch, bits,
+                       B, B_eff, gbar);
+}
+
+void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
+                    const TFactor* facs, const double2* fixed, const float2* slots, const double2* gbar,
+                    double2* fbar, hipStream_t stream) {
+    if (n_blocks <= 0) return;
+    hipLaunchKernelGGL(k_tb_gadj, dim3(uint32_t(n_blocks)), dim3(256), 0, stream, blocks, gtabs, groups, facs, fixed,
+                       slots, gbar, fbar);
+}
+
+void launch_tb_slots(const int32_t* slot_off, const int32_t* slot_occ, int n_slots, const double2* fbar,
+                     float2* grads, hipStream_t stream) {
+    if (n_slots <= 0) return;
+    hipLaunchKernelGGL(k_tb_slots, dim3((n_slots * 4 + 255) / 256), dim3(256), 0, stream, slot_off, slot_occ, n_slots,
+                       fbar, grads);
+}
+
+}  // namespace qgm

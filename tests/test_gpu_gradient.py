@@ -87,3 +87,82 @@ def test_autograd_function_and_finite_difference():
             fd = (lp - lm) / 2e-2
             an = g[s, a, b].real if unit == 1.0 else g[s, a, b].imag
             assert abs(fd - an) <= 0.05 * max(1.0, abs(an)), (s, a, b, unit, fd, an)
+
+
+# --- adjoint of the bucket path (ordering 1) -------------------------------------------------
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,kw", [
+    (1, 1, 4, 11, {}), (2, 2, 6, 1, {}), (3, 3, 10, 2, {}), (3, 4, 12, 3, {}), (4, 4, 12, 4, {}),
+    (4, 3, 14, 7, {"chain_merge": False}), (4, 4, 16, 6, {"out_c128": True})])
+def test_tree_gradient_matches_oracle(rows, cols, depth, seed, kw):
+    """Adjoint through the buckets (merged chains, absorbed buckets, tail
+    levels) against the FP64 adjoint-state gradient; the identity
+    sum_ab U conj(G) = 2m; amplitudes of the backward call equal the forward's."""
+    c = C.parameterised_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 100, seed)
+    _say("case tree %s %s" % (c.name, kw))
+    amps, amps2, got = _gpu_grad(c, bits, ordering=1, **kw)
+    vals = c.gate_vals.astype(np.complex64).astype(np.complex128)
+    ref_amps, ref = oracle.sv_log_prob_gradient(c.n, c.gates, vals, bits)
+    assert np.abs(amps2 - ref_amps).max() <= 1e-5 * 2 ** (-c.n / 2)
+    assert np.abs(amps2 - amps).max() <= 1e-5 * 2 ** (-c.n / 2)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say("  rel frobenius err %.3g" % rel)
+    assert rel <= GTOL
+    ident = np.einsum("sab,sab->s", vals, got.conj())
+    assert np.abs(ident - 2 * len(bits)).max() <= 1e-3 * 2 * len(bits)
+
+
+def test_tree_c4_workload_gradient_and_vertical_agreement():
+    """5x5 depth 20, every single-qubit gate U(theta, n), 256 bitstrings: the
+    bucket-path gradient against the oracle and against the vertical path."""
+    c, bits = C.workload("c4_5x5_d20_U")
+    _say("case tree c4 5x5 d20 B=256")
+    _, amps, got = _gpu_grad(c, bits, ordering=1)
+    vals = c.gate_vals.astype(np.complex64).astype(np.complex128)
+    ref_amps, ref = oracle.sv_log_prob_gradient(c.n, c.gates, vals, bits)
+    assert np.abs(amps - ref_amps).max() <= 1e-5 * 2 ** (-c.n / 2)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say("  tree c4 rel frobenius err %.3g" % rel)
+    assert rel <= GTOL
+    _, _, vert = _gpu_grad(c, bits)
+    assert np.linalg.norm(got - vert) / np.linalg.norm(vert) <= GTOL
+
+
+def test_tree_gradient_diagonal_gates_and_autograd():
+    """Diagonal parameterised gates (UD: every T of a random circuit becomes
+    diag(1, e^{i phi}) with its own slot, the first two sharing one) on the
+    bucket path, through the autograd function."""
+    import paper_1712_05384_amd as Q
+    base = C.random_grid_circuit(3, 3, 12, 21)
+    gates = base.gates.copy()
+    rng = np.random.default_rng(5)
+    vals = []
+    n_t = 0
+    for i in range(len(gates)):
+        if gates[i, 0] == C.T:
+            gates[i, 0] = C.UD
+            if n_t == 1:
+                gates[i, 4] = 0   # the second diagonal gate shares the first one's slot
+            else:
+                gates[i, 4] = len(vals)
+                vals.append(np.diag([1.0, np.exp(1j * rng.uniform(0, 2 * np.pi))]))
+            n_t += 1
+    kk = C.Circuit(base.rows, base.cols, gates, np.array(vals, dtype=np.complex128), base.name + "_ud")
+    assert kk.n_slots >= 3 and (gates[:, 4] == 0).sum() >= 2
+    bits = C.random_bitstrings(kk.n, 64, 21)
+    _say("case tree diagonal slots %s (%d slots)" % (kk.name, kk.n_slots))
+    _, amps, got = _gpu_grad(kk, bits, ordering=1)
+    v128 = kk.gate_vals.astype(np.complex64).astype(np.complex128)
+    ref_amps, ref = oracle.sv_log_prob_gradient(kk.n, kk.gates, v128, bits)
+    assert np.abs(amps - ref_amps).max() <= 1e-5 * 2 ** (-kk.n / 2)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say("  rel frobenius err %.3g" % rel)
+    assert rel <= GTOL
+    p = Q.plan(kk, ordering=1)
+    gv = torch.tensor(kk.gate_vals.astype(np.complex64), device="cuda", requires_grad=True)
+    bt = torch.from_numpy(bits.view(np.int64)).cuda()
+    a = Q.amplitudes_autograd(gv, bt, p)
+    torch.log(a.abs() ** 2).sum().backward()
+    assert np.linalg.norm(gv.grad.cpu().numpy() - got) <= 1e-4 * np.linalg.norm(got)

@@ -43,7 +43,7 @@ struct qgm_plan_s {
     size_t off_ttasks_all = 0, off_tfinal_all = 0, off_tbwd = 0, off_tbwdin = 0, off_tbwdg = 0, off_titems = 0;
     size_t off_tslot_off = 0, off_tslot_occ = 0;
     struct LevelItems { int off = 0, n = 0; int64_t rows = 0; };
-    std::vector<LevelItems> lv_exp, lv_in, lv_g;
+    std::vector<LevelItems> lv_exp, lv_in, lv_hred, lv_g;
     std::vector<qgm::TreeBwdItem> items;
     std::vector<int32_t> slot_off_t, slot_occ_t;
     int64_t n_fbar = 0;
@@ -113,6 +113,7 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->items.clear();
     P->lv_exp.assign(t.levels.size(), {});
     P->lv_in.assign(t.levels.size(), {});
+    P->lv_hred.assign(t.levels.size(), {});
     P->lv_g.assign(t.levels.size(), {});
     {
         int in_idx = 0;
@@ -133,6 +134,10 @@ void layout_tree_tables(qgm_plan_t* P) {
                 const qgm::TreeStep& st = t.steps[sid];
                 for (size_t k = 0; k < st.in_tensors.size(); ++k)
                     add(P->lv_in[L], in_base[sid] + int(k), int64_t(1) << t.tensor_axes[st.in_tensors[k]].size());
+            }
+            for (int sid : t.levels[L]) {   // H summed within each table row: reducer records after the inputs'
+                const qgm::TreeStep& st = t.steps[sid];
+                add(P->lv_hred[L], int(n_in_total) + sid, int64_t(1) << (st.gb() + st.kg));
             }
             for (int sid : t.levels[L]) {
                 const qgm::TreeStep& st = t.steps[sid];
@@ -165,7 +170,7 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tfinal_all = P->off_ttasks_all + al(sizeof(qgm::TreeTask) * size_t(t.n_tasks + 1));
     P->off_tbwd = P->off_tfinal_all + al(sizeof(int64_t) * (t.finals.size() + 1));
     P->off_tbwdin = P->off_tbwd + al(sizeof(qgm::TreeBwd) * (t.steps.size() + 1));
-    P->off_tbwdg = P->off_tbwdin + al(sizeof(qgm::TreeBwdIn) * (n_in_total + 1));
+    P->off_tbwdg = P->off_tbwdin + al(sizeof(qgm::TreeBwdIn) * (n_in_total + t.steps.size() + 1));
     P->off_titems = P->off_tbwdg + al(sizeof(qgm::TreeBwdG) * (t.steps.size() + 1));
     P->off_tslot_off = P->off_titems + al(sizeof(qgm::TreeBwdItem) * (P->items.size() + 1));
     P->off_tslot_occ = P->off_tslot_off + al(sizeof(int32_t) * (P->slot_off_t.size() + 1));
@@ -198,6 +203,7 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
     auto* bi = reinterpret_cast<qgm::TreeBwdIn*>(h + P->off_tbwdin);
     auto* bg = reinterpret_cast<qgm::TreeBwdG*>(h + P->off_tbwdg);
     int in_idx = 0;
+    std::vector<qgm::TreeBwdIn> h_red;
     for (size_t sid = 0; sid < t.steps.size(); ++sid) {
         const qgm::TreeStep& st = t.steps[sid];
         const int r = int(st.out_axes.size()), k = st.kg;
@@ -245,7 +251,7 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
         qgm::TreeBwdG g{};
         g.c_bits = st.gb() + k;
         g.sb = st.sb();
-        g.h_row = d.scratch_row;
+        g.h_row = t.hsum_row[sid];
         g.g_off = st.g_off;
         for (int b = 0; b < st.sb(); ++b) g.sig_q[b] = st.sig_q[b];
         for (int i = 0; i < k; ++i) g.cpos[i] = i;
@@ -254,7 +260,17 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
             if (std::find(st.gvars.begin(), st.gvars.end(), st.out_axes[j]) == st.gvars.end())
                 g.free_bits[g.n_free++] = k + j;
         bg[sid] = g;
+        // H summed over the rows of each table row (a reducer record: table row c <- class of a-rows)
+        qgm::TreeBwdIn hr{};
+        hr.r_t = g.c_bits;
+        hr.n_free = g.n_free;
+        hr.dst_row = int32_t(t.hsum_row[sid]);
+        hr.q_row = d.scratch_row;
+        for (int i = 0; i < g.c_bits; ++i) hr.pos[i] = g.cpos[i];
+        for (int i = 0; i < g.n_free; ++i) hr.free_bits[i] = g.free_bits[i];
+        h_red.push_back(hr);
     }
+    for (size_t i = 0; i < h_red.size(); ++i) bi[in_idx + int(i)] = h_red[i];
     std::memcpy(h + P->off_titems, P->items.data(), sizeof(qgm::TreeBwdItem) * P->items.size());
     std::memcpy(h + P->off_tslot_off, P->slot_off_t.data(), sizeof(int32_t) * P->slot_off_t.size());
     std::memcpy(h + P->off_tslot_occ, P->slot_occ_t.data(), sizeof(int32_t) * P->slot_occ_t.size());
@@ -518,9 +534,10 @@ qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
 
 // Workspace of qgm_backward for a tree plan: the keep-all arena, the adjoint
 // arena, the factor tables (circuits with gate values), the expansion
-// scratch, the table adjoints (FP64) and the factor adjoints (FP64).
+// scratch, the row sums of H per table row, the table adjoints (FP64) and the
+// factor adjoints (FP64).
 struct TreeBwdLayout {
-    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, gbar = 0, fbar = 0, total = 0;
+    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, hsum = 0, gbar = 0, fbar = 0, total = 0;
 };
 
 TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
@@ -531,7 +548,8 @@ TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
     L.adj = al(uint64_t(t.arena_rows_all) * be * 8);
     L.g = 2 * L.adj;
     L.scratch = L.g + (P->p.n_slots > 0 ? al(uint64_t(t.g_total) * 8) : 0);
-    L.gbar = L.scratch + al(uint64_t(t.scratch_rows) * be * 8);
+    L.hsum = L.scratch + al(uint64_t(t.scratch_rows) * be * 8);
+    L.gbar = L.hsum + al(uint64_t(t.hsum_rows) * be * 8);
     L.fbar = L.gbar + al(uint64_t(t.g_total) * 16);
     L.total = L.fbar + al(uint64_t(P->n_fbar) * 4 * 16 + 16);
     return L;
@@ -762,6 +780,7 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     auto* arena = reinterpret_cast<float2*>(ws + L.arena);
     auto* adj = reinterpret_cast<float2*>(ws + L.adj);
     auto* scratch = reinterpret_cast<float2*>(ws + L.scratch);
+    auto* hsum = reinterpret_cast<float2*>(ws + L.hsum);
     auto* gbar = reinterpret_cast<double2*>(ws + L.gbar);
     auto* fbar = reinterpret_cast<double2*>(ws + L.fbar);
     float2* gt = p.n_slots > 0 ? reinterpret_cast<float2*>(ws + L.g) : reinterpret_cast<float2*>(tables + plan->off_tg);
@@ -792,10 +811,14 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     for (int Lv = int(t.levels.size()) - 1; Lv >= t.first_level; --Lv) {
         const auto& ex = plan->lv_exp[Lv];
         const auto& in = plan->lv_in[Lv];
+        const auto& hr = plan->lv_hred[Lv];
         const auto& gg = plan->lv_g[Lv];
         qgm::launch_tb_expand(items + ex.off, ex.n, ex.rows, bwd, arena, adj, gt, scratch, bits, B, be, s);
         if (in.n > 0) qgm::launch_tb_reduce_in(items + in.off, in.n, in.rows, bin, scratch, adj, be, s);
-        if (p.n_slots > 0) qgm::launch_tb_gbar(items + gg.off, gg.n, gg.rows, bgd, scratch, bits, B, be, gbar, s);
+        if (p.n_slots > 0) {
+            qgm::launch_tb_reduce_in(items + hr.off, hr.n, hr.rows, bin, scratch, hsum, be, s);
+            qgm::launch_tb_gbin(items + gg.off, gg.n, gg.rows, bgd, hsum, bits, B, be, gbar, s);
+        }
     }
     if (p.n_slots > 0) {
         qgm::launch_tb_gadj(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gbar, fbar, s);

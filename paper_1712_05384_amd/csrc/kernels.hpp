@@ -103,10 +103,11 @@ struct TreeBwd {
     int32_t g_str[32];                          // factor-table index stride of a-bit i (c units)
 };
 
-// Adjoint of input t of a bucket: the sum over the a-bits that are not axes of t.
+// Adjoint of input t of a bucket: the sum over the a-bits that are not axes
+// of t (also used to sum H over the rows of each factor-table row).
 struct TreeBwdIn {
     int32_t r_t, n_free;
-    int32_t dst_row;                            // keep-all adjoint row of input t
+    int32_t dst_row;                            // keep-all adjoint row of input t (row-sum area row for H)
     int32_t pad;
     int64_t q_row;                              // scratch row of Q_t
     int32_t pos[32];                            // a-bit of t's axis p
@@ -116,7 +117,7 @@ struct TreeBwdIn {
 // Adjoint of a bucket's factor table, one table row c per block.
 struct TreeBwdG {
     int32_t c_bits, n_free, sb, pad;            // c_bits = gb + k
-    int64_t h_row;                              // scratch row of H
+    int64_t h_row;                              // row of H summed within table row c = 0 (row-sum area)
     int64_t g_off;                              // table base entry (the table adjoint has the same layout)
     int32_t sig_q[kTreeMaxSig];
     int32_t cpos[32];                           // a-bit of table-index bit i
@@ -175,10 +176,9 @@ void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows,
                       const float2* arena, const float2* adj, const float2* gtab, float2* scratch,
                       const uint64_t* bits, int64_t B, uint32_t B_eff, hipStream_t stream);
 void launch_tb_reduce_in(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
-                         const float2* scratch, float2* adj, uint32_t B_eff, hipStream_t stream);
-void launch_tb_gbar(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg,
-                    const float2* scratch, const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar,
-                    hipStream_t stream);
+                         const float2* scratch, float2* dst, uint32_t B_eff, hipStream_t stream);
+void launch_tb_gbin(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg, const float2* hsum,
+                    const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar, hipStream_t stream);
 void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                     const TFactor* facs, const double2* fixed, const float2* slots, const double2* gbar,
                     double2* fbar, hipStream_t stream);

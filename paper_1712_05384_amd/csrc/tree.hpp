@@ -137,6 +137,8 @@ struct TreePlan {
     int64_t arena_rows_all = 0;
     std::vector<int64_t> scratch_row;            // per step, within its level's scratch
     int64_t scratch_rows = 0;                    // the largest level's scratch
+    std::vector<int64_t> hsum_row;               // per step: its table rows of H summed within the class
+    int64_t hsum_rows = 0;
     int64_t ones_g = 0;                          // factor-table entry holding the constant 1 that a wave reads
                                                  //   (lane stride 0) for inputs its bucket does not have
     int n_absorbed = 0;                          // buckets without inputs folded into a later bucket's table

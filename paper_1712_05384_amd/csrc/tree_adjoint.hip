@@ -165,11 +165,11 @@ __global__ void __launch_bounds__(256) k_tb_expand(const TreeBwdItem* __restrict
     }
 }
 
-// Input adjoints: block (row j of one input adjoint, 64-bitstring group); its
-// four waves sum interleaved quarters of the rows a that map to j.
+// Input adjoints (and row sums of H): block (row j of one result, 64-bitstring
+// group); its four waves sum interleaved quarters of the rows a that map to j.
 __global__ void __launch_bounds__(256) k_tb_reduce_in(const TreeBwdItem* __restrict__ items, int n_items,
                                                       const TreeBwdIn* __restrict__ bin,
-                                                      const float2* __restrict__ scratch, float2* __restrict__ adj,
+                                                      const float2* __restrict__ scratch, float2* __restrict__ dst,
                                                       uint32_t B_eff) {
     __shared__ float2 part[4][64];
     const uint32_t lane = threadIdx.x & 63u;
@@ -201,43 +201,56 @@ __global__ void __launch_bounds__(256) k_tb_reduce_in(const TreeBwdItem* __restr
             s.x += part[w][lane].x;
             s.y += part[w][lane].y;
         }
-        adj[(int64_t(d->dst_row) + j) * be + b] = s;
+        dst[(int64_t(d->dst_row) + j) * be + b] = s;
     }
 }
 
-// Factor-table adjoint: block = one table row c; every thread sums H over the
-// rows of class c for its bitstrings and adds the result to the bin of its
-// bitstring's output bits (LDS, FP64); the block then writes the row.
-__global__ void __launch_bounds__(256) k_tb_gbar(const TreeBwdItem* __restrict__ items, int n_items,
-                                                 const TreeBwdG* __restrict__ bgd, const float2* __restrict__ scratch,
+// Factor-table adjoint, second pass: block = one table row c, whose row of
+// H' (H summed over the rows of class c, by k_tb_reduce_in) is staged in LDS
+// with every bitstring's output-bit value; thread s then sums the entries with
+// sigma(b) = s (deterministic, no atomics).
+__global__ void __launch_bounds__(256) k_tb_gbin(const TreeBwdItem* __restrict__ items, int n_items,
+                                                 const TreeBwdG* __restrict__ bgd, const float2* __restrict__ hsum,
                                                  const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
                                                  double2* __restrict__ gbar) {
-    __shared__ double2 bins[kTbGbarLds];
+    constexpr int CH = 1024;   // bitstrings staged per round
+    __shared__ float2 hv[CH];
+    __shared__ uint16_t sv[CH];
     const int64_t be = int64_t(B_eff);
     const TreeBwdItem it = find_item(items, n_items, blockIdx.x);
     const TreeBwdG* __restrict__ d = bgd + it.idx;
     const uint32_t c = uint32_t(int64_t(blockIdx.x) - it.row0);
     const int sb = d->sb;
-    for (int i = threadIdx.x; i < (1 << sb); i += 256) bins[i] = make_double2(0.0, 0.0);
-    __syncthreads();
-    uint32_t ac = 0;
-    for (int i = 0; i < d->c_bits; ++i) ac |= ((c >> i) & 1u) << d->cpos[i];
-    const uint32_t n_comb = 1u << d->n_free;
-    for (int64_t b = threadIdx.x; b < B; b += 256) {
-        double2 h = make_double2(0.0, 0.0);
-        for (uint32_t f = 0; f < n_comb; ++f) {
-            uint32_t a = ac;
-            for (uint32_t m = f; m; m &= m - 1u) a |= 1u << d->free_bits[__builtin_ctz(m)];
-            const float2 v = scratch[(d->h_row + a) * be + b];
-            h.x += v.x;
-            h.y += v.y;
+    const int n_sig = 1 << sb;
+    double2 acc[kTbGbarLds / 256];
+#pragma unroll
+    for (int i = 0; i < kTbGbarLds / 256; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t b0 = 0; b0 < B; b0 += CH) {
+        const int nb = int(std::min<int64_t>(CH, B - b0));
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += 256) {
+            hv[i] = hsum[(d->h_row + c) * be + b0 + i];
+            sv[i] = uint16_t(gather_sigma(bits[b0 + i], d->sig_q, sb));
         }
-        const uint32_t sig = gather_sigma(bits[b], d->sig_q, sb);
-        atomicAdd(&bins[sig].x, h.x);
-        atomicAdd(&bins[sig].y, h.y);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kTbGbarLds / 256; ++r) {
+            const int sg = threadIdx.x + r * 256;
+            if (sg >= n_sig) break;
+            double2 a = acc[r];
+            for (int i = 0; i < nb; ++i)
+                if (sv[i] == sg) {
+                    a.x += hv[i].x;
+                    a.y += hv[i].y;
+                }
+            acc[r] = a;
+        }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < (1 << sb); i += 256) gbar[d->g_off + (int64_t(c) << sb) + i] = bins[i];
+#pragma unroll
+    for (int r = 0; r < kTbGbarLds / 256; ++r) {
+        const int sg = threadIdx.x + r * 256;
+        if (sg < n_sig) gbar[d->g_off + (int64_t(c) << sb) + sg] = acc[r];
+    }
 }
 
 // Factor adjoints from the table adjoints: per table entry e (blocks as in
@@ -245,20 +258,12 @@ __global__ void __launch_bounds__(256) k_tb_gbar(const TreeBwdItem* __restrict__
 // variables, each gate-slot factor f of q receives
 //   G-bar[e] * prod_{q' != q} S_q' * prod_{f' in q, f' != f} f'
 // at the entry of its table that (c, sigma, iv) selects.
-__global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict__ blocks,
-                                                 const TreeGTab* __restrict__ gtabs,
-                                                 const TreeGroup* __restrict__ groups,
-                                                 const TFactor* __restrict__ facs, const double2* __restrict__ fixed,
-                                                 const float2* __restrict__ slots, const double2* __restrict__ gbar,
-                                                 double2* __restrict__ fbar) {
-    __shared__ FactorLds L;
-    const TreeProBlock blk = blocks[blockIdx.x];
-    const TreeGTab t = gtabs[blk.idx];
-    const TreeGroup* __restrict__ gr = groups + t.group_off;
-    const int fac0 = gr[0].fac_off;
-    const TFactor* __restrict__ tf = facs + fac0;
-    const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);
-    const int64_t e = int64_t(blk.sub) * 256 + threadIdx.x;
+// One table entry's contributions to the factor adjoints (into LDS for the
+// block's staged factors, directly to global memory beyond them).
+__device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, const TreeGroup* __restrict__ gr,
+                              int fac0, const TFactor* __restrict__ tf, const double2* __restrict__ fixed,
+                              const float2* __restrict__ slots, const double2* __restrict__ gbar,
+                              double2* __restrict__ fbar, double2* acc_lds, int64_t e) {
     if (e >= (int64_t(1) << (t.gb + t.k + t.sb))) return;
     const double2 gb = gbar[t.g_off + e];
     if (gb.x == 0.0 && gb.y == 0.0) return;
@@ -305,9 +310,37 @@ __global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict_
                 for (int i2 = f0; i2 < f1; ++i2)
                     if (i2 != i) v = cmuld(v, factor_product(L, nf, tf, i2, i2 + 1, fixed, slots, c, sig, iv));
                 const uint32_t args = val(f.src0, f.bit0, iv) * 2u + val(f.src1, f.bit1, iv);
-                atomic_add_c(fbar + size_t(fac0 + i) * 4 + args, v);
+                if (i < nf) {
+                    atomicAdd(&acc_lds[i * 4 + args].x, v.x);
+                    atomicAdd(&acc_lds[i * 4 + args].y, v.y);
+                } else {
+                    atomic_add_c(fbar + size_t(fac0 + i) * 4 + args, v);
+                }
             }
         }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict__ blocks,
+                                                 const TreeGTab* __restrict__ gtabs,
+                                                 const TreeGroup* __restrict__ groups,
+                                                 const TFactor* __restrict__ facs, const double2* __restrict__ fixed,
+                                                 const float2* __restrict__ slots, const double2* __restrict__ gbar,
+                                                 double2* __restrict__ fbar) {
+    __shared__ FactorLds L;
+    __shared__ double2 acc_lds[kTreeMaxPrologueFactors * 4];   // this block's share of the factor adjoints
+    const TreeProBlock blk = blocks[blockIdx.x];
+    const TreeGTab t = gtabs[blk.idx];
+    const TreeGroup* __restrict__ gr = groups + t.group_off;
+    const int fac0 = gr[0].fac_off;
+    const TFactor* __restrict__ tf = facs + fac0;
+    for (int i = threadIdx.x; i < kTreeMaxPrologueFactors * 4; i += 256) acc_lds[i] = make_double2(0.0, 0.0);
+    const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);   // ends with a block barrier
+    tb_gadj_entry(L, nf, t, gr, fac0, tf, fixed, slots, gbar, fbar, acc_lds, int64_t(blk.sub) * 256 + threadIdx.x);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nf * 4; i += 256) {
+        const double2 v = acc_lds[i];
+        if (v.x != 0.0 || v.y != 0.0) atomic_add_c(fbar + size_t(fac0 + (i >> 2)) * 4 + (i & 3), v);
     }
 }
 
@@ -363,19 +396,18 @@ void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows,
 }
 
 void launch_tb_reduce_in(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
-                         const float2* scratch, float2* adj, uint32_t B_eff, hipStream_t stream) {
+                         const float2* scratch, float2* dst, uint32_t B_eff, hipStream_t stream) {
     const int64_t blocks = total_rows * (B_eff / 64u);
     if (blocks <= 0) return;
-    hipLaunchKernelGGL(k_tb_reduce_in, dim3(uint32_t(blocks)), dim3(256), 0, stream, items, n_items, bin, scratch, adj,
+    hipLaunchKernelGGL(k_tb_reduce_in, dim3(uint32_t(blocks)), dim3(256), 0, stream, items, n_items, bin, scratch, dst,
                        B_eff);
 }
 
-void launch_tb_gbar(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg,
-                    const float2* scratch, const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar,
-                    hipStream_t stream) {
+void launch_tb_gbin(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg, const float2* hsum,
+                    const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar, hipStream_t stream) {
     if (total_rows <= 0) return;
-    hipLaunchKernelGGL(k_tb_gbar, dim3(uint32_t(total_rows)), dim3(256), 0, stream, items, n_items, bg, scratch, bits,
-                       B, B_eff, gbar);
+    hipLaunchKernelGGL(k_tb_gbin, dim3(uint32_t(total_rows)), dim3(256), 0, stream, items, n_items, bg, hsum, bits, B,
+                       B_eff, gbar);
 }
 
 void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,

@@ -43,7 +43,10 @@ struct qgm_plan_s {
     size_t off_ttasks_all = 0, off_tfinal_all = 0, off_tbwd = 0, off_tbwdin = 0, off_tbwdg = 0, off_titems = 0;
     size_t off_tslot_off = 0, off_tslot_occ = 0;
     struct LevelItems { int off = 0, n = 0; int64_t rows = 0; };
-    std::vector<LevelItems> lv_exp, lv_in, lv_hred, lv_g;
+    std::vector<LevelItems> lv_exp, lv_g;
+    std::vector<std::vector<LevelItems>> lv_red;   // per level: the stages of its staged sums
+    std::vector<qgm::TreeBwdIn> red_recs;
+    int64_t part_rows[2] = {0, 0};                 // rows of the two partial-sum areas
     std::vector<qgm::TreeBwdItem> items;
     std::vector<int32_t> slot_off_t, slot_occ_t;
     int64_t n_fbar = 0;
@@ -86,6 +89,17 @@ void fixed_matrices(double2 m[qgm::kFixedMats * 4]) {
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+// Bit of a bucket's index space a = (o << k) | w that holds a variable: summed
+// variable i -> i, result axis j -> k + j (-1 if the bucket does not carry it).
+int bucket_abit(const qgm::TreeStep& st, int var) {
+    const int k = st.kg;
+    for (int i = 0; i < k; ++i)
+        if (st.vars[i] == var) return i;
+    for (size_t j = 0; j < st.out_axes.size(); ++j)
+        if (st.out_axes[j] == var) return k + int(j);
+    return -1;
+}
+
 void layout_tree_tables(qgm_plan_t* P) {
     const qgm::TreePlan& t = P->p.tree;
     size_t n_fac = 0, n_groups = 0;
@@ -107,42 +121,102 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tfinal = P->off_tphase + al(sizeof(qgm::TFactor) * (t.phase.size() + 1));
     P->off_tpro = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
     P->off_tg = P->off_tpro + al(sizeof(qgm::TreeProBlock) * size_t(P->n_pro_blocks + 1));
-    // adjoint records and item lists (level by level: expansion, input adjoints, table adjoints)
-    size_t n_in_total = 0;
-    for (auto& st : t.steps) n_in_total += st.in_tensors.size();
+    // adjoint records and item lists (level by level: expansion, staged sums, table adjoints)
     P->items.clear();
+    P->red_recs.clear();
+    P->part_rows[0] = P->part_rows[1] = 0;
     P->lv_exp.assign(t.levels.size(), {});
-    P->lv_in.assign(t.levels.size(), {});
-    P->lv_hred.assign(t.levels.size(), {});
+    P->lv_red.assign(t.levels.size(), {});
     P->lv_g.assign(t.levels.size(), {});
-    {
-        int in_idx = 0;
-        std::vector<int> in_base(t.steps.size(), 0);
-        for (size_t s = 0; s < t.steps.size(); ++s) { in_base[s] = in_idx; in_idx += int(t.steps[s].in_tensors.size()); }
-        for (size_t L = 0; L < t.levels.size(); ++L) {
-            auto add = [&](qgm_plan_s::LevelItems& li, int idx, int64_t rows) {
-                if (li.n == 0) li.off = int(P->items.size());
-                P->items.push_back({idx, int32_t(li.rows)});
-                li.rows += rows;
-                li.n++;
-            };
-            for (int sid : t.levels[L]) {
-                const qgm::TreeStep& st = t.steps[sid];
-                add(P->lv_exp[L], sid, int64_t(1) << (st.out_axes.size() + st.vars.size()));
+    auto add = [&](qgm_plan_s::LevelItems& li, int idx, int64_t rows) {
+        if (li.n == 0) li.off = int(P->items.size());
+        P->items.push_back({idx, int32_t(li.rows)});
+        li.rows += rows;
+        li.n++;
+    };
+    for (size_t L = 0; L < t.levels.size(); ++L) {
+        for (int sid : t.levels[L]) {
+            const qgm::TreeStep& st = t.steps[sid];
+            add(P->lv_exp[L], sid, int64_t(1) << (st.out_axes.size() + st.vars.size()));
+        }
+        // every sum of the level: each input's adjoint (Q_t over the a-bits that are
+        // not its axes) and, with gate slots, H over the a-bits outside the table index
+        struct Sum {
+            int64_t q_row;
+            std::vector<int> axes, free;   // source-row bits of the output index; bits still to sum
+            int32_t sel, row;              // final destination
+        };
+        std::vector<Sum> sums;
+        for (int sid : t.levels[L]) {
+            const qgm::TreeStep& st = t.steps[sid];
+            const int a_bits = int(st.out_axes.size()) + st.kg;
+            for (size_t k = 0; k < st.in_tensors.size(); ++k) {
+                const int tid = st.in_tensors[k];
+                Sum u{t.scratch_row[sid] + int64_t(1 + k) * (int64_t(1) << a_bits), {}, {}, 0,
+                      int32_t(t.tensor_row_all[tid])};
+                std::vector<bool> used(a_bits, false);
+                for (int v : t.tensor_axes[tid]) {
+                    const int ab = bucket_abit(st, v);
+                    u.axes.push_back(ab);
+                    used[ab] = true;
+                }
+                for (int i = 0; i < a_bits; ++i)
+                    if (!used[i]) u.free.push_back(i);
+                sums.push_back(u);
             }
-            for (int sid : t.levels[L]) {
-                const qgm::TreeStep& st = t.steps[sid];
-                for (size_t k = 0; k < st.in_tensors.size(); ++k)
-                    add(P->lv_in[L], in_base[sid] + int(k), int64_t(1) << t.tensor_axes[st.in_tensors[k]].size());
+            if (P->p.n_slots > 0) {
+                Sum u{t.scratch_row[sid], {}, {}, 1, int32_t(t.hsum_row[sid])};
+                std::vector<bool> used(a_bits, false);
+                for (int i = 0; i < st.kg; ++i) u.axes.push_back(i);
+                for (int v : st.gvars) u.axes.push_back(bucket_abit(st, v));
+                for (int ab : u.axes) used[ab] = true;
+                for (int i = 0; i < a_bits; ++i)
+                    if (!used[i]) u.free.push_back(i);
+                sums.push_back(u);
             }
-            for (int sid : t.levels[L]) {   // H summed within each table row: reducer records after the inputs'
-                const qgm::TreeStep& st = t.steps[sid];
-                add(P->lv_hred[L], int(n_in_total) + sid, int64_t(1) << (st.gb() + st.kg));
+        }
+        // stage s sums up to kTbSumBits bits of every unfinished sum; a sum with bits
+        // left writes partial rows (its remaining bits above its axes) to area s % 2
+        for (int stage = 0; !sums.empty(); ++stage) {
+            P->lv_red[L].push_back({});
+            int64_t prow = 0;
+            std::vector<Sum> next;
+            for (Sum& u : sums) {
+                const int m = std::min<int>(qgm::kTbSumBits, int(u.free.size()));
+                const int rest = int(u.free.size()) - m;
+                qgm::TreeBwdIn e{};
+                e.r_t = int32_t(u.axes.size()) + rest;
+                e.n_sum = m;
+                e.q_row = u.q_row;
+                for (size_t p = 0; p < u.axes.size(); ++p) e.pos[p] = u.axes[p];
+                for (int i = 0; i < rest; ++i) e.pos[u.axes.size() + i] = u.free[m + i];
+                for (int f = 0; f < (1 << m); ++f) {
+                    int32_t o = 0;
+                    for (int i = 0; i < m; ++i)
+                        if ((f >> i) & 1) o += int32_t(1) << u.free[i];
+                    e.foff[f] = o;
+                }
+                if (rest == 0) {
+                    e.dst_sel = u.sel;
+                    e.dst_row = u.row;
+                } else {
+                    e.dst_sel = 2;
+                    e.dst_row = int32_t(prow);
+                    Sum w{prow, {}, {}, u.sel, u.row};
+                    for (size_t p = 0; p < u.axes.size(); ++p) w.axes.push_back(int(p));
+                    for (int i = 0; i < rest; ++i) w.free.push_back(int(u.axes.size()) + i);
+                    prow += int64_t(1) << e.r_t;
+                    next.push_back(w);
+                }
+                add(P->lv_red[L].back(), int(P->red_recs.size()), int64_t(1) << e.r_t);
+                P->red_recs.push_back(e);
             }
-            for (int sid : t.levels[L]) {
-                const qgm::TreeStep& st = t.steps[sid];
-                add(P->lv_g[L], sid, int64_t(1) << (st.gb() + st.kg));
-            }
+            P->part_rows[stage % 2] = std::max(P->part_rows[stage % 2], prow);
+            sums.swap(next);
+        }
+        for (int sid : t.levels[L]) {
+            const qgm::TreeStep& st = t.steps[sid];
+            add(P->lv_g[L], sid, int64_t(1) << (st.gb() + st.kg));
         }
     }
     // gate-slot occurrences among the table factors and the phase factors
@@ -170,7 +244,7 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tfinal_all = P->off_ttasks_all + al(sizeof(qgm::TreeTask) * size_t(t.n_tasks + 1));
     P->off_tbwd = P->off_tfinal_all + al(sizeof(int64_t) * (t.finals.size() + 1));
     P->off_tbwdin = P->off_tbwd + al(sizeof(qgm::TreeBwd) * (t.steps.size() + 1));
-    P->off_tbwdg = P->off_tbwdin + al(sizeof(qgm::TreeBwdIn) * (n_in_total + t.steps.size() + 1));
+    P->off_tbwdg = P->off_tbwdin + al(sizeof(qgm::TreeBwdIn) * (P->red_recs.size() + 1));
     P->off_titems = P->off_tbwdg + al(sizeof(qgm::TreeBwdG) * (t.steps.size() + 1));
     P->off_tslot_off = P->off_titems + al(sizeof(qgm::TreeBwdItem) * (P->items.size() + 1));
     P->off_tslot_occ = P->off_tslot_off + al(sizeof(int32_t) * (P->slot_off_t.size() + 1));
@@ -200,19 +274,10 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
     auto* fa = reinterpret_cast<int64_t*>(h + P->off_tfinal_all);
     for (size_t i = 0; i < t.finals.size(); ++i) fa[i] = t.tensor_row_all[t.finals[i]];
     auto* bw = reinterpret_cast<qgm::TreeBwd*>(h + P->off_tbwd);
-    auto* bi = reinterpret_cast<qgm::TreeBwdIn*>(h + P->off_tbwdin);
     auto* bg = reinterpret_cast<qgm::TreeBwdG*>(h + P->off_tbwdg);
-    int in_idx = 0;
-    std::vector<qgm::TreeBwdIn> h_red;
     for (size_t sid = 0; sid < t.steps.size(); ++sid) {
         const qgm::TreeStep& st = t.steps[sid];
         const int r = int(st.out_axes.size()), k = st.kg;
-        // a-bit of a variable: summed variable i -> i, result axis j -> k + j
-        auto abit = [&](int var) {
-            for (int i = 0; i < k; ++i) if (st.vars[i] == var) return i;
-            for (int j = 0; j < r; ++j) if (st.out_axes[j] == var) return k + j;
-            return -1;
-        };
         qgm::TreeBwd d{};
         d.n_in = int32_t(st.in_tensors.size());
         d.k = k;
@@ -227,25 +292,11 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
         for (int j = 0; j < r; ++j)
             for (int p = 0; p < st.gb(); ++p)
                 if (st.out_axes[j] == st.gvars[p]) d.g_str[k + j] = 1 << (k + p);
-        const int64_t arows = int64_t(1) << d.a_bits;
         for (int ti = 0; ti < d.n_in; ++ti) {
             const int tid = st.in_tensors[ti];
             const std::vector<int>& ax = t.tensor_axes[tid];
             d.in_row[ti] = int32_t(t.tensor_row_all[tid]);
-            qgm::TreeBwdIn e{};
-            e.r_t = int32_t(ax.size());
-            e.dst_row = int32_t(t.tensor_row_all[tid]);
-            e.q_row = d.scratch_row + (1 + ti) * arows;
-            std::vector<bool> used(d.a_bits, false);
-            for (int p = 0; p < int(ax.size()); ++p) {
-                const int ab = abit(ax[p]);
-                d.in_str[ti][ab] = 1 << p;
-                e.pos[p] = ab;
-                used[ab] = true;
-            }
-            for (int i = 0; i < d.a_bits; ++i)
-                if (!used[i]) e.free_bits[e.n_free++] = i;
-            bi[in_idx++] = e;
+            for (int p = 0; p < int(ax.size()); ++p) d.in_str[ti][bucket_abit(st, ax[p])] = 1 << p;
         }
         bw[sid] = d;
         qgm::TreeBwdG g{};
@@ -254,23 +305,9 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
         g.h_row = t.hsum_row[sid];
         g.g_off = st.g_off;
         for (int b = 0; b < st.sb(); ++b) g.sig_q[b] = st.sig_q[b];
-        for (int i = 0; i < k; ++i) g.cpos[i] = i;
-        for (int p = 0; p < st.gb(); ++p) g.cpos[k + p] = abit(st.gvars[p]);
-        for (int j = 0; j < r; ++j)
-            if (std::find(st.gvars.begin(), st.gvars.end(), st.out_axes[j]) == st.gvars.end())
-                g.free_bits[g.n_free++] = k + j;
         bg[sid] = g;
-        // H summed over the rows of each table row (a reducer record: table row c <- class of a-rows)
-        qgm::TreeBwdIn hr{};
-        hr.r_t = g.c_bits;
-        hr.n_free = g.n_free;
-        hr.dst_row = int32_t(t.hsum_row[sid]);
-        hr.q_row = d.scratch_row;
-        for (int i = 0; i < g.c_bits; ++i) hr.pos[i] = g.cpos[i];
-        for (int i = 0; i < g.n_free; ++i) hr.free_bits[i] = g.free_bits[i];
-        h_red.push_back(hr);
     }
-    for (size_t i = 0; i < h_red.size(); ++i) bi[in_idx + int(i)] = h_red[i];
+    std::memcpy(h + P->off_tbwdin, P->red_recs.data(), sizeof(qgm::TreeBwdIn) * P->red_recs.size());
     std::memcpy(h + P->off_titems, P->items.data(), sizeof(qgm::TreeBwdItem) * P->items.size());
     std::memcpy(h + P->off_tslot_off, P->slot_off_t.data(), sizeof(int32_t) * P->slot_off_t.size());
     std::memcpy(h + P->off_tslot_occ, P->slot_occ_t.data(), sizeof(int32_t) * P->slot_occ_t.size());
@@ -537,7 +574,7 @@ qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
 // scratch, the row sums of H per table row, the table adjoints (FP64) and the
 // factor adjoints (FP64).
 struct TreeBwdLayout {
-    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, hsum = 0, gbar = 0, fbar = 0, total = 0;
+    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, hsum = 0, part = 0, gbar = 0, fbar = 0, total = 0;
 };
 
 TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
@@ -549,7 +586,8 @@ TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
     L.g = 2 * L.adj;
     L.scratch = L.g + (P->p.n_slots > 0 ? al(uint64_t(t.g_total) * 8) : 0);
     L.hsum = L.scratch + al(uint64_t(t.scratch_rows) * be * 8);
-    L.gbar = L.hsum + al(uint64_t(t.hsum_rows) * be * 8);
+    L.part = L.hsum + al(uint64_t(t.hsum_rows) * be * 8);
+    L.gbar = L.part + al(uint64_t(P->part_rows[0] + P->part_rows[1]) * be * 8);
     L.fbar = L.gbar + al(uint64_t(t.g_total) * 16);
     L.total = L.fbar + al(uint64_t(P->n_fbar) * 4 * 16 + 16);
     return L;
@@ -781,6 +819,8 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     auto* adj = reinterpret_cast<float2*>(ws + L.adj);
     auto* scratch = reinterpret_cast<float2*>(ws + L.scratch);
     auto* hsum = reinterpret_cast<float2*>(ws + L.hsum);
+    float2* part[2] = {reinterpret_cast<float2*>(ws + L.part),
+                       reinterpret_cast<float2*>(ws + L.part) + plan->part_rows[0] * B_eff};
     auto* gbar = reinterpret_cast<double2*>(ws + L.gbar);
     auto* fbar = reinterpret_cast<double2*>(ws + L.fbar);
     float2* gt = p.n_slots > 0 ? reinterpret_cast<float2*>(ws + L.g) : reinterpret_cast<float2*>(tables + plan->off_tg);
@@ -810,15 +850,15 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     const auto* bgd = reinterpret_cast<const qgm::TreeBwdG*>(tables + plan->off_tbwdg);
     for (int Lv = int(t.levels.size()) - 1; Lv >= t.first_level; --Lv) {
         const auto& ex = plan->lv_exp[Lv];
-        const auto& in = plan->lv_in[Lv];
-        const auto& hr = plan->lv_hred[Lv];
         const auto& gg = plan->lv_g[Lv];
-        qgm::launch_tb_expand(items + ex.off, ex.n, ex.rows, bwd, arena, adj, gt, scratch, bits, B, be, s);
-        if (in.n > 0) qgm::launch_tb_reduce_in(items + in.off, in.n, in.rows, bin, scratch, adj, be, s);
-        if (p.n_slots > 0) {
-            qgm::launch_tb_reduce_in(items + hr.off, hr.n, hr.rows, bin, scratch, hsum, be, s);
-            qgm::launch_tb_gbin(items + gg.off, gg.n, gg.rows, bgd, hsum, bits, B, be, gbar, s);
+        qgm::launch_tb_expand(items + ex.off, ex.n, ex.rows, bwd, arena, adj, gt, scratch, bits, B, be,
+                              p.n_slots > 0, s);
+        for (size_t k = 0; k < plan->lv_red[Lv].size(); ++k) {
+            const auto& rs = plan->lv_red[Lv][k];
+            const float2* src = k == 0 ? scratch : part[(k - 1) % 2];
+            qgm::launch_tb_reduce(items + rs.off, rs.n, rs.rows, bin, src, adj, hsum, part[k % 2], be, s);
         }
+        if (p.n_slots > 0) qgm::launch_tb_gbin(items + gg.off, gg.n, gg.rows, bgd, hsum, bits, B, be, gbar, s);
     }
     if (p.n_slots > 0) {
         qgm::launch_tb_gadj(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gbar, fbar, s);

@@ -103,25 +103,26 @@ struct TreeBwd {
     int32_t g_str[32];                          // factor-table index stride of a-bit i (c units)
 };
 
-// Adjoint of input t of a bucket: the sum over the a-bits that are not axes
-// of t (also used to sum H over the rows of each factor-table row).
+// One stage of a sum over a-bits: output row j of the record (an input's
+// adjoint, H summed within a factor-table row, or a partial sum) is the sum of
+// 2^n_sum source rows q_row + a0(j) + foff[f], where a0(j) places bit p of j at
+// source-row bit pos[p].
+constexpr int kTbSumBits = 5;
 struct TreeBwdIn {
-    int32_t r_t, n_free;
-    int32_t dst_row;                            // keep-all adjoint row of input t (row-sum area row for H)
-    int32_t pad;
-    int64_t q_row;                              // scratch row of Q_t
-    int32_t pos[32];                            // a-bit of t's axis p
-    int32_t free_bits[32];                      // a-bits that are not axes of t
+    int32_t r_t, n_sum;                         // output index bits; summed bits (at most kTbSumBits)
+    int32_t dst_row;                            // first output row in the destination area
+    int32_t dst_sel;                            // 0: adjoint arena, 1: row-sum area, 2: partial area
+    int64_t q_row;                              // first source row (scratch, or the other partial area)
+    int32_t pos[32];                            // source-row bit of output index bit p
+    int32_t foff[1 << kTbSumBits];              // source-row offset of summed combination f
 };
 
 // Adjoint of a bucket's factor table, one table row c per block.
 struct TreeBwdG {
-    int32_t c_bits, n_free, sb, pad;            // c_bits = gb + k
+    int32_t c_bits, sb;                         // c_bits = gb + k
     int64_t h_row;                              // row of H summed within table row c = 0 (row-sum area)
     int64_t g_off;                              // table base entry (the table adjoint has the same layout)
     int32_t sig_q[kTreeMaxSig];
-    int32_t cpos[32];                           // a-bit of table-index bit i
-    int32_t free_bits[32];                      // a-bits outside the table index
 };
 
 // A list entry of one adjoint launch: descriptor index and its first row.
@@ -174,9 +175,10 @@ void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase
                     hipStream_t stream);
 void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwd* bwd,
                       const float2* arena, const float2* adj, const float2* gtab, float2* scratch,
-                      const uint64_t* bits, int64_t B, uint32_t B_eff, hipStream_t stream);
-void launch_tb_reduce_in(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
-                         const float2* scratch, float2* dst, uint32_t B_eff, hipStream_t stream);
+                      const uint64_t* bits, int64_t B, uint32_t B_eff, bool write_h, hipStream_t stream);
+void launch_tb_reduce(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
+                      const float2* src, float2* dst_adj, float2* dst_hsum, float2* dst_part, uint32_t B_eff,
+                      hipStream_t stream);
 void launch_tb_gbin(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg, const float2* hsum,
                     const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar, hipStream_t stream);
 void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,

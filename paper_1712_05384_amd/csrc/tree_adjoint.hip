@@ -24,6 +24,7 @@ namespace {
 
 constexpr int kTbMaxGroups = 16;    // factor groups of one table (the planner keeps them below this)
 constexpr int kTbGbarLds = 1 << kTreeMaxSig;
+constexpr uint32_t kTbGadjParts = 8;   // blocks per table-entry block of the factor adjoints (slot factors split)
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
@@ -38,9 +39,13 @@ __device__ __forceinline__ bool slot_factor(const TFactor& f) {
 
 // Entry of an item list whose rows cover `row` (items sorted by row0).
 __device__ __forceinline__ TreeBwdItem find_item(const TreeBwdItem* __restrict__ items, int n_items, int64_t row) {
-    int k = 0;
-    while (k + 1 < n_items && int64_t(items[k + 1].row0) <= row) ++k;
-    return items[k];
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (int64_t(items[mid].row0) <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return items[lo];
 }
 
 }  // namespace
@@ -116,7 +121,8 @@ __global__ void __launch_bounds__(256) k_tb_expand(const TreeBwdItem* __restrict
                                                    int64_t n_units, const TreeBwd* __restrict__ bwd,
                                                    const float2* __restrict__ arena, const float2* __restrict__ adj,
                                                    const float2* __restrict__ gtab, float2* __restrict__ scratch,
-                                                   const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff) {
+                                                   const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                   int write_h) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t be = int64_t(B_eff);
@@ -147,11 +153,13 @@ __global__ void __launch_bounds__(256) k_tb_expand(const TreeBwdItem* __restrict
         float2 T[kTreeMaxIn];
 #pragma unroll
         for (int t = 0; t < kTreeMaxIn; ++t) T[t] = t < n_in ? arena[idx[t] * be + b] : make_float2(1.f, 0.f);
-        float2 h = rb;
-#pragma unroll
-        for (int t = 0; t < kTreeMaxIn; ++t) h = cmulf(h, T[t]);
         const int64_t rows = int64_t(1) << d->a_bits;
-        scratch[(d->scratch_row + a) * be + b] = h;
+        if (write_h) {
+            float2 h = rb;
+#pragma unroll
+            for (int t = 0; t < kTreeMaxIn; ++t) h = cmulf(h, T[t]);
+            scratch[(d->scratch_row + a) * be + b] = h;
+        }
         const float2 base = cmulf(rb, gv);
 #pragma unroll
         for (int t = 0; t < kTreeMaxIn; ++t) {
@@ -165,61 +173,111 @@ __global__ void __launch_bounds__(256) k_tb_expand(const TreeBwdItem* __restrict
     }
 }
 
-// Input adjoints (and row sums of H): block (row j of one result, 64-bitstring
-// group); its four waves sum interleaved quarters of the rows a that map to j.
-__global__ void __launch_bounds__(256) k_tb_reduce_in(const TreeBwdItem* __restrict__ items, int n_items,
-                                                      const TreeBwdIn* __restrict__ bin,
-                                                      const float2* __restrict__ scratch, float2* __restrict__ dst,
-                                                      uint32_t B_eff) {
-    __shared__ float2 part[4][64];
+// Staged sums (input adjoints, and H summed within each factor-table row):
+// wave unit (output row j of one record, 64-bitstring group) adds the 2^n_sum
+// source rows of its class, all loads issued before the first add.  A sum over
+// more than kTbSumBits a-bits is split by the host into stages that pass partial
+// rows between two partial areas.
+template <int NS>
+__device__ __forceinline__ float2 tb_sum_rows(const float2* __restrict__ src, const int32_t* __restrict__ foff,
+                                              int64_t row0, int64_t be, uint32_t b) {
+    float2 v[1 << NS];
+#pragma unroll
+    for (int f = 0; f < (1 << NS); ++f) v[f] = src[(row0 + foff[f]) * be + b];
+#pragma unroll
+    for (int w = (1 << NS) / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int f = 0; f < w; ++f) {
+            v[f].x += v[f + w].x;
+            v[f].y += v[f + w].y;
+        }
+    return v[0];
+}
+
+__global__ void __launch_bounds__(256) k_tb_reduce(const TreeBwdItem* __restrict__ items, int n_items, int64_t n_units,
+                                                   const TreeBwdIn* __restrict__ bin, const float2* __restrict__ src,
+                                                   float2* __restrict__ dst_adj, float2* __restrict__ dst_hsum,
+                                                   float2* __restrict__ dst_part, uint32_t B_eff) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t be = int64_t(B_eff);
     const uint32_t n_bg = B_eff / 64u;
-    const int64_t R = int64_t(blockIdx.x) / n_bg;
-    const uint32_t bg = uint32_t(int64_t(blockIdx.x) - R * n_bg);
-    const TreeBwdItem it = find_item(items, n_items, R);
-    const TreeBwdIn* __restrict__ d = bin + it.idx;
-    const uint32_t j = uint32_t(R - it.row0);
-    const uint32_t b = bg * 64u + lane;
-    uint32_t a0 = 0;
-    for (int p = 0; p < d->r_t; ++p) a0 |= ((j >> p) & 1u) << d->pos[p];
-    const uint32_t n_comb = 1u << d->n_free;
-    float2 acc = make_float2(0.f, 0.f);
-    for (uint32_t f = wave; f < n_comb; f += 4u) {
-        uint32_t a = a0;
-        for (uint32_t m = f; m; m &= m - 1u) a |= 1u << d->free_bits[__builtin_ctz(m)];
-        const float2 v = scratch[(d->q_row + a) * be + b];
-        acc.x += v.x;
-        acc.y += v.y;
-    }
-    part[wave][lane] = acc;
-    __syncthreads();
-    if (wave == 0) {
-        float2 s = part[0][lane];
-        for (int w = 1; w < 4; ++w) {
-            s.x += part[w][lane].x;
-            s.y += part[w][lane].y;
+    for (int64_t u = int64_t(blockIdx.x) * 4 + wave; u < n_units; u += int64_t(gridDim.x) * 4) {
+        const int64_t R = u / n_bg;
+        const uint32_t bg = uint32_t(u - R * n_bg);
+        const TreeBwdItem it = find_item(items, n_items, R);
+        const TreeBwdIn* __restrict__ d = bin + it.idx;
+        const uint32_t j = uint32_t(R - it.row0);
+        const uint32_t b = bg * 64u + lane;
+        int64_t a0 = 0;
+        for (int p = 0; p < d->r_t; ++p) a0 |= int64_t((j >> p) & 1u) << d->pos[p];
+        const int64_t row0 = d->q_row + a0;
+        float2 s;
+        switch (d->n_sum) {
+            case 0: s = tb_sum_rows<0>(src, d->foff, row0, be, b); break;
+            case 1: s = tb_sum_rows<1>(src, d->foff, row0, be, b); break;
+            case 2: s = tb_sum_rows<2>(src, d->foff, row0, be, b); break;
+            case 3: s = tb_sum_rows<3>(src, d->foff, row0, be, b); break;
+            case 4: s = tb_sum_rows<4>(src, d->foff, row0, be, b); break;
+            default: s = tb_sum_rows<5>(src, d->foff, row0, be, b); break;
         }
+        float2* __restrict__ dst = d->dst_sel == 0 ? dst_adj : d->dst_sel == 1 ? dst_hsum : dst_part;
         dst[(int64_t(d->dst_row) + j) * be + b] = s;
     }
 }
 
-// Factor-table adjoint, second pass: block = one table row c, whose row of
-// H' (H summed over the rows of class c, by k_tb_reduce_in) is staged in LDS
-// with every bitstring's output-bit value; thread s then sums the entries with
-// sigma(b) = s (deterministic, no atomics).
-__global__ void __launch_bounds__(256) k_tb_gbin(const TreeBwdItem* __restrict__ items, int n_items,
-                                                 const TreeBwdG* __restrict__ bgd, const float2* __restrict__ hsum,
-                                                 const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
-                                                 double2* __restrict__ gbar) {
+// Factor-table adjoint, second pass: block = one table row c; G-bar[c][s] is
+// the sum of that row of H' (H summed over the rows of class c) over the
+// bitstrings whose output bits give sigma = s.  Up to 8 values of sigma: each
+// thread bins a strided share of the bitstrings in registers, then a fixed-order
+// wave and block reduction (deterministic).
+template <int NSIG>
+__device__ void tb_gbin_small(const TreeBwdG* __restrict__ d, uint32_t c, const float2* __restrict__ hsum,
+                              const uint64_t* __restrict__ bits, int64_t B, int64_t be, double2* __restrict__ gbar) {
+    __shared__ double2 part[4][NSIG];
+    double2 acc[NSIG];
+#pragma unroll
+    for (int s = 0; s < NSIG; ++s) acc[s] = make_double2(0.0, 0.0);
+    const float2* __restrict__ h = hsum + (d->h_row + c) * be;
+    for (int64_t b = threadIdx.x; b < B; b += 256) {
+        const float2 v = h[b];
+        const uint32_t sg = NSIG == 1 ? 0u : gather_sigma(bits[b], d->sig_q, d->sb);
+#pragma unroll
+        for (int s = 0; s < NSIG; ++s)
+            if (sg == uint32_t(s)) {
+                acc[s].x += v.x;
+                acc[s].y += v.y;
+            }
+    }
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < NSIG; ++s) {
+        double x = acc[s].x, y = acc[s].y;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            x += __shfl_xor(x, o);
+            y += __shfl_xor(y, o);
+        }
+        if (lane == 0) part[wave][s] = make_double2(x, y);
+    }
+    __syncthreads();
+    if (threadIdx.x < NSIG) {
+        double2 t = part[0][threadIdx.x];
+        for (int w = 1; w < 4; ++w) {
+            t.x += part[w][threadIdx.x].x;
+            t.y += part[w][threadIdx.x].y;
+        }
+        gbar[d->g_off + (int64_t(c) << d->sb) + threadIdx.x] = t;
+    }
+}
+
+// More than 8 values of sigma: the row of H' is staged in LDS with each
+// bitstring's sigma; thread s sums the entries with sigma(b) = s.
+__device__ void tb_gbin_wide(const TreeBwdG* __restrict__ d, uint32_t c, const float2* __restrict__ hsum,
+                             const uint64_t* __restrict__ bits, int64_t B, int64_t be, double2* __restrict__ gbar) {
     constexpr int CH = 1024;   // bitstrings staged per round
     __shared__ float2 hv[CH];
     __shared__ uint16_t sv[CH];
-    const int64_t be = int64_t(B_eff);
-    const TreeBwdItem it = find_item(items, n_items, blockIdx.x);
-    const TreeBwdG* __restrict__ d = bgd + it.idx;
-    const uint32_t c = uint32_t(int64_t(blockIdx.x) - it.row0);
     const int sb = d->sb;
     const int n_sig = 1 << sb;
     double2 acc[kTbGbarLds / 256];
@@ -253,6 +311,23 @@ __global__ void __launch_bounds__(256) k_tb_gbin(const TreeBwdItem* __restrict__
     }
 }
 
+__global__ void __launch_bounds__(256) k_tb_gbin(const TreeBwdItem* __restrict__ items, int n_items,
+                                                 const TreeBwdG* __restrict__ bgd, const float2* __restrict__ hsum,
+                                                 const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                 double2* __restrict__ gbar) {
+    const TreeBwdItem it = find_item(items, n_items, blockIdx.x);
+    const TreeBwdG* __restrict__ d = bgd + it.idx;
+    const uint32_t c = uint32_t(int64_t(blockIdx.x) - it.row0);
+    const int64_t be = int64_t(B_eff);
+    switch (d->sb) {
+        case 0: tb_gbin_small<1>(d, c, hsum, bits, B, be, gbar); break;
+        case 1: tb_gbin_small<2>(d, c, hsum, bits, B, be, gbar); break;
+        case 2: tb_gbin_small<4>(d, c, hsum, bits, B, be, gbar); break;
+        case 3: tb_gbin_small<8>(d, c, hsum, bits, B, be, gbar); break;
+        default: tb_gbin_wide(d, c, hsum, bits, B, be, gbar); break;
+    }
+}
+
 // Factor adjoints from the table adjoints: per table entry e (blocks as in
 // the factor-table build), for every group q and value iv of its own
 // variables, each gate-slot factor f of q receives
@@ -263,7 +338,7 @@ __global__ void __launch_bounds__(256) k_tb_gbin(const TreeBwdItem* __restrict__
 __device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, const TreeGroup* __restrict__ gr,
                               int fac0, const TFactor* __restrict__ tf, const double2* __restrict__ fixed,
                               const float2* __restrict__ slots, const double2* __restrict__ gbar,
-                              double2* __restrict__ fbar, double2* acc_lds, int64_t e) {
+                              double2* __restrict__ fbar, double2* acc_lds, int64_t e, int part, int n_parts) {
     if (e >= (int64_t(1) << (t.gb + t.k + t.sb))) return;
     const double2 gb = gbar[t.g_off + e];
     if (gb.x == 0.0 && gb.y == 0.0) return;
@@ -293,6 +368,7 @@ __device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, con
             default: return 0u;
         }
     };
+    int n_seen = 0;   // slot factors met so far: this thread takes every n_parts-th from `part`
 #pragma unroll
     for (int q = 0; q < kTbMaxGroups; ++q) {
         if (q >= t.n_groups) break;
@@ -305,6 +381,7 @@ __device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, con
         for (int i = f0; i < f1; ++i) {
             const TFactor f = tf[i];
             if (!slot_factor(f)) continue;
+            if (n_seen++ % n_parts != part) continue;
             for (uint32_t iv = 0; iv < (1u << g.k_int); ++iv) {
                 double2 v = pq;
                 for (int i2 = f0; i2 < f1; ++i2)
@@ -336,7 +413,8 @@ __global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict_
     const TFactor* __restrict__ tf = facs + fac0;
     for (int i = threadIdx.x; i < kTreeMaxPrologueFactors * 4; i += 256) acc_lds[i] = make_double2(0.0, 0.0);
     const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);   // ends with a block barrier
-    tb_gadj_entry(L, nf, t, gr, fac0, tf, fixed, slots, gbar, fbar, acc_lds, int64_t(blk.sub) * 256 + threadIdx.x);
+    tb_gadj_entry(L, nf, t, gr, fac0, tf, fixed, slots, gbar, fbar, acc_lds, int64_t(blk.sub) * 256 + threadIdx.x,
+                  int(blockIdx.y), int(gridDim.y));
     __syncthreads();
     for (int i = threadIdx.x; i < nf * 4; i += 256) {
         const double2 v = acc_lds[i];
@@ -387,20 +465,22 @@ void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase
 
 void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwd* bwd,
                       const float2* arena, const float2* adj, const float2* gtab, float2* scratch,
-                      const uint64_t* bits, int64_t B, uint32_t B_eff, hipStream_t stream) {
+                      const uint64_t* bits, int64_t B, uint32_t B_eff, bool write_h, hipStream_t stream) {
     const int64_t n_units = total_rows * (B_eff / 64u);
     if (n_units <= 0) return;
     const uint32_t grid = uint32_t(std::min<int64_t>((n_units + 3) / 4, kStepMaxGrid));
     hipLaunchKernelGGL(k_tb_expand, dim3(grid), dim3(256), 0, stream, items, n_items, n_units, bwd, arena, adj, gtab,
-                       scratch, bits, B, B_eff);
+                       scratch, bits, B, B_eff, write_h ? 1 : 0);
 }
 
-void launch_tb_reduce_in(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
-                         const float2* scratch, float2* dst, uint32_t B_eff, hipStream_t stream) {
-    const int64_t blocks = total_rows * (B_eff / 64u);
-    if (blocks <= 0) return;
-    hipLaunchKernelGGL(k_tb_reduce_in, dim3(uint32_t(blocks)), dim3(256), 0, stream, items, n_items, bin, scratch, dst,
-                       B_eff);
+void launch_tb_reduce(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdIn* bin,
+                      const float2* src, float2* dst_adj, float2* dst_hsum, float2* dst_part, uint32_t B_eff,
+                      hipStream_t stream) {
+    const int64_t n_units = total_rows * (B_eff / 64u);
+    if (n_units <= 0) return;
+    const uint32_t grid = uint32_t(std::min<int64_t>((n_units + 3) / 4, kStepMaxGrid));
+    hipLaunchKernelGGL(k_tb_reduce, dim3(grid), dim3(256), 0, stream, items, n_items, n_units, bin, src, dst_adj,
+                       dst_hsum, dst_part, B_eff);
 }
 
 void launch_tb_gbin(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwdG* bg, const float2* hsum,
@@ -414,7 +494,7 @@ void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gt
                     const TFactor* facs, const double2* fixed, const float2* slots, const double2* gbar,
                     double2* fbar, hipStream_t stream) {
     if (n_blocks <= 0) return;
-    hipLaunchKernelGGL(k_tb_gadj, dim3(uint32_t(n_blocks)), dim3(256), 0, stream, blocks, gtabs, groups, facs, fixed,
+    hipLaunchKernelGGL(k_tb_gadj, dim3(uint32_t(n_blocks), kTbGadjParts), dim3(256), 0, stream, blocks, gtabs, groups, facs, fixed,
                        slots, gbar, fbar);
 }
 

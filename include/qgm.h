@@ -94,6 +94,18 @@ typedef struct {
     int32_t no_chain_merge;    /* ordering 1 only: 1 = one variable per bucket step; 0 = a bucket whose only
                                   input is an earlier bucket's result absorbs that bucket when the merged
                                   index space grows by at most one bit (up to 3 summed variables) */
+    int32_t tree_exec;         /* ordering 1 only: how qgm_amplitudes runs the buckets.
+                                  0 = auto: one launch per level (the faster of the two on MI355X at every
+                                      batch size measured);
+                                  1 = one launch per level of the elimination tree (the last small levels
+                                      and the amplitude product in one more launch);
+                                  2 = one persistent launch for all levels and the amplitude product: each
+                                      64-bitstring group runs on one accelerator complex and each bucket task
+                                      starts when the tasks making its inputs have signalled completion; the
+                                      workspace then keeps every result at its own rows.  Calls in this mode
+                                      must not run concurrently on one device (each needs the whole GPU at
+                                      once); a launch that cannot proceed gives up after a bounded wait and
+                                      writes NaN amplitudes. */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;
@@ -199,7 +211,9 @@ qgm_status qgm_plan_timings(qgm_plan_t* plan, double* ms, int64_t* n_calls);
  * are host arrays of length n_circ; the pointers they hold follow the rules of
  * qgm_amplitudes (workspaces must not be shared between circuits).  Creation
  * uploads missing plan tables first and captures on private streams; it does
- * not launch anything.  A graph must not outlive its plans or buffers. */
+ * not launch anything.  Branches that run as one persistent launch (tree_exec)
+ * are ordered one after another; the other branches stay concurrent.  A graph
+ * must not outlive its plans or buffers. */
 typedef struct qgm_graph_s qgm_graph_t;
 qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void* const* gate_vals,
                             const uint64_t* const* bits, const int64_t* B, void* const* out,

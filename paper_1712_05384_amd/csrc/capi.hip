@@ -42,6 +42,7 @@ struct qgm_plan_s {
     // tree plans, adjoint: keep-all tasks and final rows, per-bucket records, per-level item lists, slot lists
     size_t off_ttasks_all = 0, off_tfinal_all = 0, off_tbwd = 0, off_tbwdin = 0, off_tbwdg = 0, off_titems = 0;
     size_t off_tslot_off = 0, off_tslot_occ = 0;
+    size_t off_tfdep = 0;   // (first task, count) of the bucket making each rank-0 result
     struct LevelItems { int off = 0, n = 0; int64_t rows = 0; };
     std::vector<LevelItems> lv_exp, lv_g;
     std::vector<std::vector<LevelItems>> lv_red;   // per level: the stages of its staged sums
@@ -248,7 +249,8 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_titems = P->off_tbwdg + al(sizeof(qgm::TreeBwdG) * (t.steps.size() + 1));
     P->off_tslot_off = P->off_titems + al(sizeof(qgm::TreeBwdItem) * (P->items.size() + 1));
     P->off_tslot_occ = P->off_tslot_off + al(sizeof(int32_t) * (P->slot_off_t.size() + 1));
-    P->total = P->off_tslot_occ + al(sizeof(int32_t) * (P->slot_occ_t.size() + 1));
+    P->off_tfdep = P->off_tslot_occ + al(sizeof(int32_t) * (P->slot_occ_t.size() + 1));
+    P->total = P->off_tfdep + al(sizeof(int32_t) * 2 * (t.finals.size() + 1));
 }
 
 // Adjoint tables: the forward tasks with every result at its own rows
@@ -325,6 +327,8 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
     auto* fac = reinterpret_cast<qgm::TFactor*>(h + P->off_tfac);
     auto* pro = reinterpret_cast<qgm::TreeProBlock*>(h + P->off_tpro);
     int n_fac = 0, n_grp = 0, n_pro = 0;
+    std::vector<int> maker(t.tensor_axes.size(), -1);   // bucket that makes each result
+    for (size_t i = 0; i < t.steps.size(); ++i) maker[t.steps[i].out_tensor] = int(i);
     for (size_t i = 0; i < t.steps.size(); ++i) {
         const qgm::TreeStep& st = t.steps[i];
         const int r = int(st.out_axes.size());
@@ -348,7 +352,14 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
         base.n_sig = st.sb();
         base.sb = st.sb();
         base.gshift = st.kg + st.sb();
+        base.n_in = n_in;
+        base.nin_class = qgm::launch_inputs(t.level_max_in[st.level]);
         for (int b = 0; b < st.sb(); ++b) base.sig_q[b] = st.sig_q[b];
+        for (int k = 0; k < n_in; ++k) {
+            const qgm::TreeStep& mk = t.steps[maker[st.in_tensors[k]]];
+            base.dep_off[k] = int32_t(mk.task_off);
+            base.dep_n[k] = int32_t(mk.n_tasks());
+        }
         std::vector<std::vector<int64_t>> str(n_in, std::vector<int64_t>(r, 0));
         std::vector<int64_t> gstr(r, 0);
         for (int k = 0; k < n_in; ++k) {
@@ -408,6 +419,12 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
     for (size_t i = 0; i < t.phase.size(); ++i) ph[i] = t.phase[i];
     auto* fr = reinterpret_cast<int64_t*>(h + P->off_tfinal);
     for (size_t i = 0; i < t.finals.size(); ++i) fr[i] = t.tensor_row[t.finals[i]];
+    auto* fd = reinterpret_cast<int32_t*>(h + P->off_tfdep);
+    for (size_t i = 0; i < t.finals.size(); ++i) {
+        const qgm::TreeStep& mk = t.steps[maker[t.finals[i]]];
+        fd[2 * i] = int32_t(mk.task_off);
+        fd[2 * i + 1] = int32_t(mk.n_tasks());
+    }
 }
 
 void layout_tables(qgm_plan_t* P) {
@@ -752,6 +769,45 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
                                       reinterpret_cast<const qgm::TreeGroup*>(tables + plan->off_tgroup), facs, fixed,
                                       slots, gt, t.ones_g, s);
         mark(2);
+        if (qgm::tree_persistent(p, B)) {
+            // all levels and the amplitude product in one launch, every result at its own rows
+            if (!out) return fail(QGM_E_INVALID, "out is NULL");
+            auto* flags = reinterpret_cast<int32_t*>(ws + w.flags);
+            const int64_t stride = qgm::tree_flag_stride(p);
+            qgm::launch_persist_init(flags, qgm::tree_flag_words(p, B), out, B, p.opts.out_c128 != 0, s);
+            qgm::TreePersist a{};
+            const int64_t task0 = t.levels.empty() ? 0 : t.level_task_off[t.first_level];
+            a.tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks_all) + task0;
+            a.task0 = int32_t(task0);
+            a.n_tasks = int32_t(t.n_tasks - task0);
+            a.final_dep = reinterpret_cast<const int32_t*>(tables + plan->off_tfdep);
+            a.n_final_dep = int32_t(t.finals.size());
+            a.n_final = int32_t(t.finals.size());
+            a.final_rows = reinterpret_cast<const int64_t*>(tables + plan->off_tfinal_all);
+            a.phase = phase;
+            a.n_phase = int32_t(t.phase.size());
+            a.c128 = p.opts.out_c128 != 0 ? 1 : 0;
+            a.fixed = fixed;
+            a.slots = slots;
+            a.arena = arena;
+            a.gtab = gt;
+            a.ones_g = t.ones_g;
+            a.bits = bits;
+            a.B = B;
+            a.B_eff = uint32_t(B_eff);
+            a.flag_stride = int32_t(stride);
+            int max_class = 1;
+            for (int L = t.first_level; L < int(t.levels.size()); ++L)
+                max_class = std::max(max_class, qgm::launch_inputs(t.level_max_in[L]));
+            a.max_class = max_class;
+            a.flags = flags;
+            a.out = out;
+            hipError_t he = qgm::launch_tree_persist(a, s);
+            if (he != hipSuccess) return hip_fail(he, "persistent launch");
+            mark(3);
+            mark(4);
+            return QGM_OK;
+        }
         for (int L = t.first_level; L < t.tail_start; ++L) {
             const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
             qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
@@ -1013,8 +1069,13 @@ qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void
     hipError_t e = hipStreamBeginCapture(streams[0], hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipStreamBeginCapture"); }
     (void)hipEventRecord(events[0], streams[0]);
+    int prev_persist = -1;   // persistent launches each need the whole GPU: their branches run one after another
     for (int i = 0; i < n_circ && result == QGM_OK; ++i) {
         (void)hipStreamWaitEvent(streams[i + 1], events[0], 0);
+        if (qgm::tree_persistent(plans[i]->p, B[i])) {
+            if (prev_persist >= 0) (void)hipStreamWaitEvent(streams[i + 1], events[prev_persist + 1], 0);
+            prev_persist = i;
+        }
         result = qgm_amplitudes(plans[i], gate_vals ? gate_vals[i] : nullptr, bits[i], B[i], out[i], workspace[i],
                                 ws_bytes[i], streams[i + 1]);
         (void)hipEventRecord(events[i + 1], streams[i + 1]);

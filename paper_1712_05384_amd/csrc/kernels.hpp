@@ -49,7 +49,9 @@ struct TreeTask {
     int32_t n_sig, sb, gshift;                  // output bits read by the factors; gshift = k + sb
     int32_t out_row;                            // arena row of the task's first result row
     int32_t g_ent;                              // factor-table entry of (g(o0), w = 0, sigma = 0)
-    int32_t pad0, pad1;
+    int32_t n_in;                               // inputs of the bucket
+    int32_t nin_class;                          // input variant of its level's launch (launch_inputs), which
+                                                //   fixes the result rows a unit computes
     int32_t in_row[kTreeMaxIn];                 // arena row of input t at (o0, w = 0); -1 for t beyond the
                                                 //   bucket's inputs (the wave reads the constant 1 instead)
     int32_t sig_q[kTreeMaxSig];                 // sigma bit i = bit sig_q[i] of the bitstring
@@ -57,6 +59,38 @@ struct TreeTask {
     int32_t in_inc[kTreeMaxIn][kTreeOcBits];    // row change of input t when o -> o + 1 with ctz(o + 1) = j
     int32_t g_inc[kTreeOcBits];                 // factor-table g change for the same steps
     int32_t pad2;
+    int32_t dep_off[kTreeMaxIn];                // tasks of the bucket that makes input t: [dep_off, dep_off + dep_n)
+    int32_t dep_n[kTreeMaxIn];
+};
+
+// One persistent launch of the bucket elimination (k_tree_persist): every
+// task of every level and the amplitude product.  The flags area holds the
+// abort word at [0], one word per (complex, rank) of the launch's work-groups
+// from kPersistSeen0, and from kPersistFlags0 one completion flag per
+// (bitstring group, task), the group's flags contiguous at a stride of
+// flag_stride words.
+struct TreePersist {
+    const TreeTask* tasks;                      // tasks [task0, task0 + n_tasks) in level order (keep-all rows)
+    int32_t task0, n_tasks;
+    const int32_t* final_dep;                   // (first task, count) of each bucket making a rank-0 result
+    int32_t n_final_dep;
+    int32_t n_final;
+    const int64_t* final_rows;
+    const TFactor* phase;
+    int32_t n_phase;
+    int32_t c128;
+    const double2* fixed;
+    const float2* slots;
+    float2* arena;
+    const float2* gtab;
+    int64_t ones_g;
+    const uint64_t* bits;
+    int64_t B;
+    uint32_t B_eff;
+    int32_t flag_stride;
+    int32_t max_class;                          // largest input variant among the tasks (launch_inputs)
+    int32_t* flags;
+    void* out;
 };
 
 // Factor table of a bucket (prologue kernel): entry e = (((g << k) | w) << sb)
@@ -164,6 +198,8 @@ void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGT
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        hipStream_t stream);
+hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream);
+void launch_persist_init(int32_t* flags, int64_t n_flags, void* out, int64_t B, bool c128, hipStream_t stream);
 void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask* tasks, float2* arena,
                       const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,
                       int n_phase, const double2* fixed, const float2* slots, const uint64_t* bits, int64_t B,

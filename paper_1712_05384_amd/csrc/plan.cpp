@@ -363,6 +363,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         return QGM_E_UNSUPPORTED;
     }
     if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
+    if (opts.tree_exec < 0 || opts.tree_exec > 2) { *err = "tree_exec must be 0..2"; return QGM_E_INVALID; }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }
@@ -444,17 +445,28 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     return QGM_OK;
 }
 
+bool tree_persistent(const Plan& p, int64_t) { return p.is_tree && p.opts.tree_exec == 2; }
+
+int64_t tree_flag_stride(const Plan& p) { return (p.tree.n_tasks + 31) / 32 * 32; }
+
+int64_t tree_flag_words(const Plan& p, int64_t B) {
+    return kPersistFlags0 + padded_batch(B) / 64 * tree_flag_stride(p);
+}
+
 WsLayout workspace_layout(const Plan& p, int64_t B) {
     auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
     WsLayout w;
     const uint64_t be = uint64_t(batch_eff(p, B));
     if (p.is_tree) {
-        w.f0 = w.f1 = w.var_ids = 0;
-        // factor tables live in the workspace only when the circuit reads gate values (otherwise the
-        // plan's device tables hold them, built once)
-        w.g = al(uint64_t(p.tree.arena_rows) * be * 8);
-        w.var_ids = w.g + (p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0);
-        w.total = w.var_ids;
+        // results (lifetime-packed rows; every result at its own rows for the persistent launch), factor
+        // tables only when the circuit reads gate values (otherwise the plan's device tables hold them,
+        // built once), the persistent launch's flags
+        const bool persist = tree_persistent(p, B);
+        w.f0 = w.f1 = 0;
+        w.g = al(uint64_t(persist ? p.tree.arena_rows_all : p.tree.arena_rows) * be * 8);
+        w.flags = w.g + (p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0);
+        w.var_ids = w.flags;
+        w.total = w.flags + (persist ? al(uint64_t(tree_flag_words(p, B)) * 4) : 0);
         return w;
     }
     const uint64_t fbytes = al((uint64_t(1) << p.r_max) * be * 8);

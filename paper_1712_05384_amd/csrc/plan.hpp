@@ -100,8 +100,13 @@ inline int64_t batch_eff(const Plan& p, int64_t B) { return padded_batch(B) << p
 // and the G table.  Ordering 1: the arena of bucket results (f0) and, when
 // the circuit reads gate values, the factor tables (g).
 struct WsLayout {
-    uint64_t f0 = 0, f1 = 0, var_ids = 0, g = 0, total = 0;
+    uint64_t f0 = 0, f1 = 0, var_ids = 0, g = 0, flags = 0, total = 0;
 };
 WsLayout workspace_layout(const Plan& p, int64_t B);
+// Bucket plans: whether qgm_amplitudes runs a batch of B in one persistent launch,
+// and the words of one bitstring group's completion flags in that launch.
+bool tree_persistent(const Plan& p, int64_t B);
+int64_t tree_flag_stride(const Plan& p);
+int64_t tree_flag_words(const Plan& p, int64_t B);   // the whole flags area (header, ranks, flags)
 
 }  // namespace qgm

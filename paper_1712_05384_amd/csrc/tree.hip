@@ -267,6 +267,172 @@ __global__ void __launch_bounds__(256) k_tree_final(const int64_t* __restrict__ 
     write_amplitude(P, n_lds, phase, n_phase, fixed, slots, final_rows, n_final, arena, bits[b], b, B_eff, out, c128);
 }
 
+// ---- persistent launch: every level and the amplitude product at once ----
+//
+// Wave unit (task, bitstring group g) needs only the results of its inputs'
+// tasks for the same group, so a launch can run all levels without a kernel
+// boundary if each unit waits for exactly those.  Group g is pinned to the
+// accelerator complex (XCD) g mod 8: a work-group reads the complex it runs on
+// from its XCC_ID register and serves that complex's groups, its rank among
+// the complex's work-groups being blockIdx / 8 (work-groups are dealt to the
+// complexes in turn; a rank met twice aborts the launch), so a result row of
+// group g is written and read through one L2.  Completion is signalled by one flag per (group, task), set with an
+// agent-scope atomic store after the unit's stores are complete (s_waitcnt
+// vmcnt(0): acknowledged by that L2), and polled with agent-scope atomic loads.
+// Every result has its own rows for the whole launch (keep-all layout), so no
+// L1 line read by a consumer can predate its producer's store.  Each XCD's
+// waves take the units of its groups in increasing (task, group) order with a
+// fixed stride; a unit waits only on units of lower index, and the grid fits
+// the GPU at once, so the lowest unfinished unit can always proceed.  A wait
+// that exceeds kPersistSpin polls sets the abort word; later waits return at
+// once and the amplitudes of the launch are written as NaN, so every wave
+// still ends (amplitudes start as NaN, so one that is never written reads NaN).
+constexpr int kPersistSpin = 1 << 20;
+
+__device__ __forceinline__ int32_t ld_flag(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until flags f[0, n) are all set (64 per poll, one per lane).
+__device__ void persist_wait(const int32_t* f, int n, int32_t* abort_word, uint32_t lane) {
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const bool mine = i0 + int(lane) < n;
+        for (int spin = 0;; ++spin) {
+            const int32_t v = mine ? ld_flag(f + i0 + lane) : 1;
+            if (__all(v != 0)) break;
+            if (ld_flag(abort_word) != 0) return;
+            if (spin >= kPersistSpin) {
+                if (lane == 0) st_flag(abort_word, 1);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+template <int MAXC>
+__global__ void __launch_bounds__(256) k_tree_persist(const TreePersist a) {
+    __shared__ PhaseLds P;
+    const int n_lds = stage_phase(P, a.phase, a.n_phase, a.fixed, a.slots);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t* abort_word = a.flags;
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));   // HW_REG_XCC_ID[3:0]
+    const uint32_t q = xcc % uint32_t(kPersistXcds);
+    const uint32_t rank = blockIdx.x / kPersistXcds;
+    if (threadIdx.x == 0) {
+        // a complex outside 0..7, or a (complex, rank) pair met twice, breaks the pinning: abort (units still run)
+        const int32_t seen = __hip_atomic_exchange(a.flags + kPersistSeen0 + q * kPersistMaxRanks + rank, 1,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (xcc >= uint32_t(kPersistXcds) || seen != 0) st_flag(abort_word, 2);
+    }
+    const uint32_t n_bg = a.B_eff / 64u;
+    if (q >= n_bg) return;
+    const uint32_t nbx = (n_bg - q + kPersistXcds - 1) / kPersistXcds;   // groups q, q + 8, ...
+    const uint32_t n_waves = (gridDim.x / kPersistXcds) * 4u;
+    const uint32_t w = rank * 4u + wave;
+    const int64_t n_units = int64_t(a.n_tasks + 1) * nbx;
+    const int64_t be = int64_t(a.B_eff);
+    for (int64_t u = w; u < n_units; u += n_waves) {
+        const int32_t ti = int32_t(u / nbx);
+        const uint32_t bg = q + kPersistXcds * uint32_t(u - int64_t(ti) * nbx);
+        const uint32_t b = bg * 64u + lane;
+        const uint64_t x = int64_t(b) < a.B ? a.bits[b] : 0ull;
+        int32_t* fl = a.flags + kPersistFlags0 + int64_t(bg) * a.flag_stride - a.task0;   // indexed by task number
+        if (ti < a.n_tasks) {
+            // the dependency lists are read from the record in memory (uniform index: scalar loads), not
+            // from the register copy, which a run-time index would move to scratch
+            const TreeTask* __restrict__ tp = a.tasks + ti;
+            const int n_in = tp->n_in;
+            for (int t = 0; t < n_in; ++t) persist_wait(fl + tp->dep_off[t], tp->dep_n[t], abort_word, lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // no input load moves above the polls
+            const TreeTask tk = *tp;
+            // the variant the task's rows were laid out for (the launch carries those up to the plan's largest)
+            if (MAXC <= 1 || tk.nin_class == 1) tree_task<1>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be);
+            else if (MAXC <= 2 || tk.nin_class == 2) tree_task<2>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be);
+            else if (MAXC <= 3 || tk.nin_class == 3) tree_task<3>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be);
+            else if (MAXC <= 4 || tk.nin_class == 4) tree_task<4>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be);
+            else tree_task<kTreeMaxIn>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // no result store moves below the flag
+            __builtin_amdgcn_s_waitcnt(0);   // the unit's result stores are complete in L2
+            if (lane == 0) st_flag(fl + a.task0 + ti, 1);
+        } else {
+            for (int f = 0; f < a.n_final_dep; ++f)
+                persist_wait(fl + a.final_dep[2 * f], a.final_dep[2 * f + 1], abort_word, lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (int64_t(b) < a.B) {
+                if (ld_flag(abort_word) != 0) {
+                    const double nan = __builtin_nan("");
+                    if (a.c128) static_cast<double2*>(a.out)[b] = make_double2(nan, nan);
+                    else static_cast<float2*>(a.out)[b] = make_float2(float(nan), float(nan));
+                } else {
+                    write_amplitude(P, n_lds, a.phase, a.n_phase, a.fixed, a.slots, a.final_rows, a.n_final, a.arena,
+                                    x, b, a.B_eff, a.out, a.c128);
+                }
+            }
+        }
+    }
+}
+
+// Clears the flags of a persistent launch and sets its amplitudes to NaN.
+__global__ void __launch_bounds__(256) k_persist_init(int32_t* __restrict__ flags, int64_t n_flags,
+                                                      void* __restrict__ out, int64_t B, int c128) {
+    const double nan = __builtin_nan("");
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_flags + B; i += int64_t(gridDim.x) * 256) {
+        if (i < n_flags) flags[i] = 0;
+        else if (c128) static_cast<double2*>(out)[i - n_flags] = make_double2(nan, nan);
+        else static_cast<float2*>(out)[i - n_flags] = make_float2(float(nan), float(nan));
+    }
+}
+
+void launch_persist_init(int32_t* flags, int64_t n_flags, void* out, int64_t B, bool c128, hipStream_t stream) {
+    const int64_t n = n_flags + B;
+    if (n <= 0) return;
+    const uint32_t grid = uint32_t(std::min<int64_t>((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_persist_init, dim3(grid), dim3(256), 0, stream, flags, n_flags, out, B, c128 ? 1 : 0);
+}
+
+// Grid: per XCD, as many work-groups as its compute units hold at once (the
+// whole grid is resident), but no more than the XCD's units need.
+template <int MAXC>
+static hipError_t launch_persist_c(const TreePersist& a, hipStream_t stream) {
+    static thread_local int cached_dev = -1, per_xcd = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev != cached_dev) {
+        int n_cu = 0, occ = 0;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tree_persist<MAXC>),
+                                                         256, 0);
+        if (e != hipSuccess) return e;
+        if (n_cu < kPersistXcds || occ < 1) return hipErrorInvalidConfiguration;
+        per_xcd = std::min((n_cu / kPersistXcds) * occ, kPersistMaxRanks);
+        cached_dev = dev;
+    }
+    const int64_t n_bg = a.B_eff / 64u;
+    const int64_t nbx = (n_bg + kPersistXcds - 1) / kPersistXcds;
+    const int64_t want = (int64_t(a.n_tasks + 1) * nbx + 3) / 4;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(per_xcd, want));
+    hipLaunchKernelGGL(k_tree_persist<MAXC>, dim3(uint32_t(blocks * kPersistXcds)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream) {
+    switch (a.max_class) {
+        case 1: return launch_persist_c<1>(a, stream);
+        case 2: return launch_persist_c<2>(a, stream);
+        case 3: return launch_persist_c<3>(a, stream);
+        case 4: return launch_persist_c<4>(a, stream);
+        default: return launch_persist_c<kTreeMaxIn>(a, stream);
+    }
+}
+
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                           const TFactor* facs, const double2* fixed, const float2* slots, float2* gtab,
                           int64_t ones_g, hipStream_t stream) {

@@ -35,6 +35,13 @@ namespace qgm {
 struct Plan;
 
 constexpr int kTreeMaxRank = 28;    // rank of a bucket result
+// Persistent launch (qgm_amplitudes, tree_exec): the flags area holds the
+// abort word at [0], one word per (complex, rank) of its work-groups from
+// kPersistSeen0, and the completion flags from kPersistFlags0.
+constexpr int kPersistXcds = 8;                 // accelerator complexes (each with its own L2) of one MI355X
+constexpr int kPersistMaxRanks = 256;           // work-groups per complex in one launch, at most
+constexpr int kPersistSeen0 = 64;
+constexpr int kPersistFlags0 = kPersistSeen0 + kPersistXcds * kPersistMaxRanks;
 constexpr int kTreeMaxIn = 8;       // earlier results multiplied in one bucket
 constexpr int kTreeMaxSig = 12;     // output bits read by one bucket's factors
 constexpr int kTreeMaxGBits = 10;   // variables of a bucket's factor table besides v

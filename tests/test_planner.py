@@ -286,3 +286,18 @@ def test_chain_merge_shortens_the_tree():
         assert max(len(s["vars"]) for s in b["buckets"]) <= 3
         for s in b["buckets"]:
             assert s["kg"] == len(s["vars"])
+
+
+def test_tree_exec_modes_and_persistent_workspace():
+    """tree_exec 2 keeps every result at its own rows and adds completion
+    flags; 0 (auto) and 1 run one launch per level."""
+    import paper_1712_05384_amd as Q
+    c = C.random_grid_circuit(4, 4, 16, 2)
+    per = Q.plan(c, ordering=1, tree_exec=2)
+    lev = Q.plan(c, ordering=1, tree_exec=1)
+    auto = Q.plan(c, ordering=1)
+    assert per.workspace_bytes(1024) > lev.workspace_bytes(1024)
+    assert auto.workspace_bytes(1024) == lev.workspace_bytes(1024)
+    assert per.workspace_bytes(64) > lev.workspace_bytes(64)
+    with pytest.raises(Exception):
+        Q.plan(c, ordering=1, tree_exec=3)

@@ -375,6 +375,7 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
                 const int64_t sj = j < r ? str[k][j] : 0;
                 base.in_inc[k][j] = int32_t(sj - low);
                 low += sj;
+                if (sj != 0) base.in_omask[k] |= 1 << j;
             }
         }
         for (int j = 0; j < r; ++j)
@@ -385,6 +386,7 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
             const int64_t sj = j < r ? gstr[j] : 0;
             base.g_inc[j] = int32_t(sj - low);
             low += sj;
+            if (sj != 0) base.g_omask |= 1 << j;
         }
         // task c covers result rows [c * unit_rows, (c + 1) * unit_rows), wrapping for small results
         const int64_t n_ch = st.n_tasks();

@@ -61,6 +61,9 @@ struct TreeTask {
     int32_t pad2;
     int32_t dep_off[kTreeMaxIn];                // tasks of the bucket that makes input t: [dep_off, dep_off + dep_n)
     int32_t dep_n[kTreeMaxIn];
+    int32_t in_omask[kTreeMaxIn];               // bit j: input t's row changes along the unit's result row bit j
+    int32_t g_omask;                            // the same for the factor-table entry
+    int32_t pad3;
 };
 
 // One persistent launch of the bucket elimination (k_tree_persist): every

@@ -72,6 +72,7 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
                                           int64_t sig, uint32_t b, int64_t be) {
     constexpr int W = 1 << K;
     constexpr int WC = W < 8 ? W : 8;          // summed-variable values per load batch
+    static_assert(WC == W, "one load batch holds every summed value (the repeat copies index within it)");
     constexpr int OB = tree_unit_rows(NIN, K);
     // input rows and factor-table entry of the unit's rows, and the offset of
     // each summed value w in each input (scalar)
@@ -96,6 +97,23 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
         for (int t = 0; t < NIN; ++t) row[oi][t] = row[oi - 1][t] + tk.in_inc[t][j];
         gent[oi] = gent[oi - 1] + (int64_t(tk.g_inc[j]) << tk.gshift);
     }
+    // An entry repeats an earlier one when the input (or the table) does not vary
+    // along the bit that distinguishes them: row i repeats row i - lowbit(i) if
+    // input t's stride along result bit ctz(i) is 0, and summed value w repeats
+    // w - lowbit(w) if t does not carry summed variable ctz(w).  The repeats
+    // (uniform, per task) are not loaded: all other loads are issued first,
+    // then the repeats are copied in registers.
+    uint32_t in_om[NIN], in_wm[NIN];
+#pragma unroll
+    for (int t = 0; t < NIN; ++t) {
+        in_om[t] = uint32_t(tk.in_omask[t]);
+        uint32_t wm = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (tk.in_vs[t][i] != 0) wm |= 1u << i;
+        in_wm[t] = wm;
+    }
+    const uint32_t g_om = uint32_t(tk.g_omask);
     float2 acc[OB];
 #pragma unroll
     for (int i = 0; i < OB; ++i) acc[i] = make_float2(0.f, 0.f);
@@ -108,13 +126,53 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
             for (int t = 0; t < NIN; ++t) {
                 // an input the bucket does not have reads the constant 1 (same address in every lane)
                 const float2* __restrict__ src = tk.in_row[t] >= 0 ? ain + row[i][t] * be + b : gtab + ones_g;
+                const bool rep_i = i > 0 && !((in_om[t] >> __builtin_ctz(uint32_t(i))) & 1u);
 #pragma unroll
-                for (int w = 0; w < WC; ++w) a[i][t][w] = src[off[t][w0 + w]];
+                for (int w = 0; w < WC; ++w) {
+                    const int wa = w0 + w;
+                    const bool rep_w = w > 0 && !((in_wm[t] >> __builtin_ctz(uint32_t(wa))) & 1u);
+                    if (!rep_i && !rep_w) a[i][t][w] = src[off[t][wa]];
+                }
             }
 #pragma unroll
-        for (int i = 0; i < OB; ++i)
+        for (int i = 0; i < OB; ++i) {
+            const bool rep_i = i > 0 && !((g_om >> __builtin_ctz(uint32_t(i))) & 1u);
+            if (!rep_i) {
 #pragma unroll
-            for (int w = 0; w < WC; ++w) q[i][w] = gtab[gent[i] + (int64_t(w0 + w) << tk.sb) + sig];
+                for (int w = 0; w < WC; ++w) q[i][w] = gtab[gent[i] + (int64_t(w0 + w) << tk.sb) + sig];
+            }
+        }
+        // the repeats, in ascending order (each copies an entry already final).  The
+        // masks are re-read through an empty asm so that the compiler cannot fold a
+        // copy into the load it replaces (which would wait on each load in turn)
+        uint32_t om2[NIN], wm2[NIN];
+        uint32_t g_om2 = __builtin_amdgcn_readfirstlane(g_om);   // uniform per task
+#pragma unroll
+        for (int t = 0; t < NIN; ++t) {
+            om2[t] = __builtin_amdgcn_readfirstlane(in_om[t]);
+            wm2[t] = __builtin_amdgcn_readfirstlane(in_wm[t]);
+            asm volatile("" : "+s"(om2[t]), "+s"(wm2[t]));
+        }
+        asm volatile("" : "+s"(g_om2));
+#pragma unroll
+        for (int i = 0; i < OB; ++i) {
+#pragma unroll
+            for (int t = 0; t < NIN; ++t) {
+                const bool rep_i = i > 0 && !((om2[t] >> __builtin_ctz(uint32_t(i))) & 1u);
+#pragma unroll
+                for (int w = 0; w < WC; ++w) {
+                    const int wa = w0 + w;
+                    const bool rep_w = w > 0 && !((wm2[t] >> __builtin_ctz(uint32_t(wa))) & 1u);
+                    if (rep_i) a[i][t][w] = a[i > 0 ? i - (i & -i) : 0][t][w];
+                    else if (rep_w) a[i][t][w] = a[i][t][w > 0 ? w - (wa & -wa) : 0];
+                }
+            }
+            const bool rep_g = i > 0 && !((g_om2 >> __builtin_ctz(uint32_t(i))) & 1u);
+            if (rep_g) {
+#pragma unroll
+                for (int w = 0; w < WC; ++w) q[i][w] = q[i > 0 ? i - (i & -i) : 0][w];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < OB; ++i)
 #pragma unroll

@@ -322,19 +322,60 @@ int absorb_leaves(const Plan& p, const Model& m, std::vector<RStep>& steps, std:
 // Turns the merged raw steps into the plan: compact result ids, levels,
 // factor tables (index c = (g << kg) | w, kg = most summed variables of the
 // level), arena rows, sigma rows and wave tasks.
+// Axis order of a bucket's result: a wave unit covers the result rows that
+// differ in the lowest kTreeOcBits axes, and an input that does not carry one
+// of them is read once for the rows that differ in it.  So those positions go,
+// greedily, to the axes that leave the fewest distinct input rows per unit,
+//   sum over inputs t of 2^(|U & axes(t)| + |summed & axes(t)|),
+// U the axes chosen so far (elimination order breaks ties and orders the rest).
+// The order is free: every reader indexes a result through its axis strides.
+static std::vector<int> unit_axis_order(const RStep& st, const std::vector<std::vector<int>>& out_of) {
+    std::vector<int> rest = st.out, chosen;
+    auto carries = [&](int in, int u) {
+        const std::vector<int>& ax = out_of[in];
+        return std::find(ax.begin(), ax.end(), u) != ax.end();
+    };
+    while (int(chosen.size()) < kTreeOcBits && !rest.empty()) {
+        size_t best = 0;
+        double best_cost = std::numeric_limits<double>::infinity();
+        for (size_t c = 0; c < rest.size(); ++c) {
+            double cost = 0;
+            for (int in : st.ins) {
+                int e = carries(in, rest[c]) ? 1 : 0;
+                for (int u : chosen) e += carries(in, u) ? 1 : 0;
+                for (int v : st.vars) e += carries(in, v) ? 1 : 0;
+                cost += double(int64_t(1) << e);
+            }
+            if (cost < best_cost) { best_cost = cost; best = c; }
+        }
+        chosen.push_back(rest[best]);
+        rest.erase(rest.begin() + long(best));
+    }
+    chosen.insert(chosen.end(), rest.begin(), rest.end());
+    return chosen;
+}
+
 static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector<int>& order,
                                 const std::vector<RStep>& rs, const std::vector<RTensor>& rt, TreePlan& t,
                                 std::string* err) {
     const int nF = int(order.size());
     std::vector<int> pos(nF);
     for (int i = 0; i < nF; ++i) pos[order[i]] = i;
+    // result axes (free-variable indices) of every raw result, then their unit-friendly order
+    std::vector<std::vector<int>> out_of(rt.size());
+    for (const RStep& st : rs)
+        if (st.alive) out_of[st.out_tensor] = st.out;
+    std::vector<std::vector<int>> out_ord(rs.size());
+    for (size_t i = 0; i < rs.size(); ++i)
+        if (rs[i].alive) out_ord[i] = unit_axis_order(rs[i], out_of);
     std::vector<int> tmap(rt.size(), -1);
     t.tensor_axes.clear();
-    for (const RStep& st : rs) {
+    for (size_t i = 0; i < rs.size(); ++i) {
+        const RStep& st = rs[i];
         if (!st.alive) continue;
         tmap[st.out_tensor] = int(t.tensor_axes.size());
         std::vector<int> ax;
-        for (int u : st.out) ax.push_back(m.free_var[u]);
+        for (int u : out_ord[i]) ax.push_back(m.free_var[u]);
         t.tensor_axes.push_back(ax);
     }
     const int T = int(t.tensor_axes.size());
@@ -345,12 +386,13 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     std::vector<int> sigq;
     std::vector<std::vector<std::pair<std::vector<int>, std::vector<int>>>> step_groups;   // (own vars, factors)
     double bytes = 0, flops = 0;
-    for (const RStep& st : rs) {
+    for (size_t si = 0; si < rs.size(); ++si) {
+        const RStep& st = rs[si];
         if (!st.alive) continue;
         TreeStep ts;
         for (int u : st.vars) ts.vars.push_back(m.free_var[u]);
         ts.out_tensor = tmap[st.out_tensor];
-        for (int u : st.out) ts.out_axes.push_back(m.free_var[u]);
+        for (int u : out_ord[si]) ts.out_axes.push_back(m.free_var[u]);
         int level = 0;
         for (int in : st.ins) {
             const int ti = tmap[in];

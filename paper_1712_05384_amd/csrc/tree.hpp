@@ -104,7 +104,8 @@ struct TreeStep {
     int kg = 1;                         // summed-variable bits of the table index (= vars.size())
     int level = 0;                      // level in the elimination tree (0: no earlier result)
     int out_tensor = -1;                // id of the result
-    std::vector<int> out_axes;          // result axes (variables), elimination position ascending
+    std::vector<int> out_axes;          // result axes (variables); the first kTreeOcBits chosen for wave-unit
+                                        //   reuse (unit_axis_order), the rest in elimination order
     std::vector<int> in_tensors;        // earlier results multiplied in
     std::vector<int> gvars;             // factor-table variables besides the summed ones (index bits kg..)
     std::vector<int> sig_q;             // sigma bit i = output bit of qubit sig_q[i]

@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # plain 1 GiB copy gives), valid for the kernel source with this hash.
 MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
-    ("c2_5x5_d25", 1): {"bytes_per_launch": 10497900.1, "source": "tree.hip", "sha256_16": "f98d0bf7e31fb5ec"},
+    ("c2_5x5_d25", 1): {"bytes_per_launch": 10191007.2, "source": "tree.hip", "sha256_16": "73c35d3b94342a27"},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
 
@@ -192,13 +192,9 @@ def dominant_kernel(args, p, info, B, elim_ms, kernels):
                   "the last small levels and the FP64 output in one launch)")
         n_launch = info["level_launches"]
         alg_bytes = B_eff * sum(s["bytes_per_b"] for s in info["buckets"])
-        # loads the kernel issues (cache-served re-reads of broadcast inputs, padding rows included)
-        lv_in, lv_k = {}, {}
-        for s in info["buckets"]:
-            lv_in[s["level"]] = max(lv_in.get(s["level"], 0), s["n_in"])
-            lv_k[s["level"]] = max(lv_k.get(s["level"], 1), s["kg"])
-        issued = sum(8 * max(2 ** s["r_out"], 8) * (2 ** lv_k[s["level"]] * (lv_in[s["level"]] + 1) + 1)
-                     for s in info["buckets"]) * B_eff
+        # row loads and stores the kernel issues (cache-served re-reads of broadcast inputs, constant-1
+        # padding, factor-table entries), from the plan's per-bucket count
+        issued = sum(s["issued_bytes_per_b"] for s in info["buckets"]) * B_eff
         cfg = {"buckets": info["n_buckets"], "tree_levels": info["n_levels"], "launches": n_launch,
                "bytes_per_amp": info["bytes_per_amp"]}
         extra = {"issued_load_store_bytes_per_launch": issued / n_launch}

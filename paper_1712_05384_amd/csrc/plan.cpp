@@ -494,6 +494,31 @@ static void json_factor(std::ostringstream& o, const TFactor& f) {
     o << "[" << f.type << "," << f.mat << "," << f.src0 << "," << f.bit0 << "," << f.src1 << "," << f.bit1 << "]";
 }
 
+// Row loads and stores one wave unit of a bucket issues (64 lanes x 8 bytes
+// each): the distinct input rows (an input is read once for the unit rows
+// and summed values it does not vary along), the constant 1 for each input
+// slot beyond the bucket's own, the distinct factor-table entries, and the
+// unit's result rows.
+static int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
+    const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));
+    const int r = int(st.out_axes.size());
+    auto count_in = [&](const std::vector<int>& ax, int lo, int hi, const std::vector<int>& from) {
+        int n = 0;
+        for (int j = lo; j < hi && j < int(from.size()); ++j)
+            if (std::find(ax.begin(), ax.end(), from[j]) != ax.end()) ++n;
+        return n;
+    };
+    int64_t n = 0;
+    for (int tid : st.in_tensors) {
+        const std::vector<int>& ax = t.tensor_axes[tid];
+        n += int64_t(1) << (count_in(ax, 0, std::min(ob_bits, r), st.out_axes) + count_in(ax, 0, st.kg, st.vars));
+    }
+    const int cls = launch_inputs(t.level_max_in[st.level]);
+    n += cls - int(st.in_tensors.size());
+    n += int64_t(1) << (count_in(st.gvars, 0, std::min(ob_bits, r), st.out_axes) + st.kg);
+    return n + st.unit_rows;
+}
+
 static std::string tree_json(const Plan& p, int detail) {
     const TreePlan& t = p.tree;
     std::ostringstream o;
@@ -520,7 +545,8 @@ static std::string tree_json(const Plan& p, int detail) {
         o << ",\"kg\":" << st.kg << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
-          << ",\"bytes_per_b\":" << tree_step_bytes(t, st);
+          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows
+          << ",\"issued_bytes_per_b\":" << 8 * st.n_tasks() * tree_unit_accesses(t, st);
         if (detail >= 1) {
             o << ",\"out_tensor\":" << st.out_tensor;
             o << ",\"out_axes\":"; json_ints(o, st.out_axes);

@@ -360,6 +360,18 @@ def extras(Q, C, torch, np, stream, args):
         print(f"# c5 graph ordering {ordering}: {ms:.3f} ms per launch ({total} amplitudes)", file=sys.stderr,
               flush=True)
         del g
+    # cross-entropy statistics and sampling from a set (App. B, App. C) over 2^22 complex64 amplitudes
+    nx = 1 << 22
+    ax = torch.from_numpy(C.random_amplitudes(30, nx, 1).astype(np.complex64)).cuda()
+    ux = torch.from_numpy(C.random_uniforms(1 << 20, 1)).cuda()
+    ms_x = _time(lambda: Q.xeb(ax, 30, stream=stream), 10, stream, torch)
+    ms_s = _time(lambda: Q.sample_from_set(ax, ux, stream=stream), 10, stream, torch)
+    out["xeb"] = {"workload": "2^22 complex64 amplitudes (Porter-Thomas statistics); 2^20 draws from the set",
+                  "xeb_ms": round(ms_x, 4), "xeb_read_GBps": round(8 * nx / (ms_x / 1e3) / 1e9, 1),
+                  "xeb_frac_of_hbm": round(8 * nx / (ms_x / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "sample_set_ms": round(ms_s, 4),
+                  "note": "times include the per-call workspace allocation of the Python wrapper"}
+    print(f"# xeb: {ms_x:.3f} ms, sample_set: {ms_s:.3f} ms", file=sys.stderr, flush=True)
     return out
 
 

@@ -223,6 +223,38 @@ qgm_status qgm_graph_launch(qgm_graph_t* graph, void* stream);
 /* Destroys the graph (NULL is ignored). */
 void qgm_graph_destroy(qgm_graph_t* graph);
 
+/* ---- Cross-entropy benchmarking and sampling on top of the amplitudes ------
+ * Both take a device array of B amplitudes (complex64 when c128 = 0, else
+ * complex128), e.g. the out array of qgm_amplitudes, and a caller-allocated,
+ * 256-byte aligned device workspace of at least qgm_xeb_workspace_bytes(B)
+ * bytes; they only enqueue kernels on `stream` (NULL: the null stream).
+ *
+ * qgm_xeb (App. B): with p_j = |amp_j|^2 in FP64, writes 8 doubles to the
+ * device array out: [0] sum_j log p_j, [1] sum_j p_j, [2] sum_j p_j log p_j (the
+ * three over the nonzero p_j), [3] the number of zero p_j, [4] the cross entropy
+ * of the batch taken as a sample of a device's output, -mean log p_j over the
+ * nonzero p_j (Eq. (cee)), [5] the fidelity estimate of Eq. (ae),
+ * (H_0 - [4]) / (H_0 - H(p_U)) with the Porter-Thomas values H_0 = n log 2 +
+ * gamma and H(p_U) = n log 2 - 1 + gamma (gamma: Euler's constant), [6] the
+ * entropy of the output distribution estimated from the batch taken as a
+ * uniformly chosen set, -(2^n / B) sum_j p_j log p_j (App. C), [7] (2^n / B)
+ * sum_j p_j (1 + O(1/sqrt B) for such a set).  Sums run in a fixed order: the
+ * same input gives the same bits.  Errors: QGM_E_INVALID for B < 1, n_qubits
+ * outside 1..64, a NULL pointer or an unaligned workspace; QGM_E_OOM when
+ * ws_bytes is too small.
+ *
+ * qgm_sample_set (App. C): draws m indices j of the batch, each with
+ * probability p_j / sum_k p_k: draw i uses the caller's uniform u[i] in [0, 1)
+ * (device doubles; the random numbers are the caller's) and writes to idx[i]
+ * (device int64) the first j whose FP64 inclusive cumulative sum of p exceeds
+ * u[i] times the total (B - 1 if none).  Errors as for qgm_xeb (m < 0 is
+ * QGM_E_INVALID; m = 0 only scans). */
+qgm_status qgm_xeb_workspace_bytes(int64_t B, uint64_t* bytes);
+qgm_status qgm_xeb(const void* amps, int32_t c128, int64_t B, int32_t n_qubits, double* out, void* workspace,
+                   uint64_t ws_bytes, void* stream);
+qgm_status qgm_sample_set(const void* amps, int32_t c128, int64_t B, const double* u, int64_t m, int64_t* idx,
+                          void* workspace, uint64_t ws_bytes, void* stream);
+
 /* Destroys a plan and frees its device tables (NULL is ignored). */
 void qgm_plan_destroy(qgm_plan_t* plan);
 

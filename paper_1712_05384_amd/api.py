@@ -233,6 +233,49 @@ class Graph:
             self._h = None
 
 
+def xeb(amps, n_qubits: int, *, stream=None):
+    """Cross-entropy statistics of a batch of amplitudes (qgm_xeb, App. B): a
+    float64 device tensor [sum log p, sum p, sum p log p, zeros, cross entropy
+    (Eq. (cee)), fidelity (Eq. (ae), Porter-Thomas H_0 and H), entropy from a
+    uniform set (App. C), (2^n / B) sum p]."""
+    import torch
+    a = amps.reshape(-1)
+    if a.dtype not in (torch.complex64, torch.complex128) or not a.is_cuda:
+        raise TypeError("amps must be a complex64 or complex128 CUDA tensor")
+    a = a.contiguous()
+    L = N.lib()
+    B = int(a.numel())
+    wsb = ctypes.c_uint64()
+    N.check(L.qgm_xeb_workspace_bytes(B, ctypes.byref(wsb)))
+    ws = torch.empty(int(wsb.value), dtype=torch.uint8, device=a.device)
+    out = torch.empty(8, dtype=torch.float64, device=a.device)
+    s = stream if stream is not None else torch.cuda.current_stream(a.device)
+    N.check(L.qgm_xeb(a.data_ptr(), 1 if a.dtype == torch.complex128 else 0, B, int(n_qubits), out.data_ptr(),
+                      ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+    return out
+
+
+def sample_from_set(amps, uniforms, *, stream=None):
+    """Indices drawn from a set of bitstrings with probability p_j / sum p
+    (qgm_sample_set, App. C); uniforms: float64 device tensor in [0, 1), one
+    per draw (the caller's random numbers)."""
+    import torch
+    a = amps.reshape(-1).contiguous()
+    if a.dtype not in (torch.complex64, torch.complex128) or not a.is_cuda:
+        raise TypeError("amps must be a complex64 or complex128 CUDA tensor")
+    u = uniforms.reshape(-1).to(a.device, torch.float64).contiguous()
+    L = N.lib()
+    B, m = int(a.numel()), int(u.numel())
+    wsb = ctypes.c_uint64()
+    N.check(L.qgm_xeb_workspace_bytes(B, ctypes.byref(wsb)))
+    ws = torch.empty(int(wsb.value), dtype=torch.uint8, device=a.device)
+    idx = torch.empty(max(m, 1), dtype=torch.int64, device=a.device)
+    s = stream if stream is not None else torch.cuda.current_stream(a.device)
+    N.check(L.qgm_sample_set(a.data_ptr(), 1 if a.dtype == torch.complex128 else 0, B, u.data_ptr(), m,
+                             idx.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+    return idx[:m]
+
+
 def plan(circuit, open_qubits=(), **opts) -> Plan:
     return Plan(circuit, open_qubits, **opts)
 

@@ -166,6 +166,21 @@ def random_bitstrings(n: int, count: int, seed: int) -> np.ndarray:
     return rng.integers(0, 2 ** 63, count, dtype=np.uint64) * 2 + rng.integers(0, 2, count, dtype=np.uint64)
 
 
+def random_amplitudes(n: int, count: int, seed: int, zeros: int = 0) -> np.ndarray:
+    """count complex amplitudes with independent Gaussian real and imaginary
+    parts of variance 2^-n / 2 (Porter-Thomas statistics for p = |a|^2), the
+    first `zeros` set to 0; complex128."""
+    rng = np.random.default_rng(seed + 3_000_000)
+    a = (rng.standard_normal(count) + 1j * rng.standard_normal(count)) * np.sqrt(2.0 ** (-n) / 2.0)
+    a[:zeros] = 0
+    return a
+
+
+def random_uniforms(count: int, seed: int) -> np.ndarray:
+    """count uniform doubles in [0, 1) (the random numbers of a sampling step)."""
+    return np.random.default_rng(seed + 4_000_000).random(count)
+
+
 # The five workloads (grid, depth, seed, bitstring count).
 WORKLOADS = {
     "c1_4x4_d16": dict(rows=4, cols=4, depth=16, seed=101, batch=64),

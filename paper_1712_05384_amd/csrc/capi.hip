@@ -1033,6 +1033,49 @@ qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
     return QGM_OK;
 }
 
+qgm_status qgm_xeb_workspace_bytes(int64_t B, uint64_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(QGM_E_INVALID, "bytes is NULL");
+    if (B < 1) return fail(QGM_E_INVALID, "B < 1");
+    *bytes = qgm::xeb_workspace_bytes(B);
+    return QGM_OK;
+}
+
+static qgm_status xeb_check(const void* amps, int64_t B, const void* out, void* workspace, uint64_t ws_bytes) {
+    if (B < 1) return fail(QGM_E_INVALID, "B < 1");
+    if (!amps || !out || !workspace) return fail(QGM_E_INVALID, "amps, output and workspace must be device pointers");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < qgm::xeb_workspace_bytes(B))
+        return fail(QGM_E_OOM, "workspace too small: need " + std::to_string(qgm::xeb_workspace_bytes(B)) + " bytes");
+    return QGM_OK;
+}
+
+qgm_status qgm_xeb(const void* amps, int32_t c128, int64_t B, int32_t n_qubits, double* out, void* workspace,
+                   uint64_t ws_bytes, void* stream) {
+    g_err.clear();
+    qgm_status st = xeb_check(amps, B, out, workspace, ws_bytes);
+    if (st != QGM_OK) return st;
+    if (n_qubits < 1 || n_qubits > 64) return fail(QGM_E_INVALID, "n_qubits must be 1..64");
+    qgm::launch_xeb(amps, c128 != 0, B, n_qubits, out, static_cast<double*>(workspace), static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
+qgm_status qgm_sample_set(const void* amps, int32_t c128, int64_t B, const double* u, int64_t m, int64_t* idx,
+                          void* workspace, uint64_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (m < 0) return fail(QGM_E_INVALID, "m < 0");
+    if (m > 0 && (!u || !idx)) return fail(QGM_E_INVALID, "u and idx must be device pointers");
+    qgm_status st = xeb_check(amps, B, m > 0 ? static_cast<const void*>(idx) : amps, workspace, ws_bytes);
+    if (st != QGM_OK) return st;
+    qgm::launch_sample_set(amps, c128 != 0, B, u, m, idx, static_cast<double*>(workspace),
+                           static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
 qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void* const* gate_vals,
                             const uint64_t* const* bits, const int64_t* B, void* const* out,
                             void* const* workspace, const uint64_t* ws_bytes, qgm_graph_t** graph) {

@@ -202,6 +202,11 @@ void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const fl
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        hipStream_t stream);
 hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream);
+// Cross-entropy statistics and sampling from a set of amplitudes (xeb.hip).
+uint64_t xeb_workspace_bytes(int64_t B);
+void launch_xeb(const void* amps, bool c128, int64_t B, int n_qubits, double* out, double* ws, hipStream_t stream);
+void launch_sample_set(const void* amps, bool c128, int64_t B, const double* u, int64_t m, int64_t* idx, double* ws,
+                       hipStream_t stream);
 void launch_persist_init(int32_t* flags, int64_t n_flags, void* out, int64_t B, bool c128, hipStream_t stream);
 void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask* tasks, float2* arena,
                       const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,

@@ -1,0 +1,65 @@
+"""GPU parity of qgm_xeb and qgm_sample_set (App. B, App. C) with the oracle on
+the same seeded amplitudes and uniforms: the FP64 sums to rounding (order
+differs), the sampled indices exactly except where a draw lands within
+rounding of a cumulative-sum boundary; end to end on amplitudes of the
+bucket path against the oracle's state-vector amplitudes."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import xeb as X
+from paper_1712_05384_amd import circuits as C
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("n,B,c128,zeros", [(16, 1, False, 0), (16, 100, False, 3), (20, 300_000, True, 5),
+                                            (30, 4097, False, 0), (12, 70_000, False, 1000)])
+def test_xeb_sums_match_oracle(n, B, c128, zeros):
+    import paper_1712_05384_amd as Q
+    a = C.random_amplitudes(n, B, B + n, zeros=zeros)
+    a = a if c128 else a.astype(np.complex64)
+    _say("case xeb n=%d B=%d c128=%d zeros=%d" % (n, B, c128, zeros))
+    got = Q.xeb(torch.from_numpy(a).cuda(), n).cpu().numpy()
+    ref = X.xeb_stats(a, n)
+    assert got[3] == ref[3]
+    assert np.allclose(got, ref, rtol=1e-11, atol=0), (got, ref)
+
+
+@pytest.mark.parametrize("B,m,c128", [(1, 5, False), (1000, 10_000, False), (300_000, 100_000, True)])
+def test_sample_set_matches_oracle(B, m, c128):
+    import paper_1712_05384_amd as Q
+    a = C.random_amplitudes(20, B, 7 + B, zeros=min(B - 1, 11))
+    a = a if c128 else a.astype(np.complex64)
+    u = C.random_uniforms(m, m)
+    _say("case sample_set B=%d m=%d" % (B, m))
+    got = Q.sample_from_set(torch.from_numpy(a).cuda(), torch.from_numpy(u).cuda()).cpu().numpy()
+    p = X.probabilities(a)
+    ref = X.sample_from_set(p, u)
+    diff = np.nonzero(got != ref)[0]
+    c = np.cumsum(p)
+    for i in diff:   # a draw may differ only where its target sits within rounding of a boundary
+        t = u[i] * c[-1]
+        assert np.min(np.abs(c - t)) <= 1e-12 * c[-1], (i, got[i], ref[i])
+    assert len(diff) <= 2
+    assert np.all((got >= 0) & (got < B))
+    assert np.all(p[got] > 0) or B == 1
+
+
+def test_xeb_end_to_end_on_bucket_amplitudes():
+    """Cross entropy and set entropy of the 4x4 depth-16 workload's 64 amplitudes,
+    computed on the GPU from the bucket path, against the oracle's FP64 values."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c1_4x4_d16")
+    amps = Q.plan(c, ordering=1).amplitudes(bits)
+    got = Q.xeb(amps, c.n).cpu().numpy()
+    ref = X.xeb_stats(oracle.sv_amplitudes(c.n, c.gates, None, bits), c.n)
+    assert np.allclose(got[[1, 2, 4, 6, 7]], ref[[1, 2, 4, 6, 7]], rtol=1e-4)

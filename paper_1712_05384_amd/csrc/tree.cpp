@@ -329,6 +329,9 @@ int absorb_leaves(const Plan& p, const Model& m, std::vector<RStep>& steps, std:
 //   sum over inputs t of 2^(|U & axes(t)| + |summed & axes(t)|),
 // U the axes chosen so far (elimination order breaks ties and orders the rest).
 // The order is free: every reader indexes a result through its axis strides.
+// After them come the axes that the largest inputs do not carry (by the total
+// rows of the inputs lacking the axis): consecutive tasks then re-read the same
+// rows of those inputs while they are still in the L2.
 static std::vector<int> unit_axis_order(const RStep& st, const std::vector<std::vector<int>>& out_of) {
     std::vector<int> rest = st.out, chosen;
     auto carries = [&](int in, int u) {
@@ -351,7 +354,14 @@ static std::vector<int> unit_axis_order(const RStep& st, const std::vector<std::
         chosen.push_back(rest[best]);
         rest.erase(rest.begin() + long(best));
     }
-    chosen.insert(chosen.end(), rest.begin(), rest.end());
+    std::vector<double> lack(rest.size(), 0.0);
+    for (size_t c = 0; c < rest.size(); ++c)
+        for (int in : st.ins)
+            if (!carries(in, rest[c])) lack[c] += double(int64_t(1) << out_of[in].size());
+    std::vector<size_t> idx(rest.size());
+    for (size_t c = 0; c < idx.size(); ++c) idx[c] = c;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return lack[x] > lack[y]; });
+    for (size_t c : idx) chosen.push_back(rest[c]);
     return chosen;
 }
 

@@ -206,15 +206,37 @@ __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const 
 // task record arrives, so the unit waits on two memory round trips (task and
 // bitstring together, then inputs and factor table together) before its
 // stores.
+//
+// With at least 8 groups (pin != 0) the units are dealt by complex: the blocks
+// with blockIdx = x mod 8 take, task by task, the groups g = x mod 8 (work-groups
+// go to the 8 accelerator complexes in turn, so a group's rows stay in one L2
+// and the re-read rows of consecutive tasks hit there).  The split depends only
+// on blockIdx: every unit runs once whatever the dispatch does.
 template <int NIN>
 __global__ void __launch_bounds__(256) k_tree_level(const TreeTask* __restrict__ tasks, uint32_t n_units,
                                                     const float2* __restrict__ ain, float2* __restrict__ aout,
                                                     const float2* __restrict__ gtab, int64_t ones_g,
                                                     const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
-                                                    uint32_t n_bg) {
+                                                    uint32_t n_bg, int pin) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t be = int64_t(B_eff);
+    if (pin) {
+        const uint32_t q = blockIdx.x % uint32_t(kPersistXcds);
+        const uint32_t nbx = (n_bg - q + kPersistXcds - 1) / kPersistXcds;   // groups q, q + 8, ... (n_bg >= 8)
+        const uint32_t n_tasks = n_units / n_bg;
+        const uint32_t n_q = n_tasks * nbx;
+        const uint32_t stride = (gridDim.x / kPersistXcds) * 4u;
+        for (uint32_t v = (blockIdx.x / kPersistXcds) * 4u + wave; v < n_q; v += stride) {
+            const uint32_t ti = v / nbx;
+            const uint32_t bg = q + kPersistXcds * (v - ti * nbx);
+            const uint32_t b = bg * 64u + lane;
+            const uint64_t x = int64_t(b) < B ? bits[b] : 0ull;
+            const TreeTask tk = tasks[ti];
+            tree_task<NIN>(tk, x, ain, aout, gtab, ones_g, b, be);
+        }
+        return;
+    }
     for (uint32_t u = blockIdx.x * 4u + wave; u < n_units; u += gridDim.x * 4u) {
         const uint32_t ti = u / n_bg;
         const uint32_t bg = u - ti * n_bg;
@@ -508,9 +530,11 @@ static void launch_level_n(hipStream_t stream, const TreeTask* tasks, int64_t n_
     for (int64_t t0 = 0; t0 < n_tasks; t0 += per) {
         const int64_t nt = std::min<int64_t>(per, n_tasks - t0);
         const uint32_t n_units = uint32_t(nt * n_bg);
-        const uint32_t grid = uint32_t(std::min<int64_t>((int64_t(n_units) + 3) / 4, kStepMaxGrid));
+        uint32_t grid = uint32_t(std::min<int64_t>((int64_t(n_units) + 3) / 4, kStepMaxGrid));
+        const int pin = n_bg >= uint32_t(kPersistXcds) ? 1 : 0;
+        if (pin) grid = std::max<uint32_t>(grid / kPersistXcds, 1) * kPersistXcds;   // a multiple of 8 blocks
         hipLaunchKernelGGL(k_tree_level<NIN>, dim3(grid), dim3(256), 0, stream, tasks + t0, n_units, ain, aout, gtab,
-                           ones_g, bits, B, B_eff, n_bg);
+                           ones_g, bits, B, B_eff, n_bg, pin);
     }
 }
 

@@ -77,8 +77,10 @@ typedef struct {
 typedef struct {
     int32_t ordering;          /* 0 = vertical order of Sec. IV.A (qubits along the shorter side first);
                                   1 = bucket elimination (App. A) along a greedy treewidth order (min-degree /
-                                      min-fill with randomised tie breaks, the cheapest of several; Sec. IV.B),
-                                      forward amplitudes only: no open qubits, no slicing, no qgm_backward */
+                                      min-fill with randomised tie breaks, the cheapest of several; Sec. IV.B);
+                                      open qubits (their last variables are never summed: one more bucket
+                                      multiplies every result left on them), qgm_backward without open qubits,
+                                      no slicing */
     int32_t precision;         /* 0 = complex64 with FP32 arithmetic */
     int32_t kernel_policy;     /* 0 = auto (the vector-ALU kernel, one row per thread); 1 = the same;
                                   2 = FP32 matrix-core kernel for every step it supports (K and N of

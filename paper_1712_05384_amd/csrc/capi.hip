@@ -824,7 +824,12 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
             mark(3);
         } else {
             mark(3);
-            if (out)
+            if (out && t.n_open > 0)   // a set of 2^n_open amplitudes per bitstring
+                qgm::launch_tree_final_open(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed, slots,
+                                            arena, t.open_tensor >= 0 ? t.tensor_row[t.open_tensor] : -1, t.n_open,
+                                            uint32_t(t.zero_mask), bits, B, uint32_t(B_eff), out,
+                                            p.opts.out_c128 != 0, s);
+            else if (out)
                 qgm::launch_tree_final(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed, slots, arena,
                                        bits, B, uint32_t(B_eff), out, p.opts.out_c128 != 0, s);
         }
@@ -859,6 +864,7 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
                                 uint64_t ws_bytes, void* stream) {
     const qgm::Plan& p = plan->p;
     const qgm::TreePlan& t = p.tree;
+    if (t.n_open > 0) return fail(QGM_E_UNSUPPORTED, "qgm_backward with ordering 1 supports no open qubits");
     if (B == 0) return QGM_OK;
     if (!bits || !grad_amps || !workspace || (p.n_slots > 0 && (!gate_vals || !gate_grads)))
         return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "

@@ -201,6 +201,10 @@ void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGT
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        hipStream_t stream);
+void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase,
+                            const double2* fixed, const float2* slots, const float2* arena, int64_t open_row,
+                            int n_open, uint32_t zero_mask, const uint64_t* bits, int64_t B, uint32_t B_eff,
+                            void* out, bool c128, hipStream_t stream);
 hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream);
 // Cross-entropy statistics and sampling from a set of amplitudes (xeb.hip).
 uint64_t xeb_workspace_bytes(int64_t B);

@@ -524,7 +524,8 @@ static std::string tree_json(const Plan& p, int detail) {
     std::ostringstream o;
     o.precision(17);
     o << "{\"ordering\":1,\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols
-      << ",\"n_vars\":" << p.vars.size() << ",\"n_free\":" << t.n_free << ",\"n_open\":0,\"n_slots\":" << p.n_slots
+      << ",\"n_vars\":" << p.vars.size() << ",\"n_free\":" << t.n_free << ",\"n_open\":" << t.n_open
+      << ",\"n_slots\":" << p.n_slots
       << ",\"n_steps\":0,\"n_buckets\":" << t.steps.size() << ",\"n_levels\":" << t.levels.size()
       << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
@@ -534,7 +535,8 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
-      << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size();
+      << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
+      << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask;
     o << ",\"order\":"; json_ints(o, t.order);
     o << ",\"finals\":"; json_ints(o, t.finals);
     o << ",\"steps\":[],\"buckets\":[";

@@ -40,6 +40,8 @@ struct Model {
     std::vector<int> free_var;    // free index -> variable id
     std::vector<RawFactor> facs;  // factors with at least one free variable
     std::vector<TFactor> phase;
+    std::vector<int> kept;        // free indices of the open qubits' last variables, output bit ascending
+    int zero_mask = 0;            // output bits of open qubits without non-diagonal gates (amplitude 0 if set)
 };
 
 TFactor fixed_factor(const Plan& p, const Model& m, const RawFactor& f) {
@@ -140,6 +142,7 @@ struct RStep {
     std::vector<std::pair<std::vector<int>, std::vector<int>>> absorbed;   // (variables, factors) of folded buckets
     int out_tensor = -1;
     bool alive = true;
+    bool open = false;       // multiplies the results over the open qubits' variables (sums nothing)
 };
 
 struct RTensor {
@@ -200,7 +203,8 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, st
     std::vector<int> tmade;
     std::set<int> gset;
     std::vector<int> sigq;
-    for (int i = 0; i < nF; ++i) {
+    const int n_elim = nF - int(m.kept.size());   // the kept variables close the order and are not summed
+    for (int i = 0; i < n_elim; ++i) {
         const int v = order[i];
         std::set<int> A;
         int level = 0;
@@ -250,6 +254,63 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, st
             steps->push_back(st);
         }
     }
+    // open qubits: every result and factor left on the kept variables is multiplied into one
+    // result over all of them (a chain of such buckets when more than kTreeMaxIn results remain)
+    if (!m.kept.empty()) {
+        std::vector<int> ins, facs;
+        for (int i = n_elim; i < nF; ++i) {
+            ins.insert(ins.end(), bten[i].begin(), bten[i].end());
+            facs.insert(facs.end(), bfac[i].begin(), bfac[i].end());
+        }
+        while (true) {
+            const bool last = int(ins.size()) <= kTreeMaxIn;
+            std::vector<int> take(ins.begin(), ins.begin() + std::min<size_t>(ins.size(), kTreeMaxIn));
+            std::vector<int> fac_here = last ? facs : std::vector<int>{};
+            std::vector<int> out;
+            int level = 0;
+            if (last) {
+                out = m.kept;
+            } else {
+                std::set<int> A;
+                for (int tid : take) A.insert(taxes[tid].begin(), taxes[tid].end());
+                for (int u : m.kept)
+                    if (A.count(u)) out.push_back(u);
+            }
+            for (int tid : take) level = std::max(level, tmade[tid] + 1);
+            table_vars(p, m, fac_here, {}, gset, sigq);
+            if (!fits(int(out.size()), int(take.size()), int(gset.size()), 0, int(sigq.size()))) {
+                r.why = "the bucket over the open qubits exceeds the kernel limits";
+                return r;
+            }
+            const double rows = double(int64_t(1) << out.size());
+            double bytes = 8.0 * rows;
+            for (int tid : take) bytes += 8.0 * double(int64_t(1) << taxes[tid].size());
+            r.bytes += bytes;
+            r.flops += rows * 6.0 * double(take.size());
+            r.levels = std::max(r.levels, level + 1);
+            r.max_rank = std::max(r.max_rank, int(out.size()));
+            r.max_in = std::max(r.max_in, int(take.size()));
+            const int tid = int(taxes.size());
+            taxes.push_back(out);
+            tmade.push_back(level);
+            if (steps) {
+                RStep st;
+                st.out = out;
+                st.ins = take;
+                st.facs = fac_here;
+                st.out_tensor = tid;
+                st.open = true;
+                RTensor rt;
+                rt.axes = out;
+                rt.producer = int(steps->size());
+                tens->push_back(rt);
+                steps->push_back(st);
+            }
+            if (last) break;
+            ins.erase(ins.begin(), ins.begin() + long(take.size()));
+            ins.insert(ins.begin(), tid);
+        }
+    }
     r.ok = true;
     return r;
 }
@@ -263,9 +324,10 @@ void merge_chains(const Plan& p, const Model& m, std::vector<RStep>& steps, std:
     std::vector<int> sigq;
     for (size_t i = 0; i < steps.size(); ++i) {
         RStep& par = steps[i];
-        if (par.ins.size() != 1) continue;
+        if (par.ins.size() != 1 || par.open) continue;
         const int tid = par.ins[0];
         RStep& ch = steps[tens[tid].producer];
+        if (ch.open) continue;
         std::vector<int> V = ch.vars;
         V.insert(V.end(), par.vars.begin(), par.vars.end());
         std::vector<int> facs = ch.facs;
@@ -376,8 +438,8 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     for (const RStep& st : rs)
         if (st.alive) out_of[st.out_tensor] = st.out;
     std::vector<std::vector<int>> out_ord(rs.size());
-    for (size_t i = 0; i < rs.size(); ++i)
-        if (rs[i].alive) out_ord[i] = unit_axis_order(rs[i], out_of);
+    for (size_t i = 0; i < rs.size(); ++i)   // a bucket over the open qubits keeps their order (output index bits)
+        if (rs[i].alive) out_ord[i] = rs[i].open ? rs[i].out : unit_axis_order(rs[i], out_of);
     std::vector<int> tmap(rt.size(), -1);
     t.tensor_axes.clear();
     for (size_t i = 0; i < rs.size(); ++i) {
@@ -420,6 +482,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         step_groups.push_back({{std::vector<int>{}, st.facs}});
         for (auto& a : st.absorbed) step_groups.back().push_back(a);
         if (ts.out_axes.empty()) t.finals.push_back(ts.out_tensor);
+        if (st.open) t.open_tensor = ts.out_tensor;   // the chain's last bucket comes last
         const double rows = double(int64_t(1) << ts.out_axes.size());
         double b = 8.0 * rows;
         for (int ti : ts.in_tensors) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
@@ -499,7 +562,10 @@ double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
 
 qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t = TreePlan{};
-    if (p.n_open != 0) { *err = "ordering 1 supports no open qubits"; return QGM_E_UNSUPPORTED; }
+    if (p.n_open != 0 && p.opts.tree_exec == 2) {
+        *err = "the persistent launch (tree_exec 2) supports no open qubits";
+        return QGM_E_UNSUPPORTED;
+    }
     if (p.opts.min_sliced_vars != 0 || p.opts.max_rank != 0) {
         *err = "ordering 1 does not slice (min_sliced_vars and max_rank must be 0)";
         return QGM_E_UNSUPPORTED;
@@ -512,14 +578,16 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         const VarInfo& vi = p.vars[v];
         if (vi.is_c0) {
             m.kind[v] = VK_ZERO;
-            if (vi.is_final) {   // a worldline without non-diagonal gates: b = 0 must equal x_q
+            if (vi.is_final && vi.open_idx >= 0) {   // open, without non-diagonal gates: only output bit 0
+                m.zero_mask |= 1 << vi.open_idx;
+            } else if (vi.is_final) {   // a worldline without non-diagonal gates: b = 0 must equal x_q
                 TFactor d{};
                 d.type = TF_DELTA0;
                 d.src0 = TS_SIG;
                 d.bit0 = vi.qubit;
                 m.phase.push_back(d);
             }
-        } else if (vi.is_final) {
+        } else if (vi.is_final && vi.open_idx < 0) {
             m.kind[v] = VK_SIG;
         } else {
             m.fi[v] = int(m.free_var.size());
@@ -527,6 +595,12 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         }
     }
     const int nF = int(m.free_var.size());
+    // the open qubits' last variables (free, never summed), by output bit
+    std::vector<std::pair<int, int>> kept;
+    for (int v = 0; v < nv; ++v)
+        if (p.vars[v].is_final && !p.vars[v].is_c0 && p.vars[v].open_idx >= 0) kept.push_back({p.vars[v].open_idx, m.fi[v]});
+    std::sort(kept.begin(), kept.end());
+    for (auto& k : kept) m.kept.push_back(k.second);
     for (const GateRec& g : p.recs) {
         RawFactor f{};
         f.mat = g.mat;
@@ -556,6 +630,13 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     for (int crit = 0; crit < 2; ++crit)
         for (int rs = 0; rs <= restarts; ++rs) {
             std::vector<int> ord = greedy_order(nF, adj, crit, rs == 0 ? 0 : 0x5EED0000ull + uint64_t(rs) * 131 + crit);
+            if (!m.kept.empty()) {   // the open qubits' variables close the order, by output bit
+                std::vector<int> o2;
+                for (int u : ord)
+                    if (std::find(m.kept.begin(), m.kept.end(), u) == m.kept.end()) o2.push_back(u);
+                o2.insert(o2.end(), m.kept.begin(), m.kept.end());
+                ord.swap(o2);
+            }
             SimOut r = simulate(p, m, ord, nullptr, nullptr);
             ++t.n_candidates;
             if (!r.ok) { last_why = r.why; continue; }
@@ -572,6 +653,9 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t.n_absorbed = absorb_leaves(p, m, rs, rt);
     qgm_status fst = finalize_tree(p, m, best, rs, rt, t, err);
     if (fst != QGM_OK) return fst;
+    t.n_open = p.n_open;
+    t.zero_mask = m.zero_mask;
+    for (auto& k : kept) t.open_axis_bit.push_back(k.first);
     for (int u : best) t.order.push_back(m.free_var[u]);
     const int n_levels = int(t.levels.size());
     // last level reading each result (the final product counts as level n_levels)
@@ -631,7 +715,7 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t.first_level = 0;
     while (t.first_level < int(t.levels.size()) && t.levels[t.first_level].empty()) ++t.first_level;
     t.tail_start = int(t.levels.size());
-    while (t.tail_start > std::max(t.first_level, 1)) {
+    while (t.n_open == 0 && t.tail_start > std::max(t.first_level, 1)) {   // the tail writes one amplitude per b
         const int L = t.tail_start - 1;
         const int64_t nt = t.level_task_off[L + 1] - t.level_task_off[L];
         if (nt > kTreeTailTasks || launch_inputs(t.level_max_in[L]) > kTreeTailInputs) break;

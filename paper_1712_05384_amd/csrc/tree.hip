@@ -194,9 +194,10 @@ template <int NIN>
 __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
                                           uint32_t b, int64_t be) {
-    static_assert(kTreeMaxSum == 3, "tasks sum 1, 2 or 3 variables");
+    static_assert(kTreeMaxSum == 3, "tasks sum 0 (the product over the open qubits), 1, 2 or 3 variables");
     const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
-    if (tk.k == 1) tree_unit<NIN, 1>(tk, ain, aout, gtab, ones_g, sig, b, be);
+    if (tk.k == 0) tree_unit<NIN, 0>(tk, ain, aout, gtab, ones_g, sig, b, be);
+    else if (tk.k == 1) tree_unit<NIN, 1>(tk, ain, aout, gtab, ones_g, sig, b, be);
     else if (tk.k == 2) tree_unit<NIN, 2>(tk, ain, aout, gtab, ones_g, sig, b, be);
     else tree_unit<NIN, 3>(tk, ain, aout, gtab, ones_g, sig, b, be);
 }
@@ -511,6 +512,77 @@ hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream) {
         case 4: return launch_persist_c<4>(a, stream);
         default: return launch_persist_c<kTreeMaxIn>(a, stream);
     }
+}
+
+// Sets of amplitudes (open qubits): out[b][o] = phase x rank-0 results x R[row(o)] in
+// FP64, R the result over the open qubits' variables (absent: 1), row(o) the bits
+// of o outside zero_mask packed in order (the result's axes follow the output
+// bits), and 0 when o has a bit of zero_mask set (an open qubit without
+// non-diagonal gates ends in 0).  Block: 256 bitstrings x one chunk of kOpenChunk
+// output indices.
+constexpr int kOpenChunk = 64;
+__global__ void __launch_bounds__(256) k_tree_final_open(const int64_t* __restrict__ final_rows, int n_final,
+                                                         const TFactor* __restrict__ phase, int n_phase,
+                                                         const double2* __restrict__ fixed,
+                                                         const float2* __restrict__ slots,
+                                                         const float2* __restrict__ arena, int64_t open_row,
+                                                         int n_open, uint32_t zero_mask,
+                                                         const uint64_t* __restrict__ bits, int64_t B,
+                                                         uint32_t B_eff, void* __restrict__ out, int c128) {
+    __shared__ PhaseLds P;
+    const int n_lds = stage_phase(P, phase, n_phase, fixed, slots);
+    __syncthreads();
+    const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+    if (int64_t(b) >= B) return;
+    const uint64_t x = bits[b];
+    double2 acc = make_double2(1.0, 0.0);
+    for (int i = 0; i < n_lds; ++i) {
+        const uint32_t a = P.q[i][0] >= 0 ? uint32_t((x >> P.q[i][0]) & 1ull) : 0u;
+        const uint32_t c = P.q[i][1] >= 0 ? uint32_t((x >> P.q[i][1]) & 1ull) : 0u;
+        acc = cmuld(acc, P.v[i][a * 2 + c]);
+    }
+    for (int i = n_lds; i < n_phase; ++i) {
+        const TFactor f = phase[i];
+        const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
+        const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
+        acc = cmuld(acc, factor_value(f, a, c, fixed, slots));
+    }
+    for (int i = 0; i < n_final; ++i) {
+        const float2 r = arena[final_rows[i] * int64_t(B_eff) + b];
+        acc = cmuld(acc, make_double2(r.x, r.y));
+    }
+    const uint64_t n_out = uint64_t(1) << n_open;
+    const uint64_t o0 = uint64_t(blockIdx.y) * kOpenChunk;
+    for (uint64_t o = o0; o < o0 + kOpenChunk && o < n_out; ++o) {
+        double2 v = make_double2(0.0, 0.0);
+        if ((o & zero_mask) == 0) {
+            v = acc;
+            if (open_row >= 0) {
+                uint64_t row = 0;
+                int j = 0;
+                for (int i = 0; i < n_open; ++i) {
+                    if ((zero_mask >> i) & 1u) continue;
+                    row |= ((o >> i) & 1ull) << j;
+                    ++j;
+                }
+                const float2 r = arena[(open_row + int64_t(row)) * int64_t(B_eff) + b];
+                v = cmuld(v, make_double2(r.x, r.y));
+            }
+        }
+        const uint64_t k = uint64_t(b) * n_out + o;
+        if (c128) static_cast<double2*>(out)[k] = v;
+        else static_cast<float2*>(out)[k] = make_float2(float(v.x), float(v.y));
+    }
+}
+
+void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase,
+                            const double2* fixed, const float2* slots, const float2* arena, int64_t open_row,
+                            int n_open, uint32_t zero_mask, const uint64_t* bits, int64_t B, uint32_t B_eff,
+                            void* out, bool c128, hipStream_t stream) {
+    const uint32_t gx = uint32_t((B + 255) / 256);
+    const uint32_t gy = uint32_t(((int64_t(1) << n_open) + kOpenChunk - 1) / kOpenChunk);
+    hipLaunchKernelGGL(k_tree_final_open, dim3(gx, gy), dim3(256), 0, stream, final_rows, n_final, phase, n_phase,
+                       fixed, slots, arena, open_row, n_open, zero_mask, bits, B, B_eff, out, c128 ? 1 : 0);
 }
 
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,

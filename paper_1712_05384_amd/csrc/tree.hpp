@@ -134,6 +134,12 @@ struct TreePlan {
     std::vector<int> tensor_made, tensor_used;   // level that writes / last reads each result
     std::vector<int64_t> tensor_row;             // arena row of each result
     std::vector<int> finals;                     // rank-0 results multiplied into the amplitude
+    // open qubits (sets of amplitudes): the result over their variables, the output bit of each of its
+    // axes, and the output bits of open qubits without non-diagonal gates (amplitude 0 when set)
+    int n_open = 0;
+    int open_tensor = -1;
+    std::vector<int> open_axis_bit;
+    int zero_mask = 0;
     std::vector<TFactor> phase;                  // factors without free variables
     std::vector<std::vector<int>> levels;        // step ids per level
     std::vector<int64_t> level_task_off;         // wave tasks of level L: [off[L], off[L + 1])

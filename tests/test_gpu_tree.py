@@ -168,3 +168,75 @@ def test_tree_graph_mixed_with_vertical():
     ref = oracle.sv_amplitudes(c1.n, c1.gates, None, bits[0])
     assert np.abs(eager[0][:, 0] - ref).max() <= TOL * 2 ** (-c1.n / 2)
     assert np.abs(eager[2] - eager[1]).max() <= TOL * 2 ** (-c2.n / 2)
+
+
+def _oracle_open(c, bits, open_qubits, gate_vals=None):
+    psi = oracle.sv_state(c.n, c.gates, gate_vals)
+    out = np.zeros((len(bits), 1 << len(open_qubits)), dtype=np.complex128)
+    for o in range(1 << len(open_qubits)):
+        x = np.asarray(bits, dtype=np.uint64).copy()
+        for i, q in enumerate(open_qubits):
+            x = (x & ~np.uint64(1 << q)) | np.uint64(((o >> i) & 1) << q)
+        out[:, o] = psi[x.astype(np.int64)]
+    return out
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,open_qubits,B", [(3, 4, 12, 7, (0,), 64), (3, 4, 12, 7, (5, 2), 130),
+                                                               (4, 4, 16, 3, (11, 3, 7), 70),
+                                                               (4, 5, 16, 6, (0, 4, 8, 12, 16, 19), 100),
+                                                               (3, 3, 10, 2, tuple(range(9)), 5)])
+def test_tree_open_qubits(rows, cols, depth, seed, open_qubits, B):
+    """Sets of amplitudes on the bucket path: every completion of the open qubits,
+    against the state vector and against the vertical path."""
+    import paper_1712_05384_amd as Q
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, B, seed)
+    _say("case tree open %s open=%s B=%d" % (c.name, open_qubits, B))
+    out = Q.plan(c, open_qubits, ordering=1).amplitudes(bits)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = _oracle_open(c, bits, open_qubits)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+    vert = Q.plan(c, open_qubits).amplitudes(bits).cpu().numpy()
+    assert np.abs(vert - got).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_open_qubits_gate_values_c128_chain_and_zero_bit():
+    import paper_1712_05384_amd as Q
+    # gate values and complex128 output
+    c = C.parameterised_circuit(4, 4, 14, 8)
+    bits = C.random_bitstrings(c.n, 66, 8)
+    gv = c.gate_vals.astype(np.complex64)
+    got = Q.plan(c, (3, 12), ordering=1, out_c128=True).amplitudes(bits, torch.tensor(gv)).cpu().numpy()
+    assert got.dtype == np.complex128
+    assert np.abs(got - _oracle_open(c, bits, (3, 12), gv.astype(np.complex128))).max() <= TOL * 2 ** (-c.n / 2)
+    # more than 8 results on the open qubits: a chain of buckets over them
+    n = 18
+    g = [(C.H, 0, q, -1, -1) for q in range(n)] + [(C.CZ, 1, 2 * i, 2 * i + 1, -1) for i in range(9)] + \
+        [(C.XH, 2, q, -1, -1) for q in range(n)]
+    c2 = C.Circuit(1, n, np.array(g))
+    oq = tuple(range(0, n, 2))
+    bits2 = C.random_bitstrings(n, 64, 5)
+    got2 = Q.plan(c2, oq, ordering=1).amplitudes(bits2).cpu().numpy()
+    assert np.abs(got2 - _oracle_open(c2, bits2, oq)).max() <= TOL * 2 ** (-n / 2)
+    # an open qubit without non-diagonal gates: amplitude 0 when its output bit is set
+    g3 = np.array([(C.H, 0, 0, -1, -1), (C.CZ, 1, 0, 1, -1), (C.T, 2, 1, -1, -1), (C.H, 3, 0, -1, -1),
+                   (C.H, 0, 2, -1, -1), (C.CZ, 4, 1, 2, -1), (C.XH, 5, 2, -1, -1)])
+    c3 = C.Circuit(1, 3, g3)
+    bits3 = np.arange(8, dtype=np.uint64)
+    got3 = Q.plan(c3, (2, 1), ordering=1).amplitudes(bits3).cpu().numpy()
+    assert np.abs(got3 - _oracle_open(c3, bits3, (2, 1))).max() <= 1e-7
+
+
+def test_tree_open_qubits_backward_rejected():
+    import paper_1712_05384_amd as Q
+    from paper_1712_05384_amd import _native as N
+    c = C.parameterised_circuit(3, 3, 8, 1)
+    p = Q.plan(c, (0,), ordering=1)
+    bits = C.random_bitstrings(c.n, 64, 1)
+    gv = torch.tensor(c.gate_vals.astype(np.complex64), device="cuda")
+    bd = torch.from_numpy(bits.view(np.int64)).cuda()
+    with pytest.raises(N.QgmError) as e:
+        p.backward(bd, torch.ones(64, 2, dtype=torch.complex64, device="cuda"), gv)
+    assert e.value.status == N.QGM_E_UNSUPPORTED

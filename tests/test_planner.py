@@ -250,9 +250,9 @@ def test_tree_plan_is_deterministic_and_consistent():
     assert readers == [1] * len(a["tensors"])
 
 
-def test_tree_plan_rejects_open_qubits_and_slicing():
+def test_tree_plan_rejects_slicing_and_persistent_open_qubits():
     c = C.random_grid_circuit(3, 3, 8, 1)
-    for kw in (dict(open_qubits=(0,)), dict(min_sliced_vars=1), dict(max_rank=3)):
+    for kw in (dict(min_sliced_vars=1), dict(max_rank=3), dict(open_qubits=(0,), tree_exec=2)):
         oq = kw.pop("open_qubits", ())
         with pytest.raises(N.QgmError) as e:
             Q.plan(c, oq, ordering=1, **kw)
@@ -301,3 +301,66 @@ def test_tree_exec_modes_and_persistent_workspace():
     assert per.workspace_bytes(64) > lev.workspace_bytes(64)
     with pytest.raises(Exception):
         Q.plan(c, ordering=1, tree_exec=3)
+
+
+def _oracle_open(c, bits, open_qubits):
+    cols = []
+    for o in range(1 << len(open_qubits)):
+        xb = bits.copy()
+        for i, q in enumerate(open_qubits):
+            xb = (xb & ~np.uint64(1 << q)) | np.uint64(((o >> i) & 1) << q)
+        cols.append(oracle.sv_amplitudes(c.n, c.gates, c.gate_vals, xb))
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,open_qubits", [(2, 2, 6, 1, (0,)), (3, 3, 10, 2, (4, 0)),
+                                                             (3, 4, 12, 3, (11, 3, 7)), (2, 3, 8, 4, (0, 1, 2, 3, 4, 5)),
+                                                             (4, 3, 14, 5, tuple(range(12)))])
+def test_tree_plan_open_qubits(rows, cols, depth, seed, open_qubits):
+    """Sets of amplitudes (Sec. III.A): the open qubits' last variables are never
+    summed; one bucket over them (a chain beyond 8 inputs) gives every completion."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 12, seed)
+    info = Q.plan(c, open_qubits, ordering=1).info(1)
+    assert info["n_open"] == len(open_qubits) and info["tail_levels"] == 0
+    got = run_tree_plan(info, c.gate_vals, bits)
+    ref = _oracle_open(c, bits, open_qubits)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_tree_plan_open_qubit_without_non_diagonal_gates():
+    """An open qubit whose worldline has only diagonal gates ends in 0: its
+    output bit set gives amplitude 0 (zero_mask)."""
+    g = np.array([(C.H, 0, 0, -1, -1), (C.CZ, 1, 0, 1, -1), (C.T, 2, 1, -1, -1), (C.H, 3, 0, -1, -1),
+                  (C.H, 0, 2, -1, -1), (C.CZ, 4, 1, 2, -1), (C.XH, 5, 2, -1, -1)])
+    c = C.Circuit(1, 3, g)
+    bits = np.arange(8, dtype=np.uint64)
+    for oq in ((1,), (1, 0), (2, 1)):
+        info = Q.plan(c, oq, ordering=1).info(1)
+        assert info["zero_mask"] == (1 << oq.index(1))
+        got = run_tree_plan(info, c.gate_vals, bits)
+        assert np.abs(got - _oracle_open(c, bits, oq)).max() < 1e-12
+
+
+def test_tree_plan_open_bucket_chain():
+    """More than 8 results end on the open qubits' variables: the product over
+    them runs as a chain of buckets (1x18: H, CZ on 9 disjoint pairs, X^1/2;
+    one open qubit per pair)."""
+    n = 18
+    g = [(C.H, 0, q, -1, -1) for q in range(n)] + [(C.CZ, 1, 2 * i, 2 * i + 1, -1) for i in range(9)] + \
+        [(C.XH, 2, q, -1, -1) for q in range(n)]
+    c = C.Circuit(1, n, np.array(g))
+    oq = tuple(range(0, n, 2))
+    info = Q.plan(c, oq, ordering=1).info(1)
+    assert sum(1 for b in info["buckets"] if b["kg"] == 0) >= 2
+    bits = C.random_bitstrings(n, 3, 5)
+    got = run_tree_plan(info, c.gate_vals, bits)
+    psi = oracle.sv_state(n, c.gates, None)
+    ref = np.zeros_like(got)
+    for o in range(1 << len(oq)):
+        x = bits.copy()
+        for i, q in enumerate(oq):
+            x = (x & ~np.uint64(1 << q)) | np.uint64(((o >> i) & 1) << q)
+        ref[:, o] = psi[x.astype(np.int64)]
+    assert np.abs(got - ref).max() < 1e-12

@@ -127,4 +127,22 @@ def run_tree_plan(info, gate_vals, bits):
         amp = amp * _factor(f, a, b, gate_vals)
     for tid in info["finals"]:
         amp = amp * read(tid)[0]
-    return amp
+    n_open = info.get("n_open", 0)
+    if n_open == 0:
+        return amp
+    # a set of amplitudes per bitstring: output bit i <-> open qubit i; the result over the open
+    # qubits' variables has one axis per output bit outside zero_mask, in order
+    zm = info["zero_mask"]
+    out = np.zeros((B, 1 << n_open), dtype=np.complex128)
+    R = read(info["open_tensor"]) if info["open_tensor"] >= 0 else None
+    for o in range(1 << n_open):
+        if o & zm:
+            continue
+        row, j = 0, 0
+        for i in range(n_open):
+            if (zm >> i) & 1:
+                continue
+            row |= ((o >> i) & 1) << j
+            j += 1
+        out[:, o] = amp * (R[row] if R is not None else 1.0)
+    return out

@@ -56,8 +56,14 @@ typedef enum {
  *  QGM_U  = general 2x2 read from gate_vals[slot]; non-diagonal, so it opens a
  *           new worldline variable (Sec. III.A)
  *  QGM_UD = diagonal 2x2 read from the diagonal of gate_vals[slot]; like T it
- *           adds no variable (Sec. III.A) */
-typedef enum { QGM_H = 0, QGM_T = 1, QGM_XH = 2, QGM_YH = 3, QGM_CZ = 4, QGM_U = 5, QGM_UD = 6 } qgm_kind;
+ *           adds no variable (Sec. III.A)
+ * Inverses and Pauli operators (for expectation values <0|U^dag O U|0>, which
+ * the same graphical model computes, Sec. III.B; see qgm_expectation_circuit):
+ *  QGM_TDG = diag(1, e^{-i pi/4}), QGM_XHDG = RX(-pi/2) = (1/sqrt2)[[1,i],[i,1]],
+ *  QGM_YHDG = RY(-pi/2) = (1/sqrt2)[[1,1],[-1,1]], QGM_X = [[0,1],[1,0]],
+ *  QGM_Y = [[0,-i],[i,0]], QGM_Z = diag(1,-1) (TDG and Z diagonal) */
+typedef enum { QGM_H = 0, QGM_T = 1, QGM_XH = 2, QGM_YH = 3, QGM_CZ = 4, QGM_U = 5, QGM_UD = 6, QGM_TDG = 7,
+               QGM_XHDG = 8, QGM_YHDG = 9, QGM_X = 10, QGM_Y = 11, QGM_Z = 12 } qgm_kind;
 
 typedef struct {
     int32_t kind;    /* qgm_kind */
@@ -224,6 +230,23 @@ qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void
 qgm_status qgm_graph_launch(qgm_graph_t* graph, void* stream);
 /* Destroys the graph (NULL is ignored). */
 void qgm_graph_destroy(qgm_graph_t* graph);
+
+/* ---- Expectation values of Pauli strings ------------------------------------
+ * qgm_expectation_circuit (host only): writes to gates[0, *n_gates) a circuit
+ * whose amplitude at the all-zero bitstring is <0|U^dag O U|0> for the Pauli
+ * string O = prod_i paulis[i] on qubits[i] (kinds QGM_X, QGM_Y, QGM_Z, distinct
+ * qubits; Sec. III.B: the operator enters the same graphical model as factors).
+ * It is U restricted to the backward light cone of O's qubits (gates outside
+ * it cancel against their inverses), then O at cycle d (one past U's last
+ * cycle), then the inverses of the kept gates in reverse order at cycle 2d - t;
+ * same lattice as circuit.  Plan it with qgm_plan and evaluate it with
+ * qgm_amplitudes at bitstring 0 (real up to rounding for Hermitian O).  U must
+ * use fixed gate kinds (QGM_E_UNSUPPORTED for value slots).  If cap is below
+ * the gate count, *n_gates receives the count and QGM_E_OOM is returned (call
+ * with cap = 0 to size the array).  Other errors: QGM_E_INVALID as qgm_plan's
+ * circuit checks, plus bad operator qubits or kinds. */
+qgm_status qgm_expectation_circuit(const qgm_circuit* circuit, int32_t n_ops, const int32_t* qubits,
+                                   const int32_t* paulis, qgm_gate* gates, int32_t cap, int32_t* n_gates);
 
 /* ---- Cross-entropy benchmarking and sampling on top of the amplitudes ------
  * Both take a device array of B amplitudes (complex64 when c128 = 0, else

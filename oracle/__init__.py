@@ -13,9 +13,11 @@ Contents
   bucket.py       bucket elimination of App. A in FP64 (for n > 30)
   xeb.py          cross entropy (Eq. (cee)), fidelity (Eq. (ae)), entropy and
                   sampling from a set of probabilities (App. B, App. C)
+  observable.py   <psi|O|psi> of Pauli strings from the state vector
 """
 from .gates import gate_matrix, KIND_H, KIND_T, KIND_XH, KIND_YH, KIND_CZ, KIND_U, KIND_UD  # noqa: F401
 from .statevector import sv_state, sv_amplitudes, sv_vjp, sv_log_prob_gradient, build_library  # noqa: F401
 from .brute_force import path_sum_amplitude, ising_amplitude  # noqa: F401
 from .bucket import bucket_amplitude, bucket_amplitudes  # noqa: F401
 from . import xeb  # noqa: F401
+from .observable import expectation  # noqa: F401

@@ -17,6 +17,7 @@ the notation of Sec. III.B (row = the bit after the gate).
 import numpy as np
 
 KIND_H, KIND_T, KIND_XH, KIND_YH, KIND_CZ, KIND_U, KIND_UD = 0, 1, 2, 3, 4, 5, 6
+KIND_TDG, KIND_XHDG, KIND_YHDG, KIND_X, KIND_Y, KIND_Z = 7, 8, 9, 10, 11, 12
 
 _R2 = 1.0 / np.sqrt(2.0)
 _FIXED = {
@@ -25,6 +26,12 @@ _FIXED = {
     KIND_XH: np.array([[_R2, -1j * _R2], [-1j * _R2, _R2]], dtype=np.complex128),
     KIND_YH: np.array([[_R2, -_R2], [_R2, _R2]], dtype=np.complex128),
 }
+# inverses of the fixed gates (conjugate transposes) and the Pauli operators
+for _k, _kd in ((KIND_T, KIND_TDG), (KIND_XH, KIND_XHDG), (KIND_YH, KIND_YHDG)):
+    _FIXED[_kd] = _FIXED[_k].conj().T.copy()
+_FIXED[KIND_X] = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_FIXED[KIND_Y] = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_FIXED[KIND_Z] = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 
 
 def gate_matrix(kind: int, slot: int, gate_vals) -> np.ndarray:
@@ -41,4 +48,4 @@ def gate_matrix(kind: int, slot: int, gate_vals) -> np.ndarray:
 
 
 def is_diagonal_kind(kind: int) -> bool:
-    return int(kind) in (KIND_T, KIND_CZ, KIND_UD)
+    return int(kind) in (KIND_T, KIND_CZ, KIND_UD, KIND_TDG, KIND_Z)

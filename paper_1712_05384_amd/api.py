@@ -233,6 +233,37 @@ class Graph:
             self._h = None
 
 
+_PAULI = {"X": 10, "Y": 11, "Z": 12}
+
+
+def expectation_circuit(circuit, paulis):
+    """The circuit whose amplitude at bitstring 0 is <0|U^dag O U|0> for the
+    Pauli string O = {qubit: "X" | "Y" | "Z"} (qgm_expectation_circuit: U on
+    O's backward light cone, O, the inverses in reverse order)."""
+    from .circuits import Circuit
+    items = sorted(paulis.items())
+    qs = (ctypes.c_int32 * len(items))(*[int(q) for q, _ in items])
+    ks = (ctypes.c_int32 * len(items))(*[_PAULI[str(k).upper()] for _, k in items])
+    cs, keep = _circuit_struct(circuit.rows, circuit.cols, circuit.gates, int(getattr(circuit, "n_slots", 0)))
+    L = N.lib()
+    n = ctypes.c_int32()
+    st = L.qgm_expectation_circuit(ctypes.byref(cs), len(items), qs, ks, None, 0, ctypes.byref(n))
+    if st != N.QGM_E_OOM or n.value == 0:
+        N.check(st)
+    out = (N.QgmGate * max(1, n.value))()
+    N.check(L.qgm_expectation_circuit(ctypes.byref(cs), len(items), qs, ks, out, n.value, ctypes.byref(n)))
+    g = np.array([(x.kind, x.cycle, x.q0, x.q1, x.slot) for x in out[:n.value]], dtype=np.int32).reshape(-1, 5)
+    return Circuit(circuit.rows, circuit.cols, g, None, f"{getattr(circuit, 'name', '')}<O>")
+
+
+def expectation(circuit, paulis, *, ordering: int = 1, **plan_opts):
+    """<0|U^dag O U|0> (complex; real up to rounding) on the GPU: the amplitude at
+    bitstring 0 of expectation_circuit(circuit, paulis)."""
+    c2 = expectation_circuit(circuit, paulis)
+    p = plan(c2, ordering=ordering, **plan_opts)
+    return p.amplitudes(np.zeros(1, dtype=np.uint64)).reshape(-1)[0]
+
+
 def xeb(amps, n_qubits: int, *, stream=None):
     """Cross-entropy statistics of a batch of amplitudes (qgm_xeb, App. B): a
     float64 device tensor [sum log p, sum p, sum p log p, zeros, cross entropy

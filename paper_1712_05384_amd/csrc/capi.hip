@@ -80,12 +80,15 @@ void fixed_matrices(double2 m[qgm::kFixedMats * 4]) {
     const double2 T[4] = {{1, 0}, {0, 0}, {0, 0}, {std::cos(M_PI / 4), std::sin(M_PI / 4)}};
     const double2 X[4] = {{r, 0}, {0, -r}, {0, -r}, {r, 0}};
     const double2 Y[4] = {{r, 0}, {-r, 0}, {r, 0}, {r, 0}};
-    for (int i = 0; i < 4; ++i) {
-        m[0 * 4 + i] = H[i];
-        m[1 * 4 + i] = T[i];
-        m[2 * 4 + i] = X[i];
-        m[3 * 4 + i] = Y[i];
-    }
+    const double2 Tdg[4] = {{1, 0}, {0, 0}, {0, 0}, {std::cos(M_PI / 4), -std::sin(M_PI / 4)}};
+    const double2 Xdg[4] = {{r, 0}, {0, r}, {0, r}, {r, 0}};
+    const double2 Ydg[4] = {{r, 0}, {r, 0}, {-r, 0}, {r, 0}};
+    const double2 PX[4] = {{0, 0}, {1, 0}, {1, 0}, {0, 0}};
+    const double2 PY[4] = {{0, 0}, {0, -1}, {0, 1}, {0, 0}};
+    const double2 PZ[4] = {{1, 0}, {0, 0}, {0, 0}, {-1, 0}};
+    const double2* all[qgm::kFixedMats] = {H, T, X, Y, Tdg, Xdg, Ydg, PX, PY, PZ};
+    for (int k = 0; k < qgm::kFixedMats; ++k)
+        for (int i = 0; i < 4; ++i) m[k * 4 + i] = all[k][i];
 }
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
@@ -1036,6 +1039,22 @@ qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
+qgm_status qgm_expectation_circuit(const qgm_circuit* circuit, int32_t n_ops, const int32_t* qubits,
+                                   const int32_t* paulis, qgm_gate* gates, int32_t cap, int32_t* n_gates) {
+    g_err.clear();
+    if (!n_gates) return fail(QGM_E_INVALID, "n_gates is NULL");
+    std::vector<qgm_gate> out;
+    std::string err;
+    const qgm_status st = qgm::expectation_circuit(circuit, n_ops, qubits, paulis, out, &err);
+    if (st != QGM_OK) return fail(st, err);
+    *n_gates = int32_t(out.size());
+    if (int64_t(out.size()) > int64_t(cap) || (!gates && !out.empty()))
+        return fail(QGM_E_OOM, "gates holds " + std::to_string(cap) + " gates, " + std::to_string(out.size()) +
+                                   " needed (written to n_gates)");
+    std::copy(out.begin(), out.end(), gates);
     return QGM_OK;
 }
 

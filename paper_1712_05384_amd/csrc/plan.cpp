@@ -13,7 +13,7 @@ namespace qgm {
 
 namespace {
 
-bool is_diag_kind(int k) { return k == QGM_T || k == QGM_UD || k == QGM_CZ; }
+bool is_diag_kind(int k) { return k == QGM_T || k == QGM_UD || k == QGM_CZ || k == QGM_TDG || k == QGM_Z; }
 
 int mat_index(int kind, int slot) {
     switch (kind) {
@@ -21,6 +21,12 @@ int mat_index(int kind, int slot) {
         case QGM_T: return 1;
         case QGM_XH: return 2;
         case QGM_YH: return 3;
+        case QGM_TDG: return 4;
+        case QGM_XHDG: return 5;
+        case QGM_YHDG: return 6;
+        case QGM_X: return 7;
+        case QGM_Y: return 8;
+        case QGM_Z: return 9;
         default: return kFixedMats + slot;   // QGM_U, QGM_UD
     }
 }
@@ -67,7 +73,7 @@ static qgm_status validate(const qgm_circuit* c, const int32_t* open, int32_t n_
     for (int i = 0; i < c->n_gates; ++i) {
         const qgm_gate& g = c->gates[i];
         char buf[160];
-        if (g.kind < QGM_H || g.kind > QGM_UD) {
+        if (g.kind < QGM_H || g.kind > QGM_Z) {
             snprintf(buf, sizeof buf, "gate %d: unknown kind %d", i, g.kind); *err = buf; return QGM_E_INVALID;
         }
         if (g.cycle < 0) { snprintf(buf, sizeof buf, "gate %d: negative cycle", i); *err = buf; return QGM_E_INVALID; }
@@ -352,6 +358,75 @@ static int pick_slice_var(Plan& p, std::string* err) {
     }
     if (best < 0) { *err = "no slicing candidate yields a valid plan"; return -1; }
     return best;
+}
+
+// <0|U^dag O U|0> for a Pauli string O is the amplitude at x = 0 of the circuit
+// U, O, U^dag (the graphical model of Sec. III.B with the operator's factors).
+// A gate of U outside the backward light cone of O's qubits cancels against
+// its inverse (U_a^dag U_a = 1) and is left out: walking U backwards from O,
+// a gate is kept when it touches a qubit of the cone, and a kept CZ adds its
+// other qubit.  Output: the kept gates, O at cycle d (d = 1 + the last cycle),
+// then the inverses of the kept gates in reverse order at cycle 2d - t.
+qgm_status expectation_circuit(const qgm_circuit* c, int32_t n_ops, const int32_t* qubits, const int32_t* paulis,
+                               std::vector<qgm_gate>& out, std::string* err) {
+    qgm_status st = validate(c, nullptr, 0, err);
+    if (st != QGM_OK) return st;
+    const int n = c->rows * c->cols;
+    if (n_ops < 1 || !qubits || !paulis) { *err = "the operator needs at least one (qubit, Pauli) pair"; return QGM_E_INVALID; }
+    std::vector<char> in_cone(n, 0);
+    for (int i = 0; i < n_ops; ++i) {
+        if (qubits[i] < 0 || qubits[i] >= n) { *err = "operator qubit out of range"; return QGM_E_INVALID; }
+        if (paulis[i] != QGM_X && paulis[i] != QGM_Y && paulis[i] != QGM_Z) {
+            *err = "operator kinds must be QGM_X, QGM_Y or QGM_Z";
+            return QGM_E_INVALID;
+        }
+        if (in_cone[qubits[i]]) { *err = "operator qubits must be distinct"; return QGM_E_INVALID; }
+        in_cone[qubits[i]] = 1;
+    }
+    std::vector<int> idx(c->n_gates);
+    int d = 0;
+    for (int i = 0; i < c->n_gates; ++i) {
+        idx[i] = i;
+        const qgm_gate& g = c->gates[i];
+        if (g.kind == QGM_U || g.kind == QGM_UD) {
+            *err = "expectation circuits take fixed gate kinds only (no value slots)";
+            return QGM_E_UNSUPPORTED;
+        }
+        d = std::max(d, g.cycle + 1);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c->gates[a].cycle < c->gates[b].cycle; });
+    std::vector<char> keep(c->n_gates, 0);
+    for (int k = c->n_gates - 1; k >= 0; --k) {
+        const qgm_gate& g = c->gates[idx[k]];
+        const bool touches = in_cone[g.q0] || (g.kind == QGM_CZ && in_cone[g.q1]);
+        if (!touches) continue;
+        keep[idx[k]] = 1;
+        in_cone[g.q0] = 1;
+        if (g.kind == QGM_CZ) in_cone[g.q1] = 1;
+    }
+    auto inverse = [](int kind) {
+        switch (kind) {
+            case QGM_T: return int(QGM_TDG);
+            case QGM_TDG: return int(QGM_T);
+            case QGM_XH: return int(QGM_XHDG);
+            case QGM_XHDG: return int(QGM_XH);
+            case QGM_YH: return int(QGM_YHDG);
+            case QGM_YHDG: return int(QGM_YH);
+            default: return kind;   // H, CZ, X, Y, Z are their own inverses
+        }
+    };
+    out.clear();
+    for (int k = 0; k < c->n_gates; ++k)
+        if (keep[idx[k]]) out.push_back(c->gates[idx[k]]);
+    for (int i = 0; i < n_ops; ++i) out.push_back(qgm_gate{paulis[i], d, qubits[i], -1, -1});
+    for (int k = c->n_gates - 1; k >= 0; --k)
+        if (keep[idx[k]]) {
+            qgm_gate g = c->gates[idx[k]];
+            g.kind = inverse(g.kind);
+            g.cycle = 2 * d - g.cycle;
+            out.push_back(g);
+        }
+    return QGM_OK;
 }
 
 qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,

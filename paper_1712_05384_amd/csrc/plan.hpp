@@ -103,6 +103,9 @@ struct WsLayout {
     uint64_t f0 = 0, f1 = 0, var_ids = 0, g = 0, flags = 0, total = 0;
 };
 WsLayout workspace_layout(const Plan& p, int64_t B);
+// The gates of U, O, U^dag restricted to O's backward light cone (qgm_expectation_circuit).
+qgm_status expectation_circuit(const qgm_circuit* c, int32_t n_ops, const int32_t* qubits, const int32_t* paulis,
+                               std::vector<qgm_gate>& out, std::string* err);
 // Bucket plans: whether qgm_amplitudes runs a batch of B in one persistent launch,
 // and the words of one bitstring group's completion flags in that launch.
 bool tree_persistent(const Plan& p, int64_t B);

@@ -36,7 +36,7 @@ struct GOp {
     int32_t mat;
 };
 
-constexpr int kFixedMats = 4;       // H, T, X^1/2, Y^1/2; slot s is matrix kFixedMats + s
+constexpr int kFixedMats = 10;      // H, T, X^1/2, Y^1/2, T^dag, X^-1/2, Y^-1/2, X, Y, Z; slot s is matrix kFixedMats + s
 constexpr int kMaxKB = 6;           // K bits handled with the contracted slice in registers
 constexpr int kMaxBits = 8;         // per-step bound on V bits, on sigma bits
 constexpr int kMaxNB = 10;

@@ -13,10 +13,15 @@ GOP_PROJECT, GOP_MAT, GOP_DIAG, GOP_CZ, GOP_END = range(5)
 SRC_ZERO, SRC_K, SRC_V, SRC_N, SRC_SIG, SRC_INT = range(6)
 
 
+# matrix index -> gate kind of the library's fixed matrices (H, T, X^1/2, Y^1/2, their inverses, X, Y, Z);
+# index 10 + s is value slot s
+_FIXED_KIND = (0, 1, 2, 3, 7, 8, 9, 10, 11, 12)
+
+
 def _mat(idx, gate_vals):
-    if idx < 4:
-        return gate_matrix(idx, -1, None)
-    return np.asarray(gate_vals[idx - 4], dtype=np.complex128).reshape(2, 2)
+    if idx < len(_FIXED_KIND):
+        return gate_matrix(_FIXED_KIND[idx], -1, None)
+    return np.asarray(gate_vals[idx - len(_FIXED_KIND)], dtype=np.complex128).reshape(2, 2)
 
 
 def build_g(step, gate_vals):

@@ -121,7 +121,7 @@ def test_workload_plan_sizes():
     dict(gates=[(C.H, 0, 9, -1, -1)]),
     dict(gates=[(C.H, 0, 0, -1, -1), (C.T, 0, 0, -1, -1)]),
     dict(gates=[(C.U, 0, 0, -1, 3)]),
-    dict(gates=[(9, 0, 0, -1, -1)]),
+    dict(gates=[(13, 0, 0, -1, -1)]),
     dict(gates=[(C.H, -1, 0, -1, -1)]),
     dict(gates=[(C.H, 0, 0, 1, -1)]),
 ])

@@ -17,10 +17,15 @@ TS_ZERO, TS_G, TS_SIG, TS_INT = 0, 1, 2, 3
 TF_MAT, TF_DIAG, TF_CZ, TF_DELTA0 = 0, 1, 2, 3
 
 
+# matrix index -> gate kind of the library's fixed matrices (H, T, X^1/2, Y^1/2, their inverses, X, Y, Z);
+# index 10 + s is value slot s
+_FIXED_KIND = (0, 1, 2, 3, 7, 8, 9, 10, 11, 12)
+
+
 def _mat(idx, gate_vals):
-    if idx < 4:
-        return gate_matrix(idx, -1, None)
-    return np.asarray(gate_vals[idx - 4], dtype=np.complex128).reshape(2, 2)
+    if idx < len(_FIXED_KIND):
+        return gate_matrix(_FIXED_KIND[idx], -1, None)
+    return np.asarray(gate_vals[idx - len(_FIXED_KIND)], dtype=np.complex128).reshape(2, 2)
 
 
 def _factor(f, a, b, gate_vals):

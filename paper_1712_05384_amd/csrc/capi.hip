@@ -43,6 +43,7 @@ struct qgm_plan_s {
     size_t off_ttasks_all = 0, off_tfinal_all = 0, off_tbwd = 0, off_tbwdin = 0, off_tbwdg = 0, off_titems = 0;
     size_t off_tslot_off = 0, off_tslot_occ = 0;
     size_t off_tfdep = 0;   // (first task, count) of the bucket making each rank-0 result
+    size_t off_tleaf = 0;   // leaf-table records (plans without gate values)
     struct LevelItems { int off = 0, n = 0; int64_t rows = 0; };
     std::vector<LevelItems> lv_exp, lv_g;
     std::vector<std::vector<LevelItems>> lv_red;   // per level: the stages of its staged sums
@@ -253,7 +254,8 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tslot_off = P->off_titems + al(sizeof(qgm::TreeBwdItem) * (P->items.size() + 1));
     P->off_tslot_occ = P->off_tslot_off + al(sizeof(int32_t) * (P->slot_off_t.size() + 1));
     P->off_tfdep = P->off_tslot_occ + al(sizeof(int32_t) * (P->slot_occ_t.size() + 1));
-    P->total = P->off_tfdep + al(sizeof(int32_t) * 2 * (t.finals.size() + 1));
+    P->off_tleaf = P->off_tfdep + al(sizeof(int32_t) * 2 * (t.finals.size() + 1));
+    P->total = P->off_tleaf + al(sizeof(qgm::TreeLeaf) * size_t(t.n_table_leaves + 1));
 }
 
 // Adjoint tables: the forward tasks with every result at its own rows
@@ -268,11 +270,12 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
     for (size_t i = 0; i < shift.size(); ++i) shift[i] = t.tensor_row_all[i] - t.tensor_row[i];
     for (size_t sid = 0; sid < t.steps.size(); ++sid) {
         const qgm::TreeStep& st = t.steps[sid];
+        if (st.table_leaf) continue;
         for (int64_t c = 0; c < st.n_tasks(); ++c) {
             qgm::TreeTask tk = tasks[st.task_off + c];
             tk.out_row = int32_t(tk.out_row + shift[st.out_tensor]);
             for (size_t k = 0; k < st.in_tensors.size(); ++k)
-                tk.in_row[k] = int32_t(tk.in_row[k] + shift[st.in_tensors[k]]);
+                if (tk.in_tab[k] < 0) tk.in_row[k] = int32_t(tk.in_row[k] + shift[st.in_tensors[k]]);
             tasks_all[st.task_off + c] = tk;
         }
     }
@@ -322,7 +325,7 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
 // every summed variable in every input (the index arithmetic of the bucket
 // product), one task record per wave unit of result rows, the factor tables'
 // groups and factors, the tail levels and the prologue's block list.
-void fill_tree_tables(const qgm_plan_t* P, char* h) {
+bool fill_tree_tables(const qgm_plan_t* P, char* h) {
     const qgm::TreePlan& t = P->p.tree;
     auto* tasks = reinterpret_cast<qgm::TreeTask*>(h + P->off_ttasks);
     auto* gt = reinterpret_cast<qgm::TreeGTab*>(h + P->off_tgtab);
@@ -330,6 +333,8 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
     auto* fac = reinterpret_cast<qgm::TFactor*>(h + P->off_tfac);
     auto* pro = reinterpret_cast<qgm::TreeProBlock*>(h + P->off_tpro);
     int n_fac = 0, n_grp = 0, n_pro = 0;
+    std::vector<char> task_written(size_t(t.n_tasks), 0);   // every task record is written exactly once
+    bool tasks_ok = true;
     std::vector<int> maker(t.tensor_axes.size(), -1);   // bucket that makes each result
     for (size_t i = 0; i < t.steps.size(); ++i) maker[t.steps[i].out_tensor] = int(i);
     for (size_t i = 0; i < t.steps.size(); ++i) {
@@ -358,8 +363,17 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
         base.n_in = n_in;
         base.nin_class = qgm::launch_inputs(t.level_max_in[st.level]);
         for (int b = 0; b < st.sb(); ++b) base.sig_q[b] = st.sig_q[b];
+        for (int k = 0; k < qgm::kTreeMaxIn; ++k) base.in_tab[k] = -1;
         for (int k = 0; k < n_in; ++k) {
             const qgm::TreeStep& mk = t.steps[maker[st.in_tensors[k]]];
+            if (mk.table_leaf) {   // read per lane from its table; nothing to wait for
+                base.in_tab[k] = int32_t(mk.leaf_off);
+                base.in_tsb[k] = mk.sb();
+                uint64_t pack = 0;
+                for (int b = 0; b < mk.sb(); ++b) pack |= uint64_t(mk.sig_q[b]) << (6 * b);
+                base.in_tsig[k] = pack;
+                continue;
+            }
             base.dep_off[k] = int32_t(mk.task_off);
             base.dep_n[k] = int32_t(mk.n_tasks());
         }
@@ -391,8 +405,9 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
             low += sj;
             if (sj != 0) base.g_omask |= 1 << j;
         }
-        // task c covers result rows [c * unit_rows, (c + 1) * unit_rows), wrapping for small results
-        const int64_t n_ch = st.n_tasks();
+        // task c covers result rows [c * unit_rows, (c + 1) * unit_rows), wrapping for small results (a leaf
+        // table has no tasks: the plan builds it)
+        const int64_t n_ch = st.table_leaf ? 0 : st.n_tasks();
         for (int64_t c = 0; c < n_ch; ++c) {
             const int64_t o0 = c * st.unit_rows;
             qgm::TreeTask tk = base;
@@ -403,14 +418,20 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
             tk.g_ent = int32_t(st.g_off + (g0 << base.gshift));
             for (int k = 0; k < qgm::kTreeMaxIn; ++k) {
                 if (k >= n_in) { tk.in_row[k] = -1; continue; }
-                int64_t row = t.tensor_row[st.in_tensors[k]];
+                // a leaf table's rows count from 0 within it
+                int64_t row = base.in_tab[k] >= 0 ? 0 : t.tensor_row[st.in_tensors[k]];
                 for (int j = 0; j < r; ++j)
                     if ((o0 >> j) & 1) row += str[k][j];
                 tk.in_row[k] = int32_t(row);
             }
-            tasks[st.task_off + c] = tk;
+            const int64_t ti = st.task_off + c;
+            if (ti < 0 || ti >= t.n_tasks || task_written[size_t(ti)]) { tasks_ok = false; continue; }
+            task_written[size_t(ti)] = 1;
+            tasks[ti] = tk;
         }
     }
+    for (char w : task_written) tasks_ok = tasks_ok && w;
+    if (!tasks_ok) return false;
     fill_tree_adjoint_tables(P, h);
     auto* tl = reinterpret_cast<qgm::TreeTailLevel*>(h + P->off_ttail);
     for (size_t L = size_t(t.tail_start); L < t.levels.size(); ++L) {
@@ -424,12 +445,18 @@ void fill_tree_tables(const qgm_plan_t* P, char* h) {
     for (size_t i = 0; i < t.phase.size(); ++i) ph[i] = t.phase[i];
     auto* fr = reinterpret_cast<int64_t*>(h + P->off_tfinal);
     for (size_t i = 0; i < t.finals.size(); ++i) fr[i] = t.tensor_row[t.finals[i]];
+    auto* lf = reinterpret_cast<qgm::TreeLeaf*>(h + P->off_tleaf);
+    int n_lf = 0;
+    for (const qgm::TreeStep& st : t.steps)
+        if (st.table_leaf)
+            lf[n_lf++] = {st.g_off, st.leaf_off, int32_t(st.out_axes.size()), st.kg, st.sb(), 0};
     auto* fd = reinterpret_cast<int32_t*>(h + P->off_tfdep);
     for (size_t i = 0; i < t.finals.size(); ++i) {
         const qgm::TreeStep& mk = t.steps[maker[t.finals[i]]];
         fd[2 * i] = int32_t(mk.task_off);
         fd[2 * i + 1] = int32_t(mk.n_tasks());
     }
+    return true;
 }
 
 void layout_tables(qgm_plan_t* P) {
@@ -511,8 +538,11 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     std::string host(P->total, '\0');
     char* h = &host[0];
     fixed_matrices(reinterpret_cast<double2*>(h + P->off_fixed));
-    if (P->p.is_tree) fill_tree_tables(P, h);
-    else fill_step_tables(P, h);
+    if (P->p.is_tree) {
+        if (!fill_tree_tables(P, h)) return fail(QGM_E_INTERNAL, "bucket task records overlap or leave gaps");
+    } else {
+        fill_step_tables(P, h);
+    }
     void* d = nullptr;
     e = hipMalloc(&d, P->total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
@@ -527,6 +557,12 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
                                   reinterpret_cast<const qgm::TFactor*>(b + P->off_tfac),
                                   reinterpret_cast<const double2*>(b + P->off_fixed), nullptr,
                                   reinterpret_cast<float2*>(b + P->off_tg), P->p.tree.ones_g, nullptr);
+        int64_t max_entries = 0;
+        for (const qgm::TreeStep& st : P->p.tree.steps)
+            if (st.table_leaf) max_entries = std::max<int64_t>(max_entries, int64_t(1) << (st.out_axes.size() + st.sb()));
+        qgm::launch_tree_leaf_tables(reinterpret_cast<const qgm::TreeLeaf*>(b + P->off_tleaf),
+                                     P->p.tree.n_table_leaves, max_entries, reinterpret_cast<float2*>(b + P->off_tg),
+                                     nullptr);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "building the plan's factor tables"); }
@@ -868,6 +904,8 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     const qgm::Plan& p = plan->p;
     const qgm::TreePlan& t = p.tree;
     if (t.n_open > 0) return fail(QGM_E_UNSUPPORTED, "qgm_backward with ordering 1 supports no open qubits");
+    if (t.n_table_leaves > 0)   // only plans without gate values have them: nothing to differentiate
+        return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a circuit with gate values (value-slot gates)");
     if (B == 0) return QGM_OK;
     if (!bits || !grad_amps || !workspace || (p.n_slots > 0 && (!gate_vals || !gate_grads)))
         return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "

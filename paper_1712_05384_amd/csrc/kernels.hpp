@@ -64,6 +64,18 @@ struct TreeTask {
     int32_t in_omask[kTreeMaxIn];               // bit j: input t's row changes along the unit's result row bit j
     int32_t g_omask;                            // the same for the factor-table entry
     int32_t pad3;
+    // an input that is a leaf table (a bucket without inputs, built with the plan): its entry offset in the
+    // factor-table area (-1: an arena result), its output bits and their qubits (6 bits each); row r, bits s
+    // of the lane's bitstring -> entry offset + (r << sb) + s
+    int32_t in_tab[kTreeMaxIn];
+    int32_t in_tsb[kTreeMaxIn];
+    uint64_t in_tsig[kTreeMaxIn];
+};
+
+// The leaf tables of a plan (built once): R[o][s] = sum_w G[((o << k) | w) << sb | s].
+struct TreeLeaf {
+    int64_t g_off, leaf_off;
+    int32_t r, k, sb, pad;
 };
 
 // One persistent launch of the bucket elimination (k_tree_persist): every
@@ -206,6 +218,8 @@ void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFacto
                             int n_open, uint32_t zero_mask, const uint64_t* bits, int64_t B, uint32_t B_eff,
                             void* out, bool c128, hipStream_t stream);
 hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream);
+void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_entries, float2* gtab,
+                             hipStream_t stream);
 // Cross-entropy statistics and sampling from a set of amplitudes (xeb.hip).
 uint64_t xeb_workspace_bytes(int64_t B);
 void launch_xeb(const void* amps, bool c128, int64_t B, int n_qubits, double* out, double* ws, hipStream_t stream);

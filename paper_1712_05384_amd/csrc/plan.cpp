@@ -575,6 +575,7 @@ static void json_factor(std::ostringstream& o, const TFactor& f) {
 // slot beyond the bucket's own, the distinct factor-table entries, and the
 // unit's result rows.
 static int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
+    if (st.table_leaf) return 0;
     const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));
     const int r = int(st.out_axes.size());
     auto count_in = [&](const std::vector<int>& ax, int lo, int hi, const std::vector<int>& from) {
@@ -611,7 +612,8 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
       << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
-      << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask;
+      << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask
+      << ",\"table_leaves\":" << t.n_table_leaves;
     o << ",\"order\":"; json_ints(o, t.order);
     o << ",\"finals\":"; json_ints(o, t.finals);
     o << ",\"steps\":[],\"buckets\":[";
@@ -623,6 +625,7 @@ static std::string tree_json(const Plan& p, int detail) {
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
           << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows
+          << ",\"table_leaf\":" << (st.table_leaf ? 1 : 0)
           << ",\"issued_bytes_per_b\":" << 8 * st.n_tasks() * tree_unit_accesses(t, st);
         if (detail >= 1) {
             o << ",\"out_tensor\":" << st.out_tensor;

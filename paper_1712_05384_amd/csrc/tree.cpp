@@ -479,13 +479,25 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         std::sort(g.begin(), g.end(), [&](int a, int b) { return pos[a] < pos[b]; });
         for (int u : g) ts.gvars.push_back(m.free_var[u]);
         ts.sig_q = sigq;
+        // a bucket without inputs whose table over (result, output bits) is small: with fixed gates it is
+        // built once with the plan and read per lane; its axes follow its table variables
+        if (p.n_slots == 0 && !st.open && ts.in_tensors.empty() && !ts.out_axes.empty() &&
+            ts.gvars.size() == ts.out_axes.size() && int(ts.out_axes.size() + sigq.size()) <= kTreeLeafTableBits) {
+            ts.table_leaf = true;
+            ts.level = -1;
+            t.tensor_made[ts.out_tensor] = -1;
+            ts.out_axes = ts.gvars;
+            t.tensor_axes[ts.out_tensor] = ts.gvars;
+            ++t.n_table_leaves;
+        }
         step_groups.push_back({{std::vector<int>{}, st.facs}});
         for (auto& a : st.absorbed) step_groups.back().push_back(a);
         if (ts.out_axes.empty()) t.finals.push_back(ts.out_tensor);
         if (st.open) t.open_tensor = ts.out_tensor;   // the chain's last bucket comes last
         const double rows = double(int64_t(1) << ts.out_axes.size());
-        double b = 8.0 * rows;
-        for (int ti : ts.in_tensors) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
+        double b = ts.table_leaf ? 0.0 : 8.0 * rows;   // a leaf table is read from the caches, not per bitstring
+        for (int ti : ts.in_tensors)
+            if (t.tensor_made[ti] >= 0) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
         bytes += b;
         const int mult = int(ts.in_tensors.size()) + 1;
         flops += rows * double(int64_t(1) << ts.vars.size()) * (6.0 * std::max(mult - 1, 0) + 2.0);
@@ -496,7 +508,8 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     int n_levels = 0;
     for (auto& st : t.steps) n_levels = std::max(n_levels, st.level + 1);
     t.levels.assign(n_levels, {});
-    for (int s = 0; s < int(t.steps.size()); ++s) t.levels[t.steps[s].level].push_back(s);
+    for (int s = 0; s < int(t.steps.size()); ++s)
+        if (!t.steps[s].table_leaf) t.levels[t.steps[s].level].push_back(s);
     // factor encoding: summed variable i is index bit i, table variable j is bit kg + j
     t.max_rank = 0;
     t.max_in = 0;
@@ -555,8 +568,13 @@ namespace {
 }  // namespace
 
 double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
+    if (st.table_leaf) return 0.0;   // built once with the plan
+    std::vector<char> tab(t.tensor_axes.size(), 0);
+    for (const TreeStep& s : t.steps)
+        if (s.table_leaf) tab[s.out_tensor] = 1;
     double b = 8.0 * double(int64_t(1) << st.out_axes.size());
-    for (int tid : st.in_tensors) b += 8.0 * double(int64_t(1) << t.tensor_axes[tid].size());
+    for (int tid : st.in_tensors)   // a leaf table is a few KiB shared by every bitstring (cache-resident)
+        if (!tab[tid]) b += 8.0 * double(int64_t(1) << t.tensor_axes[tid].size());
     return b;
 }
 
@@ -671,7 +689,11 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     std::vector<int> placed;
     // a result holds at least 2^kTreeOcBits rows: a wave task writes that many
     auto alloc_rows = [&](int tid) { return int64_t(1) << std::max(int(t.tensor_axes[tid].size()), kTreeOcBits); };
+    std::vector<char> is_table(T, 0);
+    for (auto& st : t.steps)
+        if (st.table_leaf) is_table[st.out_tensor] = 1;
     for (int a : idx) {
+        if (is_table[a]) continue;   // lives in the leaf-table area
         const int64_t size = alloc_rows(a);
         std::vector<std::pair<int64_t, int64_t>> busy;
         for (int b : placed)
@@ -693,6 +715,11 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         st.g_off = g;
         g += st.g_entries();
     }
+    for (auto& st : t.steps)
+        if (st.table_leaf) {
+            st.leaf_off = g;
+            g += int64_t(1) << (st.out_axes.size() + st.sig_q.size());
+        }
     t.ones_g = g;                 // constant 1 read for inputs a bucket does not have
     t.g_total = g + 1;
     // wave tasks of the buckets with inputs, grouped by level (a level is one launch)
@@ -725,6 +752,7 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t.tensor_row_all.assign(T, 0);
     t.arena_rows_all = 0;
     for (int i = 0; i < T; ++i) {
+        if (is_table[i]) { t.tensor_row_all[i] = -1; continue; }
         t.tensor_row_all[i] = t.arena_rows_all;
         t.arena_rows_all += alloc_rows(i);
     }

@@ -69,13 +69,35 @@ __global__ void __launch_bounds__(256) k_tree_prologue(const TreeProBlock* __res
 template <int NIN, int K>
 __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
-                                          int64_t sig, uint32_t b, int64_t be) {
+                                          int64_t sig, uint64_t x, uint32_t b, int64_t be) {
     constexpr int W = 1 << K;
     constexpr int WC = W < 8 ? W : 8;          // summed-variable values per load batch
     static_assert(WC == W, "one load batch holds every summed value (the repeat copies index within it)");
     constexpr int OB = tree_unit_rows(NIN, K);
-    // input rows and factor-table entry of the unit's rows, and the offset of
-    // each summed value w in each input (scalar)
+    // Where input t's row r lives for this lane: base[t] + r * pitch[t] (a result
+    // in the arena: column b, pitch B_eff; a leaf table: its entries for the
+    // lane's output bits, pitch 2^sb; an input the bucket does not have: the
+    // constant 1, pitch 0).  Rows, the factor-table entry of the unit's rows and
+    // the offset of each summed value w in each input are scalar.
+    const float2* base[NIN];
+    int64_t pitch[NIN];
+#pragma unroll
+    for (int t = 0; t < NIN; ++t) {
+        if (tk.in_row[t] < 0) {
+            base[t] = gtab + ones_g;
+            pitch[t] = 0;
+        } else if (tk.in_tab[t] >= 0) {
+            const int tsb = tk.in_tsb[t];
+            const uint64_t pk = uint64_t(tk.in_tsig[t]);
+            uint32_t s = 0;
+            for (int i = 0; i < tsb; ++i) s |= uint32_t((x >> ((pk >> (6 * i)) & 63u)) & 1ull) << i;
+            base[t] = gtab + tk.in_tab[t] + s;
+            pitch[t] = int64_t(1) << tsb;
+        } else {
+            base[t] = ain + b;
+            pitch[t] = be;
+        }
+    }
     int64_t row[OB][NIN], gent[OB], off[NIN][W];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
@@ -86,7 +108,7 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 if ((w >> i) & 1) o += tk.in_vs[t][i];
-            off[t][w] = o * be;
+            off[t][w] = o * pitch[t];
         }
     }
     gent[0] = tk.g_ent;
@@ -124,8 +146,7 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
         for (int i = 0; i < OB; ++i)
 #pragma unroll
             for (int t = 0; t < NIN; ++t) {
-                // an input the bucket does not have reads the constant 1 (same address in every lane)
-                const float2* __restrict__ src = tk.in_row[t] >= 0 ? ain + row[i][t] * be + b : gtab + ones_g;
+                const float2* __restrict__ src = base[t] + row[i][t] * pitch[t];
                 const bool rep_i = i > 0 && !((in_om[t] >> __builtin_ctz(uint32_t(i))) & 1u);
 #pragma unroll
                 for (int w = 0; w < WC; ++w) {
@@ -196,10 +217,10 @@ __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const 
                                           uint32_t b, int64_t be) {
     static_assert(kTreeMaxSum == 3, "tasks sum 0 (the product over the open qubits), 1, 2 or 3 variables");
     const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
-    if (tk.k == 0) tree_unit<NIN, 0>(tk, ain, aout, gtab, ones_g, sig, b, be);
-    else if (tk.k == 1) tree_unit<NIN, 1>(tk, ain, aout, gtab, ones_g, sig, b, be);
-    else if (tk.k == 2) tree_unit<NIN, 2>(tk, ain, aout, gtab, ones_g, sig, b, be);
-    else tree_unit<NIN, 3>(tk, ain, aout, gtab, ones_g, sig, b, be);
+    if (tk.k == 0) tree_unit<NIN, 0>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
+    else if (tk.k == 1) tree_unit<NIN, 1>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
+    else if (tk.k == 2) tree_unit<NIN, 2>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
+    else tree_unit<NIN, 3>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
 }
 
 // One level of the elimination tree: wave unit u handles task u / n_bg for
@@ -583,6 +604,31 @@ void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFacto
     const uint32_t gy = uint32_t(((int64_t(1) << n_open) + kOpenChunk - 1) / kOpenChunk);
     hipLaunchKernelGGL(k_tree_final_open, dim3(gx, gy), dim3(256), 0, stream, final_rows, n_final, phase, n_phase,
                        fixed, slots, arena, open_row, n_open, zero_mask, bits, B, B_eff, out, c128 ? 1 : 0);
+}
+
+// Leaf tables (plans without gate values, once): block (entry chunk, leaf).
+// R[o][s] = sum over the leaf's summed values w of its factor table
+// G[((o << k) | w) << sb | s], in FP64, rounded once.
+__global__ void __launch_bounds__(256) k_tree_leaf_tables(const TreeLeaf* __restrict__ leaves,
+                                                          float2* __restrict__ gtab) {
+    const TreeLeaf L = leaves[blockIdx.y];
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= (int64_t(1) << (L.r + L.sb))) return;
+    const int64_t o = e >> L.sb, sg = e & ((int64_t(1) << L.sb) - 1);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t w = 0; w < (int64_t(1) << L.k); ++w) {
+        const float2 v = gtab[L.g_off + ((((o << L.k) | w) << L.sb) | sg)];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    gtab[L.leaf_off + e] = make_float2(float(acc.x), float(acc.y));
+}
+
+void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_entries, float2* gtab,
+                             hipStream_t stream) {
+    if (n_leaves <= 0) return;
+    hipLaunchKernelGGL(k_tree_leaf_tables, dim3(uint32_t((max_entries + 255) / 256), uint32_t(n_leaves)), dim3(256),
+                       0, stream, leaves, gtab);
 }
 
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,

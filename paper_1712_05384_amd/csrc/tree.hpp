@@ -42,6 +42,7 @@ constexpr int kPersistXcds = 8;                 // accelerator complexes (each w
 constexpr int kPersistMaxRanks = 256;           // work-groups per complex in one launch, at most
 constexpr int kPersistSeen0 = 64;
 constexpr int kPersistFlags0 = kPersistSeen0 + kPersistXcds * kPersistMaxRanks;
+constexpr int kTreeLeafTableBits = 14;   // a leaf table has at most 2^14 entries (result bits + output bits)
 constexpr int kTreeMaxIn = 8;       // earlier results multiplied in one bucket
 constexpr int kTreeMaxSig = 12;     // output bits read by one bucket's factors
 constexpr int kTreeMaxGBits = 10;   // variables of a bucket's factor table besides v
@@ -116,6 +117,10 @@ struct TreeStep {
         return n;
     }
     int64_t g_off = 0;                  // complex offset in the factor-table area
+    // a bucket without inputs in a plan without gate values: its result is a table over (result index,
+    // its output bits) built once with the plan, read per lane by its reader; no level, rows or tasks
+    bool table_leaf = false;
+    int64_t leaf_off = 0;               // complex offset of that table (entry (o << sb) | sigma)
     int64_t task_off = 0;               // first wave task of this bucket
     int unit_rows = 1;                  // result rows per wave task (tree_unit_rows of its launch)
     int64_t n_tasks() const {
@@ -138,6 +143,7 @@ struct TreePlan {
     // axes, and the output bits of open qubits without non-diagonal gates (amplitude 0 when set)
     int n_open = 0;
     int open_tensor = -1;
+    int n_table_leaves = 0;
     std::vector<int> open_axis_bit;
     int zero_mask = 0;
     std::vector<TFactor> phase;                  // factors without free variables

@@ -364,3 +364,19 @@ def test_tree_plan_open_bucket_chain():
             x = (x & ~np.uint64(1 << q)) | np.uint64(((o >> i) & 1) << q)
         ref[:, o] = psi[x.astype(np.int64)]
     assert np.abs(got - ref).max() < 1e-12
+
+
+def test_tree_plan_leaf_tables():
+    """Buckets without inputs of a circuit without gate values become tables
+    over (result index, output bits), built with the plan, with no level of
+    their own; a circuit with gate values keeps them as buckets."""
+    c, bits = C.workload("c2_5x5_d25")
+    info = Q.plan(c, ordering=1).info(1)
+    leaves = [b for b in info["buckets"] if b["table_leaf"]]
+    assert info["table_leaves"] == len(leaves) > 0
+    assert all(b["level"] == -1 and b["n_in"] == 0 for b in leaves)
+    assert min(b["level"] for b in info["buckets"] if not b["table_leaf"]) == 0
+    got = run_tree_plan(info, None, bits[:16])
+    assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits[:16])).max() < 1e-12
+    c4, _ = C.workload("c4_5x5_d20_U")
+    assert Q.plan(c4, ordering=1).info(0)["table_leaves"] == 0

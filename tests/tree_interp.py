@@ -77,7 +77,11 @@ def run_tree_plan(info, gate_vals, bits):
     owner = np.full(max(info["arena_rows"], 1), -1)
     xb = lambda q: ((bits >> np.uint64(q)) & np.uint64(1)).astype(np.int64)
 
+    tables = {}   # results of leaf-table buckets (built with the plan, not in the arena)
+
     def read(tid):
+        if tid in tables:
+            return tables[tid]
         t = tensors[tid]
         rows = slice(t["row"], t["row"] + (1 << len(t["axes"])))
         assert (owner[rows] == tid).all(), f"result {tid} was overwritten before it was read"
@@ -113,6 +117,9 @@ def run_tree_plan(info, gate_vals, bits):
                         idx |= (val[ax] if ax in val else bit_of[ax]) << a
                     term *= T[idx]
                 acc += term
+            if st.get("table_leaf", 0):
+                tables[st["out_tensor"]] = acc
+                continue
             pending.append((st["out_tensor"], acc))
         for tid, acc in pending:
             t = tensors[tid]

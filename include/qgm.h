@@ -63,7 +63,13 @@ typedef enum {
  *  QGM_YHDG = RY(-pi/2) = (1/sqrt2)[[1,1],[-1,1]], QGM_X = [[0,1],[1,0]],
  *  QGM_Y = [[0,-i],[i,0]], QGM_Z = diag(1,-1) (TDG and Z diagonal) */
 typedef enum { QGM_H = 0, QGM_T = 1, QGM_XH = 2, QGM_YH = 3, QGM_CZ = 4, QGM_U = 5, QGM_UD = 6, QGM_TDG = 7,
-               QGM_XHDG = 8, QGM_YHDG = 9, QGM_X = 10, QGM_Y = 11, QGM_Z = 12 } qgm_kind;
+               QGM_XHDG = 8, QGM_YHDG = 9, QGM_X = 10, QGM_Y = 11, QGM_Z = 12, QGM_U2 = 13 } qgm_kind;
+/* QGM_U2 = general two-qubit gate on (q0, q1), non-diagonal: it opens a new
+ *           variable on both qubits and its factor couples the four (the
+ *           4-clique of Sec. III.B).  Its 4x4 matrix M[r][c], r = 2 a0 + a1 the
+ *           values after the gate and c = 2 c0 + c1 before (a0, c0 on q0), is
+ *           read from four value slots: M[r][c] = gate_vals[slot + r][c >> 1][c & 1].
+ *           Bucket elimination (ordering 1) only; no qgm_backward. */
 
 typedef struct {
     int32_t kind;    /* qgm_kind */

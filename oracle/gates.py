@@ -18,6 +18,7 @@ import numpy as np
 
 KIND_H, KIND_T, KIND_XH, KIND_YH, KIND_CZ, KIND_U, KIND_UD = 0, 1, 2, 3, 4, 5, 6
 KIND_TDG, KIND_XHDG, KIND_YHDG, KIND_X, KIND_Y, KIND_Z = 7, 8, 9, 10, 11, 12
+KIND_U2 = 13   # general two-qubit gate; row r of its 4x4 matrix in value slot (slot + r)
 
 _R2 = 1.0 / np.sqrt(2.0)
 _FIXED = {
@@ -49,3 +50,9 @@ def gate_matrix(kind: int, slot: int, gate_vals) -> np.ndarray:
 
 def is_diagonal_kind(kind: int) -> bool:
     return int(kind) in (KIND_T, KIND_CZ, KIND_UD, KIND_TDG, KIND_Z)
+
+
+def gate_matrix_2q(slot: int, gate_vals) -> np.ndarray:
+    """4x4 complex128 matrix of a general two-qubit gate: M[2 a0 + a1][2 c0 + c1]
+    (a0, c0 on its first qubit) with row r read from gate_vals[slot + r]."""
+    return np.stack([np.asarray(gate_vals[int(slot) + r], dtype=np.complex128).reshape(4) for r in range(4)])

@@ -10,7 +10,7 @@ import subprocess
 
 import numpy as np
 
-from .gates import gate_matrix, KIND_CZ
+from .gates import gate_matrix, gate_matrix_2q, KIND_CZ, KIND_U2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sv_oracle.c")
@@ -66,8 +66,40 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _has_2q(gates) -> bool:
+    g = np.asarray(gates, dtype=np.int64).reshape(-1, 5)
+    return bool((g[:, 0] == KIND_U2).any())
+
+
+def sv_state_numpy(n: int, gates, gate_vals=None) -> np.ndarray:
+    """U|0...0> by plain numpy tensor contractions (every gate kind, including
+    the general two-qubit gate); index = sum_q x_q 2^q."""
+    g = np.asarray(gates, dtype=np.int64).reshape(-1, 5)
+    g = g[np.argsort(g[:, 1], kind="stable")]
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1.0
+    psi = psi.reshape([2] * n)          # axis n - 1 - q holds qubit q
+    ax = lambda q: n - 1 - int(q)       # noqa: E731
+    for kind, _cyc, q0, q1, slot in g:
+        if kind == KIND_CZ:
+            sl = [slice(None)] * n
+            sl[ax(q0)] = 1
+            sl[ax(q1)] = 1
+            psi[tuple(sl)] *= -1.0
+        elif kind == KIND_U2:
+            T = gate_matrix_2q(slot, gate_vals).reshape(2, 2, 2, 2)   # (a0, a1, c0, c1)
+            psi = np.tensordot(T, psi, axes=([2, 3], [ax(q0), ax(q1)]))
+            psi = np.moveaxis(psi, [0, 1], [ax(q0), ax(q1)])
+        else:
+            m = gate_matrix(kind, slot, gate_vals)
+            psi = np.moveaxis(np.tensordot(m, psi, axes=([1], [ax(q0)])), 0, ax(q0))
+    return psi.reshape(-1)
+
+
 def sv_state(n: int, gates, gate_vals=None) -> np.ndarray:
     """U|0...0> as complex128 [2^n]; index = sum_q x_q 2^q."""
+    if _has_2q(gates):
+        return sv_state_numpy(n, gates, gate_vals)
     _, op_q, op_m = _ops(n, gates, gate_vals)
     out = np.empty(2 ** n, dtype=np.complex128)
     rc = _load().oracle_sv_state(n, len(op_q), _ptr(op_q), _ptr(op_m), _ptr(out))
@@ -78,6 +110,8 @@ def sv_state(n: int, gates, gate_vals=None) -> np.ndarray:
 
 def sv_amplitudes(n: int, gates, gate_vals, bits) -> np.ndarray:
     """<x|U|0...0> for each uint64 bitstring x (bit q = qubit q)."""
+    if _has_2q(gates):
+        return sv_state_numpy(n, gates, gate_vals)[np.asarray(bits, dtype=np.uint64).astype(np.int64)]
     _, op_q, op_m = _ops(n, gates, gate_vals)
     bits = np.ascontiguousarray(bits, dtype=np.uint64)
     out = np.empty(len(bits), dtype=np.complex128)

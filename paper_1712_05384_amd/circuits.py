@@ -33,6 +33,7 @@ import numpy as np
 # Gate kinds; the numbering is the C-ABI's (qgm_kind in include/qgm.h).
 H, T, XH, YH, CZ, U, UD = 0, 1, 2, 3, 4, 5, 6
 TDG, XHDG, YHDG, X, Y, Z = 7, 8, 9, 10, 11, 12   # inverses and Pauli operators (expectation values)
+U2 = 13   # general two-qubit gate: rows of its 4x4 matrix in four consecutive value slots
 KIND_NAMES = {H: "H", T: "T", XH: "X^1/2", YH: "Y^1/2", CZ: "CZ", U: "U", UD: "UD"}
 DIAGONAL_KINDS = (T, CZ, UD)
 

@@ -904,6 +904,7 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     const qgm::Plan& p = plan->p;
     const qgm::TreePlan& t = p.tree;
     if (t.n_open > 0) return fail(QGM_E_UNSUPPORTED, "qgm_backward with ordering 1 supports no open qubits");
+    if (p.n_2q > 0) return fail(QGM_E_UNSUPPORTED, "qgm_backward supports no non-diagonal two-qubit gates");
     if (t.n_table_leaves > 0)   // only plans without gate values have them: nothing to differentiate
         return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a circuit with gate values (value-slot gates)");
     if (B == 0) return QGM_OK;

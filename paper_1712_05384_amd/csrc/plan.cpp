@@ -73,29 +73,32 @@ static qgm_status validate(const qgm_circuit* c, const int32_t* open, int32_t n_
     for (int i = 0; i < c->n_gates; ++i) {
         const qgm_gate& g = c->gates[i];
         char buf[160];
-        if (g.kind < QGM_H || g.kind > QGM_Z) {
+        if (g.kind < QGM_H || g.kind > QGM_U2) {
             snprintf(buf, sizeof buf, "gate %d: unknown kind %d", i, g.kind); *err = buf; return QGM_E_INVALID;
         }
         if (g.cycle < 0) { snprintf(buf, sizeof buf, "gate %d: negative cycle", i); *err = buf; return QGM_E_INVALID; }
         if (g.q0 < 0 || g.q0 >= n) {
             snprintf(buf, sizeof buf, "gate %d: qubit %d out of range", i, g.q0); *err = buf; return QGM_E_INVALID;
         }
-        if (g.kind == QGM_CZ) {
+        const bool two_q = g.kind == QGM_CZ || g.kind == QGM_U2;
+        if (two_q) {
             if (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0) {
-                snprintf(buf, sizeof buf, "gate %d: CZ needs two distinct qubits in range", i); *err = buf;
+                snprintf(buf, sizeof buf, "gate %d: a two-qubit gate needs two distinct qubits in range", i); *err = buf;
                 return QGM_E_INVALID;
             }
         } else if (g.q1 != -1) {
             snprintf(buf, sizeof buf, "gate %d: single-qubit gate must have q1 = -1", i); *err = buf;
             return QGM_E_INVALID;
         }
-        if (g.kind == QGM_U || g.kind == QGM_UD) {
-            if (g.slot < 0 || g.slot >= c->n_slots) {
-                snprintf(buf, sizeof buf, "gate %d: slot %d out of range [0, %d)", i, g.slot, c->n_slots);
+        if (g.kind == QGM_U || g.kind == QGM_UD || g.kind == QGM_U2) {
+            const int need = g.kind == QGM_U2 ? 4 : 1;   // a two-qubit gate reads four slots
+            if (g.slot < 0 || g.slot + need > c->n_slots) {
+                snprintf(buf, sizeof buf, "gate %d: slots [%d, %d) out of range [0, %d)", i, g.slot, g.slot + need,
+                         c->n_slots);
                 *err = buf; return QGM_E_INVALID;
             }
         }
-        for (int q : {g.q0, g.kind == QGM_CZ ? g.q1 : -1}) {
+        for (int q : {g.q0, two_q ? g.q1 : -1}) {
             if (q < 0) continue;
             if (!used.insert({g.cycle, q}).second) {
                 snprintf(buf, sizeof buf, "gate %d: qubit %d used twice in cycle %d", i, q, g.cycle);
@@ -463,7 +466,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         p.chain[q].push_back(q);
     }
     p.recs.clear();
-    p.n_diag_gates = p.n_nondiag_gates = p.n_cz = 0;
+    p.n_diag_gates = p.n_nondiag_gates = p.n_cz = p.n_2q = 0;
     for (int i : idx) {
         const qgm_gate& g = c->gates[i];
         GateRec r;
@@ -473,6 +476,18 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
             r.type = 2; r.q1 = g.q1;
             r.var0 = p.chain[g.q0].back(); r.var1 = p.chain[g.q1].back();
             p.n_cz++;
+        } else if (g.kind == QGM_U2) {   // both worldlines open a variable; the factor couples all four
+            r.type = 3; r.q1 = g.q1; r.mat = kFixedMats + g.slot;
+            r.var2 = p.chain[g.q0].back(); r.var3 = p.chain[g.q1].back();
+            for (int k = 0; k < 2; ++k) {
+                const int q = k == 0 ? g.q0 : g.q1;
+                VarInfo v; v.qubit = q; v.k = int(p.chain[q].size());
+                const int id = int(p.vars.size());
+                p.vars.push_back(v);
+                (k == 0 ? r.var0 : r.var1) = id;
+                p.chain[q].push_back(id);
+            }
+            p.n_2q++;
         } else if (is_diag_kind(g.kind)) {
             r.type = 1; r.var0 = p.chain[g.q0].back(); r.mat = mat_index(g.kind, g.slot);
             p.n_diag_gates++;
@@ -490,6 +505,10 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     }
     for (int q = 0; q < n; ++q) p.vars[p.chain[q].back()].is_final = true;
     for (int i = 0; i < n_open; ++i) p.vars[p.chain[open[i]].back()].open_idx = i;
+    if (p.n_2q > 0 && opts.ordering != 1) {
+        *err = "non-diagonal two-qubit gates need bucket elimination (ordering 1)";
+        return QGM_E_UNSUPPORTED;
+    }
     p.sliced.clear();
     p.is_tree = opts.ordering == 1;
     if (p.is_tree) {
@@ -566,7 +585,9 @@ static void json_ints(std::ostringstream& o, const std::vector<int>& v) {
 }
 
 static void json_factor(std::ostringstream& o, const TFactor& f) {
-    o << "[" << f.type << "," << f.mat << "," << f.src0 << "," << f.bit0 << "," << f.src1 << "," << f.bit1 << "]";
+    o << "[" << f.type << "," << f.mat << "," << f.src0 << "," << f.bit0 << "," << f.src1 << "," << f.bit1;
+    if (f.type == TF_MAT4) o << "," << f.src2 << "," << f.bit2 << "," << f.src3 << "," << f.bit3;
+    o << "]";
 }
 
 // Row loads and stores one wave unit of a bucket issues (64 lanes x 8 bytes
@@ -608,7 +629,7 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
       << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start
       << ",\"level_launches\":" << (std::max(t.tail_start - t.first_level, 0) + (t.tail_start < int(t.levels.size()) ? 1 : 0))
-      << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
+      << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
       << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
@@ -674,7 +695,7 @@ std::string plan_json(const Plan& p, int detail) {
     o << "{\"ordering\":0,\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols << ",\"n_vars\":" << p.vars.size()
       << ",\"n_open\":" << p.n_open << ",\"n_slots\":" << p.n_slots << ",\"n_steps\":" << p.steps.size()
       << ",\"max_rank\":" << p.r_max << ",\"n_sliced\":" << p.sliced.size()
-      << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates
+      << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << p.g_total
       << ",\"bytes_per_amp\":" << bytes * double(int64_t(1) << p.sliced.size())
       << ",\"flops_per_amp\":" << flops * double(int64_t(1) << p.sliced.size());

@@ -24,9 +24,11 @@ struct VarInfo {
 
 // A gate in time order, with the variables its factor touches.
 struct GateRec {
-    int type = 0;            // 0 = non-diagonal 1q, 1 = diagonal 1q, 2 = CZ
+    int type = 0;            // 0 = non-diagonal 1q, 1 = diagonal 1q, 2 = CZ, 3 = non-diagonal 2q (QGM_U2)
     int q0 = -1, q1 = -1;
-    int var0 = -1, var1 = -1;   // NONDIAG: (new, old); DIAG: (cur, -1); CZ: (cur q0, cur q1)
+    int var0 = -1, var1 = -1;   // NONDIAG: (new, old); DIAG: (cur, -1); CZ: (cur q0, cur q1);
+                                // 2q: (new q0, new q1), with var2, var3 = (old q0, old q1)
+    int var2 = -1, var3 = -1;
     int mat = -1;            // matrix index: 0..3 fixed kinds, 4 + slot for U/UD
     int gate_index = -1;     // row in the input gate list
 };
@@ -60,6 +62,7 @@ struct Step {
 
 struct Plan {
     int rows = 0, cols = 0, n = 0, n_slots = 0;
+    int n_2q = 0;            // non-diagonal two-qubit gates (QGM_U2)
     int n_open = 0;
     std::vector<int> open_qubits;
     qgm_plan_opts opts{};

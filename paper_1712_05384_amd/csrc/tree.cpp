@@ -29,7 +29,7 @@ enum { VK_FREE = 0, VK_ZERO = 1, VK_SIG = 2 };
 
 struct RawFactor {
     int type, mat;
-    int v[2];
+    int v[4];
     int nv;
     std::vector<int> free;   // free-variable indices (fi) it touches, distinct
 };
@@ -48,7 +48,7 @@ TFactor fixed_factor(const Plan& p, const Model& m, const RawFactor& f) {
     TFactor t{};
     t.type = f.type;
     t.mat = f.mat;
-    int* srcs[2][2] = {{&t.src0, &t.bit0}, {&t.src1, &t.bit1}};
+    int* srcs[4][2] = {{&t.src0, &t.bit0}, {&t.src1, &t.bit1}, {&t.src2, &t.bit2}, {&t.src3, &t.bit3}};
     for (int i = 0; i < f.nv; ++i) {
         const int v = f.v[i];
         if (m.kind[v] == VK_SIG) { *srcs[i][0] = TS_SIG; *srcs[i][1] = p.vars[v].qubit; }
@@ -531,7 +531,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
                 TFactor tf{};
                 tf.type = rf.type;
                 tf.mat = rf.mat;
-                int* srcs[2][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}};
+                int* srcs[4][2] = {{&tf.src0, &tf.bit0}, {&tf.src1, &tf.bit1}, {&tf.src2, &tf.bit2}, {&tf.src3, &tf.bit3}};
                 for (int k = 0; k < rf.nv; ++k) {
                     const int var = rf.v[k];
                     if (m.kind[var] == VK_FREE) {
@@ -624,7 +624,9 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         f.mat = g.mat;
         if (g.type == 0) { f.type = TF_MAT; f.v[0] = g.var0; f.v[1] = g.var1; f.nv = 2; }
         else if (g.type == 1) { f.type = TF_DIAG; f.v[0] = g.var0; f.v[1] = -1; f.nv = 1; }
-        else { f.type = TF_CZ; f.mat = -1; f.v[0] = g.var0; f.v[1] = g.var1; f.nv = 2; }
+        else if (g.type == 3) {   // the 4-clique of a non-diagonal two-qubit gate
+            f.type = TF_MAT4; f.v[0] = g.var0; f.v[1] = g.var1; f.v[2] = g.var2; f.v[3] = g.var3; f.nv = 4;
+        } else { f.type = TF_CZ; f.mat = -1; f.v[0] = g.var0; f.v[1] = g.var1; f.nv = 2; }
         for (int k = 0; k < f.nv; ++k) {
             const int u = m.fi[f.v[k]];
             if (u >= 0 && std::find(f.free.begin(), f.free.end(), u) == f.free.end()) f.free.push_back(u);
@@ -635,11 +637,12 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t.phase = m.phase;
     t.n_free = nF;
     std::vector<uint8_t> adj(size_t(nF) * nF, 0);
-    for (auto& f : m.facs)
-        if (f.free.size() == 2) {
-            adj[size_t(f.free[0]) * nF + f.free[1]] = 1;
-            adj[size_t(f.free[1]) * nF + f.free[0]] = 1;
-        }
+    for (auto& f : m.facs)   // a factor joins its free variables pairwise (a 4-clique for a two-qubit gate)
+        for (size_t i = 0; i < f.free.size(); ++i)
+            for (size_t j = i + 1; j < f.free.size(); ++j) {
+                adj[size_t(f.free[i]) * nF + f.free[j]] = 1;
+                adj[size_t(f.free[j]) * nF + f.free[i]] = 1;
+            }
     // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks
     const int restarts = nF > 1500 ? 1 : (nF > 600 ? 4 : 16);
     std::vector<int> best;

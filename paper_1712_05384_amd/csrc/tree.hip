@@ -273,7 +273,8 @@ __global__ void __launch_bounds__(256) k_tree_level(const TreeTask* __restrict__
 // values staged in LDS by stage_phase.
 struct PhaseLds {
     double2 v[kTreeMaxPhaseLds][4];
-    int32_t q[kTreeMaxPhaseLds][2];   // bit of x feeding each variable (-1: fixed 0)
+    int32_t q[kTreeMaxPhaseLds][2];   // bit of x feeding each variable (-1: fixed 0; -2: a two-qubit gate
+                                      //   factor, evaluated from its record)
 };
 
 __device__ __forceinline__ int stage_phase(PhaseLds& P, const TFactor* __restrict__ phase, int n_phase,
@@ -281,13 +282,40 @@ __device__ __forceinline__ int stage_phase(PhaseLds& P, const TFactor* __restric
     const int n_lds = n_phase < kTreeMaxPhaseLds ? n_phase : kTreeMaxPhaseLds;
     for (int i = threadIdx.x; i < n_lds * 4; i += blockDim.x) {
         const TFactor f = phase[i >> 2];
-        P.v[i >> 2][i & 3] = factor_value(f, (i >> 1) & 1u, i & 1u, fixed, slots);
+        if (f.type != TF_MAT4) P.v[i >> 2][i & 3] = factor_value(f, (i >> 1) & 1u, i & 1u, fixed, slots);
         if ((i & 3) == 0) {
-            P.q[i >> 2][0] = f.src0 == TS_SIG ? f.bit0 : -1;
+            P.q[i >> 2][0] = f.type == TF_MAT4 ? -2 : (f.src0 == TS_SIG ? f.bit0 : -1);
             P.q[i >> 2][1] = f.src1 == TS_SIG ? f.bit1 : -1;
         }
     }
     return n_lds;
+}
+
+// A factor without free variables for bitstring x, from its record.
+__device__ __forceinline__ double2 phase_factor(const TFactor& f, uint64_t x, const double2* __restrict__ fixed,
+                                                const float2* __restrict__ slots) {
+    auto bit = [&](int32_t src, int32_t b) { return src == TS_SIG ? uint32_t((x >> b) & 1ull) : 0u; };
+    uint32_t a4 = bit(f.src0, f.bit0) * 2u + bit(f.src1, f.bit1);
+    if (f.type == TF_MAT4) a4 = a4 * 4u + bit(f.src2, f.bit2) * 2u + bit(f.src3, f.bit3);
+    return factor_value_any(f, a4, fixed, slots);
+}
+
+// Product of the factors without free variables for bitstring x (FP64).
+__device__ __forceinline__ double2 phase_product(const PhaseLds& P, int n_lds, const TFactor* __restrict__ phase,
+                                                 int n_phase, const double2* __restrict__ fixed,
+                                                 const float2* __restrict__ slots, uint64_t x) {
+    double2 acc = make_double2(1.0, 0.0);
+    for (int i = 0; i < n_lds; ++i) {
+        if (P.q[i][0] == -2) {
+            acc = cmuld(acc, phase_factor(phase[i], x, fixed, slots));
+            continue;
+        }
+        const uint32_t a = P.q[i][0] >= 0 ? uint32_t((x >> P.q[i][0]) & 1ull) : 0u;
+        const uint32_t c = P.q[i][1] >= 0 ? uint32_t((x >> P.q[i][1]) & 1ull) : 0u;
+        acc = cmuld(acc, P.v[i][a * 2 + c]);
+    }
+    for (int i = n_lds; i < n_phase; ++i) acc = cmuld(acc, phase_factor(phase[i], x, fixed, slots));   // beyond LDS
+    return acc;
 }
 
 // Amplitude = phase x product of the rank-0 results (FP64), written as complex64 or complex128.
@@ -296,18 +324,7 @@ __device__ __forceinline__ void write_amplitude(const PhaseLds& P, int n_lds, co
                                                 const float2* __restrict__ slots, const int64_t* __restrict__ final_rows,
                                                 int n_final, const float2* __restrict__ arena, uint64_t x, uint32_t b,
                                                 uint32_t B_eff, void* __restrict__ out, int c128) {
-    double2 acc = make_double2(1.0, 0.0);
-    for (int i = 0; i < n_lds; ++i) {
-        const uint32_t a = P.q[i][0] >= 0 ? uint32_t((x >> P.q[i][0]) & 1ull) : 0u;
-        const uint32_t c = P.q[i][1] >= 0 ? uint32_t((x >> P.q[i][1]) & 1ull) : 0u;
-        acc = cmuld(acc, P.v[i][a * 2 + c]);
-    }
-    for (int i = n_lds; i < n_phase; ++i) {   // beyond the LDS copy: read the records directly
-        const TFactor f = phase[i];
-        const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
-        const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
-        acc = cmuld(acc, factor_value(f, a, c, fixed, slots));
-    }
+    double2 acc = phase_product(P, n_lds, phase, n_phase, fixed, slots, x);
     for (int i = 0; i < n_final; ++i) {
         const float2 r = arena[final_rows[i] * int64_t(B_eff) + b];
         acc = cmuld(acc, make_double2(r.x, r.y));
@@ -556,18 +573,7 @@ __global__ void __launch_bounds__(256) k_tree_final_open(const int64_t* __restri
     const uint32_t b = blockIdx.x * 256u + threadIdx.x;
     if (int64_t(b) >= B) return;
     const uint64_t x = bits[b];
-    double2 acc = make_double2(1.0, 0.0);
-    for (int i = 0; i < n_lds; ++i) {
-        const uint32_t a = P.q[i][0] >= 0 ? uint32_t((x >> P.q[i][0]) & 1ull) : 0u;
-        const uint32_t c = P.q[i][1] >= 0 ? uint32_t((x >> P.q[i][1]) & 1ull) : 0u;
-        acc = cmuld(acc, P.v[i][a * 2 + c]);
-    }
-    for (int i = n_lds; i < n_phase; ++i) {
-        const TFactor f = phase[i];
-        const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
-        const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
-        acc = cmuld(acc, factor_value(f, a, c, fixed, slots));
-    }
+    double2 acc = phase_product(P, n_lds, phase, n_phase, fixed, slots, x);
     for (int i = 0; i < n_final; ++i) {
         const float2 r = arena[final_rows[i] * int64_t(B_eff) + b];
         acc = cmuld(acc, make_double2(r.x, r.y));

@@ -80,13 +80,17 @@ enum : int32_t {
     TF_MAT = 0,     // non-diagonal 2x2 gate: M[new][old], (src0, bit0) = new, (src1, bit1) = old
     TF_DIAG = 1,    // diagonal gate: M[c][c] on (src0, bit0)
     TF_CZ = 2,      // (-1)^(a b)
-    TF_DELTA0 = 3   // phase only: the amplitude is 0 unless (src0, bit0) is 0
+    TF_DELTA0 = 3,  // phase only: the amplitude is 0 unless (src0, bit0) is 0
+    TF_MAT4 = 4     // non-diagonal two-qubit gate: M[2 a0 + a1][2 c0 + c1], sources 0, 1 = a0, a1 (after),
+                    //   2, 3 = c0, c1 (before); the value slots mat - kFixedMats .. + 3 hold the rows
 };
 
 struct TFactor {
     int32_t type, mat;
     int32_t src0, bit0;
     int32_t src1, bit1;
+    int32_t src2, bit2;                 // TF_MAT4 only: the variables before the gate
+    int32_t src3, bit3;
 };
 
 // A group of factors of a bucket's factor table: the table entry is the

@@ -35,28 +35,50 @@ __device__ __forceinline__ double2 factor_value(const TFactor& f, uint32_t a, ui
     }
 }
 
+// Value of a two-qubit gate factor (TF_MAT4) at argument index
+// a4 = 8 a0 + 4 a1 + 2 c0 + c1: M[2 a0 + a1][2 c0 + c1], rows in consecutive slots.
+__device__ __forceinline__ double2 factor_value4(const TFactor& f, uint32_t a4, const float2* __restrict__ slots) {
+    const float2 m = slots[size_t(f.mat - kFixedMats) * 4 + a4];
+    return make_double2(m.x, m.y);
+}
+
+// Value of any factor for argument index a4 (its variables' values, first
+// variable most significant: 2 bits, or 4 for TF_MAT4).
+__device__ __forceinline__ double2 factor_value_any(const TFactor& f, uint32_t a4, const double2* __restrict__ fixed,
+                                                    const float2* __restrict__ slots) {
+    if (f.type == TF_MAT4) return factor_value4(f, a4, slots);
+    return factor_value(f, (a4 >> 1) & 1u, a4 & 1u, fixed, slots);
+}
 
 constexpr int kTreeMaxPrologueFactors = 64;
 constexpr int kTreeMaxPhaseLds = 512;
 
-// The four values of up to kTreeMaxPrologueFactors factors, and the sources
-// of their variables, staged in LDS by the whole block.
+// The values of up to kTreeMaxPrologueFactors factors (4, or 16 for a
+// two-qubit gate), and the sources of their variables, staged in LDS by the
+// whole block.
 struct FactorLds {
-    double2 v[kTreeMaxPrologueFactors][4];
-    int32_t s[kTreeMaxPrologueFactors][4];
+    double2 v[kTreeMaxPrologueFactors][16];
+    int32_t s[kTreeMaxPrologueFactors][8];
+    int32_t four[kTreeMaxPrologueFactors];
 };
 
 __device__ __forceinline__ int stage_factors(FactorLds& L, const TFactor* __restrict__ facs, int n_fac,
                                              const double2* __restrict__ fixed, const float2* __restrict__ slots) {
     const int nf = n_fac < kTreeMaxPrologueFactors ? n_fac : kTreeMaxPrologueFactors;
-    for (int i = threadIdx.x; i < nf * 4; i += blockDim.x) {
-        const TFactor f = facs[i >> 2];
-        L.v[i >> 2][i & 3] = factor_value(f, (i >> 1) & 1u, i & 1u, fixed, slots);
-        if ((i & 3) == 0) {
-            L.s[i >> 2][0] = f.src0;
-            L.s[i >> 2][1] = f.bit0;
-            L.s[i >> 2][2] = f.src1;
-            L.s[i >> 2][3] = f.bit1;
+    for (int i = threadIdx.x; i < nf * 16; i += blockDim.x) {
+        const TFactor f = facs[i >> 4];
+        const uint32_t a4 = uint32_t(i & 15);
+        if (f.type == TF_MAT4 || a4 < 4u) L.v[i >> 4][a4] = factor_value_any(f, a4, fixed, slots);
+        if (a4 == 0) {
+            L.s[i >> 4][0] = f.src0;
+            L.s[i >> 4][1] = f.bit0;
+            L.s[i >> 4][2] = f.src1;
+            L.s[i >> 4][3] = f.bit1;
+            L.s[i >> 4][4] = f.src2;
+            L.s[i >> 4][5] = f.bit2;
+            L.s[i >> 4][6] = f.src3;
+            L.s[i >> 4][7] = f.bit3;
+            L.four[i >> 4] = f.type == TF_MAT4 ? 1 : 0;
         }
     }
     __syncthreads();
@@ -80,10 +102,14 @@ __device__ __forceinline__ double2 factor_product(const FactorLds& L, int nf, co
     double2 acc = make_double2(1.0, 0.0);
     for (int i = f0; i < f1; ++i) {
         if (i < nf) {
-            acc = cmuld(acc, L.v[i][val(L.s[i][0], L.s[i][1]) * 2u + val(L.s[i][2], L.s[i][3])]);
+            uint32_t a4 = val(L.s[i][0], L.s[i][1]) * 2u + val(L.s[i][2], L.s[i][3]);
+            if (L.four[i]) a4 = a4 * 4u + val(L.s[i][4], L.s[i][5]) * 2u + val(L.s[i][6], L.s[i][7]);
+            acc = cmuld(acc, L.v[i][a4]);
         } else {   // beyond the LDS copy: read the record directly
             const TFactor f = facs[i];
-            acc = cmuld(acc, factor_value(f, val(f.src0, f.bit0), val(f.src1, f.bit1), fixed, slots));
+            uint32_t a4 = val(f.src0, f.bit0) * 2u + val(f.src1, f.bit1);
+            if (f.type == TF_MAT4) a4 = a4 * 4u + val(f.src2, f.bit2) * 2u + val(f.src3, f.bit3);
+            acc = cmuld(acc, factor_value_any(f, a4, fixed, slots));
         }
     }
     return acc;

@@ -14,7 +14,7 @@ import numpy as np
 from oracle.gates import gate_matrix
 
 TS_ZERO, TS_G, TS_SIG, TS_INT = 0, 1, 2, 3
-TF_MAT, TF_DIAG, TF_CZ, TF_DELTA0 = 0, 1, 2, 3
+TF_MAT, TF_DIAG, TF_CZ, TF_DELTA0, TF_MAT4 = 0, 1, 2, 3, 4
 
 
 # matrix index -> gate kind of the library's fixed matrices (H, T, X^1/2, Y^1/2, their inverses, X, Y, Z);
@@ -26,6 +26,20 @@ def _mat(idx, gate_vals):
     if idx < len(_FIXED_KIND):
         return gate_matrix(_FIXED_KIND[idx], -1, None)
     return np.asarray(gate_vals[idx - len(_FIXED_KIND)], dtype=np.complex128).reshape(2, 2)
+
+
+def _factor4(f, a0, a1, c0, c1, gate_vals):
+    """Two-qubit gate factor: M[2 a0 + a1][2 c0 + c1], row r in value slot (mat - 10) + r."""
+    s0 = f[1] - len(_FIXED_KIND)
+    M = np.stack([np.asarray(gate_vals[s0 + r], dtype=np.complex128).reshape(4) for r in range(4)])
+    return M[2 * a0 + a1, 2 * c0 + c1]
+
+
+def _eval(f, val, gate_vals):
+    """A factor record's value; val(src, bit) gives each variable's values."""
+    if f[0] == TF_MAT4:
+        return _factor4(f, val(f[2], f[3]), val(f[4], f[5]), val(f[6], f[7]), val(f[8], f[9]), gate_vals)
+    return _factor(f, val(f[2], f[3]), val(f[4], f[5]), gate_vals)
 
 
 def _factor(f, a, b, gate_vals):
@@ -62,7 +76,7 @@ def bucket_table(st, gate_vals):
         for iv in range(1 << grp["k"]):
             term = np.ones_like(acc)
             for f in grp["factors"]:
-                term = term * _factor(f, val(f[2], f[3], iv), val(f[4], f[5], iv), gate_vals)
+                term = term * _eval(f, lambda src, bit: val(src, bit, iv), gate_vals)
             total += term
         acc = acc * total
     return acc
@@ -134,9 +148,7 @@ def run_tree_plan(info, gate_vals, bits):
             owner[rows] = tid
     amp = np.ones(B, dtype=np.complex128)
     for f in info["phase"]:
-        a = xb(f[3]) if f[2] == TS_SIG else np.zeros(B, dtype=np.int64)
-        b = xb(f[5]) if f[4] == TS_SIG else np.zeros(B, dtype=np.int64)
-        amp = amp * _factor(f, a, b, gate_vals)
+        amp = amp * _eval(f, lambda src, bit: xb(bit) if src == TS_SIG else np.zeros(B, dtype=np.int64), gate_vals)
     for tid in info["finals"]:
         amp = amp * read(tid)[0]
     n_open = info.get("n_open", 0)

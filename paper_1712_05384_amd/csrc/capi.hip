@@ -36,9 +36,12 @@ struct qgm_plan_s {
     int max_ops = 1;
     // tree plans (ordering 1): offsets of the bucket records, factor tables, phase and final rows
     size_t off_ttasks = 0, off_tgtab = 0, off_tgroup = 0, off_tfac = 0, off_ttail = 0, off_tphase = 0, off_tfinal = 0;
+    size_t off_tttasks = 0, off_ttfin = 0;   // the tail's task copies (results made in the tail in LDS), its finals
     int n_gtabs = 0;
     size_t off_tpro = 0, off_tg = 0;   // prologue block list; factor tables of a plan without gate values
-    int n_pro_blocks = 0;
+    int n_pro_blocks = 0;     // prologue blocks of the factor tables (the adjoint's table blocks too)
+    int n_pro_phase = 0;      // then the blocks of the phase values (prologue only)
+    size_t off_tphq = 0;      // bits read by each phase factor, as the tail stages them
     // tree plans, adjoint: keep-all tasks and final rows, per-bucket records, per-level item lists, slot lists
     size_t off_ttasks_all = 0, off_tfinal_all = 0, off_tbwd = 0, off_tbwdin = 0, off_tbwdg = 0, off_titems = 0;
     size_t off_tslot_off = 0, off_tslot_occ = 0;
@@ -115,6 +118,7 @@ void layout_tree_tables(qgm_plan_t* P) {
         n_groups += st.groups.size();
         P->n_pro_blocks += int((st.g_entries() + 255) / 256);
     }
+    P->n_pro_phase = int((4 * t.phase.size() + 255) / 256);
     const size_t n_tail = t.levels.size() - size_t(t.tail_start);
     P->off_fixed = 0;
     P->off_ttasks = al(sizeof(double2) * qgm::kFixedMats * 4);
@@ -124,8 +128,12 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_ttail = P->off_tfac + al(sizeof(qgm::TFactor) * (n_fac + 1));
     P->off_tphase = P->off_ttail + al(sizeof(qgm::TreeTailLevel) * (n_tail + 1));
     P->off_tfinal = P->off_tphase + al(sizeof(qgm::TFactor) * (t.phase.size() + 1));
-    P->off_tpro = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
-    P->off_tg = P->off_tpro + al(sizeof(qgm::TreeProBlock) * size_t(P->n_pro_blocks + 1));
+    const int64_t n_tail_tasks = t.n_tasks - (n_tail > 0 ? t.level_task_off[size_t(t.tail_start)] : t.n_tasks);
+    P->off_tttasks = P->off_tfinal + al(sizeof(int64_t) * (t.finals.size() + 1));
+    P->off_ttfin = P->off_tttasks + al(sizeof(qgm::TreeTask) * size_t(n_tail_tasks + 1));
+    P->off_tpro = P->off_ttfin + al(sizeof(int32_t) * (t.finals.size() + 1));
+    P->off_tphq = P->off_tpro + al(sizeof(qgm::TreeProBlock) * size_t(P->n_pro_blocks + P->n_pro_phase + 1));
+    P->off_tg = P->off_tphq + al(sizeof(int32_t) * 2 * (t.phase.size() + 1));
     // adjoint records and item lists (level by level: expansion, staged sums, table adjoints)
     P->items.clear();
     P->red_recs.clear();
@@ -431,15 +439,56 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
         }
     }
     for (char w : task_written) tasks_ok = tasks_ok && w;
-    if (!tasks_ok) return false;
+    if (!tasks_ok || n_pro != P->n_pro_blocks) return false;
+    for (int sub = 0; sub < P->n_pro_phase; ++sub) pro[n_pro++] = {-1, sub};   // the phase values
+    auto* phq = reinterpret_cast<int32_t*>(h + P->off_tphq);
+    for (size_t i = 0; i < t.phase.size(); ++i) {
+        const qgm::TFactor& f = t.phase[i];
+        phq[2 * i] = f.type == qgm::TF_MAT4 ? -2 : (f.src0 == qgm::TS_SIG ? f.bit0 : -1);
+        phq[2 * i + 1] = f.src1 == qgm::TS_SIG ? f.bit1 : -1;
+    }
     fill_tree_adjoint_tables(P, h);
+    // the tail: its levels, copies of its tasks with the results made in the tail at their LDS rows, and
+    // the rank-0 results it multiplies (arena row, or -1 - LDS row)
     auto* tl = reinterpret_cast<qgm::TreeTailLevel*>(h + P->off_ttail);
+    auto* tt = reinterpret_cast<qgm::TreeTask*>(h + P->off_tttasks);
+    const int64_t tail0 = t.tail_start < int(t.levels.size()) ? t.level_task_off[size_t(t.tail_start)] : t.n_tasks;
+    // what the tail kernel stages in LDS must fit its arrays
+    if (t.n_tasks - tail0 > qgm::kTreeTailMaxTasks || int(t.levels.size()) - t.tail_start > qgm::kTreeTailMaxLevels ||
+        t.tail_lds_rows > qgm::kTreeTailLdsRows || t.tail_g_entries > qgm::kTreeTailGEntries ||
+        (t.tail_g0 & 1) != 0 || (t.phase_g & 1) != 0 ||
+        (t.tail_start < int(t.levels.size()) && int(t.finals.size()) > qgm::kTreeTailMaxFinal))
+        return false;
     for (size_t L = size_t(t.tail_start); L < t.levels.size(); ++L) {
         qgm::TreeTailLevel x{};
-        x.task_off = int32_t(t.level_task_off[L]);
+        x.task_off = int32_t(t.level_task_off[L] - tail0);
         x.n_tasks = int32_t(t.level_task_off[L + 1] - t.level_task_off[L]);
         x.nin = qgm::launch_inputs(t.level_max_in[L]);
         tl[L - size_t(t.tail_start)] = x;
+        for (int sid : t.levels[L]) {
+            const qgm::TreeStep& st = t.steps[size_t(sid)];
+            const int32_t lo = t.tail_lds_row[size_t(st.out_tensor)];
+            if (lo < 0) return false;   // every result made in the tail has LDS rows
+            if (st.g_off < t.tail_g0 || st.g_off + st.g_entries() > t.tail_g0 + t.tail_g_entries) return false;
+            for (int64_t c = 0; c < st.n_tasks(); ++c) {
+                qgm::TreeTask tk = tasks[st.task_off + c];
+                tk.out_row = int32_t(lo + (tk.out_row - t.tensor_row[size_t(st.out_tensor)]));
+                tk.g_ent = int32_t(tk.g_ent - t.tail_g0);
+                tk.out_lds = 1;
+                for (size_t k = 0; k < st.in_tensors.size(); ++k) {
+                    const int tid = st.in_tensors[k];
+                    if (tk.in_tab[k] >= 0 || t.tail_lds_row[size_t(tid)] < 0) continue;
+                    tk.in_row[k] = int32_t(t.tail_lds_row[size_t(tid)] + (tk.in_row[k] - t.tensor_row[size_t(tid)]));
+                    tk.in_tab[k] = -2;
+                }
+                tt[st.task_off + c - tail0] = tk;
+            }
+        }
+    }
+    auto* tf = reinterpret_cast<int32_t*>(h + P->off_ttfin);
+    for (size_t i = 0; i < t.finals.size(); ++i) {
+        const int32_t lo = t.tail_lds_row[size_t(t.finals[i])];
+        tf[i] = lo >= 0 ? -1 - lo : int32_t(t.tensor_row[size_t(t.finals[i])]);
     }
     auto* ph = reinterpret_cast<qgm::TFactor*>(h + P->off_tphase);
     for (size_t i = 0; i < t.phase.size(); ++i) ph[i] = t.phase[i];
@@ -539,7 +588,7 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     char* h = &host[0];
     fixed_matrices(reinterpret_cast<double2*>(h + P->off_fixed));
     if (P->p.is_tree) {
-        if (!fill_tree_tables(P, h)) return fail(QGM_E_INTERNAL, "bucket task records overlap or leave gaps");
+        if (!fill_tree_tables(P, h)) return fail(QGM_E_INTERNAL, "bucket task records overlap, leave gaps or exceed the tail kernel's LDS arrays");
     } else {
         fill_step_tables(P, h);
     }
@@ -551,12 +600,15 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     if (P->p.is_tree && P->p.n_slots == 0) {
         // the factor tables of a circuit without gate values depend only on the plan: build them once
         char* b = static_cast<char*>(d);
-        qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeProBlock*>(b + P->off_tpro), P->n_pro_blocks,
+        qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeProBlock*>(b + P->off_tpro),
+                                  P->n_pro_blocks + P->n_pro_phase,
                                   reinterpret_cast<const qgm::TreeGTab*>(b + P->off_tgtab),
                                   reinterpret_cast<const qgm::TreeGroup*>(b + P->off_tgroup),
                                   reinterpret_cast<const qgm::TFactor*>(b + P->off_tfac),
                                   reinterpret_cast<const double2*>(b + P->off_fixed), nullptr,
-                                  reinterpret_cast<float2*>(b + P->off_tg), P->p.tree.ones_g, nullptr);
+                                  reinterpret_cast<float2*>(b + P->off_tg), P->p.tree.ones_g,
+                                  reinterpret_cast<const qgm::TFactor*>(b + P->off_tphase),
+                                  int(P->p.tree.phase.size()), P->p.tree.phase_g, nullptr);
         int64_t max_entries = 0;
         for (const qgm::TreeStep& st : P->p.tree.steps)
             if (st.table_leaf) max_entries = std::max<int64_t>(max_entries, int64_t(1) << (st.out_axes.size() + st.sb()));
@@ -805,10 +857,10 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
         mark(1);
         if (p.n_slots > 0)   // factor tables from this call's gate values
             qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeProBlock*>(tables + plan->off_tpro),
-                                      plan->n_pro_blocks,
+                                      plan->n_pro_blocks + plan->n_pro_phase,
                                       reinterpret_cast<const qgm::TreeGTab*>(tables + plan->off_tgtab),
                                       reinterpret_cast<const qgm::TreeGroup*>(tables + plan->off_tgroup), facs, fixed,
-                                      slots, gt, t.ones_g, s);
+                                      slots, gt, t.ones_g, phase, int(t.phase.size()), t.phase_g, s);
         mark(2);
         if (qgm::tree_persistent(p, B)) {
             // all levels and the amplitude product in one launch, every result at its own rows
@@ -856,10 +908,32 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
         }
         const int n_tail = int(t.levels.size()) - t.tail_start;
         if (n_tail > 0) {
-            if (out)
-                qgm::launch_tree_tail(reinterpret_cast<const qgm::TreeTailLevel*>(tables + plan->off_ttail), n_tail,
-                                      tasks, arena, gt, t.ones_g, finals, int(t.finals.size()), phase, int(t.phase.size()),
-                                      fixed, slots, bits, B, uint32_t(B_eff), out, p.opts.out_c128 != 0, s);
+            if (out) {
+                qgm::TreeTailArgs ta{};
+                ta.levels = reinterpret_cast<const qgm::TreeTailLevel*>(tables + plan->off_ttail);
+                ta.tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_tttasks);
+                ta.final_lds = reinterpret_cast<const int32_t*>(tables + plan->off_ttfin);
+                ta.phase = phase;
+                ta.phase_q = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
+                ta.fixed = fixed;
+                ta.slots = slots;
+                ta.arena = arena;
+                ta.gtab = gt;
+                ta.bits = bits;
+                ta.out = out;
+                ta.ones_g = t.ones_g;
+                ta.tail_g0 = t.tail_g0;
+                ta.phase_g = t.phase_g;
+                ta.B = B;
+                ta.n_levels = n_tail;
+                ta.n_tasks = int32_t(t.n_tasks - t.level_task_off[size_t(t.tail_start)]);
+                ta.n_final = int32_t(t.finals.size());
+                ta.n_phase = int32_t(t.phase.size());
+                ta.tail_g_entries = int32_t(t.tail_g_entries);
+                ta.c128 = p.opts.out_c128 != 0 ? 1 : 0;
+                ta.B_eff = uint32_t(B_eff);
+                qgm::launch_tree_tail(ta, s);
+            }
             mark(3);
         } else {
             mark(3);
@@ -939,7 +1013,9 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     const auto* tasks_all = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks_all);
     const auto* items = reinterpret_cast<const qgm::TreeBwdItem*>(tables + plan->off_titems);
     const uint32_t be = uint32_t(B_eff);
-    if (p.n_slots > 0) qgm::launch_tree_prologue(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gt, t.ones_g, s);
+    if (p.n_slots > 0)   // the factor tables only (the adjoint evaluates the phase factors itself)
+        qgm::launch_tree_prologue(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gt, t.ones_g, nullptr, 0,
+                                  0, s);
     for (int Lv = t.first_level; Lv < int(t.levels.size()); ++Lv) {
         const int64_t t0 = t.level_task_off[Lv], t1 = t.level_task_off[Lv + 1];
         qgm::launch_tree_level(t.level_max_in[Lv], tasks_all + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,

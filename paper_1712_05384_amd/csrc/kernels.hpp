@@ -63,14 +63,19 @@ struct TreeTask {
     int32_t dep_n[kTreeMaxIn];
     int32_t in_omask[kTreeMaxIn];               // bit j: input t's row changes along the unit's result row bit j
     int32_t g_omask;                            // the same for the factor-table entry
-    int32_t pad3;
+    int32_t out_lds;                            // 1: the result rows and the factor table are in the tail
+                                                //   kernel's LDS (out_row and g_ent count there); only in the
+                                                //   tail's copies of its tasks
     // an input that is a leaf table (a bucket without inputs, built with the plan): its entry offset in the
-    // factor-table area (-1: an arena result), its output bits and their qubits (6 bits each); row r, bits s
-    // of the lane's bitstring -> entry offset + (r << sb) + s
+    // factor-table area (-1: an arena result; -2, in the tail's copies: a result in the tail kernel's LDS,
+    // in_row counting rows there), its output bits and their qubits (6 bits each); row r, bits s of the
+    // lane's bitstring -> entry offset + (r << sb) + s
     int32_t in_tab[kTreeMaxIn];
     int32_t in_tsb[kTreeMaxIn];
     uint64_t in_tsig[kTreeMaxIn];
+    int32_t pad4[2];                            // a whole number of 16-byte words (the tail copies records)
 };
+static_assert(sizeof(TreeTask) % 16 == 0, "task records are copied in 16-byte words");
 
 // The leaf tables of a plan (built once): R[o][s] = sum_w G[((o << k) | w) << sb | s].
 struct TreeLeaf {
@@ -123,11 +128,12 @@ struct TreeGroup {
 
 // One block of the prologue: what it computes.
 struct TreeProBlock {
-    int32_t idx;       // factor table
+    int32_t idx;       // factor table (-1: the FP64 values of the factors without free variables)
     int32_t sub;       // block within the table (256 entries)
 };
 
-// A level run by the tail kernel (one work-group per 64-bitstring group).
+// A level run by the tail kernel (one work-group per 64-bitstring group); its
+// tasks are [task_off, task_off + n_tasks) of the tail's task copies.
 struct TreeTailLevel {
     int32_t task_off, n_tasks, nin, pad;
 };
@@ -209,7 +215,7 @@ void launch_finalize(const float2* f, uint32_t B_eff, uint32_t B_pad, int64_t B,
 
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                           const TFactor* facs, const double2* fixed, const float2* slots, float2* gtab,
-                          int64_t ones_g, hipStream_t stream);
+                          int64_t ones_g, const TFactor* phase, int n_phase, int64_t phase_g, hipStream_t stream);
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        hipStream_t stream);
@@ -226,10 +232,28 @@ void launch_xeb(const void* amps, bool c128, int64_t B, int n_qubits, double* ou
 void launch_sample_set(const void* amps, bool c128, int64_t B, const double* u, int64_t m, int64_t* idx, double* ws,
                        hipStream_t stream);
 void launch_persist_init(int32_t* flags, int64_t n_flags, void* out, int64_t B, bool c128, hipStream_t stream);
-void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask* tasks, float2* arena,
-                      const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,
-                      int n_phase, const double2* fixed, const float2* slots, const uint64_t* bits, int64_t B,
-                      uint32_t B_eff, void* out, bool c128, hipStream_t stream);
+// The tail: levels, copies of their task records (results made in the tail
+// and the tail's factor tables addressed in LDS), the rank-0 results (arena
+// row, or -1 - LDS row), the phase factors with their FP64 values at float2
+// entry phase_g of gtab and the bits they read (2 per factor, as staged by the
+// tail: -1 none, -2 a two-qubit factor evaluated from its record).
+struct TreeTailArgs {
+    const TreeTailLevel* levels;
+    const TreeTask* tasks;
+    const int32_t* final_lds;
+    const TFactor* phase;
+    const int32_t* phase_q;
+    const double2* fixed;
+    const float2* slots;
+    float2* arena;
+    const float2* gtab;
+    const uint64_t* bits;
+    void* out;
+    int64_t ones_g, tail_g0, phase_g, B;
+    int32_t n_levels, n_tasks, n_final, n_phase, tail_g_entries, c128;
+    uint32_t B_eff, pad;
+};
+void launch_tree_tail(const TreeTailArgs& a, hipStream_t stream);
 void launch_tb_zero(double2* p, int64_t n, hipStream_t stream);
 void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                     const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,

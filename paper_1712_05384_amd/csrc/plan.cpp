@@ -627,7 +627,7 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
       << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
-      << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start
+      << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start << ",\"tail_lds_rows\":" << t.tail_lds_rows
       << ",\"level_launches\":" << (std::max(t.tail_start - t.first_level, 0) + (t.tail_start < int(t.levels.size()) ? 1 : 0))
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows

@@ -712,19 +712,6 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         t.arena_rows = std::max(t.arena_rows, off + size);
         placed.push_back(a);
     }
-    // factor tables of every bucket
-    int64_t g = 0;
-    for (auto& st : t.steps) {
-        st.g_off = g;
-        g += st.g_entries();
-    }
-    for (auto& st : t.steps)
-        if (st.table_leaf) {
-            st.leaf_off = g;
-            g += int64_t(1) << (st.out_axes.size() + st.sig_q.size());
-        }
-    t.ones_g = g;                 // constant 1 read for inputs a bucket does not have
-    t.g_total = g + 1;
     // wave tasks of the buckets with inputs, grouped by level (a level is one launch)
     t.level_task_off.assign(1, 0);
     t.level_max_in.clear();
@@ -744,13 +731,66 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     // tail: the longest run of last levels with few tasks and few inputs
     t.first_level = 0;
     while (t.first_level < int(t.levels.size()) && t.levels[t.first_level].empty()) ++t.first_level;
+    // (its task records and the results it makes are kept in LDS: at most kTreeTailMaxTasks records and
+    // kTreeTailLdsRows rows over all its levels)
     t.tail_start = int(t.levels.size());
-    while (t.n_open == 0 && t.tail_start > std::max(t.first_level, 1)) {   // the tail writes one amplitude per b
+    int64_t tail_tasks = 0, tail_rows = 0, tail_g = 0;
+    while (t.n_open == 0 && t.tail_start > std::max(t.first_level, 1) &&   // the tail writes one amplitude per b
+           int(t.finals.size()) <= kTreeTailMaxFinal && int(t.levels.size()) - t.tail_start < kTreeTailMaxLevels) {
         const int L = t.tail_start - 1;
         const int64_t nt = t.level_task_off[L + 1] - t.level_task_off[L];
         if (nt > kTreeTailTasks || launch_inputs(t.level_max_in[L]) > kTreeTailInputs) break;
+        int64_t rows = 0, ge = 0;
+        for (int sid : t.levels[L]) {
+            rows += alloc_rows(t.steps[sid].out_tensor);
+            ge += t.steps[sid].g_entries();
+        }
+        if (tail_tasks + nt > kTreeTailMaxTasks || tail_rows + rows > kTreeTailLdsRows ||
+            tail_g + ge > kTreeTailGEntries)
+            break;
+        tail_tasks += nt;
+        tail_rows += rows;
+        tail_g += ge;
         t.tail_start = L;
     }
+    t.tail_lds_row.assign(T, -1);
+    t.tail_lds_rows = 0;
+    for (int L = t.tail_start; L < int(t.levels.size()); ++L)
+        for (int sid : t.levels[L]) {
+            t.tail_lds_row[t.steps[sid].out_tensor] = t.tail_lds_rows;
+            t.tail_lds_rows += int(alloc_rows(t.steps[sid].out_tensor));
+        }
+    // factor tables: the buckets before the tail, then the tail's buckets in one range (which the tail
+    // kernel copies to LDS), the leaf tables, the constant 1, and the FP64 values of the factors without
+    // free variables (4 per factor, two float2 entries each)
+    std::vector<char> in_tail(t.steps.size(), 0);
+    for (int L = t.tail_start; L < int(t.levels.size()); ++L)
+        for (int sid : t.levels[L]) in_tail[size_t(sid)] = 1;
+    int64_t g = 0;
+    for (size_t i = 0; i < t.steps.size(); ++i)
+        if (!in_tail[i]) {
+            t.steps[i].g_off = g;
+            g += t.steps[i].g_entries();
+        }
+    g += g & 1;                   // 16-byte alignment of the tail's range
+    t.tail_g0 = g;
+    for (size_t i = 0; i < t.steps.size(); ++i)
+        if (in_tail[i]) {
+            t.steps[i].g_off = g;
+            g += t.steps[i].g_entries();
+        }
+    t.tail_g_entries = g - t.tail_g0;
+    for (auto& st : t.steps)
+        if (st.table_leaf) {
+            st.leaf_off = g;
+            g += int64_t(1) << (st.out_axes.size() + st.sig_q.size());
+        }
+    t.ones_g = g;                 // constant 1 read for inputs a bucket does not have
+    g += 1;
+    g += g & 1;                   // 16-byte alignment of the FP64 values
+    t.phase_g = g;
+    g += 8 * std::max<int64_t>(1, int64_t(t.phase.size()));   // at least one factor's room (read, unused)
+    t.g_total = g;
     // adjoint layout: each result at its own rows; per level, the expansion scratch of its buckets
     t.tensor_row_all.assign(T, 0);
     t.arena_rows_all = 0;

@@ -29,10 +29,20 @@ __global__ void __launch_bounds__(256) k_tree_prologue(const TreeProBlock* __res
                                                        const TFactor* __restrict__ facs,
                                                        const double2* __restrict__ fixed,
                                                        const float2* __restrict__ slots, float2* __restrict__ gtab,
-                                                       int64_t ones_g) {
+                                                       int64_t ones_g, const TFactor* __restrict__ phase, int n_phase,
+                                                       int64_t phase_g) {
     __shared__ FactorLds L;
     if (blockIdx.x == 0 && threadIdx.x == 0) gtab[ones_g] = make_float2(1.f, 0.f);
     const TreeProBlock blk = blocks[blockIdx.x];
+    if (blk.idx < 0) {   // phase factor i, entry 2a + c: its FP64 value (two-qubit factors: from the record)
+        const int i = blk.sub * 256 + int(threadIdx.x);
+        if (i >= 4 * n_phase) return;
+        const TFactor f = phase[i >> 2];
+        const double2 v = f.type == TF_MAT4 ? make_double2(0.0, 0.0)
+                                            : factor_value(f, uint32_t(i >> 1) & 1u, uint32_t(i) & 1u, fixed, slots);
+        reinterpret_cast<double2*>(gtab + phase_g)[i] = v;
+        return;
+    }
     const TreeGTab t = gtabs[blk.idx];
     const TreeGroup* __restrict__ gr = groups + t.group_off;
     const TFactor* __restrict__ tf = facs + gr[0].fac_off;   // the groups' factors are contiguous
@@ -65,11 +75,20 @@ __global__ void __launch_bounds__(256) k_tree_prologue(const TreeProBlock* __res
 // per wave), and the task of a result with fewer rows than a unit wraps onto
 // valid rows and stores into rows the arena reserves for it.  Inputs (ain) and results (aout) are views
 // of one arena whose rows a level never both reads and writes, so all loads
-// of a unit can be in flight at once.
-template <int NIN, int K>
+// of a unit can be in flight at once.  In the tail kernel (TL) an input or the
+// result may instead be rows kept in LDS for the work-group's 64 bitstrings
+// (row r of lane l at rows[r * 64 + l]), and the bucket's factor table and the
+// constant 1 are LDS copies.
+struct TailView {
+    float2* rows;
+    const float2* g;      // the tail's factor tables (g_ent of a tail task counts from here)
+    const float2* one;
+};
+
+template <int NIN, int K, bool TL>
 __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
-                                          int64_t sig, uint64_t x, uint32_t b, int64_t be) {
+                                          int64_t sig, uint64_t x, uint32_t b, int64_t be, const TailView& tv) {
     constexpr int W = 1 << K;
     constexpr int WC = W < 8 ? W : 8;          // summed-variable values per load batch
     static_assert(WC == W, "one load batch holds every summed value (the repeat copies index within it)");
@@ -84,8 +103,11 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
         if (tk.in_row[t] < 0) {
-            base[t] = gtab + ones_g;
+            base[t] = TL ? tv.one : gtab + ones_g;
             pitch[t] = 0;
+        } else if (TL && tk.in_tab[t] == -2) {
+            base[t] = tv.rows + (b & 63u);
+            pitch[t] = 64;
         } else if (tk.in_tab[t] >= 0) {
             const int tsb = tk.in_tsb[t];
             const uint64_t pk = uint64_t(tk.in_tsig[t]);
@@ -160,7 +182,7 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
             const bool rep_i = i > 0 && !((g_om >> __builtin_ctz(uint32_t(i))) & 1u);
             if (!rep_i) {
 #pragma unroll
-                for (int w = 0; w < WC; ++w) q[i][w] = gtab[gent[i] + (int64_t(w0 + w) << tk.sb) + sig];
+                for (int w = 0; w < WC; ++w) q[i][w] = (TL ? tv.g : gtab)[gent[i] + (int64_t(w0 + w) << tk.sb) + sig];
             }
         }
         // the repeats, in ascending order (each copies an entry already final).  The
@@ -205,22 +227,28 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
                 acc[i].y += pw.y;
             }
     }
+    if (TL) {
+        float2* out = tv.rows + int64_t(tk.out_row) * 64 + (b & 63u);
+#pragma unroll
+        for (int i = 0; i < OB; ++i) out[i * 64] = acc[i];
+        return;
+    }
     float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b;
 #pragma unroll
     for (int i = 0; i < OB; ++i) out[int64_t(i) * be] = acc[i];
 }
 
 // A unit of task tk for bitstring group bg (x = the lane's bitstring).
-template <int NIN>
+template <int NIN, bool TL = false>
 __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
-                                          uint32_t b, int64_t be) {
+                                          uint32_t b, int64_t be, const TailView& tv = TailView{}) {
     static_assert(kTreeMaxSum == 3, "tasks sum 0 (the product over the open qubits), 1, 2 or 3 variables");
     const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
-    if (tk.k == 0) tree_unit<NIN, 0>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
-    else if (tk.k == 1) tree_unit<NIN, 1>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
-    else if (tk.k == 2) tree_unit<NIN, 2>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
-    else tree_unit<NIN, 3>(tk, ain, aout, gtab, ones_g, sig, x, b, be);
+    if (tk.k == 0) tree_unit<NIN, 0, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+    else if (tk.k == 1) tree_unit<NIN, 1, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+    else if (tk.k == 2) tree_unit<NIN, 2, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+    else tree_unit<NIN, 3, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
 }
 
 // One level of the elimination tree: wave unit u handles task u / n_bg for
@@ -337,39 +365,143 @@ __device__ __forceinline__ void write_amplitude(const PhaseLds& P, int n_lds, co
 // work-group g owns the 64 bitstrings of group g and runs every task of
 // every tail level for them, its four waves taking the tasks of a level in
 // turn, with a block barrier between levels (a level reads only results of
-// earlier levels, written by waves of the same work-group).  Then the
-// amplitudes: phase x rank-0 results in FP64.
-__global__ void __launch_bounds__(256) k_tree_tail(const TreeTailLevel* __restrict__ levels, int n_levels,
-                                                   const TreeTask* __restrict__ tasks, float2* __restrict__ arena,
-                                                   const float2* __restrict__ gtab, int64_t ones_g,
-                                                   const int64_t* __restrict__ final_rows, int n_final,
-                                                   const TFactor* __restrict__ phase, int n_phase,
-                                                   const double2* __restrict__ fixed, const float2* __restrict__ slots,
-                                                   const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
-                                                   void* __restrict__ out, int c128) {
-    __shared__ PhaseLds P;
-    const int n_lds = stage_phase(P, phase, n_phase, fixed, slots);
-    __syncthreads();
+// earlier levels).  One burst of loads at the start copies to LDS what the
+// tail reads more than once or late: the task and level records, the tail's
+// factor tables, the FP64 values of the phase factors and the list of rank-0
+// results.  The results made here stay in LDS, so after the first level
+// (whose inputs are arena rows) a level waits only on LDS.  The phase product
+// is split over waves 1-3 (factor i to wave 1 + i mod 3), each taking its
+// share in the first level where it has no task; wave 0 then multiplies the
+// three partial products and the rank-0 results in FP64.
+constexpr int kTreeTailPhase = 64;   // phase factors whose values the tail stages in LDS
+
+struct TailLds {
+    TreeTask task[kTreeTailMaxTasks];
+    TreeTailLevel lv[kTreeTailMaxLevels];
+    int32_t fin[kTreeTailMaxFinal];
+    float2 g[kTreeTailGEntries];
+    float2 one;
+    uint4 junk;                              // written by threads of the staging that have no element
+    double2 part[3][64];
+    double2 pv[kTreeTailPhase][4];           // FP64 values of the first kTreeTailPhase phase factors
+    int32_t pq[kTreeTailPhase][2];           // the bits of x they read (-1 none, -2 from the record)
+    float2 rows[kTreeTailLdsRows * 64];
+};
+
+// A task record kept in LDS, read into scalar registers (the address is uniform).
+__device__ __forceinline__ TreeTask task_from_lds(const TreeTask* p) {
+    TreeTask tk;
+    const int32_t* src = reinterpret_cast<const int32_t*>(p);
+    int32_t* dst = reinterpret_cast<int32_t*>(&tk);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(TreeTask) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return tk;
+}
+
+constexpr int kTailTaskWords = (kTreeTailMaxTasks * int(sizeof(TreeTask)) / 16 + 255) / 256;
+constexpr int kTailGWords = (kTreeTailGEntries / 2 + 255) / 256;          // 16-byte words of the tables
+constexpr int kTailPhaseWords = (kTreeTailPhase * 4 + 255) / 256;          // double2 phase values
+
+__global__ void __launch_bounds__(256) k_tree_tail(const TreeTailArgs a) {
+    __shared__ TailLds T;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t be = int64_t(B_eff);
+    const int64_t be = int64_t(a.B_eff);
     const uint32_t b = blockIdx.x * 64u + lane;
-    const uint64_t x = int64_t(b) < B ? bits[b] : 0ull;
-    for (int l = 0; l < n_levels; ++l) {
-        const TreeTailLevel lv = levels[l];
-        for (int t = int(wave); t < lv.n_tasks; t += 4) {
-            const TreeTask tk = tasks[lv.task_off + t];
-            // arena is read and written through the same pointer here: a task
-            // reads only rows of earlier levels, which no task of this level writes
-            if (lv.nin <= 1) tree_task<1>(tk, x, arena, arena, gtab, ones_g, b, be);
-            else if (lv.nin == 2) tree_task<2>(tk, x, arena, arena, gtab, ones_g, b, be);
-            else if (lv.nin == 3) tree_task<3>(tk, x, arena, arena, gtab, ones_g, b, be);
-            else tree_task<4>(tk, x, arena, arena, gtab, ones_g, b, be);
+    const int n_lds = a.n_phase < kTreeTailPhase ? a.n_phase : kTreeTailPhase;
+    const uint64_t x = int64_t(b) < a.B ? a.bits[b] : 0ull;
+    {   // every load of the staging in flight at once, then the LDS writes, all unconditional so that the
+        // code is one straight run: indices are clamped into each array (every array holds at least one
+        // element) and a thread without an element writes to a junk word
+        const int tid = int(threadIdx.x);
+        const int n_tw = a.n_tasks * int(sizeof(TreeTask) / 16);
+        const int n_gw = (a.tail_g_entries + 1) / 2;
+        const int n_pw = 4 * n_lds;
+        const uint4* __restrict__ tsrc = reinterpret_cast<const uint4*>(a.tasks);
+        const float4* __restrict__ gsrc = reinterpret_cast<const float4*>(a.gtab + a.tail_g0);   // tail_g0 is even
+        const double2* __restrict__ psrc = reinterpret_cast<const double2*>(a.gtab + a.phase_g);
+        auto clamp = [](int i, int n) { return i < n ? i : (n > 0 ? n - 1 : 0); };
+        uint4 tv[kTailTaskWords];
+        float4 gv[kTailGWords];
+        double2 pv[kTailPhaseWords];
+#pragma unroll
+        for (int k = 0; k < kTailTaskWords; ++k) tv[k] = tsrc[clamp(tid + 256 * k, n_tw)];
+#pragma unroll
+        for (int k = 0; k < kTailGWords; ++k) gv[k] = gsrc[clamp(tid + 256 * k, n_gw)];
+#pragma unroll
+        for (int k = 0; k < kTailPhaseWords; ++k) pv[k] = psrc[clamp(tid + 256 * k, n_pw)];
+        const TreeTailLevel lv = a.levels[clamp(tid, a.n_levels)];
+        const int32_t fin = a.final_lds[clamp(tid, a.n_final)];
+        const int32_t q0 = a.phase_q[2 * clamp(tid, n_lds)];
+        const int32_t q1 = a.phase_q[2 * clamp(tid, n_lds) + 1];
+        uint4* junk = &T.junk;
+#pragma unroll
+        for (int k = 0; k < kTailTaskWords; ++k) {
+            const int i = tid + 256 * k;
+            *(i < n_tw ? reinterpret_cast<uint4*>(T.task) + i : junk) = tv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kTailGWords; ++k) {
+            const int i = tid + 256 * k;
+            *(i < n_gw ? reinterpret_cast<float4*>(T.g) + i : reinterpret_cast<float4*>(junk)) = gv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kTailPhaseWords; ++k) {
+            const int i = tid + 256 * k;
+            *(i < n_pw ? &T.pv[i >> 2][i & 3] : reinterpret_cast<double2*>(junk)) = pv[k];
+        }
+        *(tid < a.n_levels ? &T.lv[tid] : reinterpret_cast<TreeTailLevel*>(junk)) = lv;
+        *(tid < a.n_final ? &T.fin[tid] : reinterpret_cast<int32_t*>(junk)) = fin;
+        *(tid < n_lds ? &T.pq[tid][0] : reinterpret_cast<int32_t*>(junk)) = q0;
+        *(tid < n_lds ? &T.pq[tid][1] : reinterpret_cast<int32_t*>(junk) + 1) = q1;
+        if (tid == 0) T.one = make_float2(1.f, 0.f);
+    }
+    __syncthreads();
+    const TailView view{T.rows, T.g, &T.one};
+    // this wave's share of the phase product (waves 1-3), into LDS
+    auto phase_part = [&]() {
+        double2 acc = make_double2(1.0, 0.0);
+        for (int i = int(wave) - 1; i < a.n_phase; i += 3) {
+            if (i >= n_lds || T.pq[i][0] == -2) {
+                acc = cmuld(acc, phase_factor(a.phase[i], x, a.fixed, a.slots));
+                continue;
+            }
+            const uint32_t ba = T.pq[i][0] >= 0 ? uint32_t((x >> T.pq[i][0]) & 1ull) : 0u;
+            const uint32_t bc = T.pq[i][1] >= 0 ? uint32_t((x >> T.pq[i][1]) & 1ull) : 0u;
+            acc = cmuld(acc, T.pv[i][ba * 2 + bc]);
+        }
+        T.part[wave - 1][lane] = acc;
+    };
+    bool part_done = wave == 0;
+    for (int l = 0; l < a.n_levels; ++l) {
+        const int task_off = __builtin_amdgcn_readfirstlane(T.lv[l].task_off);
+        const int n_tasks = __builtin_amdgcn_readfirstlane(T.lv[l].n_tasks);
+        const int nin = __builtin_amdgcn_readfirstlane(T.lv[l].nin);
+        for (int t = int(wave); t < n_tasks; t += 4) {
+            const TreeTask tk = task_from_lds(&T.task[task_off + t]);
+            if (nin <= 1) tree_task<1, true>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be, view);
+            else if (nin == 2) tree_task<2, true>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be, view);
+            else if (nin == 3) tree_task<3, true>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be, view);
+            else tree_task<4, true>(tk, x, a.arena, a.arena, a.gtab, a.ones_g, b, be, view);
+        }
+        if (!part_done && int(wave) >= n_tasks) {
+            phase_part();
+            part_done = true;
         }
         __syncthreads();
     }
-    if (wave == 0 && int64_t(b) < B)
-        write_amplitude(P, n_lds, phase, n_phase, fixed, slots, final_rows, n_final, arena, x, b, B_eff, out, c128);
+    if (!part_done) phase_part();
+    __syncthreads();
+    if (wave == 0 && int64_t(b) < a.B) {
+        double2 acc = cmuld(cmuld(T.part[0][lane], T.part[1][lane]), T.part[2][lane]);
+        for (int i = 0; i < a.n_final; ++i) {
+            const int32_t f = T.fin[i];
+            const float2 r = f < 0 ? T.rows[(-1 - f) * 64 + int(lane)] : a.arena[int64_t(f) * be + b];
+            acc = cmuld(acc, make_double2(r.x, r.y));
+        }
+        if (a.c128) static_cast<double2*>(a.out)[b] = acc;
+        else static_cast<float2*>(a.out)[b] = make_float2(float(acc.x), float(acc.y));
+    }
 }
 
 // The amplitudes when the tree has no tail levels.
@@ -639,10 +771,10 @@ void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_e
 
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                           const TFactor* facs, const double2* fixed, const float2* slots, float2* gtab,
-                          int64_t ones_g, hipStream_t stream) {
+                          int64_t ones_g, const TFactor* phase, int n_phase, int64_t phase_g, hipStream_t stream) {
     if (n_blocks <= 0) return;   // a plan without buckets reads no table
     hipLaunchKernelGGL(k_tree_prologue, dim3(uint32_t(n_blocks)), dim3(256), 0, stream, blocks, gtabs, groups, facs,
-                       fixed, slots, gtab, ones_g);
+                       fixed, slots, gtab, ones_g, phase, n_phase, phase_g);
 }
 
 template <int NIN>
@@ -676,12 +808,8 @@ void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const fl
     }
 }
 
-void launch_tree_tail(const TreeTailLevel* levels, int n_levels, const TreeTask* tasks, float2* arena,
-                      const float2* gtab, int64_t ones_g, const int64_t* final_rows, int n_final, const TFactor* phase,
-                      int n_phase, const double2* fixed, const float2* slots, const uint64_t* bits, int64_t B,
-                      uint32_t B_eff, void* out, bool c128, hipStream_t stream) {
-    hipLaunchKernelGGL(k_tree_tail, dim3(B_eff / 64u), dim3(256), 0, stream, levels, n_levels, tasks, arena, gtab,
-                       ones_g, final_rows, n_final, phase, n_phase, fixed, slots, bits, B, B_eff, out, c128 ? 1 : 0);
+void launch_tree_tail(const TreeTailArgs& a, hipStream_t stream) {
+    hipLaunchKernelGGL(k_tree_tail, dim3(a.B_eff / 64u), dim3(256), 0, stream, a);
 }
 
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,

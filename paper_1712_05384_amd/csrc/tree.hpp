@@ -51,6 +51,11 @@ constexpr int kTreeMaxSum = 3;      // variables summed by one (merged) bucket: 
                                     // serial load batches of a wave outweigh the saved launch
 constexpr int kTreeTailTasks = 8;   // tail levels: at most this many wave tasks per bitstring group
 constexpr int kTreeTailInputs = 4;  // ... and at most this many inputs per bucket
+constexpr int kTreeTailMaxTasks = 32;    // task records of all tail levels (staged in LDS)
+constexpr int kTreeTailLdsRows = 64;     // result rows made in the tail, kept in LDS (64 bitstrings each)
+constexpr int kTreeTailMaxLevels = 16;
+constexpr int kTreeTailMaxFinal = 64;    // rank-0 results the tail multiplies
+constexpr int kTreeTailGEntries = 2048;  // factor-table entries of the tail's buckets (copied to LDS)
 constexpr int kTreeOcBits = 3;      // a wave unit covers up to 2^kTreeOcBits consecutive result rows
 constexpr int64_t kTreeMaxTasks = int64_t(1) << 22;   // (bucket, row chunk) records of a plan
 
@@ -169,6 +174,12 @@ struct TreePlan {
     int first_level = 1;                         // first level with buckets (0 unless every level-0 bucket
                                                  //   was absorbed)
     int tail_start = 0;                          // levels [tail_start, n_levels) run in the tail kernel
+    std::vector<int32_t> tail_lds_row;           // per result made in the tail: its first row in the tail
+                                                 //   kernel's LDS (-1: an arena result)
+    int tail_lds_rows = 0;
+    int64_t tail_g0 = 0, tail_g_entries = 0;     // factor tables of the tail's buckets: one range
+    int64_t phase_g = 0;                         // FP64 values of the factors without free variables
+                                                 //   (double2 [n_phase][4] from this float2 entry)
     int64_t arena_rows = 0;
     int64_t g_total = 0;
     int max_rank = 0;

@@ -240,3 +240,65 @@ def test_tree_open_qubits_backward_rejected():
     with pytest.raises(N.QgmError) as e:
         p.backward(bd, torch.ones(64, 2, dtype=torch.complex64, device="cuda"), gv)
     assert e.value.status == N.QGM_E_UNSUPPORTED
+
+
+def _shifted(c, off):
+    return [(int(r[0]), int(r[1]), int(r[2]) + off, int(r[3]) + off if r[3] >= 0 else -1, int(r[4])) for r in c.gates]
+
+
+def _tail_table_inputs(info):
+    maker = {bk["out_tensor"]: bk for bk in info["buckets"]}
+    return sum(1 for bk in info["buckets"] if bk["level"] >= info["tail_start"]
+               for t in bk["in_tensors"] if maker.get(t, {}).get("table_leaf"))
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(3, 4, 16, 2), (4, 4, 16, 4)])
+def test_tree_tail_reads_leaf_tables(rows, cols, depth, seed):
+    """Buckets of the last levels (run from LDS in one work-group per group)
+    whose inputs include leaf tables read from the table area."""
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    p = _tree(c)
+    assert _tail_table_inputs(p.info(1)) > 0
+    bits = C.random_bitstrings(c.n, 130, seed)
+    _say("case tree tail leaf tables %s" % c.name)
+    got = _amps(p, bits)
+    assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits)).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_tail_many_phase_factors_60_qubits():
+    """More factors without free variables than the tail stages in LDS (the rest
+    are evaluated from their records): a 3x4 block on qubits 0..11 and H then T
+    on qubits 12..59, whose amplitude factor is <x|TH|0> = (1, e^{i pi/4})[x] / sqrt 2."""
+    blk = C.random_grid_circuit(3, 4, 12, 3)
+    n = 60
+    g = _shifted(blk, 0) + [(C.H, 0, q, -1, -1) for q in range(12, n)] + [(C.T, 1, q, -1, -1) for q in range(12, n)]
+    c = C.Circuit(1, n, np.array(g, dtype=np.int32))
+    p = _tree(c)
+    info = p.info(0)
+    assert info["n_phase"] > 64 and info["tail_levels"] > 0
+    bits = C.random_bitstrings(n, 200, 11)
+    _say("case tree tail 60 qubits, %d phase factors" % info["n_phase"])
+    got = _amps(p, bits)
+    psi = oracle.sv_state(12, blk.gates, None)
+    ref = psi[(bits & np.uint64(0xFFF)).astype(np.int64)].copy()
+    for q in range(12, n):
+        xq = ((bits >> np.uint64(q)) & np.uint64(1)).astype(bool)
+        ref *= np.where(xq, np.exp(1j * np.pi / 4), 1.0) / np.sqrt(2.0)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-n / 2)
+
+
+def test_tree_tail_with_final_from_the_arena():
+    """Two components: the shallow one's rank-0 result is made before the tail
+    (the tail reads it from the arena), the deep one's in the tail (LDS)."""
+    a = C.random_grid_circuit(2, 2, 6, 5)
+    b = C.random_grid_circuit(4, 4, 16, 6)
+    c = C.Circuit(1, 20, np.array(_shifted(a, 0) + _shifted(b, 4), dtype=np.int32))
+    p = _tree(c)
+    info = p.info(1)
+    made = {bk["out_tensor"]: bk["level"] for bk in info["buckets"]}
+    levels = [made[f] for f in info["finals"]]
+    assert info["tail_levels"] > 0 and min(levels) < info["tail_start"] <= max(levels)
+    bits = C.random_bitstrings(20, 100, 12)
+    _say("case tree tail final from arena")
+    got = _amps(p, bits)
+    assert np.abs(got - oracle.sv_amplitudes(20, c.gates, None, bits)).max() <= TOL * 2 ** (-20 / 2)

@@ -380,3 +380,39 @@ def test_tree_plan_leaf_tables():
     assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits[:16])).max() < 1e-12
     c4, _ = C.workload("c4_5x5_d20_U")
     assert Q.plan(c4, ordering=1).info(0)["table_leaves"] == 0
+
+
+def test_tail_fits_the_tail_kernels_lds_arrays():
+    """The last levels run in one work-group per bitstring group with their task
+    records, factor tables and results in LDS: at most 32 task records, 64
+    result rows, 2048 factor-table entries and 16 levels."""
+    import paper_1712_05384_amd as Q
+    circs = [C.random_grid_circuit(r, c, d, s) for (r, c, d, s) in
+             [(3, 4, 16, 2), (4, 4, 16, 4), (4, 5, 20, 1), (5, 5, 25, 201), (2, 6, 18, 3)]]
+    for c in circs:
+        info = Q.plan(c, ordering=1).info(1)
+        tail = [bk for bk in info["buckets"] if bk["level"] >= info["tail_start"]]
+        rows = sum(2 ** max(bk["r_out"], 3) for bk in tail)
+        tasks = sum(max(1, 2 ** bk["r_out"] // bk["unit_rows"]) for bk in tail)
+        gent = sum(2 ** (len(bk["gvars"]) + bk["kg"] + bk["sb"]) for bk in tail)
+        assert rows == info["tail_lds_rows"] <= 64
+        assert tasks <= 32 and gent <= 2048 and info["tail_levels"] <= 16
+
+
+def test_tail_plan_with_many_phase_factors_closed_form():
+    """60 qubits: a 3x4 block and H then T on the other 48 (each contributes
+    <x|TH|0> = (1, e^{i pi/4})[x] / sqrt 2); the plan, run by the interpreter."""
+    import paper_1712_05384_amd as Q
+    from tree_interp import run_tree_plan
+    blk = C.random_grid_circuit(3, 4, 12, 3)
+    n = 60
+    g = [tuple(int(v) for v in r) for r in blk.gates] + [(C.H, 0, q, -1, -1) for q in range(12, n)] + \
+        [(C.T, 1, q, -1, -1) for q in range(12, n)]
+    c = C.Circuit(1, n, np.array(g, dtype=np.int32))
+    info = Q.plan(c, ordering=1).info(1)
+    assert info["n_phase"] > 64 and info["tail_levels"] > 0
+    bits = C.random_bitstrings(n, 12, 11)
+    ref = oracle.sv_state(12, blk.gates, None)[(bits & np.uint64(0xFFF)).astype(np.int64)]
+    for q in range(12, n):
+        ref = ref * np.where(((bits >> np.uint64(q)) & np.uint64(1)).astype(bool), np.exp(1j * np.pi / 4), 1.0) / np.sqrt(2)
+    assert np.abs(run_tree_plan(info, None, bits) - ref).max() < 1e-12 * 2 ** (-n / 2)

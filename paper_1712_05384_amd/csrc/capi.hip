@@ -474,7 +474,6 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
                 qgm::TreeTask tk = tasks[st.task_off + c];
                 tk.out_row = int32_t(lo + (tk.out_row - t.tensor_row[size_t(st.out_tensor)]));
                 tk.g_ent = int32_t(tk.g_ent - t.tail_g0);
-                tk.out_lds = 1;
                 for (size_t k = 0; k < st.in_tensors.size(); ++k) {
                     const int tid = st.in_tensors[k];
                     if (tk.in_tab[k] >= 0 || t.tail_lds_row[size_t(tid)] < 0) continue;
@@ -689,7 +688,7 @@ struct TreeBwdLayout {
 
 TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
     const qgm::TreePlan& t = P->p.tree;
-    const uint64_t be = uint64_t(qgm::padded_batch(B));
+    const uint64_t be = uint64_t(qgm::tree_pitch(B));
     TreeBwdLayout L;
     L.arena = 0;
     L.adj = al(uint64_t(t.arena_rows_all) * be * 8);
@@ -813,6 +812,8 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     const int64_t B_pad = qgm::padded_batch(B);
     const int64_t B_eff = qgm::batch_eff(p, B);
     if (B_eff > (int64_t(1) << 26)) return fail(QGM_E_UNSUPPORTED, "batch times slice count exceeds 2^26");
+    if (p.is_tree && (B_eff & (B_eff - 1)) != 0)   // the bucket kernels scale arena rows by a shift
+        return fail(QGM_E_INTERNAL, "bucket arena pitch is not a power of two");
     if ((int64_t(1) << p.r_max) * (B_eff / 64) >= (int64_t(1) << 31))
         return fail(QGM_E_UNSUPPORTED, "frontier rows times batch blocks exceed 2^31");
     const qgm::WsLayout w = qgm::workspace_layout(p, B);
@@ -904,7 +905,7 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
         for (int L = t.first_level; L < t.tail_start; ++L) {
             const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
             qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
-                                   B, uint32_t(B_eff), s);
+                                   B, uint32_t(B_eff), uint32_t((B + 63) / 64), s);
         }
         const int n_tail = int(t.levels.size()) - t.tail_start;
         if (n_tail > 0) {
@@ -986,7 +987,7 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
         return fail(QGM_E_INVALID, "bits, grad_amps, workspace (and gate_vals, gate_grads when the circuit has slots) "
                                    "must be device pointers");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
-    const int64_t B_eff = qgm::padded_batch(B);
+    const int64_t B_eff = qgm::tree_pitch(B);   // the arena's row pitch (a power of two)
     if (B_eff > (int64_t(1) << 26)) return fail(QGM_E_UNSUPPORTED, "batch exceeds 2^26");
     const TreeBwdLayout L = tree_backward_layout(plan, B);
     if (ws_bytes < L.total) return fail(QGM_E_OOM, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -1019,7 +1020,7 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     for (int Lv = t.first_level; Lv < int(t.levels.size()); ++Lv) {
         const int64_t t0 = t.level_task_off[Lv], t1 = t.level_task_off[Lv + 1];
         qgm::launch_tree_level(t.level_max_in[Lv], tasks_all + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
-                               B, be, s);
+                               B, be, be / 64u, s);   // every group of the pitch: the adjoint reads them all
     }
     const int64_t n_fbar4 = plan->n_fbar * 4;
     qgm::launch_tb_zero(fbar, n_fbar4, s);

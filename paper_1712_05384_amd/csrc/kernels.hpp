@@ -63,9 +63,8 @@ struct TreeTask {
     int32_t dep_n[kTreeMaxIn];
     int32_t in_omask[kTreeMaxIn];               // bit j: input t's row changes along the unit's result row bit j
     int32_t g_omask;                            // the same for the factor-table entry
-    int32_t out_lds;                            // 1: the result rows and the factor table are in the tail
-                                                //   kernel's LDS (out_row and g_ent count there); only in the
-                                                //   tail's copies of its tasks
+    int32_t pad3;                               // (in the tail's copies of its tasks, out_row and g_ent count
+                                                //   rows and entries of the tail kernel's LDS)
     // an input that is a leaf table (a bucket without inputs, built with the plan): its entry offset in the
     // factor-table area (-1: an arena result; -2, in the tail's copies: a result in the tail kernel's LDS,
     // in_row counting rows there), its output bits and their qubits (6 bits each); row r, bits s of the
@@ -216,9 +215,11 @@ void launch_finalize(const float2* f, uint32_t B_eff, uint32_t B_pad, int64_t B,
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                           const TFactor* facs, const double2* fixed, const float2* slots, float2* gtab,
                           int64_t ones_g, const TFactor* phase, int n_phase, int64_t phase_g, hipStream_t stream);
+// One level of a bucket plan for the first n_groups groups of 64 bitstrings;
+// B_eff is the arena's row pitch and must be a power of two.
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
-                       hipStream_t stream);
+                       uint32_t n_groups, hipStream_t stream);
 void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase,
                             const double2* fixed, const float2* slots, const float2* arena, int64_t open_row,
                             int n_open, uint32_t zero_mask, const uint64_t* bits, int64_t B, uint32_t B_eff,

@@ -51,6 +51,12 @@ struct Src { uint8_t src = SRC_ZERO; uint8_t bit = 0; };
 
 int64_t padded_batch(int64_t B) { return (B + 63) / 64 * 64; }
 
+int64_t tree_pitch(int64_t B) {
+    int64_t p = 64;
+    while (p < B) p <<= 1;
+    return p;
+}
+
 double Step::bytes_per_b() const {
     double in = input_is_one ? 0.0 : 8.0 * double(int64_t(1) << r_in);
     return in + 8.0 * double(int64_t(1) << r_out) + 2.0;
@@ -544,7 +550,7 @@ bool tree_persistent(const Plan& p, int64_t) { return p.is_tree && p.opts.tree_e
 int64_t tree_flag_stride(const Plan& p) { return (p.tree.n_tasks + 31) / 32 * 32; }
 
 int64_t tree_flag_words(const Plan& p, int64_t B) {
-    return kPersistFlags0 + padded_batch(B) / 64 * tree_flag_stride(p);
+    return kPersistFlags0 + tree_pitch(B) / 64 * tree_flag_stride(p);   // one flag row per group of the pitch
 }
 
 WsLayout workspace_layout(const Plan& p, int64_t B) {

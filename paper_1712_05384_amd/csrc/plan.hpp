@@ -97,7 +97,12 @@ std::string plan_json(const Plan& p, int detail);
 
 // Slices (bitstring copies per call) and padded batch.
 int64_t padded_batch(int64_t B);
-inline int64_t batch_eff(const Plan& p, int64_t B) { return padded_batch(B) << p.sliced.size(); }
+// Row pitch of the bucket path's arena: the padded batch rounded up to a power
+// of two, so that the kernels scale rows by a shift.
+int64_t tree_pitch(int64_t B);
+inline int64_t batch_eff(const Plan& p, int64_t B) {
+    return p.is_tree ? tree_pitch(B) : padded_batch(B) << p.sliced.size();
+}
 
 // Workspace of a call.  Ordering 0: two frontier buffers, the variant ids
 // and the G table.  Ordering 1: the arena of bucket results (f0) and, when

@@ -1,7 +1,8 @@
 // Device kernels of the bucket-elimination path (ordering 1, gfx950).
 //
 // Every bucket result is a batch-minor [2^r][B_eff] complex64 array in one
-// arena: element (o, b) lives at (row + o) * B_eff + b, so a wave that owns 64
+// arena: element (o, b) lives at (row + o) * B_eff + b, B_eff being the batch
+// padded to a power of two (rows are scaled by a shift), so a wave that owns 64
 // consecutive bitstrings reads and writes 512 contiguous bytes per tensor row
 // whatever the bucket's axes.  The index arithmetic of a bucket (which input
 // row belongs to result row o and value v of the summed variable) depends on
@@ -93,44 +94,48 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
     constexpr int WC = W < 8 ? W : 8;          // summed-variable values per load batch
     static_assert(WC == W, "one load batch holds every summed value (the repeat copies index within it)");
     constexpr int OB = tree_unit_rows(NIN, K);
-    // Where input t's row r lives for this lane: base[t] + r * pitch[t] (a result
-    // in the arena: column b, pitch B_eff; a leaf table: its entries for the
-    // lane's output bits, pitch 2^sb; an input the bucket does not have: the
-    // constant 1, pitch 0).  Rows, the factor-table entry of the unit's rows and
-    // the offset of each summed value w in each input are scalar.
+    // Where input t's row r lives for this lane: base[t] + (r << sh[t]) (a result
+    // in the arena: column b, rows B_eff apart, a power of two; a leaf table: its
+    // entries for the lane's output bits, rows 2^sb apart; an input the bucket
+    // does not have: the constant 1 at row 0, whose row steps are all 0).  Rows
+    // (32-bit), the factor-table entry of the unit's rows and the row offset of
+    // each summed value w in each input are scalar; a power-of-two row pitch
+    // makes the row scaling one shift instead of a 64-bit multiply per load.
+    const uint32_t be_sh = uint32_t(__builtin_ctzll(uint64_t(be)));
     const float2* base[NIN];
-    int64_t pitch[NIN];
+    uint32_t sh[NIN];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
         if (tk.in_row[t] < 0) {
             base[t] = TL ? tv.one : gtab + ones_g;
-            pitch[t] = 0;
+            sh[t] = 0;
         } else if (TL && tk.in_tab[t] == -2) {
             base[t] = tv.rows + (b & 63u);
-            pitch[t] = 64;
+            sh[t] = 6;
         } else if (tk.in_tab[t] >= 0) {
             const int tsb = tk.in_tsb[t];
             const uint64_t pk = uint64_t(tk.in_tsig[t]);
             uint32_t s = 0;
             for (int i = 0; i < tsb; ++i) s |= uint32_t((x >> ((pk >> (6 * i)) & 63u)) & 1ull) << i;
             base[t] = gtab + tk.in_tab[t] + s;
-            pitch[t] = int64_t(1) << tsb;
+            sh[t] = uint32_t(tsb);
         } else {
             base[t] = ain + b;
-            pitch[t] = be;
+            sh[t] = be_sh;
         }
     }
-    int64_t row[OB][NIN], gent[OB], off[NIN][W];
+    int32_t row[OB][NIN], off[NIN][W];
+    int64_t gent[OB];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
-        row[0][t] = tk.in_row[t];
+        row[0][t] = tk.in_row[t] < 0 ? 0 : tk.in_row[t];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            int64_t o = 0;
+            int32_t o = 0;
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 if ((w >> i) & 1) o += tk.in_vs[t][i];
-            off[t][w] = o * pitch[t];
+            off[t][w] = o;
         }
     }
     gent[0] = tk.g_ent;
@@ -158,6 +163,23 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
         in_wm[t] = wm;
     }
     const uint32_t g_om = uint32_t(tk.g_omask);
+    // which entries (i, t, w) are loaded: bit w of lm[i][t] (all repeats cleared),
+    // one mask per row and input, read through an empty asm so that each load
+    // tests one bit instead of the compiler re-deriving both conditions per load
+    uint32_t lm[OB][NIN];
+#pragma unroll
+    for (int t = 0; t < NIN; ++t) {
+        uint32_t wl = 1u;
+#pragma unroll
+        for (int w = 1; w < W; ++w)
+            if ((in_wm[t] >> __builtin_ctz(uint32_t(w))) & 1u) wl |= 1u << w;
+#pragma unroll
+        for (int i = 0; i < OB; ++i) {
+            const bool rep_i = i > 0 && !((in_om[t] >> __builtin_ctz(uint32_t(i))) & 1u);
+            lm[i][t] = __builtin_amdgcn_readfirstlane(rep_i ? 0u : wl);
+            asm volatile("" : "+s"(lm[i][t]));
+        }
+    }
     float2 acc[OB];
 #pragma unroll
     for (int i = 0; i < OB; ++i) acc[i] = make_float2(0.f, 0.f);
@@ -168,13 +190,11 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
         for (int i = 0; i < OB; ++i)
 #pragma unroll
             for (int t = 0; t < NIN; ++t) {
-                const float2* __restrict__ src = base[t] + row[i][t] * pitch[t];
-                const bool rep_i = i > 0 && !((in_om[t] >> __builtin_ctz(uint32_t(i))) & 1u);
 #pragma unroll
                 for (int w = 0; w < WC; ++w) {
                     const int wa = w0 + w;
-                    const bool rep_w = w > 0 && !((in_wm[t] >> __builtin_ctz(uint32_t(wa))) & 1u);
-                    if (!rep_i && !rep_w) a[i][t][w] = src[off[t][wa]];
+                    if ((lm[i][t] >> wa) & 1u)
+                        a[i][t][w] = base[t][int64_t(uint32_t(row[i][t] + off[t][wa])) << sh[t]];
                 }
             }
 #pragma unroll
@@ -222,9 +242,13 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
             for (int w = 0; w < WC; ++w) {
                 float2 pw = q[i][w];
 #pragma unroll
-                for (int t = 0; t < NIN; ++t) pw = cmulf(pw, a[i][t][w]);
-                acc[i].x += pw.x;
-                acc[i].y += pw.y;
+                for (int t = 0; t + 1 < NIN; ++t) pw = cmulf(pw, a[i][t][w]);
+                // the last factor goes straight into the sum: four fused multiply-adds
+                const float2 l = a[i][NIN - 1][w];
+                acc[i].x = fmaf(pw.x, l.x, acc[i].x);
+                acc[i].x = fmaf(-pw.y, l.y, acc[i].x);
+                acc[i].y = fmaf(pw.x, l.y, acc[i].y);
+                acc[i].y = fmaf(pw.y, l.x, acc[i].y);
             }
     }
     if (TL) {
@@ -796,9 +820,9 @@ static void launch_level_n(hipStream_t stream, const TreeTask* tasks, int64_t n_
 
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
-                       hipStream_t stream) {
-    const uint32_t n_bg = B_eff / 64u;
-    if (n_tasks <= 0) return;
+                       uint32_t n_groups, hipStream_t stream) {
+    const uint32_t n_bg = n_groups;
+    if (n_tasks <= 0 || n_bg == 0) return;
     switch (launch_inputs(nin)) {
         case 1: launch_level_n<1>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
         case 2: launch_level_n<2>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
@@ -809,7 +833,7 @@ void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const fl
 }
 
 void launch_tree_tail(const TreeTailArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL(k_tree_tail, dim3(a.B_eff / 64u), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_tree_tail, dim3(uint32_t((a.B + 63) / 64)), dim3(256), 0, stream, a);
 }
 
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,

@@ -94,13 +94,16 @@ def test_autograd_function_and_finite_difference():
 
 @pytest.mark.parametrize("rows,cols,depth,seed,kw", [
     (1, 1, 4, 11, {}), (2, 2, 6, 1, {}), (3, 3, 10, 2, {}), (3, 4, 12, 3, {}), (4, 4, 12, 4, {}),
-    (4, 3, 14, 7, {"chain_merge": False}), (4, 4, 16, 6, {"out_c128": True})])
+    (4, 3, 14, 7, {"chain_merge": False}), (4, 4, 16, 6, {"out_c128": True}), (3, 4, 12, 5, {"B": 130})])
 def test_tree_gradient_matches_oracle(rows, cols, depth, seed, kw):
     """Adjoint through the buckets (merged chains, absorbed buckets, tail
     levels) against the FP64 adjoint-state gradient; the identity
-    sum_ab U conj(G) = 2m; amplitudes of the backward call equal the forward's."""
+    sum_ab U conj(G) = 2m; amplitudes of the backward call equal the forward's.
+    B = 130: three groups of 64 in an arena of row pitch 256."""
+    kw = dict(kw)
+    B = kw.pop("B", 100)
     c = C.parameterised_circuit(rows, cols, depth, seed)
-    bits = C.random_bitstrings(c.n, 100, seed)
+    bits = C.random_bitstrings(c.n, B, seed)
     _say("case tree %s %s" % (c.name, kw))
     amps, amps2, got = _gpu_grad(c, bits, ordering=1, **kw)
     vals = c.gate_vals.astype(np.complex64).astype(np.complex128)

@@ -120,6 +120,11 @@ typedef struct {
                                       must not run concurrently on one device (each needs the whole GPU at
                                       once); a launch that cannot proceed gives up after a bounded wait and
                                       writes NaN amplitudes. */
+    int32_t no_tile;           /* ordering 1 only: 1 = every bucket uses the general wave unit; 0 = a
+                                  two-input bucket summing two or more variables whose result has two bits
+                                  carried by one input only and one carried by the other only (neither in
+                                  its factor table) computes 8 result rows per wave unit from 4 + 2 input
+                                  rows per summed value */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;

@@ -370,6 +370,7 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
         base.gshift = st.kg + st.sb();
         base.n_in = n_in;
         base.nin_class = qgm::launch_inputs(t.level_max_in[st.level]);
+        base.tile = st.tile;
         for (int b = 0; b < st.sb(); ++b) base.sig_q[b] = st.sig_q[b];
         for (int k = 0; k < qgm::kTreeMaxIn; ++k) base.in_tab[k] = -1;
         for (int k = 0; k < n_in; ++k) {

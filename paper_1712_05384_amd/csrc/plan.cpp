@@ -448,6 +448,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     }
     if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
     if (opts.tree_exec < 0 || opts.tree_exec > 2) { *err = "tree_exec must be 0..2"; return QGM_E_INVALID; }
+    if (opts.no_tile < 0 || opts.no_tile > 1) { *err = "no_tile must be 0 or 1"; return QGM_E_INVALID; }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }
@@ -603,6 +604,7 @@ static void json_factor(std::ostringstream& o, const TFactor& f) {
 // unit's result rows.
 static int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
     if (st.table_leaf) return 0;
+    if (st.tile) return (int64_t(4 + 2 + 1) << st.kg) + st.unit_rows;   // 4 + 2 input rows and a table row per value
     const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));
     const int r = int(st.out_axes.size());
     auto count_in = [&](const std::vector<int>& ax, int lo, int hi, const std::vector<int>& from) {
@@ -651,7 +653,7 @@ static std::string tree_json(const Plan& p, int detail) {
         o << ",\"kg\":" << st.kg << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
-          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows
+          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows << ",\"tile\":" << st.tile
           << ",\"table_leaf\":" << (st.table_leaf ? 1 : 0)
           << ",\"issued_bytes_per_b\":" << 8 * st.n_tasks() * tree_unit_accesses(t, st);
         if (detail >= 1) {

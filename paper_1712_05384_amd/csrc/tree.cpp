@@ -427,6 +427,47 @@ static std::vector<int> unit_axis_order(const RStep& st, const std::vector<std::
     return chosen;
 }
 
+// A two-input bucket summing at least two variables whose result has two bits
+// carried by one input only and one bit carried by the other only, none of them
+// a factor-table variable: its result axes start with those three bits and a
+// wave unit covers the 2 x 2 x 2 rows from 4 + 2 input rows per summed value
+// (the general unit holds every (row, input, value) entry and covers 2-4 rows).
+// Returns 1 or 2 (the input with the two bits, plus one) and the axis order.
+static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
+                           const std::vector<std::vector<int>>& out_of, std::vector<int>& order) {
+    if (st.open || st.ins.size() != 2 || st.vars.size() < 2) return 0;
+    std::set<int> gset;
+    std::vector<int> sigq;
+    group_table_vars(p, m, st, gset, sigq);
+    auto carries = [&](int in, int u) {
+        const std::vector<int>& ax = out_of[in];
+        return std::find(ax.begin(), ax.end(), u) != ax.end();
+    };
+    std::vector<int> only[2];
+    for (int u : st.out)
+        if (!gset.count(u))
+            for (int k = 0; k < 2; ++k)
+                if (carries(st.ins[k], u) && !carries(st.ins[1 - k], u)) only[k].push_back(u);
+    int ka = -1;
+    if (only[0].size() >= 2 && !only[1].empty()) ka = 0;
+    else if (only[1].size() >= 2 && !only[0].empty()) ka = 1;
+    if (ka < 0) return 0;
+    order = {only[ka][0], only[ka][1], only[1 - ka][0]};
+    std::vector<int> rest;
+    for (int u : st.out)
+        if (std::find(order.begin(), order.end(), u) == order.end()) rest.push_back(u);
+    // the other axes as in the general order: those that most inputs lack (by size) lowest
+    std::vector<double> lack(rest.size(), 0.0);
+    for (size_t c = 0; c < rest.size(); ++c)
+        for (int in : st.ins)
+            if (!carries(in, rest[c])) lack[c] += double(int64_t(1) << out_of[in].size());
+    std::vector<size_t> idx(rest.size());
+    for (size_t c = 0; c < idx.size(); ++c) idx[c] = c;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return lack[x] > lack[y]; });
+    for (size_t c : idx) order.push_back(rest[c]);
+    return ka + 1;
+}
+
 static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector<int>& order,
                                 const std::vector<RStep>& rs, const std::vector<RTensor>& rt, TreePlan& t,
                                 std::string* err) {
@@ -438,8 +479,13 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     for (const RStep& st : rs)
         if (st.alive) out_of[st.out_tensor] = st.out;
     std::vector<std::vector<int>> out_ord(rs.size());
-    for (size_t i = 0; i < rs.size(); ++i)   // a bucket over the open qubits keeps their order (output index bits)
-        if (rs[i].alive) out_ord[i] = rs[i].open ? rs[i].out : unit_axis_order(rs[i], out_of);
+    std::vector<int> tile_of(rs.size(), 0);
+    for (size_t i = 0; i < rs.size(); ++i) {   // a bucket over the open qubits keeps their order (output index bits)
+        if (!rs[i].alive) continue;
+        if (rs[i].open) out_ord[i] = rs[i].out;
+        else if (p.opts.no_tile == 0 && (tile_of[i] = tile_axis_order(p, m, rs[i], out_of, out_ord[i])) != 0) {}
+        else out_ord[i] = unit_axis_order(rs[i], out_of);
+    }
     std::vector<int> tmap(rt.size(), -1);
     t.tensor_axes.clear();
     for (size_t i = 0; i < rs.size(); ++i) {
@@ -473,6 +519,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
             level = std::max(level, t.tensor_made[ti] + 1);
         }
         ts.level = level;
+        ts.tile = tile_of[si];
         t.tensor_made[ts.out_tensor] = level;
         group_table_vars(p, m, st, gset, sigq);
         std::vector<int> g(gset.begin(), gset.end());
@@ -721,7 +768,7 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         const int nin = launch_inputs(mi);
         for (int sid : t.levels[L]) {
             TreeStep& st = t.steps[sid];
-            st.unit_rows = tree_unit_rows(nin, st.kg);
+            st.unit_rows = st.tile ? (1 << kTreeOcBits) : tree_unit_rows(nin, st.kg);
             st.task_off = t.n_tasks;
             t.n_tasks += st.n_tasks();
         }

@@ -86,6 +86,34 @@ struct TailView {
     const float2* one;
 };
 
+// Where input t's row r lives for this lane: base + (r << sh) (a result in the
+// arena: column b, rows B_eff apart, a power of two; a leaf table: its entries
+// for the lane's output bits, rows 2^sb apart; a result kept in the tail's LDS:
+// rows 64 apart; an input the bucket does not have: the constant 1 at row 0,
+// whose row steps are all 0).
+template <bool TL>
+__device__ __forceinline__ void input_view(const TreeTask& tk, int t, const float2* __restrict__ ain,
+                                           const float2* __restrict__ gtab, int64_t ones_g, uint64_t x, uint32_t b,
+                                           uint32_t be_sh, const TailView& tv, const float2*& base, uint32_t& sh) {
+    if (tk.in_row[t] < 0) {
+        base = TL ? tv.one : gtab + ones_g;
+        sh = 0;
+    } else if (TL && tk.in_tab[t] == -2) {
+        base = tv.rows + (b & 63u);
+        sh = 6;
+    } else if (tk.in_tab[t] >= 0) {
+        const int tsb = tk.in_tsb[t];
+        const uint64_t pk = uint64_t(tk.in_tsig[t]);
+        uint32_t s = 0;
+        for (int i = 0; i < tsb; ++i) s |= uint32_t((x >> ((pk >> (6 * i)) & 63u)) & 1ull) << i;
+        base = gtab + tk.in_tab[t] + s;
+        sh = uint32_t(tsb);
+    } else {
+        base = ain + b;
+        sh = be_sh;
+    }
+}
+
 template <int NIN, int K, bool TL>
 __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
@@ -94,10 +122,7 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
     constexpr int WC = W < 8 ? W : 8;          // summed-variable values per load batch
     static_assert(WC == W, "one load batch holds every summed value (the repeat copies index within it)");
     constexpr int OB = tree_unit_rows(NIN, K);
-    // Where input t's row r lives for this lane: base[t] + (r << sh[t]) (a result
-    // in the arena: column b, rows B_eff apart, a power of two; a leaf table: its
-    // entries for the lane's output bits, rows 2^sb apart; an input the bucket
-    // does not have: the constant 1 at row 0, whose row steps are all 0).  Rows
+    // Input t's row r for this lane is base[t] + (r << sh[t]) (input_view).  Rows
     // (32-bit), the factor-table entry of the unit's rows and the row offset of
     // each summed value w in each input are scalar; a power-of-two row pitch
     // makes the row scaling one shift instead of a 64-bit multiply per load.
@@ -105,25 +130,7 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
     const float2* base[NIN];
     uint32_t sh[NIN];
 #pragma unroll
-    for (int t = 0; t < NIN; ++t) {
-        if (tk.in_row[t] < 0) {
-            base[t] = TL ? tv.one : gtab + ones_g;
-            sh[t] = 0;
-        } else if (TL && tk.in_tab[t] == -2) {
-            base[t] = tv.rows + (b & 63u);
-            sh[t] = 6;
-        } else if (tk.in_tab[t] >= 0) {
-            const int tsb = tk.in_tsb[t];
-            const uint64_t pk = uint64_t(tk.in_tsig[t]);
-            uint32_t s = 0;
-            for (int i = 0; i < tsb; ++i) s |= uint32_t((x >> ((pk >> (6 * i)) & 63u)) & 1ull) << i;
-            base[t] = gtab + tk.in_tab[t] + s;
-            sh[t] = uint32_t(tsb);
-        } else {
-            base[t] = ain + b;
-            sh[t] = be_sh;
-        }
-    }
+    for (int t = 0; t < NIN; ++t) input_view<TL>(tk, t, ain, gtab, ones_g, x, b, be_sh, tv, base[t], sh[t]);
     int32_t row[OB][NIN], off[NIN][W];
     int64_t gent[OB];
 #pragma unroll
@@ -262,6 +269,83 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
     for (int i = 0; i < OB; ++i) out[int64_t(i) * be] = acc[i];
 }
 
+// A tile unit: a two-input bucket whose unit bits 0 and 1 vary only input
+// ta = tile - 1 and bit 2 only the other input tb, the factor table along none:
+//   R[i + 4 j] = sum_w G[w, sigma] A[i][w] B[j][w]   (i < 4, j < 2),
+// with A, B the rows of ta, tb at those unit rows and summed value w.  It loads
+// 4 + 2 input rows and one table row per w for 8 result rows (the general unit
+// would hold every (row, input, w) entry and cover 2-4 rows).
+// (TA, the input with the two bits, is a template parameter: a task field indexed
+// by a run-time input number would send the task record to scratch memory.)
+template <int K, bool TL, int TA>
+__device__ __forceinline__ void tile_unit(const TreeTask& tk, const float2* __restrict__ ain,
+                                          float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
+                                          int64_t sig, uint64_t x, uint32_t b, int64_t be, const TailView& tv) {
+    constexpr int W = 1 << K;
+    constexpr int ta = TA, tb = 1 - TA;
+    const uint32_t be_sh = uint32_t(__builtin_ctzll(uint64_t(be)));
+    const float2 *base_a, *base_b;
+    uint32_t sh_a, sh_b;
+    input_view<TL>(tk, ta, ain, gtab, ones_g, x, b, be_sh, tv, base_a, sh_a);
+    input_view<TL>(tk, tb, ain, gtab, ones_g, x, b, be_sh, tv, base_b, sh_b);
+    // unit row o = o-1 + increment of bit ctz(o): rows 0..3 of ta, rows 0 and 4 of tb
+    int32_t ra[4], rb[2];
+    ra[0] = tk.in_row[ta];
+    ra[1] = ra[0] + tk.in_inc[ta][0];
+    ra[2] = ra[1] + tk.in_inc[ta][1];
+    ra[3] = ra[2] + tk.in_inc[ta][0];
+    rb[0] = tk.in_row[tb];
+    rb[1] = rb[0] + 2 * tk.in_inc[tb][0] + tk.in_inc[tb][1] + tk.in_inc[tb][2];
+    int32_t oa[W], ob[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        oa[w] = 0;
+        ob[w] = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((w >> i) & 1) {
+                oa[w] += tk.in_vs[ta][i];
+                ob[w] += tk.in_vs[tb][i];
+            }
+    }
+    float2 A[4][W], Bv[2][W], Q[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) A[i][w] = base_a[int64_t(uint32_t(ra[i] + oa[w])) << sh_a];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) Bv[j][w] = base_b[int64_t(uint32_t(rb[j] + ob[w])) << sh_b];
+        Q[w] = (TL ? tv.g : gtab)[tk.g_ent + (int64_t(w) << tk.sb) + sig];
+    }
+    float2 acc[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc[o] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float2 qa = cmulf(Q[w], A[i][w]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const float2 l = Bv[j][w];
+                float2& c = acc[i + 4 * j];
+                c.x = fmaf(qa.x, l.x, c.x);
+                c.x = fmaf(-qa.y, l.y, c.x);
+                c.y = fmaf(qa.x, l.y, c.y);
+                c.y = fmaf(qa.y, l.x, c.y);
+            }
+        }
+    if (TL) {
+        float2* out = tv.rows + int64_t(tk.out_row) * 64 + (b & 63u);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) out[o * 64] = acc[o];
+        return;
+    }
+    float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) out[int64_t(o) * be] = acc[o];
+}
+
 // A unit of task tk for bitstring group bg (x = the lane's bitstring).
 template <int NIN, bool TL = false>
 __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const float2* __restrict__ ain,
@@ -269,6 +353,18 @@ __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const 
                                           uint32_t b, int64_t be, const TailView& tv = TailView{}) {
     static_assert(kTreeMaxSum == 3, "tasks sum 0 (the product over the open qubits), 1, 2 or 3 variables");
     const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
+    if constexpr (NIN >= 2) {
+        if (tk.tile) {   // two or three summed variables
+            if (tk.k == 2) {
+                if (tk.tile == 1) tile_unit<2, TL, 0>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+                else tile_unit<2, TL, 1>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            } else {
+                if (tk.tile == 1) tile_unit<3, TL, 0>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+                else tile_unit<3, TL, 1>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            }
+            return;
+        }
+    }
     if (tk.k == 0) tree_unit<NIN, 0, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
     else if (tk.k == 1) tree_unit<NIN, 1, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
     else if (tk.k == 2) tree_unit<NIN, 2, TL>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);

@@ -302,3 +302,39 @@ def test_tree_tail_with_final_from_the_arena():
     _say("case tree tail final from arena")
     got = _amps(p, bits)
     assert np.abs(got - oracle.sv_amplitudes(20, c.gates, None, bits)).max() <= TOL * 2 ** (-20 / 2)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,B", [(4, 4, 16, 3, 130), (5, 5, 20, 8, 64), (4, 5, 20, 2, 200)])
+def test_tree_tile_units(rows, cols, depth, seed, B):
+    """Tile units (two-input buckets, 8 rows per unit from 4 + 2 input rows) against
+    the oracle, and the same plan without them."""
+    import paper_1712_05384_amd as Q
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    p = Q.plan(c, ordering=1)
+    n_tiles = sum(1 for bk in p.info(1)["buckets"] if bk["tile"])
+    bits = C.random_bitstrings(c.n, B, seed)
+    _say("case tree tiles %s (%d tile buckets) B=%d" % (c.name, n_tiles, B))
+    got = _amps(p, bits)
+    assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits)).max() <= TOL * 2 ** (-c.n / 2)
+    plain = _amps(Q.plan(c, ordering=1, tile=False), bits)
+    assert np.abs(got - plain).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_tile_units_c3_and_parameterised():
+    """5x6 depth 30 (six tile buckets) against the stored oracle amplitudes, and
+    a circuit with gate values whose plan has tiles."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c3_5x6_d30")
+    p = Q.plan(c, ordering=1)
+    assert sum(1 for bk in p.info(1)["buckets"] if bk["tile"]) >= 3
+    ref = np.load(os.path.join(GOLDEN, "c3_5x6_d30_amps.npy"), allow_pickle=False)
+    got = _amps(p, bits)
+    assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+    cp, _ = C.workload("c4_5x5_d20_U")
+    pp = Q.plan(cp, ordering=1)
+    assert sum(1 for bk in pp.info(1)["buckets"] if bk["tile"]) >= 1
+    bits2 = C.random_bitstrings(cp.n, 70, 8)
+    gv = cp.gate_vals.astype(np.complex64)
+    got2 = _amps(pp, bits2, torch.tensor(gv))
+    ref2 = oracle.sv_amplitudes(cp.n, cp.gates, gv.astype(np.complex128), bits2)
+    assert np.abs(got2 - ref2).max() <= TOL * 2 ** (-cp.n / 2)

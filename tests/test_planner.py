@@ -416,3 +416,30 @@ def test_tail_plan_with_many_phase_factors_closed_form():
     for q in range(12, n):
         ref = ref * np.where(((bits >> np.uint64(q)) & np.uint64(1)).astype(bool), np.exp(1j * np.pi / 4), 1.0) / np.sqrt(2)
     assert np.abs(run_tree_plan(info, None, bits) - ref).max() < 1e-12 * 2 ** (-n / 2)
+
+
+def test_tile_buckets_planned_and_interpreted():
+    """Two-input buckets with two bits carried by one input only and one by the
+    other only become tile units (8 result rows, those three bits lowest); the
+    plan computes the same amplitudes with and without tiles."""
+    import paper_1712_05384_amd as Q
+    from tree_interp import run_tree_plan
+    c, _ = C.workload("c3_5x6_d30")
+    info = Q.plan(c, ordering=1).info(1)
+    tiles = [bk for bk in info["buckets"] if bk["tile"]]
+    assert len(tiles) >= 3
+    tensors = info["tensors"]
+    for bk in tiles:
+        assert bk["n_in"] == 2 and bk["kg"] >= 2 and bk["unit_rows"] == 8
+        a, b = (bk["in_tensors"] if bk["tile"] == 1 else bk["in_tensors"][::-1])
+        ax_a, ax_b, out = tensors[a]["axes"], tensors[b]["axes"], bk["out_axes"]
+        assert out[0] in ax_a and out[0] not in ax_b and out[1] in ax_a and out[1] not in ax_b
+        assert out[2] in ax_b and out[2] not in ax_a
+        assert not set(out[:3]) & set(bk["gvars"])
+    assert not any(bk["tile"] for bk in Q.plan(c, ordering=1, tile=False).info(1)["buckets"])
+    c2 = C.random_grid_circuit(4, 4, 16, 3)
+    bits = C.random_bitstrings(c2.n, 8, 3)
+    ref = oracle.sv_amplitudes(c2.n, c2.gates, None, bits)
+    for tile in (True, False):
+        got = run_tree_plan(Q.plan(c2, ordering=1, tile=tile).info(1), None, bits)
+        assert np.abs(got - ref).max() < 1e-12

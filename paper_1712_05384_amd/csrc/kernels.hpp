@@ -58,9 +58,9 @@ struct TreeTask {
     int32_t in_vs[kTreeMaxIn][kTreeMaxSum];     // row stride of summed variable i in input t (0: not an axis)
     int32_t in_inc[kTreeMaxIn][kTreeOcBits];    // row change of input t when o -> o + 1 with ctz(o + 1) = j
     int32_t g_inc[kTreeOcBits];                 // factor-table g change for the same steps
-    int32_t tile;                               // 0: the general unit; 1, 2: a tile unit whose input tile - 1
-                                                //   varies along unit bits 0, 1 and the other input along bit 2
-                                                //   (the factor table along none): 8 rows per unit
+    int32_t tile;                               // 0: the general unit; 1 (two inputs), 2 (three): a tile unit
+                                                //   whose input 0 varies along unit bits 0, 1, input 1 along
+                                                //   bit 2, input 2 and the factor table along none: 8 rows
     int32_t dep_off[kTreeMaxIn];                // tasks of the bucket that makes input t: [dep_off, dep_off + dep_n)
     int32_t dep_n[kTreeMaxIn];
     int32_t in_omask[kTreeMaxIn];               // bit j: input t's row changes along the unit's result row bit j

@@ -604,7 +604,8 @@ static void json_factor(std::ostringstream& o, const TFactor& f) {
 // unit's result rows.
 static int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
     if (st.table_leaf) return 0;
-    if (st.tile) return (int64_t(4 + 2 + 1) << st.kg) + st.unit_rows;   // 4 + 2 input rows and a table row per value
+    if (st.tile)   // 4 + 2 (+ 1) input rows and a table row per summed value
+        return (int64_t(4 + 2 + 1 + (st.tile == 2 ? 1 : 0)) << st.kg) + st.unit_rows;
     const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));
     const int r = int(st.out_axes.size());
     auto count_in = [&](const std::vector<int>& ax, int lo, int hi, const std::vector<int>& from) {

@@ -427,15 +427,19 @@ static std::vector<int> unit_axis_order(const RStep& st, const std::vector<std::
     return chosen;
 }
 
-// A two-input bucket summing at least two variables whose result has two bits
-// carried by one input only and one bit carried by the other only, none of them
-// a factor-table variable: its result axes start with those three bits and a
-// wave unit covers the 2 x 2 x 2 rows from 4 + 2 input rows per summed value
-// (the general unit holds every (row, input, value) entry and covers 2-4 rows).
-// Returns 1 or 2 (the input with the two bits, plus one) and the axis order.
+// A bucket with two or three inputs summing at least two variables whose result
+// has two bits carried by one input only (A) and one bit carried by another
+// input only (B), none of them a factor-table variable: its result axes start
+// with those three bits and a wave unit covers the 2 x 2 x 2 rows from 4 rows of
+// A, 2 of B and (a third input C, which varies along none of them) 1 of C per
+// summed value (the general unit holds every (row, input, value) entry and
+// covers 2-4 rows).  Returns 1 (two inputs) or 2 (three), the axis order and
+// the inputs in the order A, B, C.
 static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
-                           const std::vector<std::vector<int>>& out_of, std::vector<int>& order) {
-    if (st.open || st.ins.size() != 2 || st.vars.size() < 2) return 0;
+                           const std::vector<std::vector<int>>& out_of, std::vector<int>& order,
+                           std::vector<int>& ins) {
+    const int n = int(st.ins.size());
+    if (st.open || (n != 2 && n != 3) || st.vars.size() < 2) return 0;
     std::set<int> gset;
     std::vector<int> sigq;
     group_table_vars(p, m, st, gset, sigq);
@@ -443,16 +447,23 @@ static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
         const std::vector<int>& ax = out_of[in];
         return std::find(ax.begin(), ax.end(), u) != ax.end();
     };
-    std::vector<int> only[2];
-    for (int u : st.out)
-        if (!gset.count(u))
-            for (int k = 0; k < 2; ++k)
-                if (carries(st.ins[k], u) && !carries(st.ins[1 - k], u)) only[k].push_back(u);
-    int ka = -1;
-    if (only[0].size() >= 2 && !only[1].empty()) ka = 0;
-    else if (only[1].size() >= 2 && !only[0].empty()) ka = 1;
+    std::vector<std::vector<int>> only(n);
+    for (int u : st.out) {
+        if (gset.count(u)) continue;
+        int holder = -1, count = 0;
+        for (int k = 0; k < n; ++k)
+            if (carries(st.ins[k], u)) { holder = k; ++count; }
+        if (count == 1) only[holder].push_back(u);
+    }
+    int ka = -1, kb = -1;
+    for (int a = 0; a < n && ka < 0; ++a)
+        for (int b = 0; b < n; ++b)
+            if (a != b && only[a].size() >= 2 && !only[b].empty()) { ka = a; kb = b; break; }
     if (ka < 0) return 0;
-    order = {only[ka][0], only[ka][1], only[1 - ka][0]};
+    order = {only[ka][0], only[ka][1], only[kb][0]};
+    ins = {st.ins[ka], st.ins[kb]};
+    for (int k = 0; k < n; ++k)
+        if (k != ka && k != kb) ins.push_back(st.ins[k]);
     std::vector<int> rest;
     for (int u : st.out)
         if (std::find(order.begin(), order.end(), u) == order.end()) rest.push_back(u);
@@ -465,7 +476,7 @@ static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
     for (size_t c = 0; c < idx.size(); ++c) idx[c] = c;
     std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return lack[x] > lack[y]; });
     for (size_t c : idx) order.push_back(rest[c]);
-    return ka + 1;
+    return n - 1;
 }
 
 static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector<int>& order,
@@ -480,10 +491,12 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         if (st.alive) out_of[st.out_tensor] = st.out;
     std::vector<std::vector<int>> out_ord(rs.size());
     std::vector<int> tile_of(rs.size(), 0);
+    std::vector<std::vector<int>> tile_ins(rs.size());
     for (size_t i = 0; i < rs.size(); ++i) {   // a bucket over the open qubits keeps their order (output index bits)
         if (!rs[i].alive) continue;
         if (rs[i].open) out_ord[i] = rs[i].out;
-        else if (p.opts.no_tile == 0 && (tile_of[i] = tile_axis_order(p, m, rs[i], out_of, out_ord[i])) != 0) {}
+        else if (p.opts.no_tile == 0 &&
+                 (tile_of[i] = tile_axis_order(p, m, rs[i], out_of, out_ord[i], tile_ins[i])) != 0) {}
         else out_ord[i] = unit_axis_order(rs[i], out_of);
     }
     std::vector<int> tmap(rt.size(), -1);
@@ -512,7 +525,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         ts.out_tensor = tmap[st.out_tensor];
         for (int u : out_ord[si]) ts.out_axes.push_back(m.free_var[u]);
         int level = 0;
-        for (int in : st.ins) {
+        for (int in : (tile_of[si] ? tile_ins[si] : st.ins)) {   // a tile's inputs in the order A, B, C
             const int ti = tmap[in];
             if (ti < 0) { *err = "internal: merged result still read"; return QGM_E_INTERNAL; }
             ts.in_tensors.push_back(ti);

@@ -269,53 +269,57 @@ __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __re
     for (int i = 0; i < OB; ++i) out[int64_t(i) * be] = acc[i];
 }
 
-// A tile unit: a two-input bucket whose unit bits 0 and 1 vary only input
-// ta = tile - 1 and bit 2 only the other input tb, the factor table along none:
-//   R[i + 4 j] = sum_w G[w, sigma] A[i][w] B[j][w]   (i < 4, j < 2),
-// with A, B the rows of ta, tb at those unit rows and summed value w.  It loads
-// 4 + 2 input rows and one table row per w for 8 result rows (the general unit
-// would hold every (row, input, w) entry and cover 2-4 rows).
-// (TA, the input with the two bits, is a template parameter: a task field indexed
-// by a run-time input number would send the task record to scratch memory.)
-template <int K, bool TL, int TA>
+// A tile unit: a bucket whose unit bits 0 and 1 vary only input 0 (A), bit 2
+// only input 1 (B), and neither a third input C (NC) nor the factor table:
+//   R[i + 4 j] = sum_w G[w, sigma] C[w] A[i][w] B[j][w]   (i < 4, j < 2),
+// with A, B the rows of inputs 0, 1 at those unit rows and summed value w.  It
+// loads 4 + 2 (+ 1) input rows and one table row per w for 8 result rows (the
+// general unit would hold every (row, input, w) entry and cover 2-4 rows).
+template <int K, bool TL, bool NC>
 __device__ __forceinline__ void tile_unit(const TreeTask& tk, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
                                           int64_t sig, uint64_t x, uint32_t b, int64_t be, const TailView& tv) {
     constexpr int W = 1 << K;
-    constexpr int ta = TA, tb = 1 - TA;
     const uint32_t be_sh = uint32_t(__builtin_ctzll(uint64_t(be)));
-    const float2 *base_a, *base_b;
-    uint32_t sh_a, sh_b;
-    input_view<TL>(tk, ta, ain, gtab, ones_g, x, b, be_sh, tv, base_a, sh_a);
-    input_view<TL>(tk, tb, ain, gtab, ones_g, x, b, be_sh, tv, base_b, sh_b);
-    // unit row o = o-1 + increment of bit ctz(o): rows 0..3 of ta, rows 0 and 4 of tb
+    const float2 *base_a, *base_b, *base_c = nullptr;
+    uint32_t sh_a, sh_b, sh_c = 0;
+    input_view<TL>(tk, 0, ain, gtab, ones_g, x, b, be_sh, tv, base_a, sh_a);
+    input_view<TL>(tk, 1, ain, gtab, ones_g, x, b, be_sh, tv, base_b, sh_b);
+    if (NC) input_view<TL>(tk, 2, ain, gtab, ones_g, x, b, be_sh, tv, base_c, sh_c);
+    // unit row o = o-1 + increment of bit ctz(o): rows 0..3 of A, rows 0 and 4 of B
     int32_t ra[4], rb[2];
-    ra[0] = tk.in_row[ta];
-    ra[1] = ra[0] + tk.in_inc[ta][0];
-    ra[2] = ra[1] + tk.in_inc[ta][1];
-    ra[3] = ra[2] + tk.in_inc[ta][0];
-    rb[0] = tk.in_row[tb];
-    rb[1] = rb[0] + 2 * tk.in_inc[tb][0] + tk.in_inc[tb][1] + tk.in_inc[tb][2];
-    int32_t oa[W], ob[W];
+    ra[0] = tk.in_row[0];
+    ra[1] = ra[0] + tk.in_inc[0][0];
+    ra[2] = ra[1] + tk.in_inc[0][1];
+    ra[3] = ra[2] + tk.in_inc[0][0];
+    rb[0] = tk.in_row[1];
+    rb[1] = rb[0] + 2 * tk.in_inc[1][0] + tk.in_inc[1][1] + tk.in_inc[1][2];
+    const int32_t rc = NC ? tk.in_row[2] : 0;
+    int32_t oa[W], ob[W], oc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        oa[w] = 0;
-        ob[w] = 0;
+        oa[w] = ob[w] = oc[w] = 0;
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if ((w >> i) & 1) {
-                oa[w] += tk.in_vs[ta][i];
-                ob[w] += tk.in_vs[tb][i];
+                oa[w] += tk.in_vs[0][i];
+                ob[w] += tk.in_vs[1][i];
+                if (NC) oc[w] += tk.in_vs[2][i];
             }
     }
-    float2 A[4][W], Bv[2][W], Q[W];
+    float2 A[4][W], Bv[2][W], Q[W], Cv[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) A[i][w] = base_a[int64_t(uint32_t(ra[i] + oa[w])) << sh_a];
 #pragma unroll
         for (int j = 0; j < 2; ++j) Bv[j][w] = base_b[int64_t(uint32_t(rb[j] + ob[w])) << sh_b];
+        if (NC) Cv[w] = base_c[int64_t(uint32_t(rc + oc[w])) << sh_c];
         Q[w] = (TL ? tv.g : gtab)[tk.g_ent + (int64_t(w) << tk.sb) + sig];
+    }
+    if (NC) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) Q[w] = cmulf(Q[w], Cv[w]);
     }
     float2 acc[8];
 #pragma unroll
@@ -354,14 +358,16 @@ __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const 
     static_assert(kTreeMaxSum == 3, "tasks sum 0 (the product over the open qubits), 1, 2 or 3 variables");
     const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
     if constexpr (NIN >= 2) {
-        if (tk.tile) {   // two or three summed variables
-            if (tk.k == 2) {
-                if (tk.tile == 1) tile_unit<2, TL, 0>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
-                else tile_unit<2, TL, 1>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
-            } else {
-                if (tk.tile == 1) tile_unit<3, TL, 0>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
-                else tile_unit<3, TL, 1>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
-            }
+        if (tk.tile == 1) {   // two or three summed variables
+            if (tk.k == 2) tile_unit<2, TL, false>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            else tile_unit<3, TL, false>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            return;
+        }
+    }
+    if constexpr (NIN >= 3) {
+        if (tk.tile == 2) {
+            if (tk.k == 2) tile_unit<2, TL, true>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            else tile_unit<3, TL, true>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
             return;
         }
     }

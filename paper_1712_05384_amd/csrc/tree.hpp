@@ -133,10 +133,10 @@ struct TreeStep {
     int64_t task_off = 0;               // first wave task of this bucket
     int unit_rows = 1;                  // result rows per wave task (tree_unit_rows of its launch, or 8 for a
                                         //   tile)
-    int tile = 0;                       // two inputs, unit = 2 result bits varying only input tile - 1 and
-                                        //   one varying only the other input, none of them in the factor
-                                        //   table: its 8 rows from 4 + 2 input rows and 1 table row per
-                                        //   summed value (0: the general unit)
+    int tile = 0;                       // 1 (two inputs) or 2 (three): a tile unit, whose unit bits 0 and 1
+                                        //   vary only input 0, bit 2 only input 1 and none input 2 or the
+                                        //   factor table; its 8 rows from 4 + 2 (+ 1) input rows and 1
+                                        //   table row per summed value (0: the general unit)
     int64_t n_tasks() const {
         const int64_t rows = int64_t(1) << out_axes.size();
         return rows <= unit_rows ? 1 : rows / unit_rows;

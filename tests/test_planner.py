@@ -443,3 +443,30 @@ def test_tile_buckets_planned_and_interpreted():
     for tile in (True, False):
         got = run_tree_plan(Q.plan(c2, ordering=1, tile=tile).info(1), None, bits)
         assert np.abs(got - ref).max() < 1e-12
+
+
+def test_tile_in_tail_and_option_validation():
+    """4x4 depth 16: a tile bucket runs in the tail (tile units reading and writing
+    the tail's LDS); an invalid no_tile value is rejected."""
+    import paper_1712_05384_amd as Q
+    c, _ = C.workload("c1_4x4_d16")
+    info = Q.plan(c, ordering=1).info(1)
+    assert any(bk["tile"] and bk["level"] >= info["tail_start"] for bk in info["buckets"])
+    cs, keep = Q.api._circuit_struct(c.rows, c.cols, c.gates, 0)
+    opts = N.QgmPlanOpts()
+    L = N.lib()
+    L.qgm_default_opts(ctypes.byref(opts))
+    opts.ordering = 1
+    opts.no_tile = 2
+    h = ctypes.c_void_p()
+    assert L.qgm_plan(ctypes.byref(cs), None, 0, ctypes.byref(opts), ctypes.byref(h)) == N.QGM_E_INVALID
+
+
+def test_bucket_workspace_uses_power_of_two_pitch():
+    """The bucket arena's row pitch is the padded batch rounded up to a power of
+    two: a batch of 130 (3 groups of 64) takes the workspace of a batch of 256."""
+    import paper_1712_05384_amd as Q
+    c = C.random_grid_circuit(3, 4, 12, 5)
+    p = Q.plan(c, ordering=1)
+    assert p.workspace_bytes(130) == p.workspace_bytes(256) > p.workspace_bytes(128)
+    assert p.workspace_bytes(64) == p.workspace_bytes(1)

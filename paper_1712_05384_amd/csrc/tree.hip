@@ -67,19 +67,9 @@ __global__ void __launch_bounds__(256) k_tree_prologue(const TreeProBlock* __res
     gtab[t.g_off + e] = make_float2(float(acc.x), float(acc.y));
 }
 
-// One wave unit of a bucket with inputs: the task's rows for the 64
-// bitstrings b of one group,
-//   R[o][b] = sum_{w < 2^K} G[g(o), w, sigma(b)] * prod_t T_t[idx_t(o) + off_t(w)][b],
-// w running over the values of the bucket's K summed variables (one, or up to
-// three for a merged chain).  No data-dependent branch: a bucket with fewer
-// inputs than NIN multiplies a constant 1 (one address for all lanes, chosen
-// per wave), and the task of a result with fewer rows than a unit wraps onto
-// valid rows and stores into rows the arena reserves for it.  Inputs (ain) and results (aout) are views
-// of one arena whose rows a level never both reads and writes, so all loads
-// of a unit can be in flight at once.  In the tail kernel (TL) an input or the
-// result may instead be rows kept in LDS for the work-group's 64 bitstrings
-// (row r of lane l at rows[r * 64 + l]), and the bucket's factor table and the
-// constant 1 are LDS copies.
+// What the tail kernel keeps in LDS for its work-group's 64 bitstrings: the
+// results made in the tail (row r of lane l at rows[r * 64 + l]), the tail's
+// factor tables and the constant 1.
 struct TailView {
     float2* rows;
     const float2* g;      // the tail's factor tables (g_ent of a tail task counts from here)
@@ -114,6 +104,17 @@ __device__ __forceinline__ void input_view(const TreeTask& tk, int t, const floa
     }
 }
 
+// One wave unit of a bucket with inputs: the task's rows for the 64
+// bitstrings b of one group,
+//   R[o][b] = sum_{w < 2^K} G[g(o), w, sigma(b)] * prod_t T_t[idx_t(o) + off_t(w)][b],
+// w running over the values of the bucket's K summed variables (one, or up to
+// three for a merged chain).  No data-dependent branch: a bucket with fewer
+// inputs than NIN multiplies a constant 1 (one address for all lanes, chosen
+// per wave), and the task of a result with fewer rows than a unit wraps onto
+// valid rows and stores into rows the arena reserves for it.  Inputs (ain) and
+// results (aout) are views of one arena whose rows a level never both reads and
+// writes, so all loads of a unit can be in flight at once.  In the tail kernel
+// (TL) an input or the result may instead be rows kept in LDS (TailView).
 template <int NIN, int K, bool TL>
 __device__ __forceinline__ void tree_unit(const TreeTask& tk, const float2* __restrict__ ain,
                                           float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,

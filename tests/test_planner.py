@@ -419,9 +419,9 @@ def test_tail_plan_with_many_phase_factors_closed_form():
 
 
 def test_tile_buckets_planned_and_interpreted():
-    """Two-input buckets with two bits carried by one input only and one by the
-    other only become tile units (8 result rows, those three bits lowest); the
-    plan computes the same amplitudes with and without tiles."""
+    """Buckets with two bits carried by one input only and one by another only
+    become tile units (8 result rows, those three bits lowest); the plan
+    computes the same amplitudes with and without them."""
     import paper_1712_05384_amd as Q
     from tree_interp import run_tree_plan
     c, _ = C.workload("c3_5x6_d30")
@@ -429,12 +429,15 @@ def test_tile_buckets_planned_and_interpreted():
     tiles = [bk for bk in info["buckets"] if bk["tile"]]
     assert len(tiles) >= 3
     tensors = info["tensors"]
+
+    def alone(u, t, ins):   # result bit u carried by input t and by no other input
+        return u in tensors[ins[t]]["axes"] and all(u not in tensors[o]["axes"] for k, o in enumerate(ins) if k != t)
+
     for bk in tiles:
-        assert bk["n_in"] == 2 and bk["kg"] >= 2 and bk["unit_rows"] == 8
-        a, b = (bk["in_tensors"] if bk["tile"] == 1 else bk["in_tensors"][::-1])
-        ax_a, ax_b, out = tensors[a]["axes"], tensors[b]["axes"], bk["out_axes"]
-        assert out[0] in ax_a and out[0] not in ax_b and out[1] in ax_a and out[1] not in ax_b
-        assert out[2] in ax_b and out[2] not in ax_a
+        ins, out = bk["in_tensors"], bk["out_axes"]
+        assert bk["n_in"] == bk["tile"] + 1 and bk["kg"] >= 2 and bk["unit_rows"] == 8
+        # inputs in the order A (two bits), B (one bit), C (none)
+        assert alone(out[0], 0, ins) and alone(out[1], 0, ins) and alone(out[2], 1, ins)
         assert not set(out[:3]) & set(bk["gvars"])
     assert not any(bk["tile"] for bk in Q.plan(c, ordering=1, tile=False).info(1)["buckets"])
     c2 = C.random_grid_circuit(4, 4, 16, 3)

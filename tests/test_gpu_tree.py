@@ -338,3 +338,25 @@ def test_tree_tile_units_c3_and_parameterised():
     got2 = _amps(pp, bits2, torch.tensor(gv))
     ref2 = oracle.sv_amplitudes(cp.n, cp.gates, gv.astype(np.complex128), bits2)
     assert np.abs(got2 - ref2).max() <= TOL * 2 ** (-cp.n / 2)
+
+
+@pytest.mark.parametrize("B", [1, 65, 200])
+def test_tree_tile_units_ragged_batches_c128(B):
+    """Tile plans at batches that do not fill the arena's power-of-two pitch, with
+    complex128 output, and a circuit with gate values whose plan has tiles."""
+    import paper_1712_05384_amd as Q
+    c = C.random_grid_circuit(4, 5, 20, 2)
+    p = Q.plan(c, ordering=1, out_c128=True)
+    assert any(bk["tile"] for bk in p.info(1)["buckets"])
+    bits = C.random_bitstrings(c.n, B, 40 + B)
+    _say("case tree tiles ragged B=%d c128" % B)
+    got = p.amplitudes(bits).cpu().numpy()[:, 0]
+    assert got.dtype == np.complex128
+    assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits)).max() <= TOL * 2 ** (-c.n / 2)
+    cp, _ = C.workload("c4_5x5_d20_U")
+    pp = Q.plan(cp, ordering=1)
+    gv = cp.gate_vals.astype(np.complex64)
+    bits2 = C.random_bitstrings(cp.n, B, 50 + B)
+    got2 = _amps(pp, bits2, torch.tensor(gv))
+    ref2 = oracle.sv_amplitudes(cp.n, cp.gates, gv.astype(np.complex128), bits2)
+    assert np.abs(got2 - ref2).max() <= TOL * 2 ** (-cp.n / 2)

@@ -154,7 +154,11 @@ qgm_status qgm_plan(const qgm_circuit* circuit, const int32_t* open_qubits, int3
  * be NULL to query the size). */
 qgm_status qgm_plan_info(const qgm_plan_t* plan, int32_t detail, char* json, size_t cap, size_t* needed);
 
-/* Device workspace (bytes) that qgm_amplitudes needs for a batch of B bitstrings. */
+/* Device workspace (bytes) that qgm_amplitudes needs for a batch of B bitstrings.
+ * For ordering 1 the arena's rows hold B rounded up to a power of two (at least
+ * 64) bitstrings, so the kernels scale rows by a shift: a batch just above a
+ * power of two takes up to twice the memory of one just below it (the work
+ * covers only the batch's own 64-bitstring groups). */
 qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);
 
 /* Computes out[b][o] = <x_b with the open bits set to o | U | 0...0> for
@@ -172,7 +176,8 @@ qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* byte
 qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
                           void* out, void* workspace, uint64_t ws_bytes, void* stream);
 
-/* Device workspace (bytes) that qgm_backward needs for a batch of B bitstrings. */
+/* Device workspace (bytes) that qgm_backward needs for a batch of B bitstrings
+ * (for ordering 1 sized by the same power-of-two row pitch). */
 qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);
 
 /* Gradient of a real loss with respect to the gate values (the gate

@@ -473,3 +473,20 @@ def test_bucket_workspace_uses_power_of_two_pitch():
     p = Q.plan(c, ordering=1)
     assert p.workspace_bytes(130) == p.workspace_bytes(256) > p.workspace_bytes(128)
     assert p.workspace_bytes(64) == p.workspace_bytes(1)
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(3, 4, 18, 3), (3, 4, 20, 4), (4, 4, 16, 3), (4, 4, 20, 2),
+                                                  (4, 4, 24, 1), (5, 5, 25, 201)])
+def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
+    """Plans with tile units (inputs reordered, tile bits lowest; the 5x5 depth-25
+    plan has a three-input tile) and without, run by the interpreter, against
+    the state vector."""
+    import paper_1712_05384_amd as Q
+    from tree_interp import run_tree_plan
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    assert any(bk["tile"] for bk in Q.plan(c, ordering=1).info(1)["buckets"])
+    bits = C.random_bitstrings(c.n, 4, seed)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    for tile in (True, False):
+        got = run_tree_plan(Q.plan(c, ordering=1, tile=tile).info(1), None, bits)
+        assert np.abs(got - ref).max() < 1e-12

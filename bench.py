@@ -32,10 +32,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per dominant-kernel launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
-# plain 1 GiB copy gives), valid for the kernel source with this hash.
+# plain 1 GiB copy gives), valid for the kernel source with this hash and the
+# plan with these figures.
 MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
-    ("c2_5x5_d25", 1): {"bytes_per_launch": 10209629.4, "source": "tree.hip", "sha256_16": "59f05b1860937ba8"},
+    ("c2_5x5_d25", 1): {"bytes_per_launch": 10209629.4, "source": "tree.hip", "sha256_16": "59f05b1860937ba8",
+                        "plan": {"bytes_per_amp": 72488, "level_launches": 8}},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
 
@@ -217,7 +219,9 @@ def dominant_kernel(args, p, info, B, elim_ms, kernels):
     if rec and args.kernel_policy == 0 and (info["ordering"] == 1 or args.no_autotune):
         import hashlib
         path = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", rec["source"])
-        if rec["source"] == src and hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == rec["sha256_16"]:
+        same_plan = all(info.get(k) == v for k, v in rec.get("plan", {}).items())
+        if rec["source"] == src and same_plan and \
+                hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == rec["sha256_16"]:
             tb = rec["bytes_per_launch"]
             traffic = round(tb / (elim_ms / n_launch / 1e3) / 1e9, 1)   # GB/s of HBM traffic
     roofline = dict({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -125,6 +125,12 @@ typedef struct {
                                   carried by one input only and one carried by the other only (neither in
                                   its factor table) computes 8 result rows per wave unit from 4 + 2 input
                                   rows per summed value */
+    int32_t order_finalists;   /* ordering 1 only: the candidate elimination orders (greedy min-degree and
+                                  min-fill with randomised tie breaks, ranked by their symbolic traffic
+                                  before chains are merged) of which this many first ones are built in full
+                                  and scored by the bytes the kernels issue per bitstring plus 8 KiB per
+                                  launch; the lowest score is kept.  0 = 12; 1 = the first order as ranked;
+                                  at most 64 */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;

@@ -449,6 +449,10 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
     if (opts.tree_exec < 0 || opts.tree_exec > 2) { *err = "tree_exec must be 0..2"; return QGM_E_INVALID; }
     if (opts.no_tile < 0 || opts.no_tile > 1) { *err = "no_tile must be 0 or 1"; return QGM_E_INVALID; }
+    if (opts.order_finalists < 0 || opts.order_finalists > kTreeMaxFinalists) {
+        *err = "order_finalists must be in [0, 64]";
+        return QGM_E_INVALID;
+    }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }
@@ -597,34 +601,6 @@ static void json_factor(std::ostringstream& o, const TFactor& f) {
     o << "]";
 }
 
-// Row loads and stores one wave unit of a bucket issues (64 lanes x 8 bytes
-// each): the distinct input rows (an input is read once for the unit rows
-// and summed values it does not vary along), the constant 1 for each input
-// slot beyond the bucket's own, the distinct factor-table entries, and the
-// unit's result rows.
-static int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
-    if (st.table_leaf) return 0;
-    if (st.tile)   // 4 + 2 (+ 1) input rows and a table row per summed value
-        return (int64_t(4 + 2 + 1 + (st.tile == 2 ? 1 : 0)) << st.kg) + st.unit_rows;
-    const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));
-    const int r = int(st.out_axes.size());
-    auto count_in = [&](const std::vector<int>& ax, int lo, int hi, const std::vector<int>& from) {
-        int n = 0;
-        for (int j = lo; j < hi && j < int(from.size()); ++j)
-            if (std::find(ax.begin(), ax.end(), from[j]) != ax.end()) ++n;
-        return n;
-    };
-    int64_t n = 0;
-    for (int tid : st.in_tensors) {
-        const std::vector<int>& ax = t.tensor_axes[tid];
-        n += int64_t(1) << (count_in(ax, 0, std::min(ob_bits, r), st.out_axes) + count_in(ax, 0, st.kg, st.vars));
-    }
-    const int cls = launch_inputs(t.level_max_in[st.level]);
-    n += cls - int(st.in_tensors.size());
-    n += int64_t(1) << (count_in(st.gvars, 0, std::min(ob_bits, r), st.out_axes) + st.kg);
-    return n + st.unit_rows;
-}
-
 static std::string tree_json(const Plan& p, int detail) {
     const TreePlan& t = p.tree;
     std::ostringstream o;
@@ -637,10 +613,10 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
       << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
       << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start << ",\"tail_lds_rows\":" << t.tail_lds_rows
-      << ",\"level_launches\":" << (std::max(t.tail_start - t.first_level, 0) + (t.tail_start < int(t.levels.size()) ? 1 : 0))
+      << ",\"level_launches\":" << tree_launches(t)
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
-      << ",\"orders_tried\":" << t.n_candidates << ",\"bytes_per_amp\":" << t.bytes_per_b
+      << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"bytes_per_amp\":" << t.bytes_per_b
       << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
       << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask
       << ",\"table_leaves\":" << t.n_table_leaves;

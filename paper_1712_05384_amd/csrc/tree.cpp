@@ -638,6 +638,9 @@ double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
     return b;
 }
 
+static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vector<std::pair<int, int>>& kept,
+                                  const std::vector<int>& best, TreePlan& t, std::string* err);
+
 qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t = TreePlan{};
     if (p.n_open != 0 && p.opts.tree_exec == 2) {
@@ -703,10 +706,10 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
                 adj[size_t(f.free[i]) * nF + f.free[j]] = 1;
                 adj[size_t(f.free[j]) * nF + f.free[i]] = 1;
             }
-    // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks
+    // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks, ranked by the
+    // symbolic cost (bytes before chain merging, a level weighed as 4 KiB per bitstring)
     const int restarts = nF > 1500 ? 1 : (nF > 600 ? 4 : 16);
-    std::vector<int> best;
-    double best_cost = std::numeric_limits<double>::infinity();
+    std::vector<std::pair<double, std::vector<int>>> cands;
     std::string last_why;
     for (int crit = 0; crit < 2; ++crit)
         for (int rs = 0; rs <= restarts; ++rs) {
@@ -721,11 +724,46 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
             SimOut r = simulate(p, m, ord, nullptr, nullptr);
             ++t.n_candidates;
             if (!r.ok) { last_why = r.why; continue; }
-            // a level costs about one launch: weigh it as 4 KiB per bitstring
-            const double cost = r.bytes + 4096.0 * r.levels;
-            if (cost < best_cost) { best_cost = cost; best = ord; }
+            cands.push_back({r.bytes + 4096.0 * r.levels, ord});
         }
-    if (best.empty() && nF > 0) { *err = "no elimination order fits the kernels: " + last_why; return QGM_E_UNSUPPORTED; }
+    if (cands.empty()) {
+        if (nF > 0) { *err = "no elimination order fits the kernels: " + last_why; return QGM_E_UNSUPPORTED; }
+        cands.push_back({0.0, {}});
+    }
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    // the first finalists are built in full (chains merged, leaves absorbed, tail chosen) and the plan
+    // whose kernels issue the fewest bytes per bitstring, a launch weighed as kTreeLaunchBytes, is kept:
+    // merging and absorption change the traffic of each order by different amounts
+    const int n_fin = p.opts.order_finalists > 0 ? p.opts.order_finalists : (nF > 600 ? 2 : kTreeOrderFinalists);
+    std::vector<std::vector<int>> tried;
+    double best_score = std::numeric_limits<double>::infinity();
+    TreePlan best_t;
+    qgm_status first_st = QGM_OK;
+    std::string first_err;
+    for (size_t i = 0; i < cands.size() && int(tried.size()) < n_fin; ++i) {
+        if (std::find(tried.begin(), tried.end(), cands[i].second) != tried.end()) continue;
+        tried.push_back(cands[i].second);
+        TreePlan tc = t;
+        std::string e;
+        const qgm_status st = tree_from_order(p, m, kept, cands[i].second, tc, &e);
+        if (st != QGM_OK) {
+            if (first_st == QGM_OK) { first_st = st; first_err = e; }
+            continue;
+        }
+        const double score = tree_issued_bytes_per_b(tc) + kTreeLaunchBytes * tree_launches(tc);
+        if (score < best_score) { best_score = score; best_t = std::move(tc); }
+    }
+    if (best_score == std::numeric_limits<double>::infinity()) { *err = first_err; return first_st; }
+    t = std::move(best_t);
+    t.n_built = int(tried.size());
+    return QGM_OK;
+}
+
+// The plan of one elimination order: buckets, chains merged, leaves absorbed,
+// levels, arena rows, wave tasks, the tail and the factor-table layout.
+static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vector<std::pair<int, int>>& kept,
+                                  const std::vector<int>& best, TreePlan& t, std::string* err) {
     std::vector<RStep> rs;
     std::vector<RTensor> rt;
     SimOut r = simulate(p, m, best, &rs, &rt);
@@ -883,6 +921,44 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         return QGM_E_UNSUPPORTED;
     }
     return QGM_OK;
+}
+
+// Row loads and stores one wave unit of a bucket issues (64 lanes x 8 bytes
+// each): the distinct input rows (an input is read once for the unit rows
+// and summed values it does not vary along), the constant 1 for each input
+// slot beyond the bucket's own, the distinct factor-table entries, and the
+// unit's result rows.
+int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
+    if (st.table_leaf) return 0;
+    if (st.tile)   // 4 + 2 (+ 1) input rows and a table row per summed value
+        return (int64_t(4 + 2 + 1 + (st.tile == 2 ? 1 : 0)) << st.kg) + st.unit_rows;
+    const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));
+    const int r = int(st.out_axes.size());
+    auto count_in = [&](const std::vector<int>& ax, int lo, int hi, const std::vector<int>& from) {
+        int n = 0;
+        for (int j = lo; j < hi && j < int(from.size()); ++j)
+            if (std::find(ax.begin(), ax.end(), from[j]) != ax.end()) ++n;
+        return n;
+    };
+    int64_t n = 0;
+    for (int tid : st.in_tensors) {
+        const std::vector<int>& ax = t.tensor_axes[tid];
+        n += int64_t(1) << (count_in(ax, 0, std::min(ob_bits, r), st.out_axes) + count_in(ax, 0, st.kg, st.vars));
+    }
+    const int cls = launch_inputs(t.level_max_in[st.level]);
+    n += cls - int(st.in_tensors.size());
+    n += int64_t(1) << (count_in(st.gvars, 0, std::min(ob_bits, r), st.out_axes) + st.kg);
+    return n + st.unit_rows;
+}
+
+double tree_issued_bytes_per_b(const TreePlan& t) {
+    double n = 0;
+    for (const TreeStep& st : t.steps) n += 8.0 * double(st.n_tasks()) * double(tree_unit_accesses(t, st));
+    return n;
+}
+
+int tree_launches(const TreePlan& t) {
+    return std::max(t.tail_start - t.first_level, 0) + (t.tail_start < int(t.levels.size()) ? 1 : 0);
 }
 
 }  // namespace qgm

@@ -57,6 +57,9 @@ constexpr int kTreeTailMaxLevels = 16;
 constexpr int kTreeTailMaxFinal = 64;    // rank-0 results the tail multiplies
 constexpr int kTreeTailGEntries = 2048;  // factor-table entries of the tail's buckets (copied to LDS)
 constexpr int kTreeOcBits = 3;      // a wave unit covers up to 2^kTreeOcBits consecutive result rows
+constexpr int kTreeOrderFinalists = 12;        // candidate orders built in full and scored by issued bytes
+constexpr int kTreeMaxFinalists = 64;          //   (plan option order_finalists: 0 = the default, at most this)
+constexpr double kTreeLaunchBytes = 8192.0;    // ... a launch weighed as this many bytes per bitstring
 constexpr int64_t kTreeMaxTasks = int64_t(1) << 22;   // (bucket, row chunk) records of a plan
 
 // Result rows of one wave unit of a bucket with k summed variables in a
@@ -191,6 +194,7 @@ struct TreePlan {
     int max_in = 0;
     int n_free = 0;
     int n_candidates = 0;                        // orders tried
+    int n_built = 0;                             // ... of which built in full and scored
     double bytes_per_b = 0;                      // algorithmic HBM bytes per bitstring
     double flops_per_b = 0;
 };
@@ -198,6 +202,13 @@ struct TreePlan {
 // Builds the bucket plan from the variables and gate records in `p`
 // (ordering 1; no open qubits, no slicing).
 qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err);
+
+// Row accesses (loads and stores of 64 lanes x 8 bytes) of one wave unit of a bucket.
+int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st);
+// Bytes the bucket kernels issue per bitstring (cache-served repeats included).
+double tree_issued_bytes_per_b(const TreePlan& t);
+// Kernel launches of one call: one per level before the tail, and the tail.
+int tree_launches(const TreePlan& t);
 
 // Per-bucket algorithmic bytes per batch entry: inputs read once, result written once.
 double tree_step_bytes(const TreePlan& t, const TreeStep& st);

@@ -106,7 +106,9 @@ def test_tree_clifford_probabilities_dyadic_36_qubits():
 
 def test_tree_c2_full_size_and_vertical_agreement():
     """5x5 depth 25, 1024 bitstrings: the bucket path against the 2^25 state
-    vector, and against the vertical path."""
+    vector, and against the vertical path; the plan of the first order by
+    symbolic cost (order_finalists = 1, which has a three-input tile bucket)
+    against the same state vector."""
     import paper_1712_05384_amd as Q
     c, bits = C.workload("c2_5x5_d25")
     _say("case tree c2_5x5_d25 B=1024")
@@ -117,6 +119,11 @@ def test_tree_c2_full_size_and_vertical_agreement():
     assert err <= TOL * 2 ** (-c.n / 2)
     vert = _amps(Q.plan(c), bits)
     assert np.abs(vert - got).max() <= TOL * 2 ** (-c.n / 2)
+    p1 = _tree(c, order_finalists=1)
+    assert any(bk["tile"] == 2 for bk in p1.info(1)["buckets"])
+    _say("case tree c2_5x5_d25 B=1024 order_finalists=1")
+    got1 = _amps(p1, bits)
+    assert np.abs(got1 - ref).max() <= TOL * 2 ** (-c.n / 2)
 
 
 def test_tree_c3_against_stored_oracle():
@@ -273,7 +280,7 @@ def test_tree_tail_many_phase_factors_60_qubits():
     n = 60
     g = _shifted(blk, 0) + [(C.H, 0, q, -1, -1) for q in range(12, n)] + [(C.T, 1, q, -1, -1) for q in range(12, n)]
     c = C.Circuit(1, n, np.array(g, dtype=np.int32))
-    p = _tree(c)
+    p = _tree(c, order_finalists=1)   # the first order's plan has tail levels
     info = p.info(0)
     assert info["n_phase"] > 64 and info["tail_levels"] > 0
     bits = C.random_bitstrings(n, 200, 11)

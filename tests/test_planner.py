@@ -275,17 +275,50 @@ def test_tree_plan_without_chain_merge(rows, cols, depth, seed):
 
 def test_chain_merge_shortens_the_tree():
     """Merged chains sum up to three variables per bucket: fewer levels, fewer
-    buckets and less traffic, the same elimination order."""
+    buckets and less traffic, the same elimination order (the first order by
+    symbolic cost, which merging does not change)."""
     for name in ("c2_5x5_d25", "c3_5x6_d30"):
         c, _ = C.workload(name)
-        a = Q.plan(c, ordering=1, chain_merge=False).info(0)
-        b = Q.plan(c, ordering=1).info(1)
+        a = Q.plan(c, ordering=1, chain_merge=False, order_finalists=1).info(0)
+        b = Q.plan(c, ordering=1, order_finalists=1).info(1)
         assert b["order"] == a["order"]
         assert b["n_levels"] < a["n_levels"] and b["n_buckets"] < a["n_buckets"]
         assert b["bytes_per_amp"] < a["bytes_per_amp"]
         assert max(len(s["vars"]) for s in b["buckets"]) <= 3
         for s in b["buckets"]:
             assert s["kg"] == len(s["vars"])
+
+
+def _issued_score(info):
+    return sum(b["issued_bytes_per_b"] for b in info["buckets"]) + 8192 * info["level_launches"]
+
+
+def test_order_finalists_scored_by_issued_bytes():
+    """The planner builds the first candidate orders in full and keeps the one
+    whose kernels issue the fewest bytes per bitstring (plus 8 KiB per launch):
+    never worse than the first order by symbolic cost (order_finalists = 1),
+    strictly better on the 5x5 depth-25 and depth-24 circuits, the same
+    amplitudes through the interpreter, and the option checked."""
+    for name, better in (("c2_5x5_d25", True), ("c5_5x5_d24", True), ("c5_4x5_d20", False), ("c3_5x6_d30", False)):
+        c, _ = C.workload(name)
+        one = Q.plan(c, ordering=1, order_finalists=1).info(1)
+        dflt = Q.plan(c, ordering=1).info(1)
+        assert one["orders_built"] == 1 and 1 < dflt["orders_built"] <= 12 <= dflt["orders_tried"]
+        assert _issued_score(dflt) <= _issued_score(one)
+        if better:
+            assert _issued_score(dflt) < 0.9 * _issued_score(one)
+            assert dflt["order"] != one["order"]
+    for seed, (rows, cols, depth) in enumerate([(3, 3, 12), (2, 4, 16), (3, 4, 10)]):
+        c = C.random_grid_circuit(rows, cols, depth, 40 + seed)
+        bits = C.random_bitstrings(c.n, 24, seed)
+        a = _check_tree(c, bits, order_finalists=1)
+        b = _check_tree(c, bits, order_finalists=64)
+        assert _issued_score(b) <= _issued_score(a)
+        assert b["orders_built"] <= b["orders_tried"]
+    c = C.random_grid_circuit(2, 2, 4, 1)
+    for bad in (-1, 65):
+        with pytest.raises(Exception):
+            Q.plan(c, ordering=1, order_finalists=bad)
 
 
 def test_tree_exec_modes_and_persistent_workspace():
@@ -409,7 +442,7 @@ def test_tail_plan_with_many_phase_factors_closed_form():
     g = [tuple(int(v) for v in r) for r in blk.gates] + [(C.H, 0, q, -1, -1) for q in range(12, n)] + \
         [(C.T, 1, q, -1, -1) for q in range(12, n)]
     c = C.Circuit(1, n, np.array(g, dtype=np.int32))
-    info = Q.plan(c, ordering=1).info(1)
+    info = Q.plan(c, ordering=1, order_finalists=1).info(1)   # the first order's plan has tail levels
     assert info["n_phase"] > 64 and info["tail_levels"] > 0
     bits = C.random_bitstrings(n, 12, 11)
     ref = oracle.sv_state(12, blk.gates, None)[(bits & np.uint64(0xFFF)).astype(np.int64)]
@@ -479,14 +512,21 @@ def test_bucket_workspace_uses_power_of_two_pitch():
                                                   (4, 4, 24, 1), (5, 5, 25, 201)])
 def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     """Plans with tile units (inputs reordered, tile bits lowest; the 5x5 depth-25
-    plan has a three-input tile) and without, run by the interpreter, against
-    the state vector."""
+    plan of the first order by symbolic cost has a three-input tile) and without,
+    for the chosen order and the first one, run by the interpreter, against the
+    state vector."""
     import paper_1712_05384_amd as Q
     from tree_interp import run_tree_plan
     c = C.random_grid_circuit(rows, cols, depth, seed)
-    assert any(bk["tile"] for bk in Q.plan(c, ordering=1).info(1)["buckets"])
+    kinds = set()
+    for fin in (0, 1):
+        kinds |= {bk["tile"] for bk in Q.plan(c, ordering=1, order_finalists=fin).info(1)["buckets"]}
+    assert kinds & {1, 2}
+    if (rows, cols, depth, seed) == (5, 5, 25, 201):
+        assert 2 in kinds
     bits = C.random_bitstrings(c.n, 4, seed)
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
-    for tile in (True, False):
-        got = run_tree_plan(Q.plan(c, ordering=1, tile=tile).info(1), None, bits)
-        assert np.abs(got - ref).max() < 1e-12
+    for fin in (0, 1):
+        for tile in (True, False):
+            got = run_tree_plan(Q.plan(c, ordering=1, tile=tile, order_finalists=fin).info(1), None, bits)
+            assert np.abs(got - ref).max() < 1e-12

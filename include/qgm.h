@@ -129,8 +129,12 @@ typedef struct {
                                   min-fill with randomised tie breaks, ranked by their symbolic traffic
                                   before chains are merged) of which this many first ones are built in full
                                   and scored by the bytes the kernels issue per bitstring plus 8 KiB per
-                                  launch; the lowest score is kept.  0 = 12; 1 = the first order as ranked;
-                                  at most 64 */
+                                  launch; the lowest score is kept.  0 = 64 (2 beyond 600 free variables);
+                                  1 = the first order as ranked; at most 64 */
+    int32_t order_restarts;    /* ordering 1 only: randomised tie-break restarts of each greedy criterion
+                                  (candidates = 2 x (restarts + 1)).  0 = 64 up to 600 free variables, 4 up
+                                  to 1500, 1 beyond; at most 1024.  More restarts find plans with fewer
+                                  bytes on larger circuits at a plan time of up to about 0.2 s at 64 */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;

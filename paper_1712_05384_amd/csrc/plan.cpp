@@ -453,6 +453,10 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         *err = "order_finalists must be in [0, 64]";
         return QGM_E_INVALID;
     }
+    if (opts.order_restarts < 0 || opts.order_restarts > kTreeMaxRestarts) {
+        *err = "order_restarts must be in [0, 1024]";
+        return QGM_E_INVALID;
+    }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }

@@ -708,7 +708,8 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
             }
     // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks, ranked by the
     // symbolic cost (bytes before chain merging, a level weighed as 4 KiB per bitstring)
-    const int restarts = nF > 1500 ? 1 : (nF > 600 ? 4 : 16);
+    const int restarts = p.opts.order_restarts > 0 ? p.opts.order_restarts
+                                                   : (nF > 1500 ? 1 : (nF > 600 ? 4 : kTreeOrderRestarts));
     std::vector<std::pair<double, std::vector<int>>> cands;
     std::string last_why;
     for (int crit = 0; crit < 2; ++crit)

@@ -57,8 +57,10 @@ constexpr int kTreeTailMaxLevels = 16;
 constexpr int kTreeTailMaxFinal = 64;    // rank-0 results the tail multiplies
 constexpr int kTreeTailGEntries = 2048;  // factor-table entries of the tail's buckets (copied to LDS)
 constexpr int kTreeOcBits = 3;      // a wave unit covers up to 2^kTreeOcBits consecutive result rows
-constexpr int kTreeOrderFinalists = 12;        // candidate orders built in full and scored by issued bytes
+constexpr int kTreeOrderFinalists = 64;        // candidate orders built in full and scored by issued bytes
 constexpr int kTreeMaxFinalists = 64;          //   (plan option order_finalists: 0 = the default, at most this)
+constexpr int kTreeOrderRestarts = 64;         // randomised restarts per greedy criterion up to 600 free variables
+constexpr int kTreeMaxRestarts = 1024;         //   (plan option order_restarts: 0 = the default, at most this)
 constexpr double kTreeLaunchBytes = 8192.0;    // ... a launch weighed as this many bytes per bitstring
 constexpr int64_t kTreeMaxTasks = int64_t(1) << 22;   // (bucket, row chunk) records of a plan
 

@@ -42,11 +42,20 @@ def test_app_d_tree():
 
 
 def test_tree_c1_full_batch():
+    """4x4 depth 16, 64 bitstrings, with the chosen plan and with the first order's
+    plan among 16 restarts per criterion (order_restarts = 16, order_finalists = 1),
+    whose tail runs a tile bucket from LDS."""
     c, bits = C.workload("c1_4x4_d16")
     _say("case tree c1_4x4_d16 B=64")
     got = _amps(_tree(c), bits)
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
+    p1 = _tree(c, order_restarts=16, order_finalists=1)
+    info = p1.info(1)
+    assert any(bk["tile"] and bk["level"] >= info["tail_start"] for bk in info["buckets"])
+    _say("case tree c1_4x4_d16 B=64 order_finalists=1")
+    got1 = _amps(p1, bits)
+    assert np.abs(got1 - ref).max() <= TOL * 2 ** (-c.n / 2)
 
 
 @pytest.mark.parametrize("B", [1, 5, 63, 64, 65, 130])
@@ -107,7 +116,7 @@ def test_tree_clifford_probabilities_dyadic_36_qubits():
 def test_tree_c2_full_size_and_vertical_agreement():
     """5x5 depth 25, 1024 bitstrings: the bucket path against the 2^25 state
     vector, and against the vertical path; the plan of the first order by
-    symbolic cost (order_finalists = 1, which has a three-input tile bucket)
+    symbolic cost among 16 restarts per criterion (which has a three-input tile)
     against the same state vector."""
     import paper_1712_05384_amd as Q
     c, bits = C.workload("c2_5x5_d25")
@@ -119,7 +128,7 @@ def test_tree_c2_full_size_and_vertical_agreement():
     assert err <= TOL * 2 ** (-c.n / 2)
     vert = _amps(Q.plan(c), bits)
     assert np.abs(vert - got).max() <= TOL * 2 ** (-c.n / 2)
-    p1 = _tree(c, order_finalists=1)
+    p1 = _tree(c, order_restarts=16, order_finalists=1)
     assert any(bk["tile"] == 2 for bk in p1.info(1)["buckets"])
     _say("case tree c2_5x5_d25 B=1024 order_finalists=1")
     got1 = _amps(p1, bits)
@@ -280,7 +289,7 @@ def test_tree_tail_many_phase_factors_60_qubits():
     n = 60
     g = _shifted(blk, 0) + [(C.H, 0, q, -1, -1) for q in range(12, n)] + [(C.T, 1, q, -1, -1) for q in range(12, n)]
     c = C.Circuit(1, n, np.array(g, dtype=np.int32))
-    p = _tree(c, order_finalists=1)   # the first order's plan has tail levels
+    p = _tree(c, order_restarts=16, order_finalists=1)   # this plan has tail levels
     info = p.info(0)
     assert info["n_phase"] > 64 and info["tail_levels"] > 0
     bits = C.random_bitstrings(n, 200, 11)

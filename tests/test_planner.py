@@ -303,7 +303,7 @@ def test_order_finalists_scored_by_issued_bytes():
         c, _ = C.workload(name)
         one = Q.plan(c, ordering=1, order_finalists=1).info(1)
         dflt = Q.plan(c, ordering=1).info(1)
-        assert one["orders_built"] == 1 and 1 < dflt["orders_built"] <= 12 <= dflt["orders_tried"]
+        assert one["orders_built"] == 1 and 1 < dflt["orders_built"] <= 64 and dflt["orders_tried"] == 2 * 65
         assert _issued_score(dflt) <= _issued_score(one)
         if better:
             assert _issued_score(dflt) < 0.9 * _issued_score(one)
@@ -319,6 +319,13 @@ def test_order_finalists_scored_by_issued_bytes():
     for bad in (-1, 65):
         with pytest.raises(Exception):
             Q.plan(c, ordering=1, order_finalists=bad)
+    for bad in (-1, 1025):
+        with pytest.raises(Exception):
+            Q.plan(c, ordering=1, order_restarts=bad)
+    c, _ = C.workload("c3_5x6_d30")
+    few = Q.plan(c, ordering=1, order_restarts=4).info(0)
+    assert few["orders_tried"] == 2 * 5 and few["orders_built"] == 10
+    assert _issued_score(Q.plan(c, ordering=1).info(1)) <= _issued_score(Q.plan(c, ordering=1, order_restarts=4).info(1))
 
 
 def test_tree_exec_modes_and_persistent_workspace():
@@ -442,7 +449,7 @@ def test_tail_plan_with_many_phase_factors_closed_form():
     g = [tuple(int(v) for v in r) for r in blk.gates] + [(C.H, 0, q, -1, -1) for q in range(12, n)] + \
         [(C.T, 1, q, -1, -1) for q in range(12, n)]
     c = C.Circuit(1, n, np.array(g, dtype=np.int32))
-    info = Q.plan(c, ordering=1, order_finalists=1).info(1)   # the first order's plan has tail levels
+    info = Q.plan(c, ordering=1, order_restarts=16, order_finalists=1).info(1)   # this plan has tail levels
     assert info["n_phase"] > 64 and info["tail_levels"] > 0
     bits = C.random_bitstrings(n, 12, 11)
     ref = oracle.sv_state(12, blk.gates, None)[(bits & np.uint64(0xFFF)).astype(np.int64)]
@@ -482,11 +489,11 @@ def test_tile_buckets_planned_and_interpreted():
 
 
 def test_tile_in_tail_and_option_validation():
-    """4x4 depth 16: a tile bucket runs in the tail (tile units reading and writing
-    the tail's LDS); an invalid no_tile value is rejected."""
+    """4x4 depth 16, the first order's plan: a tile bucket runs in the tail (tile
+    units reading and writing the tail's LDS); an invalid no_tile value is rejected."""
     import paper_1712_05384_amd as Q
     c, _ = C.workload("c1_4x4_d16")
-    info = Q.plan(c, ordering=1).info(1)
+    info = Q.plan(c, ordering=1, order_restarts=16, order_finalists=1).info(1)
     assert any(bk["tile"] and bk["level"] >= info["tail_start"] for bk in info["buckets"])
     cs, keep = Q.api._circuit_struct(c.rows, c.cols, c.gates, 0)
     opts = N.QgmPlanOpts()
@@ -512,7 +519,8 @@ def test_bucket_workspace_uses_power_of_two_pitch():
                                                   (4, 4, 24, 1), (5, 5, 25, 201)])
 def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     """Plans with tile units (inputs reordered, tile bits lowest; the 5x5 depth-25
-    plan of the first order by symbolic cost has a three-input tile) and without,
+    plan of the first order by symbolic cost among 16 restarts per criterion has a
+    three-input tile) and without,
     for the chosen order and the first one, run by the interpreter, against the
     state vector."""
     import paper_1712_05384_amd as Q
@@ -520,7 +528,7 @@ def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     c = C.random_grid_circuit(rows, cols, depth, seed)
     kinds = set()
     for fin in (0, 1):
-        kinds |= {bk["tile"] for bk in Q.plan(c, ordering=1, order_finalists=fin).info(1)["buckets"]}
+        kinds |= {bk["tile"] for bk in Q.plan(c, ordering=1, order_restarts=16 * fin, order_finalists=fin).info(1)["buckets"]}
     assert kinds & {1, 2}
     if (rows, cols, depth, seed) == (5, 5, 25, 201):
         assert 2 in kinds
@@ -528,5 +536,5 @@ def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     for fin in (0, 1):
         for tile in (True, False):
-            got = run_tree_plan(Q.plan(c, ordering=1, tile=tile, order_finalists=fin).info(1), None, bits)
+            got = run_tree_plan(Q.plan(c, ordering=1, tile=tile, order_restarts=16 * fin, order_finalists=fin).info(1), None, bits)
             assert np.abs(got - ref).max() < 1e-12

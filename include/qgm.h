@@ -135,6 +135,9 @@ typedef struct {
                                   (candidates = 2 x (restarts + 1)).  0 = 64 up to 600 free variables, 4 up
                                   to 1500, 1 beyond; at most 1024.  More restarts find plans with fewer
                                   bytes on larger circuits at a plan time of up to about 0.2 s at 64 */
+    int32_t order_pick;        /* ordering 1 only: keep the finalist of this rank by score (0 = the lowest
+                                  score); for callers that time several finalists on their own batch.
+                                  QGM_E_INVALID if fewer finalists build; at most 63 */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;

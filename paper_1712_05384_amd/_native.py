@@ -33,7 +33,8 @@ class QgmPlanOpts(ctypes.Structure):
                 ("min_sliced_vars", ctypes.c_int32), ("out_c128", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("no_chain_merge", ctypes.c_int32),
                 ("tree_exec", ctypes.c_int32), ("no_tile", ctypes.c_int32),
-                ("order_finalists", ctypes.c_int32), ("order_restarts", ctypes.c_int32)]
+                ("order_finalists", ctypes.c_int32), ("order_restarts", ctypes.c_int32),
+                ("order_pick", ctypes.c_int32)]
 
 
 class QgmError(RuntimeError):

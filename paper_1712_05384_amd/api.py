@@ -25,7 +25,7 @@ class Plan:
     def __init__(self, circuit, open_qubits=(), *, min_sliced_vars: int = 0, max_rank: int = 0,
                  out_c128: bool = False, kernel_policy: int = 0, checkpoint_every: int = 0, ordering: int = 0,
                  chain_merge: bool = True, tree_exec: int = 0, tile: bool = True, order_finalists: int = 0,
-                 order_restarts: int = 0):
+                 order_restarts: int = 0, order_pick: int = 0):
         L = N.lib()
         self._lib = L
         self._h = None
@@ -47,6 +47,7 @@ class Plan:
         opts.no_tile = 0 if tile else 1
         opts.order_finalists = int(order_finalists)
         opts.order_restarts = int(order_restarts)
+        opts.order_pick = int(order_pick)
         self.ordering = int(ordering)
         op = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         h = ctypes.c_void_p()

@@ -457,6 +457,10 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         *err = "order_restarts must be in [0, 1024]";
         return QGM_E_INVALID;
     }
+    if (opts.order_pick < 0 || opts.order_pick >= kTreeMaxFinalists) {
+        *err = "order_pick must be in [0, 63]";
+        return QGM_E_INVALID;
+    }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }
@@ -620,7 +624,7 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"level_launches\":" << tree_launches(t)
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
-      << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"bytes_per_amp\":" << t.bytes_per_b
+      << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"order_score\":" << t.order_score << ",\"bytes_per_amp\":" << t.bytes_per_b
       << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
       << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask
       << ",\"table_leaves\":" << t.n_table_leaves;

@@ -738,8 +738,7 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     // merging and absorption change the traffic of each order by different amounts
     const int n_fin = p.opts.order_finalists > 0 ? p.opts.order_finalists : (nF > 600 ? 2 : kTreeOrderFinalists);
     std::vector<std::vector<int>> tried;
-    double best_score = std::numeric_limits<double>::infinity();
-    TreePlan best_t;
+    std::vector<std::pair<double, size_t>> scored;   // (score, candidate) of the finalists that build
     qgm_status first_st = QGM_OK;
     std::string first_err;
     for (size_t i = 0; i < cands.size() && int(tried.size()) < n_fin; ++i) {
@@ -752,12 +751,24 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
             if (first_st == QGM_OK) { first_st = st; first_err = e; }
             continue;
         }
-        const double score = tree_issued_bytes_per_b(tc) + kTreeLaunchBytes * tree_launches(tc);
-        if (score < best_score) { best_score = score; best_t = std::move(tc); }
+        scored.push_back({tree_issued_bytes_per_b(tc) + kTreeLaunchBytes * tree_launches(tc), i});
     }
-    if (best_score == std::numeric_limits<double>::infinity()) { *err = first_err; return first_st; }
-    t = std::move(best_t);
-    t.n_built = int(tried.size());
+    if (scored.empty()) { *err = first_err; return first_st; }
+    std::stable_sort(scored.begin(), scored.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    // the lowest score, or the order_pick-th lowest (a caller timing the finalists)
+    if (p.opts.order_pick >= int(scored.size())) {
+        *err = "order_pick " + std::to_string(p.opts.order_pick) + " beyond the " + std::to_string(scored.size()) +
+               " finalists built";
+        return QGM_E_INVALID;
+    }
+    const size_t pick = scored[size_t(p.opts.order_pick)].second;
+    TreePlan tc = t;
+    const qgm_status st = tree_from_order(p, m, kept, cands[pick].second, tc, err);
+    if (st != QGM_OK) return st;
+    t = std::move(tc);
+    t.n_built = int(scored.size());
+    t.order_score = scored[size_t(p.opts.order_pick)].first;
     return QGM_OK;
 }
 

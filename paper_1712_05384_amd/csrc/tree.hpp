@@ -197,6 +197,7 @@ struct TreePlan {
     int n_free = 0;
     int n_candidates = 0;                        // orders tried
     int n_built = 0;                             // ... of which built in full and scored
+    double order_score = 0;                      // the kept plan's score (issued bytes + launches)
     double bytes_per_b = 0;                      // algorithmic HBM bytes per bitstring
     double flops_per_b = 0;
 };

@@ -322,6 +322,21 @@ def test_order_finalists_scored_by_issued_bytes():
     for bad in (-1, 1025):
         with pytest.raises(Exception):
             Q.plan(c, ordering=1, order_restarts=bad)
+    for bad in (-1, 64):
+        with pytest.raises(Exception):
+            Q.plan(c, ordering=1, order_pick=bad)
+    with pytest.raises(Exception):   # beyond the finalists that build
+        Q.plan(c, ordering=1, order_finalists=2, order_pick=5)
+    # order_pick keeps the finalist of that rank: scores rise with the rank, rank 0 is the default plan, and
+    # a lower-ranked plan still gives the state vector's amplitudes through the interpreter
+    c, _ = C.workload("c2_5x5_d25")
+    picks = [Q.plan(c, ordering=1, order_pick=k).info(1) for k in range(4)]
+    assert all(a["order_score"] <= b["order_score"] for a, b in zip(picks, picks[1:]))
+    assert picks[0]["order"] == Q.plan(c, ordering=1).info(1)["order"] and picks[1]["order"] != picks[0]["order"]
+    assert abs(picks[0]["order_score"] - _issued_score(picks[0])) < 1e-6 * picks[0]["order_score"]
+    c = C.random_grid_circuit(3, 4, 12, 44)
+    bits = C.random_bitstrings(c.n, 16, 44)
+    _check_tree(c, bits, order_pick=1)
     c, _ = C.workload("c3_5x6_d30")
     few = Q.plan(c, ordering=1, order_restarts=4).info(0)
     assert few["orders_tried"] == 2 * 5 and few["orders_built"] == 10

@@ -338,6 +338,8 @@ def test_order_finalists_scored_by_issued_bytes():
     bits = C.random_bitstrings(c.n, 16, 44)
     _check_tree(c, bits, order_pick=1)
     c, _ = C.workload("c3_5x6_d30")
+    again = [Q.plan(c, ordering=1).info(1) for _ in range(2)]   # seeded restarts, stable ranking: one plan
+    assert again[0]["order"] == again[1]["order"] and again[0]["order_score"] == again[1]["order_score"]
     few = Q.plan(c, ordering=1, order_restarts=4).info(0)
     assert few["orders_tried"] == 2 * 5 and few["orders_built"] == 10
     assert _issued_score(Q.plan(c, ordering=1).info(1)) <= _issued_score(Q.plan(c, ordering=1, order_restarts=4).info(1))

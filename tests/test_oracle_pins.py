@@ -176,6 +176,77 @@ def test_gradient_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (s, a, b, part, fd, an)
 
 
+def _shared_and_diagonal_slot_circuit(seed):
+    """A random circuit whose T gates become diagonal value-slot gates (kind UD,
+    only the diagonal of the slot is read) and whose non-diagonal gates become
+    general value-slot gates (kind U), with two UD gates reading one slot and two
+    U gates reading one slot."""
+    base = C.random_grid_circuit(2, 3, 10, seed)
+    gates = base.gates.copy()
+    rng = np.random.default_rng(seed)
+    vals = []
+    first_ud = first_u = -1
+    for i in range(len(gates)):
+        kind = gates[i, 0]
+        if kind == C.CZ:
+            continue
+        if kind == C.T:
+            gates[i, 0] = C.UD
+            if first_ud >= 0 and (gates[:i, 4] == first_ud).sum() == 1:
+                gates[i, 4] = first_ud          # the second UD gate reuses the first one's slot
+                continue
+            gates[i, 4] = len(vals)
+            if first_ud < 0:
+                first_ud = len(vals)
+            # a full 2x2 value: the off-diagonal entries are never read by a UD gate
+            vals.append(np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 2))) + 0.3 * np.array([[0, 1], [1, 0]]))
+        else:
+            gates[i, 0] = C.U
+            if first_u >= 0 and (gates[:i, 4] == first_u).sum() == 1:
+                gates[i, 4] = first_u           # the second U gate reuses the first one's slot
+                continue
+            gates[i, 4] = len(vals)
+            if first_u < 0:
+                first_u = len(vals)
+            z = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+            q, _ = np.linalg.qr(z)
+            vals.append(q)
+    c = C.Circuit(base.rows, base.cols, gates, np.array(vals, dtype=np.complex128), base.name + "_slots")
+    return c, first_ud, first_u
+
+
+def test_gradient_finite_differences_diagonal_and_shared_slots():
+    """Finite differences of L = sum log p through the state vector alone pin the
+    two slot rules of the gradient: a slot read by two gates gets the sum of both
+    gates' gradients (perturbing the slot moves both), and a diagonal slot gate
+    reads only the diagonal, so its off-diagonal entries have gradient 0 (their
+    perturbation leaves L unchanged).  Appendix B, Eq. (cee) gives the loss."""
+    c, s_ud, s_u = _shared_and_diagonal_slot_circuit(52)
+    assert s_ud >= 0 and s_u >= 0
+    assert (c.gates[:, 4] == s_ud).sum() == 2 and (c.gates[:, 4] == s_u).sum() == 2
+    bits = C.random_bitstrings(c.n, 12, 52)
+    _, grad = oracle.sv_log_prob_gradient(c.n, c.gates, c.gate_vals, bits)
+    h = 1e-6
+    ud_slots = {int(r[4]) for r in c.gates if r[0] == C.UD}
+    for s in range(c.n_slots):
+        for a in range(2):
+            for b in range(2):
+                for part, unit in (("re", 1.0), ("im", 1j)):
+                    vp = c.gate_vals.copy(); vp[s, a, b] += h * unit
+                    vm = c.gate_vals.copy(); vm[s, a, b] -= h * unit
+                    fd = (_loss(c, bits, vp) - _loss(c, bits, vm)) / (2 * h)
+                    an = grad[s, a, b].real if part == "re" else grad[s, a, b].imag
+                    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (s, a, b, part, fd, an)
+                    if s in ud_slots and a != b:
+                        assert fd == 0.0 and an == 0.0
+    # the shared slots' gradients are not those of either gate alone
+    _, per_gate = oracle.sv_vjp(c.n, c.gates, c.gate_vals, bits,
+                                2.0 / np.conj(oracle.sv_amplitudes(c.n, c.gates, c.gate_vals, bits)))
+    two = np.flatnonzero(c.gates[:, 4] == s_u)
+    assert np.abs(grad[s_u] - per_gate[two[0]]).max() > 1e-3
+    assert np.abs(grad[s_u] - per_gate[two[1]]).max() > 1e-3
+
+
 def test_gradient_scale_identity():
     """A is linear in each gate matrix, so L(lambda U_g) = L + 2m log|lambda| and
     sum_ab U_g[a,b] conj(G_g[a,b]) = 2m exactly, for every gate."""

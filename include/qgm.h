@@ -118,8 +118,9 @@ typedef struct {
                                       starts when the tasks making its inputs have signalled completion; the
                                       workspace then keeps every result at its own rows.  Calls in this mode
                                       must not run concurrently on one device (each needs the whole GPU at
-                                      once); a launch that cannot proceed gives up after a bounded wait and
-                                      writes NaN amplitudes. */
+                                      once); a launch that cannot proceed gives up after a bounded wait,
+                                      writes NaN amplitudes and records the failure in the plan
+                                      (qgm_plan_check returns QGM_E_INTERNAL). */
     int32_t no_tile;           /* ordering 1 only: 1 = every bucket uses the general wave unit; 0 = a
                                   two-input bucket summing two or more variables whose result has two bits
                                   carried by one input only and one carried by the other only (neither in
@@ -138,6 +139,10 @@ typedef struct {
     int32_t order_pick;        /* ordering 1 only: keep the finalist of this rank by score (0 = the lowest
                                   score); for callers that time several finalists on their own batch.
                                   QGM_E_INVALID if fewer finalists build; at most 63 */
+    int32_t persist_spin;      /* tree_exec 2 only: polls after which a wait of the persistent launch gives up
+                                  (0 = 2^20).  A launch that gives up writes NaN for the amplitudes it could
+                                  not finish and records the failure in the plan, which qgm_plan_check reports;
+                                  a small value forces that path (for tests of the error report) */
 } qgm_plan_opts;
 
 typedef struct qgm_plan_s qgm_plan_t;
@@ -248,8 +253,9 @@ qgm_status qgm_plan_timings(qgm_plan_t* plan, double* ms, int64_t* n_calls);
  * are host arrays of length n_circ; the pointers they hold follow the rules of
  * qgm_amplitudes (workspaces must not be shared between circuits).  Creation
  * uploads missing plan tables first and captures on private streams; it does
- * not launch anything.  Branches that run as one persistent launch (tree_exec)
- * are ordered one after another; the other branches stay concurrent.  A graph
+ * not launch anything.  When a branch runs as one persistent launch (tree_exec
+ * 2), which needs the whole GPU at once, every branch runs after the previous
+ * one; otherwise the branches are concurrent.  A graph
  * must not outlive its plans or buffers. */
 typedef struct qgm_graph_s qgm_graph_t;
 qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void* const* gate_vals,
@@ -303,11 +309,33 @@ qgm_status qgm_expectation_circuit(const qgm_circuit* circuit, int32_t n_ops, co
  * (device int64) the first j whose FP64 inclusive cumulative sum of p exceeds
  * u[i] times the total (B - 1 if none).  Errors as for qgm_xeb (m < 0 is
  * QGM_E_INVALID; m = 0 only scans). */
+/* qgm_prob_sums (Sec. III.A, sets of amplitudes): for each of the B
+ * bitstrings of an amplitude array laid out as qgm_amplitudes writes it,
+ * amps[b][o] for o < 2^n_open (complex64 when c128 = 0, else complex128),
+ * writes out[b] = sum_o |amps[b][o]|^2 computed in FP64, summed in a fixed
+ * order (the same input gives the same bits).  It is the normalisation check
+ * of a set: the sum is at most 1 (the probability that the fixed qubits read
+ * x_b), and exactly 1 with every qubit open.  out: device doubles [B].  No
+ * workspace; one launch on `stream`.  Errors: QGM_E_INVALID for B < 0, n_open
+ * outside 0..40 or a NULL pointer (B = 0 does nothing); QGM_E_UNSUPPORTED for
+ * B >= 2^31. */
+qgm_status qgm_prob_sums(const void* amps, int32_t c128, int64_t B, int32_t n_open, double* out, void* stream);
+
 qgm_status qgm_xeb_workspace_bytes(int64_t B, uint64_t* bytes);
 qgm_status qgm_xeb(const void* amps, int32_t c128, int64_t B, int32_t n_qubits, double* out, void* workspace,
                    uint64_t ws_bytes, void* stream);
 qgm_status qgm_sample_set(const void* amps, int32_t c128, int64_t B, const double* u, int64_t m, int64_t* idx,
                           void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Synchronises `stream`, then reports whether a persistent launch of this
+ * plan (tree_exec 2) on the current device gave up since the last check: its
+ * bounded wait for another wave ran out (the GPU was shared, or the grid could
+ * not be resident at once) and it wrote NaN for the amplitudes it could not
+ * finish.  The record is cleared by the check.  Returns QGM_E_HIP for a pending
+ * HIP error, QGM_E_INTERNAL for a launch that gave up, QGM_E_INVALID for a
+ * NULL plan, else QGM_OK (also for plans never run on this device).  Call it
+ * after qgm_amplitudes or qgm_graph_launch when the plan runs persistently. */
+qgm_status qgm_plan_check(qgm_plan_t* plan, void* stream);
 
 /* Destroys a plan and frees its device tables (NULL is ignored). */
 void qgm_plan_destroy(qgm_plan_t* plan);

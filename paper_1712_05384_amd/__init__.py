@@ -10,5 +10,5 @@ include/qgm.h.
 Importing the package does not load the native library; the first plan()
 does, and raises if libqgm.so has not been built.
 """
-from .api import Plan, Graph, plan, amplitudes, amplitudes_autograd, sync_check, xeb, sample_from_set, expectation_circuit, expectation  # noqa: F401
+from .api import Plan, Graph, plan, amplitudes, amplitudes_autograd, sync_check, xeb, sample_from_set, prob_sums, expectation_circuit, expectation  # noqa: F401
 from . import circuits  # noqa: F401

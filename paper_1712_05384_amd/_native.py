@@ -15,7 +15,8 @@ STATUS_NAMES = {0: "QGM_OK", -1: "QGM_E_INVALID", -2: "QGM_E_UNSUPPORTED", -3: "
 EXPORTED = ("qgm_default_opts", "qgm_plan", "qgm_plan_info", "qgm_workspace_bytes", "qgm_amplitudes",
             "qgm_backward_workspace_bytes", "qgm_backward", "qgm_graph_create", "qgm_graph_launch",
             "qgm_graph_destroy", "qgm_autotune", "qgm_plan_set_timing", "qgm_plan_timings", "qgm_plan_destroy", "qgm_last_error",
-            "qgm_sync_check", "qgm_xeb_workspace_bytes", "qgm_xeb", "qgm_sample_set", "qgm_expectation_circuit")
+            "qgm_sync_check", "qgm_xeb_workspace_bytes", "qgm_xeb", "qgm_sample_set", "qgm_expectation_circuit",
+            "qgm_prob_sums", "qgm_plan_check")
 
 
 class QgmGate(ctypes.Structure):
@@ -34,7 +35,7 @@ class QgmPlanOpts(ctypes.Structure):
                 ("checkpoint_every", ctypes.c_int32), ("no_chain_merge", ctypes.c_int32),
                 ("tree_exec", ctypes.c_int32), ("no_tile", ctypes.c_int32),
                 ("order_finalists", ctypes.c_int32), ("order_restarts", ctypes.c_int32),
-                ("order_pick", ctypes.c_int32)]
+                ("order_pick", ctypes.c_int32), ("persist_spin", ctypes.c_int32)]
 
 
 class QgmError(RuntimeError):
@@ -81,13 +82,16 @@ def lib():
         L.qgm_xeb_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
         L.qgm_xeb.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_uint64, P]
         L.qgm_sample_set.argtypes = [P, ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int64, P, P, ctypes.c_uint64, P]
+        L.qgm_prob_sums.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P]
+        L.qgm_plan_check.argtypes = [P, P]
         I32P = ctypes.POINTER(ctypes.c_int32)
         L.qgm_expectation_circuit.argtypes = [ctypes.POINTER(QgmCircuit), ctypes.c_int32, I32P, I32P,
                                               ctypes.POINTER(QgmGate), ctypes.c_int32, I32P]
         for f in (L.qgm_plan, L.qgm_plan_info, L.qgm_workspace_bytes, L.qgm_amplitudes, L.qgm_sync_check,
                   L.qgm_plan_set_timing, L.qgm_plan_timings, L.qgm_backward_workspace_bytes, L.qgm_backward,
                   L.qgm_graph_create, L.qgm_graph_launch, L.qgm_autotune, L.qgm_xeb_workspace_bytes, L.qgm_xeb,
-                  L.qgm_sample_set, L.qgm_expectation_circuit):
+                  L.qgm_sample_set, L.qgm_expectation_circuit, L.qgm_prob_sums,
+                  L.qgm_plan_check):
             f.restype = ctypes.c_int
         _lib = L
     return _lib

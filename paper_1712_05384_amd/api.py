@@ -25,7 +25,7 @@ class Plan:
     def __init__(self, circuit, open_qubits=(), *, min_sliced_vars: int = 0, max_rank: int = 0,
                  out_c128: bool = False, kernel_policy: int = 0, checkpoint_every: int = 0, ordering: int = 0,
                  chain_merge: bool = True, tree_exec: int = 0, tile: bool = True, order_finalists: int = 0,
-                 order_restarts: int = 0, order_pick: int = 0):
+                 order_restarts: int = 0, order_pick: int = 0, persist_spin: int = 0):
         L = N.lib()
         self._lib = L
         self._h = None
@@ -48,6 +48,7 @@ class Plan:
         opts.order_finalists = int(order_finalists)
         opts.order_restarts = int(order_restarts)
         opts.order_pick = int(order_pick)
+        opts.persist_spin = int(persist_spin)
         self.ordering = int(ordering)
         op = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         h = ctypes.c_void_p()
@@ -108,6 +109,14 @@ class Plan:
                                          out.data_ptr(), workspace.data_ptr(), workspace.numel(),
                                          ctypes.c_void_p(stream.cuda_stream)))
         return out
+
+    def check(self, stream=None) -> None:
+        """qgm_plan_check: synchronise the stream and raise QgmError if a
+        persistent launch of this plan gave up since the last check."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        N.check(self._lib.qgm_plan_check(self._h, ctypes.c_void_p(stream.cuda_stream)))
 
     def backward_workspace_bytes(self, B: int) -> int:
         out = ctypes.c_uint64()
@@ -288,6 +297,29 @@ def xeb(amps, n_qubits: int, *, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream(a.device)
     N.check(L.qgm_xeb(a.data_ptr(), 1 if a.dtype == torch.complex128 else 0, B, int(n_qubits), out.data_ptr(),
                       ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+    return out
+
+
+def prob_sums(amps, *, out=None, stream=None):
+    """FP64 sum over each row of |amps|^2 (qgm_prob_sums, Sec. III.A): amps is
+    the [B, 2^n_open] complex64/complex128 device tensor of a set of amplitudes
+    per bitstring; returns float64 [B] (each at most 1; exactly 1 with every
+    qubit open)."""
+    import torch
+    if amps.dim() != 2 or amps.dtype not in (torch.complex64, torch.complex128) or not amps.is_cuda:
+        raise TypeError("amps must be a [B, 2^n_open] complex64 or complex128 CUDA tensor")
+    B, n_out = int(amps.shape[0]), int(amps.shape[1])
+    n_open = n_out.bit_length() - 1
+    if n_out != 1 << n_open:
+        raise ValueError("the second dimension of amps must be a power of two")
+    a = amps.contiguous()
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=a.device)
+    elif out.dtype != torch.float64 or out.numel() != B or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of B entries")
+    s = stream if stream is not None else torch.cuda.current_stream(a.device)
+    N.check(N.lib().qgm_prob_sums(a.data_ptr(), 1 if a.dtype == torch.complex128 else 0, B, n_open, out.data_ptr(),
+                                  ctypes.c_void_p(s.cuda_stream)))
     return out
 
 

@@ -55,6 +55,9 @@ struct qgm_plan_s {
     std::vector<qgm::TreeBwdItem> items;
     std::vector<int32_t> slot_off_t, slot_occ_t;
     int64_t n_fbar = 0;
+    std::vector<int64_t> part_off;   // per factor: first partial sum of its adjoint (n_fbar + 1 entries)
+    size_t off_tpart = 0;
+    size_t off_status = 0;           // int32 failure record of persistent launches (0: none since the last check)
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -240,11 +243,23 @@ void layout_tree_tables(qgm_plan_t* P) {
             if ((f.type == qgm::TF_MAT || f.type == qgm::TF_DIAG) && f.mat >= qgm::kFixedMats)
                 occ[f.mat - qgm::kFixedMats].push_back(int32_t(index) * 2 + (f.type == qgm::TF_DIAG ? 1 : 0));
         };
+        auto is_slot = [](const qgm::TFactor& f) {
+            return (f.type == qgm::TF_MAT || f.type == qgm::TF_DIAG) && f.mat >= qgm::kFixedMats;
+        };
+        // partial sums of the factor adjoints: one per table block for a table factor, one per summing block
+        // for a phase factor (factors without a gate slot have none)
+        P->part_off.assign(1, 0);
         for (auto& st : t.steps)
             for (auto& g : st.groups)
-                for (auto& f : g.factors) note(f, gi++);
+                for (auto& f : g.factors) {
+                    note(f, gi++);
+                    P->part_off.push_back(P->part_off.back() + (is_slot(f) ? (st.g_entries() + 255) / 256 : 0));
+                }
         P->n_fbar = gi + int64_t(t.phase.size());
-        for (size_t i = 0; i < t.phase.size(); ++i) note(t.phase[i], gi + int(i));
+        for (size_t i = 0; i < t.phase.size(); ++i) {
+            note(t.phase[i], gi + int(i));
+            P->part_off.push_back(P->part_off.back() + (is_slot(t.phase[i]) ? int64_t(qgm::kTbPhaseBlocks) : 0));
+        }
         P->slot_off_t.assign(1, 0);
         P->slot_occ_t.clear();
         for (auto& v : occ) {
@@ -263,7 +278,8 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tslot_occ = P->off_tslot_off + al(sizeof(int32_t) * (P->slot_off_t.size() + 1));
     P->off_tfdep = P->off_tslot_occ + al(sizeof(int32_t) * (P->slot_occ_t.size() + 1));
     P->off_tleaf = P->off_tfdep + al(sizeof(int32_t) * 2 * (t.finals.size() + 1));
-    P->total = P->off_tleaf + al(sizeof(qgm::TreeLeaf) * size_t(t.n_table_leaves + 1));
+    P->off_tpart = P->off_tleaf + al(sizeof(qgm::TreeLeaf) * size_t(t.n_table_leaves + 1));
+    P->total = P->off_tpart + al(sizeof(int64_t) * P->part_off.size());
 }
 
 // Adjoint tables: the forward tasks with every result at its own rows
@@ -327,6 +343,7 @@ void fill_tree_adjoint_tables(const qgm_plan_t* P, char* h) {
     std::memcpy(h + P->off_titems, P->items.data(), sizeof(qgm::TreeBwdItem) * P->items.size());
     std::memcpy(h + P->off_tslot_off, P->slot_off_t.data(), sizeof(int32_t) * P->slot_off_t.size());
     std::memcpy(h + P->off_tslot_occ, P->slot_occ_t.data(), sizeof(int32_t) * P->slot_occ_t.size());
+    std::memcpy(h + P->off_tpart, P->part_off.data(), sizeof(int64_t) * P->part_off.size());
 }
 
 // Device records of the buckets: the row stride of every result bit and
@@ -508,9 +525,19 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
     return true;
 }
 
+void layout_step_tables(qgm_plan_t* P);
+
+// Offsets of the constant tables in each device copy of the plan; the last 256
+// bytes hold the plan's failure record (a persistent launch that gave up).
 void layout_tables(qgm_plan_t* P) {
+    if (P->p.is_tree) layout_tree_tables(P);
+    else layout_step_tables(P);
+    P->off_status = P->total;
+    P->total += 256;
+}
+
+void layout_step_tables(qgm_plan_t* P) {
     const qgm::Plan& p = P->p;
-    if (p.is_tree) { layout_tree_tables(P); return; }
     size_t n_sig = 0;
     for (auto& st : p.steps) n_sig += st.sig_src.size();
     P->off_fixed = 0;
@@ -684,7 +711,8 @@ qgm::GbarParams gbar_params(const qgm::Step& stp, uint32_t B_eff) {
 // scratch, the row sums of H per table row, the table adjoints (FP64) and the
 // factor adjoints (FP64).
 struct TreeBwdLayout {
-    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, hsum = 0, part = 0, gbar = 0, fbar = 0, total = 0;
+    uint64_t arena = 0, adj = 0, g = 0, scratch = 0, hsum = 0, part = 0, gbar = 0, fbar = 0, phibar = 0, fpart = 0,
+             total = 0;
 };
 
 TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
@@ -699,7 +727,9 @@ TreeBwdLayout tree_backward_layout(const qgm_plan_t* P, int64_t B) {
     L.part = L.hsum + al(uint64_t(t.hsum_rows) * be * 8);
     L.gbar = L.part + al(uint64_t(P->part_rows[0] + P->part_rows[1]) * be * 8);
     L.fbar = L.gbar + al(uint64_t(t.g_total) * 16);
-    L.total = L.fbar + al(uint64_t(P->n_fbar) * 4 * 16 + 16);
+    L.phibar = L.fbar + al(uint64_t(P->n_fbar) * 4 * 16 + 16);
+    L.fpart = L.phibar + al(be * 16);
+    L.total = L.fpart + al(uint64_t(P->part_off.empty() ? 0 : P->part_off.back()) * 4 * 16 + 16);
     return L;
 }
 
@@ -897,6 +927,8 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
             a.max_class = max_class;
             a.flags = flags;
             a.out = out;
+            a.status = reinterpret_cast<int32_t*>(tables + plan->off_status);
+            a.spin_limit = p.opts.persist_spin > 0 ? p.opts.persist_spin : (1 << 20);
             hipError_t he = qgm::launch_tree_persist(a, s);
             if (he != hipSuccess) return hip_fail(he, "persistent launch");
             mark(3);
@@ -1023,12 +1055,17 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
         qgm::launch_tree_level(t.level_max_in[Lv], tasks_all + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
                                B, be, be / 64u, s);   // every group of the pitch: the adjoint reads them all
     }
-    const int64_t n_fbar4 = plan->n_fbar * 4;
-    qgm::launch_tb_zero(fbar, n_fbar4, s);
+    auto* phibar = reinterpret_cast<double2*>(ws + L.phibar);
+    auto* fpart = reinterpret_cast<double2*>(ws + L.fpart);
+    const auto* part_off = reinterpret_cast<const int64_t*>(tables + plan->off_tpart);
     qgm::launch_tb_seed(reinterpret_cast<const int64_t*>(tables + plan->off_tfinal_all), int(t.finals.size()),
                         reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tphase), int(t.phase.size()), fixed,
                         slots, arena, adj, bits, B, be, static_cast<const float2*>(grad_amps), amps_out,
-                        p.opts.out_c128 != 0, fbar + (plan->n_fbar - int64_t(t.phase.size())) * 4, s);
+                        p.opts.out_c128 != 0, phibar, s);
+    if (p.n_slots > 0)
+        qgm::launch_tb_phase_adj(reinterpret_cast<const qgm::TFactor*>(tables + plan->off_tphase), int(t.phase.size()),
+                                 fixed, slots, bits, B, phibar, part_off, plan->n_fbar - int64_t(t.phase.size()),
+                                 fpart, s);
     const auto* bwd = reinterpret_cast<const qgm::TreeBwd*>(tables + plan->off_tbwd);
     const auto* bin = reinterpret_cast<const qgm::TreeBwdIn*>(tables + plan->off_tbwdin);
     const auto* bgd = reinterpret_cast<const qgm::TreeBwdG*>(tables + plan->off_tbwdg);
@@ -1045,7 +1082,8 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
         if (p.n_slots > 0) qgm::launch_tb_gbin(items + gg.off, gg.n, gg.rows, bgd, hsum, bits, B, be, gbar, s);
     }
     if (p.n_slots > 0) {
-        qgm::launch_tb_gadj(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gbar, fbar, s);
+        qgm::launch_tb_gadj(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gbar, part_off, fpart, s);
+        qgm::launch_tb_fsum(part_off, plan->n_fbar, fpart, fbar, s);
         qgm::launch_tb_slots(reinterpret_cast<const int32_t*>(tables + plan->off_tslot_off),
                              reinterpret_cast<const int32_t*>(tables + plan->off_tslot_occ), p.n_slots, fbar,
                              static_cast<float2*>(gate_grads), s);
@@ -1204,6 +1242,18 @@ qgm_status qgm_xeb(const void* amps, int32_t c128, int64_t B, int32_t n_qubits, 
     return QGM_OK;
 }
 
+qgm_status qgm_prob_sums(const void* amps, int32_t c128, int64_t B, int32_t n_open, double* out, void* stream) {
+    g_err.clear();
+    if (B < 0 || n_open < 0 || n_open > 40) return fail(QGM_E_INVALID, "B < 0 or n_open outside 0..40");
+    if (B == 0) return QGM_OK;
+    if (!amps || !out) return fail(QGM_E_INVALID, "amps and out must be device pointers");
+    if (B > 0x7fffffff) return fail(QGM_E_UNSUPPORTED, "B exceeds 2^31 - 1");
+    qgm::launch_prob_sums(amps, c128 ? 1 : 0, B, int64_t(1) << n_open, out, static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return QGM_OK;
+}
+
 qgm_status qgm_sample_set(const void* amps, int32_t c128, int64_t B, const double* u, int64_t m, int64_t* idx,
                           void* workspace, uint64_t ws_bytes, void* stream) {
     g_err.clear();
@@ -1256,13 +1306,13 @@ qgm_status qgm_graph_create(int32_t n_circ, qgm_plan_t* const* plans, const void
     hipError_t e = hipStreamBeginCapture(streams[0], hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipStreamBeginCapture"); }
     (void)hipEventRecord(events[0], streams[0]);
-    int prev_persist = -1;   // persistent launches each need the whole GPU: their branches run one after another
+    // a persistent launch needs the whole GPU at once: with one in the graph, every branch waits for the
+    // previous one (nothing runs beside it)
+    bool any_persist = false;
+    for (int i = 0; i < n_circ; ++i) any_persist = any_persist || qgm::tree_persistent(plans[i]->p, B[i]);
     for (int i = 0; i < n_circ && result == QGM_OK; ++i) {
         (void)hipStreamWaitEvent(streams[i + 1], events[0], 0);
-        if (qgm::tree_persistent(plans[i]->p, B[i])) {
-            if (prev_persist >= 0) (void)hipStreamWaitEvent(streams[i + 1], events[prev_persist + 1], 0);
-            prev_persist = i;
-        }
+        if (any_persist && i > 0) (void)hipStreamWaitEvent(streams[i + 1], events[i], 0);
         result = qgm_amplitudes(plans[i], gate_vals ? gate_vals[i] : nullptr, bits[i], B[i], out[i], workspace[i],
                                 ws_bytes[i], streams[i + 1]);
         (void)hipEventRecord(events[i + 1], streams[i + 1]);
@@ -1440,6 +1490,35 @@ void qgm_plan_destroy(qgm_plan_t* plan) {
 }
 
 const char* qgm_last_error(void) { return g_err.c_str(); }
+
+qgm_status qgm_plan_check(qgm_plan_t* plan, void* stream) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending HIP error");
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (auto& d : plan->p.dev) {
+        if (d.device != dev) continue;
+        char* rec = static_cast<char*>(d.base) + plan->off_status;
+        int32_t v = 0;
+        e = hipMemcpy(&v, rec, sizeof v, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "reading the plan's failure record");
+        if (v == 0) return QGM_OK;
+        const int32_t zero = 0;
+        e = hipMemcpy(rec, &zero, sizeof zero, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "clearing the plan's failure record");
+        return fail(QGM_E_INTERNAL, v == 2 ? "a persistent launch found its work-groups on unexpected accelerator "
+                                             "complexes and gave up (its amplitudes read NaN)"
+                                           : "a persistent launch gave up waiting for another wave (the GPU was "
+                                             "shared or its grid was not resident at once); its unfinished "
+                                             "amplitudes read NaN");
+    }
+    return QGM_OK;
+}
 
 qgm_status qgm_sync_check(void* stream) {
     g_err.clear();

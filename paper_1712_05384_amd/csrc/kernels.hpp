@@ -112,6 +112,9 @@ struct TreePersist {
     int32_t max_class;                          // largest input variant among the tasks (launch_inputs)
     int32_t* flags;
     void* out;
+    int32_t* status;                            // the plan's failure record on this device (set, never cleared)
+    int32_t spin_limit;                         // polls after which a wait gives up
+    int32_t pad;
 };
 
 // Factor table of a bucket (prologue kernel): entry e = (((g << k) | w) << sb)
@@ -164,6 +167,11 @@ struct TreeBwd {
 // 2^n_sum source rows q_row + a0(j) + foff[f], where a0(j) places bit p of j at
 // source-row bit pos[p].
 constexpr int kTbSumBits = 5;
+// Factor adjoints are summed without atomics: every table block (and each of
+// the kTbPhaseBlocks blocks of the phase factors) writes its partial sums per
+// factor, then one pass adds them in order.
+constexpr uint32_t kTbGadjParts = 8;     // blocks per table-entry block of the factor adjoints (slot factors split)
+constexpr uint32_t kTbPhaseBlocks = 64;  // blocks summing the phase factors' adjoints over the bitstrings
 struct TreeBwdIn {
     int32_t r_t, n_sum;                         // output index bits; summed bits (at most kTbSumBits)
     int32_t dst_row;                            // first output row in the destination area
@@ -232,6 +240,7 @@ void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_e
 // Cross-entropy statistics and sampling from a set of amplitudes (xeb.hip).
 uint64_t xeb_workspace_bytes(int64_t B);
 void launch_xeb(const void* amps, bool c128, int64_t B, int n_qubits, double* out, double* ws, hipStream_t stream);
+void launch_prob_sums(const void* amps, int c128, int64_t B, int64_t n_out, double* out, hipStream_t stream);
 void launch_sample_set(const void* amps, bool c128, int64_t B, const double* u, int64_t m, int64_t* idx, double* ws,
                        hipStream_t stream);
 void launch_persist_init(int32_t* flags, int64_t n_flags, void* out, int64_t B, bool c128, hipStream_t stream);
@@ -257,10 +266,14 @@ struct TreeTailArgs {
     uint32_t B_eff, pad;
 };
 void launch_tree_tail(const TreeTailArgs& a, hipStream_t stream);
-void launch_tb_zero(double2* p, int64_t n, hipStream_t stream);
 void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                     const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,
-                    uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* fbar_phase,
+                    uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* phibar,
+                    hipStream_t stream);
+void launch_tb_phase_adj(const TFactor* phase, int n_phase, const double2* fixed, const float2* slots,
+                         const uint64_t* bits, int64_t B, const double2* phibar, const int64_t* part_off, int64_t f0,
+                         double2* fpart, hipStream_t stream);
+void launch_tb_fsum(const int64_t* part_off, int64_t n_fbar, const double2* fpart, double2* fbar,
                     hipStream_t stream);
 void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwd* bwd,
                       const float2* arena, const float2* adj, const float2* gtab, float2* scratch,
@@ -272,7 +285,7 @@ void launch_tb_gbin(const TreeBwdItem* items, int n_items, int64_t total_rows, c
                     const uint64_t* bits, int64_t B, uint32_t B_eff, double2* gbar, hipStream_t stream);
 void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                     const TFactor* facs, const double2* fixed, const float2* slots, const double2* gbar,
-                    double2* fbar, hipStream_t stream);
+                    const int64_t* part_off, double2* fpart, hipStream_t stream);
 void launch_tb_slots(const int32_t* slot_off, const int32_t* slot_occ, int n_slots, const double2* fbar,
                      float2* grads, hipStream_t stream);
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,

@@ -461,6 +461,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         *err = "order_pick must be in [0, 63]";
         return QGM_E_INVALID;
     }
+    if (opts.persist_spin < 0) { *err = "persist_spin must be >= 0"; return QGM_E_INVALID; }
     if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
         *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
     }

@@ -662,10 +662,11 @@ __global__ void __launch_bounds__(256) k_tree_final(const int64_t* __restrict__ 
 // waves take the units of its groups in increasing (task, group) order with a
 // fixed stride; a unit waits only on units of lower index, and the grid fits
 // the GPU at once, so the lowest unfinished unit can always proceed.  A wait
-// that exceeds kPersistSpin polls sets the abort word; later waits return at
-// once and the amplitudes of the launch are written as NaN, so every wave
-// still ends (amplitudes start as NaN, so one that is never written reads NaN).
-constexpr int kPersistSpin = 1 << 20;
+// that exceeds the launch's spin limit (2^20 polls unless the plan sets
+// another) sets the abort word and the plan's failure record; later waits
+// return at once and the amplitudes of the launch are written as NaN, so every
+// wave still ends (amplitudes start as NaN, so one that is never written reads
+// NaN).
 
 __device__ __forceinline__ int32_t ld_flag(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -674,16 +675,21 @@ __device__ __forceinline__ void st_flag(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until flags f[0, n) are all set (64 per poll, one per lane).
-__device__ void persist_wait(const int32_t* f, int n, int32_t* abort_word, uint32_t lane) {
+// Waits until flags f[0, n) are all set (64 per poll, one per lane).  Giving
+// up sets the launch's abort word and the plan's failure record.
+__device__ void persist_wait(const int32_t* f, int n, int32_t* abort_word, int32_t* status, int spin_limit,
+                             uint32_t lane) {
     for (int i0 = 0; i0 < n; i0 += 64) {
         const bool mine = i0 + int(lane) < n;
         for (int spin = 0;; ++spin) {
             const int32_t v = mine ? ld_flag(f + i0 + lane) : 1;
             if (__all(v != 0)) break;
             if (ld_flag(abort_word) != 0) return;
-            if (spin >= kPersistSpin) {
-                if (lane == 0) st_flag(abort_word, 1);
+            if (spin >= spin_limit) {
+                if (lane == 0) {
+                    st_flag(abort_word, 1);
+                    st_flag(status, 1);
+                }
                 return;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -706,7 +712,10 @@ __global__ void __launch_bounds__(256) k_tree_persist(const TreePersist a) {
         // a complex outside 0..7, or a (complex, rank) pair met twice, breaks the pinning: abort (units still run)
         const int32_t seen = __hip_atomic_exchange(a.flags + kPersistSeen0 + q * kPersistMaxRanks + rank, 1,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (xcc >= uint32_t(kPersistXcds) || seen != 0) st_flag(abort_word, 2);
+        if (xcc >= uint32_t(kPersistXcds) || seen != 0) {
+            st_flag(abort_word, 2);
+            st_flag(a.status, 2);
+        }
     }
     const uint32_t n_bg = a.B_eff / 64u;
     if (q >= n_bg) return;
@@ -726,7 +735,8 @@ __global__ void __launch_bounds__(256) k_tree_persist(const TreePersist a) {
             // from the register copy, which a run-time index would move to scratch
             const TreeTask* __restrict__ tp = a.tasks + ti;
             const int n_in = tp->n_in;
-            for (int t = 0; t < n_in; ++t) persist_wait(fl + tp->dep_off[t], tp->dep_n[t], abort_word, lane);
+            for (int t = 0; t < n_in; ++t)
+                persist_wait(fl + tp->dep_off[t], tp->dep_n[t], abort_word, a.status, a.spin_limit, lane);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // no input load moves above the polls
             const TreeTask tk = *tp;
             // the variant the task's rows were laid out for (the launch carries those up to the plan's largest)
@@ -740,7 +750,8 @@ __global__ void __launch_bounds__(256) k_tree_persist(const TreePersist a) {
             if (lane == 0) st_flag(fl + a.task0 + ti, 1);
         } else {
             for (int f = 0; f < a.n_final_dep; ++f)
-                persist_wait(fl + a.final_dep[2 * f], a.final_dep[2 * f + 1], abort_word, lane);
+                persist_wait(fl + a.final_dep[2 * f], a.final_dep[2 * f + 1], abort_word, a.status, a.spin_limit,
+                             lane);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             if (int64_t(b) < a.B) {
                 if (ld_flag(abort_word) != 0) {

@@ -24,13 +24,37 @@ namespace {
 
 constexpr int kTbMaxGroups = 16;    // factor groups of one table (the planner keeps them below this)
 constexpr int kTbGbarLds = 1 << kTreeMaxSig;
-constexpr uint32_t kTbGadjParts = 8;   // blocks per table-entry block of the factor adjoints (slot factors split)
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
-__device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
-    atomicAdd(&p->x, v.x);
-    atomicAdd(&p->y, v.y);
+// Sum of v over the 256 threads of a block, for 4 values per thread, in a
+// fixed order (a butterfly within each wave, then the four waves in turn), so
+// that the same inputs always give the same bits.  Every thread of the block
+// must call it; the sums are valid in thread 0.  `red` is 16 double2 of LDS.
+__device__ __forceinline__ void block_sum4(double2 (&v)[4], double2* red) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            v[a].x += __shfl_xor(v[a].x, m, 64);
+            v[a].y += __shfl_xor(v[a].y, m, 64);
+        }
+    const int wave = int(threadIdx.x >> 6);
+    if ((threadIdx.x & 63u) == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) red[wave * 4 + a] = v[a];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double2 s = red[a];
+            for (int w = 1; w < 4; ++w) {
+                s.x += red[w * 4 + a].x;
+                s.y += red[w * 4 + a].y;
+            }
+            v[a] = s;
+        }
+    __syncthreads();
 }
 
 __device__ __forceinline__ bool slot_factor(const TFactor& f) {
@@ -50,11 +74,6 @@ __device__ __forceinline__ TreeBwdItem find_item(const TreeBwdItem* __restrict__
 
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_tb_zero(double2* __restrict__ p, int64_t n) {
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-        p[i] = make_double2(0.0, 0.0);
-}
-
 // Seed: A = phase x prod of the rank-0 results (FP64), A-bar = conj(grad_amps);
 // the adjoint of every rank-0 result, and the phase factors' share of the
 // gate-slot gradients.  Padded bitstrings (b >= B) get zero adjoints.
@@ -64,7 +83,7 @@ __global__ void __launch_bounds__(256) k_tb_seed(const int64_t* __restrict__ fin
                                                  const float2* __restrict__ arena, float2* __restrict__ adj,
                                                  const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
                                                  const float2* __restrict__ grad_amps, void* __restrict__ amps_out,
-                                                 int c128, double2* __restrict__ fbar_phase) {
+                                                 int c128, double2* __restrict__ phibar_out) {
     const uint32_t b = blockIdx.x * 256u + threadIdx.x;
     if (b >= B_eff) return;
     const bool live = int64_t(b) < B;
@@ -101,17 +120,55 @@ __global__ void __launch_bounds__(256) k_tb_seed(const int64_t* __restrict__ fin
         }
         adj[final_rows[f] * int64_t(B_eff) + b] = make_float2(float(v.x), float(v.y));
     }
-    if (!live) return;
-    const double2 phibar = cmuld(abar, prod);
+    // the adjoint of the phase (zero for padded bitstrings), summed per phase factor by k_tb_phase_adj
+    phibar_out[b] = cmuld(abar, prod);
+}
+
+// Adjoints of the phase factors that read gate slots: factor i receives
+// phibar(b) * prod_{j != i} phase_j(b) at its entry (a, c) selected by the
+// bits of bitstring b.  Block k sums the bitstrings b = k * 256 + tid +
+// m * 256 * gridDim.x in increasing m per thread, then over the block in a
+// fixed order, and writes its partial sums to fpart[part_off[f0 + i] + k].
+__global__ void __launch_bounds__(256) k_tb_phase_adj(const TFactor* __restrict__ phase, int n_phase,
+                                                      const double2* __restrict__ fixed,
+                                                      const float2* __restrict__ slots,
+                                                      const uint64_t* __restrict__ bits, int64_t B,
+                                                      const double2* __restrict__ phibar,
+                                                      const int64_t* __restrict__ part_off, int64_t f0,
+                                                      double2* __restrict__ fpart) {
+    __shared__ double2 red[16];
     for (int i = 0; i < n_phase; ++i) {
         const TFactor f = phase[i];
-        if (!slot_factor(f)) continue;
-        double2 v = phibar;
-        for (int j = 0; j < n_phase; ++j)
-            if (j != i) v = cmuld(v, phase_value(j));
-        const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
-        const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
-        atomic_add_c(fbar_phase + size_t(i) * 4 + a * 2 + c, v);
+        if (!slot_factor(f)) continue;   // uniform over the block
+        double2 acc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a] = make_double2(0.0, 0.0);
+        for (int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x; b < B; b += int64_t(gridDim.x) * 256) {
+            const uint64_t x = bits[b];
+            double2 v = phibar[b];
+            for (int j = 0; j < n_phase; ++j) {
+                if (j == i) continue;
+                const TFactor g = phase[j];
+                const uint32_t ga = g.src0 == TS_SIG ? uint32_t((x >> g.bit0) & 1ull) : 0u;
+                const uint32_t gc = g.src1 == TS_SIG ? uint32_t((x >> g.bit1) & 1ull) : 0u;
+                v = cmuld(v, factor_value(g, ga, gc, fixed, slots));
+            }
+            const uint32_t a = f.src0 == TS_SIG ? uint32_t((x >> f.bit0) & 1ull) : 0u;
+            const uint32_t c = f.src1 == TS_SIG ? uint32_t((x >> f.bit1) & 1ull) : 0u;
+            const uint32_t e = a * 2u + c;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k)
+                if (k == e) {
+                    acc[k].x += v.x;
+                    acc[k].y += v.y;
+                }
+        }
+        block_sum4(acc, red);
+        if (threadIdx.x == 0) {
+            double2* dst = fpart + (part_off[f0 + i] + blockIdx.x) * 4;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dst[a] = acc[a];
+        }
     }
 }
 
@@ -332,18 +389,31 @@ __global__ void __launch_bounds__(256) k_tb_gbin(const TreeBwdItem* __restrict__
 // the factor-table build), for every group q and value iv of its own
 // variables, each gate-slot factor f of q receives
 //   G-bar[e] * prod_{q' != q} S_q' * prod_{f' in q, f' != f} f'
-// at the entry of its table that (c, sigma, iv) selects.
-// One table entry's contributions to the factor adjoints (into LDS for the
-// block's staged factors, directly to global memory beyond them).
-__device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, const TreeGroup* __restrict__ gr,
-                              int fac0, const TFactor* __restrict__ tf, const double2* __restrict__ fixed,
-                              const float2* __restrict__ slots, const double2* __restrict__ gbar,
-                              double2* __restrict__ fbar, double2* acc_lds, int64_t e, int part, int n_parts) {
-    if (e >= (int64_t(1) << (t.gb + t.k + t.sb))) return;
-    const double2 gb = gbar[t.g_off + e];
-    if (gb.x == 0.0 && gb.y == 0.0) return;
-    const uint32_t sig = uint32_t(e) & ((1u << t.sb) - 1u);
-    const uint32_t c = uint32_t(e) >> t.sb;
+// at the entry of its table that (c, sigma, iv) selects.  Each block sums its
+// 256 entries' shares per factor in a fixed order (block_sum4) and writes
+// them to fpart[part_off[f] + sub]; k_tb_fsum adds the blocks of a factor in
+// order, so the result does not depend on scheduling.  Block (x, y) handles
+// the y-th of every kTbGadjParts slot factors of its table.
+__global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict__ blocks,
+                                                 const TreeGTab* __restrict__ gtabs,
+                                                 const TreeGroup* __restrict__ groups,
+                                                 const TFactor* __restrict__ facs, const double2* __restrict__ fixed,
+                                                 const float2* __restrict__ slots, const double2* __restrict__ gbar,
+                                                 const int64_t* __restrict__ part_off, double2* __restrict__ fpart) {
+    __shared__ FactorLds L;
+    __shared__ double2 red[16];
+    const TreeProBlock blk = blocks[blockIdx.x];
+    const TreeGTab t = gtabs[blk.idx];
+    const TreeGroup* __restrict__ gr = groups + t.group_off;
+    const int fac0 = gr[0].fac_off;
+    const TFactor* __restrict__ tf = facs + fac0;
+    const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);   // ends with a block barrier
+    const int part = int(blockIdx.y), n_parts = int(gridDim.y);
+    const int64_t e = int64_t(blk.sub) * 256 + threadIdx.x;
+    const bool valid = e < (int64_t(1) << (t.gb + t.k + t.sb));
+    const double2 gb = valid ? gbar[t.g_off + e] : make_double2(0.0, 0.0);
+    const uint32_t sig = valid ? uint32_t(e) & ((1u << t.sb) - 1u) : 0u;
+    const uint32_t c = valid ? uint32_t(e) >> t.sb : 0u;
     double2 S[kTbMaxGroups];
 #pragma unroll
     for (int q = 0; q < kTbMaxGroups; ++q) {
@@ -368,10 +438,8 @@ __device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, con
             default: return 0u;
         }
     };
-    int n_seen = 0;   // slot factors met so far: this thread takes every n_parts-th from `part`
-#pragma unroll
-    for (int q = 0; q < kTbMaxGroups; ++q) {
-        if (q >= t.n_groups) break;
+    int n_seen = 0;   // slot factors met so far (uniform over the block)
+    for (int q = 0; q < t.n_groups; ++q) {
         double2 pq = gb;
 #pragma unroll
         for (int q2 = 0; q2 < kTbMaxGroups; ++q2)
@@ -382,44 +450,47 @@ __device__ void tb_gadj_entry(const FactorLds& L, int nf, const TreeGTab& t, con
             const TFactor f = tf[i];
             if (!slot_factor(f)) continue;
             if (n_seen++ % n_parts != part) continue;
-            for (uint32_t iv = 0; iv < (1u << g.k_int); ++iv) {
-                double2 v = pq;
-                for (int i2 = f0; i2 < f1; ++i2)
-                    if (i2 != i) v = cmuld(v, factor_product(L, nf, tf, i2, i2 + 1, fixed, slots, c, sig, iv));
-                const uint32_t args = val(f.src0, f.bit0, iv) * 2u + val(f.src1, f.bit1, iv);
-                if (i < nf) {
-                    atomicAdd(&acc_lds[i * 4 + args].x, v.x);
-                    atomicAdd(&acc_lds[i * 4 + args].y, v.y);
-                } else {
-                    atomic_add_c(fbar + size_t(fac0 + i) * 4 + args, v);
+            double2 acc[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a] = make_double2(0.0, 0.0);
+            if (valid && (gb.x != 0.0 || gb.y != 0.0)) {
+                for (uint32_t iv = 0; iv < (1u << g.k_int); ++iv) {
+                    double2 v = pq;
+                    for (int i2 = f0; i2 < f1; ++i2)
+                        if (i2 != i) v = cmuld(v, factor_product(L, nf, tf, i2, i2 + 1, fixed, slots, c, sig, iv));
+                    const uint32_t args = val(f.src0, f.bit0, iv) * 2u + val(f.src1, f.bit1, iv);
+#pragma unroll
+                    for (uint32_t k = 0; k < 4; ++k)
+                        if (k == args) {
+                            acc[k].x += v.x;
+                            acc[k].y += v.y;
+                        }
                 }
+            }
+            block_sum4(acc, red);
+            if (threadIdx.x == 0) {
+                double2* dst = fpart + (part_off[fac0 + i] + blk.sub) * 4;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) dst[a] = acc[a];
             }
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_tb_gadj(const TreeProBlock* __restrict__ blocks,
-                                                 const TreeGTab* __restrict__ gtabs,
-                                                 const TreeGroup* __restrict__ groups,
-                                                 const TFactor* __restrict__ facs, const double2* __restrict__ fixed,
-                                                 const float2* __restrict__ slots, const double2* __restrict__ gbar,
-                                                 double2* __restrict__ fbar) {
-    __shared__ FactorLds L;
-    __shared__ double2 acc_lds[kTreeMaxPrologueFactors * 4];   // this block's share of the factor adjoints
-    const TreeProBlock blk = blocks[blockIdx.x];
-    const TreeGTab t = gtabs[blk.idx];
-    const TreeGroup* __restrict__ gr = groups + t.group_off;
-    const int fac0 = gr[0].fac_off;
-    const TFactor* __restrict__ tf = facs + fac0;
-    for (int i = threadIdx.x; i < kTreeMaxPrologueFactors * 4; i += 256) acc_lds[i] = make_double2(0.0, 0.0);
-    const int nf = stage_factors(L, tf, t.n_fac, fixed, slots);   // ends with a block barrier
-    tb_gadj_entry(L, nf, t, gr, fac0, tf, fixed, slots, gbar, fbar, acc_lds, int64_t(blk.sub) * 256 + threadIdx.x,
-                  int(blockIdx.y), int(gridDim.y));
-    __syncthreads();
-    for (int i = threadIdx.x; i < nf * 4; i += 256) {
-        const double2 v = acc_lds[i];
-        if (v.x != 0.0 || v.y != 0.0) atomic_add_c(fbar + size_t(fac0 + (i >> 2)) * 4 + (i & 3), v);
+// fbar[f][a] = sum over the partial sums of factor f in order (zero for a
+// factor that reads no gate slot: it has none).
+__global__ void __launch_bounds__(256) k_tb_fsum(const int64_t* __restrict__ part_off, int64_t n_fbar,
+                                                 const double2* __restrict__ fpart, double2* __restrict__ fbar) {
+    const int64_t id = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (id >= n_fbar * 4) return;
+    const int64_t f = id >> 2;
+    const int a = int(id & 3);
+    double2 s = make_double2(0.0, 0.0);
+    for (int64_t k = part_off[f]; k < part_off[f + 1]; ++k) {
+        s.x += fpart[k * 4 + a].x;
+        s.y += fpart[k * 4 + a].y;
     }
+    fbar[id] = s;
 }
 
 // Gradient of every gate slot: the sum of its factors' adjoints (a diagonal
@@ -449,18 +520,27 @@ __global__ void __launch_bounds__(256) k_tb_slots(const int32_t* __restrict__ sl
     grads[id] = conjf2(make_float2(float(acc.x), float(acc.y)));
 }
 
-void launch_tb_zero(double2* p, int64_t n, hipStream_t stream) {
-    if (n <= 0) return;
-    const uint32_t grid = uint32_t(std::min<int64_t>((n + 255) / 256, 1024));
-    hipLaunchKernelGGL(k_tb_zero, dim3(grid), dim3(256), 0, stream, p, n);
-}
-
 void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                     const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,
-                    uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* fbar_phase,
+                    uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* phibar,
                     hipStream_t stream) {
     hipLaunchKernelGGL(k_tb_seed, dim3((B_eff + 255) / 256), dim3(256), 0, stream, final_rows, n_final, phase, n_phase,
-                       fixed, slots, arena, adj, bits, B, B_eff, grad_amps, amps_out, c128 ? 1 : 0, fbar_phase);
+                       fixed, slots, arena, adj, bits, B, B_eff, grad_amps, amps_out, c128 ? 1 : 0, phibar);
+}
+
+void launch_tb_phase_adj(const TFactor* phase, int n_phase, const double2* fixed, const float2* slots,
+                         const uint64_t* bits, int64_t B, const double2* phibar, const int64_t* part_off, int64_t f0,
+                         double2* fpart, hipStream_t stream) {
+    if (n_phase <= 0 || B <= 0) return;
+    hipLaunchKernelGGL(k_tb_phase_adj, dim3(kTbPhaseBlocks), dim3(256), 0, stream, phase, n_phase, fixed, slots, bits,
+                       B, phibar, part_off, f0, fpart);
+}
+
+void launch_tb_fsum(const int64_t* part_off, int64_t n_fbar, const double2* fpart, double2* fbar,
+                    hipStream_t stream) {
+    if (n_fbar <= 0) return;
+    hipLaunchKernelGGL(k_tb_fsum, dim3(uint32_t((n_fbar * 4 + 255) / 256)), dim3(256), 0, stream, part_off, n_fbar,
+                       fpart, fbar);
 }
 
 void launch_tb_expand(const TreeBwdItem* items, int n_items, int64_t total_rows, const TreeBwd* bwd,
@@ -492,10 +572,10 @@ void launch_tb_gbin(const TreeBwdItem* items, int n_items, int64_t total_rows, c
 
 void launch_tb_gadj(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,
                     const TFactor* facs, const double2* fixed, const float2* slots, const double2* gbar,
-                    double2* fbar, hipStream_t stream) {
+                    const int64_t* part_off, double2* fpart, hipStream_t stream) {
     if (n_blocks <= 0) return;
-    hipLaunchKernelGGL(k_tb_gadj, dim3(uint32_t(n_blocks), kTbGadjParts), dim3(256), 0, stream, blocks, gtabs, groups, facs, fixed,
-                       slots, gbar, fbar);
+    hipLaunchKernelGGL(k_tb_gadj, dim3(uint32_t(n_blocks), kTbGadjParts), dim3(256), 0, stream, blocks, gtabs, groups,
+                       facs, fixed, slots, gbar, part_off, fpart);
 }
 
 void launch_tb_slots(const int32_t* slot_off, const int32_t* slot_occ, int n_slots, const double2* fbar,

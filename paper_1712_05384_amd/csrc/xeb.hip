@@ -48,6 +48,20 @@ __device__ double block_sum(double v, double* lds) {
 
 }  // namespace
 
+// Normalisation of sets of amplitudes (Sec. III.A): block b writes
+// sum_o |A(x_b, o)|^2 over the 2^n_open entries of bitstring b, in FP64 and in
+// a fixed order (strided per thread, then the block tree).  With every qubit
+// open the one set is the whole output distribution, whose sum is 1.
+__global__ void __launch_bounds__(kXebThreads) k_prob_sums(const void* __restrict__ amps, int c128, int64_t n_out,
+                                                           double* __restrict__ out) {
+    __shared__ double lds[kXebThreads];
+    const int64_t j0 = int64_t(blockIdx.x) * n_out;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n_out; j += kXebThreads) s += prob(amps, c128, j0 + j);
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 // Block i sums p over the batch entries [i * chunk, (i + 1) * chunk).
 __global__ void __launch_bounds__(kXebThreads) k_xeb_partial(const void* __restrict__ amps, int c128, int64_t B,
                                                              int64_t chunk, double* __restrict__ part) {
@@ -188,6 +202,10 @@ uint64_t xeb_workspace_bytes(int64_t B) {
     const int64_t chunk = xeb_chunk(B > 0 ? B : 1);
     const int64_t blocks = (B + chunk - 1) / chunk + 1;
     return uint64_t(8 * (B + 4 * blocks + blocks + 1) + 256);
+}
+
+void launch_prob_sums(const void* amps, int c128, int64_t B, int64_t n_out, double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_prob_sums, dim3(uint32_t(B)), dim3(kXebThreads), 0, stream, amps, c128, n_out, out);
 }
 
 void launch_xeb(const void* amps, bool c128, int64_t B, int n_qubits, double* out, double* ws, hipStream_t stream) {

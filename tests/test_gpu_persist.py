@@ -78,6 +78,27 @@ def test_persistent_c2_full_size():
     assert err <= TOL * 2 ** (-c.n / 2)
 
 
+def test_persistent_give_up_is_reported():
+    """A spin limit of one poll, set from the host, makes the launch's own
+    bounded waits give up (every wave still ends): the call itself returns,
+    qgm_plan_check reports QGM_E_INTERNAL once and then clears the record, and
+    a plan with the default limit reports nothing."""
+    import paper_1712_05384_amd as Q
+    from paper_1712_05384_amd import _native as N
+    c, bits = C.workload("c2_5x5_d25")
+    _say("case persistent give-up c2_5x5_d25 B=1024 spin limit 1")
+    p = _plan(c, 2, persist_spin=1)
+    p.amplitudes(bits)
+    with pytest.raises(N.QgmError) as ei:
+        p.check()
+    assert ei.value.status == N.QGM_E_INTERNAL
+    p.check()                      # the record was cleared by the first check
+    q = _plan(c, 2)
+    got = _amps(q, bits)
+    q.check()
+    assert np.isfinite(got).all()
+
+
 def test_persistent_graph_branches_and_replays():
     """A HIP graph with two persistent branches and a per-level branch replays to the eager results."""
     import paper_1712_05384_amd as Q
@@ -94,6 +115,8 @@ def test_persistent_graph_branches_and_replays():
             assert np.array_equal(a, b), (rep, i, int(np.isnan(a).sum()), int(np.isnan(b).sum()),
                                           float(np.nanmax(np.abs(a - b))), int((a != b).sum()))
         _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+    for p in plans:
+        p.check()
     ref = oracle.sv_amplitudes(c1.n, c1.gates, None, bits[0])
     assert np.abs(eager[0][:, 0] - ref).max() <= TOL * 2 ** (-c1.n / 2)
     assert np.abs(eager[2] - eager[1]).max() <= TOL * 2 ** (-c2.n / 2)

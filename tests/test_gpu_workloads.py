@@ -44,6 +44,30 @@ def test_c3_sliced_against_stored_oracle():
     assert np.abs(got0 - got).max() <= TOL * 2 ** (-c.n / 2)
 
 
+BF16X3_TOL = 2e-3   # BF16x3 split precision, max |A - A_oracle| * 2^(n/2)
+
+
+@pytest.mark.parametrize("policy,kind,tol", [(2, "mfma_f32", TOL), (4, "mfma_bf16x3", BF16X3_TOL)])
+def test_c3_matrix_core_precisions_against_stored_oracle(policy, kind, tol):
+    """5x6 depth 30, 1024 bitstrings, vertical order with 2 sliced variables
+    summed in FP64: the steps the matrix-core kernel supports run on FP32 MFMA
+    (policy 2, complex64 bound) or in BF16x3 split precision (policy 4, three
+    bf16 products accumulated in FP32), against the stored FP64 state vector."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c3_5x6_d30")
+    ref = np.load(os.path.join(GOLDEN, "c3_5x6_d30_amps.npy"), allow_pickle=False)
+    _say("case c3 5x6 d30 B=1024 slices=2 policy %d" % policy)
+    p = Q.plan(c, min_sliced_vars=2, out_c128=True, kernel_policy=policy)
+    info = p.info(0)
+    kinds = [s["kernel"] for s in info["steps"]]
+    assert info["n_sliced"] == 2 and kinds.count(kind) >= 10
+    got = p.amplitudes(bits).cpu().numpy()[:, 0]
+    err = np.abs(got - ref) * 2 ** (c.n / 2)
+    _say("  c3 %s (%d of %d steps): max err * 2^(n/2) = %.3g, median %.3g"
+         % (kind, kinds.count(kind), len(kinds), err.max(), np.median(err)))
+    assert err.max() <= tol
+
+
 def test_graph_replays_match_eager():
     """Several circuits in one graph; every replay (with eager work and
     synchronisation in between) equals the eager result bit for bit."""

@@ -194,6 +194,23 @@ qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* byte
 qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
                           void* out, void* workspace, uint64_t ws_bytes, void* stream);
 
+/* qgm_amplitudes without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc.  It computes exactly what
+ * qgm_amplitudes computes, with the same kernels, using as its workspace a
+ * file-scope device array of the library (64 MiB; one copy per device, held
+ * until the process ends).  It calls no hipMalloc, hipFree or other allocating
+ * routine, so the plan's constant tables must already be on the current device:
+ * run qgm_amplitudes (or qgm_graph_create) with the plan once on the device
+ * first, else QGM_E_INVALID.  QGM_E_OOM when qgm_workspace_bytes(plan, B)
+ * exceeds 64 MiB; QGM_E_INVALID when per-phase timing is on.  Every call on a
+ * device shares that device's array: calls that overlap on one device (on
+ * different streams, or from several threads) race and must be ordered by the
+ * caller; the array keeps the last call's contents, which no call relies on.
+ * Other arguments, layouts and errors as qgm_amplitudes. */
+qgm_status qgm_amplitudes_static(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
+                                 void* out, void* stream);
+
 /* Device workspace (bytes) that qgm_backward needs for a batch of B bitstrings
  * (for ordering 1 sized by the same power-of-two row pitch). */
 qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);

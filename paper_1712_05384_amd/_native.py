@@ -16,7 +16,7 @@ EXPORTED = ("qgm_default_opts", "qgm_plan", "qgm_plan_info", "qgm_workspace_byte
             "qgm_backward_workspace_bytes", "qgm_backward", "qgm_graph_create", "qgm_graph_launch",
             "qgm_graph_destroy", "qgm_autotune", "qgm_plan_set_timing", "qgm_plan_timings", "qgm_plan_destroy", "qgm_last_error",
             "qgm_sync_check", "qgm_xeb_workspace_bytes", "qgm_xeb", "qgm_sample_set", "qgm_expectation_circuit",
-            "qgm_prob_sums", "qgm_plan_check")
+            "qgm_prob_sums", "qgm_plan_check", "qgm_amplitudes_static")
 
 
 class QgmGate(ctypes.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.qgm_sample_set.argtypes = [P, ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int64, P, P, ctypes.c_uint64, P]
         L.qgm_prob_sums.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P]
         L.qgm_plan_check.argtypes = [P, P]
+        L.qgm_amplitudes_static.argtypes = [P, P, P, ctypes.c_int64, P, P]
         I32P = ctypes.POINTER(ctypes.c_int32)
         L.qgm_expectation_circuit.argtypes = [ctypes.POINTER(QgmCircuit), ctypes.c_int32, I32P, I32P,
                                               ctypes.POINTER(QgmGate), ctypes.c_int32, I32P]
@@ -91,7 +92,7 @@ def lib():
                   L.qgm_plan_set_timing, L.qgm_plan_timings, L.qgm_backward_workspace_bytes, L.qgm_backward,
                   L.qgm_graph_create, L.qgm_graph_launch, L.qgm_autotune, L.qgm_xeb_workspace_bytes, L.qgm_xeb,
                   L.qgm_sample_set, L.qgm_expectation_circuit, L.qgm_prob_sums,
-                  L.qgm_plan_check):
+                  L.qgm_plan_check, L.qgm_amplitudes_static):
             f.restype = ctypes.c_int
         _lib = L
     return _lib

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <new>
 #include <string>
@@ -1098,6 +1099,69 @@ extern "C" {
 qgm_status qgm_amplitudes(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
                           void* workspace, uint64_t ws_bytes, void* stream) {
     return amplitudes_impl(plan, gate_vals, bits, B, out, workspace, ws_bytes, stream, false);
+}
+
+}  // extern "C"
+
+// Workspace of qgm_amplitudes_static: one file-scope device array, of which
+// every device the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: the device address of
+// each copy comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+constexpr uint64_t kStaticScratchBytes = uint64_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+qgm_status static_scratch(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(QGM_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return fail(QGM_E_INTERNAL, "scratch array misaligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return QGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qgm_status qgm_amplitudes_static(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B, void* out,
+                                 void* stream) {
+    g_err.clear();
+    if (!plan) return fail(QGM_E_INVALID, "plan is NULL");
+    if (B < 0) return fail(QGM_E_INVALID, "B < 0");
+    if (B == 0) return QGM_OK;
+    if (plan->timing) return fail(QGM_E_INVALID, "per-phase timing records events: turn it off for this entry point");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    bool uploaded = false;
+    for (auto& d : plan->p.dev) uploaded = uploaded || d.device == dev;
+    if (!uploaded)
+        return fail(QGM_E_INVALID, "the plan's tables are not on this device yet: run qgm_amplitudes (or "
+                                   "qgm_graph_create) with this plan once on the device first");
+    const uint64_t need = qgm::workspace_layout(plan->p, B).total;
+    if (need > kStaticScratchBytes)
+        return fail(QGM_E_OOM, "the batch needs " + std::to_string(need) + " bytes of workspace, beyond the " +
+                               std::to_string(kStaticScratchBytes) + " bytes of the static scratch array");
+    void* ws = nullptr;
+    qgm_status st = static_scratch(&ws);
+    if (st != QGM_OK) return st;
+    return amplitudes_impl(plan, gate_vals, bits, B, out, ws, kStaticScratchBytes, stream, false);
 }
 
 qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes) {

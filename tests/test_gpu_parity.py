@@ -184,12 +184,12 @@ def test_c2_kernel_policies(policy):
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
 
 
-BF16X3_TOL = 2e-3   # BF16x3: per-product relative error ~2^-16 (dropped lo*lo and lo rounding)
+BF16X3_TOL = 1e-4   # BF16x3 bound frozen from the 5x6 depth-30 run (max 2.7e-5, median 8.8e-6)
 
 
 @pytest.mark.parametrize("rows,cols,depth,seed", [(4, 4, 24, 4), (4, 4, 30, 12)])
 def test_bf16x3_steps(rows, cols, depth, seed):
-    """Matrix-core steps in BF16x3 split precision, within 2e-3 * 2^-n/2 of the oracle
+    """Matrix-core steps in BF16x3 split precision, within 1e-4 * 2^-n/2 of the oracle
     (and visibly less exact than FP32, so the split path really runs)."""
     c = C.random_grid_circuit(rows, cols, depth, seed)
     bits = C.random_bitstrings(c.n, 200, seed)

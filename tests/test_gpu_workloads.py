@@ -44,7 +44,7 @@ def test_c3_sliced_against_stored_oracle():
     assert np.abs(got0 - got).max() <= TOL * 2 ** (-c.n / 2)
 
 
-BF16X3_TOL = 2e-3   # BF16x3 split precision, max |A - A_oracle| * 2^(n/2)
+BF16X3_TOL = 1e-4   # BF16x3 split precision, max |A - A_oracle| * 2^(n/2); frozen from the 5x6 depth-30 run (2.7e-5)
 
 
 @pytest.mark.parametrize("policy,kind,tol", [(2, "mfma_f32", TOL), (4, "mfma_bf16x3", BF16X3_TOL)])

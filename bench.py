@@ -4,19 +4,20 @@
 A "step" is one qgm_amplitudes call over the whole batch, with bitstrings,
 workspace and output already resident in HBM, launched on one stream; the same
 call captured in a HIP graph (qgm_graph_create) and replayed is reported beside
-it (the replay measured about 4 us slower per call than the direct launches of
-the same kernels, with the host well ahead in both).  Default workload: the 5x5
-depth-25 random grid circuit (seed 201) with 1024 uniform bitstrings, planned
-with ordering 1 (bucket elimination along a greedy treewidth order): the
-prologue kernel (factor tables, sigma rows), one bucket-kernel launch per
-elimination-tree level and the FP64 output product.  --ordering 0 times the
-vertical-order path instead (worldline steps, autotuned kernels).
+it.  Default workload: the 5x5 depth-25 random grid circuit (seed 201) with
+1024 uniform bitstrings, planned with ordering 1 (bucket elimination along a
+greedy treewidth order), which runs as one LDS-resident launch (one work-group
+per bitstring, every result of the elimination tree in LDS, the factor tables
+built once per plan).  --tree-exec 1 times the same plan with one launch per
+elimination-tree level instead (results in HBM); --ordering 0 the
+vertical-order path (worldline steps, autotuned kernels).
 
-Prints one JSON line.  The roofline object is for the dominant kernel (the
-bucket kernel, or the worldline-step kernel for ordering 0): algorithmic bytes
-per launch (every input result read once, every result written once, from
-the plan) over its average launch duration, timed with HIP events on the
-stream the kernels run on.  The cpu_baseline leg times the FP64 state-vector
+Prints one JSON line.  The roofline object is for the dominant kernel: for the
+LDS-resident launch, the plan's algorithmic flops over its launch time against
+the FP32 vector peak (its HBM traffic is kilobytes); for the level launches and
+the worldline steps, algorithmic bytes per launch (every input result read
+once, every result written once, from the plan) against HBM; launch times from
+HIP events on the stream the kernels run on.  The cpu_baseline leg times the FP64 state-vector
 oracle on the host cores over the same circuit and bitstrings, and its
 amplitudes give the max error of the GPU result.
 """
@@ -30,6 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+LDS_HEADER = 4 * 256 + 16   # LDS bytes before the data of the LDS-resident launch (table output bits, phase)
 # HBM bytes per dominant-kernel launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
 # plain 1 GiB copy gives), valid for the kernel source with this hash and the
@@ -59,6 +62,9 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="ordering 0: keep the policy's kernels")
     ap.add_argument("--kernel-policy", type=int, default=0,
                     help="ordering 0: 0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
+    ap.add_argument("--tree-exec", type=int, default=0,
+                    help="ordering 1: 0 auto (LDS-resident launch when the plan fits), 1 one launch per level, "
+                         "3 LDS-resident")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -83,7 +89,8 @@ def main() -> int:
     c, bits = C.workload(args.workload)
     B = len(bits)
     t0 = time.perf_counter()
-    p = Q.plan(c, kernel_policy=args.kernel_policy, ordering=args.ordering)
+    p = Q.plan(c, kernel_policy=args.kernel_policy, ordering=args.ordering,
+               **({"tree_exec": args.tree_exec} if args.ordering == 1 else {}))
     plan_s = time.perf_counter() - t0
     info = p.info(0)
     print(f"# plan: n={c.n} ordering={args.ordering} max_rank={info['max_rank']} "
@@ -139,7 +146,7 @@ def main() -> int:
     print(f"# {args.steps} graph replays: {graph_ms:.4f} ms/step, {B / (graph_ms / 1e3):.4g} amplitudes/s",
           file=sys.stderr, flush=True)
 
-    roofline, cfg = dominant_kernel(args, p, info, B, phases[2] / max(ncalls, 1), kernels)
+    roofline, cfg = dominant_kernel(args, p, info, B, phases[2] / max(ncalls, 1), kernels, args.tree_exec)
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
@@ -187,10 +194,35 @@ def main() -> int:
     return 0
 
 
-def dominant_kernel(args, p, info, B, elim_ms, kernels):
+def dominant_kernel(args, p, info, B, elim_ms, kernels, tree_exec=0):
     """Roofline object of the dominant kernel and its config keys.  elim_ms is
     the per-call time of all its launches (HIP events around them)."""
     B_eff = ((B + 63) // 64 * 64) << info["n_sliced"]
+    if info["ordering"] == 1 and info.get("lds_ok") and tree_exec in (0, 3) and not info.get("n_open"):
+        # one launch, every result in LDS: its HBM traffic is the bitstrings, the table entries at their
+        # output bits and the amplitudes (kilobytes), so its roof is the vector ALU (plus LDS issue): the
+        # plan's algorithmic flops (6 per complex product, 2 per complex add) over the launch time
+        flops = info["flops_per_amp"] * B
+        achieved = flops / (elim_ms / 1e3) / 1e12
+        cfg = {"buckets": info["n_buckets"], "tree_levels": info["n_levels"], "launches": 1,
+               "execution_form": "LDS-resident: one work-group of %d threads per bitstring" % info["lds_threads"],
+               "lds_bytes_per_workgroup": 8 * info["lds_entries"] + LDS_HEADER, "lds_jobs": info["lds_jobs"],
+               "flops_per_amp": info["flops_per_amp"], "bytes_per_amp_of_the_level_launches": info["bytes_per_amp"]}
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                    "kernel": "k_tree_lds (bucket elimination with every result in LDS, one launch per call)",
+                    "flops_per_launch": flops, "launch_ms": elim_ms, "launches_per_step": 1,
+                    "peak_note": "fp32 vector peak of MI355X (packed FP32); the build disables packed FP32, "
+                                 "so 78.6 TFLOP/s is the issue limit of these kernels"}
+        rec = MEASURED_TRAFFIC.get((args.workload, "lds"))
+        if rec:
+            import hashlib
+            path = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", rec["source"])
+            if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == rec["sha256_16"]:
+                roofline["traffic"] = round(rec["bytes_per_launch"] / (elim_ms / 1e3) / 1e9, 2)
+                roofline["traffic_bytes_per_launch"] = rec["bytes_per_launch"]
+                roofline["traffic_unit"] = "GB/s"
+        return roofline, cfg
     if info["ordering"] == 1:
         kernel = ("k_tree_level + k_tree_tail (bucket elimination: one launch per elimination-tree level, "
                   "the last small levels and the FP64 output in one launch)")
@@ -245,8 +277,8 @@ def _time(fn, reps, stream, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def _amps_per_sec(Q, C, torch, np, stream, name, reps=5, **plan_kw):
-    """Eager amplitudes/s of one workload with inputs resident; returns (value, plan, ms)."""
+def _amps_per_sec(Q, C, torch, np, stream, name, reps=5, autotune=True, **plan_kw):
+    """Eager amplitudes/s of one workload with inputs resident; returns (value, plan, ms, out)."""
     dev = torch.device("cuda", 0)
     c, bits = C.workload(name)
     p = Q.plan(c, **plan_kw)
@@ -255,61 +287,83 @@ def _amps_per_sec(Q, C, torch, np, stream, name, reps=5, **plan_kw):
     o = torch.empty((len(bits), 1), dtype=torch.complex128 if plan_kw.get("out_c128") else torch.complex64,
                     device=dev)
     w = torch.empty(max(p.workspace_bytes(len(bits)), 256), dtype=torch.uint8, device=dev)
-    if plan_kw.get("ordering", 0) == 0:
+    if plan_kw.get("ordering", 0) == 0 and autotune:
         p.autotune(bd, gv, stream=stream)
     ms = _time(lambda: p.amplitudes(bd, gv, out=o, workspace=w, stream=stream), reps, stream, torch)
-    return len(bits) / (ms / 1e3), p, ms
+    return len(bits) / (ms / 1e3), p, ms, o
+
+
+def _kernel_ms(p, bd, out, ws, stream, torch, reps=5):
+    """Per-call time of the elimination phase (HIP events the plan records around its launches)."""
+    p.set_timing(True)
+    for _ in range(reps):
+        p.amplitudes(bd, None, out=out, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    ph, nc = p.timings()
+    p.set_timing(False)
+    return ph[2] / max(nc, 1)
 
 
 def extras(Q, C, torch, np, stream, args):
     """Secondary workloads, timed the same way (inputs resident, HIP events)."""
     out = {}
     dev = torch.device("cuda", 0)
-    # the other elimination order on the default workload
-    other = 1 - args.ordering
-    v, p, ms = _amps_per_sec(Q, C, torch, np, stream, args.workload, 10, ordering=other)
-    info = p.info(0)
-    p.set_timing(True)
     c, bits = C.workload(args.workload)
     bd = torch.from_numpy(bits.view(np.int64)).to(dev)
-    for _ in range(5):
-        p.amplitudes(bd, None, stream=stream)
-    torch.cuda.synchronize()
-    ph, nc = p.timings()
-    p.set_timing(False)
-    rf, _ = dominant_kernel(argparse.Namespace(workload=args.workload, kernel_policy=0, no_autotune=False), p, info,
-                            len(bits), ph[2] / max(nc, 1), None)
-    out["ordering_%d" % other] = {"workload": args.workload, "amplitudes_per_sec": round(v, 1),
-                                  "ms_per_call": round(ms, 4), "bytes_per_amp": info["bytes_per_amp"],
-                                  "max_rank": info["max_rank"], "roofline": rf}
-    print(f"# ordering {other}: {ms:.3f} ms per call, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
-    # batch scaling of the bucket path on the default circuit: larger batches give the level kernels
-    # enough wave units to approach the HBM roof
-    c, _ = C.workload(args.workload)
-    p = Q.plan(c, ordering=1)
-    info = p.info(0)
+    # the same plan with one launch per elimination-tree level (results in HBM), and the vertical order
+    for key, kw in (("ordering_1_level_launches", {"ordering": 1, "tree_exec": 1}),
+                    ("ordering_0", {"ordering": 0})):
+        v, p, ms, o = _amps_per_sec(Q, C, torch, np, stream, args.workload, 10, **kw)
+        info = p.info(0)
+        w = torch.empty(max(p.workspace_bytes(len(bits)), 256), dtype=torch.uint8, device=dev)
+        kms = _kernel_ms(p, bd, o, w, stream, torch)
+        rf, _ = dominant_kernel(argparse.Namespace(workload=args.workload, kernel_policy=0, no_autotune=False),
+                                p, info, len(bits), kms, None, kw.get("tree_exec", 0))
+        out[key] = {"workload": args.workload, "amplitudes_per_sec": round(v, 1), "ms_per_call": round(ms, 4),
+                    "bytes_per_amp": info["bytes_per_amp"], "max_rank": info["max_rank"], "roofline": rf}
+        print(f"# {key}: {ms:.4f} ms per call, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
+    # batch scaling on the default circuit, both launch forms of the bucket plan (graph replay)
     scale = {}
-    for Bs in (4096, 16384, 65536):
-        bs = C.random_bitstrings(c.n, Bs, 77)
-        bd = torch.from_numpy(bs.view(np.int64)).to(dev)
-        o = torch.empty((Bs, 1), dtype=torch.complex64, device=dev)
-        w = torch.empty(p.workspace_bytes(Bs), dtype=torch.uint8, device=dev)
-        g = Q.Graph([p], [bd])
-        ms = _time(lambda: g.launch(stream), 10, stream, torch)
-        p.set_timing(True)
-        for _ in range(5):
-            p.amplitudes(bd, None, out=o, workspace=w, stream=stream)
-        torch.cuda.synchronize()
-        ph, nc = p.timings()
-        p.set_timing(False)
-        rf, _ = dominant_kernel(argparse.Namespace(workload="", kernel_policy=0, no_autotune=True), p, info, Bs,
-                                ph[2] / max(nc, 1), None)
-        scale[str(Bs)] = {"amplitudes_per_sec": round(Bs / (ms / 1e3), 1), "ms_per_call": round(ms, 4),
-                          "roofline_frac": rf["frac"], "achieved_GBps": rf["achieved"]}
-        print(f"# ordering 1 B={Bs}: {ms:.3f} ms, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
-        del g, w, o
-    out["ordering_1_batch_scaling"] = {"workload": f"{args.workload} with B uniform bitstrings (seed 77), graph replay",
-                                       **scale}
+    for mode in (0, 1):
+        p = Q.plan(c, ordering=1, tree_exec=mode)
+        info = p.info(0)
+        form = "lds" if mode == 0 and info["lds_ok"] else "level_launches"
+        for Bs in (4096, 16384, 65536):
+            bs = C.random_bitstrings(c.n, Bs, 77)
+            bdx = torch.from_numpy(bs.view(np.int64)).to(dev)
+            o = torch.empty((Bs, 1), dtype=torch.complex64, device=dev)
+            w = torch.empty(max(p.workspace_bytes(Bs), 256), dtype=torch.uint8, device=dev)
+            g = Q.Graph([p], [bdx])
+            ms = _time(lambda: g.launch(stream), 10, stream, torch)
+            kms = _kernel_ms(p, bdx, o, w, stream, torch)
+            rf, _ = dominant_kernel(argparse.Namespace(workload="", kernel_policy=0, no_autotune=True), p, info, Bs,
+                                    kms, None, mode)
+            scale.setdefault(form, {})[str(Bs)] = {"amplitudes_per_sec": round(Bs / (ms / 1e3), 1),
+                                                   "ms_per_call": round(ms, 4), "roofline_bound": rf["bound"],
+                                                   "roofline_frac": rf["frac"], "achieved": rf["achieved"],
+                                                   "achieved_unit": rf["unit"]}
+            print(f"# {form} B={Bs}: {ms:.4f} ms, roofline frac {rf['frac']} ({rf['bound']})", file=sys.stderr,
+                  flush=True)
+            del g, w, o
+    out["batch_scaling"] = {"workload": f"{args.workload} with B uniform bitstrings (seed 77), graph replay",
+                            **scale}
+    # sets of amplitudes (Sec. III.A): 2^k amplitudes per bitstring with k open qubits, counted as amplitudes
+    sets = {}
+    for oq in ((0, 6, 12, 18), (0, 3, 6, 9, 12, 15, 18, 21)):
+        p = Q.plan(c, oq, ordering=1)
+        o = torch.empty((len(bits), 1 << len(oq)), dtype=torch.complex64, device=dev)
+        w = torch.empty(max(p.workspace_bytes(len(bits)), 256), dtype=torch.uint8, device=dev)
+        ms = _time(lambda: p.amplitudes(bd, None, out=o, workspace=w, stream=stream), 10, stream, torch)
+        n_amp = len(bits) << len(oq)
+        sets[f"open_{len(oq)}"] = {"open_qubits": list(oq), "amplitudes_per_call": n_amp,
+                                   "amplitudes_per_sec": round(n_amp / (ms / 1e3), 1), "ms_per_call": round(ms, 4),
+                                   "max_rank": p.info(0)["max_rank"]}
+        print(f"# sets of {1 << len(oq)} amplitudes: {ms:.4f} ms per call ({n_amp} amplitudes)", file=sys.stderr,
+              flush=True)
+        del w, o
+    out["sets_of_amplitudes"] = {"workload": f"{args.workload}, {len(bits)} bitstrings, k open qubits "
+                                             "(one level-launch plan per set; every completion of the open bits)",
+                                 **sets}
     # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2
     c, bits = C.workload("c4_5x5_d20_U")
     gv = torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
@@ -335,22 +389,35 @@ def extras(Q, C, torch, np, stream, args):
     p = Q.plan(c, ordering=args.ordering)
     one = [torch.from_numpy(bits[i:i + 1].view(np.int64)).to(dev) for i in range(64)]
     o1 = torch.empty((1, 1), dtype=torch.complex64, device=dev)
-    w1 = torch.empty(p.workspace_bytes(1), dtype=torch.uint8, device=dev)
+    w1 = torch.empty(max(p.workspace_bytes(1), 256), dtype=torch.uint8, device=dev)
     ms = _time(lambda: [p.amplitudes(b1, None, out=o1, workspace=w1, stream=stream) for b1 in one], 3, stream, torch)
     out["per_bitstring_baseline"] = {"workload": f"{c.name}, same plan, B = 1 per call, 64 calls",
                                      "amplitudes_per_sec": round(64 / (ms / 1e3), 1), "ms_per_amplitude": round(ms / 64, 4)}
     print(f"# per-bitstring baseline: {ms / 64:.3f} ms per amplitude", file=sys.stderr, flush=True)
-    # 5x6 depth 30: bucket path (no slicing needed) and vertical path with 2 sliced variables, FP64 slice sum
-    v1, p1, ms1 = _amps_per_sec(Q, C, torch, np, stream, "c3_5x6_d30", 5, ordering=1, out_c128=True)
-    v0, p0, ms0 = _amps_per_sec(Q, C, torch, np, stream, "c3_5x6_d30", 3, ordering=0, min_sliced_vars=2,
-                                out_c128=True)
-    out["c3"] = {"workload": "5x6 depth 30, 1024 bitstrings, complex128 output",
-                 "ordering_1": {"amplitudes_per_sec": round(v1, 1), "ms_per_call": round(ms1, 4),
-                                "bytes_per_amp": p1.info(0)["bytes_per_amp"]},
-                 "ordering_0_sliced_2": {"amplitudes_per_sec": round(v0, 1), "ms_per_call": round(ms0, 4),
-                                         "bytes_per_amp": p0.info(0)["bytes_per_amp"]}}
-    print(f"# c3: bucket {ms1:.3f} ms, vertical sliced {ms0:.3f} ms per 1024 amplitudes", file=sys.stderr,
-          flush=True)
+    # 5x6 depth 30: bucket path (no slicing needed) and vertical path with 2 sliced variables (FP64 slice
+    # sum) in three precisions of its steps: autotuned vector ALU, FP32 matrix cores, BF16x3 matrix cores;
+    # each against the stored FP64 state-vector amplitudes (tests/golden, written by the oracle)
+    golden = np.load(os.path.join(ROOT, "tests", "golden", "c3_5x6_d30_amps.npy"), allow_pickle=False)
+    n3 = C.workload("c3_5x6_d30")[0].n
+
+    def c3_row(**kw):
+        v, p, ms, o = _amps_per_sec(Q, C, torch, np, stream, "c3_5x6_d30", 3, out_c128=True, **kw)
+        err = np.abs(o.cpu().numpy()[:, 0] - golden) * 2 ** (n3 / 2)
+        info = p.info(0)
+        row = {"amplitudes_per_sec": round(v, 1), "ms_per_call": round(ms, 4), "bytes_per_amp": info["bytes_per_amp"],
+               "max_err_x_2^(n/2)": float(err.max()), "median_err_x_2^(n/2)": float(np.median(err))}
+        if kw.get("ordering") == 0:
+            kinds = [st["kernel"] for st in info["steps"]]
+            row["step_kernels"] = {k: kinds.count(k) for k in sorted(set(kinds))}
+        return row, ms
+    out["c3"] = {"workload": "5x6 depth 30, 1024 bitstrings, complex128 output"}
+    out["c3"]["ordering_1"], ms1 = c3_row(ordering=1)
+    for key, pol, tune in (("ordering_0_sliced_2_valu", 0, True), ("ordering_0_sliced_2_fp32_mfma", 2, False),
+                           ("ordering_0_sliced_2_bf16x3", 4, False)):
+        out["c3"][key], ms0 = c3_row(ordering=0, min_sliced_vars=2, kernel_policy=pol, autotune=tune)
+        print(f"# c3 {key}: {ms0:.3f} ms per 1024 amplitudes, max err x 2^(n/2) "
+              f"{out['c3'][key]['max_err_x_2^(n/2)']:.3g}", file=sys.stderr, flush=True)
+    print(f"# c3: bucket {ms1:.3f} ms per 1024 amplitudes", file=sys.stderr, flush=True)
     # uneven batch: 4x5 d20, 5x5 d24, 6x6 d24, 6x7 d27, 1024 bitstrings each, one graph
     names = ("c5_4x5_d20", "c5_5x5_d24", "c5_6x6_d24", "c5_6x7_d27")
     cs, bs = zip(*[C.workload(nm) for nm in names])
@@ -370,13 +437,15 @@ def extras(Q, C, torch, np, stream, args):
     nx = 1 << 22
     ax = torch.from_numpy(C.random_amplitudes(30, nx, 1).astype(np.complex64)).cuda()
     ux = torch.from_numpy(C.random_uniforms(1 << 20, 1)).cuda()
-    ms_x = _time(lambda: Q.xeb(ax, 30, stream=stream), 10, stream, torch)
-    ms_s = _time(lambda: Q.sample_from_set(ax, ux, stream=stream), 10, stream, torch)
+    wsx = Q.api.xeb_workspace(nx)
+    ox = torch.empty(8, dtype=torch.float64, device=dev)
+    ix = torch.empty(1 << 20, dtype=torch.int64, device=dev)
+    ms_x = _time(lambda: Q.xeb(ax, 30, stream=stream, workspace=wsx, out=ox), 10, stream, torch)
+    ms_s = _time(lambda: Q.sample_from_set(ax, ux, stream=stream, workspace=wsx, out=ix), 10, stream, torch)
     out["xeb"] = {"workload": "2^22 complex64 amplitudes (Porter-Thomas statistics); 2^20 draws from the set",
                   "xeb_ms": round(ms_x, 4), "xeb_read_GBps": round(8 * nx / (ms_x / 1e3) / 1e9, 1),
                   "xeb_frac_of_hbm": round(8 * nx / (ms_x / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                  "sample_set_ms": round(ms_s, 4),
-                  "note": "times include the per-call workspace allocation of the Python wrapper"}
+                  "sample_set_ms": round(ms_s, 4), "note": "workspace and outputs allocated once, outside the timing"}
     print(f"# xeb: {ms_x:.3f} ms, sample_set: {ms_s:.3f} ms", file=sys.stderr, flush=True)
     return out
 

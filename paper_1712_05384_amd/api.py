@@ -278,7 +278,15 @@ def expectation(circuit, paulis, *, ordering: int = 1, **plan_opts):
     return p.amplitudes(np.zeros(1, dtype=np.uint64)).reshape(-1)[0]
 
 
-def xeb(amps, n_qubits: int, *, stream=None):
+def xeb_workspace(B: int, device=None):
+    """A device workspace for xeb / sample_from_set over B amplitudes (allocate once, pass to every call)."""
+    import torch
+    wsb = ctypes.c_uint64()
+    N.check(N.lib().qgm_xeb_workspace_bytes(int(B), ctypes.byref(wsb)))
+    return torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def xeb(amps, n_qubits: int, *, stream=None, workspace=None, out=None):
     """Cross-entropy statistics of a batch of amplitudes (qgm_xeb, App. B): a
     float64 device tensor [sum log p, sum p, sum p log p, zeros, cross entropy
     (Eq. (cee)), fidelity (Eq. (ae), Porter-Thomas H_0 and H), entropy from a
@@ -290,10 +298,9 @@ def xeb(amps, n_qubits: int, *, stream=None):
     a = a.contiguous()
     L = N.lib()
     B = int(a.numel())
-    wsb = ctypes.c_uint64()
-    N.check(L.qgm_xeb_workspace_bytes(B, ctypes.byref(wsb)))
-    ws = torch.empty(int(wsb.value), dtype=torch.uint8, device=a.device)
-    out = torch.empty(8, dtype=torch.float64, device=a.device)
+    ws = workspace if workspace is not None else xeb_workspace(B, a.device)
+    if out is None:
+        out = torch.empty(8, dtype=torch.float64, device=a.device)
     s = stream if stream is not None else torch.cuda.current_stream(a.device)
     N.check(L.qgm_xeb(a.data_ptr(), 1 if a.dtype == torch.complex128 else 0, B, int(n_qubits), out.data_ptr(),
                       ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
@@ -323,7 +330,7 @@ def prob_sums(amps, *, out=None, stream=None):
     return out
 
 
-def sample_from_set(amps, uniforms, *, stream=None):
+def sample_from_set(amps, uniforms, *, stream=None, workspace=None, out=None):
     """Indices drawn from a set of bitstrings with probability p_j / sum p
     (qgm_sample_set, App. C); uniforms: float64 device tensor in [0, 1), one
     per draw (the caller's random numbers)."""
@@ -334,10 +341,8 @@ def sample_from_set(amps, uniforms, *, stream=None):
     u = uniforms.reshape(-1).to(a.device, torch.float64).contiguous()
     L = N.lib()
     B, m = int(a.numel()), int(u.numel())
-    wsb = ctypes.c_uint64()
-    N.check(L.qgm_xeb_workspace_bytes(B, ctypes.byref(wsb)))
-    ws = torch.empty(int(wsb.value), dtype=torch.uint8, device=a.device)
-    idx = torch.empty(max(m, 1), dtype=torch.int64, device=a.device)
+    ws = workspace if workspace is not None else xeb_workspace(B, a.device)
+    idx = out if out is not None else torch.empty(max(m, 1), dtype=torch.int64, device=a.device)
     s = stream if stream is not None else torch.cuda.current_stream(a.device)
     N.check(L.qgm_sample_set(a.data_ptr(), 1 if a.dtype == torch.complex128 else 0, B, u.data_ptr(), m,
                              idx.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))

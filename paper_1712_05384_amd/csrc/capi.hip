@@ -59,6 +59,8 @@ struct qgm_plan_s {
     std::vector<int64_t> part_off;   // per factor: first partial sum of its adjoint (n_fbar + 1 entries)
     size_t off_tpart = 0;
     size_t off_status = 0;           // int32 failure record of persistent launches (0: none since the last check)
+    // the LDS-resident program (tree plans whose results fit a work-group's LDS)
+    size_t off_lstage = 0, off_lentry = 0, off_lrec = 0, off_llvl = 0, off_lfin = 0;
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -280,7 +282,13 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_tfdep = P->off_tslot_occ + al(sizeof(int32_t) * (P->slot_occ_t.size() + 1));
     P->off_tleaf = P->off_tfdep + al(sizeof(int32_t) * 2 * (t.finals.size() + 1));
     P->off_tpart = P->off_tleaf + al(sizeof(qgm::TreeLeaf) * size_t(t.n_table_leaves + 1));
-    P->total = P->off_tpart + al(sizeof(int64_t) * P->part_off.size());
+    const qgm::LdsProgram& lp = t.lds;
+    P->off_lstage = P->off_tpart + al(sizeof(int64_t) * P->part_off.size());
+    P->off_lentry = P->off_lstage + al(sizeof(qgm::LdsStage) * (lp.stages.size() + 1));
+    P->off_lrec = P->off_lentry + al(sizeof(qgm::LdsEntry) * (lp.entries.size() + 1));
+    P->off_llvl = P->off_lrec + al(sizeof(uint16_t) * (lp.recs.size() + 8));
+    P->off_lfin = P->off_llvl + al(sizeof(int32_t) * (lp.level_job_off.size() + 1));
+    P->total = P->off_lfin + al(sizeof(int32_t) * (lp.finals.size() + 1));
 }
 
 // Adjoint tables: the forward tasks with every result at its own rows
@@ -517,6 +525,14 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
     for (const qgm::TreeStep& st : t.steps)
         if (st.table_leaf)
             lf[n_lf++] = {st.g_off, st.leaf_off, int32_t(st.out_axes.size()), st.kg, st.sb(), 0};
+    const qgm::LdsProgram& lp = t.lds;
+    if (lp.ok) {
+        std::memcpy(h + P->off_lstage, lp.stages.data(), sizeof(qgm::LdsStage) * lp.stages.size());
+        std::memcpy(h + P->off_lentry, lp.entries.data(), sizeof(qgm::LdsEntry) * lp.entries.size());
+        std::memcpy(h + P->off_lrec, lp.recs.data(), sizeof(uint16_t) * lp.recs.size());
+        std::memcpy(h + P->off_llvl, lp.level_job_off.data(), sizeof(int32_t) * lp.level_job_off.size());
+        std::memcpy(h + P->off_lfin, lp.finals.data(), sizeof(int32_t) * lp.finals.size());
+    }
     auto* fd = reinterpret_cast<int32_t*>(h + P->off_tfdep);
     for (size_t i = 0; i < t.finals.size(); ++i) {
         const qgm::TreeStep& mk = t.steps[maker[t.finals[i]]];
@@ -895,6 +911,43 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
                                       reinterpret_cast<const qgm::TreeGroup*>(tables + plan->off_tgroup), facs, fixed,
                                       slots, gt, t.ones_g, phase, int(t.phase.size()), t.phase_g, s);
         mark(2);
+        if (qgm::tree_lds(p, B)) {
+            // one work-group per bitstring, every level in LDS, then the FP64 product
+            if (!out) return fail(QGM_E_INVALID, "out is NULL");
+            const qgm::LdsProgram& lp = t.lds;
+            qgm::LdsArgs a{};
+            a.stages = reinterpret_cast<const qgm::LdsStage*>(tables + plan->off_lstage);
+            a.entries = reinterpret_cast<const qgm::LdsEntry*>(tables + plan->off_lentry);
+            a.recs = reinterpret_cast<const uint16_t*>(tables + plan->off_lrec);
+            a.phq = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
+            a.pv = reinterpret_cast<const double2*>(gt + t.phase_g);
+            a.threads = lp.threads;
+            a.n_jobs = int32_t(lp.jobs.size());
+            a.recs0 = lp.recs0;
+            a.level_job_off = reinterpret_cast<const int32_t*>(tables + plan->off_llvl);
+            a.finals = reinterpret_cast<const int32_t*>(tables + plan->off_lfin);
+            a.phase = phase;
+            a.fixed = fixed;
+            a.slots = slots;
+            a.gtab = gt;
+            a.bits = bits;
+            a.out = out;
+            a.B = B;
+            a.n_stages = int32_t(lp.stages.size());
+            a.n_entries = int32_t(lp.entries.size());
+            a.tables0 = lp.tables0;
+            a.lds_size = lp.lds_size;
+            a.n_levels = int32_t(lp.level_job_off.size()) - 1;
+            a.n_final = int32_t(lp.finals.size());
+            a.n_phase = int32_t(t.phase.size());
+            a.c128 = p.opts.out_c128 != 0 ? 1 : 0;
+            qgm::launch_tree_lds(a, s);
+            mark(3);
+            mark(4);
+            hipError_t he = hipGetLastError();
+            if (he != hipSuccess) return hip_fail(he, "kernel launch");
+            return QGM_OK;
+        }
         if (qgm::tree_persistent(p, B)) {
             // all levels and the amplitude product in one launch, every result at its own rows
             if (!out) return fail(QGM_E_INVALID, "out is NULL");

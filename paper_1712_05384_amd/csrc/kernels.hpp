@@ -266,6 +266,31 @@ struct TreeTailArgs {
     uint32_t B_eff, pad;
 };
 void launch_tree_tail(const TreeTailArgs& a, hipStream_t stream);
+
+// The LDS-resident launch of a bucket plan (tree_exec 3): one work-group of
+// a.threads threads per bitstring, kLdsHeader bytes + a.lds_size complex64
+// entries of dynamic LDS.
+struct LdsArgs {
+    const LdsStage* stages;
+    const LdsEntry* entries;
+    const uint16_t* recs;                       // [job][kLdsRecordHalves]
+    const int32_t* level_job_off;               // n_levels + 1
+    const int32_t* finals;                      // LDS byte offsets of the rank-0 results
+    const TFactor* phase;
+    const int32_t* phq;                         // per phase factor: the bits its two variables read (-1: 0;
+                                                //   -2: a two-qubit gate, evaluated from its record)
+    const double2* pv;                          // per phase factor: its 4 FP64 values (the prologue's)
+    const double2* fixed;
+    const float2* slots;
+    const float2* gtab;                         // factor tables (and leaf tables) of the call
+    const uint64_t* bits;
+    void* out;
+    int64_t B;
+    int32_t n_stages, n_entries, tables0, lds_size;
+    int32_t n_levels, n_final, n_phase, c128;
+    int32_t threads, n_jobs, recs0, pad;
+};
+void launch_tree_lds(const LdsArgs& a, hipStream_t stream);
 void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                     const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,
                     uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* phibar,

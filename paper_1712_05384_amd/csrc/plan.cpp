@@ -447,7 +447,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         return QGM_E_UNSUPPORTED;
     }
     if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
-    if (opts.tree_exec < 0 || opts.tree_exec > 2) { *err = "tree_exec must be 0..2"; return QGM_E_INVALID; }
+    if (opts.tree_exec < 0 || opts.tree_exec > 3) { *err = "tree_exec must be 0..3"; return QGM_E_INVALID; }
     if (opts.no_tile < 0 || opts.no_tile > 1) { *err = "no_tile must be 0 or 1"; return QGM_E_INVALID; }
     if (opts.order_finalists < 0 || opts.order_finalists > kTreeMaxFinalists) {
         *err = "order_finalists must be in [0, 64]";
@@ -561,6 +561,10 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
 
 bool tree_persistent(const Plan& p, int64_t) { return p.is_tree && p.opts.tree_exec == 2; }
 
+bool tree_lds(const Plan& p, int64_t) {
+    return p.is_tree && p.tree.lds.ok && (p.opts.tree_exec == 3 || p.opts.tree_exec == 0);
+}
+
 int64_t tree_flag_stride(const Plan& p) { return (p.tree.n_tasks + 31) / 32 * 32; }
 
 int64_t tree_flag_words(const Plan& p, int64_t B) {
@@ -577,6 +581,12 @@ WsLayout workspace_layout(const Plan& p, int64_t B) {
         // built once), the persistent launch's flags
         const bool persist = tree_persistent(p, B);
         w.f0 = w.f1 = 0;
+        if (tree_lds(p, B)) {   // results in LDS: only the call's factor tables when it reads gate values
+            w.g = 0;
+            w.flags = w.var_ids = p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0;
+            w.total = w.flags;
+            return w;
+        }
         w.g = al(uint64_t(persist ? p.tree.arena_rows_all : p.tree.arena_rows) * be * 8);
         w.flags = w.g + (p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0);
         w.var_ids = w.flags;
@@ -628,7 +638,11 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"order_score\":" << t.order_score << ",\"bytes_per_amp\":" << t.bytes_per_b
       << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
       << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask
-      << ",\"table_leaves\":" << t.n_table_leaves;
+      << ",\"table_leaves\":" << t.n_table_leaves
+      << ",\"lds_ok\":" << (t.lds.ok ? 1 : 0) << ",\"lds_entries\":" << t.lds.lds_size
+      << ",\"lds_jobs\":" << t.lds.jobs.size() << ",\"lds_tables0\":" << t.lds.tables0
+      << ",\"lds_threads\":" << t.lds.threads << ",\"lds_recs0\":" << t.lds.recs0
+      << ",\"lds_why\":\"" << t.lds.why << "\"";
     o << ",\"order\":"; json_ints(o, t.order);
     o << ",\"finals\":"; json_ints(o, t.finals);
     o << ",\"steps\":[],\"buckets\":[";
@@ -640,7 +654,7 @@ static std::string tree_json(const Plan& p, int detail) {
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
           << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows << ",\"tile\":" << st.tile
-          << ",\"table_leaf\":" << (st.table_leaf ? 1 : 0)
+          << ",\"table_leaf\":" << (st.table_leaf ? 1 : 0) << ",\"leaf_off\":" << st.leaf_off
           << ",\"issued_bytes_per_b\":" << 8 * st.n_tasks() * tree_unit_accesses(t, st);
         if (detail >= 1) {
             o << ",\"out_tensor\":" << st.out_tensor;
@@ -675,6 +689,46 @@ static std::string tree_json(const Plan& p, int detail) {
         o << "],\"phase\":[";
         for (size_t j = 0; j < t.phase.size(); ++j) { if (j) o << ","; json_factor(o, t.phase[j]); }
         o << "]";
+    }
+    if (detail >= 2 && t.lds.ok) {   // the LDS-resident program, for the CPU interpreter of the tests
+        const LdsProgram& L = t.lds;
+        o << ",\"lds\":{\"size\":" << L.lds_size << ",\"tables0\":" << L.tables0 << ",\"stages\":[";
+        for (size_t i = 0; i < L.stages.size(); ++i) {
+            o << (i ? "," : "") << "{\"bucket\":" << L.stage_bucket[i] << ",\"sig_q\":[";
+            for (int b = 0; b < L.stages[i].n_sig; ++b) o << (b ? "," : "") << L.stages[i].sig_q[b];
+            o << "]}";
+        }
+        o << "],\"entries\":[";
+        for (size_t i = 0; i < L.entries.size(); ++i)
+            o << (i ? "," : "") << "[" << L.entries[i].src << "," << L.entries[i].stage << "]";
+        o << "],\"jobs\":[";
+        for (size_t j = 0; j < L.jobs.size(); ++j) {
+            const LdsJob& jb = L.jobs[j];
+            o << (j ? "," : "") << "{\"bucket\":" << L.job_bucket[j] << ",\"nin\":" << jb.nin << ",\"k\":" << jb.k
+              << ",\"lanes\":" << jb.lanes << ",\"out_row\":" << (jb.out_row - kLdsHeader) / 8 << ",\"in_w\":[";
+            for (int k = 0; k < jb.nin; ++k) {
+                o << (k ? "," : "") << "[";
+                for (int w = 0; w < (1 << jb.k); ++w) o << (w ? "," : "") << jb.in_w[k][w] / 8;
+                o << "]";
+            }
+            o << "],\"tw\":[";
+            for (int w = 0; w < (1 << jb.k); ++w) o << (w ? "," : "") << jb.tw[w] / 8;
+            o << "],\"base\":[";
+            for (int sl = 0; sl <= jb.nin; ++sl)
+                o << (sl ? "," : "") << (jb.base[sl < jb.nin ? sl : kLdsMaxIn] - kLdsHeader) / 8;
+            o << "],\"str\":[";
+            for (int sl = 0; sl <= jb.nin; ++sl) {
+                o << (sl ? "," : "") << "[";
+                for (int i = 0; i < 6; ++i) o << (i ? "," : "") << jb.str[sl < jb.nin ? sl : kLdsMaxIn][i] / 8;
+                o << "]";
+            }
+            o << "]}";
+        }
+        o << "],\"level_job_off\":[";
+        for (size_t i = 0; i < L.level_job_off.size(); ++i) o << (i ? "," : "") << L.level_job_off[i];
+        o << "],\"finals\":[";
+        for (size_t i = 0; i < L.finals.size(); ++i) o << (i ? "," : "") << (L.finals[i] - kLdsHeader) / 8;
+        o << "]}";
     }
     o << "}";
     return o.str();

@@ -117,6 +117,8 @@ qgm_status expectation_circuit(const qgm_circuit* c, int32_t n_ops, const int32_
 // Bucket plans: whether qgm_amplitudes runs a batch of B in one persistent launch,
 // and the words of one bitstring group's completion flags in that launch.
 bool tree_persistent(const Plan& p, int64_t B);
+// ... or in the LDS-resident launch (one work-group per bitstring, tree_exec 3, the default when it fits)
+bool tree_lds(const Plan& p, int64_t B);
 int64_t tree_flag_stride(const Plan& p);
 int64_t tree_flag_words(const Plan& p, int64_t B);   // the whole flags area (header, ranks, flags)
 

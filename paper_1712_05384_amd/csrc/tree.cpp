@@ -769,6 +769,11 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     t = std::move(tc);
     t.n_built = int(scored.size());
     t.order_score = scored[size_t(p.opts.order_pick)].first;
+    build_lds_program(t);
+    if (p.opts.tree_exec == 3 && !t.lds.ok) {
+        *err = "tree_exec 3 (LDS-resident launch) does not fit this plan: " + t.lds.why;
+        return QGM_E_UNSUPPORTED;
+    }
     return QGM_OK;
 }
 

@@ -446,15 +446,6 @@ __device__ __forceinline__ int stage_phase(PhaseLds& P, const TFactor* __restric
     return n_lds;
 }
 
-// A factor without free variables for bitstring x, from its record.
-__device__ __forceinline__ double2 phase_factor(const TFactor& f, uint64_t x, const double2* __restrict__ fixed,
-                                                const float2* __restrict__ slots) {
-    auto bit = [&](int32_t src, int32_t b) { return src == TS_SIG ? uint32_t((x >> b) & 1ull) : 0u; };
-    uint32_t a4 = bit(f.src0, f.bit0) * 2u + bit(f.src1, f.bit1);
-    if (f.type == TF_MAT4) a4 = a4 * 4u + bit(f.src2, f.bit2) * 2u + bit(f.src3, f.bit3);
-    return factor_value_any(f, a4, fixed, slots);
-}
-
 // Product of the factors without free variables for bitstring x (FP64).
 __device__ __forceinline__ double2 phase_product(const PhaseLds& P, int n_lds, const TFactor* __restrict__ phase,
                                                  int n_phase, const double2* __restrict__ fixed,

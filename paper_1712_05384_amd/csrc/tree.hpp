@@ -151,6 +151,70 @@ struct TreeStep {
     int64_t g_entries() const { return int64_t(1) << (gb() + kg + sb()); }
 };
 
+// ---- LDS-resident execution (qgm_amplitudes, tree_exec 3) -------------------
+// One work-group per bitstring runs every level of the plan with its results
+// in LDS: the factor tables and leaf tables are first copied to LDS at the
+// bitstring's output bits, then each level's jobs (64 result rows of one
+// bucket, one row per lane) read inputs and table entries from LDS, with a
+// block barrier between levels, and thread 0 writes phase x the rank-0 results.
+// In LDS every tensor keeps its variables in decreasing order of elimination
+// (the last eliminated lowest) and a factor table is indexed (w << gb) | g, so
+// the lowest result axes of a bucket are the lowest axes of each input and of
+// its table: the lanes of a job read consecutive entries (or the same entry),
+// never two entries of one LDS bank.
+constexpr int kLdsMaxComplex = 7936;   // complex64 entries of LDS data per work-group (62 KiB)
+constexpr int kLdsMaxIn = 4;           // inputs of a bucket the LDS jobs handle
+constexpr int kLdsMaxStages = 256;     // tables copied to LDS (each with its own output bits)
+constexpr int kLdsHeader = 4 * kLdsMaxStages + 16;   // LDS bytes before the data: each table's output bits,
+                                                     //   the FP64 phase
+constexpr int kLdsSmallThreads = 256, kLdsLargeThreads = 512;   // work-group sizes (4 or 8 waves)
+
+// A factor-table or leaf-table slice: the table entries src + sigma of its
+// LdsEntry records, sigma bit i = bit sig_q[i] of the bitstring.
+struct LdsStage {
+    int32_t n_sig, pad0, pad1, pad2;
+    int32_t sig_q[kTreeMaxSig];
+};
+// lds[tables0 + e] = table area[src + sigma of stage `stage`]
+struct LdsEntry {
+    uint32_t src;
+    uint32_t stage;
+};
+// Rows o0 + l of one bucket's result, l < 64 (fewer for a small result: lanes
+// beyond `lanes` compute a copy of a valid row and store nothing).  Lane l computes
+//   R[o0 + l] = sum_w T[off_T(l) + tw[w]] * prod_t I_t[off_t(l) + in_w[t][w]]
+// with off_s(l) = base[s] + sum_{i < 6} (bit i of l) * str[s][i] for each input
+// s < nin and the table s = kLdsMaxIn.  Offsets are LDS bytes (< 64 KiB).
+struct LdsJob {
+    int32_t nin, k, lanes, out_row;
+    int32_t base[kLdsMaxIn + 1];
+    int32_t tw[8];
+    int32_t in_w[kLdsMaxIn][8];
+    int32_t str[kLdsMaxIn + 1][6];
+};
+// The device form of a job: kLdsRecordHalves 16-bit fields, 16-byte aligned:
+// [0] nin | k << 3 | (lanes - 1) << 5, [1] out_row, [2..6] base, [8..15] tw,
+// [16..47] in_w[t][w] at 16 + 8 t + w, [48..77] str[s][i] at 48 + 6 s + i.
+constexpr int kLdsRecordHalves = 80;
+constexpr int kLdsRecordBytes = 2 * kLdsRecordHalves;
+struct LdsProgram {
+    bool ok = false;
+    std::string why;                     // reason when not ok
+    int32_t lds_size = 0;                // complex64 entries of LDS data (results, tables, job records)
+    int32_t tables0 = 0;                 // first entry of the copied tables
+    int32_t recs0 = -1;                  // first entry of the job records in LDS (-1: read from memory)
+    int32_t threads = 0;                 // work-group size
+    std::vector<LdsStage> stages;
+    std::vector<int32_t> stage_bucket;   // bucket of each stage
+    std::vector<LdsEntry> entries;
+    std::vector<LdsJob> jobs;
+    std::vector<int32_t> job_bucket;
+    std::vector<uint16_t> recs;          // [job][kLdsRecordHalves]
+    std::vector<int32_t> level_job_off;  // jobs of level L: [off[L], off[L + 1])
+    std::vector<int32_t> finals;         // LDS byte offsets of the rank-0 results
+    std::vector<int32_t> tensor_lds;     // LDS data entry of each result's row 0 (-1: none)
+};
+
 struct TreePlan {
     std::vector<int> order;                      // elimination order (variable ids)
     std::vector<TreeStep> steps;                 // in elimination order
@@ -200,7 +264,12 @@ struct TreePlan {
     double order_score = 0;                      // the kept plan's score (issued bytes + launches)
     double bytes_per_b = 0;                      // algorithmic HBM bytes per bitstring
     double flops_per_b = 0;
+    LdsProgram lds;                              // the LDS-resident program (lds.ok when the plan fits)
 };
+
+// Builds t.lds from a finished bucket plan (sets t.lds.ok = false with a reason
+// when the plan does not fit: open qubits, more than kLdsMaxIn inputs, LDS size).
+void build_lds_program(TreePlan& t);
 
 // Builds the bucket plan from the variables and gate records in `p`
 // (ordering 1; no open qubits, no slicing).

@@ -50,6 +50,15 @@ __device__ __forceinline__ double2 factor_value_any(const TFactor& f, uint32_t a
     return factor_value(f, (a4 >> 1) & 1u, a4 & 1u, fixed, slots);
 }
 
+// A factor without free variables for bitstring x, from its record.
+__device__ __forceinline__ double2 phase_factor(const TFactor& f, uint64_t x, const double2* __restrict__ fixed,
+                                                const float2* __restrict__ slots) {
+    auto bit = [&](int32_t src, int32_t b) { return src == TS_SIG ? uint32_t((x >> b) & 1ull) : 0u; };
+    uint32_t a4 = bit(f.src0, f.bit0) * 2u + bit(f.src1, f.bit1);
+    if (f.type == TF_MAT4) a4 = a4 * 4u + bit(f.src2, f.bit2) * 2u + bit(f.src3, f.bit3);
+    return factor_value_any(f, a4, fixed, slots);
+}
+
 constexpr int kTreeMaxPrologueFactors = 64;
 constexpr int kTreeMaxPhaseLds = 512;
 

@@ -1,0 +1,287 @@
+// LDS-resident bucket elimination (qgm_amplitudes with tree_exec 3, gfx950).
+//
+// Work-group b evaluates App. A's buckets for bitstring b alone: every result
+// of the elimination tree lives in the work-group's LDS, so the launch reads
+// from HBM only the bitstring, the table entries at its output bits (the
+// deltas of Eq. (psi_x) select them) and its job records, and writes one
+// amplitude.  The waves share each level's jobs (64 result rows of one bucket,
+// one row per lane): lane l multiplies the factor-table entry of its row and
+// summed value w by its input rows, sums over w, and stores the row; a block
+// barrier separates levels, as a level reads only results of earlier levels.
+// A job record holds the LDS byte offsets at its first row and the strides of
+// the six lane bits; the records are copied to LDS with the tables when they
+// fit, so after the first burst of loads the levels touch no memory.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "tree_dev.hpp"
+
+namespace qgm {
+
+using namespace tree_dev;
+
+namespace {
+
+constexpr int kLdsBatchLoads = 12;
+
+// 16 bytes of a job record (LDS or memory; the address is wave-uniform).
+__device__ __forceinline__ uint4 rec16(const char* __restrict__ rp, int byte) {
+    return *reinterpret_cast<const uint4*>(rp + byte);
+}
+__device__ __forceinline__ uint32_t rec4(const char* __restrict__ rp, int byte) {
+    return *reinterpret_cast<const uint32_t*>(rp + byte);
+}
+__device__ __forceinline__ uint32_t half(uint4 v, int i) {   // 16-bit field i of a 16-byte word
+    const uint32_t d = (i >> 1) == 0 ? v.x : (i >> 1) == 1 ? v.y : (i >> 1) == 2 ? v.z : v.w;
+    return (i & 1) ? d >> 16 : d & 0xFFFFu;
+}
+
+// Lane offset of slot s: base + sum_i (bit i of the lane) * stride i, the six
+// 16-bit strides at record bytes 96 + 12 s (one 24-bit multiply-add each).
+__device__ __forceinline__ uint32_t lane_off(const char* __restrict__ rp, int s, uint32_t base,
+                                             const uint32_t (&lb)[6]) {
+    const uint32_t d0 = rec4(rp, 96 + 12 * s), d1 = rec4(rp, 100 + 12 * s), d2 = rec4(rp, 104 + 12 * s);
+    uint32_t o = base;
+    o = __umul24(lb[0], d0 & 0xFFFFu) + o;
+    o = __umul24(lb[1], d0 >> 16) + o;
+    o = __umul24(lb[2], d1 & 0xFFFFu) + o;
+    o = __umul24(lb[3], d1 >> 16) + o;
+    o = __umul24(lb[4], d2 & 0xFFFFu) + o;
+    o = __umul24(lb[5], d2 >> 16) + o;
+    return o;
+}
+
+// One job: rows out_row + lane of its bucket's result (lanes < the record's
+// count); h is the record's first 16 bytes, rp the record, L the work-group's LDS.
+template <int NIN, int K>
+__device__ __forceinline__ void lds_job(uint4 h, uint32_t lanes, const char* __restrict__ rp, char* __restrict__ L,
+                                        const uint32_t (&lb)[6], uint32_t lane) {
+    constexpr int W = 1 << K;
+    constexpr int NR = NIN > 0 ? NIN : 1;
+    const uint4 tw = rec16(rp, 16);
+    uint4 iw[NR];
+#pragma unroll
+    for (int t = 0; t < NIN; ++t) iw[t] = rec16(rp, 32 + 16 * t);
+    uint32_t row[NR];
+#pragma unroll
+    for (int t = 0; t < NIN; ++t) row[t] = lane_off(rp, t, half(h, 2 + t), lb);
+    const uint32_t tb = lane_off(rp, kLdsMaxIn, half(h, 2 + kLdsMaxIn), lb);
+    float2 q[W], v[NR][W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) q[w] = *reinterpret_cast<const float2*>(L + tb + half(tw, w));
+#pragma unroll
+    for (int t = 0; t < NIN; ++t)
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[t][w] = *reinterpret_cast<const float2*>(L + row[t] + half(iw[t], w));
+    // every load of a job with at most kLdsBatchLoads loads is issued before the first product: the
+    // values pass through empty asm statements, so the compiler cannot interleave the loads with the
+    // arithmetic (one LDS round trip per job instead of one per summed value; larger jobs would hold
+    // more registers than the occupancy allows)
+    if constexpr ((NIN + 1) * W <= kLdsBatchLoads) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) asm volatile("" : "+v"(q[w].x), "+v"(q[w].y));
+#pragma unroll
+        for (int t = 0; t < NIN; ++t)
+#pragma unroll
+            for (int w = 0; w < W; ++w) asm volatile("" : "+v"(v[t][w].x), "+v"(v[t][w].y));
+    }
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        if constexpr (NIN == 0) {
+            acc.x += q[w].x;
+            acc.y += q[w].y;
+        } else {
+            float2 pw = q[w];
+#pragma unroll
+            for (int t = 0; t + 1 < NIN; ++t) pw = cmulf(pw, v[t][w]);
+            const float2 l = v[NIN - 1][w];   // the last factor goes into the sum as fused multiply-adds
+            acc.x = fmaf(pw.x, l.x, acc.x);
+            acc.x = fmaf(-pw.y, l.y, acc.x);
+            acc.y = fmaf(pw.x, l.y, acc.y);
+            acc.y = fmaf(pw.y, l.x, acc.y);
+        }
+    }
+    if (lane < lanes) *reinterpret_cast<float2*>(L + (h.x >> 16) + 8 * lane) = acc;
+}
+
+template <int NIN>
+__device__ __forceinline__ void lds_job_k(int k, uint4 h, uint32_t lanes, const char* __restrict__ rp,
+                                          char* __restrict__ L, const uint32_t (&lb)[6], uint32_t lane) {
+    switch (k) {
+        case 0: lds_job<NIN, 0>(h, lanes, rp, L, lb, lane); break;
+        case 1: lds_job<NIN, 1>(h, lanes, rp, L, lb, lane); break;
+        case 2: lds_job<NIN, 2>(h, lanes, rp, L, lb, lane); break;
+        default: lds_job<NIN, 3>(h, lanes, rp, L, lb, lane); break;
+    }
+}
+
+// The FP64 product of the factors without free variables for bitstring x, on
+// one wave, in a fixed order: lane partial products (factor i on lane i mod 64)
+// from lane_phase, then a butterfly (phase_butterfly) whose lane-0 result is
+// written to *phase_v.  The first 64 factors' values (pv0..pv3 at the bits pq)
+// come from the launch's first burst of loads; a two-qubit gate's factor is
+// evaluated from its record.
+__device__ __forceinline__ double2 lane_phase(const LdsArgs& a, uint64_t x, uint32_t lane, int2 pq, double2 pv0,
+                                              double2 pv1, double2 pv2, double2 pv3) {
+    double2 ph = make_double2(1.0, 0.0);
+    if (int(lane) < a.n_phase) {
+        const uint32_t e = (pq.x >= 0 ? uint32_t((x >> pq.x) & 1ull) * 2u : 0u) +
+                           (pq.y >= 0 ? uint32_t((x >> pq.y) & 1ull) : 0u);
+        ph = e == 0 ? pv0 : e == 1 ? pv1 : e == 2 ? pv2 : pv3;
+        if (pq.x == -2) ph = phase_factor(a.phase[lane], x, a.fixed, a.slots);
+    }
+    for (int i = int(lane) + 64; i < a.n_phase; i += 64) {   // more than 64 phase factors
+        const int2 q = reinterpret_cast<const int2*>(a.phq)[i];
+        const uint32_t e = (q.x >= 0 ? uint32_t((x >> q.x) & 1ull) * 2u : 0u) +
+                           (q.y >= 0 ? uint32_t((x >> q.y) & 1ull) : 0u);
+        ph = cmuld(ph, q.x == -2 ? phase_factor(a.phase[i], x, a.fixed, a.slots) : a.pv[4 * i + e]);
+    }
+    return ph;
+}
+
+__device__ __forceinline__ void phase_butterfly(double2 ph, uint32_t lane, double2* phase_v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const double2 o = make_double2(__shfl_xor(ph.x, m, 64), __shfl_xor(ph.y, m, 64));
+        ph = cmuld(ph, o);
+    }
+    if (lane == 0) *phase_v = ph;
+}
+
+}  // namespace
+
+// The launch: work-group b evaluates bitstring b with NT threads; RL: the job
+// records are in LDS (copied with the tables), else read from memory.  LDS (all
+// of it dynamic, so record offsets are absolute): the output bits of each table
+// slice, the FP64 phase, then the data (results, table slices, job records).
+template <int NT, bool RL>
+__global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) char L[];
+    uint32_t* sig = reinterpret_cast<uint32_t*>(L);
+    double2* phase_v = reinterpret_cast<double2*>(L + 4 * kLdsMaxStages);
+    float2* data = reinterpret_cast<float2*>(L + kLdsHeader);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t b = blockIdx.x;
+    const uint64_t x = a.bits[b];
+    // Everything the levels read from memory, in one burst of loads issued before any is waited for: the
+    // table entries' descriptors and the job records (independent of the bitstring; records as 16-byte
+    // words), the stage records, the phase factors' values.  Indices are clamped to valid entries (the
+    // arrays are never empty), so no load is conditional.
+    constexpr int R = 4;
+    const int n_e = a.n_entries;
+    LdsEntry en[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) en[i] = a.entries[min(i * NT + int(tid), max(n_e - 1, 0))];
+    const int n_rw = RL ? a.n_jobs * (kLdsRecordBytes / 16) : 0;
+    const uint4* __restrict__ rsrc = reinterpret_cast<const uint4*>(a.recs);
+    uint4* rdst = reinterpret_cast<uint4*>(L + kLdsHeader + 8 * a.recs0);
+    uint4 rw[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) rw[i] = rsrc[min(i * NT + int(tid), max(n_rw - 1, 0))];
+#pragma unroll
+    for (int i = 0; i < R; ++i) asm volatile("" : "+v"(rw[i].x), "+v"(rw[i].y), "+v"(rw[i].z), "+v"(rw[i].w));
+    // the stage record of stage tid (n_sig, then the 12 qubits)
+    static_assert(sizeof(LdsStage) == 64 && kTreeMaxSig == 12, "stage records are four 16-byte words");
+    const int4* sp = reinterpret_cast<const int4*>(a.stages + min(int(tid), max(a.n_stages - 1, 0)));
+    const int4 sh0 = sp[0], sq0 = sp[1], sq1 = sp[2], sq2 = sp[3];
+    // the phase factor of lane tid of the last wave: the bits its variables read and its 4 FP64 values (its
+    // product is formed in the last level)
+    const int ip = min(int(lane), max(a.n_phase - 1, 0));
+    const int2 pq = reinterpret_cast<const int2*>(a.phq)[ip];
+    const double2 pv0 = a.pv[4 * ip], pv1 = a.pv[4 * ip + 1], pv2 = a.pv[4 * ip + 2], pv3 = a.pv[4 * ip + 3];
+    // now the values
+    const double2 ph = wave == NW - 1 ? lane_phase(a, x, lane, pq, pv0, pv1, pv2, pv3) : make_double2(1.0, 0.0);
+    if (int(tid) < a.n_stages) {
+        const int q[12] = {sq0.x, sq0.y, sq0.z, sq0.w, sq1.x, sq1.y, sq1.z, sq1.w, sq2.x, sq2.y, sq2.z, sq2.w};
+        uint32_t g = 0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if (i < sh0.x) g |= uint32_t((x >> q[i]) & 1ull) << i;
+        sig[tid] = g;
+    }
+    for (int s2 = int(tid) + NT; s2 < a.n_stages; s2 += NT) {   // more stages than threads
+        const LdsStage& st = a.stages[s2];
+        sig[s2] = gather_sigma(x, st.sig_q, st.n_sig);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        if (i * NT + int(tid) < n_rw) rdst[i * NT + int(tid)] = rw[i];
+    for (int i = R * NT + int(tid); i < n_rw; i += NT) rdst[i] = rsrc[i];   // more record words than one round
+    __syncthreads();
+    // the table slices: R entries per thread per round, every load issued before any store
+    for (int e0 = 0; e0 < n_e;) {
+        uint32_t sg[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) sg[i] = sig[en[i].stage];
+        float2 v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = a.gtab[int64_t(en[i].src) + sg[i]];
+        const int e1 = e0 + R * NT;
+        if (e1 < n_e) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) en[i] = a.entries[min(e1 + i * NT + int(tid), n_e - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int e = e0 + i * NT + int(tid);
+            if (e < n_e) data[a.tables0 + e] = v[i];
+        }
+        e0 = e1;
+    }
+    uint32_t lb[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) lb[i] = (lane >> i) & 1u;
+    const char* __restrict__ recs = RL ? L + kLdsHeader + 8 * a.recs0 : reinterpret_cast<const char*>(a.recs);
+    __syncthreads();
+    for (int lv = 0; lv < a.n_levels; ++lv) {
+        const int j1 = a.level_job_off[lv + 1];
+        for (int j = a.level_job_off[lv] + int(wave); j < j1; j += NW) {
+            const char* __restrict__ rp = recs + j * kLdsRecordBytes;
+            const uint4 h = rec16(rp, 0);
+            const uint32_t hd = __builtin_amdgcn_readfirstlane(h.x & 0xFFFFu);
+            const uint32_t lanes = ((hd >> 5) & 63u) + 1u;
+            const int k = int((hd >> 3) & 3u);
+            switch (hd & 7u) {
+                case 0: lds_job_k<0>(k, h, lanes, rp, L, lb, lane); break;
+                case 1: lds_job_k<1>(k, h, lanes, rp, L, lb, lane); break;
+                case 2: lds_job_k<2>(k, h, lanes, rp, L, lb, lane); break;
+                case 3: lds_job_k<3>(k, h, lanes, rp, L, lb, lane); break;
+                default: lds_job_k<4>(k, h, lanes, rp, L, lb, lane); break;
+            }
+        }
+        // the phase product on the last wave during the last level (it usually has no job there)
+        if (lv == a.n_levels - 1 && wave == NW - 1) phase_butterfly(ph, lane, phase_v);
+        __syncthreads();
+    }
+    if (a.n_levels == 0) {
+        if (wave == NW - 1) phase_butterfly(ph, lane, phase_v);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double2 acc = *phase_v;
+        for (int f = 0; f < a.n_final; ++f) {
+            const float2 r = *reinterpret_cast<const float2*>(L + a.finals[f]);
+            acc = cmuld(acc, make_double2(r.x, r.y));
+        }
+        if (a.c128) static_cast<double2*>(a.out)[b] = acc;
+        else static_cast<float2*>(a.out)[b] = make_float2(float(acc.x), float(acc.y));
+    }
+}
+
+void launch_tree_lds(const LdsArgs& a, hipStream_t stream) {
+    if (a.B <= 0) return;
+    const size_t sh = size_t(kLdsHeader) + size_t(a.lds_size) * sizeof(float2);
+    const dim3 g(uint32_t(a.B));
+    constexpr int S = kLdsSmallThreads, G = kLdsLargeThreads;
+    const bool rl = a.recs0 >= 0;
+    if (a.threads == G && rl) hipLaunchKernelGGL((k_tree_lds<G, true>), g, dim3(G), sh, stream, a);
+    else if (a.threads == G) hipLaunchKernelGGL((k_tree_lds<G, false>), g, dim3(G), sh, stream, a);
+    else if (rl) hipLaunchKernelGGL((k_tree_lds<S, true>), g, dim3(S), sh, stream, a);
+    else hipLaunchKernelGGL((k_tree_lds<S, false>), g, dim3(S), sh, stream, a);
+}
+
+}  // namespace qgm

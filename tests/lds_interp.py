@@ -1,0 +1,100 @@
+"""CPU interpreter of the LDS-resident program of a bucket plan (qgm_amplitudes
+with tree_exec 3), complex128.
+
+It executes the program the planner exports (plan JSON detail 2, "lds"): the
+table slices copied at a bitstring's output bits, then level by level the jobs
+-- 64 result rows of one bucket, lane l reading its inputs and the factor-table
+slice at the job's base offsets plus the strides of its six lane bits plus the
+per-summed-value offsets --
+and finally phase x the rank-0 results.  Every LDS entry read must have been
+written (entries start as NaN) and stay inside the program's LDS size, and
+no level may write an entry that the same level reads, which is what the
+kernel's one barrier per level relies on.  The table contents come from the
+bucket definitions of the same JSON (the semantics the device's table
+builder implements).  It is neither the oracle nor a fallback of the product
+path.
+"""
+import numpy as np
+
+from tree_interp import TS_SIG, _eval, bucket_table
+
+
+def _table_area(info, gate_vals):
+    """The table area as the device builds it, as a dict offset -> value:
+    bucket s's factor table at g_off, entry (c << sb) | sigma with
+    c = (g << kg) | w, and a leaf bucket's result table at leaf_off, entry
+    (o << sb) | sigma with o over the result's axes in the planner's order."""
+    area = {}
+    for st in info["buckets"]:
+        G = bucket_table(st, gate_vals)             # [2^(gb + kg), 2^sb]
+        sb, kg = st["sb"], st["kg"]
+        if not st["table_leaf"]:
+            for c in range(G.shape[0]):
+                for sg in range(G.shape[1]):
+                    area[st["g_off"] + (c << sb) + sg] = G[c, sg]
+            continue
+        gpos = {v: j for j, v in enumerate(st["gvars"])}
+        for o in range(1 << st["r_out"]):
+            g = 0
+            for j, ax in enumerate(st["out_axes"]):
+                g |= ((o >> j) & 1) << gpos[ax]
+            for sg in range(1 << sb):
+                area[st["leaf_off"] + (o << sb) + sg] = sum(G[(g << kg) | w, sg] for w in range(1 << kg))
+    return area
+
+
+def run_lds_program(info, gate_vals, bits):
+    """Amplitudes complex128 [B] of a detail-2 plan with an LDS program."""
+    L = info["lds"]
+    area = _table_area(info, gate_vals)
+    size = L["size"]
+    out = np.zeros(len(bits), dtype=np.complex128)
+    stage_q = [st["sig_q"] for st in L["stages"]]
+    for bi, x in enumerate(np.asarray(bits, dtype=np.uint64)):
+        x = int(x)
+        lds = np.full(size, np.nan, dtype=np.complex128)
+        sig = [sum(((x >> q) & 1) << i for i, q in enumerate(sq)) for sq in stage_q]
+        for e, (src, s) in enumerate(L["entries"]):
+            dst = L["tables0"] + e
+            assert 0 <= dst < size
+            lds[dst] = area[src + sig[s]]
+        offs = L["level_job_off"]
+        for lv in range(len(offs) - 1):
+            writes, reads = {}, set()
+            for j in range(offs[lv], offs[lv + 1]):
+                jb = L["jobs"][j]
+                nin, k, lanes = jb["nin"], jb["k"], jb["lanes"]
+                for lane in range(64):
+                    # the lane's offsets: the job's base plus the strides of the lane's six bits (inputs, then
+                    # the table)
+                    off = [jb["base"][sl] + sum(((lane >> i) & 1) * jb["str"][sl][i] for i in range(6))
+                           for sl in range(nin + 1)]
+                    acc = 0j
+                    for w in range(1 << k):
+                        a = off[nin] + jb["tw"][w]
+                        assert 0 <= a < size
+                        v = lds[a]
+                        reads.add(a)
+                        for t in range(nin):
+                            a = off[t] + jb["in_w"][t][w]
+                            assert 0 <= a < size, (j, lane, t, w, a)
+                            reads.add(a)
+                            v = v * lds[a]
+                        acc += v
+                    if lane < lanes:
+                        dst = jb["out_row"] + lane
+                        assert 0 <= dst < L["tables0"], (j, lane, dst)
+                        assert not np.isnan(acc), (lv, j, lane)
+                        assert dst not in writes
+                        writes[dst] = acc
+            assert not (set(writes) & reads), "a level writes an entry it reads"
+            for d, v in writes.items():
+                lds[d] = v
+        amp = 1.0 + 0j
+        for f in info["phase"]:
+            amp = amp * complex(_eval(f, lambda src, bit: ((x >> bit) & 1) if src == TS_SIG else 0, gate_vals))
+        for fr in L["finals"]:
+            assert not np.isnan(lds[fr])
+            amp *= lds[fr]
+        out[bi] = amp
+    return out

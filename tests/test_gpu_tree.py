@@ -1,5 +1,7 @@
 """GPU parity of the bucket-elimination path (ordering 1: greedy treewidth
-order, one launch per elimination-tree level) against the FP64 oracle.
+order) against the FP64 oracle, in both of its launch forms: one launch per
+elimination-tree level (tree_exec 1) and one work-group per bitstring with
+every result in LDS (tree_exec 3, the default when the plan fits).
 
 Same tolerance as the vertical path: max |A_gpu - A_oracle| <= 1e-5 * 2^{-n/2}.
 """
@@ -58,33 +60,39 @@ def test_tree_c1_full_batch():
     assert np.abs(got1 - ref).max() <= TOL * 2 ** (-c.n / 2)
 
 
+@pytest.mark.parametrize("mode", [1, 3])
 @pytest.mark.parametrize("B", [1, 5, 63, 64, 65, 130])
-def test_tree_ragged_batches(B):
+def test_tree_ragged_batches(B, mode):
     c = C.random_grid_circuit(3, 4, 12, 7)
     bits = C.random_bitstrings(c.n, B, 7)
-    _say("case tree 3x4_d12 B=%d" % B)
-    got = _amps(_tree(c), bits)
+    _say("case tree 3x4_d12 B=%d tree_exec %d" % (B, mode))
+    got = _amps(_tree(c, tree_exec=mode), bits)
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
 
 
-@pytest.mark.parametrize("rows,cols,depth,seed", [(1, 1, 3, 1), (2, 2, 1, 2), (1, 5, 12, 3), (4, 4, 24, 4),
-                                                  (3, 5, 20, 5), (4, 5, 16, 6), (5, 4, 30, 16)])
-def test_tree_random_circuits(rows, cols, depth, seed):
+_RANDOM = [(1, 1, 3, 1), (2, 2, 1, 2), (1, 5, 12, 3), (4, 4, 24, 4), (3, 5, 20, 5), (4, 5, 16, 6), (5, 4, 30, 16)]
+
+
+# the 5x4 depth-30 plan's factor tables exceed a work-group's LDS: level launches only
+@pytest.mark.parametrize("rows,cols,depth,seed,mode", [r + (m,) for r in _RANDOM for m in (1, 3)
+                                                       if not (m == 3 and r == (5, 4, 30, 16))])
+def test_tree_random_circuits(rows, cols, depth, seed, mode):
     c = C.random_grid_circuit(rows, cols, depth, seed)
     bits = C.random_bitstrings(c.n, 256, seed)
-    _say("case tree %s B=256" % c.name)
-    got = _amps(_tree(c), bits)
+    _say("case tree %s B=256 tree_exec %d" % (c.name, mode))
+    got = _amps(_tree(c, tree_exec=mode), bits)
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
 
 
-def test_tree_gate_values_and_c128():
+@pytest.mark.parametrize("mode", [1, 3])
+def test_tree_gate_values_and_c128(mode):
     c = C.parameterised_circuit(4, 4, 14, 8)
     bits = C.random_bitstrings(c.n, 128, 8)
     gv = c.gate_vals.astype(np.complex64)
-    _say("case tree %s B=128 (gate_vals, complex128 out)" % c.name)
-    got = _amps(_tree(c, out_c128=True), bits, torch.tensor(gv))
+    _say("case tree %s B=128 (gate_vals, complex128 out) tree_exec %d" % (c.name, mode))
+    got = _amps(_tree(c, out_c128=True, tree_exec=mode), bits, torch.tensor(gv))
     assert got.dtype == np.complex128
     ref = oracle.sv_amplitudes(c.n, c.gates, gv.astype(np.complex128), bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
@@ -273,7 +281,7 @@ def test_tree_tail_reads_leaf_tables(rows, cols, depth, seed):
     """Buckets of the last levels (run from LDS in one work-group per group)
     whose inputs include leaf tables read from the table area."""
     c = C.random_grid_circuit(rows, cols, depth, seed)
-    p = _tree(c)
+    p = _tree(c, tree_exec=1)
     assert _tail_table_inputs(p.info(1)) > 0
     bits = C.random_bitstrings(c.n, 130, seed)
     _say("case tree tail leaf tables %s" % c.name)
@@ -289,7 +297,7 @@ def test_tree_tail_many_phase_factors_60_qubits():
     n = 60
     g = _shifted(blk, 0) + [(C.H, 0, q, -1, -1) for q in range(12, n)] + [(C.T, 1, q, -1, -1) for q in range(12, n)]
     c = C.Circuit(1, n, np.array(g, dtype=np.int32))
-    p = _tree(c, order_restarts=16, order_finalists=1)   # this plan has tail levels
+    p = _tree(c, order_restarts=16, order_finalists=1, tree_exec=1)   # this plan has tail levels
     info = p.info(0)
     assert info["n_phase"] > 64 and info["tail_levels"] > 0
     bits = C.random_bitstrings(n, 200, 11)
@@ -309,7 +317,7 @@ def test_tree_tail_with_final_from_the_arena():
     a = C.random_grid_circuit(2, 2, 6, 5)
     b = C.random_grid_circuit(4, 4, 16, 6)
     c = C.Circuit(1, 20, np.array(_shifted(a, 0) + _shifted(b, 4), dtype=np.int32))
-    p = _tree(c)
+    p = _tree(c, tree_exec=1)
     info = p.info(1)
     made = {bk["out_tensor"]: bk["level"] for bk in info["buckets"]}
     levels = [made[f] for f in info["finals"]]
@@ -326,13 +334,13 @@ def test_tree_tile_units(rows, cols, depth, seed, B):
     the oracle, and the same plan without them."""
     import paper_1712_05384_amd as Q
     c = C.random_grid_circuit(rows, cols, depth, seed)
-    p = Q.plan(c, ordering=1)
+    p = Q.plan(c, ordering=1, tree_exec=1)
     n_tiles = sum(1 for bk in p.info(1)["buckets"] if bk["tile"])
     bits = C.random_bitstrings(c.n, B, seed)
     _say("case tree tiles %s (%d tile buckets) B=%d" % (c.name, n_tiles, B))
     got = _amps(p, bits)
     assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits)).max() <= TOL * 2 ** (-c.n / 2)
-    plain = _amps(Q.plan(c, ordering=1, tile=False), bits)
+    plain = _amps(Q.plan(c, ordering=1, tile=False, tree_exec=1), bits)
     assert np.abs(got - plain).max() <= TOL * 2 ** (-c.n / 2)
 
 
@@ -347,7 +355,7 @@ def test_tree_tile_units_c3_and_parameterised():
     got = _amps(p, bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
     cp, _ = C.workload("c4_5x5_d20_U")
-    pp = Q.plan(cp, ordering=1)
+    pp = Q.plan(cp, ordering=1, tree_exec=1)
     assert sum(1 for bk in pp.info(1)["buckets"] if bk["tile"]) >= 1
     bits2 = C.random_bitstrings(cp.n, 70, 8)
     gv = cp.gate_vals.astype(np.complex64)
@@ -362,7 +370,7 @@ def test_tree_tile_units_ragged_batches_c128(B):
     complex128 output, and a circuit with gate values whose plan has tiles."""
     import paper_1712_05384_amd as Q
     c = C.random_grid_circuit(4, 5, 20, 2)
-    p = Q.plan(c, ordering=1, out_c128=True)
+    p = Q.plan(c, ordering=1, out_c128=True, tree_exec=1)
     assert any(bk["tile"] for bk in p.info(1)["buckets"])
     bits = C.random_bitstrings(c.n, B, 40 + B)
     _say("case tree tiles ragged B=%d c128" % B)
@@ -370,9 +378,62 @@ def test_tree_tile_units_ragged_batches_c128(B):
     assert got.dtype == np.complex128
     assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits)).max() <= TOL * 2 ** (-c.n / 2)
     cp, _ = C.workload("c4_5x5_d20_U")
-    pp = Q.plan(cp, ordering=1)
+    pp = Q.plan(cp, ordering=1, tree_exec=1)
     gv = cp.gate_vals.astype(np.complex64)
     bits2 = C.random_bitstrings(cp.n, B, 50 + B)
     got2 = _amps(pp, bits2, torch.tensor(gv))
     ref2 = oracle.sv_amplitudes(cp.n, cp.gates, gv.astype(np.complex128), bits2)
     assert np.abs(got2 - ref2).max() <= TOL * 2 ** (-cp.n / 2)
+
+
+@pytest.mark.parametrize("name", ["c2_5x5_d25", "c5_4x5_d20", "c5_5x5_d24"])
+def test_tree_lds_workloads_against_state_vector(name):
+    """Full-size workloads (1024 bitstrings) in the LDS-resident launch against
+    the FP64 state vector, and against the level launches of the same plan."""
+    c, bits = C.workload(name)
+    p = _tree(c, tree_exec=3)
+    assert p.info(0)["lds_ok"] == 1
+    _say("case tree lds %s B=%d" % (name, len(bits)))
+    got = _amps(p, bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    err = np.abs(got - ref).max()
+    _say("  lds %s max err * 2^(n/2) = %.3g" % (name, err * 2 ** (c.n / 2)))
+    assert err <= TOL * 2 ** (-c.n / 2)
+    lev = _amps(_tree(c, tree_exec=1), bits)
+    assert np.abs(got - lev).max() <= TOL * 2 ** (-c.n / 2)
+
+
+def test_tree_lds_36_qubits_and_gradient_workload():
+    """6x6 depth 24 (44 KiB of LDS per work-group) against the level launches and
+    the FP64 bucket oracle on 8 bitstrings; the parameterised 5x5 depth-20
+    circuit (tables from gate values each call) against the state vector."""
+    c, bits = C.workload("c5_6x6_d24")
+    p = _tree(c, tree_exec=3)
+    assert p.info(0)["lds_ok"] == 1
+    _say("case tree lds c5_6x6_d24 B=%d" % len(bits))
+    got = _amps(p, bits)
+    lev = _amps(_tree(c, tree_exec=1), bits)
+    assert np.abs(got - lev).max() <= TOL * 2 ** (-c.n / 2)
+    ref = oracle.bucket_amplitudes(c.n, c.gates, None, bits[:8])
+    assert np.abs(got[:8] - ref).max() <= TOL * 2 ** (-c.n / 2)
+    cp, bp = C.workload("c4_5x5_d20_U")
+    gv = cp.gate_vals.astype(np.complex64)
+    _say("case tree lds c4 B=%d" % len(bp))
+    got2 = _amps(_tree(cp, tree_exec=3, out_c128=True), bp, torch.tensor(gv))
+    ref2 = oracle.sv_amplitudes(cp.n, cp.gates, gv.astype(np.complex128), bp)
+    assert np.abs(got2 - ref2).max() <= TOL * 2 ** (-cp.n / 2)
+
+
+def test_tree_lds_repeat_and_graph():
+    """The LDS launch gives the same bits on repeated calls and in a graph replay."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c2_5x5_d25")
+    p = _tree(c, tree_exec=3)
+    a = p.amplitudes(bits).cpu().numpy()
+    for _ in range(2):
+        assert np.array_equal(p.amplitudes(bits).cpu().numpy(), a)
+    g = Q.Graph([p], [bits], [None])
+    for _ in range(3):
+        out = g.launch()[0].cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(out, a)

@@ -347,17 +347,22 @@ def test_order_finalists_scored_by_issued_bytes():
 
 def test_tree_exec_modes_and_persistent_workspace():
     """tree_exec 2 keeps every result at its own rows and adds completion
-    flags; 0 (auto) and 1 run one launch per level."""
+    flags; 1 runs one launch per level; 3 (and 0, auto, when the plan fits)
+    keeps every result in LDS, so it needs no arena (only the per-call factor
+    tables of a circuit with gate values)."""
     import paper_1712_05384_amd as Q
     c = C.random_grid_circuit(4, 4, 16, 2)
     per = Q.plan(c, ordering=1, tree_exec=2)
     lev = Q.plan(c, ordering=1, tree_exec=1)
+    lds = Q.plan(c, ordering=1, tree_exec=3)
     auto = Q.plan(c, ordering=1)
     assert per.workspace_bytes(1024) > lev.workspace_bytes(1024)
-    assert auto.workspace_bytes(1024) == lev.workspace_bytes(1024)
+    assert auto.workspace_bytes(1024) == lds.workspace_bytes(1024) == 0
     assert per.workspace_bytes(64) > lev.workspace_bytes(64)
+    cp = C.parameterised_circuit(3, 3, 10, 2)
+    assert 0 < Q.plan(cp, ordering=1, tree_exec=3).workspace_bytes(1024) < Q.plan(cp, ordering=1, tree_exec=1).workspace_bytes(1024)
     with pytest.raises(Exception):
-        Q.plan(c, ordering=1, tree_exec=3)
+        Q.plan(c, ordering=1, tree_exec=4)
 
 
 def _oracle_open(c, bits, open_qubits):
@@ -527,7 +532,7 @@ def test_bucket_workspace_uses_power_of_two_pitch():
     two: a batch of 130 (3 groups of 64) takes the workspace of a batch of 256."""
     import paper_1712_05384_amd as Q
     c = C.random_grid_circuit(3, 4, 12, 5)
-    p = Q.plan(c, ordering=1)
+    p = Q.plan(c, ordering=1, tree_exec=1)
     assert p.workspace_bytes(130) == p.workspace_bytes(256) > p.workspace_bytes(128)
     assert p.workspace_bytes(64) == p.workspace_bytes(1)
 
@@ -555,3 +560,53 @@ def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
         for tile in (True, False):
             got = run_tree_plan(Q.plan(c, ordering=1, tile=tile, order_restarts=16 * fin, order_finalists=fin).info(1), None, bits)
             assert np.abs(got - ref).max() < 1e-12
+
+
+# --- the LDS-resident program (tree_exec 3) -------------------------------------------------
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,B", [(1, 1, 3, 1, 3), (2, 2, 1, 2, 2), (3, 3, 10, 1, 4),
+                                                    (4, 4, 16, 3, 4), (4, 5, 20, 2, 3), (1, 5, 12, 3, 3)])
+def test_lds_program_interpreted_matches_oracle(rows, cols, depth, seed, B):
+    """The program one work-group runs per bitstring (tables copied at the output
+    bits, 64-row jobs at 16-bit LDS offsets, one barrier per level), executed on
+    the CPU with its bounds and same-level read/write checks, equals the FP64
+    state vector."""
+    from lds_interp import run_lds_program
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, B, seed)
+    info = Q.plan(c, ordering=1).info(2)
+    assert info["lds_ok"] == 1
+    got = run_lds_program(info, None, bits)
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(got - ref).max() < 1e-12 * 2 ** (-c.n / 2)
+
+
+def test_lds_program_gate_values_and_benchmark_plan():
+    """Gate values (per-call tables, no leaf tables) and the 5x5 depth-25
+    benchmark plan (27 buckets, 11 levels) through the LDS interpreter."""
+    from lds_interp import run_lds_program
+    cp = C.parameterised_circuit(3, 4, 12, 3)
+    bits = C.random_bitstrings(cp.n, 3, 3)
+    info = Q.plan(cp, ordering=1).info(2)
+    got = run_lds_program(info, cp.gate_vals, bits)
+    assert np.abs(got - oracle.sv_amplitudes(cp.n, cp.gates, cp.gate_vals, bits)).max() < 1e-12 * 2 ** (-cp.n / 2)
+    c, bits = C.workload("c2_5x5_d25")
+    info = Q.plan(c, ordering=1).info(2)
+    assert info["lds_ok"] == 1 and info["lds_entries"] * 8 <= 62 * 1024
+    got = run_lds_program(info, None, bits[:2])
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits[:2])
+    assert np.abs(got - ref).max() < 1e-12 * 2 ** (-c.n / 2)
+
+
+def test_lds_program_limits():
+    """Open qubits and plans whose results exceed the LDS stay on the level
+    launches; asking for the LDS launch there is QGM_E_UNSUPPORTED."""
+    c = C.random_grid_circuit(3, 3, 10, 1)
+    info = Q.plan(c, (0, 4), ordering=1).info(0)
+    assert info["lds_ok"] == 0 and "open" in info["lds_why"]
+    big, _ = C.workload("c3_5x6_d30")
+    assert Q.plan(big, ordering=1).info(0)["lds_ok"] == 0
+    with pytest.raises(N.QgmError) as ei:
+        Q.plan(big, ordering=1, tree_exec=3)
+    assert ei.value.status == N.QGM_E_UNSUPPORTED

@@ -13,9 +13,10 @@ elimination-tree level instead (results in HBM); --ordering 0 the
 vertical-order path (worldline steps, autotuned kernels).
 
 Prints one JSON line.  The roofline object is for the dominant kernel: for the
-LDS-resident launch, the plan's algorithmic flops over its launch time against
-the FP32 vector peak (its HBM traffic is kilobytes); for the level launches and
-the worldline steps, algorithmic bytes per launch (every input result read
+LDS-resident launch, the plan's algorithmic LDS bytes over its launch time
+against the LDS rate of the chip (its HBM traffic is under a megabyte; its
+flops against the FP32 vector peak are given beside); for the level launches
+and the worldline steps, algorithmic bytes per launch (every input result read
 once, every result written once, from the plan) against HBM; launch times from
 HIP events on the stream the kernels run on.  The cpu_baseline leg times the FP64 state-vector
 oracle on the host cores over the same circuit and bitstrings, and its
@@ -32,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+LDS_PEAK_TBS = 157.3        # 256 B/clk per CU (LDS reads and writes), 256 CUs, 2.4 GHz
 LDS_HEADER = 4 * 256 + 16   # LDS bytes before the data of the LDS-resident launch (table output bits, phase)
 # HBM bytes per dominant-kernel launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
@@ -41,6 +43,8 @@ MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
     ("c2_5x5_d25", 1): {"bytes_per_launch": 6998897.6, "source": "tree.hip", "sha256_16": "59f05b1860937ba8",
                         "plan": {"bytes_per_amp": 62088, "level_launches": 10}},
+    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 976466.0, "source": "tree_lds.hip", "sha256_16": "6bcc3d9bd61505ce",
+                            "plan": {"lds_entries": 2696, "lds_jobs": 63, "lds_threads": 256}},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
 
@@ -62,6 +66,9 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="ordering 0: keep the policy's kernels")
     ap.add_argument("--kernel-policy", type=int, default=0,
                     help="ordering 0: 0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
+    ap.add_argument("--section", default=None, choices=None,
+                    help="run only this secondary workload (launch_forms, batch_scaling, sets, c4_grad, "
+                         "per_bitstring, c3, c3_mfma, c5_graph, xeb) and print its JSON, for profiling it alone")
     ap.add_argument("--tree-exec", type=int, default=0,
                     help="ordering 1: 0 auto (LDS-resident launch when the plan fits), 1 one launch per level, "
                          "3 LDS-resident")
@@ -86,6 +93,12 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.section is not None:
+        if args.section not in SECTIONS:
+            print(json.dumps({"error": f"unknown section {args.section}; one of {sorted(SECTIONS)}"}))
+            return 2
+        print(json.dumps(extras(Q, C, torch, np, torch.cuda.current_stream(dev), args, args.section)), flush=True)
+        return 0
     c, bits = C.workload(args.workload)
     B = len(bits)
     t0 = time.perf_counter()
@@ -200,28 +213,36 @@ def dominant_kernel(args, p, info, B, elim_ms, kernels, tree_exec=0):
     B_eff = ((B + 63) // 64 * 64) << info["n_sliced"]
     if info["ordering"] == 1 and info.get("lds_ok") and tree_exec in (0, 3) and not info.get("n_open"):
         # one launch, every result in LDS: its HBM traffic is the bitstrings, the table entries at their
-        # output bits and the amplitudes (kilobytes), so its roof is the vector ALU (plus LDS issue): the
-        # plan's algorithmic flops (6 per complex product, 2 per complex add) over the launch time
+        # output bits (served by L2) and the amplitudes, so its roofs are on chip.  The plan's LDS bytes
+        # (per result row kept: 2^k input and table reads plus one write; plus the copied table entries)
+        # against the LDS read/write rate, and its flops against the vector ALU; the LDS roof is the
+        # higher time floor of the two, so it is the one reported.
+        lds_bytes = info["lds_bytes_per_amp"] * B
         flops = info["flops_per_amp"] * B
-        achieved = flops / (elim_ms / 1e3) / 1e12
+        t = elim_ms / 1e3
+        achieved = lds_bytes / t / 1e12
         cfg = {"buckets": info["n_buckets"], "tree_levels": info["n_levels"], "launches": 1,
                "execution_form": "LDS-resident: one work-group of %d threads per bitstring" % info["lds_threads"],
                "lds_bytes_per_workgroup": 8 * info["lds_entries"] + LDS_HEADER, "lds_jobs": info["lds_jobs"],
-               "flops_per_amp": info["flops_per_amp"], "bytes_per_amp_of_the_level_launches": info["bytes_per_amp"]}
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+               "flops_per_amp": info["flops_per_amp"], "lds_bytes_per_amp": info["lds_bytes_per_amp"],
+               "bytes_per_amp_of_the_level_launches": info["bytes_per_amp"]}
+        roofline = {"bound": "lds", "achieved": round(achieved, 3), "peak": LDS_PEAK_TBS, "unit": "TB/s",
+                    "frac": round(achieved / LDS_PEAK_TBS, 4), "traffic": None,
                     "kernel": "k_tree_lds (bucket elimination with every result in LDS, one launch per call)",
-                    "flops_per_launch": flops, "launch_ms": elim_ms, "launches_per_step": 1,
-                    "peak_note": "fp32 vector peak of MI355X (packed FP32); the build disables packed FP32, "
-                                 "so 78.6 TFLOP/s is the issue limit of these kernels"}
+                    "lds_bytes_per_launch": lds_bytes, "launch_ms": elim_ms, "launches_per_step": 1,
+                    "peak_note": "LDS peak from unit counts: 256 B/clk per CU x 256 CUs x 2.4 GHz",
+                    "alu": {"flops_per_launch": flops, "achieved_TFLOPs": round(flops / t / 1e12, 3),
+                            "peak_TFLOPs": FP32_VECTOR_PEAK_TFLOPS,
+                            "frac": round(flops / t / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)}}
         rec = MEASURED_TRAFFIC.get((args.workload, "lds"))
         if rec:
             import hashlib
             path = os.path.join(ROOT, "paper_1712_05384_amd", "csrc", rec["source"])
-            if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == rec["sha256_16"]:
-                roofline["traffic"] = round(rec["bytes_per_launch"] / (elim_ms / 1e3) / 1e9, 2)
+            same_plan = all(info.get(k) == v for k, v in rec.get("plan", {}).items())
+            if same_plan and hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == rec["sha256_16"]:
+                roofline["traffic"] = round(rec["bytes_per_launch"] / t / 1e9, 2)
                 roofline["traffic_bytes_per_launch"] = rec["bytes_per_launch"]
-                roofline["traffic_unit"] = "GB/s"
+                roofline["traffic_unit"] = "GB/s of HBM"
         return roofline, cfg
     if info["ordering"] == 1:
         kernel = ("k_tree_level + k_tree_tail (bucket elimination: one launch per elimination-tree level, "
@@ -304,13 +325,11 @@ def _kernel_ms(p, bd, out, ws, stream, torch, reps=5):
     return ph[2] / max(nc, 1)
 
 
-def extras(Q, C, torch, np, stream, args):
-    """Secondary workloads, timed the same way (inputs resident, HIP events)."""
-    out = {}
+def _sec_launch_forms(Q, C, torch, np, stream, args, out):
+    """The default plan with one launch per elimination-tree level (results in HBM), and the vertical order."""
     dev = torch.device("cuda", 0)
     c, bits = C.workload(args.workload)
     bd = torch.from_numpy(bits.view(np.int64)).to(dev)
-    # the same plan with one launch per elimination-tree level (results in HBM), and the vertical order
     for key, kw in (("ordering_1_level_launches", {"ordering": 1, "tree_exec": 1}),
                     ("ordering_0", {"ordering": 0})):
         v, p, ms, o = _amps_per_sec(Q, C, torch, np, stream, args.workload, 10, **kw)
@@ -322,7 +341,12 @@ def extras(Q, C, torch, np, stream, args):
         out[key] = {"workload": args.workload, "amplitudes_per_sec": round(v, 1), "ms_per_call": round(ms, 4),
                     "bytes_per_amp": info["bytes_per_amp"], "max_rank": info["max_rank"], "roofline": rf}
         print(f"# {key}: {ms:.4f} ms per call, roofline frac {rf['frac']}", file=sys.stderr, flush=True)
-    # batch scaling on the default circuit, both launch forms of the bucket plan (graph replay)
+
+
+def _sec_batch_scaling(Q, C, torch, np, stream, args, out):
+    """Batch scaling on the default circuit, both launch forms of the bucket plan (graph replay)."""
+    dev = torch.device("cuda", 0)
+    c, _ = C.workload(args.workload)
     scale = {}
     for mode in (0, 1):
         p = Q.plan(c, ordering=1, tree_exec=mode)
@@ -347,7 +371,13 @@ def extras(Q, C, torch, np, stream, args):
             del g, w, o
     out["batch_scaling"] = {"workload": f"{args.workload} with B uniform bitstrings (seed 77), graph replay",
                             **scale}
-    # sets of amplitudes (Sec. III.A): 2^k amplitudes per bitstring with k open qubits, counted as amplitudes
+
+
+def _sec_sets(Q, C, torch, np, stream, args, out):
+    """Sets of amplitudes (Sec. III.A): 2^k amplitudes per bitstring with k open qubits, counted as amplitudes."""
+    dev = torch.device("cuda", 0)
+    c, bits = C.workload(args.workload)
+    bd = torch.from_numpy(bits.view(np.int64)).to(dev)
     sets = {}
     for oq in ((0, 6, 12, 18), (0, 3, 6, 9, 12, 15, 18, 21)):
         p = Q.plan(c, oq, ordering=1)
@@ -364,7 +394,11 @@ def extras(Q, C, torch, np, stream, args):
     out["sets_of_amplitudes"] = {"workload": f"{args.workload}, {len(bits)} bitstrings, k open qubits "
                                              "(one level-launch plan per set; every completion of the open bits)",
                                  **sets}
-    # gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2
+
+
+def _sec_c4_grad(Q, C, torch, np, stream, args, out):
+    """Gradients: 5x5 depth 20 with parameterised gates, 256 bitstrings, L = sum log |A|^2."""
+    dev = torch.device("cuda", 0)
     c, bits = C.workload("c4_5x5_d20_U")
     gv = torch.tensor(c.gate_vals.astype(np.complex64), device=dev)
     bd = torch.from_numpy(bits.view(np.int64)).to(dev)
@@ -375,16 +409,23 @@ def extras(Q, C, torch, np, stream, args):
         amps = p.amplitudes(bd, gv)
         gamps = (2.0 / torch.conj(amps)).contiguous()
         ws = torch.empty(p.backward_workspace_bytes(len(bits)), dtype=torch.uint8, device=dev)
-        ms = _time(lambda: p.backward(bd, gamps, gv, workspace=ws, stream=stream), 10, stream, torch)
-        msf = _time(lambda: p.amplitudes(bd, gv, stream=stream), 10, stream, torch)
+        gg = torch.empty((c.n_slots, 2, 2), dtype=torch.complex64, device=dev)
+        ao = torch.empty_like(amps)
+        ms = _time(lambda: p.backward(bd, gamps, gv, workspace=ws, stream=stream, gate_grads=gg, amps_out=ao),
+                   10, stream, torch)
+        wf = torch.empty(max(p.workspace_bytes(len(bits)), 256), dtype=torch.uint8, device=dev)
+        msf = _time(lambda: p.amplitudes(bd, gv, out=ao, workspace=wf, stream=stream), 10, stream, torch)
         out["c4_grad"]["ordering_%d" % ordering] = {"grad_evals_per_sec": round(1e3 / ms, 2),
                                                     "ms_per_grad_eval": round(ms, 4),
                                                     "ms_forward_only": round(msf, 4)}
         print(f"# c4 gradient ordering {ordering}: {ms:.3f} ms per evaluation (forward alone {msf:.3f} ms)",
               file=sys.stderr, flush=True)
         del ws
-    # plain per-bitstring baseline: the default workload's plan called with B = 1
-    # in a host loop (no graph; B is padded to one 64-wide wave)
+
+
+def _sec_per_bitstring(Q, C, torch, np, stream, args, out):
+    """Plain per-bitstring baseline: the default workload's plan called with B = 1 in a host loop (no graph)."""
+    dev = torch.device("cuda", 0)
     c, bits = C.workload(args.workload)
     p = Q.plan(c, ordering=args.ordering)
     one = [torch.from_numpy(bits[i:i + 1].view(np.int64)).to(dev) for i in range(64)]
@@ -392,11 +433,15 @@ def extras(Q, C, torch, np, stream, args):
     w1 = torch.empty(max(p.workspace_bytes(1), 256), dtype=torch.uint8, device=dev)
     ms = _time(lambda: [p.amplitudes(b1, None, out=o1, workspace=w1, stream=stream) for b1 in one], 3, stream, torch)
     out["per_bitstring_baseline"] = {"workload": f"{c.name}, same plan, B = 1 per call, 64 calls",
-                                     "amplitudes_per_sec": round(64 / (ms / 1e3), 1), "ms_per_amplitude": round(ms / 64, 4)}
+                                     "amplitudes_per_sec": round(64 / (ms / 1e3), 1),
+                                     "ms_per_amplitude": round(ms / 64, 4)}
     print(f"# per-bitstring baseline: {ms / 64:.3f} ms per amplitude", file=sys.stderr, flush=True)
-    # 5x6 depth 30: bucket path (no slicing needed) and vertical path with 2 sliced variables (FP64 slice
-    # sum) in three precisions of its steps: autotuned vector ALU, FP32 matrix cores, BF16x3 matrix cores;
-    # each against the stored FP64 state-vector amplitudes (tests/golden, written by the oracle)
+
+
+def _sec_c3(Q, C, torch, np, stream, args, out, mfma_only=False):
+    """5x6 depth 30: bucket path (no slicing needed) and vertical path with 2 sliced variables (FP64 slice sum)
+    in three precisions of its steps: autotuned vector ALU, FP32 matrix cores, BF16x3 matrix cores; each against
+    the stored FP64 state-vector amplitudes (tests/golden, written by the oracle)."""
     golden = np.load(os.path.join(ROOT, "tests", "golden", "c3_5x6_d30_amps.npy"), allow_pickle=False)
     n3 = C.workload("c3_5x6_d30")[0].n
 
@@ -411,14 +456,19 @@ def extras(Q, C, torch, np, stream, args):
             row["step_kernels"] = {k: kinds.count(k) for k in sorted(set(kinds))}
         return row, ms
     out["c3"] = {"workload": "5x6 depth 30, 1024 bitstrings, complex128 output"}
-    out["c3"]["ordering_1"], ms1 = c3_row(ordering=1)
-    for key, pol, tune in (("ordering_0_sliced_2_valu", 0, True), ("ordering_0_sliced_2_fp32_mfma", 2, False),
-                           ("ordering_0_sliced_2_bf16x3", 4, False)):
+    if not mfma_only:
+        out["c3"]["ordering_1"], ms1 = c3_row(ordering=1)
+        print(f"# c3: bucket {ms1:.3f} ms per 1024 amplitudes", file=sys.stderr, flush=True)
+    rows = (("ordering_0_sliced_2_valu", 0, True), ("ordering_0_sliced_2_fp32_mfma", 2, False),
+            ("ordering_0_sliced_2_bf16x3", 4, False))
+    for key, pol, tune in rows[1:] if mfma_only else rows:
         out["c3"][key], ms0 = c3_row(ordering=0, min_sliced_vars=2, kernel_policy=pol, autotune=tune)
         print(f"# c3 {key}: {ms0:.3f} ms per 1024 amplitudes, max err x 2^(n/2) "
               f"{out['c3'][key]['max_err_x_2^(n/2)']:.3g}", file=sys.stderr, flush=True)
-    print(f"# c3: bucket {ms1:.3f} ms per 1024 amplitudes", file=sys.stderr, flush=True)
-    # uneven batch: 4x5 d20, 5x5 d24, 6x6 d24, 6x7 d27, 1024 bitstrings each, one graph
+
+
+def _sec_c5_graph(Q, C, torch, np, stream, args, out):
+    """Uneven batch: 4x5 d20, 5x5 d24, 6x6 d24, 6x7 d27, 1024 bitstrings each, one graph."""
     names = ("c5_4x5_d20", "c5_5x5_d24", "c5_6x6_d24", "c5_6x7_d27")
     cs, bs = zip(*[C.workload(nm) for nm in names])
     total = sum(len(b) for b in bs)
@@ -433,10 +483,14 @@ def extras(Q, C, torch, np, stream, args):
         print(f"# c5 graph ordering {ordering}: {ms:.3f} ms per launch ({total} amplitudes)", file=sys.stderr,
               flush=True)
         del g
-    # cross-entropy statistics and sampling from a set (App. B, App. C) over 2^22 complex64 amplitudes
+
+
+def _sec_xeb(Q, C, torch, np, stream, args, out):
+    """Cross-entropy statistics and sampling from a set (App. B, App. C) over 2^22 complex64 amplitudes."""
+    dev = torch.device("cuda", 0)
     nx = 1 << 22
-    ax = torch.from_numpy(C.random_amplitudes(30, nx, 1).astype(np.complex64)).cuda()
-    ux = torch.from_numpy(C.random_uniforms(1 << 20, 1)).cuda()
+    ax = torch.from_numpy(C.random_amplitudes(30, nx, 1).astype(np.complex64)).to(dev)
+    ux = torch.from_numpy(C.random_uniforms(1 << 20, 1)).to(dev)
     wsx = Q.api.xeb_workspace(nx)
     ox = torch.empty(8, dtype=torch.float64, device=dev)
     ix = torch.empty(1 << 20, dtype=torch.int64, device=dev)
@@ -447,6 +501,24 @@ def extras(Q, C, torch, np, stream, args):
                   "xeb_frac_of_hbm": round(8 * nx / (ms_x / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                   "sample_set_ms": round(ms_s, 4), "note": "workspace and outputs allocated once, outside the timing"}
     print(f"# xeb: {ms_x:.3f} ms, sample_set: {ms_s:.3f} ms", file=sys.stderr, flush=True)
+
+
+def _sec_c3_mfma(Q, C, torch, np, stream, args, out):
+    """The two matrix-core rows of the 5x6 depth-30 workload alone (no autotuning), for counter runs."""
+    _sec_c3(Q, C, torch, np, stream, args, out, mfma_only=True)
+
+
+SECTIONS = {"launch_forms": _sec_launch_forms, "batch_scaling": _sec_batch_scaling, "sets": _sec_sets,
+            "c4_grad": _sec_c4_grad, "per_bitstring": _sec_per_bitstring, "c3": _sec_c3, "c5_graph": _sec_c5_graph,
+            "xeb": _sec_xeb, "c3_mfma": _sec_c3_mfma}
+
+
+def extras(Q, C, torch, np, stream, args, only=None):
+    """Secondary workloads, timed the same way (inputs resident, HIP events)."""
+    out = {}
+    for name, fn in SECTIONS.items():
+        if (only is None and name != "c3_mfma") or name == only:
+            fn(Q, C, torch, np, stream, args, out)
     return out
 
 

@@ -109,10 +109,11 @@ typedef struct {
                                   input is an earlier bucket's result absorbs that bucket when the merged
                                   index space grows by at most one bit (up to 3 summed variables) */
     int32_t tree_exec;         /* ordering 1 only: how qgm_amplitudes runs the buckets.
-                                  0 = auto: one launch per level (the faster of the two on MI355X at every
-                                      batch size measured);
+                                  0 = auto: the LDS-resident launch (3) when the plan fits it, else one
+                                      launch per level (1);
                                   1 = one launch per level of the elimination tree (the last small levels
-                                      and the amplitude product in one more launch);
+                                      and the amplitude product in one more launch), results in a
+                                      batch-minor workspace arena in HBM;
                                   2 = one persistent launch for all levels and the amplitude product: each
                                       64-bitstring group runs on one accelerator complex and each bucket task
                                       starts when the tasks making its inputs have signalled completion; the
@@ -120,7 +121,15 @@ typedef struct {
                                       must not run concurrently on one device (each needs the whole GPU at
                                       once); a launch that cannot proceed gives up after a bounded wait,
                                       writes NaN amplitudes and records the failure in the plan
-                                      (qgm_plan_check returns QGM_E_INTERNAL). */
+                                      (qgm_plan_check returns QGM_E_INTERNAL);
+                                  3 = one launch of one work-group per bitstring that keeps every result of
+                                      the elimination and the factor-table entries at the bitstring's output
+                                      bits in LDS (at most 7936 complex64 values, i.e. 62 KiB, per
+                                      work-group): no workspace unless the circuit reads gate values (then
+                                      the factor tables of the call).  Needs no open qubits, buckets of at
+                                      most 4 inputs and 3 summed variables; qgm_plan returns
+                                      QGM_E_UNSUPPORTED when the plan does not fit (qgm_plan_info gives the
+                                      reason as lds_why). */
     int32_t no_tile;           /* ordering 1 only: 1 = every bucket uses the general wave unit; 0 = a
                                   two-input bucket summing two or more variables whose result has two bits
                                   carried by one input only and one carried by the other only (neither in
@@ -186,7 +195,9 @@ qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* byte
  *  bits:      device uint64 [B].
  *  out:       device complex64 or complex128 (opts.out_c128) [B][2^n_open].
  *  workspace: device buffer of at least qgm_workspace_bytes(plan, B) bytes,
- *             256-byte aligned; its contents are scratch.
+ *             256-byte aligned; its contents are scratch.  May be NULL when
+ *             that size is 0 (the LDS-resident launch of a circuit that reads
+ *             no gate values).
  * The first call of a plan on a device uploads the plan's constant tables
  * (a synchronous hipMalloc + hipMemcpy, kept until qgm_plan_destroy).
  * Sums over sliced variables are done in FP64.  Calls that share a workspace

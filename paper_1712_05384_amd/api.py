@@ -123,10 +123,13 @@ class Plan:
         N.check(self._lib.qgm_backward_workspace_bytes(self._h, int(B), ctypes.byref(out)))
         return int(out.value)
 
-    def backward(self, bits, grad_amps, gate_vals=None, *, workspace=None, stream=None, want_amps=True):
+    def backward(self, bits, grad_amps, gate_vals=None, *, workspace=None, stream=None, want_amps=True,
+                 gate_grads=None, amps_out=None):
         """Gradient with respect to gate_vals of a real loss whose torch gradient
         with respect to the amplitudes is grad_amps ([B, 2^n_open] complex).
-        Returns (amps or None, gate_grads [n_slots, 2, 2] complex64)."""
+        Returns (amps or None, gate_grads [n_slots, 2, 2] complex64); gate_grads
+        and amps_out, when given, are device tensors the call writes instead of
+        allocating."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         if isinstance(bits, np.ndarray):
@@ -142,9 +145,20 @@ class Plan:
             gv = torch.as_tensor(gate_vals).to(dev, torch.complex64).contiguous()
             if tuple(gv.shape) != (self.n_slots, 2, 2):
                 raise ValueError("gate_vals must be [n_slots, 2, 2]")
-        grads = torch.zeros((max(self.n_slots, 1), 2, 2), dtype=torch.complex64, device=dev)
+        if gate_grads is not None:
+            if tuple(gate_grads.shape) != (self.n_slots, 2, 2) or gate_grads.dtype != torch.complex64 \
+                    or not gate_grads.is_contiguous():
+                raise ValueError("gate_grads must be a contiguous complex64 [n_slots, 2, 2] tensor")
+            grads = gate_grads
+        else:
+            grads = torch.zeros((max(self.n_slots, 1), 2, 2), dtype=torch.complex64, device=dev)
         odt = torch.complex128 if self.out_c128 else torch.complex64
-        amps = torch.empty((B, n_out), dtype=odt, device=dev) if want_amps else None
+        if amps_out is not None:
+            if tuple(amps_out.shape) != (B, n_out) or amps_out.dtype != odt or not amps_out.is_contiguous():
+                raise ValueError("amps_out must be a contiguous [B, 2^n_open] tensor of the plan's output type")
+            amps = amps_out
+        else:
+            amps = torch.empty((B, n_out), dtype=odt, device=dev) if want_amps else None
         need = self.backward_workspace_bytes(B)
         if workspace is None:
             workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)

@@ -853,8 +853,8 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     if (B < 0) return fail(QGM_E_INVALID, "B < 0");
     if (B == 0) return QGM_OK;
     const qgm::Plan& p = plan->p;
-    if (!bits || (!out && !allow_no_out) || !workspace)
-        return fail(QGM_E_INVALID, "bits, out and workspace must be device pointers");
+    if (!bits || (!out && !allow_no_out))
+        return fail(QGM_E_INVALID, "bits and out must be device pointers");
     if (p.n_slots > 0 && !gate_vals) return fail(QGM_E_INVALID, "the circuit reads gate_vals but it is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(QGM_E_INVALID, "workspace must be 256-byte aligned");
     const int64_t B_pad = qgm::padded_batch(B);
@@ -865,6 +865,8 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
     if ((int64_t(1) << p.r_max) * (B_eff / 64) >= (int64_t(1) << 31))
         return fail(QGM_E_UNSUPPORTED, "frontier rows times batch blocks exceed 2^31");
     const qgm::WsLayout w = qgm::workspace_layout(p, B);
+    if (w.total > 0 && !workspace)
+        return fail(QGM_E_INVALID, "workspace is NULL but the call needs " + std::to_string(w.total) + " bytes");
     if (ws_bytes < w.total)
         return fail(QGM_E_OOM, "workspace too small: need " + std::to_string(w.total) + " bytes");
     char* tables = nullptr;

@@ -642,6 +642,7 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"lds_ok\":" << (t.lds.ok ? 1 : 0) << ",\"lds_entries\":" << t.lds.lds_size
       << ",\"lds_jobs\":" << t.lds.jobs.size() << ",\"lds_tables0\":" << t.lds.tables0
       << ",\"lds_threads\":" << t.lds.threads << ",\"lds_recs0\":" << t.lds.recs0
+      << ",\"lds_bytes_per_amp\":" << lds_bytes_per_amp(t.lds)
       << ",\"lds_why\":\"" << t.lds.why << "\"";
     o << ",\"order\":"; json_ints(o, t.order);
     o << ",\"finals\":"; json_ints(o, t.finals);

@@ -270,6 +270,10 @@ struct TreePlan {
 // Builds t.lds from a finished bucket plan (sets t.lds.ok = false with a reason
 // when the plan does not fit: open qubits, more than kLdsMaxIn inputs, LDS size).
 void build_lds_program(TreePlan& t);
+// LDS bytes one bitstring's program moves, counting only the rows a job keeps:
+// per result row 2^k (inputs + table) complex64 reads and one write, plus one
+// write per factor-table entry copied in (0 when the program does not fit).
+int64_t lds_bytes_per_amp(const LdsProgram& P);
 
 // Builds the bucket plan from the variables and gate records in `p`
 // (ordering 1; no open qubits, no slicing).

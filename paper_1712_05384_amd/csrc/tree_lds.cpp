@@ -230,4 +230,11 @@ void build_lds_program(TreePlan& t) {
     t.lds = std::move(P);
 }
 
+int64_t lds_bytes_per_amp(const LdsProgram& P) {
+    if (!P.ok) return 0;
+    int64_t b = int64_t(P.entries.size()) * 8;
+    for (const LdsJob& j : P.jobs) b += int64_t(j.lanes) * (((int64_t(1) << j.k) * (j.nin + 1) + 1) * 8);
+    return b;
+}
+
 }  // namespace qgm

@@ -437,3 +437,28 @@ def test_tree_lds_repeat_and_graph():
         out = g.launch()[0].cpu().numpy()
         torch.cuda.synchronize()
         assert np.array_equal(out, a)
+
+
+@pytest.mark.gpu
+def test_tree_lds_null_workspace():
+    """A circuit without gate values needs no workspace in the LDS launch: the C-ABI takes NULL for it and gives
+    the same amplitudes; a plan that needs a workspace rejects NULL with QGM_E_INVALID."""
+    import ctypes
+    from paper_1712_05384_amd import _native as N
+    c, bits = C.workload("c2_5x5_d25")
+    p = _tree(c, tree_exec=3)
+    assert p.workspace_bytes(len(bits)) == 0
+    a = p.amplitudes(bits).cpu().numpy()
+    bd = torch.from_numpy(bits.view(np.int64)).cuda()
+    out = torch.empty((len(bits), 1), dtype=torch.complex64, device="cuda")
+    s = torch.cuda.current_stream()
+    L = N.lib()
+    N.check(L.qgm_amplitudes(p._h, None, bd.data_ptr(), len(bits), out.data_ptr(), None, 0,
+                             ctypes.c_void_p(s.cuda_stream)))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), a)
+    p1 = _tree(c, tree_exec=1)
+    assert p1.workspace_bytes(len(bits)) > 0
+    st = L.qgm_amplitudes(p1._h, None, bd.data_ptr(), len(bits), out.data_ptr(), None, 0,
+                          ctypes.c_void_p(s.cuda_stream))
+    assert st == N.QGM_E_INVALID

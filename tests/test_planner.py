@@ -597,6 +597,11 @@ def test_lds_program_gate_values_and_benchmark_plan():
     got = run_lds_program(info, None, bits[:2])
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits[:2])
     assert np.abs(got - ref).max() < 1e-12 * 2 ** (-c.n / 2)
+    # the LDS bytes the bench's roofline uses: per kept row 2^k (inputs + table) reads and one write, plus the
+    # copied table entries, counted from the exported jobs
+    L = info["lds"]
+    want = 8 * len(L["entries"]) + sum(j["lanes"] * 8 * ((1 << j["k"]) * (j["nin"] + 1) + 1) for j in L["jobs"])
+    assert info["lds_bytes_per_amp"] == want
 
 
 def test_lds_program_limits():

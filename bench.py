@@ -68,7 +68,8 @@ def main() -> int:
                     help="ordering 0: 0 auto, 1 vector ALU one row per thread, 2 FP32 matrix cores where supported")
     ap.add_argument("--section", default=None, choices=None,
                     help="run only this secondary workload (launch_forms, batch_scaling, sets, c4_grad, "
-                         "per_bitstring, c3, c3_mfma, c5_graph, xeb) and print its JSON, for profiling it alone")
+                         "per_bitstring, c3, c3_mfma, c5_graph, xeb, paper_circuits) and print its JSON, for profiling it "
+                         "alone")
     ap.add_argument("--tree-exec", type=int, default=0,
                     help="ordering 1: 0 auto (LDS-resident launch when the plan fits), 1 one launch per level, "
                          "3 LDS-resident")
@@ -508,9 +509,39 @@ def _sec_c3_mfma(Q, C, torch, np, stream, args, out):
     _sec_c3(Q, C, torch, np, stream, args, out, mfma_only=True)
 
 
+def _sec_paper_circuits(Q, C, torch, np, stream, args, out):
+    """The 5x9 depth-40 and 7x8 depth-30 circuits of the Abstract (seed 1), 64 uniform bitstrings per call,
+    bucket plans sliced until every result fits the kernels; for context, the paper's workstation aims at
+    about 100 s per amplitude (Sec. II)."""
+    dev = torch.device("cuda", 0)
+    out["paper_circuits"] = {"workload": "random grid circuits of the Abstract, 64 bitstrings per call, ordering 1"}
+    for r, cc, d in ((5, 9, 40), (7, 8, 30)):
+        c = C.random_grid_circuit(r, cc, d, 1)
+        bits = C.random_bitstrings(c.n, 64, 1)
+        t0 = time.perf_counter()
+        p = Q.plan(c, ordering=1)
+        plan_s = time.perf_counter() - t0
+        info = p.info(0)
+        bd = torch.from_numpy(bits.view(np.int64)).to(dev)
+        o = torch.empty((64, 1), dtype=torch.complex64, device=dev)
+        w = torch.empty(max(p.workspace_bytes(64), 256), dtype=torch.uint8, device=dev)
+        ms = _time(lambda: p.amplitudes(bd, None, out=o, workspace=w, stream=stream), 3, stream, torch)
+        kms = _kernel_ms(p, bd, o, w, stream, torch, reps=3)
+        rf, _ = dominant_kernel(argparse.Namespace(workload="", kernel_policy=0, no_autotune=True), p, info, 64, kms,
+                                None, 0)
+        out["paper_circuits"][f"{r}x{cc}_d{d}"] = {
+            "qubits": c.n, "sliced_vars": info["n_sliced"], "max_rank": info["max_rank"],
+            "workspace_GB": round(p.workspace_bytes(64) / 1e9, 3), "plan_seconds": round(plan_s, 3),
+            "bytes_per_amp": info["bytes_per_amp"], "ms_per_call": round(ms, 3),
+            "amplitudes_per_sec": round(64 / (ms / 1e3), 1), "roofline_frac": rf["frac"], "roofline_bound": rf["bound"]}
+        print(f"# {r}x{cc} d{d}: {ms:.3f} ms per 64 amplitudes ({info['n_sliced']} sliced), roofline frac {rf['frac']}",
+              file=sys.stderr, flush=True)
+        del w, o
+
+
 SECTIONS = {"launch_forms": _sec_launch_forms, "batch_scaling": _sec_batch_scaling, "sets": _sec_sets,
             "c4_grad": _sec_c4_grad, "per_bitstring": _sec_per_bitstring, "c3": _sec_c3, "c5_graph": _sec_c5_graph,
-            "xeb": _sec_xeb, "c3_mfma": _sec_c3_mfma}
+            "xeb": _sec_xeb, "paper_circuits": _sec_paper_circuits, "c3_mfma": _sec_c3_mfma}
 
 
 def extras(Q, C, torch, np, stream, args, only=None):

@@ -91,9 +91,13 @@ typedef struct {
                                   1 = bucket elimination (App. A) along a greedy treewidth order (min-degree /
                                       min-fill with randomised tie breaks, the cheapest of several; Sec. IV.B);
                                       open qubits (their last variables are never summed: one more bucket
-                                      multiplies every result left on them), qgm_backward without open qubits,
-                                      no slicing */
-    int32_t precision;         /* 0 = complex64 with FP32 arithmetic */
+                                      multiplies every result left on them), slicing, qgm_backward without open
+                                      qubits or slicing */
+    int32_t precision;         /* qgm_precision: QGM_PREC_C64 = complex64 values, FP32 arithmetic in every
+                                  step; QGM_PREC_BF16X3 = ordering 0 only: every worldline step that the
+                                  matrix-core kernel supports (K and N of 2^3..2^5) runs in BF16x3 (as
+                                  kernel_policy 4; kernel_policy must then be 0 or 4), the others in FP32;
+                                  QGM_E_UNSUPPORTED for ordering 1 or when no step supports it */
     int32_t kernel_policy;     /* 0 = auto (the vector-ALU kernel, one row per thread); 1 = the same;
                                   2 = FP32 matrix-core kernel for every step it supports (K and N of
                                       2^3..2^5), the vector-ALU kernel elsewhere;
@@ -101,9 +105,16 @@ typedef struct {
                                       (|K|+|N| >= 8 bits);
                                   4 = as 2 with BF16x3 split-precision matrix cores (bf16 hi+lo
                                       operands, three products, FP32 accumulation) */
-    int32_t min_sliced_vars;   /* slice at least this many variables (Sec. V outlook: space-time tradeoffs) */
+    int32_t min_sliced_vars;   /* slice at least this many variables (Sec. V outlook: space-time tradeoffs):
+                                  each sliced variable is fixed to 0 and to 1 in turn and the amplitudes of
+                                  the slices are summed in FP64.  Ordering 0: at most 12, slices run as
+                                  batch columns.  Ordering 1: at most 24 and n + slices <= 64 (slice j is
+                                  carried by bit n + j of a batch column's 64-bit word); the slices run in
+                                  chunks of batch columns (see mem_budget) */
     int32_t out_c128;          /* 1: amplitudes are written as complex128, 0: complex64 */
-    int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor has rank <= max_rank */
+    int32_t max_rank;          /* 0 = no limit; else slice until every frontier tensor (ordering 0) or
+                                  bucket result (ordering 1) has rank <= max_rank; QGM_E_OOM if slicing
+                                  cannot reach it */
     int32_t checkpoint_every;  /* qgm_backward keeps every c-th frontier (0 = ceil(sqrt(steps))) */
     int32_t no_chain_merge;    /* ordering 1 only: 1 = one variable per bucket step; 0 = a bucket whose only
                                   input is an earlier bucket's result absorbs that bucket when the merged
@@ -152,7 +163,22 @@ typedef struct {
                                   (0 = 2^20).  A launch that gives up writes NaN for the amplitudes it could
                                   not finish and records the failure in the plan, which qgm_plan_check reports;
                                   a small value forces that path (for tests of the error report) */
+    uint64_t mem_budget;       /* 0 = no limit; else a bound on qgm_workspace_bytes(plan, 64), the workspace
+                                  of a call over 64 bitstrings (a call over B needs about B / 64 times
+                                  that).  Ordering 1 slices further until one slice at a time fits, then
+                                  runs as many slices per chunk as fit (Sec. II memory wall, Sec. V
+                                  space-time tradeoff); QGM_E_OOM when 24 sliced variables do not fit.
+                                  Ordering 0 runs its slices as batch columns, which does not shrink the
+                                  frontier, so there the budget is a check: QGM_E_OOM when it is exceeded */
+    uint64_t checkpoint_budget;/* 0 = no limit; else a bound on the forward frames qgm_backward keeps for 64
+                                  bitstrings.  Ordering 0 with checkpoint_every = 0: the interval c with the
+                                  least recomputation whose (steps - 1) / c checkpoints plus c - 1 segment
+                                  frames fit, at most ceil(sqrt(steps)); QGM_E_OOM when even that does not
+                                  fit.  Ordering 1 keeps every result for its adjoint: QGM_E_OOM when those
+                                  exceed the budget */
 } qgm_plan_opts;
+
+typedef enum { QGM_PREC_C64 = 0, QGM_PREC_BF16X3 = 1 } qgm_precision;
 
 typedef struct qgm_plan_s qgm_plan_t;
 

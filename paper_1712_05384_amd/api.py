@@ -25,7 +25,8 @@ class Plan:
     def __init__(self, circuit, open_qubits=(), *, min_sliced_vars: int = 0, max_rank: int = 0,
                  out_c128: bool = False, kernel_policy: int = 0, checkpoint_every: int = 0, ordering: int = 0,
                  chain_merge: bool = True, tree_exec: int = 0, tile: bool = True, order_finalists: int = 0,
-                 order_restarts: int = 0, order_pick: int = 0, persist_spin: int = 0):
+                 order_restarts: int = 0, order_pick: int = 0, persist_spin: int = 0, precision: int = 0,
+                 mem_budget: int = 0, checkpoint_budget: int = 0):
         L = N.lib()
         self._lib = L
         self._h = None
@@ -49,6 +50,9 @@ class Plan:
         opts.order_restarts = int(order_restarts)
         opts.order_pick = int(order_pick)
         opts.persist_spin = int(persist_spin)
+        opts.precision = int(precision)
+        opts.mem_budget = int(mem_budget)
+        opts.checkpoint_budget = int(checkpoint_budget)
         self.ordering = int(ordering)
         op = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         h = ctypes.c_void_p()

@@ -762,7 +762,8 @@ BwdLayout backward_layout(const qgm_plan_t* P, int64_t B) {
     const int S = int(p.steps.size());
     const uint64_t be = uint64_t(qgm::batch_eff(p, B));
     L.frame = al((uint64_t(1) << p.r_max) * be * 8);
-    L.c = p.opts.checkpoint_every > 0 ? p.opts.checkpoint_every : std::max(1, int(std::ceil(std::sqrt(double(S)))));
+    L.c = p.opts.checkpoint_every > 0 ? p.opts.checkpoint_every
+                                      : (p.ckpt_every > 0 ? p.ckpt_every : std::max(1, int(std::ceil(std::sqrt(double(S))))));
     L.n_ck = (S - 1) / L.c;
     const uint64_t n_frames = 4 + uint64_t(L.n_ck) + uint64_t(L.c - 1);
     L.frames = 0;
@@ -913,128 +914,149 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
                                       reinterpret_cast<const qgm::TreeGroup*>(tables + plan->off_tgroup), facs, fixed,
                                       slots, gt, t.ones_g, phase, int(t.phase.size()), t.phase_g, s);
         mark(2);
-        if (qgm::tree_lds(p, B)) {
-            // one work-group per bitstring, every level in LDS, then the FP64 product
-            if (!out) return fail(QGM_E_INVALID, "out is NULL");
-            const qgm::LdsProgram& lp = t.lds;
-            qgm::LdsArgs a{};
-            a.stages = reinterpret_cast<const qgm::LdsStage*>(tables + plan->off_lstage);
-            a.entries = reinterpret_cast<const qgm::LdsEntry*>(tables + plan->off_lentry);
-            a.recs = reinterpret_cast<const uint16_t*>(tables + plan->off_lrec);
-            a.phq = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
-            a.pv = reinterpret_cast<const double2*>(gt + t.phase_g);
-            a.threads = lp.threads;
-            a.n_jobs = int32_t(lp.jobs.size());
-            a.recs0 = lp.recs0;
-            a.level_job_off = reinterpret_cast<const int32_t*>(tables + plan->off_llvl);
-            a.finals = reinterpret_cast<const int32_t*>(tables + plan->off_lfin);
-            a.phase = phase;
-            a.fixed = fixed;
-            a.slots = slots;
-            a.gtab = gt;
-            a.bits = bits;
-            a.out = out;
-            a.B = B;
-            a.n_stages = int32_t(lp.stages.size());
-            a.n_entries = int32_t(lp.entries.size());
-            a.tables0 = lp.tables0;
-            a.lds_size = lp.lds_size;
-            a.n_levels = int32_t(lp.level_job_off.size()) - 1;
-            a.n_final = int32_t(lp.finals.size());
-            a.n_phase = int32_t(t.phase.size());
-            a.c128 = p.opts.out_c128 != 0 ? 1 : 0;
-            qgm::launch_tree_lds(a, s);
-            mark(3);
-            mark(4);
-            hipError_t he = hipGetLastError();
-            if (he != hipSuccess) return hip_fail(he, "kernel launch");
+        // one pass of the launches over nb batch columns whose words are cb, writing the amplitudes to o
+        // (marks the phase events when `marks`)
+        auto run = [&](const uint64_t* cb, int64_t nb, void* o, bool c128, bool marks) -> qgm_status {
+            const int64_t be = qgm::tree_pitch(nb);
+            auto mk = [&](int i) { if (marks) mark(i); };
+            if (qgm::tree_lds(p, B)) {
+                // one work-group per batch column, every level in LDS, then the FP64 product
+                const qgm::LdsProgram& lp = t.lds;
+                qgm::LdsArgs a{};
+                a.stages = reinterpret_cast<const qgm::LdsStage*>(tables + plan->off_lstage);
+                a.entries = reinterpret_cast<const qgm::LdsEntry*>(tables + plan->off_lentry);
+                a.recs = reinterpret_cast<const uint16_t*>(tables + plan->off_lrec);
+                a.phq = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
+                a.pv = reinterpret_cast<const double2*>(gt + t.phase_g);
+                a.threads = lp.threads;
+                a.n_jobs = int32_t(lp.jobs.size());
+                a.recs0 = lp.recs0;
+                a.level_job_off = reinterpret_cast<const int32_t*>(tables + plan->off_llvl);
+                a.finals = reinterpret_cast<const int32_t*>(tables + plan->off_lfin);
+                a.phase = phase;
+                a.fixed = fixed;
+                a.slots = slots;
+                a.gtab = gt;
+                a.bits = cb;
+                a.out = o;
+                a.B = nb;
+                a.n_stages = int32_t(lp.stages.size());
+                a.n_entries = int32_t(lp.entries.size());
+                a.tables0 = lp.tables0;
+                a.lds_size = lp.lds_size;
+                a.n_levels = int32_t(lp.level_job_off.size()) - 1;
+                a.n_final = int32_t(lp.finals.size());
+                a.n_phase = int32_t(t.phase.size());
+                a.c128 = c128 ? 1 : 0;
+                qgm::launch_tree_lds(a, s);
+                mk(3);
+                return QGM_OK;
+            }
+            if (qgm::tree_persistent(p, B)) {
+                // all levels and the amplitude product in one launch, every result at its own rows
+                auto* flags = reinterpret_cast<int32_t*>(ws + w.flags);
+                const int64_t stride = qgm::tree_flag_stride(p);
+                qgm::launch_persist_init(flags, qgm::tree_flag_words(p, nb), o, nb, c128, s);
+                qgm::TreePersist a{};
+                const int64_t task0 = t.levels.empty() ? 0 : t.level_task_off[t.first_level];
+                a.tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks_all) + task0;
+                a.task0 = int32_t(task0);
+                a.n_tasks = int32_t(t.n_tasks - task0);
+                a.final_dep = reinterpret_cast<const int32_t*>(tables + plan->off_tfdep);
+                a.n_final_dep = int32_t(t.finals.size());
+                a.n_final = int32_t(t.finals.size());
+                a.final_rows = reinterpret_cast<const int64_t*>(tables + plan->off_tfinal_all);
+                a.phase = phase;
+                a.n_phase = int32_t(t.phase.size());
+                a.c128 = c128 ? 1 : 0;
+                a.fixed = fixed;
+                a.slots = slots;
+                a.arena = arena;
+                a.gtab = gt;
+                a.ones_g = t.ones_g;
+                a.bits = cb;
+                a.B = nb;
+                a.B_eff = uint32_t(be);
+                a.flag_stride = int32_t(stride);
+                int max_class = 1;
+                for (int L = t.first_level; L < int(t.levels.size()); ++L)
+                    max_class = std::max(max_class, qgm::launch_inputs(t.level_max_in[L]));
+                a.max_class = max_class;
+                a.flags = flags;
+                a.out = o;
+                a.status = reinterpret_cast<int32_t*>(tables + plan->off_status);
+                a.spin_limit = p.opts.persist_spin > 0 ? p.opts.persist_spin : (1 << 20);
+                hipError_t he = qgm::launch_tree_persist(a, s);
+                if (he != hipSuccess) return hip_fail(he, "persistent launch");
+                mk(3);
+                return QGM_OK;
+            }
+            for (int L = t.first_level; L < t.tail_start; ++L) {
+                const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
+                qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g,
+                                       cb, nb, uint32_t(be), uint32_t((nb + 63) / 64), s);
+            }
+            const int n_tail = int(t.levels.size()) - t.tail_start;
+            if (n_tail > 0) {
+                if (o) {
+                    qgm::TreeTailArgs ta{};
+                    ta.levels = reinterpret_cast<const qgm::TreeTailLevel*>(tables + plan->off_ttail);
+                    ta.tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_tttasks);
+                    ta.final_lds = reinterpret_cast<const int32_t*>(tables + plan->off_ttfin);
+                    ta.phase = phase;
+                    ta.phase_q = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
+                    ta.fixed = fixed;
+                    ta.slots = slots;
+                    ta.arena = arena;
+                    ta.gtab = gt;
+                    ta.bits = cb;
+                    ta.out = o;
+                    ta.ones_g = t.ones_g;
+                    ta.tail_g0 = t.tail_g0;
+                    ta.phase_g = t.phase_g;
+                    ta.B = nb;
+                    ta.n_levels = n_tail;
+                    ta.n_tasks = int32_t(t.n_tasks - t.level_task_off[size_t(t.tail_start)]);
+                    ta.n_final = int32_t(t.finals.size());
+                    ta.n_phase = int32_t(t.phase.size());
+                    ta.tail_g_entries = int32_t(t.tail_g_entries);
+                    ta.c128 = c128 ? 1 : 0;
+                    ta.B_eff = uint32_t(be);
+                    qgm::launch_tree_tail(ta, s);
+                }
+                mk(3);
+            } else {
+                mk(3);
+                if (o && t.n_open > 0)   // a set of 2^n_open amplitudes per bitstring
+                    qgm::launch_tree_final_open(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed,
+                                                slots, arena, t.open_tensor >= 0 ? t.tensor_row[t.open_tensor] : -1,
+                                                t.n_open, uint32_t(t.zero_mask), cb, nb, uint32_t(be), o, c128, s);
+                else if (o)
+                    qgm::launch_tree_final(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed, slots,
+                                           arena, cb, nb, uint32_t(be), o, c128, s);
+            }
             return QGM_OK;
-        }
-        if (qgm::tree_persistent(p, B)) {
-            // all levels and the amplitude product in one launch, every result at its own rows
-            if (!out) return fail(QGM_E_INVALID, "out is NULL");
-            auto* flags = reinterpret_cast<int32_t*>(ws + w.flags);
-            const int64_t stride = qgm::tree_flag_stride(p);
-            qgm::launch_persist_init(flags, qgm::tree_flag_words(p, B), out, B, p.opts.out_c128 != 0, s);
-            qgm::TreePersist a{};
-            const int64_t task0 = t.levels.empty() ? 0 : t.level_task_off[t.first_level];
-            a.tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_ttasks_all) + task0;
-            a.task0 = int32_t(task0);
-            a.n_tasks = int32_t(t.n_tasks - task0);
-            a.final_dep = reinterpret_cast<const int32_t*>(tables + plan->off_tfdep);
-            a.n_final_dep = int32_t(t.finals.size());
-            a.n_final = int32_t(t.finals.size());
-            a.final_rows = reinterpret_cast<const int64_t*>(tables + plan->off_tfinal_all);
-            a.phase = phase;
-            a.n_phase = int32_t(t.phase.size());
-            a.c128 = p.opts.out_c128 != 0 ? 1 : 0;
-            a.fixed = fixed;
-            a.slots = slots;
-            a.arena = arena;
-            a.gtab = gt;
-            a.ones_g = t.ones_g;
-            a.bits = bits;
-            a.B = B;
-            a.B_eff = uint32_t(B_eff);
-            a.flag_stride = int32_t(stride);
-            int max_class = 1;
-            for (int L = t.first_level; L < int(t.levels.size()); ++L)
-                max_class = std::max(max_class, qgm::launch_inputs(t.level_max_in[L]));
-            a.max_class = max_class;
-            a.flags = flags;
-            a.out = out;
-            a.status = reinterpret_cast<int32_t*>(tables + plan->off_status);
-            a.spin_limit = p.opts.persist_spin > 0 ? p.opts.persist_spin : (1 << 20);
-            hipError_t he = qgm::launch_tree_persist(a, s);
-            if (he != hipSuccess) return hip_fail(he, "persistent launch");
-            mark(3);
-            mark(4);
-            return QGM_OK;
-        }
-        for (int L = t.first_level; L < t.tail_start; ++L) {
-            const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
-            qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g, bits,
-                                   B, uint32_t(B_eff), uint32_t((B + 63) / 64), s);
-        }
-        const int n_tail = int(t.levels.size()) - t.tail_start;
-        if (n_tail > 0) {
-            if (out) {
-                qgm::TreeTailArgs ta{};
-                ta.levels = reinterpret_cast<const qgm::TreeTailLevel*>(tables + plan->off_ttail);
-                ta.tasks = reinterpret_cast<const qgm::TreeTask*>(tables + plan->off_tttasks);
-                ta.final_lds = reinterpret_cast<const int32_t*>(tables + plan->off_ttfin);
-                ta.phase = phase;
-                ta.phase_q = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
-                ta.fixed = fixed;
-                ta.slots = slots;
-                ta.arena = arena;
-                ta.gtab = gt;
-                ta.bits = bits;
-                ta.out = out;
-                ta.ones_g = t.ones_g;
-                ta.tail_g0 = t.tail_g0;
-                ta.phase_g = t.phase_g;
-                ta.B = B;
-                ta.n_levels = n_tail;
-                ta.n_tasks = int32_t(t.n_tasks - t.level_task_off[size_t(t.tail_start)]);
-                ta.n_final = int32_t(t.finals.size());
-                ta.n_phase = int32_t(t.phase.size());
-                ta.tail_g_entries = int32_t(t.tail_g_entries);
-                ta.c128 = p.opts.out_c128 != 0 ? 1 : 0;
-                ta.B_eff = uint32_t(B_eff);
-                qgm::launch_tree_tail(ta, s);
+        };
+        if (t.sliced.empty()) {
+            if (!out && (qgm::tree_lds(p, B) || qgm::tree_persistent(p, B))) return QGM_OK;   // nothing to fill
+            qgm_status rs = run(bits, B, out, p.opts.out_c128 != 0, true);
+            if (rs != QGM_OK) return rs;
+        } else {
+            // slices in chunks of 2^chunk_bits as batch columns; FP64 sums in slice order
+            const int S = int(t.sliced.size()), cb = t.chunk_bits;
+            auto* cols = reinterpret_cast<uint64_t*>(ws + w.ext);
+            auto* part = reinterpret_cast<double2*>(ws + w.part);
+            auto* acc = reinterpret_cast<double2*>(ws + w.acc);
+            const int64_t n_chunks = int64_t(1) << (S - cb);
+            for (int64_t c = 0; c < n_chunks; ++c) {
+                qgm::launch_slice_cols(bits, B, p.n, cb, uint64_t(c) << cb, cols, s);
+                qgm_status rs = run(cols, B << cb, part, true, false);
+                if (rs != QGM_OK) return rs;
+                if (out || c + 1 < n_chunks)
+                    qgm::launch_slice_sum(part, B, cb, t.n_open, acc, c == 0, c + 1 == n_chunks, out,
+                                          p.opts.out_c128 != 0, s);
             }
             mark(3);
-        } else {
-            mark(3);
-            if (out && t.n_open > 0)   // a set of 2^n_open amplitudes per bitstring
-                qgm::launch_tree_final_open(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed, slots,
-                                            arena, t.open_tensor >= 0 ? t.tensor_row[t.open_tensor] : -1, t.n_open,
-                                            uint32_t(t.zero_mask), bits, B, uint32_t(B_eff), out,
-                                            p.opts.out_c128 != 0, s);
-            else if (out)
-                qgm::launch_tree_final(finals, int(t.finals.size()), phase, int(t.phase.size()), fixed, slots, arena,
-                                       bits, B, uint32_t(B_eff), out, p.opts.out_c128 != 0, s);
         }
         mark(4);
         hipError_t e = hipGetLastError();
@@ -1068,6 +1090,7 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     const qgm::Plan& p = plan->p;
     const qgm::TreePlan& t = p.tree;
     if (t.n_open > 0) return fail(QGM_E_UNSUPPORTED, "qgm_backward with ordering 1 supports no open qubits");
+    if (!t.sliced.empty()) return fail(QGM_E_UNSUPPORTED, "qgm_backward with ordering 1 supports no slicing");
     if (p.n_2q > 0) return fail(QGM_E_UNSUPPORTED, "qgm_backward supports no non-diagonal two-qubit gates");
     if (t.n_table_leaves > 0)   // only plans without gate values have them: nothing to differentiate
         return fail(QGM_E_UNSUPPORTED, "qgm_backward needs a circuit with gate values (value-slot gates)");
@@ -1526,6 +1549,8 @@ qgm_status qgm_autotune(qgm_plan_t* plan, const void* gate_vals, const uint64_t*
         for (int cand = qgm::KC_VALU; cand <= qgm::KC_MFMA_BF16X3; ++cand) {
             if (!qgm::step_supports(stp, cand)) continue;
             if (cand == qgm::KC_MFMA_BF16X3 && !allow_bf16x3) continue;
+            // precision BF16X3: the steps the plan gave the BF16x3 kernel keep it
+            if (p.opts.precision == QGM_PREC_BF16X3 && stp.kclass == 2 && cand != qgm::KC_MFMA_BF16X3) continue;
             std::ostringstream k;
             k << arch << ' ' << stp.kb << ' ' << stp.vb << ' ' << stp.nb << ' ' << stp.sb << ' ' << stp.r_in << ' '
               << B_eff << ' ' << cand;

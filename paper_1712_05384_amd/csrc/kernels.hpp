@@ -316,5 +316,12 @@ void launch_tb_slots(const int32_t* slot_off, const int32_t* slot_occ, int n_slo
 void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                        const float2* slots, const float2* arena, const uint64_t* bits, int64_t B, uint32_t B_eff,
                        void* out, bool c128, hipStream_t stream);
+// Slicing of bucket plans: the words of a chunk's batch columns (bitstring b, slice slice0 + j at column
+// b * 2^chunk_bits + j, slice bits above bit n), and the FP64 sum of a chunk's column amplitudes
+// (complex128 [B << chunk_bits][2^n_open]) into acc or, for the last chunk, into out.
+void launch_slice_cols(const uint64_t* bits, int64_t B, int n, int chunk_bits, uint64_t slice0, uint64_t* cols,
+                       hipStream_t stream);
+void launch_slice_sum(const double2* part, int64_t B, int chunk_bits, int n_open, double2* acc, bool first, bool last,
+                      void* out, bool c128, hipStream_t stream);
 
 }  // namespace qgm

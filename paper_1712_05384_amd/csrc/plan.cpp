@@ -175,7 +175,7 @@ void configure_step(Step& st, int cand) {
 // Kernel of a step under a kernel_policy (autotuning may change it later).
 static void classify_step(const Plan& p, Step& st) {
     int cand = KC_VALU;
-    const int pol = p.opts.kernel_policy;
+    const int pol = p.opts.precision == QGM_PREC_BF16X3 ? 4 : p.opts.kernel_policy;
     if ((pol == 2 || pol == 4) && step_supports(st, KC_MFMA_F32)) cand = pol == 4 ? KC_MFMA_BF16X3 : KC_MFMA_F32;
     else if (pol == 3 && st.kb + st.nb >= 8 && step_supports(st, KC_VALU_PAIR)) cand = KC_VALU_PAIR;
     configure_step(st, cand);
@@ -438,15 +438,26 @@ qgm_status expectation_circuit(const qgm_circuit* c, int32_t n_ops, const int32_
     return QGM_OK;
 }
 
+static qgm_status build_tree_sliced(Plan& p, std::string* err);
+
 qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
                       const qgm_plan_opts& opts, Plan& p, std::string* err) {
     qgm_status st = validate(c, open, n_open, err);
     if (st != QGM_OK) return st;
-    if ((opts.ordering != 0 && opts.ordering != 1) || opts.precision != 0) {
-        *err = "ordering must be 0 or 1 and precision 0";
-        return QGM_E_UNSUPPORTED;
+    if (opts.ordering != 0 && opts.ordering != 1) { *err = "ordering must be 0 or 1"; return QGM_E_INVALID; }
+    if (opts.precision != QGM_PREC_C64 && opts.precision != QGM_PREC_BF16X3) {
+        *err = "precision must be QGM_PREC_C64 (0) or QGM_PREC_BF16X3 (1)";
+        return QGM_E_INVALID;
     }
     if (opts.kernel_policy < 0 || opts.kernel_policy > 4) { *err = "kernel_policy must be 0..4"; return QGM_E_INVALID; }
+    if (opts.precision == QGM_PREC_BF16X3 && opts.ordering == 1) {
+        *err = "precision BF16X3 runs on the matrix-core worldline steps of ordering 0; the bucket kernels are FP32";
+        return QGM_E_UNSUPPORTED;
+    }
+    if (opts.precision == QGM_PREC_BF16X3 && opts.kernel_policy != 0 && opts.kernel_policy != 4) {
+        *err = "precision BF16X3 selects the BF16x3 kernels: kernel_policy must be 0 or 4";
+        return QGM_E_INVALID;
+    }
     if (opts.tree_exec < 0 || opts.tree_exec > 3) { *err = "tree_exec must be 0..3"; return QGM_E_INVALID; }
     if (opts.no_tile < 0 || opts.no_tile > 1) { *err = "no_tile must be 0 or 1"; return QGM_E_INVALID; }
     if (opts.order_finalists < 0 || opts.order_finalists > kTreeMaxFinalists) {
@@ -462,8 +473,10 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         return QGM_E_INVALID;
     }
     if (opts.persist_spin < 0) { *err = "persist_spin must be >= 0"; return QGM_E_INVALID; }
-    if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > 12 || opts.max_rank < 0) {
-        *err = "min_sliced_vars must be in [0, 12] and max_rank >= 0"; return QGM_E_INVALID;
+    const int max_sliced = opts.ordering == 1 ? kTreeMaxSliced : 12;
+    if (opts.min_sliced_vars < 0 || opts.min_sliced_vars > max_sliced || opts.max_rank < 0) {
+        *err = "min_sliced_vars must be in [0, " + std::to_string(max_sliced) + "] and max_rank >= 0";
+        return QGM_E_INVALID;
     }
     p.opts = opts;
     p.rows = c->rows;
@@ -531,16 +544,7 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     }
     p.sliced.clear();
     p.is_tree = opts.ordering == 1;
-    if (p.is_tree) {
-        st = build_tree_plan(p, p.tree, err);
-        if (st != QGM_OK) return st;
-        p.steps.clear();
-        p.order.clear();
-        p.final_pos.clear();
-        p.r_max = p.tree.max_rank;
-        p.g_total = p.tree.g_total;
-        return QGM_OK;
-    }
+    if (p.is_tree) return build_tree_sliced(p, err);
     p.order = vertical_order(p.rows, p.cols);
     st = build_steps(p, err);
     if (st != QGM_OK) return st;
@@ -555,6 +559,107 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
         p.sliced.push_back(v);
         st = build_steps(p, err);
         if (st != QGM_OK) return st;
+    }
+    if (opts.precision == QGM_PREC_BF16X3 &&
+        std::none_of(p.steps.begin(), p.steps.end(), [](const Step& x) { return x.kclass == 2; })) {
+        *err = "precision BF16X3: no step of this plan fits the BF16x3 matrix-core kernel (K and N of 2^3..2^5)";
+        return QGM_E_UNSUPPORTED;
+    }
+    // the slices of ordering 0 run as batch columns, which does not shrink the frontier: the budget is a check
+    if (opts.mem_budget > 0 && workspace_layout(p, 64).total > opts.mem_budget) {
+        *err = "mem_budget: the vertical plan needs " + std::to_string(workspace_layout(p, 64).total) +
+               " bytes per 64 bitstrings (ordering 1 slices to fit a budget)";
+        return QGM_E_OOM;
+    }
+    // checkpoints of qgm_backward: as many as the budget holds (less recomputation), at least the sqrt(steps)
+    // schedule
+    p.ckpt_every = 0;
+    if (opts.checkpoint_budget > 0 && opts.checkpoint_every == 0) {
+        const int S = int(p.steps.size());
+        const uint64_t frame = (uint64_t(1) << p.r_max) * 64 * 8;
+        const int c_sqrt = std::max(1, int(std::ceil(std::sqrt(double(S)))));
+        for (int c = 1; c <= c_sqrt; ++c) {
+            const uint64_t frames = uint64_t((S - 1) / c) + uint64_t(c - 1);
+            if (frames * frame <= opts.checkpoint_budget) { p.ckpt_every = c; break; }
+        }
+        if (p.ckpt_every == 0) {
+            *err = "checkpoint_budget: the sqrt(steps) checkpoint schedule needs " +
+                   std::to_string((uint64_t((S - 1) / c_sqrt) + uint64_t(c_sqrt - 1)) * frame) +
+                   " bytes per 64 bitstrings";
+            return QGM_E_OOM;
+        }
+    }
+    return QGM_OK;
+}
+
+// Ordering 1: bucket plans with sliced variables added one at a time (the one
+// in the most of the largest results) until the plan fits the kernels and
+// meets min_sliced_vars, max_rank and mem_budget; then the largest chunk of
+// slices per launch sequence whose workspace fits the budget.
+static qgm_status build_tree_sliced(Plan& p, std::string* err) {
+    const qgm_plan_opts& opts = p.opts;
+    std::vector<int> sliced;
+    std::string why;
+    while (true) {
+        std::string e;
+        const qgm_status st = build_tree_plan(p, sliced, p.tree, &e);
+        if (st != QGM_OK && st != QGM_E_UNSUPPORTED) { *err = e; return st; }
+        bool more = false;
+        if (st == QGM_E_UNSUPPORTED) {
+            // a persistent-launch or open-qubit refusal is not cured by slicing
+            if (e.find("persistent") != std::string::npos || e.find("tree_exec 3") != std::string::npos) {
+                *err = e;
+                return st;
+            }
+            more = true;
+            why = e;
+        } else {
+            p.r_max = p.tree.max_rank;
+            p.g_total = p.tree.g_total;
+            p.tree.chunk_bits = int(sliced.size());
+            if (int(sliced.size()) < opts.min_sliced_vars) {
+                more = true;
+            } else if (opts.max_rank > 0 && p.tree.max_rank > opts.max_rank) {
+                more = true;
+                why = "max_rank " + std::to_string(opts.max_rank) + " (the plan's largest result has rank " +
+                      std::to_string(p.tree.max_rank) + ")";
+            } else if (opts.mem_budget > 0) {
+                // the largest chunk of slices that fits; slice further when even one slice at a time does not
+                int cb = int(sliced.size());
+                while (cb > 0 && workspace_layout_chunk(p, 64, cb).total > opts.mem_budget) --cb;
+                if (workspace_layout_chunk(p, 64, cb).total > opts.mem_budget) {
+                    more = true;
+                    why = "mem_budget " + std::to_string(opts.mem_budget) + " bytes (one slice at a time needs " +
+                          std::to_string(workspace_layout_chunk(p, 64, cb).total) + " per 64 bitstrings)";
+                } else {
+                    p.tree.chunk_bits = cb;
+                }
+            }
+        }
+        if (!more) break;
+        if (int(sliced.size()) >= kTreeMaxSliced || p.n + int(sliced.size()) >= 64) {
+            *err = "slicing " + std::to_string(sliced.size()) + " variables does not meet " + why;
+            return opts.mem_budget > 0 || opts.max_rank > 0 ? QGM_E_OOM : QGM_E_UNSUPPORTED;
+        }
+        const int v = tree_pick_slice_var(p, sliced, st == QGM_OK ? &p.tree : nullptr);
+        if (v < 0) {
+            *err = "no variable left to slice: " + why;
+            return opts.mem_budget > 0 || opts.max_rank > 0 ? QGM_E_OOM : QGM_E_UNSUPPORTED;
+        }
+        sliced.push_back(v);
+    }
+    for (size_t j = 0; j < sliced.size(); ++j) p.vars[sliced[j]].slice_idx = int(j);
+    p.steps.clear();
+    p.order.clear();
+    p.final_pos.clear();
+    if (opts.checkpoint_budget > 0) {
+        // the bucket path's adjoint keeps every result: no schedule to trade
+        const uint64_t keep = uint64_t(p.tree.arena_rows_all) * 64 * 8;
+        if (keep > opts.checkpoint_budget) {
+            *err = "checkpoint_budget: the bucket adjoint keeps every result, " + std::to_string(keep) +
+                   " bytes per 64 bitstrings";
+            return QGM_E_OOM;
+        }
     }
     return QGM_OK;
 }
@@ -571,28 +676,36 @@ int64_t tree_flag_words(const Plan& p, int64_t B) {
     return kPersistFlags0 + tree_pitch(B) / 64 * tree_flag_stride(p);   // one flag row per group of the pitch
 }
 
-WsLayout workspace_layout(const Plan& p, int64_t B) {
+WsLayout workspace_layout(const Plan& p, int64_t B) { return workspace_layout_chunk(p, B, p.tree.chunk_bits); }
+
+WsLayout workspace_layout_chunk(const Plan& p, int64_t B, int chunk_bits) {
     auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
     WsLayout w;
-    const uint64_t be = uint64_t(batch_eff(p, B));
     if (p.is_tree) {
         // results (lifetime-packed rows; every result at its own rows for the persistent launch), factor
         // tables only when the circuit reads gate values (otherwise the plan's device tables hold them,
-        // built once), the persistent launch's flags
+        // built once), the persistent launch's flags; with slicing, the words of one chunk's batch columns,
+        // their amplitudes (complex128) and, over several chunks, the FP64 running sums
         const bool persist = tree_persistent(p, B);
+        const uint64_t cols = uint64_t(B) << chunk_bits;
+        const uint64_t be = uint64_t(tree_pitch(int64_t(cols)));
         w.f0 = w.f1 = 0;
-        if (tree_lds(p, B)) {   // results in LDS: only the call's factor tables when it reads gate values
-            w.g = 0;
-            w.flags = w.var_ids = p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0;
-            w.total = w.flags;
-            return w;
-        }
-        w.g = al(uint64_t(persist ? p.tree.arena_rows_all : p.tree.arena_rows) * be * 8);
+        const uint64_t arena = tree_lds(p, B) ? 0 : al(uint64_t(persist ? p.tree.arena_rows_all : p.tree.arena_rows) * be * 8);
+        w.g = arena;
         w.flags = w.g + (p.n_slots > 0 ? al(uint64_t(p.tree.g_total) * 8) : 0);
         w.var_ids = w.flags;
-        w.total = w.flags + (persist ? al(uint64_t(tree_flag_words(p, B)) * 4) : 0);
+        uint64_t end = w.flags + (persist ? al(uint64_t(tree_flag_words(p, B)) * 4) : 0);
+        if (!p.tree.sliced.empty()) {
+            const uint64_t n_out = uint64_t(1) << p.n_open;
+            w.ext = end;
+            w.part = w.ext + al(cols * 8);
+            w.acc = w.part + al(cols * n_out * 16);
+            end = w.acc + (chunk_bits < int(p.tree.sliced.size()) ? al(uint64_t(B) * n_out * 16) : 0);
+        }
+        w.total = end;
         return w;
     }
+    const uint64_t be = uint64_t(batch_eff(p, B));
     const uint64_t fbytes = al((uint64_t(1) << p.r_max) * be * 8);
     w.f0 = 0;
     w.f1 = fbytes;
@@ -622,28 +735,34 @@ static void json_factor(std::ostringstream& o, const TFactor& f) {
 
 static std::string tree_json(const Plan& p, int detail) {
     const TreePlan& t = p.tree;
+    const double sl_mult = double(int64_t(1) << t.sliced.size());   // per amplitude: every slice's column
     std::ostringstream o;
     o.precision(17);
     o << "{\"ordering\":1,\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols
       << ",\"n_vars\":" << p.vars.size() << ",\"n_free\":" << t.n_free << ",\"n_open\":" << t.n_open
       << ",\"n_slots\":" << p.n_slots
       << ",\"n_steps\":0,\"n_buckets\":" << t.steps.size() << ",\"n_levels\":" << t.levels.size()
-      << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":0"
+      << ",\"max_rank\":" << t.max_rank << ",\"max_inputs\":" << t.max_in << ",\"n_sliced\":" << t.sliced.size()
+      << ",\"slice_chunk_bits\":" << t.chunk_bits
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
       << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
       << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start << ",\"tail_lds_rows\":" << t.tail_lds_rows
       << ",\"level_launches\":" << tree_launches(t)
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
-      << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"order_score\":" << t.order_score << ",\"bytes_per_amp\":" << t.bytes_per_b
-      << ",\"flops_per_amp\":" << t.flops_per_b << ",\"n_phase\":" << t.phase.size()
+      << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"order_score\":" << t.order_score << ",\"bytes_per_amp\":" << t.bytes_per_b * sl_mult
+      << ",\"flops_per_amp\":" << t.flops_per_b * sl_mult << ",\"n_phase\":" << t.phase.size()
       << ",\"open_tensor\":" << t.open_tensor << ",\"zero_mask\":" << t.zero_mask
       << ",\"table_leaves\":" << t.n_table_leaves
       << ",\"lds_ok\":" << (t.lds.ok ? 1 : 0) << ",\"lds_entries\":" << t.lds.lds_size
       << ",\"lds_jobs\":" << t.lds.jobs.size() << ",\"lds_tables0\":" << t.lds.tables0
       << ",\"lds_threads\":" << t.lds.threads << ",\"lds_recs0\":" << t.lds.recs0
-      << ",\"lds_bytes_per_amp\":" << lds_bytes_per_amp(t.lds)
+      << ",\"lds_bytes_per_amp\":" << double(lds_bytes_per_amp(t.lds)) * sl_mult
       << ",\"lds_why\":\"" << t.lds.why << "\"";
+    std::vector<int> sl_q, sl_k;
+    for (int v : t.sliced) { sl_q.push_back(p.vars[v].qubit); sl_k.push_back(p.vars[v].k); }
+    o << ",\"sliced_qubit\":"; json_ints(o, sl_q);
+    o << ",\"sliced_k\":"; json_ints(o, sl_k);
     o << ",\"order\":"; json_ints(o, t.order);
     o << ",\"finals\":"; json_ints(o, t.finals);
     o << ",\"steps\":[],\"buckets\":[";
@@ -744,6 +863,7 @@ std::string plan_json(const Plan& p, int detail) {
     o << "{\"ordering\":0,\"n\":" << p.n << ",\"rows\":" << p.rows << ",\"cols\":" << p.cols << ",\"n_vars\":" << p.vars.size()
       << ",\"n_open\":" << p.n_open << ",\"n_slots\":" << p.n_slots << ",\"n_steps\":" << p.steps.size()
       << ",\"max_rank\":" << p.r_max << ",\"n_sliced\":" << p.sliced.size()
+      << ",\"checkpoint_every\":" << (p.opts.checkpoint_every > 0 ? p.opts.checkpoint_every : p.ckpt_every)
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << p.g_total
       << ",\"bytes_per_amp\":" << bytes * double(int64_t(1) << p.sliced.size())

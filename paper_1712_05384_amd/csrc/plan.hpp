@@ -77,6 +77,7 @@ struct Plan {
     int64_t g_total = 0;
     int64_t n_ops_total = 0;
     int n_diag_gates = 0, n_nondiag_gates = 0, n_cz = 0;
+    int ckpt_every = 0;                      // qgm_backward checkpoint interval chosen for checkpoint_budget (0: none)
     bool is_tree = false;                    // ordering 1: bucket elimination with a greedy order
     TreePlan tree;
     // Device copies of the constant tables, one per device ordinal.
@@ -101,7 +102,7 @@ int64_t padded_batch(int64_t B);
 // of two, so that the kernels scale rows by a shift.
 int64_t tree_pitch(int64_t B);
 inline int64_t batch_eff(const Plan& p, int64_t B) {
-    return p.is_tree ? tree_pitch(B) : padded_batch(B) << p.sliced.size();
+    return p.is_tree ? tree_pitch(B << p.tree.chunk_bits) : padded_batch(B) << p.sliced.size();
 }
 
 // Workspace of a call.  Ordering 0: two frontier buffers, the variant ids
@@ -109,8 +110,11 @@ inline int64_t batch_eff(const Plan& p, int64_t B) {
 // the circuit reads gate values, the factor tables (g).
 struct WsLayout {
     uint64_t f0 = 0, f1 = 0, var_ids = 0, g = 0, flags = 0, total = 0;
+    uint64_t ext = 0, part = 0, acc = 0;   // ordering 1 with slicing: column words, column amplitudes, sums
 };
 WsLayout workspace_layout(const Plan& p, int64_t B);
+// ... of a bucket plan run with 2^chunk_bits slices per chunk (the plan's own chunk in workspace_layout).
+WsLayout workspace_layout_chunk(const Plan& p, int64_t B, int chunk_bits);
 // The gates of U, O, U^dag restricted to O's backward light cone (qgm_expectation_circuit).
 qgm_status expectation_circuit(const qgm_circuit* c, int32_t n_ops, const int32_t* qubits, const int32_t* paulis,
                                std::vector<qgm_gate>& out, std::string* err);

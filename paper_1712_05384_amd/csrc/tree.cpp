@@ -3,6 +3,7 @@
 #include "tree.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <limits>
 #include <map>
@@ -42,6 +43,8 @@ struct Model {
     std::vector<TFactor> phase;
     std::vector<int> kept;        // free indices of the open qubits' last variables, output bit ascending
     int zero_mask = 0;            // output bits of open qubits without non-diagonal gates (amplitude 0 if set)
+    std::vector<int> sig_bit;     // per VK_SIG variable: bit of the batch column's word that fixes it (the
+                                  //   qubit for an output variable, n + j for sliced variable j)
 };
 
 TFactor fixed_factor(const Plan& p, const Model& m, const RawFactor& f) {
@@ -51,7 +54,7 @@ TFactor fixed_factor(const Plan& p, const Model& m, const RawFactor& f) {
     int* srcs[4][2] = {{&t.src0, &t.bit0}, {&t.src1, &t.bit1}, {&t.src2, &t.bit2}, {&t.src3, &t.bit3}};
     for (int i = 0; i < f.nv; ++i) {
         const int v = f.v[i];
-        if (m.kind[v] == VK_SIG) { *srcs[i][0] = TS_SIG; *srcs[i][1] = p.vars[v].qubit; }
+        if (m.kind[v] == VK_SIG) { *srcs[i][0] = TS_SIG; *srcs[i][1] = m.sig_bit[v]; }
         else { *srcs[i][0] = TS_ZERO; *srcs[i][1] = 0; }
     }
     return t;
@@ -161,7 +164,7 @@ void table_vars(const Plan& p, const Model& m, const std::vector<int>& facs, con
             if (std::find(summed.begin(), summed.end(), u) == summed.end()) gset.insert(u);
         for (int k = 0; k < rf.nv; ++k)
             if (m.kind[rf.v[k]] == VK_SIG) {
-                const int q = p.vars[rf.v[k]].qubit;
+                const int q = m.sig_bit[rf.v[k]];
                 if (std::find(sigq.begin(), sigq.end(), q) == sigq.end()) sigq.push_back(q);
             }
     }
@@ -188,7 +191,7 @@ bool fits(int rank, int n_in, int gb, int k, int sb) {
 // order[i] and sums that variable out.  With `steps`/`tens` set, also
 // records the steps.
 SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, std::vector<RStep>* steps,
-                std::vector<RTensor>* tens) {
+                std::vector<RTensor>* tens, bool check_limits = true) {
     SimOut r;
     const int nF = int(order.size());
     std::vector<int> pos(nF);
@@ -220,7 +223,7 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, st
         for (int u : A) if (u != v) out.push_back(u);
         std::sort(out.begin(), out.end(), [&](int a, int b) { return pos[a] < pos[b]; });
         const int n_in = int(bten[i].size());
-        if (!fits(int(out.size()), n_in, int(gset.size()), 1, int(sigq.size()))) {
+        if (check_limits && !fits(int(out.size()), n_in, int(gset.size()), 1, int(sigq.size()))) {
             char buf[200];
             snprintf(buf, sizeof buf, "bucket exceeds kernel limits (rank %d, inputs %d, table bits %d, output bits %d)",
                      int(out.size()), n_in, int(gset.size()), int(sigq.size()));
@@ -278,7 +281,7 @@ SimOut simulate(const Plan& p, const Model& m, const std::vector<int>& order, st
             }
             for (int tid : take) level = std::max(level, tmade[tid] + 1);
             table_vars(p, m, fac_here, {}, gset, sigq);
-            if (!fits(int(out.size()), int(take.size()), int(gset.size()), 0, int(sigq.size()))) {
+            if (check_limits && !fits(int(out.size()), int(take.size()), int(gset.size()), 0, int(sigq.size()))) {
                 r.why = "the bucket over the open qubits exceeds the kernel limits";
                 return r;
             }
@@ -610,7 +613,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
                         }
                     } else if (m.kind[var] == VK_SIG) {
                         *srcs[k][0] = TS_SIG;
-                        *srcs[k][1] = int(std::find(st.sig_q.begin(), st.sig_q.end(), p.vars[var].qubit) - st.sig_q.begin());
+                        *srcs[k][1] = int(std::find(st.sig_q.begin(), st.sig_q.end(), m.sig_bit[var]) - st.sig_q.begin());
                     } else {
                         *srcs[k][0] = TS_ZERO;
                         *srcs[k][1] = 0;
@@ -623,9 +626,6 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     }
     return QGM_OK;
 }
-
-namespace {
-}  // namespace
 
 double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
     if (st.table_leaf) return 0.0;   // built once with the plan
@@ -641,22 +641,20 @@ double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
 static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vector<std::pair<int, int>>& kept,
                                   const std::vector<int>& best, TreePlan& t, std::string* err);
 
-qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
-    t = TreePlan{};
-    if (p.n_open != 0 && p.opts.tree_exec == 2) {
-        *err = "the persistent launch (tree_exec 2) supports no open qubits";
-        return QGM_E_UNSUPPORTED;
-    }
-    if (p.opts.min_sliced_vars != 0 || p.opts.max_rank != 0) {
-        *err = "ordering 1 does not slice (min_sliced_vars and max_rank must be 0)";
-        return QGM_E_UNSUPPORTED;
-    }
-    Model m;
+namespace {
+
+// The variables left free by the deltas of Eq. (psi_x) and by slicing, the
+// factors over them, and the factors without any (the per-bitstring phase).
+// A sliced variable is fixed like an output variable, by bit n + j of the
+// batch column's word (j: its position in `sliced`).
+void build_model(const Plan& p, const std::vector<int>& sliced, Model& m, std::vector<std::pair<int, int>>& kept) {
     const int nv = int(p.vars.size());
     m.kind.assign(nv, VK_FREE);
     m.fi.assign(nv, -1);
+    m.sig_bit.assign(nv, -1);
     for (int v = 0; v < nv; ++v) {
         const VarInfo& vi = p.vars[v];
+        const auto sl = std::find(sliced.begin(), sliced.end(), v);
         if (vi.is_c0) {
             m.kind[v] = VK_ZERO;
             if (vi.is_final && vi.open_idx >= 0) {   // open, without non-diagonal gates: only output bit 0
@@ -670,14 +668,17 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
             }
         } else if (vi.is_final && vi.open_idx < 0) {
             m.kind[v] = VK_SIG;
+            m.sig_bit[v] = vi.qubit;
+        } else if (sl != sliced.end()) {
+            m.kind[v] = VK_SIG;
+            m.sig_bit[v] = p.n + int(sl - sliced.begin());
         } else {
             m.fi[v] = int(m.free_var.size());
             m.free_var.push_back(v);
         }
     }
-    const int nF = int(m.free_var.size());
     // the open qubits' last variables (free, never summed), by output bit
-    std::vector<std::pair<int, int>> kept;
+    kept.clear();
     for (int v = 0; v < nv; ++v)
         if (p.vars[v].is_final && !p.vars[v].is_c0 && p.vars[v].open_idx >= 0) kept.push_back({p.vars[v].open_idx, m.fi[v]});
     std::sort(kept.begin(), kept.end());
@@ -697,15 +698,60 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         if (f.free.empty()) m.phase.push_back(fixed_factor(p, m, f));
         else m.facs.push_back(f);
     }
-    t.phase = m.phase;
-    t.n_free = nF;
+}
+
+// The interaction graph of the free variables: a factor joins its free
+// variables pairwise (a 4-clique for a two-qubit gate).
+std::vector<uint8_t> model_graph(const Model& m) {
+    const int nF = int(m.free_var.size());
     std::vector<uint8_t> adj(size_t(nF) * nF, 0);
-    for (auto& f : m.facs)   // a factor joins its free variables pairwise (a 4-clique for a two-qubit gate)
+    for (auto& f : m.facs)
         for (size_t i = 0; i < f.free.size(); ++i)
             for (size_t j = i + 1; j < f.free.size(); ++j) {
                 adj[size_t(f.free[i]) * nF + f.free[j]] = 1;
                 adj[size_t(f.free[j]) * nF + f.free[i]] = 1;
             }
+    return adj;
+}
+
+// Greedy order with the open qubits' variables moved to its end.
+std::vector<int> candidate_order(const Model& m, const std::vector<uint8_t>& adj, int crit, int rs) {
+    const int nF = int(m.free_var.size());
+    std::vector<int> ord = greedy_order(nF, adj, crit, rs == 0 ? 0 : 0x5EED0000ull + uint64_t(rs) * 131 + crit);
+    if (!m.kept.empty()) {   // the open qubits' variables close the order, by output bit
+        std::vector<int> o2;
+        for (int u : ord)
+            if (std::find(m.kept.begin(), m.kept.end(), u) == m.kept.end()) o2.push_back(u);
+        o2.insert(o2.end(), m.kept.begin(), m.kept.end());
+        ord.swap(o2);
+    }
+    return ord;
+}
+
+}  // namespace
+
+qgm_status build_tree_plan(const Plan& p, const std::vector<int>& sliced, TreePlan& t, std::string* err) {
+    t = TreePlan{};
+    if (p.n_open != 0 && p.opts.tree_exec == 2) {
+        *err = "the persistent launch (tree_exec 2) supports no open qubits";
+        return QGM_E_UNSUPPORTED;
+    }
+    if (!sliced.empty() && p.opts.tree_exec == 2) {
+        *err = "the persistent launch (tree_exec 2) supports no slicing";
+        return QGM_E_UNSUPPORTED;
+    }
+    if (p.n + int(sliced.size()) > 64) {
+        *err = "sliced variables are fixed by the bits above the qubits of a 64-bit word: n + sliced <= 64";
+        return QGM_E_UNSUPPORTED;
+    }
+    Model m;
+    std::vector<std::pair<int, int>> kept;
+    build_model(p, sliced, m, kept);
+    t.sliced = sliced;
+    const int nF = int(m.free_var.size());
+    t.phase = m.phase;
+    t.n_free = nF;
+    const std::vector<uint8_t> adj = model_graph(m);
     // candidate orders: deterministic min-degree and min-fill, then randomised tie breaks, ranked by the
     // symbolic cost (bytes before chain merging, a level weighed as 4 KiB per bitstring)
     const int restarts = p.opts.order_restarts > 0 ? p.opts.order_restarts
@@ -714,14 +760,7 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
     std::string last_why;
     for (int crit = 0; crit < 2; ++crit)
         for (int rs = 0; rs <= restarts; ++rs) {
-            std::vector<int> ord = greedy_order(nF, adj, crit, rs == 0 ? 0 : 0x5EED0000ull + uint64_t(rs) * 131 + crit);
-            if (!m.kept.empty()) {   // the open qubits' variables close the order, by output bit
-                std::vector<int> o2;
-                for (int u : ord)
-                    if (std::find(m.kept.begin(), m.kept.end(), u) == m.kept.end()) o2.push_back(u);
-                o2.insert(o2.end(), m.kept.begin(), m.kept.end());
-                ord.swap(o2);
-            }
+            std::vector<int> ord = candidate_order(m, adj, crit, rs);
             SimOut r = simulate(p, m, ord, nullptr, nullptr);
             ++t.n_candidates;
             if (!r.ok) { last_why = r.why; continue; }
@@ -775,6 +814,48 @@ qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err) {
         return QGM_E_UNSUPPORTED;
     }
     return QGM_OK;
+}
+
+int tree_pick_slice_var(const Plan& p, const std::vector<int>& sliced, const TreePlan* t) {
+    // index spaces (summed and result variables, as variable ids) of the buckets of the built plan, or of
+    // the plain min-fill order's buckets without the kernel limits when no order fits
+    std::vector<std::vector<int>> spaces;
+    if (t) {
+        for (const TreeStep& st : t->steps) {
+            std::vector<int> sp = st.vars;
+            sp.insert(sp.end(), st.out_axes.begin(), st.out_axes.end());
+            spaces.push_back(sp);
+        }
+    } else {
+        Model m;
+        std::vector<std::pair<int, int>> kept;
+        build_model(p, sliced, m, kept);
+        if (m.free_var.empty()) return -1;
+        const std::vector<int> ord = candidate_order(m, model_graph(m), 1, 0);
+        std::vector<RStep> rs;
+        std::vector<RTensor> rt;
+        SimOut r = simulate(p, m, ord, &rs, &rt, false);
+        if (!r.ok) return -1;
+        for (const RStep& st : rs) {
+            std::vector<int> sp;
+            for (int u : st.vars) sp.push_back(m.free_var[u]);
+            for (int u : st.out) sp.push_back(m.free_var[u]);
+            spaces.push_back(sp);
+        }
+    }
+    int big = 0;
+    for (const auto& sp : spaces) big = std::max(big, int(sp.size()));
+    // score: sum over the buckets using the variable of 4^(size - largest size), so the variables of the
+    // largest buckets come first; open qubits' variables are never sliced
+    std::map<int, double> score;
+    for (const auto& sp : spaces)
+        for (int v : sp)
+            if (!(p.vars[v].is_final && p.vars[v].open_idx >= 0)) score[v] += std::ldexp(1.0, 2 * (int(sp.size()) - big));
+    int best = -1;
+    double bs = 0.0;
+    for (const auto& kv : score)
+        if (kv.second > bs) { bs = kv.second; best = kv.first; }
+    return best;
 }
 
 // The plan of one elimination order: buckets, chains merged, leaves absorbed,

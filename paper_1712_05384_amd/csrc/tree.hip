@@ -949,4 +949,52 @@ void launch_tree_final(const int64_t* final_rows, int n_final, const TFactor* ph
                        slots, arena, bits, B, B_eff, out, c128 ? 1 : 0);
 }
 
+// Slicing (Sec. V outlook): the batch columns of one chunk of slices.  Column
+// b * 2^chunk_bits + j carries bitstring b with slice (slice0 + j) in the
+// bits above the n qubits, so the kernels fix sliced variable i by bit n + i
+// exactly as they fix an output variable by its qubit's bit.
+__global__ void __launch_bounds__(256) k_slice_cols(const uint64_t* __restrict__ bits, int64_t B, int n,
+                                                    int chunk_bits, uint64_t slice0, uint64_t* __restrict__ cols) {
+    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= (B << chunk_bits)) return;
+    const int64_t b = c >> chunk_bits;
+    const uint64_t j = uint64_t(c) & ((uint64_t(1) << chunk_bits) - 1);
+    cols[c] = bits[b] | ((slice0 + j) << n);
+}
+
+// Sum over the slices of one chunk, in slice order, in FP64: v = (first ? 0 :
+// acc) + sum_j part[b * 2^chunk_bits + j][o]; the last chunk writes the
+// amplitude (complex64 or complex128), the others the running sum.
+__global__ void __launch_bounds__(256) k_slice_sum(const double2* __restrict__ part, int64_t B, int chunk_bits,
+                                                   int n_open, double2* __restrict__ acc, int first, int last,
+                                                   void* __restrict__ out, int c128) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t n_out = int64_t(1) << n_open;
+    if (e >= B * n_out) return;
+    const int64_t b = e >> n_open, o = e & (n_out - 1);
+    double2 v = first ? make_double2(0.0, 0.0) : acc[e];
+    for (int64_t j = 0; j < (int64_t(1) << chunk_bits); ++j) {
+        const double2 x = part[(((b << chunk_bits) + j) << n_open) + o];
+        v.x += x.x;
+        v.y += x.y;
+    }
+    if (!last) acc[e] = v;
+    else if (c128) static_cast<double2*>(out)[e] = v;
+    else static_cast<float2*>(out)[e] = make_float2(float(v.x), float(v.y));
+}
+
+void launch_slice_cols(const uint64_t* bits, int64_t B, int n, int chunk_bits, uint64_t slice0, uint64_t* cols,
+                       hipStream_t stream) {
+    const int64_t m = B << chunk_bits;
+    hipLaunchKernelGGL(k_slice_cols, dim3(uint32_t((m + 255) / 256)), dim3(256), 0, stream, bits, B, n, chunk_bits,
+                       slice0, cols);
+}
+
+void launch_slice_sum(const double2* part, int64_t B, int chunk_bits, int n_open, double2* acc, bool first, bool last,
+                      void* out, bool c128, hipStream_t stream) {
+    const int64_t m = B << n_open;
+    hipLaunchKernelGGL(k_slice_sum, dim3(uint32_t((m + 255) / 256)), dim3(256), 0, stream, part, B, chunk_bits, n_open,
+                       acc, first ? 1 : 0, last ? 1 : 0, out, c128 ? 1 : 0);
+}
+
 }  // namespace qgm

@@ -35,6 +35,7 @@ namespace qgm {
 struct Plan;
 
 constexpr int kTreeMaxRank = 28;    // rank of a bucket result
+constexpr int kTreeMaxSliced = 24;  // sliced variables of a bucket plan (also n + sliced <= 64)
 // Persistent launch (qgm_amplitudes, tree_exec): the flags area holds the
 // abort word at [0], one word per (complex, rank) of its work-groups from
 // kPersistSeen0, and the completion flags from kPersistFlags0.
@@ -265,6 +266,11 @@ struct TreePlan {
     double bytes_per_b = 0;                      // algorithmic HBM bytes per bitstring
     double flops_per_b = 0;
     LdsProgram lds;                              // the LDS-resident program (lds.ok when the plan fits)
+    // slicing (Sec. V outlook): sliced variable j is fixed by bit n + j of a batch column's word; a call runs
+    // the 2^sliced slices of every bitstring in chunks of 2^chunk_bits as batch columns (column
+    // b * 2^chunk_bits + j) and sums them in FP64 in slice order
+    std::vector<int> sliced;
+    int chunk_bits = 0;
 };
 
 // Builds t.lds from a finished bucket plan (sets t.lds.ok = false with a reason
@@ -276,8 +282,14 @@ void build_lds_program(TreePlan& t);
 int64_t lds_bytes_per_amp(const LdsProgram& P);
 
 // Builds the bucket plan from the variables and gate records in `p`
-// (ordering 1; no open qubits, no slicing).
-qgm_status build_tree_plan(const Plan& p, TreePlan& t, std::string* err);
+// (ordering 1) with the variables in `sliced` fixed: slice j's value is bit
+// n + j of a batch column's word (n + sliced.size() <= 64).
+qgm_status build_tree_plan(const Plan& p, const std::vector<int>& sliced, TreePlan& t, std::string* err);
+// The next variable to slice: the one in the most of the largest bucket index
+// spaces (summed and result variables) of `t` (or, when no order fits the
+// kernels, of the min-fill order's buckets without the limits); -1 when none
+// is left.
+int tree_pick_slice_var(const Plan& p, const std::vector<int>& sliced, const TreePlan* t);
 
 // Row accesses (loads and stores of 64 lanes x 8 bytes) of one wave unit of a bucket.
 int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st);

@@ -50,51 +50,57 @@ def run_lds_program(info, gate_vals, bits):
     size = L["size"]
     out = np.zeros(len(bits), dtype=np.complex128)
     stage_q = [st["sig_q"] for st in L["stages"]]
+    S, n = info.get("n_sliced", 0), info["n"]
     for bi, x in enumerate(np.asarray(bits, dtype=np.uint64)):
-        x = int(x)
-        lds = np.full(size, np.nan, dtype=np.complex128)
-        sig = [sum(((x >> q) & 1) << i for i, q in enumerate(sq)) for sq in stage_q]
-        for e, (src, s) in enumerate(L["entries"]):
-            dst = L["tables0"] + e
-            assert 0 <= dst < size
-            lds[dst] = area[src + sig[s]]
-        offs = L["level_job_off"]
-        for lv in range(len(offs) - 1):
-            writes, reads = {}, set()
-            for j in range(offs[lv], offs[lv + 1]):
-                jb = L["jobs"][j]
-                nin, k, lanes = jb["nin"], jb["k"], jb["lanes"]
-                for lane in range(64):
-                    # the lane's offsets: the job's base plus the strides of the lane's six bits (inputs, then
-                    # the table)
-                    off = [jb["base"][sl] + sum(((lane >> i) & 1) * jb["str"][sl][i] for i in range(6))
-                           for sl in range(nin + 1)]
-                    acc = 0j
-                    for w in range(1 << k):
-                        a = off[nin] + jb["tw"][w]
-                        assert 0 <= a < size
-                        v = lds[a]
-                        reads.add(a)
-                        for t in range(nin):
-                            a = off[t] + jb["in_w"][t][w]
-                            assert 0 <= a < size, (j, lane, t, w, a)
-                            reads.add(a)
-                            v = v * lds[a]
-                        acc += v
-                    if lane < lanes:
-                        dst = jb["out_row"] + lane
-                        assert 0 <= dst < L["tables0"], (j, lane, dst)
-                        assert not np.isnan(acc), (lv, j, lane)
-                        assert dst not in writes
-                        writes[dst] = acc
-            assert not (set(writes) & reads), "a level writes an entry it reads"
-            for d, v in writes.items():
-                lds[d] = v
-        amp = 1.0 + 0j
-        for f in info["phase"]:
-            amp = amp * complex(_eval(f, lambda src, bit: ((x >> bit) & 1) if src == TS_SIG else 0, gate_vals))
-        for fr in L["finals"]:
-            assert not np.isnan(lds[fr])
-            amp *= lds[fr]
-        out[bi] = amp
+        # a sliced plan: one program run per slice s (sliced variable j fixed by bit n + j), summed
+        out[bi] = sum(_run_column(info, L, area, stage_q, size, int(x) | (s << n), gate_vals) for s in range(1 << S))
     return out
+
+
+def _run_column(info, L, area, stage_q, size, x, gate_vals):
+    """One batch column (bitstring word x, slice bits above the qubits) through the LDS program."""
+    lds = np.full(size, np.nan, dtype=np.complex128)
+    sig = [sum(((x >> q) & 1) << i for i, q in enumerate(sq)) for sq in stage_q]
+    for e, (src, s) in enumerate(L["entries"]):
+        dst = L["tables0"] + e
+        assert 0 <= dst < size
+        lds[dst] = area[src + sig[s]]
+    offs = L["level_job_off"]
+    for lv in range(len(offs) - 1):
+        writes, reads = {}, set()
+        for j in range(offs[lv], offs[lv + 1]):
+            jb = L["jobs"][j]
+            nin, k, lanes = jb["nin"], jb["k"], jb["lanes"]
+            for lane in range(64):
+                # the lane's offsets: the job's base plus the strides of the lane's six bits (inputs, then
+                # the table)
+                off = [jb["base"][sl] + sum(((lane >> i) & 1) * jb["str"][sl][i] for i in range(6))
+                       for sl in range(nin + 1)]
+                acc = 0j
+                for w in range(1 << k):
+                    a = off[nin] + jb["tw"][w]
+                    assert 0 <= a < size
+                    v = lds[a]
+                    reads.add(a)
+                    for t in range(nin):
+                        a = off[t] + jb["in_w"][t][w]
+                        assert 0 <= a < size, (j, lane, t, w, a)
+                        reads.add(a)
+                        v = v * lds[a]
+                    acc += v
+                if lane < lanes:
+                    dst = jb["out_row"] + lane
+                    assert 0 <= dst < L["tables0"], (j, lane, dst)
+                    assert not np.isnan(acc), (lv, j, lane)
+                    assert dst not in writes
+                    writes[dst] = acc
+        assert not (set(writes) & reads), "a level writes an entry it reads"
+        for d, v in writes.items():
+            lds[d] = v
+    amp = 1.0 + 0j
+    for f in info["phase"]:
+        amp = amp * complex(_eval(f, lambda src, bit: ((x >> bit) & 1) if src == TS_SIG else 0, gate_vals))
+    for fr in L["finals"]:
+        assert not np.isnan(lds[fr])
+        amp *= lds[fr]
+    return amp

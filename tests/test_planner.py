@@ -250,16 +250,22 @@ def test_tree_plan_is_deterministic_and_consistent():
     assert readers == [1] * len(a["tensors"])
 
 
-def test_tree_plan_rejects_slicing_and_persistent_open_qubits():
+def test_tree_plan_refusals():
+    """What the bucket path refuses: the persistent launch with open qubits or
+    slicing, BF16x3 precision, too many sliced variables; out-of-range options
+    are QGM_E_INVALID."""
     c = C.random_grid_circuit(3, 3, 8, 1)
-    for kw in (dict(min_sliced_vars=1), dict(max_rank=3), dict(open_qubits=(0,), tree_exec=2)):
-        oq = kw.pop("open_qubits", ())
+    for oq, kw, status in (((0,), dict(tree_exec=2), N.QGM_E_UNSUPPORTED),
+                           ((), dict(tree_exec=2, min_sliced_vars=1), N.QGM_E_UNSUPPORTED),
+                           ((), dict(precision=N.QGM_PREC_BF16X3), N.QGM_E_UNSUPPORTED),
+                           ((), dict(min_sliced_vars=25), N.QGM_E_INVALID),
+                           ((), dict(precision=2), N.QGM_E_INVALID)):
         with pytest.raises(N.QgmError) as e:
             Q.plan(c, oq, ordering=1, **kw)
-        assert e.value.status == N.QGM_E_UNSUPPORTED
+        assert e.value.status == status, kw
     with pytest.raises(N.QgmError) as e:
         Q.plan(c, ordering=2)
-    assert e.value.status == N.QGM_E_UNSUPPORTED
+    assert e.value.status == N.QGM_E_INVALID
     # the adjoint is supported: its workspace holds every result and its adjoint
     p = Q.plan(c, ordering=1)
     assert p.backward_workspace_bytes(64) > 2 * p.workspace_bytes(64) - 4096
@@ -615,3 +621,122 @@ def test_lds_program_limits():
     with pytest.raises(N.QgmError) as ei:
         Q.plan(big, ordering=1, tree_exec=3)
     assert ei.value.status == N.QGM_E_UNSUPPORTED
+
+
+# ---- slicing of bucket plans (Sec. V outlook: space-time tradeoffs) ----------
+
+@pytest.mark.parametrize("rows,cols,depth,seed,msv", [(3, 4, 12, 7, 1), (3, 4, 12, 7, 3), (4, 4, 16, 2, 2),
+                                                      (2, 5, 14, 9, 4)])
+def test_tree_slicing_interpreted_matches_oracle(rows, cols, depth, seed, msv):
+    """A sliced bucket plan fixes each sliced variable by a bit above the
+    qubits of a batch column's word; the sum over its 2^s slices, run through
+    the CPU interpreter of the exported plan, equals the state-vector
+    amplitudes, and so does its LDS program."""
+    from lds_interp import run_lds_program
+    c = C.random_grid_circuit(rows, cols, depth, seed)
+    bits = C.random_bitstrings(c.n, 6, seed)
+    p = Q.plan(c, ordering=1, min_sliced_vars=msv)
+    info = p.info(2)
+    assert info["n_sliced"] == msv == len(info["sliced_qubit"]) and info["slice_chunk_bits"] == msv
+    ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
+    assert np.abs(run_tree_plan(info, None, bits) - ref).max() < 1e-12 * 2 ** (-c.n / 2)
+    if info["lds_ok"]:
+        assert np.abs(run_lds_program(info, None, bits[:2]) - ref[:2]).max() < 1e-12 * 2 ** (-c.n / 2)
+    # the slicing variables are gone from every result, and the sliced plan's largest result is no larger
+    sl = set(zip(info["sliced_qubit"], info["sliced_k"]))
+    assert info["max_rank"] <= Q.plan(c, ordering=1).info(0)["max_rank"]
+    assert len(sl) == msv
+
+
+def test_tree_slicing_gate_values_and_open_qubits():
+    cp = C.parameterised_circuit(3, 4, 12, 3)
+    bits = C.random_bitstrings(cp.n, 4, 3)
+    info = Q.plan(cp, ordering=1, min_sliced_vars=2).info(2)
+    ref = oracle.sv_amplitudes(cp.n, cp.gates, cp.gate_vals, bits)
+    assert np.abs(run_tree_plan(info, cp.gate_vals, bits) - ref).max() < 1e-12 * 2 ** (-cp.n / 2)
+    c = C.random_grid_circuit(3, 3, 10, 4)
+    oq = (1, 5)
+    info = Q.plan(c, oq, ordering=1, min_sliced_vars=2).info(2)
+    assert info["n_sliced"] == 2
+    got = run_tree_plan(info, None, C.random_bitstrings(c.n, 3, 4))
+    for i, x in enumerate(C.random_bitstrings(c.n, 3, 4)):
+        for o in range(4):
+            y = int(x)
+            for j, q in enumerate(oq):
+                y = (y & ~(1 << q)) | (((o >> j) & 1) << q)
+            want = oracle.sv_amplitudes(c.n, c.gates, None, np.array([y], dtype=np.uint64))[0]
+            assert abs(got[i, o] - want) < 1e-12 * 2 ** (-c.n / 2)
+
+
+def test_tree_mem_budget_and_max_rank():
+    """mem_budget bounds the workspace of 64 bitstrings: the planner slices and
+    then runs as many slices per chunk as fit; max_rank bounds every result;
+    a budget that no slicing meets is QGM_E_OOM."""
+    c, _ = C.workload("c3_5x6_d30")
+    free = Q.plan(c, ordering=1)
+    assert free.info(0)["n_sliced"] == 0
+    budget = free.workspace_bytes(64) // 2
+    p = Q.plan(c, ordering=1, mem_budget=budget, tree_exec=1)
+    info = p.info(0)
+    assert info["n_sliced"] >= 1 and p.workspace_bytes(64) <= budget
+    assert info["slice_chunk_bits"] <= info["n_sliced"]
+    # the same slices all at once take more memory than the budget allows
+    p_all = Q.plan(c, ordering=1, min_sliced_vars=info["n_sliced"], tree_exec=1)
+    if info["slice_chunk_bits"] < info["n_sliced"]:
+        assert p_all.workspace_bytes(64) > budget
+    r = Q.plan(c, ordering=1, max_rank=10).info(0)
+    assert r["max_rank"] <= 10 and r["n_sliced"] >= 1
+    # the LDS-resident launch of a circuit without gate values needs no workspace at all; the level
+    # launches need their arena, which no slicing brings to one byte
+    small = C.random_grid_circuit(2, 3, 8, 1)
+    assert Q.plan(small, ordering=1, mem_budget=1).workspace_bytes(64) == 0
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(small, ordering=1, mem_budget=1, tree_exec=1)
+    assert e.value.status == N.QGM_E_OOM
+
+
+def test_tree_headline_circuits_plan_with_slicing():
+    """The 5x9 depth-40 and 7x8 depth-30 circuits (Abstract) plan on the bucket
+    path: slicing brings every result under the kernels' rank limit, and a
+    memory budget slices further."""
+    for r, cc, d in ((5, 9, 40), (7, 8, 30)):
+        c = C.random_grid_circuit(r, cc, d, 1)
+        p = Q.plan(c, ordering=1)
+        info = p.info(0)
+        assert info["max_rank"] <= 28 and info["n"] + info["n_sliced"] <= 64
+        b = Q.plan(c, ordering=1, mem_budget=2 << 30)
+        assert b.workspace_bytes(64) <= 2 << 30 and b.info(0)["n_sliced"] > info["n_sliced"]
+
+
+def test_precision_and_checkpoint_budget_ordering_0():
+    """precision BF16X3 gives every supporting step the BF16x3 kernel (the same
+    plan as kernel_policy 4); checkpoint_budget picks the checkpoint interval
+    with the least recomputation that fits, at most ceil(sqrt(steps))."""
+    c, _ = C.workload("c3_5x6_d30")
+    a = Q.plan(c, precision=N.QGM_PREC_BF16X3, min_sliced_vars=2).info(0)
+    b = Q.plan(c, kernel_policy=4, min_sliced_vars=2).info(0)
+    ka = [s["kernel"] for s in a["steps"]]
+    assert ka == [s["kernel"] for s in b["steps"]] and "mfma_bf16x3" in ka
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(c, precision=N.QGM_PREC_BF16X3, kernel_policy=2)
+    assert e.value.status == N.QGM_E_INVALID
+    tiny = C.random_grid_circuit(2, 2, 4, 1)
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(tiny, precision=N.QGM_PREC_BF16X3)
+    assert e.value.status == N.QGM_E_UNSUPPORTED
+    cp = C.parameterised_circuit(3, 3, 12, 2)
+    info = Q.plan(cp).info(0)
+    S, r = info["n_steps"], info["max_rank"]
+    frame = (1 << r) * 64 * 8
+    c_sqrt = int(np.ceil(np.sqrt(S)))
+    assert Q.plan(cp).info(0)["checkpoint_every"] == 0
+    assert Q.plan(cp, checkpoint_budget=(S - 1) * frame).info(0)["checkpoint_every"] == 1
+    need_sqrt = ((S - 1) // c_sqrt + c_sqrt - 1) * frame
+    ce = Q.plan(cp, checkpoint_budget=need_sqrt).info(0)["checkpoint_every"]
+    assert 1 <= ce <= c_sqrt and ((S - 1) // ce + ce - 1) * frame <= need_sqrt
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(cp, checkpoint_budget=need_sqrt - 1)
+    assert e.value.status == N.QGM_E_OOM
+    with pytest.raises(N.QgmError) as e:
+        Q.plan(cp, ordering=1, checkpoint_budget=1024)
+    assert e.value.status == N.QGM_E_OOM

@@ -83,8 +83,18 @@ def bucket_table(st, gate_vals):
 
 
 def run_tree_plan(info, gate_vals, bits):
-    """Executes a detail-1 tree plan for uint64 bitstrings; returns complex128 [B]."""
+    """Executes a detail-1 tree plan for uint64 bitstrings; returns complex128 [B]
+    (or [B, 2^n_open]).  A sliced plan runs once per slice s, with s in the bits
+    above the n qubits of every word (sliced variable j is fixed by bit n + j),
+    and the slices are summed."""
     bits = np.asarray(bits, dtype=np.uint64)
+    S = info.get("n_sliced", 0)
+    if S == 0:
+        return _run_tree_columns(info, gate_vals, bits)
+    return sum(_run_tree_columns(info, gate_vals, bits | np.uint64(s << info["n"])) for s in range(1 << S))
+
+
+def _run_tree_columns(info, gate_vals, bits):
     B = len(bits)
     tensors = info["tensors"]
     arena = np.zeros((max(info["arena_rows"], 1), B), dtype=np.complex128)

@@ -6,14 +6,22 @@
  * single-qubit gates and CZ gates (Sec. III.A, Eq. (fpath)), for a batch of
  * output bitstrings x, by variable elimination on the graphical model of
  * Sec. III.B (Eq. (psi_x)): one Boolean variable per qubit per non-diagonal
- * gate, complex factors per gate, eliminated in the vertical (worldline by
- * worldline) order of Sec. IV.A.  Leaving some output deltas out of Eq. (psi_x)
- * gives sets of amplitudes at once (the "open" qubits below).
+ * gate, complex factors per gate, eliminated either in the vertical (worldline
+ * by worldline) order of Sec. IV.A (ordering 0) or by bucket elimination
+ * (App. A) along greedy treewidth orders (Sec. IV.B; ordering 1, the faster).
+ * Leaving some output deltas out of Eq. (psi_x) gives sets of amplitudes at
+ * once (the "open" qubits below, Sec. III.A); fixing some variables and
+ * summing over their values ("slicing", the space-time tradeoff of Sec. V)
+ * bounds the memory of the largest intermediate results (Sec. II).
  *
  * Conventions (all entry points)
  *  - Qubit (r, c) of a rows x cols lattice has index q = r*cols + c; n <= 64.
  *  - A bitstring is a uint64_t whose bit q is the output bit of qubit q.  Bits
  *    at positions >= n and bits on open qubits are ignored.
+ *  - Entry points that implement a passage of the paper name it; the
+ *    multi-circuit entry is qgm_graph_create (there is no separate
+ *    plan-for-many-circuits call: each circuit gets its own plan, order and
+ *    slicing from qgm_plan, and one graph runs them together).
  *  - Complex numbers are interleaved (re, im): complex64 = 2 floats,
  *    complex128 = 2 doubles.  A 2x2 gate matrix is stored row-major with
  *    element [row][col] = <row|U|col> (row = the state after the gate).
@@ -185,9 +193,15 @@ typedef struct qgm_plan_s qgm_plan_t;
 /* Fills *opts with the defaults (all zero: vertical order, complex64 out). */
 void qgm_default_opts(qgm_plan_opts* opts);
 
-/* Builds a contraction plan on the host (no device call).  The plan depends on
- * which gates are diagonal and on the open qubits, not on gate values or
- * bitstrings, so one plan serves any batch of bitstrings and any gate_vals.
+/* Builds a contraction plan on the host (no device call): the graphical model
+ * of Sec. III.B (a variable per qubit at the start and after every
+ * non-diagonal gate; one factor per gate, CZ as the pairwise factor
+ * (-1)^(a b)), the elimination order (the vertical order of Sec. IV.A, or the
+ * cheapest of several greedy min-degree / min-fill orders, Sec. IV.B, run as
+ * the bucket elimination of App. A), the sliced variables (Sec. V) and the
+ * device program of every step.  The plan depends on which gates are diagonal
+ * and on the open qubits, not on gate values or bitstrings, so one plan serves
+ * any batch of bitstrings and any gate_vals.
  *  open_qubits: host array [n_open] of distinct qubits whose output bit is left
  *               free (the delta of Eq. (psi_x) omitted); output index bit i
  *               corresponds to open_qubits[i].  May be NULL when n_open = 0.
@@ -195,28 +209,40 @@ void qgm_default_opts(qgm_plan_opts* opts);
  *  *out:        receives the plan; free it with qgm_plan_destroy.
  * Errors: QGM_E_INVALID for a malformed circuit (qubit out of range, CZ with
  * q0 == q1, a qubit used twice in one cycle, unknown kind, slot out of range),
- * duplicate or out-of-range open qubits; QGM_E_UNSUPPORTED when a step would
- * exceed the kernels' limits. */
+ * duplicate or out-of-range open qubits, out-of-range options;
+ * QGM_E_UNSUPPORTED when a step would exceed the kernels' limits (ordering 1
+ * first slices to meet them); QGM_E_OOM when max_rank, mem_budget or
+ * checkpoint_budget cannot be met. */
 qgm_status qgm_plan(const qgm_circuit* circuit, const int32_t* open_qubits, int32_t n_open,
                     const qgm_plan_opts* opts, qgm_plan_t** out);
 
 /* Writes a JSON description of the plan into json[0..cap) (NUL-terminated) and
  * the size it needs (including the NUL) into *needed (may be NULL).  detail 0:
- * summary and per-step sizes; detail 1: also the axis layouts and the factor
- * programs of every step.  Returns QGM_E_INVALID if cap is too small (json may
+ * summary and per-step sizes (rank, sliced variables, bytes and flops per
+ * amplitude); detail 1: also the axis layouts and the factor programs of every
+ * step; detail 2 (ordering 1): also the LDS-resident program (its jobs and
+ * table copies).  Returns QGM_E_INVALID if cap is too small (json may
  * be NULL to query the size). */
 qgm_status qgm_plan_info(const qgm_plan_t* plan, int32_t detail, char* json, size_t cap, size_t* needed);
 
-/* Device workspace (bytes) that qgm_amplitudes needs for a batch of B bitstrings.
- * For ordering 1 the arena's rows hold B rounded up to a power of two (at least
- * 64) bitstrings, so the kernels scale rows by a shift: a batch just above a
- * power of two takes up to twice the memory of one just below it (the work
- * covers only the batch's own 64-bitstring groups). */
+/* Device workspace (bytes) that qgm_amplitudes needs for a batch of B
+ * bitstrings: the live intermediate results of the elimination, whose size is
+ * the memory wall of Sec. II (ordering 0: two frontier tensors and the variant
+ * ids; ordering 1: the arena of bucket results, none for the LDS-resident
+ * launch), the factor tables of the call when the circuit reads gate values,
+ * and for a sliced bucket plan the words and amplitudes of one chunk's batch
+ * columns and the FP64 slice sums.  For ordering 1 the arena's rows hold the
+ * chunk's columns (B << slice_chunk_bits) rounded up to a power of two (at
+ * least 64), so the kernels scale rows by a shift: a batch just above a power
+ * of two takes up to twice the memory of one just below it (the work covers
+ * only the batch's own 64-column groups). */
 qgm_status qgm_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);
 
 /* Computes out[b][o] = <x_b with the open bits set to o | U | 0...0> for
- * b < B and o < 2^n_open (Eq. (psi_x) with the deltas of the open qubits
- * left out), by the plan's elimination steps on the device.
+ * b < B and o < 2^n_open (the path sum of Eq. (fpath) written as the
+ * graphical model of Eq. (psi_x), with the deltas of the open qubits left out:
+ * the sets of amplitudes of Sec. III.A), by the plan's elimination steps on
+ * the device.
  *  gate_vals: device complex64 [n_slots][2][2]; may be NULL when n_slots = 0.
  *  bits:      device uint64 [B].
  *  out:       device complex64 or complex128 (opts.out_c128) [B][2^n_open].
@@ -249,7 +275,9 @@ qgm_status qgm_amplitudes_static(qgm_plan_t* plan, const void* gate_vals, const 
                                  void* out, void* stream);
 
 /* Device workspace (bytes) that qgm_backward needs for a batch of B bitstrings
- * (for ordering 1 sized by the same power-of-two row pitch). */
+ * (for ordering 1 sized by the same power-of-two row pitch): the forward
+ * frames it keeps (checkpoints, or every bucket result), their adjoints and
+ * the factor-adjoint partial sums. */
 qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint64_t* bytes);
 
 /* Gradient of a real loss with respect to the gate values (the gate
@@ -266,7 +294,9 @@ qgm_status qgm_backward_workspace_bytes(const qgm_plan_t* plan, int64_t B, uint6
  *              NULL when n_slots = 0.
  *  workspace:  at least qgm_backward_workspace_bytes(plan, B) bytes, 256-byte aligned.
  * With L = sum_x log |A_x|^2 (grad_amps = 2 / conj(A)) this is the gradient of
- * m times the cross-entropy estimator of App. B, Eq. (cee). */
+ * m times the cross-entropy estimator of App. B, Eq. (cee).  Ordering 1 keeps
+ * every bucket result instead of checkpoints and supports no open qubits, no
+ * slicing and no QGM_U2 gates (QGM_E_UNSUPPORTED). */
 qgm_status qgm_backward(qgm_plan_t* plan, const void* gate_vals, const uint64_t* bits, int64_t B,
                         const void* grad_amps, void* amps_out, void* gate_grads, void* workspace, uint64_t ws_bytes,
                         void* stream);

@@ -959,7 +959,7 @@ __global__ void __launch_bounds__(256) k_slice_cols(const uint64_t* __restrict__
     if (c >= (B << chunk_bits)) return;
     const int64_t b = c >> chunk_bits;
     const uint64_t j = uint64_t(c) & ((uint64_t(1) << chunk_bits) - 1);
-    cols[c] = bits[b] | ((slice0 + j) << n);
+    cols[c] = (bits[b] & ((uint64_t(1) << n) - 1)) | ((slice0 + j) << n);   // n < 64 when a plan slices
 }
 
 // Sum over the slices of one chunk, in slice order, in FP64: v = (first ? 0 :

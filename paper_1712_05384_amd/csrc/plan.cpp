@@ -826,7 +826,8 @@ static std::string tree_json(const Plan& p, int detail) {
         for (size_t j = 0; j < L.jobs.size(); ++j) {
             const LdsJob& jb = L.jobs[j];
             o << (j ? "," : "") << "{\"bucket\":" << L.job_bucket[j] << ",\"nin\":" << jb.nin << ",\"k\":" << jb.k
-              << ",\"lanes\":" << jb.lanes << ",\"out_row\":" << (jb.out_row - kLdsHeader) / 8 << ",\"in_w\":[";
+              << ",\"lanes\":" << jb.lanes << ",\"rows2\":" << jb.rows2 << ",\"out_row\":" << (jb.out_row - kLdsHeader) / 8
+              << ",\"in_w\":[";
             for (int k = 0; k < jb.nin; ++k) {
                 o << (k ? "," : "") << "[";
                 for (int w = 0; w < (1 << jb.k); ++w) o << (w ? "," : "") << jb.in_w[k][w] / 8;
@@ -843,6 +844,8 @@ static std::string tree_json(const Plan& p, int detail) {
                 for (int i = 0; i < 6; ++i) o << (i ? "," : "") << jb.str[sl < jb.nin ? sl : kLdsMaxIn][i] / 8;
                 o << "]";
             }
+            o << "],\"str6\":[";
+            for (int sl = 0; sl <= jb.nin; ++sl) o << (sl ? "," : "") << jb.str6[sl < jb.nin ? sl : kLdsMaxIn] / 8;
             o << "]}";
         }
         o << "],\"level_job_off\":[";

@@ -182,21 +182,29 @@ struct LdsEntry {
     uint32_t stage;
 };
 // Rows o0 + l of one bucket's result, l < 64 (fewer for a small result: lanes
-// beyond `lanes` compute a copy of a valid row and store nothing).  Lane l computes
+// beyond `lanes` compute a copy of a valid row and store nothing), and with
+// `rows2` also rows o0 + 64 + l.  Lane l computes
 //   R[o0 + l] = sum_w T[off_T(l) + tw[w]] * prod_t I_t[off_t(l) + in_w[t][w]]
 // with off_s(l) = base[s] + sum_{i < 6} (bit i of l) * str[s][i] for each input
-// s < nin and the table s = kLdsMaxIn.  Offsets are LDS bytes (< 64 KiB).
+// s < nin and the table s = kLdsMaxIn, and row o0 + 64 + l the same with
+// off_s(l) + str6[s].  Offsets are LDS bytes (< 64 KiB).
 struct LdsJob {
     int32_t nin, k, lanes, out_row;
     int32_t base[kLdsMaxIn + 1];
     int32_t tw[8];
     int32_t in_w[kLdsMaxIn][8];
     int32_t str[kLdsMaxIn + 1][6];
+    int32_t rows2;                       // 1: the job also computes the 64 rows after its first 64
+    int32_t str6[kLdsMaxIn + 1];
 };
 // The device form of a job: kLdsRecordHalves 16-bit fields, 16-byte aligned:
-// [0] nin | k << 3 | (lanes - 1) << 5, [1] out_row, [2..6] base, [8..15] tw,
-// [16..47] in_w[t][w] at 16 + 8 t + w, [48..77] str[s][i] at 48 + 6 s + i.
-constexpr int kLdsRecordHalves = 80;
+// [0] nin | k << 3 | (lanes - 1) << 5 | rows2 << 11, [1] out_row, [2..6] base,
+// [8..15] tw, [16..47] in_w[t][w] at 16 + 8 t + w, [48..77] str[s][i] at
+// 48 + 6 s + i, [80..84] str6[s].
+constexpr int kLdsRecordHalves = 88;
+// A job with at most this many loads per row issues them all before its first product (and may take two
+// rows per lane); a larger one interleaves loads and products to bound its registers.
+constexpr int kLdsBatchLoads = 12;
 constexpr int kLdsRecordBytes = 2 * kLdsRecordHalves;
 struct LdsProgram {
     bool ok = false;

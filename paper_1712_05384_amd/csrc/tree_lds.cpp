@@ -160,20 +160,25 @@ void build_lds_program(TreePlan& t) {
                 }
             }
             const int64_t n_rows = int64_t(1) << r;
-            for (int64_t o0 = 0; o0 < n_rows; o0 += 64) {
+            // a bucket of 128 rows or more whose job batches its loads takes 128 rows per job (two per
+            // lane): the rows share the record and the lane offsets, and their loads are independent
+            const bool two = r >= 7 && (nin + 1) * (1 << st.kg) <= kLdsBatchLoads;
+            for (int64_t o0 = 0; o0 < n_rows; o0 += two ? 128 : 64) {
                 LdsJob jb{};
                 jb.nin = nin;
                 jb.k = st.kg;
                 jb.lanes = int32_t(std::min<int64_t>(64, n_rows));
+                jb.rows2 = two ? 1 : 0;
                 jb.out_row = bytes(P.tensor_lds[st.out_tensor] + o0);
                 for (int k = 0; k <= nin; ++k) {
                     int64_t row = k < nin ? P.tensor_lds[st.in_tensors[size_t(k)]] : tab_lds[size_t(sid)];
                     if (row < 0) return fail("an input without LDS rows");
-                    for (int j = 6; j < r; ++j)
+                    for (int j = two ? 7 : 6; j < r; ++j)
                         if ((o0 >> j) & 1) row += ostr[size_t(k)][size_t(j)];
                     const int slot = k < nin ? k : kLdsMaxIn;
                     jb.base[slot] = bytes(row);
                     for (int j = 0; j < std::min(r, 6); ++j) jb.str[slot][j] = int32_t(8 * ostr[size_t(k)][size_t(j)]);
+                    if (two) jb.str6[slot] = int32_t(8 * ostr[size_t(k)][6]);
                 }
                 // the summed values: their offset in each input, and in the table (w << gb)
                 for (int w = 0; w < (1 << st.kg); ++w) {
@@ -201,13 +206,13 @@ void build_lds_program(TreePlan& t) {
     }
     // 8 waves when levels have many jobs (fewer bitstrings fit a compute unit, each finishes sooner), else 4
     const double mean_jobs = n_levels > 0 ? double(P.jobs.size()) / n_levels : 0.0;
-    P.threads = mean_jobs >= 10.0 || max_jobs >= 24 ? kLdsLargeThreads : kLdsSmallThreads;
+    P.threads = mean_jobs >= 5.0 || max_jobs >= 12 ? kLdsLargeThreads : kLdsSmallThreads;
     // the device records; kept in LDS after the tables when they fit (then a job reads nothing from memory)
     P.recs.assign(P.jobs.size() * size_t(kLdsRecordHalves), 0);
     for (size_t j = 0; j < P.jobs.size(); ++j) {
         const LdsJob& jb = P.jobs[j];
         uint16_t* rc = &P.recs[j * size_t(kLdsRecordHalves)];
-        rc[0] = uint16_t(jb.nin | (jb.k << 3) | ((jb.lanes - 1) << 5));
+        rc[0] = uint16_t(jb.nin | (jb.k << 3) | ((jb.lanes - 1) << 5) | (jb.rows2 << 11));
         rc[1] = uint16_t(jb.out_row);
         for (int s2 = 0; s2 <= kLdsMaxIn; ++s2) rc[2 + s2] = uint16_t(jb.base[s2]);
         for (int w = 0; w < 8; ++w) rc[8 + w] = uint16_t(jb.tw[w]);
@@ -215,16 +220,15 @@ void build_lds_program(TreePlan& t) {
             for (int w = 0; w < 8; ++w) rc[16 + 8 * k + w] = uint16_t(jb.in_w[k][w]);
         for (int s2 = 0; s2 <= kLdsMaxIn; ++s2)
             for (int i = 0; i < 6; ++i) rc[48 + 6 * s2 + i] = uint16_t(jb.str[s2][i]);
+        for (int s2 = 0; s2 <= kLdsMaxIn; ++s2) rc[80 + s2] = uint16_t(jb.str6[s2]);
     }
-    // records in LDS only when that costs no resident work-group per compute unit (160 KiB of LDS each):
-    // more bitstrings in flight outweigh the scalar loads of the records at large batches
+    // records in LDS whenever they fit: a job then reads its record with one LDS round trip instead of a
+    // memory one (measured faster at every batch on 5x5 depth 25, although fewer work-groups fit a CU)
     const int64_t rec_entries = int64_t(P.jobs.size()) * (kLdsRecordBytes / 8);
-    auto per_cu = [&](int64_t entries) {   // work-groups per compute unit by LDS, and by its 32 wave slots
-        return std::min<int64_t>((160 * 1024) / (kLdsHeader + 8 * entries), 32 / (P.threads / 64));
-    };
-    if (P.lds_size + rec_entries <= kLdsMaxComplex && per_cu(P.lds_size + rec_entries) >= per_cu(P.lds_size)) {
-        P.recs0 = P.lds_size;
-        P.lds_size += int32_t(rec_entries);
+    const int32_t recs0 = (P.lds_size + 1) & ~1;   // 16-byte aligned (the header is 16-byte aligned)
+    if (recs0 + rec_entries <= kLdsMaxComplex) {
+        P.recs0 = recs0;
+        P.lds_size = recs0 + int32_t(rec_entries);
     }
     P.ok = true;
     t.lds = std::move(P);
@@ -233,7 +237,8 @@ void build_lds_program(TreePlan& t) {
 int64_t lds_bytes_per_amp(const LdsProgram& P) {
     if (!P.ok) return 0;
     int64_t b = int64_t(P.entries.size()) * 8;
-    for (const LdsJob& j : P.jobs) b += int64_t(j.lanes) * (((int64_t(1) << j.k) * (j.nin + 1) + 1) * 8);
+    for (const LdsJob& j : P.jobs)
+        b += int64_t(j.lanes) * (1 + j.rows2) * (((int64_t(1) << j.k) * (j.nin + 1) + 1) * 8);
     return b;
 }
 

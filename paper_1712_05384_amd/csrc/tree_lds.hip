@@ -9,8 +9,10 @@
 // summed value w by its input rows, sums over w, and stores the row; a block
 // barrier separates levels, as a level reads only results of earlier levels.
 // A job record holds the LDS byte offsets at its first row and the strides of
-// the six lane bits; the records are copied to LDS with the tables when they
-// fit, so after the first burst of loads the levels touch no memory.
+// the six lane bits (a bucket of 128 rows or more takes two rows per lane,
+// the second at a seventh stride); the records are copied to LDS with the
+// tables when they fit, so after the first burst of loads the levels touch no
+// memory.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -21,8 +23,6 @@ namespace qgm {
 using namespace tree_dev;
 
 namespace {
-
-constexpr int kLdsBatchLoads = 12;
 
 // 16 bytes of a job record (LDS or memory; the address is wave-uniform).
 __device__ __forceinline__ uint4 rec16(const char* __restrict__ rp, int byte) {
@@ -52,8 +52,10 @@ __device__ __forceinline__ uint32_t lane_off(const char* __restrict__ rp, int s,
 }
 
 // One job: rows out_row + lane of its bucket's result (lanes < the record's
-// count); h is the record's first 16 bytes, rp the record, L the work-group's LDS.
-template <int NIN, int K>
+// count) and, with M = 2, rows out_row + 64 + lane too (slot offsets + the
+// record's str6); h is the record's first 16 bytes, rp the record, L the
+// work-group's LDS.
+template <int NIN, int K, int M>
 __device__ __forceinline__ void lds_job(uint4 h, uint32_t lanes, const char* __restrict__ rp, char* __restrict__ L,
                                         const uint32_t (&lb)[6], uint32_t lane) {
     constexpr int W = 1 << K;
@@ -62,57 +64,83 @@ __device__ __forceinline__ void lds_job(uint4 h, uint32_t lanes, const char* __r
     uint4 iw[NR];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) iw[t] = rec16(rp, 32 + 16 * t);
-    uint32_t row[NR];
+    uint32_t row[M][NR], tb[M];
 #pragma unroll
-    for (int t = 0; t < NIN; ++t) row[t] = lane_off(rp, t, half(h, 2 + t), lb);
-    const uint32_t tb = lane_off(rp, kLdsMaxIn, half(h, 2 + kLdsMaxIn), lb);
-    float2 q[W], v[NR][W];
+    for (int t = 0; t < NIN; ++t) row[0][t] = lane_off(rp, t, half(h, 2 + t), lb);
+    tb[0] = lane_off(rp, kLdsMaxIn, half(h, 2 + kLdsMaxIn), lb);
+    if constexpr (M == 2) {
+        const uint4 s6 = rec16(rp, 160);
 #pragma unroll
-    for (int w = 0; w < W; ++w) q[w] = *reinterpret_cast<const float2*>(L + tb + half(tw, w));
+        for (int t = 0; t < NIN; ++t) row[1][t] = row[0][t] + half(s6, t);
+        tb[1] = tb[0] + half(s6, kLdsMaxIn);
+    }
+    float2 q[M][W], v[M][NR][W];
 #pragma unroll
-    for (int t = 0; t < NIN; ++t)
+    for (int m = 0; m < M; ++m) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) v[t][w] = *reinterpret_cast<const float2*>(L + row[t] + half(iw[t], w));
-    // every load of a job with at most kLdsBatchLoads loads is issued before the first product: the
-    // values pass through empty asm statements, so the compiler cannot interleave the loads with the
-    // arithmetic (one LDS round trip per job instead of one per summed value; larger jobs would hold
-    // more registers than the occupancy allows)
-    if constexpr ((NIN + 1) * W <= kLdsBatchLoads) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) asm volatile("" : "+v"(q[w].x), "+v"(q[w].y));
+        for (int w = 0; w < W; ++w) q[m][w] = *reinterpret_cast<const float2*>(L + tb[m] + half(tw, w));
 #pragma unroll
         for (int t = 0; t < NIN; ++t)
 #pragma unroll
-            for (int w = 0; w < W; ++w) asm volatile("" : "+v"(v[t][w].x), "+v"(v[t][w].y));
+            for (int w = 0; w < W; ++w) v[m][t][w] = *reinterpret_cast<const float2*>(L + row[m][t] + half(iw[t], w));
     }
-    float2 acc = make_float2(0.f, 0.f);
+    // every load of a job with at most kLdsBatchLoads loads per row is issued before the first product:
+    // the values pass through empty asm statements, so the compiler cannot interleave the loads with the
+    // arithmetic (one LDS round trip per job instead of one per summed value; larger jobs would hold more
+    // registers than the occupancy allows)
+    if constexpr ((NIN + 1) * W <= kLdsBatchLoads) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        if constexpr (NIN == 0) {
-            acc.x += q[w].x;
-            acc.y += q[w].y;
-        } else {
-            float2 pw = q[w];
+        for (int m = 0; m < M; ++m) {
 #pragma unroll
-            for (int t = 0; t + 1 < NIN; ++t) pw = cmulf(pw, v[t][w]);
-            const float2 l = v[NIN - 1][w];   // the last factor goes into the sum as fused multiply-adds
-            acc.x = fmaf(pw.x, l.x, acc.x);
-            acc.x = fmaf(-pw.y, l.y, acc.x);
-            acc.y = fmaf(pw.x, l.y, acc.y);
-            acc.y = fmaf(pw.y, l.x, acc.y);
+            for (int w = 0; w < W; ++w) asm volatile("" : "+v"(q[m][w].x), "+v"(q[m][w].y));
+#pragma unroll
+            for (int t = 0; t < NIN; ++t)
+#pragma unroll
+                for (int w = 0; w < W; ++w) asm volatile("" : "+v"(v[m][t][w].x), "+v"(v[m][t][w].y));
         }
     }
-    if (lane < lanes) *reinterpret_cast<float2*>(L + (h.x >> 16) + 8 * lane) = acc;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if constexpr (NIN == 0) {
+                acc.x += q[m][w].x;
+                acc.y += q[m][w].y;
+            } else {
+                float2 pw = q[m][w];
+#pragma unroll
+                for (int t = 0; t + 1 < NIN; ++t) pw = cmulf(pw, v[m][t][w]);
+                const float2 l = v[m][NIN - 1][w];   // the last factor goes into the sum as fused multiply-adds
+                acc.x = fmaf(pw.x, l.x, acc.x);
+                acc.x = fmaf(-pw.y, l.y, acc.x);
+                acc.y = fmaf(pw.x, l.y, acc.y);
+                acc.y = fmaf(pw.y, l.x, acc.y);
+            }
+        }
+        if (lane < lanes) *reinterpret_cast<float2*>(L + (h.x >> 16) + 512 * m + 8 * lane) = acc;
+    }
 }
 
 template <int NIN>
-__device__ __forceinline__ void lds_job_k(int k, uint4 h, uint32_t lanes, const char* __restrict__ rp,
+__device__ __forceinline__ void lds_job_k(int k, bool two, uint4 h, uint32_t lanes, const char* __restrict__ rp,
                                           char* __restrict__ L, const uint32_t (&lb)[6], uint32_t lane) {
+    // two rows per lane only where a row's loads are batched (the planner's rule)
+    constexpr bool T1 = (NIN + 1) * 2 <= kLdsBatchLoads, T2 = (NIN + 1) * 4 <= kLdsBatchLoads;
     switch (k) {
-        case 0: lds_job<NIN, 0>(h, lanes, rp, L, lb, lane); break;
-        case 1: lds_job<NIN, 1>(h, lanes, rp, L, lb, lane); break;
-        case 2: lds_job<NIN, 2>(h, lanes, rp, L, lb, lane); break;
-        default: lds_job<NIN, 3>(h, lanes, rp, L, lb, lane); break;
+        case 0:
+            if (two) lds_job<NIN, 0, 2>(h, lanes, rp, L, lb, lane);
+            else lds_job<NIN, 0, 1>(h, lanes, rp, L, lb, lane);
+            break;
+        case 1:
+            if (T1 && two) lds_job<NIN, 1, T1 ? 2 : 1>(h, lanes, rp, L, lb, lane);
+            else lds_job<NIN, 1, 1>(h, lanes, rp, L, lb, lane);
+            break;
+        case 2:
+            if (T2 && two) lds_job<NIN, 2, T2 ? 2 : 1>(h, lanes, rp, L, lb, lane);
+            else lds_job<NIN, 2, 1>(h, lanes, rp, L, lb, lane);
+            break;
+        default: lds_job<NIN, 3, 1>(h, lanes, rp, L, lb, lane); break;
     }
 }
 
@@ -245,12 +273,13 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
             const uint32_t hd = __builtin_amdgcn_readfirstlane(h.x & 0xFFFFu);
             const uint32_t lanes = ((hd >> 5) & 63u) + 1u;
             const int k = int((hd >> 3) & 3u);
+            const bool two = (hd >> 11) & 1u;
             switch (hd & 7u) {
-                case 0: lds_job_k<0>(k, h, lanes, rp, L, lb, lane); break;
-                case 1: lds_job_k<1>(k, h, lanes, rp, L, lb, lane); break;
-                case 2: lds_job_k<2>(k, h, lanes, rp, L, lb, lane); break;
-                case 3: lds_job_k<3>(k, h, lanes, rp, L, lb, lane); break;
-                default: lds_job_k<4>(k, h, lanes, rp, L, lb, lane); break;
+                case 0: lds_job_k<0>(k, two, h, lanes, rp, L, lb, lane); break;
+                case 1: lds_job_k<1>(k, two, h, lanes, rp, L, lb, lane); break;
+                case 2: lds_job_k<2>(k, two, h, lanes, rp, L, lb, lane); break;
+                case 3: lds_job_k<3>(k, two, h, lanes, rp, L, lb, lane); break;
+                default: lds_job_k<4>(k, two, h, lanes, rp, L, lb, lane); break;
             }
         }
         // the phase product on the last wave during the last level (it usually has no job there)

@@ -3,8 +3,9 @@ with tree_exec 3), complex128.
 
 It executes the program the planner exports (plan JSON detail 2, "lds"): the
 table slices copied at a bitstring's output bits, then level by level the jobs
--- 64 result rows of one bucket, lane l reading its inputs and the factor-table
-slice at the job's base offsets plus the strides of its six lane bits plus the
+-- 64 result rows of one bucket (128 for a two-row job, the second 64 at a
+seventh stride), lane l reading its inputs and the factor-table slice at the
+job's base offsets plus the strides of its six lane bits plus the
 per-summed-value offsets --
 and finally phase x the rank-0 results.  Every LDS entry read must have been
 written (entries start as NaN) and stay inside the program's LDS size, and
@@ -71,10 +72,11 @@ def _run_column(info, L, area, stage_q, size, x, gate_vals):
         for j in range(offs[lv], offs[lv + 1]):
             jb = L["jobs"][j]
             nin, k, lanes = jb["nin"], jb["k"], jb["lanes"]
-            for lane in range(64):
+            for lane in range(64 * (1 + jb["rows2"])):
                 # the lane's offsets: the job's base plus the strides of the lane's six bits (inputs, then
-                # the table)
-                off = [jb["base"][sl] + sum(((lane >> i) & 1) * jb["str"][sl][i] for i in range(6))
+                # the table); a two-row job's second row adds its seventh stride
+                m, ln = lane >> 6, lane & 63
+                off = [jb["base"][sl] + sum(((ln >> i) & 1) * jb["str"][sl][i] for i in range(6)) + m * jb["str6"][sl]
                        for sl in range(nin + 1)]
                 acc = 0j
                 for w in range(1 << k):
@@ -88,7 +90,7 @@ def _run_column(info, L, area, stage_q, size, x, gate_vals):
                         reads.add(a)
                         v = v * lds[a]
                     acc += v
-                if lane < lanes:
+                if ln < lanes:
                     dst = jb["out_row"] + lane
                     assert 0 <= dst < L["tables0"], (j, lane, dst)
                     assert not np.isnan(acc), (lv, j, lane)

@@ -60,7 +60,8 @@ struct qgm_plan_s {
     size_t off_tpart = 0;
     size_t off_status = 0;           // int32 failure record of persistent launches (0: none since the last check)
     // the LDS-resident program (tree plans whose results fit a work-group's LDS)
-    size_t off_lstage = 0, off_lentry = 0, off_lrec = 0, off_llvl = 0, off_lfin = 0;
+    size_t off_lstage = 0, off_lentry = 0, off_lrec = 0, off_llvl = 0, off_lfin = 0, off_lzent = 0, off_lz = 0;
+    size_t off_lgent = 0;
     // optional per-phase timing
     bool timing = false;
     std::vector<hipEvent_t> events;   // 5 per timed call
@@ -288,7 +289,11 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->off_lrec = P->off_lentry + al(sizeof(qgm::LdsEntry) * (lp.entries.size() + 1));
     P->off_llvl = P->off_lrec + al(sizeof(uint16_t) * (lp.recs.size() + 8));
     P->off_lfin = P->off_llvl + al(sizeof(int32_t) * (lp.level_job_off.size() + 1));
-    P->total = P->off_lfin + al(sizeof(int32_t) * (lp.finals.size() + 1));
+    P->off_lzent = P->off_lfin + al(sizeof(int32_t) * (lp.finals.size() + 1));
+    P->off_lgent = P->off_lzent + al(sizeof(uint32_t) * (lp.zent.size() + 1));
+    P->off_lz = P->off_lgent + al(sizeof(uint32_t) * (lp.gent.size() + 1));
+    // the staged copy of the LDS launch's tables: built once here when the circuit reads no gate values
+    P->total = P->off_lz + (P->p.n_slots == 0 ? al(sizeof(float2) * size_t(lp.z_entries + 1)) : 0);
 }
 
 // Adjoint tables: the forward tasks with every result at its own rows
@@ -532,6 +537,8 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
         std::memcpy(h + P->off_lrec, lp.recs.data(), sizeof(uint16_t) * lp.recs.size());
         std::memcpy(h + P->off_llvl, lp.level_job_off.data(), sizeof(int32_t) * lp.level_job_off.size());
         std::memcpy(h + P->off_lfin, lp.finals.data(), sizeof(int32_t) * lp.finals.size());
+        std::memcpy(h + P->off_lzent, lp.zent.data(), sizeof(uint32_t) * lp.zent.size());
+        std::memcpy(h + P->off_lgent, lp.gent.data(), sizeof(uint32_t) * lp.gent.size());
     }
     auto* fd = reinterpret_cast<int32_t*>(h + P->off_tfdep);
     for (size_t i = 0; i < t.finals.size(); ++i) {
@@ -620,6 +627,13 @@ void fill_step_tables(const qgm_plan_t* P, char* h) {
     std::memcpy(h + P->off_slot_ops, P->slot_ops.data(), sizeof(int32_t) * P->slot_ops.size());
 }
 
+// The largest staged block (entries x sigma values) of an LDS program.
+int64_t lds_stage_max(const qgm::LdsProgram& lp) {
+    int64_t m = 0;
+    for (const qgm::LdsStage& sg : lp.stages) m = std::max<int64_t>(m, int64_t(sg.n) << sg.n_sig);
+    return m;
+}
+
 // Returns the device copy of the plan's constant tables for the current
 // device, uploading it on first use.
 qgm_status device_tables(qgm_plan_t* P, char** base) {
@@ -659,6 +673,12 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
         qgm::launch_tree_leaf_tables(reinterpret_cast<const qgm::TreeLeaf*>(b + P->off_tleaf),
                                      P->p.tree.n_table_leaves, max_entries, reinterpret_cast<float2*>(b + P->off_tg),
                                      nullptr);
+        const qgm::LdsProgram& lp = P->p.tree.lds;
+        if (lp.ok)
+            qgm::launch_lds_stage(reinterpret_cast<const qgm::LdsStage*>(b + P->off_lstage), int(lp.stages.size()),
+                                  reinterpret_cast<const qgm::LdsEntry*>(b + P->off_lentry),
+                                  reinterpret_cast<const float2*>(b + P->off_tg), reinterpret_cast<float2*>(b + P->off_lz),
+                                  lds_stage_max(lp), nullptr);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "building the plan's factor tables"); }
@@ -924,7 +944,11 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
                 const qgm::LdsProgram& lp = t.lds;
                 qgm::LdsArgs a{};
                 a.stages = reinterpret_cast<const qgm::LdsStage*>(tables + plan->off_lstage);
-                a.entries = reinterpret_cast<const qgm::LdsEntry*>(tables + plan->off_lentry);
+                // a circuit without gate values reads the plan's staged copy (a slice is one contiguous
+                // read); one with gate values gathers from this call's tables (no staging launch per call)
+                a.staged = p.n_slots == 0 ? 1 : 0;
+                a.zent = reinterpret_cast<const uint32_t*>(tables + (a.staged ? plan->off_lzent : plan->off_lgent));
+                a.ztab = a.staged ? reinterpret_cast<const float2*>(tables + plan->off_lz) : gt;
                 a.recs = reinterpret_cast<const uint16_t*>(tables + plan->off_lrec);
                 a.phq = reinterpret_cast<const int32_t*>(tables + plan->off_tphq);
                 a.pv = reinterpret_cast<const double2*>(gt + t.phase_g);

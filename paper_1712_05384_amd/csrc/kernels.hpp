@@ -272,7 +272,9 @@ void launch_tree_tail(const TreeTailArgs& a, hipStream_t stream);
 // entries of dynamic LDS.
 struct LdsArgs {
     const LdsStage* stages;
-    const LdsEntry* entries;
+    const uint32_t* zent;                       // per table entry: its index in ztab | stage << 24
+    const float2* ztab;                         // the staged copy of the tables (LdsStage), or (staged = 0)
+                                                //   the table area itself
     const uint16_t* recs;                       // [job][kLdsRecordHalves]
     const int32_t* level_job_off;               // n_levels + 1
     const int32_t* finals;                      // LDS byte offsets of the rank-0 results
@@ -288,9 +290,13 @@ struct LdsArgs {
     int64_t B;
     int32_t n_stages, n_entries, tables0, lds_size;
     int32_t n_levels, n_final, n_phase, c128;
-    int32_t threads, n_jobs, recs0, pad;
+    int32_t threads, n_jobs, recs0, staged;
 };
 void launch_tree_lds(const LdsArgs& a, hipStream_t stream);
+// The staged copy of the tables for the LDS launch: for every stage, every sigma and every entry i of the
+// stage, z[zoff + sigma * n + i] = gtab[entries[e0 + i].src + sigma]; max_m = the largest n << n_sig.
+void launch_lds_stage(const LdsStage* stages, int n_stages, const LdsEntry* entries, const float2* gtab, float2* z,
+                      int64_t max_m, hipStream_t stream);
 void launch_tb_seed(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase, const double2* fixed,
                     const float2* slots, const float2* arena, float2* adj, const uint64_t* bits, int64_t B,
                     uint32_t B_eff, const float2* grad_amps, void* amps_out, bool c128, double2* phibar,

@@ -817,11 +817,11 @@ static std::string tree_json(const Plan& p, int detail) {
         for (size_t i = 0; i < L.stages.size(); ++i) {
             o << (i ? "," : "") << "{\"bucket\":" << L.stage_bucket[i] << ",\"sig_q\":[";
             for (int b = 0; b < L.stages[i].n_sig; ++b) o << (b ? "," : "") << L.stages[i].sig_q[b];
-            o << "]}";
+            o << "],\"n\":" << L.stages[i].n << ",\"zoff\":" << L.stages[i].zoff << ",\"e0\":" << L.stages[i].e0 << "}";
         }
-        o << "],\"entries\":[";
+        o << "],\"z_entries\":" << L.z_entries << ",\"entries\":[";
         for (size_t i = 0; i < L.entries.size(); ++i)
-            o << (i ? "," : "") << "[" << L.entries[i].src << "," << L.entries[i].stage << "]";
+            o << (i ? "," : "") << "[" << L.entries[i].src << "," << L.entries[i].stage << "," << (L.zent[i] & 0xFFFFFFu) << "]";
         o << "],\"jobs\":[";
         for (size_t j = 0; j < L.jobs.size(); ++j) {
             const LdsJob& jb = L.jobs[j];

@@ -171,9 +171,12 @@ constexpr int kLdsHeader = 4 * kLdsMaxStages + 16;   // LDS bytes before the dat
 constexpr int kLdsSmallThreads = 256, kLdsLargeThreads = 512;   // work-group sizes (4 or 8 waves)
 
 // A factor-table or leaf-table slice: the table entries src + sigma of its
-// LdsEntry records, sigma bit i = bit sig_q[i] of the bitstring.
+// LdsEntry records, sigma bit i = bit sig_q[i] of the bitstring.  Its n
+// entries are entries [e0, e0 + n) (n a power of two); the staged copy of the
+// table area holds, for every sigma, the slice contiguously:
+// staged[zoff + sigma * n + i] = area[entries[e0 + i].src + sigma].
 struct LdsStage {
-    int32_t n_sig, pad0, pad1, pad2;
+    int32_t n_sig, n, zoff, e0;
     int32_t sig_q[kTreeMaxSig];
 };
 // lds[tables0 + e] = table area[src + sigma of stage `stage`]
@@ -216,6 +219,10 @@ struct LdsProgram {
     std::vector<LdsStage> stages;
     std::vector<int32_t> stage_bucket;   // bucket of each stage
     std::vector<LdsEntry> entries;
+    std::vector<uint32_t> zent;          // per entry: its staged index zoff + i, and its stage << 24
+    std::vector<uint32_t> gent;          // per entry: its table-area index src, and its stage << 24 (for a
+                                         //   circuit with gate values, whose tables change per call)
+    int64_t z_entries = 0;               // size of the staged copy
     std::vector<LdsJob> jobs;
     std::vector<int32_t> job_bucket;
     std::vector<uint16_t> recs;          // [job][kLdsRecordHalves]

@@ -117,6 +117,11 @@ void build_lds_program(TreePlan& t) {
         if (int(P.stages.size()) >= kLdsMaxStages) return fail("more than 256 tables");
         LdsStage sg{};
         sg.n_sig = st.sb();
+        sg.n = int32_t(n);
+        sg.e0 = int32_t(e);
+        sg.zoff = int32_t(P.z_entries);
+        P.z_entries += n << st.sb();
+        if (P.z_entries >= (int64_t(1) << 24)) return fail("staged tables exceed 2^24 entries");
         for (int b = 0; b < st.sb(); ++b) sg.sig_q[b] = st.sig_q[size_t(b)];
         const uint32_t s = uint32_t(P.stages.size());
         P.stages.push_back(sg);
@@ -139,6 +144,13 @@ void build_lds_program(TreePlan& t) {
     }
     P.lds_size = int32_t(P.tables0 + e);
     if (P.lds_size > kLdsMaxComplex) return fail("LDS of a work-group exceeded");
+    // the device's entry list: the staged index of each entry and its stage (a slice is one contiguous read)
+    for (size_t i = 0; i < P.entries.size(); ++i) {
+        const LdsStage& sg = P.stages[P.entries[i].stage];
+        P.zent.push_back(uint32_t(sg.zoff + (int64_t(i) - sg.e0)) | (P.entries[i].stage << 24));
+        if (P.entries[i].src >= (1u << 24)) return fail("a table entry beyond 2^24");
+        P.gent.push_back(P.entries[i].src | (P.entries[i].stage << 24));
+    }
     auto bytes = [](int64_t entry) { return int32_t(kLdsHeader + 8 * entry); };
     // jobs, level by level
     P.level_job_off.assign(1, 0);

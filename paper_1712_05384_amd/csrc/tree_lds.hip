@@ -15,6 +15,8 @@
 // memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "tree_dev.hpp"
 
@@ -201,9 +203,9 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
     // arrays are never empty), so no load is conditional.
     constexpr int R = 4;
     const int n_e = a.n_entries;
-    LdsEntry en[R];
+    uint32_t en[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) en[i] = a.entries[min(i * NT + int(tid), max(n_e - 1, 0))];
+    for (int i = 0; i < R; ++i) en[i] = a.zent[min(i * NT + int(tid), max(n_e - 1, 0))];
     const int n_rw = RL ? a.n_jobs * (kLdsRecordBytes / 16) : 0;
     const uint4* __restrict__ rsrc = reinterpret_cast<const uint4*>(a.recs);
     uint4* rdst = reinterpret_cast<uint4*>(L + kLdsHeader + 8 * a.recs0);
@@ -229,29 +231,30 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
 #pragma unroll
         for (int i = 0; i < 12; ++i)
             if (i < sh0.x) g |= uint32_t((x >> q[i]) & 1ull) << i;
-        sig[tid] = g;
+        sig[tid] = a.staged ? g * uint32_t(sh0.y) : g;   // the slice's offset in its staged block, or sigma
     }
     for (int s2 = int(tid) + NT; s2 < a.n_stages; s2 += NT) {   // more stages than threads
         const LdsStage& st = a.stages[s2];
-        sig[s2] = gather_sigma(x, st.sig_q, st.n_sig);
+        sig[s2] = gather_sigma(x, st.sig_q, st.n_sig) * (a.staged ? uint32_t(st.n) : 1u);
     }
 #pragma unroll
     for (int i = 0; i < R; ++i)
         if (i * NT + int(tid) < n_rw) rdst[i * NT + int(tid)] = rw[i];
     for (int i = R * NT + int(tid); i < n_rw; i += NT) rdst[i] = rsrc[i];   // more record words than one round
     __syncthreads();
-    // the table slices: R entries per thread per round, every load issued before any store
+    // the table slices from the staged copy (consecutive entries of a slice are consecutive there): R entries
+    // per thread per round, every load issued before any store
     for (int e0 = 0; e0 < n_e;) {
         uint32_t sg[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) sg[i] = sig[en[i].stage];
+        for (int i = 0; i < R; ++i) sg[i] = sig[en[i] >> 24];
         float2 v[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = a.gtab[int64_t(en[i].src) + sg[i]];
+        for (int i = 0; i < R; ++i) v[i] = a.ztab[int64_t(en[i] & 0xFFFFFFu) + sg[i]];
         const int e1 = e0 + R * NT;
         if (e1 < n_e) {
 #pragma unroll
-            for (int i = 0; i < R; ++i) en[i] = a.entries[min(e1 + i * NT + int(tid), n_e - 1)];
+            for (int i = 0; i < R; ++i) en[i] = a.zent[min(e1 + i * NT + int(tid), n_e - 1)];
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -299,6 +302,25 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
         if (a.c128) static_cast<double2*>(a.out)[b] = acc;
         else static_cast<float2*>(a.out)[b] = make_float2(float(acc.x), float(acc.y));
     }
+}
+
+__global__ void __launch_bounds__(256) k_lds_stage(const LdsStage* __restrict__ stages,
+                                                   const LdsEntry* __restrict__ entries,
+                                                   const float2* __restrict__ gtab, float2* __restrict__ z) {
+    const LdsStage st = stages[blockIdx.y];
+    const int64_t m = int64_t(st.n) << st.n_sig;
+    const int lg = __ffs(st.n) - 1;   // n is a power of two
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < m; idx += int64_t(gridDim.x) * 256) {
+        const int64_t sg = idx >> lg, i = idx & (st.n - 1);
+        z[st.zoff + idx] = gtab[int64_t(entries[st.e0 + i].src) + sg];
+    }
+}
+
+void launch_lds_stage(const LdsStage* stages, int n_stages, const LdsEntry* entries, const float2* gtab, float2* z,
+                      int64_t max_m, hipStream_t stream) {
+    if (n_stages <= 0 || max_m <= 0) return;
+    const uint32_t gx = uint32_t(std::min<int64_t>((max_m + 255) / 256, 64));
+    hipLaunchKernelGGL(k_lds_stage, dim3(gx, uint32_t(n_stages)), dim3(256), 0, stream, stages, entries, gtab, z);
 }
 
 void launch_tree_lds(const LdsArgs& a, hipStream_t stream) {

@@ -62,10 +62,17 @@ def _run_column(info, L, area, stage_q, size, x, gate_vals):
     """One batch column (bitstring word x, slice bits above the qubits) through the LDS program."""
     lds = np.full(size, np.nan, dtype=np.complex128)
     sig = [sum(((x >> q) & 1) << i for i, q in enumerate(sq)) for sq in stage_q]
-    for e, (src, s) in enumerate(L["entries"]):
+    stages = L["stages"]
+    for e, (src, s, zsrc) in enumerate(L["entries"]):
         dst = L["tables0"] + e
         assert 0 <= dst < size
-        lds[dst] = area[src + sig[s]]
+        # the device reads the staged copy: staged[zoff + sigma * n + i] = area[src of entry e0 + i + sigma]
+        st = stages[s]
+        i = e - st["e0"]
+        assert 0 <= i < st["n"] and zsrc == st["zoff"] + i
+        assert st["zoff"] + sig[s] * st["n"] + i < L["z_entries"]
+        lds[dst] = area[L["entries"][st["e0"] + i][0] + sig[s]]
+        assert L["entries"][st["e0"] + i][0] == src
     offs = L["level_job_off"]
     for lv in range(len(offs) - 1):
         writes, reads = {}, set()

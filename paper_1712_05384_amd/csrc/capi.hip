@@ -435,6 +435,14 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
                 if (sj != 0) base.in_omask[k] |= 1 << j;
             }
         }
+        if (st.tile >= 3) {   // the 32-row tile: row strides of A's unit bits 0, 1, 3 and of B's 2, 4
+            const int abit[3] = {0, 1, 3}, bbit[2] = {2, 4};
+            for (int j = 0; j < 3; ++j) base.in_inc[0][j] = int32_t(str[0][abit[j]]);
+            for (int j = 0; j < 2; ++j) base.in_inc[1][j] = int32_t(str[1][bbit[j]]);
+            base.in_inc[1][2] = 0;
+            if (n_in > 2)
+                for (int j = 0; j < qgm::kTreeOcBits; ++j) base.in_inc[2][j] = 0;
+        }
         for (int j = 0; j < r; ++j)
             for (int gi = 0; gi < st.gb(); ++gi)
                 if (st.out_axes[j] == st.gvars[gi]) gstr[j] = int64_t(1) << gi;

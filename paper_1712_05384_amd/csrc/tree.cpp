@@ -463,7 +463,17 @@ static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
         for (int b = 0; b < n; ++b)
             if (a != b && only[a].size() >= 2 && !only[b].empty()) { ka = a; kb = b; break; }
     if (ka < 0) return 0;
+    // the 32-row tile when A has three bits alone and B two: unit bits a0 a1 b0 a2 b1 (bits 0-2 also make the
+    // 8-row tile, which a level whose launch cannot hold the large unit falls back to)
+    int big = 0;
+    for (int a = 0; a < n && !big; ++a)
+        for (int b = 0; b < n; ++b)
+            if (a != b && only[a].size() >= 3 && only[b].size() >= 2) { ka = a; kb = b; big = 2; break; }
     order = {only[ka][0], only[ka][1], only[kb][0]};
+    if (big) {
+        order.push_back(only[ka][2]);
+        order.push_back(only[kb][1]);
+    }
     ins = {st.ins[ka], st.ins[kb]};
     for (int k = 0; k < n; ++k)
         if (k != ka && k != kb) ins.push_back(st.ins[k]);
@@ -479,7 +489,7 @@ static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
     for (size_t c = 0; c < idx.size(); ++c) idx[c] = c;
     std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return lack[x] > lack[y]; });
     for (size_t c : idx) order.push_back(rest[c]);
-    return n - 1;
+    return n - 1 + big;
 }
 
 static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector<int>& order,
@@ -917,7 +927,10 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
         const int nin = launch_inputs(mi);
         for (int sid : t.levels[L]) {
             TreeStep& st = t.steps[sid];
-            st.unit_rows = st.tile ? (1 << kTreeOcBits) : tree_unit_rows(nin, st.kg);
+            // the 32-row tile runs in the 2- and 3-input launches of levels that are not the tail's (it holds
+            // 64 accumulator registers, more than the wider launches leave); elsewhere its 8-row form
+            if (st.tile >= 3 && (nin > 3 || st.out_axes.size() < 10)) st.tile -= 2;
+            st.unit_rows = st.tile >= 3 ? 32 : (st.tile ? (1 << kTreeOcBits) : tree_unit_rows(nin, st.kg));
             st.task_off = t.n_tasks;
             t.n_tasks += st.n_tasks();
         }
@@ -937,10 +950,13 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
         const int64_t nt = t.level_task_off[L + 1] - t.level_task_off[L];
         if (nt > kTreeTailTasks || launch_inputs(t.level_max_in[L]) > kTreeTailInputs) break;
         int64_t rows = 0, ge = 0;
+        bool big_tile = false;   // the tail kernel has no 32-row tile unit
         for (int sid : t.levels[L]) {
             rows += alloc_rows(t.steps[sid].out_tensor);
             ge += t.steps[sid].g_entries();
+            big_tile = big_tile || t.steps[sid].tile >= 3;
         }
+        if (big_tile) break;
         if (tail_tasks + nt > kTreeTailMaxTasks || tail_rows + rows > kTreeTailLdsRows ||
             tail_g + ge > kTreeTailGEntries)
             break;
@@ -1028,6 +1044,8 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
 // unit's result rows.
 int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st) {
     if (st.table_leaf) return 0;
+    if (st.tile >= 3)   // 8 + 4 (+ 1) input rows and a table row per summed value
+        return (int64_t(8 + 4 + 1 + (st.tile == 4 ? 1 : 0)) << st.kg) + st.unit_rows;
     if (st.tile)   // 4 + 2 (+ 1) input rows and a table row per summed value
         return (int64_t(4 + 2 + 1 + (st.tile == 2 ? 1 : 0)) << st.kg) + st.unit_rows;
     const int ob_bits = __builtin_ctz(uint32_t(st.unit_rows));

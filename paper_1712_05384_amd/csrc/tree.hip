@@ -351,6 +351,79 @@ __device__ __forceinline__ void tile_unit(const TreeTask& tk, const float2* __re
     for (int o = 0; o < 8; ++o) out[int64_t(o) * be] = acc[o];
 }
 
+// A large tile unit (tile 3: two inputs; 4: a third input C): 32 result rows,
+// unit bits 0, 1, 3 varying input A only (8 rows of A) and bits 2, 4 input B
+// only (4 rows of B), none of them input C or the factor table.  The summed
+// values are streamed: per value w one table entry, 8 rows of A, 4 of B (and
+// 1 of C) are loaded and the 32 results accumulated, so each loaded row serves
+// 4 or 8 results (the 8-row tile loads 7 rows per 8 result rows and value,
+// this one 13 per 32).  The task's in_inc[0][0..2] and in_inc[1][0..1] hold
+// the row strides of those bits in A and B.
+template <int K, bool TL, bool NC>
+__device__ __forceinline__ void tile32_unit(const TreeTask& tk, const float2* __restrict__ ain,
+                                            float2* __restrict__ aout, const float2* __restrict__ gtab,
+                                            int64_t ones_g, int64_t sig, uint64_t x, uint32_t b, int64_t be,
+                                            const TailView& tv) {
+    constexpr int W = 1 << K;
+    const uint32_t be_sh = uint32_t(__builtin_ctzll(uint64_t(be)));
+    const float2 *base_a, *base_b, *base_c = nullptr;
+    uint32_t sh_a, sh_b, sh_c = 0;
+    input_view<TL>(tk, 0, ain, gtab, ones_g, x, b, be_sh, tv, base_a, sh_a);
+    input_view<TL>(tk, 1, ain, gtab, ones_g, x, b, be_sh, tv, base_b, sh_b);
+    if (NC) input_view<TL>(tk, 2, ain, gtab, ones_g, x, b, be_sh, tv, base_c, sh_c);
+    int32_t ra[8], rb[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        ra[i] = tk.in_row[0] + ((i & 1) ? tk.in_inc[0][0] : 0) + ((i & 2) ? tk.in_inc[0][1] : 0) +
+                ((i & 4) ? tk.in_inc[0][2] : 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rb[j] = tk.in_row[1] + ((j & 1) ? tk.in_inc[1][0] : 0) + ((j & 2) ? tk.in_inc[1][1] : 0);
+    float2 acc[32];
+#pragma unroll
+    for (int o = 0; o < 32; ++o) acc[o] = make_float2(0.f, 0.f);
+#pragma unroll 2
+    for (int w = 0; w < W; ++w) {
+        int32_t oa = 0, ob = 0, oc = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((w >> i) & 1) {
+                oa += tk.in_vs[0][i];
+                ob += tk.in_vs[1][i];
+                if (NC) oc += tk.in_vs[2][i];
+            }
+        float2 q = (TL ? tv.g : gtab)[tk.g_ent + (int64_t(w) << tk.sb) + sig];
+        float2 A[8], Bv[4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) A[i] = base_a[int64_t(uint32_t(ra[i] + oa)) << sh_a];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bv[j] = base_b[int64_t(uint32_t(rb[j] + ob)) << sh_b];
+        if (NC) q = cmulf(q, base_c[int64_t(uint32_t(tk.in_row[2] + oc)) << sh_c]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float2 qa = cmulf(q, A[i]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 l = Bv[j];
+                // unit row of (A value i, B value j): bits 0, 1, 3 from i, bits 2, 4 from j
+                float2& c = acc[(i & 3) | ((j & 1) << 2) | ((i & 4) << 1) | ((j & 2) << 3)];
+                c.x = fmaf(qa.x, l.x, c.x);
+                c.x = fmaf(-qa.y, l.y, c.x);
+                c.y = fmaf(qa.x, l.y, c.y);
+                c.y = fmaf(qa.y, l.x, c.y);
+            }
+        }
+    }
+    if (TL) {
+        float2* out = tv.rows + int64_t(tk.out_row) * 64 + (b & 63u);
+#pragma unroll
+        for (int o = 0; o < 32; ++o) out[o * 64] = acc[o];
+        return;
+    }
+    float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b;
+#pragma unroll
+    for (int o = 0; o < 32; ++o) out[int64_t(o) * be] = acc[o];
+}
+
 // A unit of task tk for bitstring group bg (x = the lane's bitstring).
 template <int NIN, bool TL = false>
 __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const float2* __restrict__ ain,
@@ -365,10 +438,24 @@ __device__ __forceinline__ void tree_task(const TreeTask& tk, uint64_t x, const 
             return;
         }
     }
+    if constexpr (NIN == 2 || NIN == 3) {
+        if (!TL && tk.tile == 3) {   // never in the tail (32-row units have too many tasks for it)
+            if (tk.k == 2) tile32_unit<2, TL, false>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            else tile32_unit<3, TL, false>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            return;
+        }
+    }
     if constexpr (NIN >= 3) {
         if (tk.tile == 2) {
             if (tk.k == 2) tile_unit<2, TL, true>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
             else tile_unit<3, TL, true>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            return;
+        }
+    }
+    if constexpr (NIN == 3) {
+        if (!TL && tk.tile == 4) {
+            if (tk.k == 2) tile32_unit<2, TL, true>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
+            else tile32_unit<3, TL, true>(tk, ain, aout, gtab, ones_g, sig, x, b, be, tv);
             return;
         }
     }

@@ -142,7 +142,9 @@ struct TreeStep {
     int tile = 0;                       // 1 (two inputs) or 2 (three): a tile unit, whose unit bits 0 and 1
                                         //   vary only input 0, bit 2 only input 1 and none input 2 or the
                                         //   factor table; its 8 rows from 4 + 2 (+ 1) input rows and 1
-                                        //   table row per summed value (0: the general unit)
+                                        //   table row per summed value (0: the general unit); 3 or 4: the
+                                        //   32-row tile, unit bits 0, 1, 3 varying input 0 only and 2, 4
+                                        //   input 1 only, from 8 + 4 (+ 1) rows and 1 entry per value
     int64_t n_tasks() const {
         const int64_t rows = int64_t(1) << out_axes.size();
         return rows <= unit_rows ? 1 : rows / unit_rows;

@@ -488,8 +488,9 @@ def test_tail_plan_with_many_phase_factors_closed_form():
 
 def test_tile_buckets_planned_and_interpreted():
     """Buckets with two bits carried by one input only and one by another only
-    become tile units (8 result rows, those three bits lowest); the plan
-    computes the same amplitudes with and without them."""
+    become tile units (8 result rows, those three bits lowest; with three and
+    two such bits and at least 1024 rows, 32-row units whose five bits come
+    lowest); the plan computes the same amplitudes with and without them."""
     import paper_1712_05384_amd as Q
     from tree_interp import run_tree_plan
     c, _ = C.workload("c3_5x6_d30")
@@ -503,10 +504,14 @@ def test_tile_buckets_planned_and_interpreted():
 
     for bk in tiles:
         ins, out = bk["in_tensors"], bk["out_axes"]
-        assert bk["n_in"] == bk["tile"] + 1 and bk["kg"] >= 2 and bk["unit_rows"] == 8
-        # inputs in the order A (two bits), B (one bit), C (none)
+        big = bk["tile"] >= 3
+        assert bk["n_in"] == bk["tile"] + 1 - 2 * big and bk["kg"] >= 2 and bk["unit_rows"] == (32 if big else 8)
+        # inputs in the order A (unit bits 0, 1, and 3 for the 32-row tile), B (bit 2, and 4), C (none)
         assert alone(out[0], 0, ins) and alone(out[1], 0, ins) and alone(out[2], 1, ins)
-        assert not set(out[:3]) & set(bk["gvars"])
+        if big:
+            assert alone(out[3], 0, ins) and alone(out[4], 1, ins) and bk["r_out"] >= 10
+        assert not set(out[:5 if big else 3]) & set(bk["gvars"])
+    assert any(bk["tile"] >= 3 for bk in tiles)
     assert not any(bk["tile"] for bk in Q.plan(c, ordering=1, tile=False).info(1)["buckets"])
     c2 = C.random_grid_circuit(4, 4, 16, 3)
     bits = C.random_bitstrings(c2.n, 8, 3)
@@ -557,7 +562,7 @@ def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     kinds = set()
     for fin in (0, 1):
         kinds |= {bk["tile"] for bk in Q.plan(c, ordering=1, order_restarts=16 * fin, order_finalists=fin).info(1)["buckets"]}
-    assert kinds & {1, 2}
+    assert kinds & {1, 2, 3, 4}
     if (rows, cols, depth, seed) == (5, 5, 25, 201):
         assert 2 in kinds
     bits = C.random_bitstrings(c.n, 4, seed)

@@ -57,6 +57,7 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_5x5_d25")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-single-core", action="store_true", help="skip the one-core oracle timing")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary workloads (C4 gradients, C3 sliced, C5 four-circuit graph)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -201,6 +202,28 @@ def main() -> int:
                                   "sample": f"FP64 state vector of the same circuit (2^{c.n} entries), "
                                             f"{args.cpu_reps} full sweeps, median; each sweep yields the {B} "
                                             f"amplitudes; {tmed:.2f} s per sweep"}
+        if not args.no_single_core:
+            # the same oracle on one host core (OpenMP limited to one thread in a child process): the 5x5 depth-25
+            # batch (one sweep) and the 4x4 depth-16 batch (64 bitstrings, five sweeps)
+            import subprocess
+            code = ("import json, time, oracle\n"
+                    "from paper_1712_05384_amd import circuits as C\n"
+                    "r = {}\n"
+                    "for name, reps in (('c2_5x5_d25', 1), ('c1_4x4_d16', 5)):\n"
+                    "    c, b = C.workload(name)\n"
+                    "    t = time.perf_counter()\n"
+                    "    for _ in range(reps):\n"
+                    "        oracle.sv_amplitudes(c.n, c.gates, c.gate_vals, b)\n"
+                    "    dt = (time.perf_counter() - t) / reps\n"
+                    "    r[name] = {'amplitudes_per_sec': round(len(b) / dt, 2), 'seconds_per_sweep': round(dt, 4),\n"
+                    "               'bitstrings': len(b)}\n"
+                    "print(json.dumps(r))\n")
+            env = dict(os.environ, OMP_NUM_THREADS="1")
+            r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                               timeout=600)
+            if r.returncode == 0:
+                result["cpu_baseline"]["single_core"] = dict(json.loads(r.stdout.strip().splitlines()[-1]),
+                                                             note="FP64 state-vector oracle, one thread")
         result["max_abs_err"] = err
         result["max_abs_err_x_2^(n/2)"] = err * 2 ** (c.n / 2)
         result["tolerance_x_2^(n/2)"] = 1e-5

@@ -826,7 +826,7 @@ static std::string tree_json(const Plan& p, int detail) {
         for (size_t j = 0; j < L.jobs.size(); ++j) {
             const LdsJob& jb = L.jobs[j];
             o << (j ? "," : "") << "{\"bucket\":" << L.job_bucket[j] << ",\"nin\":" << jb.nin << ",\"k\":" << jb.k
-              << ",\"lanes\":" << jb.lanes << ",\"rows2\":" << jb.rows2 << ",\"out_row\":" << (jb.out_row - kLdsHeader) / 8
+              << ",\"lanes\":" << jb.lanes << ",\"rl\":" << jb.rl << ",\"out_row\":" << (jb.out_row - kLdsHeader) / 8
               << ",\"in_w\":[";
             for (int k = 0; k < jb.nin; ++k) {
                 o << (k ? "," : "") << "[";
@@ -844,8 +844,12 @@ static std::string tree_json(const Plan& p, int detail) {
                 for (int i = 0; i < 6; ++i) o << (i ? "," : "") << jb.str[sl < jb.nin ? sl : kLdsMaxIn][i] / 8;
                 o << "]";
             }
-            o << "],\"str6\":[";
-            for (int sl = 0; sl <= jb.nin; ++sl) o << (sl ? "," : "") << jb.str6[sl < jb.nin ? sl : kLdsMaxIn] / 8;
+            o << "],\"strx\":[";
+            for (int x = 0; x < 2; ++x) {
+                o << (x ? ",[" : "[");
+                for (int sl = 0; sl <= jb.nin; ++sl) o << (sl ? "," : "") << jb.strx[x][sl < jb.nin ? sl : kLdsMaxIn] / 8;
+                o << "]";
+            }
             o << "]}";
         }
         o << "],\"level_job_off\":[";

@@ -188,28 +188,41 @@ struct LdsEntry {
 };
 // Rows o0 + l of one bucket's result, l < 64 (fewer for a small result: lanes
 // beyond `lanes` compute a copy of a valid row and store nothing), and with
-// `rows2` also rows o0 + 64 + l.  Lane l computes
+// rl > 0 also rows o0 + 64 m + l for m < 2^rl.  Lane l computes
 //   R[o0 + l] = sum_w T[off_T(l) + tw[w]] * prod_t I_t[off_t(l) + in_w[t][w]]
 // with off_s(l) = base[s] + sum_{i < 6} (bit i of l) * str[s][i] for each input
-// s < nin and the table s = kLdsMaxIn, and row o0 + 64 + l the same with
-// off_s(l) + str6[s].  Offsets are LDS bytes (< 64 KiB).
+// s < nin and the table s = kLdsMaxIn, and row o0 + 64 m + l the same with
+// off_s(l) + (bit 0 of m) * strx[0][s] + (bit 1 of m) * strx[1][s] (the
+// strides of result bits 6 and 7).  Offsets are LDS bytes (< 64 KiB).
 struct LdsJob {
     int32_t nin, k, lanes, out_row;
     int32_t base[kLdsMaxIn + 1];
     int32_t tw[8];
     int32_t in_w[kLdsMaxIn][8];
     int32_t str[kLdsMaxIn + 1][6];
-    int32_t rows2;                       // 1: the job also computes the 64 rows after its first 64
-    int32_t str6[kLdsMaxIn + 1];
+    int32_t rl;                          // log2 of the rows per lane (0, 1 or 2)
+    int32_t strx[2][kLdsMaxIn + 1];
 };
 // The device form of a job: kLdsRecordHalves 16-bit fields, 16-byte aligned:
-// [0] nin | k << 3 | (lanes - 1) << 5 | rows2 << 11, [1] out_row, [2..6] base,
-// [8..15] tw, [16..47] in_w[t][w] at 16 + 8 t + w, [48..77] str[s][i] at
-// 48 + 6 s + i, [80..84] str6[s].
-constexpr int kLdsRecordHalves = 88;
-// A job with at most this many loads per row issues them all before its first product (and may take two
-// rows per lane); a larger one interleaves loads and products to bound its registers.
+// [0] nin | k << 3 | (lanes - 1) << 5 | rl << 11, [1] out_row, [2..6] base,
+// [8..15] tw, [16..47] in_w[t][w] at 16 + 8 t + w, then for each slot s the
+// lane offsets by three-bit groups: [48 + 16 s + c] = base[s] + the strides of
+// the set bits of c (lane bits 0-2), [56 + 16 s + c] = the strides of the set
+// bits of c as lane bits 3-5, so off_s(l) is one entry of each; [128..132]
+// strx[0][s], [136..140] strx[1][s].
+constexpr int kLdsRecordHalves = 144;
+// A job with at most this many loads per row issues them all before its first product; a larger one
+// interleaves loads and products to bound its registers.
 constexpr int kLdsBatchLoads = 12;
+// A job of 2^rl rows per lane batches its loads when (nin + 1) 2^k <= kLdsBatchLoads (rl <= 1) or
+// <= kLdsBatchLoads / 2 (rl = 2).  The largest rl a job may take: 2 when its four rows batch, 1 when one
+// row has at most two batches of loads, else 0.
+constexpr bool lds_batched(int nin, int k, int rl) {
+    return (nin + 1) * (1 << k) <= (rl >= 2 ? kLdsBatchLoads / 2 : kLdsBatchLoads);
+}
+constexpr int lds_max_rl(int nin, int k) {
+    return lds_batched(nin, k, 2) ? 2 : (nin + 1) * (1 << k) <= 2 * kLdsBatchLoads ? 1 : 0;
+}
 constexpr int kLdsRecordBytes = 2 * kLdsRecordHalves;
 struct LdsProgram {
     bool ok = false;

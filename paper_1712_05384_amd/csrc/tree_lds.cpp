@@ -152,9 +152,49 @@ void build_lds_program(TreePlan& t) {
         P.gent.push_back(P.entries[i].src | (P.entries[i].stage << 24));
     }
     auto bytes = [](int64_t entry) { return int32_t(kLdsHeader + 8 * entry); };
+    // Rows per lane of each bucket (rl: 2^rl rows): 2 where a row's loads batch and the result has 128 rows
+    // or more (the rows share the record and the lane offsets, their loads are independent); then, per level,
+    // more rows per lane for the bucket with the most jobs while the level has more jobs than the work-group
+    // has waves and a bucket can take more (a level whose jobs take one pass of the waves ends sooner than
+    // one that takes two, although its longest job is longer).
+    std::vector<int> rl(t.steps.size(), 0);
+    auto rank = [&](int sid) { return int(lax[size_t(t.steps[size_t(sid)].out_tensor)].size()); };
+    auto jobs_of = [&](int sid) { return std::max<int64_t>(1, (int64_t(1) << rank(sid)) >> (6 + rl[size_t(sid)])); };
+    auto can_grow = [&](int sid) {
+        const TreeStep& st = t.steps[size_t(sid)];
+        const int nin = int(st.in_tensors.size());
+        return rl[size_t(sid)] < lds_max_rl(nin, st.kg) && rank(sid) >= 7 + rl[size_t(sid)];
+    };
+    int64_t n_jobs = 0, max_jobs = 0;
+    for (int L = 0; L < n_levels; ++L) {
+        int64_t nj = 0;
+        for (int sid : t.levels[size_t(L)]) {
+            const TreeStep& st = t.steps[size_t(sid)];
+            if (st.table_leaf) continue;
+            if (rank(sid) >= 7 && lds_batched(int(st.in_tensors.size()), st.kg, 1)) rl[size_t(sid)] = 1;
+            nj += jobs_of(sid);
+        }
+        n_jobs += nj;
+        max_jobs = std::max(max_jobs, nj);
+    }
+    // 8 waves when levels have many jobs (fewer bitstrings fit a compute unit, each finishes sooner), else 4
+    const double mean_jobs = n_levels > 0 ? double(n_jobs) / n_levels : 0.0;
+    P.threads = mean_jobs >= 5.0 || max_jobs >= 12 ? kLdsLargeThreads : kLdsSmallThreads;
+    const int64_t n_waves = P.threads / 64;
+    for (int L = 0; L < n_levels; ++L) {
+        for (;;) {
+            int64_t nj = 0, best = -1;
+            for (int sid : t.levels[size_t(L)]) {
+                if (t.steps[size_t(sid)].table_leaf) continue;
+                nj += jobs_of(sid);
+                if (can_grow(sid) && (best < 0 || jobs_of(sid) > jobs_of(int(best)))) best = sid;
+            }
+            if (nj <= n_waves || best < 0) break;
+            ++rl[size_t(best)];
+        }
+    }
     // jobs, level by level
     P.level_job_off.assign(1, 0);
-    int max_jobs = 0;
     for (int L = 0; L < n_levels; ++L) {
         for (int sid : t.levels[size_t(L)]) {
             const TreeStep& st = t.steps[size_t(sid)];
@@ -172,25 +212,23 @@ void build_lds_program(TreePlan& t) {
                 }
             }
             const int64_t n_rows = int64_t(1) << r;
-            // a bucket of 128 rows or more whose job batches its loads takes 128 rows per job (two per
-            // lane): the rows share the record and the lane offsets, and their loads are independent
-            const bool two = r >= 7 && (nin + 1) * (1 << st.kg) <= kLdsBatchLoads;
-            for (int64_t o0 = 0; o0 < n_rows; o0 += two ? 128 : 64) {
+            const int jrl = rl[size_t(sid)];
+            for (int64_t o0 = 0; o0 < n_rows; o0 += int64_t(64) << jrl) {
                 LdsJob jb{};
                 jb.nin = nin;
                 jb.k = st.kg;
                 jb.lanes = int32_t(std::min<int64_t>(64, n_rows));
-                jb.rows2 = two ? 1 : 0;
+                jb.rl = jrl;
                 jb.out_row = bytes(P.tensor_lds[st.out_tensor] + o0);
                 for (int k = 0; k <= nin; ++k) {
                     int64_t row = k < nin ? P.tensor_lds[st.in_tensors[size_t(k)]] : tab_lds[size_t(sid)];
                     if (row < 0) return fail("an input without LDS rows");
-                    for (int j = two ? 7 : 6; j < r; ++j)
+                    for (int j = 6 + jrl; j < r; ++j)
                         if ((o0 >> j) & 1) row += ostr[size_t(k)][size_t(j)];
                     const int slot = k < nin ? k : kLdsMaxIn;
                     jb.base[slot] = bytes(row);
                     for (int j = 0; j < std::min(r, 6); ++j) jb.str[slot][j] = int32_t(8 * ostr[size_t(k)][size_t(j)]);
-                    if (two) jb.str6[slot] = int32_t(8 * ostr[size_t(k)][6]);
+                    for (int x = 0; x < jrl; ++x) jb.strx[x][slot] = int32_t(8 * ostr[size_t(k)][size_t(6 + x)]);
                 }
                 // the summed values: their offset in each input, and in the table (w << gb)
                 for (int w = 0; w < (1 << st.kg); ++w) {
@@ -210,29 +248,36 @@ void build_lds_program(TreePlan& t) {
             }
         }
         P.level_job_off.push_back(int32_t(P.jobs.size()));
-        max_jobs = std::max(max_jobs, P.level_job_off[size_t(L) + 1] - P.level_job_off[size_t(L)]);
     }
     for (int f : t.finals) {
         if (P.tensor_lds[f] < 0) return fail("a rank-0 result without LDS rows");
         P.finals.push_back(bytes(P.tensor_lds[f]));
     }
-    // 8 waves when levels have many jobs (fewer bitstrings fit a compute unit, each finishes sooner), else 4
-    const double mean_jobs = n_levels > 0 ? double(P.jobs.size()) / n_levels : 0.0;
-    P.threads = mean_jobs >= 5.0 || max_jobs >= 12 ? kLdsLargeThreads : kLdsSmallThreads;
     // the device records; kept in LDS after the tables when they fit (then a job reads nothing from memory)
     P.recs.assign(P.jobs.size() * size_t(kLdsRecordHalves), 0);
     for (size_t j = 0; j < P.jobs.size(); ++j) {
         const LdsJob& jb = P.jobs[j];
         uint16_t* rc = &P.recs[j * size_t(kLdsRecordHalves)];
-        rc[0] = uint16_t(jb.nin | (jb.k << 3) | ((jb.lanes - 1) << 5) | (jb.rows2 << 11));
+        rc[0] = uint16_t(jb.nin | (jb.k << 3) | ((jb.lanes - 1) << 5) | (jb.rl << 11));
         rc[1] = uint16_t(jb.out_row);
         for (int s2 = 0; s2 <= kLdsMaxIn; ++s2) rc[2 + s2] = uint16_t(jb.base[s2]);
         for (int w = 0; w < 8; ++w) rc[8 + w] = uint16_t(jb.tw[w]);
         for (int k = 0; k < kLdsMaxIn; ++k)
             for (int w = 0; w < 8; ++w) rc[16 + 8 * k + w] = uint16_t(jb.in_w[k][w]);
         for (int s2 = 0; s2 <= kLdsMaxIn; ++s2)
-            for (int i = 0; i < 6; ++i) rc[48 + 6 * s2 + i] = uint16_t(jb.str[s2][i]);
-        for (int s2 = 0; s2 <= kLdsMaxIn; ++s2) rc[80 + s2] = uint16_t(jb.str6[s2]);
+            for (int c = 0; c < 8; ++c) {
+                int32_t lo = jb.base[s2], hi = 0;
+                for (int i = 0; i < 3; ++i)
+                    if ((c >> i) & 1) {
+                        lo += jb.str[s2][i];
+                        hi += jb.str[s2][3 + i];
+                    }
+                if (lo > 0xFFFF || hi > 0xFFFF) return fail("a lane offset beyond 64 KiB");
+                rc[48 + 16 * s2 + c] = uint16_t(lo);
+                rc[56 + 16 * s2 + c] = uint16_t(hi);
+            }
+        for (int x = 0; x < 2; ++x)
+            for (int s2 = 0; s2 <= kLdsMaxIn; ++s2) rc[128 + 8 * x + s2] = uint16_t(jb.strx[x][s2]);
     }
     // records in LDS whenever they fit: a job then reads its record with one LDS round trip instead of a
     // memory one (measured faster at every batch on 5x5 depth 25, although fewer work-groups fit a CU)
@@ -250,7 +295,7 @@ int64_t lds_bytes_per_amp(const LdsProgram& P) {
     if (!P.ok) return 0;
     int64_t b = int64_t(P.entries.size()) * 8;
     for (const LdsJob& j : P.jobs)
-        b += int64_t(j.lanes) * (1 + j.rows2) * (((int64_t(1) << j.k) * (j.nin + 1) + 1) * 8);
+        b += int64_t(j.lanes) * (int64_t(1) << j.rl) * (((int64_t(1) << j.k) * (j.nin + 1) + 1) * 8);
     return b;
 }
 

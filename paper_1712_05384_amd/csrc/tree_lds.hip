@@ -9,8 +9,8 @@
 // summed value w by its input rows, sums over w, and stores the row; a block
 // barrier separates levels, as a level reads only results of earlier levels.
 // A job record holds the LDS byte offsets at its first row and the strides of
-// the six lane bits (a bucket of 128 rows or more takes two rows per lane,
-// the second at a seventh stride); the records are copied to LDS with the
+// the six lane bits (a bucket of 128 rows or more may take two or four rows
+// per lane, at the strides of result bits 6 and 7); the records are copied to LDS with the
 // tables when they fit, so after the first burst of loads the levels touch no
 // memory.
 #include <hip/hip_runtime.h>
@@ -30,36 +30,27 @@ namespace {
 __device__ __forceinline__ uint4 rec16(const char* __restrict__ rp, int byte) {
     return *reinterpret_cast<const uint4*>(rp + byte);
 }
-__device__ __forceinline__ uint32_t rec4(const char* __restrict__ rp, int byte) {
-    return *reinterpret_cast<const uint32_t*>(rp + byte);
-}
 __device__ __forceinline__ uint32_t half(uint4 v, int i) {   // 16-bit field i of a 16-byte word
     const uint32_t d = (i >> 1) == 0 ? v.x : (i >> 1) == 1 ? v.y : (i >> 1) == 2 ? v.z : v.w;
     return (i & 1) ? d >> 16 : d & 0xFFFFu;
 }
 
-// Lane offset of slot s: base + sum_i (bit i of the lane) * stride i, the six
-// 16-bit strides at record bytes 96 + 12 s (one 24-bit multiply-add each).
-__device__ __forceinline__ uint32_t lane_off(const char* __restrict__ rp, int s, uint32_t base,
-                                             const uint32_t (&lb)[6]) {
-    const uint32_t d0 = rec4(rp, 96 + 12 * s), d1 = rec4(rp, 100 + 12 * s), d2 = rec4(rp, 104 + 12 * s);
-    uint32_t o = base;
-    o = __umul24(lb[0], d0 & 0xFFFFu) + o;
-    o = __umul24(lb[1], d0 >> 16) + o;
-    o = __umul24(lb[2], d1 & 0xFFFFu) + o;
-    o = __umul24(lb[3], d1 >> 16) + o;
-    o = __umul24(lb[4], d2 & 0xFFFFu) + o;
-    o = __umul24(lb[5], d2 >> 16) + o;
-    return o;
+// Lane offset of slot s: the record's entry for the lane's bits 0-2 (which
+// includes the slot's base) plus its entry for bits 3-5; lo and hi are the
+// record addresses of the lane's entries of slot 0 (2 (l & 7) and
+// 16 + 2 (l >> 3) bytes past the tables), so each entry is one 16-bit load.
+__device__ __forceinline__ uint32_t lane_off(const char* __restrict__ lo, const char* __restrict__ hi, int s) {
+    return uint32_t(*reinterpret_cast<const uint16_t*>(lo + 32 * s)) +
+           uint32_t(*reinterpret_cast<const uint16_t*>(hi + 32 * s));
 }
 
-// One job: rows out_row + lane of its bucket's result (lanes < the record's
-// count) and, with M = 2, rows out_row + 64 + lane too (slot offsets + the
-// record's str6); h is the record's first 16 bytes, rp the record, L the
-// work-group's LDS.
+// One job: rows out_row + 64 m + lane of its bucket's result for m < M (lanes
+// < the record's count; row m's slot offsets add the record's strides of
+// result bits 6 and 7 for the bits of m); h is the record's first 16 bytes, rp
+// the record, L the work-group's LDS.
 template <int NIN, int K, int M>
 __device__ __forceinline__ void lds_job(uint4 h, uint32_t lanes, const char* __restrict__ rp, char* __restrict__ L,
-                                        const uint32_t (&lb)[6], uint32_t lane) {
+                                        const uint32_t (&lb)[2], uint32_t lane) {
     constexpr int W = 1 << K;
     constexpr int NR = NIN > 0 ? NIN : 1;
     const uint4 tw = rec16(rp, 16);
@@ -67,82 +58,99 @@ __device__ __forceinline__ void lds_job(uint4 h, uint32_t lanes, const char* __r
 #pragma unroll
     for (int t = 0; t < NIN; ++t) iw[t] = rec16(rp, 32 + 16 * t);
     uint32_t row[M][NR], tb[M];
+    const char* __restrict__ lo = rp + 96 + lb[0];
+    const char* __restrict__ hi = rp + 96 + lb[1];
 #pragma unroll
-    for (int t = 0; t < NIN; ++t) row[0][t] = lane_off(rp, t, half(h, 2 + t), lb);
-    tb[0] = lane_off(rp, kLdsMaxIn, half(h, 2 + kLdsMaxIn), lb);
-    if constexpr (M == 2) {
-        const uint4 s6 = rec16(rp, 160);
+    for (int t = 0; t < NIN; ++t) row[0][t] = lane_off(lo, hi, t);
+    tb[0] = lane_off(lo, hi, kLdsMaxIn);
+    if constexpr (M >= 2) {
+        const uint4 s6 = rec16(rp, 256);
 #pragma unroll
         for (int t = 0; t < NIN; ++t) row[1][t] = row[0][t] + half(s6, t);
         tb[1] = tb[0] + half(s6, kLdsMaxIn);
     }
-    float2 q[M][W], v[M][NR][W];
+    if constexpr (M == 4) {
+        const uint4 s7 = rec16(rp, 272);
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
+        for (int m = 2; m < 4; ++m) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) q[m][w] = *reinterpret_cast<const float2*>(L + tb[m] + half(tw, w));
-#pragma unroll
-        for (int t = 0; t < NIN; ++t)
-#pragma unroll
-            for (int w = 0; w < W; ++w) v[m][t][w] = *reinterpret_cast<const float2*>(L + row[m][t] + half(iw[t], w));
+            for (int t = 0; t < NIN; ++t) row[m][t] = row[m - 2][t] + half(s7, t);
+            tb[m] = tb[m - 2] + half(s7, kLdsMaxIn);
+        }
     }
-    // every load of a job with at most kLdsBatchLoads loads per row is issued before the first product:
-    // the values pass through empty asm statements, so the compiler cannot interleave the loads with the
-    // arithmetic (one LDS round trip per job instead of one per summed value; larger jobs would hold more
-    // registers than the occupancy allows)
-    if constexpr ((NIN + 1) * W <= kLdsBatchLoads) {
+    // every load of a job with at most kLdsBatchLoads loads per row (half as many with four rows) is issued
+    // before the first product: the values pass through empty asm statements, so the compiler cannot
+    // interleave the loads with the arithmetic (one LDS round trip per job instead of one per summed value).
+    // A larger job takes its rows one after the other (each row's store precedes the next row's loads, which
+    // may read the same LDS), so its registers stay those of one row.
+    constexpr bool BATCH = lds_batched(NIN, K, M == 4 ? 2 : M - 1);
+    constexpr int MB = BATCH ? M : 1;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
+    for (int m0 = 0; m0 < M; m0 += MB) {
+        float2 q[MB][W], v[MB][NR][W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) asm volatile("" : "+v"(q[m][w].x), "+v"(q[m][w].y));
+        for (int m = 0; m < MB; ++m) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) q[m][w] = *reinterpret_cast<const float2*>(L + tb[m0 + m] + half(tw, w));
 #pragma unroll
             for (int t = 0; t < NIN; ++t)
 #pragma unroll
-                for (int w = 0; w < W; ++w) asm volatile("" : "+v"(v[m][t][w].x), "+v"(v[m][t][w].y));
+                for (int w = 0; w < W; ++w)
+                    v[m][t][w] = *reinterpret_cast<const float2*>(L + row[m0 + m][t] + half(iw[t], w));
         }
-    }
+        if constexpr (BATCH) {
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        float2 acc = make_float2(0.f, 0.f);
+            for (int m = 0; m < MB; ++m) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-            if constexpr (NIN == 0) {
-                acc.x += q[m][w].x;
-                acc.y += q[m][w].y;
-            } else {
-                float2 pw = q[m][w];
+                for (int w = 0; w < W; ++w) asm volatile("" : "+v"(q[m][w].x), "+v"(q[m][w].y));
 #pragma unroll
-                for (int t = 0; t + 1 < NIN; ++t) pw = cmulf(pw, v[m][t][w]);
-                const float2 l = v[m][NIN - 1][w];   // the last factor goes into the sum as fused multiply-adds
-                acc.x = fmaf(pw.x, l.x, acc.x);
-                acc.x = fmaf(-pw.y, l.y, acc.x);
-                acc.y = fmaf(pw.x, l.y, acc.y);
-                acc.y = fmaf(pw.y, l.x, acc.y);
+                for (int t = 0; t < NIN; ++t)
+#pragma unroll
+                    for (int w = 0; w < W; ++w) asm volatile("" : "+v"(v[m][t][w].x), "+v"(v[m][t][w].y));
             }
         }
-        if (lane < lanes) *reinterpret_cast<float2*>(L + (h.x >> 16) + 512 * m + 8 * lane) = acc;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                if constexpr (NIN == 0) {
+                    acc.x += q[m][w].x;
+                    acc.y += q[m][w].y;
+                } else {
+                    float2 pw = q[m][w];
+#pragma unroll
+                    for (int t = 0; t + 1 < NIN; ++t) pw = cmulf(pw, v[m][t][w]);
+                    const float2 l = v[m][NIN - 1][w];   // the last factor enters the sum as fused multiply-adds
+                    acc.x = fmaf(pw.x, l.x, acc.x);
+                    acc.x = fmaf(-pw.y, l.y, acc.x);
+                    acc.y = fmaf(pw.x, l.y, acc.y);
+                    acc.y = fmaf(pw.y, l.x, acc.y);
+                }
+            }
+            if (lane < lanes) *reinterpret_cast<float2*>(L + (h.x >> 16) + 512 * (m0 + m) + 8 * lane) = acc;
+        }
     }
 }
 
+template <int NIN, int K>
+__device__ __forceinline__ void lds_job_m(int rl, uint4 h, uint32_t lanes, const char* __restrict__ rp,
+                                          char* __restrict__ L, const uint32_t (&lb)[2], uint32_t lane) {
+    // rows per lane up to the planner's limit for this shape (the other cases are never recorded)
+    constexpr int R = lds_max_rl(NIN, K);
+    if (R >= 2 && rl == 2) lds_job<NIN, K, R >= 2 ? 4 : 1>(h, lanes, rp, L, lb, lane);
+    else if (R >= 1 && rl >= 1) lds_job<NIN, K, R >= 1 ? 2 : 1>(h, lanes, rp, L, lb, lane);
+    else lds_job<NIN, K, 1>(h, lanes, rp, L, lb, lane);
+}
+
 template <int NIN>
-__device__ __forceinline__ void lds_job_k(int k, bool two, uint4 h, uint32_t lanes, const char* __restrict__ rp,
-                                          char* __restrict__ L, const uint32_t (&lb)[6], uint32_t lane) {
-    // two rows per lane only where a row's loads are batched (the planner's rule)
-    constexpr bool T1 = (NIN + 1) * 2 <= kLdsBatchLoads, T2 = (NIN + 1) * 4 <= kLdsBatchLoads;
+__device__ __forceinline__ void lds_job_k(int k, int rl, uint4 h, uint32_t lanes, const char* __restrict__ rp,
+                                          char* __restrict__ L, const uint32_t (&lb)[2], uint32_t lane) {
     switch (k) {
-        case 0:
-            if (two) lds_job<NIN, 0, 2>(h, lanes, rp, L, lb, lane);
-            else lds_job<NIN, 0, 1>(h, lanes, rp, L, lb, lane);
-            break;
-        case 1:
-            if (T1 && two) lds_job<NIN, 1, T1 ? 2 : 1>(h, lanes, rp, L, lb, lane);
-            else lds_job<NIN, 1, 1>(h, lanes, rp, L, lb, lane);
-            break;
-        case 2:
-            if (T2 && two) lds_job<NIN, 2, T2 ? 2 : 1>(h, lanes, rp, L, lb, lane);
-            else lds_job<NIN, 2, 1>(h, lanes, rp, L, lb, lane);
-            break;
-        default: lds_job<NIN, 3, 1>(h, lanes, rp, L, lb, lane); break;
+        case 0: lds_job_m<NIN, 0>(rl, h, lanes, rp, L, lb, lane); break;
+        case 1: lds_job_m<NIN, 1>(rl, h, lanes, rp, L, lb, lane); break;
+        case 2: lds_job_m<NIN, 2>(rl, h, lanes, rp, L, lb, lane); break;
+        default: lds_job_m<NIN, 3>(rl, h, lanes, rp, L, lb, lane); break;
     }
 }
 
@@ -263,9 +271,8 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
         }
         e0 = e1;
     }
-    uint32_t lb[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) lb[i] = (lane >> i) & 1u;
+    // the byte offsets of the lane's entries in a record's lane-offset tables (bits 0-2, bits 3-5)
+    const uint32_t lb[2] = {2u * (lane & 7u), 16u + 2u * (lane >> 3)};
     const char* __restrict__ recs = RL ? L + kLdsHeader + 8 * a.recs0 : reinterpret_cast<const char*>(a.recs);
     __syncthreads();
     for (int lv = 0; lv < a.n_levels; ++lv) {
@@ -276,13 +283,13 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
             const uint32_t hd = __builtin_amdgcn_readfirstlane(h.x & 0xFFFFu);
             const uint32_t lanes = ((hd >> 5) & 63u) + 1u;
             const int k = int((hd >> 3) & 3u);
-            const bool two = (hd >> 11) & 1u;
+            const int rl = int((hd >> 11) & 3u);
             switch (hd & 7u) {
-                case 0: lds_job_k<0>(k, two, h, lanes, rp, L, lb, lane); break;
-                case 1: lds_job_k<1>(k, two, h, lanes, rp, L, lb, lane); break;
-                case 2: lds_job_k<2>(k, two, h, lanes, rp, L, lb, lane); break;
-                case 3: lds_job_k<3>(k, two, h, lanes, rp, L, lb, lane); break;
-                default: lds_job_k<4>(k, two, h, lanes, rp, L, lb, lane); break;
+                case 0: lds_job_k<0>(k, rl, h, lanes, rp, L, lb, lane); break;
+                case 1: lds_job_k<1>(k, rl, h, lanes, rp, L, lb, lane); break;
+                case 2: lds_job_k<2>(k, rl, h, lanes, rp, L, lb, lane); break;
+                case 3: lds_job_k<3>(k, rl, h, lanes, rp, L, lb, lane); break;
+                default: lds_job_k<4>(k, rl, h, lanes, rp, L, lb, lane); break;
             }
         }
         // the phase product on the last wave during the last level (it usually has no job there)

@@ -3,8 +3,8 @@ with tree_exec 3), complex128.
 
 It executes the program the planner exports (plan JSON detail 2, "lds"): the
 table slices copied at a bitstring's output bits, then level by level the jobs
--- 64 result rows of one bucket (128 for a two-row job, the second 64 at a
-seventh stride), lane l reading its inputs and the factor-table slice at the
+-- 64 result rows of one bucket (128 or 256 for a job of two or four rows
+per lane, the further rows at the strides of result bits 6 and 7), lane l reading its inputs and the factor-table slice at the
 job's base offsets plus the strides of its six lane bits plus the
 per-summed-value offsets --
 and finally phase x the rank-0 results.  Every LDS entry read must have been
@@ -79,11 +79,12 @@ def _run_column(info, L, area, stage_q, size, x, gate_vals):
         for j in range(offs[lv], offs[lv + 1]):
             jb = L["jobs"][j]
             nin, k, lanes = jb["nin"], jb["k"], jb["lanes"]
-            for lane in range(64 * (1 + jb["rows2"])):
+            for lane in range(64 << jb["rl"]):
                 # the lane's offsets: the job's base plus the strides of the lane's six bits (inputs, then
-                # the table); a two-row job's second row adds its seventh stride
+                # the table); row m of a job of 2 or 4 rows per lane adds the strides of result bits 6, 7
                 m, ln = lane >> 6, lane & 63
-                off = [jb["base"][sl] + sum(((ln >> i) & 1) * jb["str"][sl][i] for i in range(6)) + m * jb["str6"][sl]
+                off = [jb["base"][sl] + sum(((ln >> i) & 1) * jb["str"][sl][i] for i in range(6))
+                       + sum(((m >> x) & 1) * jb["strx"][x][sl] for x in range(2))
                        for sl in range(nin + 1)]
                 acc = 0j
                 for w in range(1 << k):

@@ -611,7 +611,7 @@ def test_lds_program_gate_values_and_benchmark_plan():
     # the LDS bytes the bench's roofline uses: per kept row 2^k (inputs + table) reads and one write, plus the
     # copied table entries, counted from the exported jobs
     L = info["lds"]
-    want = 8 * len(L["entries"]) + sum(j["lanes"] * (1 + j["rows2"]) * 8 * ((1 << j["k"]) * (j["nin"] + 1) + 1)
+    want = 8 * len(L["entries"]) + sum(j["lanes"] * (1 << j["rl"]) * 8 * ((1 << j["k"]) * (j["nin"] + 1) + 1)
                                        for j in L["jobs"])
     assert info["lds_bytes_per_amp"] == want
 

@@ -1026,7 +1026,8 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
             for (int L = t.first_level; L < t.tail_start; ++L) {
                 const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
                 qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g,
-                                       cb, nb, uint32_t(be), uint32_t((nb + 63) / 64), s);
+                                       cb, nb, uint32_t(be), uint32_t((nb + 63) / 64), s,
+                                       int32_t(t.level_quad[size_t(L)]));
             }
             const int n_tail = int(t.levels.size()) - t.tail_start;
             if (n_tail > 0) {

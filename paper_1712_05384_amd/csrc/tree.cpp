@@ -440,7 +440,8 @@ static std::vector<int> unit_axis_order(const RStep& st, const std::vector<std::
 // the inputs in the order A, B, C.
 static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
                            const std::vector<std::vector<int>>& out_of, std::vector<int>& order,
-                           std::vector<int>& ins) {
+                           std::vector<int>& ins, char& quad) {
+    quad = 0;
     const int n = int(st.ins.size());
     if (st.open || (n != 2 && n != 3) || st.vars.size() < 2) return 0;
     std::set<int> gset;
@@ -473,6 +474,13 @@ static int tile_axis_order(const Plan& p, const Model& m, const RStep& st,
     if (big) {
         order.push_back(only[ka][2]);
         order.push_back(only[kb][1]);
+        // two inputs and two more bits of B alone: those next (result bits 5 and 6), so four consecutive
+        // 32-row units read the same rows of A
+        if (n == 2 && only[kb].size() >= 4) {
+            order.push_back(only[kb][2]);
+            order.push_back(only[kb][3]);
+            quad = 1;
+        }
     }
     ins = {st.ins[ka], st.ins[kb]};
     for (int k = 0; k < n; ++k)
@@ -504,12 +512,13 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         if (st.alive) out_of[st.out_tensor] = st.out;
     std::vector<std::vector<int>> out_ord(rs.size());
     std::vector<int> tile_of(rs.size(), 0);
+    std::vector<char> quad_of(rs.size(), 0);
     std::vector<std::vector<int>> tile_ins(rs.size());
     for (size_t i = 0; i < rs.size(); ++i) {   // a bucket over the open qubits keeps their order (output index bits)
         if (!rs[i].alive) continue;
         if (rs[i].open) out_ord[i] = rs[i].out;
         else if (p.opts.no_tile == 0 &&
-                 (tile_of[i] = tile_axis_order(p, m, rs[i], out_of, out_ord[i], tile_ins[i])) != 0) {}
+                 (tile_of[i] = tile_axis_order(p, m, rs[i], out_of, out_ord[i], tile_ins[i], quad_of[i])) != 0) {}
         else out_ord[i] = unit_axis_order(rs[i], out_of);
     }
     std::vector<int> tmap(rt.size(), -1);
@@ -546,6 +555,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         }
         ts.level = level;
         ts.tile = tile_of[si];
+        ts.quad = quad_of[si] != 0;
         t.tensor_made[ts.out_tensor] = level;
         group_table_vars(p, m, st, gset, sigq);
         std::vector<int> g(gset.begin(), gset.end());
@@ -921,6 +931,7 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
     // wave tasks of the buckets with inputs, grouped by level (a level is one launch)
     t.level_task_off.assign(1, 0);
     t.level_max_in.clear();
+    t.level_quad.clear();
     for (size_t L = 0; L < t.levels.size(); ++L) {
         int mi = 0;
         for (int sid : t.levels[L]) mi = std::max(mi, int(t.steps[sid].in_tensors.size()));
@@ -930,12 +941,21 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
             // the 32-row tile runs in the 2- and 3-input launches of levels that are not the tail's (it holds
             // 64 accumulator registers, more than the wider launches leave); elsewhere its 8-row form
             if (st.tile >= 3 && (nin > 3 || st.out_axes.size() < 10)) st.tile -= 2;
+            st.quad = st.quad && st.tile == 3 && !st.table_leaf;
             st.unit_rows = st.tile >= 3 ? 32 : (st.tile ? (1 << kTreeOcBits) : tree_unit_rows(nin, st.kg));
+        }
+        // the quad tiles' tasks first (their launch takes blocks of four tasks)
+        std::stable_partition(t.levels[L].begin(), t.levels[L].end(), [&](int sid) { return t.steps[sid].quad; });
+        int64_t nq = 0;
+        for (int sid : t.levels[L]) {
+            TreeStep& st = t.steps[sid];
             st.task_off = t.n_tasks;
             t.n_tasks += st.n_tasks();
+            if (st.quad) nq += st.n_tasks();
         }
         t.level_task_off.push_back(t.n_tasks);
         t.level_max_in.push_back(mi);
+        t.level_quad.push_back(nq);
     }
     // tail: the longest run of last levels with few tasks and few inputs
     t.first_level = 0;

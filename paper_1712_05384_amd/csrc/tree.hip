@@ -511,6 +511,136 @@ __global__ void __launch_bounds__(256) k_tree_level(const TreeTask* __restrict__
     }
 }
 
+// Quad tiles: a work-group of 4 waves runs 4 consecutive 32-row tile tasks of
+// one two-input bucket (result bits 5 and 6 vary input B only) for one group
+// of 64 bitstrings.  The 8 rows of A and the factor-table entry of every
+// summed value are the same for the four tasks, so the waves first load them
+// once into LDS (a quarter each), then each wave runs its own task reading A
+// and the table from LDS and its 4 rows of B from memory: per wave
+// 9 * 2^K / 4 + 4 * 2^K row loads instead of 13 * 2^K.  Results as in
+// tile32_unit (same rows, same order of the products).
+constexpr int kQuadRows = 9 << kTreeMaxSum;   // 8 rows of A and one table row per summed value
+// Results of a level's quad tiles beyond this many bytes are stored non-temporally: they exceed the
+// last-level cache, so keeping them there would only evict the rows of A and B that other units re-read.
+constexpr int64_t kQuadStreamBytes = int64_t(256) << 20;
+
+template <int K, bool NT>
+__device__ __forceinline__ void quad_unit(const TreeTask& tk, const float2* __restrict__ ain,
+                                          float2* __restrict__ aout, const float2* __restrict__ gtab, int64_t ones_g,
+                                          int64_t sig, uint64_t x, uint32_t b, int64_t be, uint32_t lane,
+                                          uint32_t wave, float2 (*sA)[64]) {
+    constexpr int W = 1 << K;
+    const uint32_t be_sh = uint32_t(__builtin_ctzll(uint64_t(be)));
+    const float2 *base_a, *base_b;
+    uint32_t sh_a, sh_b;
+    input_view<false>(tk, 0, ain, gtab, ones_g, x, b, be_sh, TailView{}, base_a, sh_a);
+    input_view<false>(tk, 1, ain, gtab, ones_g, x, b, be_sh, TailView{}, base_b, sh_b);
+    // LDS row r < 8W: row i = r >> K of A at summed value w = r & (W - 1); row 8W + w: the table entry
+    constexpr int PER = 9 * W / 4;
+    float2 v[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const int r = int(wave) + 4 * s;
+        const int w = r & (W - 1);
+        if (r < 8 * W) {
+            const int i = r >> K;
+            int32_t ra = tk.in_row[0] + ((i & 1) ? tk.in_inc[0][0] : 0) + ((i & 2) ? tk.in_inc[0][1] : 0) +
+                         ((i & 4) ? tk.in_inc[0][2] : 0);
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if ((w >> c) & 1) ra += tk.in_vs[0][c];
+            v[s] = base_a[int64_t(uint32_t(ra)) << sh_a];
+        } else {
+            v[s] = gtab[tk.g_ent + (int64_t(w) << tk.sb) + sig];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < PER; ++s) sA[int(wave) + 4 * s][lane] = v[s];
+    __syncthreads();
+    int32_t rb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rb[j] = tk.in_row[1] + ((j & 1) ? tk.in_inc[1][0] : 0) + ((j & 2) ? tk.in_inc[1][1] : 0);
+    float2 acc[32];
+#pragma unroll
+    for (int o = 0; o < 32; ++o) acc[o] = make_float2(0.f, 0.f);
+#pragma unroll 2
+    for (int w = 0; w < W; ++w) {
+        int32_t ob = 0;
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if ((w >> c) & 1) ob += tk.in_vs[1][c];
+        float2 Bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bv[j] = base_b[int64_t(uint32_t(rb[j] + ob)) << sh_b];
+        const float2 q = sA[8 * W + w][lane];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float2 qa = cmulf(q, sA[(i << K) + w][lane]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 l = Bv[j];
+                float2& c = acc[(i & 3) | ((j & 1) << 2) | ((i & 4) << 1) | ((j & 2) << 3)];
+                c.x = fmaf(qa.x, l.x, c.x);
+                c.x = fmaf(-qa.y, l.y, c.x);
+                c.y = fmaf(qa.x, l.y, c.y);
+                c.y = fmaf(qa.y, l.x, c.y);
+            }
+        }
+    }
+    float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b;
+#pragma unroll
+    for (int o = 0; o < 32; ++o) {
+        if constexpr (NT) {
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            const f2v v2 = {acc[o].x, acc[o].y};
+            __builtin_nontemporal_store(v2, reinterpret_cast<f2v*>(out + int64_t(o) * be));
+        } else {
+            out[int64_t(o) * be] = acc[o];
+        }
+    }
+    __syncthreads();   // the next block overwrites the LDS rows
+}
+
+// The quad tiles of one level: block (task block tb, group bg) runs tasks
+// 4 tb .. 4 tb + 3 on the work-group's 4 waves.  With at least 8 groups the
+// blocks are dealt by accelerator complex as in k_tree_level.  Every wave of a
+// work-group runs the same blocks (the barriers inside a block are reached by
+// all of them); the four tasks of a block have the same K.
+template <bool NT>
+__global__ void __launch_bounds__(256) k_tree_quad(const TreeTask* __restrict__ tasks, uint32_t n_tb,
+                                                   const float2* __restrict__ ain, float2* __restrict__ aout,
+                                                   const float2* __restrict__ gtab, int64_t ones_g,
+                                                   const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                   uint32_t n_bg, int pin) {
+    __shared__ float2 sA[kQuadRows][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t be = int64_t(B_eff);
+    auto block = [&](uint32_t tb, uint32_t bg) {
+        const uint32_t b = bg * 64u + lane;
+        const uint64_t x = int64_t(b) < B ? bits[b] : 0ull;
+        const TreeTask tk = tasks[4u * tb + wave];
+        const int64_t sig = gather_sigma(x, tk.sig_q, tk.n_sig);
+        if (tk.k == 2) quad_unit<2, NT>(tk, ain, aout, gtab, ones_g, sig, x, b, be, lane, wave, sA);
+        else quad_unit<3, NT>(tk, ain, aout, gtab, ones_g, sig, x, b, be, lane, wave, sA);
+    };
+    if (pin) {
+        const uint32_t q = blockIdx.x % uint32_t(kPersistXcds);
+        const uint32_t nbx = (n_bg - q + kPersistXcds - 1) / kPersistXcds;   // groups q, q + 8, ... (n_bg >= 8)
+        const uint32_t n_q = n_tb * nbx;
+        const uint32_t stride = gridDim.x / kPersistXcds;
+        for (uint32_t v = blockIdx.x / kPersistXcds; v < n_q; v += stride) {
+            const uint32_t tb = v / nbx;
+            block(tb, q + kPersistXcds * (v - tb * nbx));
+        }
+        return;
+    }
+    for (uint32_t v = blockIdx.x; v < n_tb * n_bg; v += gridDim.x) {
+        const uint32_t tb = v / n_bg;
+        block(tb, v - tb * n_bg);
+    }
+}
+
 // Phase of the factors without free variables for bitstring x (FP64), from
 // values staged in LDS by stage_phase.
 struct PhaseLds {
@@ -1012,9 +1142,28 @@ static void launch_level_n(hipStream_t stream, const TreeTask* tasks, int64_t n_
 
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
-                       uint32_t n_groups, hipStream_t stream) {
+                       uint32_t n_groups, hipStream_t stream, int32_t n_quad) {
     const uint32_t n_bg = n_groups;
     if (n_tasks <= 0 || n_bg == 0) return;
+    if (n_quad > 0) {   // the level's quad tiles first, then the rest of its tasks
+        const bool nt = int64_t(n_quad) * 32 * int64_t(B_eff) * int64_t(sizeof(float2)) > kQuadStreamBytes;
+        const int64_t per = std::max<int64_t>(1, (int64_t(1) << 31) / int64_t(n_bg));   // blocks per launch
+        for (int64_t tb0 = 0; tb0 < n_quad / 4; tb0 += per) {
+            const int64_t ntb = std::min<int64_t>(per, n_quad / 4 - tb0);
+            const int pin = n_bg >= uint32_t(kPersistXcds) ? 1 : 0;
+            uint32_t grid = uint32_t(std::min<int64_t>(ntb * int64_t(n_bg), kStepMaxGrid));
+            if (pin) grid = std::max<uint32_t>(grid / kPersistXcds, 1) * kPersistXcds;
+            if (nt)
+                hipLaunchKernelGGL(k_tree_quad<true>, dim3(grid), dim3(256), 0, stream, tasks + 4 * tb0, uint32_t(ntb),
+                                   ain, aout, gtab, ones_g, bits, B, B_eff, n_bg, pin);
+            else
+                hipLaunchKernelGGL(k_tree_quad<false>, dim3(grid), dim3(256), 0, stream, tasks + 4 * tb0,
+                                   uint32_t(ntb), ain, aout, gtab, ones_g, bits, B, B_eff, n_bg, pin);
+        }
+        tasks += n_quad;
+        n_tasks -= n_quad;
+        if (n_tasks <= 0) return;
+    }
     switch (launch_inputs(nin)) {
         case 1: launch_level_n<1>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;
         case 2: launch_level_n<2>(stream, tasks, n_tasks, ain, aout, gtab, ones_g, bits, B, B_eff, n_bg); break;

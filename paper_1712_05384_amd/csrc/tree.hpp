@@ -145,6 +145,10 @@ struct TreeStep {
                                         //   table row per summed value (0: the general unit); 3 or 4: the
                                         //   32-row tile, unit bits 0, 1, 3 varying input 0 only and 2, 4
                                         //   input 1 only, from 8 + 4 (+ 1) rows and 1 entry per value
+    bool quad = false;                  // a two-input 32-row tile whose result bits 5 and 6 vary input 1
+                                        //   only: tasks 4m .. 4m + 3 read the same rows of input 0 and of
+                                        //   the factor table, and run as one work-group that loads those
+                                        //   once into LDS (level_quad)
     int64_t n_tasks() const {
         const int64_t rows = int64_t(1) << out_axes.size();
         return rows <= unit_rows ? 1 : rows / unit_rows;
@@ -264,6 +268,8 @@ struct TreePlan {
     std::vector<std::vector<int>> levels;        // step ids per level
     std::vector<int64_t> level_task_off;         // wave tasks of level L: [off[L], off[L + 1])
     std::vector<int> level_max_in;               // most inputs of a bucket in level L
+    std::vector<int64_t> level_quad;             // the first level_quad[L] tasks of level L are quad tiles
+                                                 //   (a multiple of 4, bucket by bucket)
     int64_t n_tasks = 0;
     // adjoint (qgm_backward): every result at its own rows, and per level the
     // scratch rows of the expansion (H and one Q per input for each bucket)

@@ -748,7 +748,10 @@ static std::string tree_json(const Plan& p, int detail) {
       << ",\"chain_merge\":" << (p.opts.no_chain_merge ? 0 : 1) << ",\"n_tasks\":" << t.n_tasks
       << ",\"absorbed_buckets\":" << t.n_absorbed << ",\"tail_levels\":" << (int(t.levels.size()) - t.tail_start)
       << ",\"first_level\":" << t.first_level << ",\"tail_start\":" << t.tail_start << ",\"tail_lds_rows\":" << t.tail_lds_rows
-      << ",\"level_launches\":" << tree_launches(t)
+      << ",\"level_launches\":" << tree_launches(t) << ",\"kernel_launches\":" << tree_kernel_launches(t)
+      << ",\"level_quad\":[";
+    for (size_t L = 0; L < t.level_quad.size(); ++L) o << (L ? "," : "") << t.level_quad[L];
+    o << "]"
       << ",\"n_cz\":" << p.n_cz << ",\"n_diag_1q\":" << p.n_diag_gates << ",\"n_nondiag_1q\":" << p.n_nondiag_gates << ",\"n_2q\":" << p.n_2q
       << ",\"g_entries\":" << t.g_total << ",\"arena_rows\":" << t.arena_rows
       << ",\"orders_tried\":" << t.n_candidates << ",\"orders_built\":" << t.n_built << ",\"order_score\":" << t.order_score << ",\"bytes_per_amp\":" << t.bytes_per_b * sl_mult
@@ -774,7 +777,7 @@ static std::string tree_json(const Plan& p, int detail) {
         o << ",\"kg\":" << st.kg << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
-          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows << ",\"tile\":" << st.tile
+          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows << ",\"tile\":" << st.tile << ",\"quad\":" << (st.quad ? 1 : 0)
           << ",\"table_leaf\":" << (st.table_leaf ? 1 : 0) << ",\"leaf_off\":" << st.leaf_off
           << ",\"issued_bytes_per_b\":" << 8 * st.n_tasks() * tree_unit_accesses(t, st);
         if (detail >= 1) {

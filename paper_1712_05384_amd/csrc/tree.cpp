@@ -1097,4 +1097,13 @@ int tree_launches(const TreePlan& t) {
     return std::max(t.tail_start - t.first_level, 0) + (t.tail_start < int(t.levels.size()) ? 1 : 0);
 }
 
+int tree_kernel_launches(const TreePlan& t) {
+    int n = t.tail_start < int(t.levels.size()) ? 1 : 0;
+    for (int L = t.first_level; L < t.tail_start; ++L) {   // a level with quad tiles and other tasks: two launches
+        const int64_t nq = L < int(t.level_quad.size()) ? t.level_quad[size_t(L)] : 0;
+        n += (nq > 0 ? 1 : 0) + (t.level_task_off[size_t(L) + 1] - t.level_task_off[size_t(L)] > nq ? 1 : 0);
+    }
+    return n;
+}
+
 }  // namespace qgm

@@ -332,7 +332,8 @@ int64_t tree_unit_accesses(const TreePlan& t, const TreeStep& st);
 // Bytes the bucket kernels issue per bitstring (cache-served repeats included).
 double tree_issued_bytes_per_b(const TreePlan& t);
 // Kernel launches of one call: one per level before the tail, and the tail.
-int tree_launches(const TreePlan& t);
+int tree_launches(const TreePlan& t);          // levels before the tail, plus the tail (the order score)
+int tree_kernel_launches(const TreePlan& t);   // the same, a level with quad tiles and other tasks counted twice
 
 // Per-bucket algorithmic bytes per batch entry: inputs read once, result written once.
 double tree_step_bytes(const TreePlan& t, const TreeStep& st);

@@ -521,6 +521,35 @@ def test_tile_buckets_planned_and_interpreted():
         assert np.abs(got - ref).max() < 1e-12
 
 
+def test_quad_tiles_planned():
+    """Two-input 32-row tiles with two more bits carried by input B alone take
+    them as result bits 5 and 6 (quad tiles: tasks 4m .. 4m + 3 read the same
+    rows of A and the same table entries); a level's quad tasks come first, a
+    multiple of 4, and a level with quad and other tasks is two launches."""
+    import paper_1712_05384_amd as Q
+    c, _ = C.workload("c5_6x7_d27")
+    info = Q.plan(c, ordering=1, tree_exec=1).info(1)
+    tensors, bks = info["tensors"], info["buckets"]
+    quads = [bk for bk in bks if bk["quad"]]
+    assert len(quads) >= 4 and {bk["level"] for bk in quads} >= {6}
+    for bk in quads:
+        ins, out = bk["in_tensors"], bk["out_axes"]
+        assert bk["tile"] == 3 and bk["n_in"] == 2 and bk["r_out"] >= 10
+        for u in out[5:7]:
+            assert u in tensors[ins[1]]["axes"] and u not in tensors[ins[0]]["axes"] and u not in bk["gvars"]
+    mixed = 0
+    for L, nq in enumerate(info["level_quad"]):
+        inl = [bk for bk in bks if bk["level"] == L and not bk["table_leaf"]]
+        want = sum(1 << (bk["r_out"] - 5) for bk in inl if bk["quad"])
+        assert nq == want and nq % 4 == 0
+        if nq and any(not bk["quad"] for bk in inl):
+            mixed += 1
+    assert mixed >= 1 and info["kernel_launches"] == info["level_launches"] + mixed
+    # no quad tile where the second input has fewer than four bits alone: the 5x5 depth-25 plan has none
+    c2, _ = C.workload("c2_5x5_d25")
+    assert not any(bk["quad"] for bk in Q.plan(c2, ordering=1, tree_exec=1).info(1)["buckets"])
+
+
 def test_tile_in_tail_and_option_validation():
     """4x4 depth 16, the first order's plan: a tile bucket runs in the tail (tile
     units reading and writing the tail's LDS); an invalid no_tile value is rejected."""

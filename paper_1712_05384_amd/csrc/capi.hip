@@ -49,7 +49,8 @@ struct qgm_plan_s {
     size_t off_tfdep = 0;   // (first task, count) of the bucket making each rank-0 result
     size_t off_tleaf = 0;   // leaf-table records (plans without gate values)
     struct LevelItems { int off = 0, n = 0; int64_t rows = 0; };
-    std::vector<LevelItems> lv_exp, lv_g;
+    std::vector<LevelItems> lv_exp;
+    LevelItems g_all;   // every bucket's table adjoint rows, one launch after the adjoint sweep
     std::vector<std::vector<LevelItems>> lv_red;   // per level: the stages of its staged sums
     std::vector<qgm::TreeBwdIn> red_recs;
     int64_t part_rows[2] = {0, 0};                 // rows of the two partial-sum areas
@@ -147,7 +148,7 @@ void layout_tree_tables(qgm_plan_t* P) {
     P->part_rows[0] = P->part_rows[1] = 0;
     P->lv_exp.assign(t.levels.size(), {});
     P->lv_red.assign(t.levels.size(), {});
-    P->lv_g.assign(t.levels.size(), {});
+    P->g_all = {};
     auto add = [&](qgm_plan_s::LevelItems& li, int idx, int64_t rows) {
         if (li.n == 0) li.off = int(P->items.size());
         P->items.push_back({idx, int32_t(li.rows)});
@@ -234,11 +235,12 @@ void layout_tree_tables(qgm_plan_t* P) {
             P->part_rows[stage % 2] = std::max(P->part_rows[stage % 2], prow);
             sums.swap(next);
         }
+    }
+    for (size_t L = 0; L < t.levels.size(); ++L)
         for (int sid : t.levels[L]) {
             const qgm::TreeStep& st = t.steps[sid];
-            add(P->lv_g[L], sid, int64_t(1) << (st.gb() + st.kg));
+            add(P->g_all, sid, int64_t(1) << (st.gb() + st.kg));
         }
-    }
     // gate-slot occurrences among the table factors and the phase factors
     {
         std::vector<std::vector<int32_t>> occ(std::max(P->p.n_slots, 0));
@@ -1183,7 +1185,6 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
     const auto* bgd = reinterpret_cast<const qgm::TreeBwdG*>(tables + plan->off_tbwdg);
     for (int Lv = int(t.levels.size()) - 1; Lv >= t.first_level; --Lv) {
         const auto& ex = plan->lv_exp[Lv];
-        const auto& gg = plan->lv_g[Lv];
         qgm::launch_tb_expand(items + ex.off, ex.n, ex.rows, bwd, arena, adj, gt, scratch, bits, B, be,
                               p.n_slots > 0, s);
         for (size_t k = 0; k < plan->lv_red[Lv].size(); ++k) {
@@ -1191,9 +1192,10 @@ static qgm_status tree_backward(qgm_plan_t* plan, const void* gate_vals, const u
             const float2* src = k == 0 ? scratch : part[(k - 1) % 2];
             qgm::launch_tb_reduce(items + rs.off, rs.n, rs.rows, bin, src, adj, hsum, part[k % 2], be, s);
         }
-        if (p.n_slots > 0) qgm::launch_tb_gbin(items + gg.off, gg.n, gg.rows, bgd, hsum, bits, B, be, gbar, s);
     }
     if (p.n_slots > 0) {
+        const auto& gg = plan->g_all;
+        qgm::launch_tb_gbin(items + gg.off, gg.n, gg.rows, bgd, hsum, bits, B, be, gbar, s);
         qgm::launch_tb_gadj(pro, plan->n_pro_blocks, gtabs, groups, facs, fixed, slots, gbar, part_off, fpart, s);
         qgm::launch_tb_fsum(part_off, plan->n_fbar, fpart, fbar, s);
         qgm::launch_tb_slots(reinterpret_cast<const int32_t*>(tables + plan->off_tslot_off),

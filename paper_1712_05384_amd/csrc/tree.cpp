@@ -1034,18 +1034,17 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
     t.scratch_row.assign(t.steps.size(), 0);
     t.hsum_row.assign(t.steps.size(), 0);
     t.scratch_rows = 0;
-    t.hsum_rows = 0;
+    t.hsum_rows = 0;   // every bucket keeps its own rows of H sums: the table adjoints are taken after the sweep
     for (auto& lvl : t.levels) {
-        int64_t rows = 0, hrows = 0;
+        int64_t rows = 0;
         for (int sid : lvl) {
             const TreeStep& st = t.steps[sid];
             t.scratch_row[sid] = rows;
             rows += int64_t(st.in_tensors.size() + 1) << (st.out_axes.size() + st.vars.size());
-            t.hsum_row[sid] = hrows;
-            hrows += int64_t(1) << (st.gb() + st.kg);
+            t.hsum_row[sid] = t.hsum_rows;
+            t.hsum_rows += int64_t(1) << (st.gb() + st.kg);
         }
         t.scratch_rows = std::max(t.scratch_rows, rows);
-        t.hsum_rows = std::max(t.hsum_rows, hrows);
     }
     for (auto& st : t.steps)
         if (st.groups.size() > 16) { *err = "internal: more than 16 factor groups"; return QGM_E_INTERNAL; }

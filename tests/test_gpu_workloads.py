@@ -44,6 +44,28 @@ def test_c3_sliced_against_stored_oracle():
     assert np.abs(got0 - got).max() <= TOL * 2 ** (-c.n / 2)
 
 
+@pytest.mark.parametrize("B,chunked", [(100, False), (1024, False), (1024, True)])
+def test_c3_bucket_quad_tiles_against_stored_oracle(B, chunked):
+    """5x6 depth 30 on the bucket path (level launches), whose three two-input
+    32-row tile buckets run as quad tiles (four tasks per work-group sharing
+    one input's rows through LDS): a ragged batch of 100 (2 groups of 64, one
+    work-group per block of tasks), the full 1024 (8 and more groups, blocks
+    dealt by accelerator complex), and the full batch with 2 sliced variables
+    as batch columns; against the stored FP64 state-vector amplitudes."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c3_5x6_d30")
+    ref = np.load(os.path.join(GOLDEN, "c3_5x6_d30_amps.npy"), allow_pickle=False)[:B]
+    _say("case c3 5x6 d30 ordering 1 level launches B=%d sliced=%d" % (B, 2 if chunked else 0))
+    kw = dict(min_sliced_vars=2) if chunked else {}
+    p = Q.plan(c, ordering=1, tree_exec=1, out_c128=True, **kw)
+    info = p.info(1)
+    assert sum(bk["quad"] for bk in info["buckets"]) >= 3 and sum(info["level_quad"]) > 0
+    got = p.amplitudes(bits[:B]).cpu().numpy()[:, 0]
+    err = np.abs(got - ref).max() * 2 ** (c.n / 2)
+    _say("  max err * 2^(n/2) = %.3g" % err)
+    assert err <= TOL
+
+
 BF16X3_TOL = 1e-4   # BF16x3 split precision, max |A - A_oracle| * 2^(n/2); frozen from the 5x6 depth-30 run (2.7e-5)
 
 

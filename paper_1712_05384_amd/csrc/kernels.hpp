@@ -170,7 +170,7 @@ constexpr int kTbSumBits = 5;
 // Factor adjoints are summed without atomics: every table block (and each of
 // the kTbPhaseBlocks blocks of the phase factors) writes its partial sums per
 // factor, then one pass adds them in order.
-constexpr uint32_t kTbGadjParts = 8;     // blocks per table-entry block of the factor adjoints (slot factors split)
+constexpr uint32_t kTbGadjParts = 32;     // blocks per table-entry block of the factor adjoints (slot factors split)
 constexpr uint32_t kTbPhaseBlocks = 64;  // blocks summing the phase factors' adjoints over the bitstrings
 struct TreeBwdIn {
     int32_t r_t, n_sum;                         // output index bits; summed bits (at most kTbSumBits)

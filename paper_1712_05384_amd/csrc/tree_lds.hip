@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
     const int n_e = a.n_entries;
     uint32_t en[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) en[i] = a.zent[min(i * NT + int(tid), max(n_e - 1, 0))];
+    for (int i = 0; i < R; ++i) en[i] = a.zent[uint32_t(min(i * NT + int(tid), max(n_e - 1, 0)))];
     const int n_rw = RL ? a.n_jobs * (kLdsRecordBytes / 16) : 0;
     const uint4* __restrict__ rsrc = reinterpret_cast<const uint4*>(a.recs);
     uint4* rdst = reinterpret_cast<uint4*>(L + kLdsHeader + 8 * a.recs0);
@@ -258,11 +258,13 @@ __global__ void __launch_bounds__(NT) k_tree_lds(const LdsArgs a) {
         for (int i = 0; i < R; ++i) sg[i] = sig[en[i] >> 24];
         float2 v[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = a.ztab[int64_t(en[i] & 0xFFFFFFu) + sg[i]];
+        for (int i = 0; i < R; ++i)   // staged index < 2^24: a 32-bit byte offset from the copy's base
+            v[i] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.ztab) +
+                                                    (((en[i] & 0xFFFFFFu) + sg[i]) << 3));
         const int e1 = e0 + R * NT;
         if (e1 < n_e) {
 #pragma unroll
-            for (int i = 0; i < R; ++i) en[i] = a.zent[min(e1 + i * NT + int(tid), n_e - 1)];
+            for (int i = 0; i < R; ++i) en[i] = a.zent[uint32_t(min(e1 + i * NT + int(tid), n_e - 1))];
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {

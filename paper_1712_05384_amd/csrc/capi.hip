@@ -1029,7 +1029,7 @@ static qgm_status amplitudes_impl(qgm_plan_t* plan, const void* gate_vals, const
                 const int64_t t0 = t.level_task_off[L], t1 = t.level_task_off[L + 1];
                 qgm::launch_tree_level(t.level_max_in[L], tasks + t0, int32_t(t1 - t0), arena, arena, gt, t.ones_g,
                                        cb, nb, uint32_t(be), uint32_t((nb + 63) / 64), s,
-                                       int32_t(t.level_quad[size_t(L)]));
+                                       int32_t(t.level_quad[size_t(L)]), t.level_quad_arena[size_t(L)] != 0);
             }
             const int n_tail = int(t.levels.size()) - t.tail_start;
             if (n_tail > 0) {

@@ -227,10 +227,11 @@ void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGT
                           int64_t ones_g, const TFactor* phase, int n_phase, int64_t phase_g, hipStream_t stream);
 // One level of a bucket plan for the first n_groups groups of 64 bitstrings;
 // B_eff is the arena's row pitch and must be a power of two.
-// n_quad: the first n_quad tasks (a multiple of 4) are quad tiles, run four to a work-group
+// n_quad: the first n_quad tasks (a multiple of 4) are quad tiles, run four to a work-group; quad_arena: both
+// inputs of each of those buckets are arena results (not leaf tables)
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
-                       uint32_t n_groups, hipStream_t stream, int32_t n_quad = 0);
+                       uint32_t n_groups, hipStream_t stream, int32_t n_quad = 0, bool quad_arena = false);
 void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFactor* phase, int n_phase,
                             const double2* fixed, const float2* slots, const float2* arena, int64_t open_row,
                             int n_open, uint32_t zero_mask, const uint64_t* bits, int64_t B, uint32_t B_eff,

@@ -932,6 +932,10 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
     t.level_task_off.assign(1, 0);
     t.level_max_in.clear();
     t.level_quad.clear();
+    t.level_quad_arena.clear();
+    std::vector<char> leaf_made(t.tensor_axes.size(), 0);   // results that are leaf tables
+    for (const TreeStep& st : t.steps)
+        if (st.table_leaf) leaf_made[size_t(st.out_tensor)] = 1;
     for (size_t L = 0; L < t.levels.size(); ++L) {
         int mi = 0;
         for (int sid : t.levels[L]) mi = std::max(mi, int(t.steps[sid].in_tensors.size()));
@@ -947,15 +951,21 @@ static qgm_status tree_from_order(const Plan& p, const Model& m, const std::vect
         // the quad tiles' tasks first (their launch takes blocks of four tasks)
         std::stable_partition(t.levels[L].begin(), t.levels[L].end(), [&](int sid) { return t.steps[sid].quad; });
         int64_t nq = 0;
+        char arena = 1;
         for (int sid : t.levels[L]) {
             TreeStep& st = t.steps[sid];
             st.task_off = t.n_tasks;
             t.n_tasks += st.n_tasks();
-            if (st.quad) nq += st.n_tasks();
+            if (st.quad) {
+                nq += st.n_tasks();
+                for (int tin : st.in_tensors)
+                    if (leaf_made[size_t(tin)]) arena = 0;
+            }
         }
         t.level_task_off.push_back(t.n_tasks);
         t.level_max_in.push_back(mi);
         t.level_quad.push_back(nq);
+        t.level_quad_arena.push_back(arena);
     }
     // tail: the longest run of last levels with few tasks and few inputs
     t.first_level = 0;

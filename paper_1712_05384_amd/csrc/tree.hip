@@ -601,6 +601,159 @@ __device__ __forceinline__ void quad_unit(const TreeTask& tk, const float2* __re
     __syncthreads();   // the next block overwrites the LDS rows
 }
 
+// Quad tiles with two bitstrings per lane (batch pitch of 128 or more): a
+// work-group of 8 waves runs the 4 tasks of a block for 128 consecutive
+// bitstrings; wave (t, h) computes the 16 rows of task t whose unit bit 3
+// (A's third bit) is h, for bitstrings 2l and 2l + 1 of lane l.  Every row
+// load and store then moves 16 bytes per lane: the address path of the
+// vector memory unit takes about the same time per instruction for 16 bytes
+// as for 8, so a row costs half the instructions of the one-bitstring form.
+// The rows of A and the table entries shared by the 4 tasks are staged in
+// LDS, 4 summed values at a time.  Same products in the same order as
+// tile32_unit and quad_unit, per bitstring.
+struct Q2Lds {
+    float4 a[8 * 4][64];    // row i of A at summed value w0 + c: [i * 4 + c][lane], bitstrings 2l, 2l + 1
+    float2 q[4][128];       // table entry at summed value w0 + c for bitstring column j
+};
+
+// Two consecutive bitstrings' entries of an arena input at row `row`: one 16-byte load.
+__device__ __forceinline__ float4 q2_load(int32_t row, const float2* __restrict__ ain, uint32_t b0, uint32_t be_sh) {
+    return *reinterpret_cast<const float4*>(ain + ((int64_t(uint32_t(row)) << be_sh) + b0));
+}
+
+template <int K>
+__device__ __forceinline__ void quad2_unit(const TreeTask& tk, const float2* __restrict__ ain,
+                                           float2* __restrict__ aout, const float2* __restrict__ gtab,
+                                           const uint64_t* __restrict__ bits, int64_t B, uint32_t c0, int64_t be,
+                                           uint32_t lane, uint32_t wave, Q2Lds& S) {
+    constexpr int W = 1 << K;
+    constexpr int CW = W < 4 ? W : 4;   // summed values staged at a time
+    const uint32_t be_sh = uint32_t(__builtin_ctzll(uint64_t(be)));
+    const uint32_t tid = wave * 64u + lane;
+    const uint32_t h = wave >> 2;
+    const uint32_t b0 = c0 + 2u * lane;
+    const uint64_t x0 = int64_t(b0) < B ? bits[b0] : 0ull, x1 = int64_t(b0) + 1 < B ? bits[b0 + 1] : 0ull;
+    // the table column this thread stages, and its bitstring's output bits
+    const uint32_t jc = tid & 127u;
+    const uint64_t xc = int64_t(c0 + jc) < B ? bits[c0 + jc] : 0ull;
+    const int64_t sig_c = gather_sigma(xc, tk.sig_q, tk.n_sig);
+    int32_t rb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rb[j] = tk.in_row[1] + ((j & 1) ? tk.in_inc[1][0] : 0) + ((j & 2) ? tk.in_inc[1][1] : 0);
+    float2 acc[16][2];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) acc[o][0] = acc[o][1] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w0 = 0; w0 < W; w0 += CW) {
+        // stage rows i of A at values w0 .. w0 + CW - 1 (wave takes rows r = wave + 8 s) and the table entries
+        constexpr int PER = 8 * CW / 8;
+        float4 v[PER];
+#pragma unroll
+        for (int s2 = 0; s2 < PER; ++s2) {
+            const int r = int(wave) + 8 * s2;
+            const int i = r / CW, w = w0 + r % CW;
+            int32_t ra = tk.in_row[0] + ((i & 1) ? tk.in_inc[0][0] : 0) + ((i & 2) ? tk.in_inc[0][1] : 0) +
+                         ((i & 4) ? tk.in_inc[0][2] : 0);
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if ((w >> c) & 1) ra += tk.in_vs[0][c];
+            v[s2] = q2_load(ra, ain, b0, be_sh);
+        }
+        float2 qv[CW * 128 / 512 > 0 ? CW * 128 / 512 : 1];
+        constexpr int QPER = CW * 128 / 512;   // table entries per thread (1 for CW = 4)
+#pragma unroll
+        for (int s2 = 0; s2 < QPER; ++s2) {
+            const int w = w0 + int(tid >> 7) + 4 * s2;
+            qv[s2] = gtab[tk.g_ent + (int64_t(w) << tk.sb) + sig_c];
+        }
+        if (QPER == 0 && tid < uint32_t(CW) * 128u) qv[0] = gtab[tk.g_ent + (int64_t(w0 + int(tid >> 7)) << tk.sb) + sig_c];
+#pragma unroll
+        for (int s2 = 0; s2 < PER; ++s2) S.a[int(wave) + 8 * s2][lane] = v[s2];
+#pragma unroll
+        for (int s2 = 0; s2 < QPER; ++s2) S.q[int(tid >> 7) + 4 * s2][jc] = qv[s2];
+        if (QPER == 0 && tid < uint32_t(CW) * 128u) S.q[tid >> 7][jc] = qv[0];
+        __syncthreads();
+#pragma unroll 1   // (unrolled, 153 VGPRs and 3 waves per SIMD: one work-group per compute unit)
+        for (int c = 0; c < CW; ++c) {
+            const int w = w0 + c;
+            int32_t ob = 0;
+#pragma unroll
+            for (int cc = 0; cc < K; ++cc)
+                if ((w >> cc) & 1) ob += tk.in_vs[1][cc];
+            float4 Bv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Bv[j] = q2_load(rb[j] + ob, ain, b0, be_sh);
+            const float4 q = reinterpret_cast<const float4*>(S.q[c])[lane];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+                const int i = ii | int(h << 2);
+                const float4 A = S.a[i * CW + c][lane];
+                const float2 qa0 = cmulf(make_float2(q.x, q.y), make_float2(A.x, A.y));
+                const float2 qa1 = cmulf(make_float2(q.z, q.w), make_float2(A.z, A.w));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float2& a0 = acc[ii | ((j & 1) << 2) | ((j & 2) << 2)][0];
+                    float2& a1 = acc[ii | ((j & 1) << 2) | ((j & 2) << 2)][1];
+                    a0.x = fmaf(qa0.x, Bv[j].x, a0.x);
+                    a0.x = fmaf(-qa0.y, Bv[j].y, a0.x);
+                    a0.y = fmaf(qa0.x, Bv[j].y, a0.y);
+                    a0.y = fmaf(qa0.y, Bv[j].x, a0.y);
+                    a1.x = fmaf(qa1.x, Bv[j].z, a1.x);
+                    a1.x = fmaf(-qa1.y, Bv[j].w, a1.x);
+                    a1.y = fmaf(qa1.x, Bv[j].w, a1.y);
+                    a1.y = fmaf(qa1.y, Bv[j].z, a1.y);
+                }
+            }
+        }
+        __syncthreads();   // the next values (or the next block) overwrite the staged rows
+    }
+    // local row o = ii | j0 << 2 | j1 << 3 is unit row ii | j0 << 2 | h << 3 | j1 << 4
+    float2* __restrict__ out = aout + int64_t(tk.out_row) * be + b0;
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        const int u = (o & 7) | int(h << 3) | ((o & 8) << 1);
+        float4* dst = reinterpret_cast<float4*>(out + int64_t(u) * be);
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        const f4v r4 = {acc[o][0].x, acc[o][0].y, acc[o][1].x, acc[o][1].y};
+        __builtin_nontemporal_store(r4, reinterpret_cast<f4v*>(dst));
+    }
+}
+
+// The quad tiles of one level with two bitstrings per lane (levels whose results exceed the last-level cache,
+// both inputs of every quad bucket arena results; stores non-temporal): block (task block tb, column group
+// g2) runs tasks 4 tb .. 4 tb + 3 for bitstring columns 128 g2 .. 128 g2 + 127 on the work-group's 8 waves.
+// With at least 8 column groups the blocks are dealt by accelerator complex.  Every wave runs the same blocks.
+__global__ void __launch_bounds__(512) k_tree_quad2(const TreeTask* __restrict__ tasks, uint32_t n_tb,
+                                                    const float2* __restrict__ ain, float2* __restrict__ aout,
+                                                    const float2* __restrict__ gtab,
+                                                    const uint64_t* __restrict__ bits, int64_t B, uint32_t B_eff,
+                                                    uint32_t n_g2, int pin) {
+    __shared__ Q2Lds S;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t be = int64_t(B_eff);
+    auto block = [&](uint32_t tb, uint32_t g2) {
+        const TreeTask tk = tasks[4u * tb + (wave & 3u)];   // (the 4 tasks of a block have the same K)
+        if (tk.k == 2) quad2_unit<2>(tk, ain, aout, gtab, bits, B, g2 * 128u, be, lane, wave, S);
+        else quad2_unit<3>(tk, ain, aout, gtab, bits, B, g2 * 128u, be, lane, wave, S);
+    };
+    if (pin) {
+        const uint32_t q = blockIdx.x % uint32_t(kPersistXcds);
+        const uint32_t nbx = (n_g2 - q + kPersistXcds - 1) / kPersistXcds;   // column groups q, q + 8, ...
+        const uint32_t n_q = n_tb * nbx;
+        const uint32_t stride = gridDim.x / kPersistXcds;
+        for (uint32_t v = blockIdx.x / kPersistXcds; v < n_q; v += stride) {
+            const uint32_t tb = v / nbx;
+            block(tb, q + kPersistXcds * (v - tb * nbx));
+        }
+        return;
+    }
+    for (uint32_t v = blockIdx.x; v < n_tb * n_g2; v += gridDim.x) {
+        const uint32_t tb = v / n_g2;
+        block(tb, v - tb * n_g2);
+    }
+}
+
 // The quad tiles of one level: block (task block tb, group bg) runs tasks
 // 4 tb .. 4 tb + 3 on the work-group's 4 waves.  With at least 8 groups the
 // blocks are dealt by accelerator complex as in k_tree_level.  Every wave of a
@@ -1142,11 +1295,31 @@ static void launch_level_n(hipStream_t stream, const TreeTask* tasks, int64_t n_
 
 void launch_tree_level(int nin, const TreeTask* tasks, int32_t n_tasks, const float2* ain, float2* aout,
                        const float2* gtab, int64_t ones_g, const uint64_t* bits, int64_t B, uint32_t B_eff,
-                       uint32_t n_groups, hipStream_t stream, int32_t n_quad) {
+                       uint32_t n_groups, hipStream_t stream, int32_t n_quad, bool quad_arena) {
     const uint32_t n_bg = n_groups;
     if (n_tasks <= 0 || n_bg == 0) return;
-    if (n_quad > 0) {   // the level's quad tiles first, then the rest of its tasks
-        const bool nt = int64_t(n_quad) * 32 * int64_t(B_eff) * int64_t(sizeof(float2)) > kQuadStreamBytes;
+    // the level's quad tiles first, then its other tasks; results beyond the last-level cache: two bitstrings
+    // per lane (half the load and store instructions; a smaller level runs faster with twice the work-groups)
+    // and non-temporal stores
+    const bool big = int64_t(n_quad) * 32 * int64_t(B_eff) * int64_t(sizeof(float2)) > kQuadStreamBytes;
+    if (n_quad > 0 && B_eff >= 128 && big && quad_arena) {
+        const uint32_t n_g2 = (n_bg + 1) / 2;   // column groups of 128 (within the pitch, a power of two >= 128)
+        const int64_t per = std::max<int64_t>(1, (int64_t(1) << 31) / int64_t(n_g2));
+        for (int64_t tb0 = 0; tb0 < n_quad / 4; tb0 += per) {
+            const int64_t ntb = std::min<int64_t>(per, n_quad / 4 - tb0);
+            const int pin = n_g2 >= uint32_t(kPersistXcds) ? 1 : 0;
+            uint32_t grid = uint32_t(std::min<int64_t>(ntb * int64_t(n_g2), kStepMaxGrid));
+            if (pin) grid = std::max<uint32_t>(grid / kPersistXcds, 1) * kPersistXcds;
+            hipLaunchKernelGGL(k_tree_quad2, dim3(grid), dim3(512), 0, stream, tasks + 4 * tb0, uint32_t(ntb), ain,
+                               aout, gtab, bits, B, B_eff, n_g2, pin);
+        }
+        tasks += n_quad;
+        n_tasks -= n_quad;
+        n_quad = 0;
+        if (n_tasks <= 0) return;
+    }
+    if (n_quad > 0) {
+        const bool nt = big;
         const int64_t per = std::max<int64_t>(1, (int64_t(1) << 31) / int64_t(n_bg));   // blocks per launch
         for (int64_t tb0 = 0; tb0 < n_quad / 4; tb0 += per) {
             const int64_t ntb = std::min<int64_t>(per, n_quad / 4 - tb0);

@@ -270,6 +270,7 @@ struct TreePlan {
     std::vector<int> level_max_in;               // most inputs of a bucket in level L
     std::vector<int64_t> level_quad;             // the first level_quad[L] tasks of level L are quad tiles
                                                  //   (a multiple of 4, bucket by bucket)
+    std::vector<char> level_quad_arena;          // every quad bucket of level L reads two arena results
     int64_t n_tasks = 0;
     // adjoint (qgm_backward): every result at its own rows, and per level the
     // scratch rows of the expansion (H and one Q per input for each bucket)

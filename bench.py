@@ -43,7 +43,7 @@ MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
     ("c2_5x5_d25", 1): {"bytes_per_launch": 7001527.7, "source": "tree.hip", "sha256_16": "df4ff7611c3e3e50",
                         "plan": {"bytes_per_amp": 62088, "level_launches": 10}},
-    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 1038976.0, "source": "tree_lds.hip", "sha256_16": "ce761e455a210a92",
+    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 1018470.4, "source": "tree_lds.hip", "sha256_16": "0c738d1202637c3e",
                             "plan": {"lds_entries": 3812, "lds_jobs": 31, "lds_threads": 256}},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
@@ -52,8 +52,8 @@ METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; gr
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2_5x5_d25")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
@@ -161,7 +161,15 @@ def main() -> int:
     print(f"# {args.steps} graph replays: {graph_ms:.4f} ms/step, {B / (graph_ms / 1e3):.4g} amplitudes/s",
           file=sys.stderr, flush=True)
 
-    roofline, cfg = dominant_kernel(args, p, info, B, phases[2] / max(ncalls, 1), kernels, args.tree_exec)
+    # a call that is exactly one k_tree_lds launch (no gate values: the tables are the plan's): the timed
+    # region's time per call is that kernel's average launch duration on the launch stream; otherwise the
+    # elimination phase's own events
+    one_launch = (info["ordering"] == 1 and info.get("lds_ok") and args.tree_exec in (0, 3)
+                  and not info.get("n_open") and gv is None)
+    elim_ms = eager_ms if one_launch else phases[2] / max(ncalls, 1)
+    roofline, cfg = dominant_kernel(args, p, info, B, elim_ms, kernels, args.tree_exec)
+    roofline["launch_ms_from"] = ("the timed region (one launch per call)" if one_launch
+                                  else "HIP events around the elimination phase")
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),

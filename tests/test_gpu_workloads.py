@@ -66,6 +66,27 @@ def test_c3_bucket_quad_tiles_against_stored_oracle(B, chunked):
     assert err <= TOL
 
 
+def test_6x7_quad_tile_forms_agree_across_batches():
+    """6x7 depth 27 on the bucket path: its largest level runs the quad tiles
+    with two bitstrings per lane (results beyond the last-level cache) at a
+    pitch of 1024, including a batch of 900 (15 groups of 64: the last pair of
+    groups half past the batch), and with one bitstring per lane at a pitch
+    of 64.  Each bitstring's amplitude is the same bits whatever the batch (the
+    same products in the same order)."""
+    import paper_1712_05384_amd as Q
+    c, bits = C.workload("c5_6x7_d27")
+    p = Q.plan(c, ordering=1, tree_exec=1)
+    info = p.info(0)
+    assert max(info["level_quad"]) * 32 * 1024 * 8 > 256 << 20
+    _say("case 6x7 d27 ordering 1 B=1024, 900, 64")
+    full = p.amplitudes(bits).cpu().numpy()[:, 0]
+    assert np.isfinite(full).all()
+    for B in (900, 64):
+        part = p.amplitudes(bits[:B]).cpu().numpy()[:, 0]
+        _say("  B=%d: max |diff| = %.3g" % (B, np.abs(part - full[:B]).max()))
+        assert np.array_equal(part, full[:B])
+
+
 BF16X3_TOL = 1e-4   # BF16x3 split precision, max |A - A_oracle| * 2^(n/2); frozen from the 5x6 depth-30 run (2.7e-5)
 
 

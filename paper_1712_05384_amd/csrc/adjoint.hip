@@ -197,10 +197,26 @@ __global__ void __launch_bounds__(256) k_gbar_reduce(GbarParams gp, const float2
         for (uint32_t b = uint32_t(tid); b < B_eff; b += 256) {
             const uint32_t sg = uint32_t(vids[b]) - s0;
             if (sg >= 16u) continue;
+            // the row chunks' partials in order; 16 loads in flight before their adds (the order of the adds,
+            // and so the sums, as one at a time)
             double xr = 0.0, xi = 0.0;
-            for (uint32_t rc = 0; rc < uint32_t(gp.n_rc); ++rc) {
+            auto at = [&](uint32_t rc) {
                 const uint32_t unit = ((v * gp.n_rc + rc) * gp.n_kc + kc) * gp.n_nc + nc;
-                const float2 x = part[(size_t(unit) * 64 + ki * 8 + nj) * B_eff + b];
+                return part[(size_t(unit) * 64 + ki * 8 + nj) * B_eff + b];
+            };
+            uint32_t rc = 0;
+            for (; rc + 16 <= uint32_t(gp.n_rc); rc += 16) {
+                float2 x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = at(rc + uint32_t(u));
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    xr += double(x[u].x);
+                    xi += double(x[u].y);
+                }
+            }
+            for (; rc < uint32_t(gp.n_rc); ++rc) {
+                const float2 x = at(rc);
                 xr += double(x.x);
                 xi += double(x.y);
             }

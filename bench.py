@@ -43,7 +43,7 @@ MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
     ("c2_5x5_d25", 1): {"bytes_per_launch": 7001527.7, "source": "tree.hip", "sha256_16": "df4ff7611c3e3e50",
                         "plan": {"bytes_per_amp": 62088, "level_launches": 10}},
-    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 1018470.4, "source": "tree_lds.hip", "sha256_16": "0c738d1202637c3e",
+    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 1018470.4, "source": "tree_lds.hip", "sha256_16": "37b2ea1941df5ce9",
                             "plan": {"lds_entries": 3812, "lds_jobs": 31, "lds_threads": 256}},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"

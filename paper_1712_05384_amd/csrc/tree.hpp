@@ -161,8 +161,8 @@ struct TreeStep {
 // ---- LDS-resident execution (qgm_amplitudes, tree_exec 3) -------------------
 // One work-group per bitstring runs every level of the plan with its results
 // in LDS: the factor tables and leaf tables are first copied to LDS at the
-// bitstring's output bits, then each level's jobs (64 result rows of one
-// bucket, one row per lane) read inputs and table entries from LDS, with a
+// bitstring's output bits, then each level's jobs (64, 128 or 256 result rows
+// of one bucket, 1, 2 or 4 per lane) read inputs and table entries from LDS, with a
 // block barrier between levels, and thread 0 writes phase x the rank-0 results.
 // In LDS every tensor keeps its variables in decreasing order of elimination
 // (the last eliminated lowest) and a factor table is indexed (w << gb) | g, so

@@ -5,10 +5,13 @@
 // by lifetime, as the HBM arena of the level launches), and the factor tables
 // and leaf tables, which depend on the bitstring only through its output bits
 // (the deltas of Eq. (psi_x)), are copied to LDS at those bits before the first
-// level.  A job is 64 consecutive result rows of one bucket, one row per lane;
-// its record holds the LDS byte offset of each input row and table entry at
-// its first row and the offset strides of the six lane bits.  The records are
-// copied to LDS with the tables when they fit, so a job reads no memory.
+// level.  A job is 64, 128 or 256 consecutive result rows of one bucket (1, 2
+// or 4 rows per lane, chosen per level so that a level's jobs take one pass
+// of the waves where they can); its record holds, per input and for the
+// table, the lane offsets of its first row by three-bit groups of the lane
+// (two 16-bit loads and an add give a lane's offset) and the strides of
+// result bits 6 and 7.  The records are copied to LDS with the tables when
+// they fit, so a job reads no memory.
 //
 // Layout in LDS: a tensor's variables in decreasing order of elimination (the
 // variable eliminated last is axis 0), a factor table indexed (w << gb) | g

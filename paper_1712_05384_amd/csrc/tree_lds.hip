@@ -5,14 +5,14 @@
 // from HBM only the bitstring, the table entries at its output bits (the
 // deltas of Eq. (psi_x) select them) and its job records, and writes one
 // amplitude.  The waves share each level's jobs (64 result rows of one bucket,
-// one row per lane): lane l multiplies the factor-table entry of its row and
-// summed value w by its input rows, sums over w, and stores the row; a block
-// barrier separates levels, as a level reads only results of earlier levels.
-// A job record holds the LDS byte offsets at its first row and the strides of
-// the six lane bits (a bucket of 128 rows or more may take two or four rows
-// per lane, at the strides of result bits 6 and 7); the records are copied to LDS with the
-// tables when they fit, so after the first burst of loads the levels touch no
-// memory.
+// one row per lane, or 128 or 256 with two or four rows per lane): lane l
+// multiplies the factor-table entry of its row and summed value w by its
+// input rows, sums over w, and stores the row; a block barrier separates
+// levels, as a level reads only results of earlier levels.  A job record
+// holds the lane offsets of its first row (per input and for the table, two
+// 8-entry tables by three-bit groups of the lane) and the strides of result
+// bits 6 and 7; the records are copied to LDS with the tables when they fit,
+// so after the first burst of loads the levels touch no memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -184,6 +184,14 @@ typedef struct {
                                   frames fit, at most ceil(sqrt(steps)); QGM_E_OOM when even that does not
                                   fit.  Ordering 1 keeps every result for its adjoint: QGM_E_OOM when those
                                   exceed the budget */
+    int32_t no_compose;        /* ordering 1 only: 1 = only buckets without inputs become leaf tables; 0 = a
+                                  bucket whose inputs are all leaf tables, whose result bits plus the output
+                                  bits of its subtree are at most 15 (those output bits at most 10), becomes
+                                  a leaf table too: its result depends on the bitstring only through those
+                                  bits, so it is built once with the plan for all their values (Sec. V:
+                                  reuse across bitstrings) and read at each bitstring's bits.  Circuits
+                                  with gate values have no leaf tables */
+    int32_t reserved0;         /* 0 */
 } qgm_plan_opts;
 
 typedef enum { QGM_PREC_C64 = 0, QGM_PREC_BF16X3 = 1 } qgm_precision;

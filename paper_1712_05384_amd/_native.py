@@ -36,7 +36,8 @@ class QgmPlanOpts(ctypes.Structure):
                 ("tree_exec", ctypes.c_int32), ("no_tile", ctypes.c_int32),
                 ("order_finalists", ctypes.c_int32), ("order_restarts", ctypes.c_int32),
                 ("order_pick", ctypes.c_int32), ("persist_spin", ctypes.c_int32),
-                ("mem_budget", ctypes.c_uint64), ("checkpoint_budget", ctypes.c_uint64)]
+                ("mem_budget", ctypes.c_uint64), ("checkpoint_budget", ctypes.c_uint64),
+                ("no_compose", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 QGM_PREC_C64, QGM_PREC_BF16X3 = 0, 1
 
 

@@ -26,7 +26,7 @@ class Plan:
                  out_c128: bool = False, kernel_policy: int = 0, checkpoint_every: int = 0, ordering: int = 0,
                  chain_merge: bool = True, tree_exec: int = 0, tile: bool = True, order_finalists: int = 0,
                  order_restarts: int = 0, order_pick: int = 0, persist_spin: int = 0, precision: int = 0,
-                 mem_budget: int = 0, checkpoint_budget: int = 0):
+                 mem_budget: int = 0, checkpoint_budget: int = 0, compose: bool = True):
         L = N.lib()
         self._lib = L
         self._h = None
@@ -53,6 +53,7 @@ class Plan:
         opts.precision = int(precision)
         opts.mem_budget = int(mem_budget)
         opts.checkpoint_budget = int(checkpoint_budget)
+        opts.no_compose = 0 if compose else 1
         self.ordering = int(ordering)
         op = (ctypes.c_int32 * max(1, len(self.open_qubits)))(*self.open_qubits)
         h = ctypes.c_void_p()

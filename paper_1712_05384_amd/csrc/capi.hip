@@ -537,9 +537,43 @@ bool fill_tree_tables(const qgm_plan_t* P, char* h) {
     for (size_t i = 0; i < t.finals.size(); ++i) fr[i] = t.tensor_row[t.finals[i]];
     auto* lf = reinterpret_cast<qgm::TreeLeaf*>(h + P->off_tleaf);
     int n_lf = 0;
-    for (const qgm::TreeStep& st : t.steps)
-        if (st.table_leaf)
-            lf[n_lf++] = {st.g_off, st.leaf_off, int32_t(st.out_axes.size()), st.kg, st.sb(), 0};
+    {
+        std::vector<int> made_by(t.tensor_axes.size(), -1);
+        for (size_t i = 0; i < t.steps.size(); ++i) made_by[size_t(t.steps[i].out_tensor)] = int(i);
+        auto index_of = [](const std::vector<int>& v, int x) {
+            const auto it = std::find(v.begin(), v.end(), x);
+            return it == v.end() ? -1 : int(it - v.begin());
+        };
+        for (const qgm::TreeStep& st : t.steps) {
+            if (!st.table_leaf) continue;
+            qgm::TreeLeaf L{};
+            L.g_off = st.g_off;
+            L.leaf_off = st.leaf_off;
+            L.r = int32_t(st.out_axes.size());
+            L.k = st.kg;
+            L.sb = st.sb();
+            L.depth = st.leaf_depth;
+            if (st.composed) {
+                L.n_in = int32_t(st.in_tensors.size());
+                L.gb = st.gb();
+                for (int j = 0; j < st.gb(); ++j) L.gpos[j] = index_of(st.out_axes, st.gvars[size_t(j)]);
+                for (int k = 0; k < L.n_in; ++k) {
+                    const int ti = st.in_tensors[size_t(k)];
+                    const qgm::TreeStep& mk = t.steps[size_t(made_by[size_t(ti)])];
+                    const std::vector<int>& ax = t.tensor_axes[size_t(ti)];
+                    L.in_off[k] = mk.leaf_off;
+                    L.in_sb[k] = mk.sb();
+                    L.in_na[k] = int32_t(ax.size());
+                    for (size_t a = 0; a < ax.size(); ++a) {
+                        const int po = index_of(st.out_axes, ax[a]), pv = index_of(st.vars, ax[a]);
+                        L.in_src[k][a] = int8_t(po >= 0 ? po : 16 + pv);
+                    }
+                    for (int b = 0; b < mk.sb(); ++b) L.in_spos[k][b] = int8_t(index_of(st.sig_q, mk.sig_q[size_t(b)]));
+                }
+            }
+            lf[n_lf++] = L;
+        }
+    }
     const qgm::LdsProgram& lp = t.lds;
     if (lp.ok) {
         std::memcpy(h + P->off_lstage, lp.stages.data(), sizeof(qgm::LdsStage) * lp.stages.size());
@@ -678,11 +712,15 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
                                   reinterpret_cast<const qgm::TFactor*>(b + P->off_tphase),
                                   int(P->p.tree.phase.size()), P->p.tree.phase_g, nullptr);
         int64_t max_entries = 0;
+        int max_depth = 0;
         for (const qgm::TreeStep& st : P->p.tree.steps)
-            if (st.table_leaf) max_entries = std::max<int64_t>(max_entries, int64_t(1) << (st.out_axes.size() + st.sb()));
+            if (st.table_leaf) {
+                max_entries = std::max<int64_t>(max_entries, int64_t(1) << (st.out_axes.size() + st.sb()));
+                max_depth = std::max(max_depth, st.leaf_depth);
+            }
         qgm::launch_tree_leaf_tables(reinterpret_cast<const qgm::TreeLeaf*>(b + P->off_tleaf),
-                                     P->p.tree.n_table_leaves, max_entries, reinterpret_cast<float2*>(b + P->off_tg),
-                                     nullptr);
+                                     P->p.tree.n_table_leaves, max_entries, max_depth,
+                                     reinterpret_cast<float2*>(b + P->off_tg), nullptr);
         const qgm::LdsProgram& lp = P->p.tree.lds;
         if (lp.ok)
             qgm::launch_lds_stage(reinterpret_cast<const qgm::LdsStage*>(b + P->off_lstage), int(lp.stages.size()),

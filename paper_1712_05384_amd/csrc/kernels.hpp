@@ -79,9 +79,20 @@ struct TreeTask {
 static_assert(sizeof(TreeTask) % 16 == 0, "task records are copied in 16-byte words");
 
 // The leaf tables of a plan (built once): R[o][s] = sum_w G[((o << k) | w) << sb | s].
+// A leaf table built with the plan: entry (o << sb) | sigma = sum over the k summed values w of the factor
+// table's entry (((g << k) | w) << sb) | sigma, times, for a composed leaf (n_in > 0), each input leaf table t
+// at (o_t << in_sb[t]) | sigma_t: g bit j = o bit gpos[j]; input axis a = o bit in_src[t][a], or summed bit
+// in_src[t][a] - 16 when >= 16; sigma_t bit b = sigma bit in_spos[t][b].  A leaf without inputs has g = o.
+// Leaves of depth d read only leaves of smaller depth (one launch per depth).
 struct TreeLeaf {
     int64_t g_off, leaf_off;
-    int32_t r, k, sb, pad;
+    int32_t r, k, sb, n_in;
+    int32_t gb, depth;
+    int32_t gpos[16];
+    int64_t in_off[kTreeMaxIn];
+    int32_t in_sb[kTreeMaxIn], in_na[kTreeMaxIn];
+    int8_t in_src[kTreeMaxIn][16];
+    int8_t in_spos[kTreeMaxIn][16];
 };
 
 // One persistent launch of the bucket elimination (k_tree_persist): every
@@ -237,7 +248,7 @@ void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFacto
                             int n_open, uint32_t zero_mask, const uint64_t* bits, int64_t B, uint32_t B_eff,
                             void* out, bool c128, hipStream_t stream);
 hipError_t launch_tree_persist(const TreePersist& a, hipStream_t stream);
-void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_entries, float2* gtab,
+void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_entries, int max_depth, float2* gtab,
                              hipStream_t stream);
 // Cross-entropy statistics and sampling from a set of amplitudes (xeb.hip).
 uint64_t xeb_workspace_bytes(int64_t B);

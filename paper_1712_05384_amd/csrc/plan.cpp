@@ -461,6 +461,8 @@ qgm_status build_plan(const qgm_circuit* c, const int32_t* open, int32_t n_open,
     }
     if (opts.tree_exec < 0 || opts.tree_exec > 3) { *err = "tree_exec must be 0..3"; return QGM_E_INVALID; }
     if (opts.no_tile < 0 || opts.no_tile > 1) { *err = "no_tile must be 0 or 1"; return QGM_E_INVALID; }
+    if (opts.no_compose < 0 || opts.no_compose > 1) { *err = "no_compose must be 0 or 1"; return QGM_E_INVALID; }
+    if (opts.reserved0 != 0) { *err = "reserved0 must be 0"; return QGM_E_INVALID; }
     if (opts.order_finalists < 0 || opts.order_finalists > kTreeMaxFinalists) {
         *err = "order_finalists must be in [0, 64]";
         return QGM_E_INVALID;
@@ -777,7 +779,7 @@ static std::string tree_json(const Plan& p, int detail) {
         o << ",\"kg\":" << st.kg << ",\"level\":" << st.level << ",\"r_out\":" << st.out_axes.size()
           << ",\"n_in\":" << st.in_tensors.size() << ",\"gb\":" << st.gb() << ",\"sb\":" << st.sb()
           << ",\"n_factors\":" << st.n_factors() << ",\"g_off\":" << st.g_off
-          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows << ",\"tile\":" << st.tile << ",\"quad\":" << (st.quad ? 1 : 0)
+          << ",\"bytes_per_b\":" << tree_step_bytes(t, st) << ",\"unit_rows\":" << st.unit_rows << ",\"tile\":" << st.tile << ",\"quad\":" << (st.quad ? 1 : 0) << ",\"composed\":" << (st.composed ? 1 : 0)
           << ",\"table_leaf\":" << (st.table_leaf ? 1 : 0) << ",\"leaf_off\":" << st.leaf_off
           << ",\"issued_bytes_per_b\":" << 8 * st.n_tasks() * tree_unit_accesses(t, st);
         if (detail >= 1) {

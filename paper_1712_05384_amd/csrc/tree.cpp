@@ -538,6 +538,7 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
     std::set<int> gset;
     std::vector<int> sigq;
     std::vector<std::vector<std::pair<std::vector<int>, std::vector<int>>>> step_groups;   // (own vars, factors)
+    std::vector<int> step_of_tensor(static_cast<size_t>(T), -1);                             // step making each result
     double bytes = 0, flops = 0;
     for (size_t si = 0; si < rs.size(); ++si) {
         const RStep& st = rs[si];
@@ -573,6 +574,39 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
             t.tensor_axes[ts.out_tensor] = ts.gvars;
             ++t.n_table_leaves;
         }
+        // a bucket whose inputs are all leaf tables (Sec. V: its result depends on the bitstring only through
+        // the output bits its subtree reads): with few result and output bits, a leaf table too, built once for
+        // every value of those bits; its output bits are its own, then its inputs' others
+        if (p.n_slots == 0 && !st.open && !ts.table_leaf && !ts.in_tensors.empty() && !ts.out_axes.empty() &&
+            p.opts.no_compose == 0 && int(ts.in_tensors.size()) <= kTreeMaxIn && ts.kg <= kTreeMaxSum &&
+            ts.out_axes.size() <= 16) {
+            bool leaves = true;
+            std::vector<int> sig_all = sigq;
+            int depth = 0;
+            for (int ti : ts.in_tensors) {
+                const int ms = step_of_tensor[size_t(ti)];
+                if (ms < 0 || !t.steps[size_t(ms)].table_leaf || t.tensor_axes[size_t(ti)].size() > 16) {
+                    leaves = false;
+                    break;
+                }
+                depth = std::max(depth, t.steps[size_t(ms)].leaf_depth + 1);
+                for (int q : t.steps[size_t(ms)].sig_q)
+                    if (std::find(sig_all.begin(), sig_all.end(), q) == sig_all.end()) sig_all.push_back(q);
+            }
+            const int sb_all = int(sig_all.size());
+            if (leaves && sb_all <= kTreeComposeSig && int(ts.out_axes.size()) + sb_all <= kTreeComposeBits &&
+                int(ts.gvars.size()) + ts.kg + sb_all <= kTreeMaxGIndex) {
+                ts.table_leaf = true;
+                ts.composed = true;
+                ts.tile = 0;   // (no unit runs it; its axes keep the order chosen for its consumers)
+                ts.quad = false;
+                ts.leaf_depth = depth;
+                ts.level = -1;
+                t.tensor_made[ts.out_tensor] = -1;
+                ts.sig_q = sig_all;
+                ++t.n_table_leaves;
+            }
+        }
         step_groups.push_back({{std::vector<int>{}, st.facs}});
         for (auto& a : st.absorbed) step_groups.back().push_back(a);
         if (ts.out_axes.empty()) t.finals.push_back(ts.out_tensor);
@@ -583,7 +617,8 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
             if (t.tensor_made[ti] >= 0) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
         bytes += b;
         const int mult = int(ts.in_tensors.size()) + 1;
-        flops += rows * double(int64_t(1) << ts.vars.size()) * (6.0 * std::max(mult - 1, 0) + 2.0);
+        if (!ts.composed) flops += rows * double(int64_t(1) << ts.vars.size()) * (6.0 * std::max(mult - 1, 0) + 2.0);
+        step_of_tensor[size_t(ts.out_tensor)] = int(t.steps.size());
         t.steps.push_back(std::move(ts));
     }
     t.bytes_per_b = bytes;

@@ -1246,26 +1246,45 @@ void launch_tree_final_open(const int64_t* final_rows, int n_final, const TFacto
 // Leaf tables (plans without gate values, once): block (entry chunk, leaf).
 // R[o][s] = sum over the leaf's summed values w of its factor table
 // G[((o << k) | w) << sb | s], in FP64, rounded once.
-__global__ void __launch_bounds__(256) k_tree_leaf_tables(const TreeLeaf* __restrict__ leaves,
+__global__ void __launch_bounds__(256) k_tree_leaf_tables(const TreeLeaf* __restrict__ leaves, int depth,
                                                           float2* __restrict__ gtab) {
-    const TreeLeaf L = leaves[blockIdx.y];
+    const TreeLeaf& L = leaves[blockIdx.y];
+    if (L.depth != depth) return;
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (e >= (int64_t(1) << (L.r + L.sb))) return;
     const int64_t o = e >> L.sb, sg = e & ((int64_t(1) << L.sb) - 1);
+    int64_t g = o;
+    if (L.n_in > 0) {
+        g = 0;
+        for (int j = 0; j < L.gb; ++j) g |= ((o >> L.gpos[j]) & 1) << j;
+    }
     double2 acc = make_double2(0.0, 0.0);
     for (int64_t w = 0; w < (int64_t(1) << L.k); ++w) {
-        const float2 v = gtab[L.g_off + ((((o << L.k) | w) << L.sb) | sg)];
-        acc.x += v.x;
-        acc.y += v.y;
+        const float2 v = gtab[L.g_off + ((((g << L.k) | w) << L.sb) | sg)];
+        double2 term = make_double2(v.x, v.y);
+        for (int t = 0; t < L.n_in; ++t) {   // a composed leaf: its inputs' entries (FP64 products)
+            int64_t idx = 0;
+            for (int a = 0; a < L.in_na[t]; ++a) {
+                const int src = L.in_src[t][a];
+                idx |= (src >= 16 ? (w >> (src - 16)) & 1 : (o >> src) & 1) << a;
+            }
+            int64_t s = 0;
+            for (int b = 0; b < L.in_sb[t]; ++b) s |= ((sg >> L.in_spos[t][b]) & 1) << b;
+            const float2 x = gtab[L.in_off[t] + ((idx << L.in_sb[t]) | s)];
+            term = cmuld(term, make_double2(x.x, x.y));
+        }
+        acc.x += term.x;
+        acc.y += term.y;
     }
     gtab[L.leaf_off + e] = make_float2(float(acc.x), float(acc.y));
 }
 
-void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_entries, float2* gtab,
+void launch_tree_leaf_tables(const TreeLeaf* leaves, int n_leaves, int64_t max_entries, int max_depth, float2* gtab,
                              hipStream_t stream) {
     if (n_leaves <= 0) return;
-    hipLaunchKernelGGL(k_tree_leaf_tables, dim3(uint32_t((max_entries + 255) / 256), uint32_t(n_leaves)), dim3(256),
-                       0, stream, leaves, gtab);
+    for (int d = 0; d <= max_depth; ++d)   // a composed leaf reads leaves of smaller depth
+        hipLaunchKernelGGL(k_tree_leaf_tables, dim3(uint32_t((max_entries + 255) / 256), uint32_t(n_leaves)),
+                           dim3(256), 0, stream, leaves, d, gtab);
 }
 
 void launch_tree_prologue(const TreeProBlock* blocks, int n_blocks, const TreeGTab* gtabs, const TreeGroup* groups,

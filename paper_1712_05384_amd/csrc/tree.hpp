@@ -44,6 +44,11 @@ constexpr int kPersistMaxRanks = 256;           // work-groups per complex in on
 constexpr int kPersistSeen0 = 64;
 constexpr int kPersistFlags0 = kPersistSeen0 + kPersistXcds * kPersistMaxRanks;
 constexpr int kTreeLeafTableBits = 14;   // a leaf table has at most 2^14 entries (result bits + output bits)
+// A bucket whose inputs are all leaf tables becomes a leaf table too (built once for every value of the output
+// bits its subtree reads, instead of per bitstring) when its result bits plus those output bits are at most
+// this many and the output bits at most kTreeComposeSig.
+constexpr int kTreeComposeBits = 15;
+constexpr int kTreeComposeSig = 10;
 constexpr int kTreeMaxIn = 8;       // earlier results multiplied in one bucket
 constexpr int kTreeMaxSig = 12;     // output bits read by one bucket's factors
 constexpr int kTreeMaxGBits = 10;   // variables of a bucket's factor table besides v
@@ -145,6 +150,9 @@ struct TreeStep {
                                         //   table row per summed value (0: the general unit); 3 or 4: the
                                         //   32-row tile, unit bits 0, 1, 3 varying input 0 only and 2, 4
                                         //   input 1 only, from 8 + 4 (+ 1) rows and 1 entry per value
+    bool composed = false;              // a leaf table built from its inputs, which are leaf tables; its
+                                        //   sig_q lists its own output bits first, then its inputs' others
+    int leaf_depth = 0;                 // leaf tables: 0 without inputs, else 1 + the deepest input's
     bool quad = false;                  // a two-input 32-row tile whose result bits 5 and 6 vary input 1
                                         //   only: tasks 4m .. 4m + 3 read the same rows of input 0 and of
                                         //   the factor table, and run as one work-group that loads those

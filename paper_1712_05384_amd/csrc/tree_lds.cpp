@@ -113,8 +113,13 @@ void build_lds_program(TreePlan& t) {
     int64_t e = 0;
     std::vector<int64_t> tab_lds(t.steps.size(), -1);
     std::vector<std::vector<int>> gax(t.steps.size());
+    std::vector<char> read_by_job(static_cast<size_t>(T), 0);   // leaf tables some job reads (not only composed leaves)
+    for (const TreeStep& st : t.steps)
+        if (!st.table_leaf)
+            for (int tin : st.in_tensors) read_by_job[size_t(tin)] = 1;
     for (size_t i = 0; i < t.steps.size(); ++i) {
         const TreeStep& st = t.steps[i];
+        if (st.table_leaf && !read_by_job[size_t(st.out_tensor)]) continue;
         const int64_t n = st.table_leaf ? (int64_t(1) << st.out_axes.size()) : (int64_t(1) << (st.gb() + st.kg));
         if (P.tables0 + e + n > kLdsMaxComplex) return fail("factor tables exceed the LDS of a work-group");
         if (int(P.stages.size()) >= kLdsMaxStages) return fail("more than 256 tables");

@@ -24,8 +24,14 @@ def _table_area(info, gate_vals):
     """The table area as the device builds it, as a dict offset -> value:
     bucket s's factor table at g_off, entry (c << sb) | sigma with
     c = (g << kg) | w, and a leaf bucket's result table at leaf_off, entry
-    (o << sb) | sigma with o over the result's axes in the planner's order."""
+    (o << sb) | sigma with o over the result's axes in the planner's order.  A
+    composed leaf (inputs all leaf tables) sums over w its factor table times
+    its inputs' tables, read at the entries its result index, w and output
+    bits select (its output bits are its own, then its inputs' others)."""
     area = {}
+    tensors = info["tensors"]
+    maker = {st["out_tensor"]: st for st in info["buckets"]}
+    leaf = {}   # leaf tables as arrays [2^r, 2^sb], by result
     for st in info["buckets"]:
         G = bucket_table(st, gate_vals)             # [2^(gb + kg), 2^sb]
         sb, kg = st["sb"], st["kg"]
@@ -34,13 +40,33 @@ def _table_area(info, gate_vals):
                 for sg in range(G.shape[1]):
                     area[st["g_off"] + (c << sb) + sg] = G[c, sg]
             continue
-        gpos = {v: j for j, v in enumerate(st["gvars"])}
-        for o in range(1 << st["r_out"]):
-            g = 0
-            for j, ax in enumerate(st["out_axes"]):
-                g |= ((o >> j) & 1) << gpos[ax]
+        out_axes = st["out_axes"]
+        r = st["r_out"]
+        O = np.arange(1 << r)[:, None]
+        SG = np.arange(1 << sb)[None, :]
+        g = np.zeros_like(O)
+        for j, ax in enumerate(st["gvars"]):
+            g |= ((O >> out_axes.index(ax)) & 1) << j
+        R = np.zeros((1 << r, 1 << sb), dtype=np.complex128)
+        for w in range(1 << kg):
+            term = G[(g << kg) | w, SG]
+            if st.get("composed", 0):
+                for tin in st["in_tensors"]:
+                    mk = maker[tin]
+                    idx = np.zeros_like(O)
+                    for a, ax in enumerate(tensors[tin]["axes"]):
+                        bit = ((O >> out_axes.index(ax)) & 1) if ax in out_axes else \
+                            np.full_like(O, (w >> st["vars"].index(ax)) & 1)
+                        idx |= bit << a
+                    s_t = np.zeros_like(SG)
+                    for b, q in enumerate(mk["sig_q"]):
+                        s_t |= ((SG >> st["sig_q"].index(q)) & 1) << b
+                    term = term * leaf[tin][idx, s_t]
+            R = R + term
+        leaf[st["out_tensor"]] = R
+        for o in range(1 << r):
             for sg in range(1 << sb):
-                area[st["leaf_off"] + (o << sb) + sg] = sum(G[(g << kg) | w, sg] for w in range(1 << kg))
+                area[st["leaf_off"] + (o << sb) + sg] = R[o, sg]
     return area
 
 

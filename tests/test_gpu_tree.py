@@ -52,7 +52,7 @@ def test_tree_c1_full_batch():
     got = _amps(_tree(c), bits)
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     assert np.abs(got - ref).max() <= TOL * 2 ** (-c.n / 2)
-    p1 = _tree(c, order_restarts=16, order_finalists=1)
+    p1 = _tree(c, order_restarts=16, order_finalists=1, compose=False)   # (composed leaves take that bucket)
     info = p1.info(1)
     assert any(bk["tile"] and bk["level"] >= info["tail_start"] for bk in info["buckets"])
     _say("case tree c1_4x4_d16 B=64 order_finalists=1")
@@ -281,7 +281,7 @@ def test_tree_tail_reads_leaf_tables(rows, cols, depth, seed):
     """Buckets of the last levels (run from LDS in one work-group per group)
     whose inputs include leaf tables read from the table area."""
     c = C.random_grid_circuit(rows, cols, depth, seed)
-    p = _tree(c, tree_exec=1)
+    p = _tree(c, tree_exec=1, compose=False)   # (composed leaves take those buckets)
     assert _tail_table_inputs(p.info(1)) > 0
     bits = C.random_bitstrings(c.n, 130, seed)
     _say("case tree tail leaf tables %s" % c.name)

@@ -46,7 +46,7 @@ def test_c3_sliced_against_stored_oracle():
 
 @pytest.mark.parametrize("B,chunked", [(100, False), (1024, False), (1024, True)])
 def test_c3_bucket_quad_tiles_against_stored_oracle(B, chunked):
-    """5x6 depth 30 on the bucket path (level launches), whose three two-input
+    """5x6 depth 30 on the bucket path (level launches), whose two-input
     32-row tile buckets run as quad tiles (four tasks per work-group sharing
     one input's rows through LDS): a ragged batch of 100 (2 groups of 64, one
     work-group per block of tasks), the full 1024 (8 and more groups, blocks
@@ -59,7 +59,7 @@ def test_c3_bucket_quad_tiles_against_stored_oracle(B, chunked):
     kw = dict(min_sliced_vars=2) if chunked else {}
     p = Q.plan(c, ordering=1, tree_exec=1, out_c128=True, **kw)
     info = p.info(1)
-    assert sum(bk["quad"] for bk in info["buckets"]) >= 3 and sum(info["level_quad"]) > 0
+    assert sum(bk["quad"] for bk in info["buckets"]) >= 2 and sum(info["level_quad"]) > 0
     got = p.amplitudes(bits[:B]).cpu().numpy()[:, 0]
     err = np.abs(got - ref).max() * 2 ** (c.n / 2)
     _say("  max err * 2^(n/2) = %.3g" % err)

@@ -239,12 +239,16 @@ def test_tree_plan_is_deterministic_and_consistent():
     assert a["absorbed_buckets"] == sum(len(s["groups"]) - 1 for s in a["buckets"]) > 0
     assert a["n_free"] == len(a["order"])
     assert abs(sum(s["bytes_per_b"] for s in a["buckets"]) - a["bytes_per_amp"]) < 1e-6 * a["bytes_per_amp"]
-    # every result is read by exactly one later bucket or by the final product
+    # every result is read by exactly one later bucket or by the final product; a composed leaf table
+    # (built with the plan) reads leaf tables only
     readers = [0] * len(a["tensors"])
     for s in a["buckets"]:
         for t in s["in_tensors"]:
             readers[t] += 1
-            assert a["tensors"][t]["made"] < s["level"]
+            if s["level"] >= 0:
+                assert a["tensors"][t]["made"] < s["level"]
+            else:
+                assert s["composed"] and a["tensors"][t]["made"] == -1
     for t in a["finals"]:
         readers[t] += 1
     assert readers == [1] * len(a["tensors"])
@@ -437,12 +441,26 @@ def test_tree_plan_open_bucket_chain():
 def test_tree_plan_leaf_tables():
     """Buckets without inputs of a circuit without gate values become tables
     over (result index, output bits), built with the plan, with no level of
-    their own; a circuit with gate values keeps them as buckets."""
+    their own, and so do buckets whose inputs are all such tables when their
+    result and output bits are few (composed leaves: their output bits are
+    their own, then their inputs' others); a circuit with gate values keeps
+    them as buckets."""
     c, bits = C.workload("c2_5x5_d25")
     info = Q.plan(c, ordering=1).info(1)
     leaves = [b for b in info["buckets"] if b["table_leaf"]]
     assert info["table_leaves"] == len(leaves) > 0
-    assert all(b["level"] == -1 and b["n_in"] == 0 for b in leaves)
+    assert all(b["level"] == -1 for b in leaves)
+    tens = info["tensors"]
+    maker = {b["out_tensor"]: b for b in info["buckets"]}
+    composed = [b for b in leaves if b["composed"]]
+    assert composed and all(b["n_in"] == 0 for b in leaves if not b["composed"])
+    for b in composed:
+        assert all(maker[t]["table_leaf"] for t in b["in_tensors"])
+        sig = set(b["sig_q"])
+        assert all(set(maker[t]["sig_q"]) <= sig for t in b["in_tensors"])
+        assert b["r_out"] + len(sig) <= 15 and len(sig) <= 10
+    off = Q.plan(c, ordering=1, compose=False).info(1)
+    assert not any(b["composed"] for b in off["buckets"]) and off["n_levels"] > info["n_levels"]
     assert min(b["level"] for b in info["buckets"] if not b["table_leaf"]) == 0
     got = run_tree_plan(info, None, bits[:16])
     assert np.abs(got - oracle.sv_amplitudes(c.n, c.gates, None, bits[:16])).max() < 1e-12
@@ -531,7 +549,7 @@ def test_quad_tiles_planned():
     info = Q.plan(c, ordering=1, tree_exec=1).info(1)
     tensors, bks = info["tensors"], info["buckets"]
     quads = [bk for bk in bks if bk["quad"]]
-    assert len(quads) >= 4 and {bk["level"] for bk in quads} >= {6}
+    assert len(quads) >= 4 and max(bk["r_out"] for bk in quads) >= 17
     for bk in quads:
         ins, out = bk["in_tensors"], bk["out_axes"]
         assert bk["tile"] == 3 and bk["n_in"] == 2 and bk["r_out"] >= 10
@@ -555,7 +573,7 @@ def test_tile_in_tail_and_option_validation():
     units reading and writing the tail's LDS); an invalid no_tile value is rejected."""
     import paper_1712_05384_amd as Q
     c, _ = C.workload("c1_4x4_d16")
-    info = Q.plan(c, ordering=1, order_restarts=16, order_finalists=1).info(1)
+    info = Q.plan(c, ordering=1, order_restarts=16, order_finalists=1, compose=False).info(1)
     assert any(bk["tile"] and bk["level"] >= info["tail_start"] for bk in info["buckets"])
     cs, keep = Q.api._circuit_struct(c.rows, c.cols, c.gates, 0)
     opts = N.QgmPlanOpts()
@@ -582,15 +600,17 @@ def test_bucket_workspace_uses_power_of_two_pitch():
 def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     """Plans with tile units (inputs reordered, tile bits lowest; the 5x5 depth-25
     plan of the first order by symbolic cost among 16 restarts per criterion has a
-    three-input tile) and without,
-    for the chosen order and the first one, run by the interpreter, against the
-    state vector."""
+    three-input tile; without composed leaf tables, which take the small tile
+    buckets of these circuits) and without,
+    for the chosen order and the first one, with and without composed leaves,
+    run by the interpreter, against the state vector."""
     import paper_1712_05384_amd as Q
     from tree_interp import run_tree_plan
     c = C.random_grid_circuit(rows, cols, depth, seed)
     kinds = set()
     for fin in (0, 1):
-        kinds |= {bk["tile"] for bk in Q.plan(c, ordering=1, order_restarts=16 * fin, order_finalists=fin).info(1)["buckets"]}
+        kinds |= {bk["tile"] for bk in Q.plan(c, ordering=1, order_restarts=16 * fin, order_finalists=fin,
+                                              compose=False).info(1)["buckets"]}
     assert kinds & {1, 2, 3, 4}
     if (rows, cols, depth, seed) == (5, 5, 25, 201):
         assert 2 in kinds
@@ -598,8 +618,10 @@ def test_tile_plans_random_circuits_interpreted(rows, cols, depth, seed):
     ref = oracle.sv_amplitudes(c.n, c.gates, None, bits)
     for fin in (0, 1):
         for tile in (True, False):
-            got = run_tree_plan(Q.plan(c, ordering=1, tile=tile, order_restarts=16 * fin, order_finalists=fin).info(1), None, bits)
-            assert np.abs(got - ref).max() < 1e-12
+            for compose in (True, False):
+                got = run_tree_plan(Q.plan(c, ordering=1, tile=tile, order_restarts=16 * fin, order_finalists=fin,
+                                           compose=compose).info(1), None, bits)
+                assert np.abs(got - ref).max() < 1e-12
 
 
 # --- the LDS-resident program (tree_exec 3) -------------------------------------------------

@@ -186,7 +186,7 @@ typedef struct {
                                   exceed the budget */
     int32_t no_compose;        /* ordering 1 only: 1 = only buckets without inputs become leaf tables; 0 = a
                                   bucket whose inputs are all leaf tables, whose result bits plus the output
-                                  bits of its subtree are at most 15 (those output bits at most 10), becomes
+                                  bits of its subtree are at most 18 (those output bits at most 10), becomes
                                   a leaf table too: its result depends on the bitstring only through those
                                   bits, so it is built once with the plan for all their values (Sec. V:
                                   reuse across bitstrings) and read at each bitstring's bits.  Circuits

@@ -47,7 +47,7 @@ constexpr int kTreeLeafTableBits = 14;   // a leaf table has at most 2^14 entrie
 // A bucket whose inputs are all leaf tables becomes a leaf table too (built once for every value of the output
 // bits its subtree reads, instead of per bitstring) when its result bits plus those output bits are at most
 // this many and the output bits at most kTreeComposeSig.
-constexpr int kTreeComposeBits = 15;
+constexpr int kTreeComposeBits = 18;
 constexpr int kTreeComposeSig = 10;
 constexpr int kTreeMaxIn = 8;       // earlier results multiplied in one bucket
 constexpr int kTreeMaxSig = 12;     // output bits read by one bucket's factors

@@ -136,7 +136,7 @@ def test_tree_c2_full_size_and_vertical_agreement():
     assert err <= TOL * 2 ** (-c.n / 2)
     vert = _amps(Q.plan(c), bits)
     assert np.abs(vert - got).max() <= TOL * 2 ** (-c.n / 2)
-    p1 = _tree(c, order_restarts=16, order_finalists=1)
+    p1 = _tree(c, order_restarts=16, order_finalists=1, compose=False)   # (composed leaves take the tile)
     assert any(bk["tile"] == 2 for bk in p1.info(1)["buckets"])
     _say("case tree c2_5x5_d25 B=1024 order_finalists=1")
     got1 = _amps(p1, bits)
@@ -370,7 +370,7 @@ def test_tree_tile_units_ragged_batches_c128(B):
     complex128 output, and a circuit with gate values whose plan has tiles."""
     import paper_1712_05384_amd as Q
     c = C.random_grid_circuit(4, 5, 20, 2)
-    p = Q.plan(c, ordering=1, out_c128=True, tree_exec=1)
+    p = Q.plan(c, ordering=1, out_c128=True, tree_exec=1, compose=False)   # (composed leaves take the tiles)
     assert any(bk["tile"] for bk in p.info(1)["buckets"])
     bits = C.random_bitstrings(c.n, B, 40 + B)
     _say("case tree tiles ragged B=%d c128" % B)

@@ -458,7 +458,7 @@ def test_tree_plan_leaf_tables():
         assert all(maker[t]["table_leaf"] for t in b["in_tensors"])
         sig = set(b["sig_q"])
         assert all(set(maker[t]["sig_q"]) <= sig for t in b["in_tensors"])
-        assert b["r_out"] + len(sig) <= 15 and len(sig) <= 10
+        assert b["r_out"] + len(sig) <= 18 and len(sig) <= 10
     off = Q.plan(c, ordering=1, compose=False).info(1)
     assert not any(b["composed"] for b in off["buckets"]) and off["n_levels"] > info["n_levels"]
     assert min(b["level"] for b in info["buckets"] if not b["table_leaf"]) == 0

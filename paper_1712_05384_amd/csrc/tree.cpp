@@ -613,8 +613,12 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
         if (st.open) t.open_tensor = ts.out_tensor;   // the chain's last bucket comes last
         const double rows = double(int64_t(1) << ts.out_axes.size());
         double b = ts.table_leaf ? 0.0 : 8.0 * rows;   // a leaf table is read from the caches, not per bitstring
-        for (int ti : ts.in_tensors)
-            if (t.tensor_made[ti] >= 0) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
+        for (int ti : ts.in_tensors) {
+            // a composed leaf table is read at each bitstring's own output bits: one slice per bitstring
+            const int ms = step_of_tensor[size_t(ti)];
+            const bool sliced = !ts.table_leaf && ms >= 0 && t.steps[size_t(ms)].composed;
+            if (t.tensor_made[ti] >= 0 || sliced) b += 8.0 * double(int64_t(1) << t.tensor_axes[ti].size());
+        }
         bytes += b;
         const int mult = int(ts.in_tensors.size()) + 1;
         if (!ts.composed) flops += rows * double(int64_t(1) << ts.vars.size()) * (6.0 * std::max(mult - 1, 0) + 2.0);
@@ -685,10 +689,10 @@ static qgm_status finalize_tree(const Plan& p, const Model& m, const std::vector
 double tree_step_bytes(const TreePlan& t, const TreeStep& st) {
     if (st.table_leaf) return 0.0;   // built once with the plan
     std::vector<char> tab(t.tensor_axes.size(), 0);
-    for (const TreeStep& s : t.steps)
-        if (s.table_leaf) tab[s.out_tensor] = 1;
+    for (const TreeStep& s : t.steps)   // a plain leaf table is a few KiB shared by every bitstring (cache-resident);
+        if (s.table_leaf && !s.composed) tab[s.out_tensor] = 1;   // a composed one is read in per-bitstring slices
     double b = 8.0 * double(int64_t(1) << st.out_axes.size());
-    for (int tid : st.in_tensors)   // a leaf table is a few KiB shared by every bitstring (cache-resident)
+    for (int tid : st.in_tensors)
         if (!tab[tid]) b += 8.0 * double(int64_t(1) << t.tensor_axes[tid].size());
     return b;
 }

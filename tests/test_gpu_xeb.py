@@ -34,7 +34,8 @@ def test_xeb_sums_match_oracle(n, B, c128, zeros):
     assert np.allclose(got, ref, rtol=1e-11, atol=0), (got, ref)
 
 
-@pytest.mark.parametrize("B,m,c128", [(1, 5, False), (1000, 10_000, False), (300_000, 100_000, True)])
+@pytest.mark.parametrize("B,m,c128", [(1, 5, False), (1000, 10_000, False), (300_000, 100_000, True),
+                                      ((1 << 22) + 12_345, 20_000, False)])   # chunks of two scan tiles
 def test_sample_set_matches_oracle(B, m, c128):
     import paper_1712_05384_amd as Q
     a = C.random_amplitudes(20, B, 7 + B, zeros=min(B - 1, 11))

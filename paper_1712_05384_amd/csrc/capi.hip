@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <sstream>
 #include <new>
@@ -686,8 +687,10 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     for (auto& d : P->p.dev)
         if (d.device == dev) { *base = static_cast<char*>(d.base); return QGM_OK; }
-    std::string host(P->total, '\0');
-    char* h = &host[0];
+    // zero-filled host image (calloc: the pages of the areas built on the device are never touched here)
+    std::unique_ptr<char, void (*)(void*)> img(static_cast<char*>(std::calloc(P->total, 1)), std::free);
+    if (!img) return fail(QGM_E_OOM, "host memory for the plan's tables");
+    char* h = img.get();
     fixed_matrices(reinterpret_cast<double2*>(h + P->off_fixed));
     if (P->p.is_tree) {
         if (!fill_tree_tables(P, h)) return fail(QGM_E_INTERNAL, "bucket task records overlap, leave gaps or exceed the tail kernel's LDS arrays");
@@ -697,9 +700,20 @@ qgm_status device_tables(qgm_plan_t* P, char** base) {
     void* d = nullptr;
     e = hipMalloc(&d, P->total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
-    e = hipMemcpy(d, h, P->total, hipMemcpyHostToDevice);
-    if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "hipMemcpy(plan tables)"); }
-    if (P->p.is_tree && P->p.n_slots == 0) {
+    // a bucket plan without gate values builds its factor tables and the LDS launch's staged copy on the
+    // device below: those areas are zeroed there, the records around them copied
+    const bool built = P->p.is_tree && P->p.n_slots == 0;
+    const size_t zero[2][2] = {{P->off_tg, P->off_ttasks_all}, {P->off_lz, P->off_status}};
+    size_t from = 0;
+    for (int r = 0; r <= (built ? 2 : 0) && e == hipSuccess; ++r) {
+        const size_t to = built && r < 2 ? zero[r][0] : P->total;
+        if (to > from) e = hipMemcpy(static_cast<char*>(d) + from, h + from, to - from, hipMemcpyHostToDevice);
+        if (built && r < 2 && e == hipSuccess && zero[r][1] > zero[r][0])
+            e = hipMemset(static_cast<char*>(d) + zero[r][0], 0, zero[r][1] - zero[r][0]);
+        if (built && r < 2) from = zero[r][1];
+    }
+    if (e != hipSuccess) { (void)hipFree(d); return hip_fail(e, "uploading the plan tables"); }
+    if (built) {
         // the factor tables of a circuit without gate values depend only on the plan: build them once
         char* b = static_cast<char*>(d);
         qgm::launch_tree_prologue(reinterpret_cast<const qgm::TreeProBlock*>(b + P->off_tpro),

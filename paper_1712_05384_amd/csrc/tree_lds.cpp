@@ -47,6 +47,49 @@ int64_t relayout(int64_t i, const std::vector<int>& to, const std::vector<int>& 
     return o;
 }
 
+// Orders the jobs [j0, j1) of one level for the kernel's fixed assignment (wave
+// w takes the level's jobs w, w + W, w + 2W, ...): longest first, each to the
+// least loaded wave that still takes a job in the assignment (waves 0 .. m - 1
+// take one more than the rest when W does not divide the count), then the
+// jobs in pass order.  The cost of a job is its loads per lane (rows per lane
+// x (inputs + table) x summed values) plus a fixed part for the record and
+// the lane offsets.
+void order_level_jobs(LdsProgram& P, int32_t j0, int32_t j1, int W) {
+    const int n = j1 - j0;
+    if (n <= W) return;   // one pass: every job on a wave of its own
+    auto cost = [&](int32_t j) {
+        const LdsJob& jb = P.jobs[size_t(j)];
+        return 16 + (1 << jb.rl) * (jb.nin + 1) * (1 << jb.k);
+    };
+    std::vector<int32_t> idx;
+    for (int32_t j = j0; j < j1; ++j) idx.push_back(j);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    const int full = n / W, extra = n % W;
+    std::vector<std::vector<int32_t>> wave(static_cast<size_t>(W));
+    std::vector<int64_t> load(static_cast<size_t>(W), 0);
+    for (int32_t j : idx) {
+        int best = -1;
+        for (int w = 0; w < W; ++w) {
+            const int cap = full + (w < extra ? 1 : 0);
+            if (int(wave[size_t(w)].size()) < cap && (best < 0 || load[size_t(w)] < load[size_t(best)])) best = w;
+        }
+        wave[size_t(best)].push_back(j);
+        load[size_t(best)] += cost(j);
+    }
+    std::vector<LdsJob> jobs;
+    std::vector<int32_t> bucket;
+    for (int pass = 0; pass <= full; ++pass)
+        for (int w = 0; w < W; ++w)
+            if (pass < int(wave[size_t(w)].size())) {
+                jobs.push_back(P.jobs[size_t(wave[size_t(w)][size_t(pass)])]);
+                bucket.push_back(P.job_bucket[size_t(wave[size_t(w)][size_t(pass)])]);
+            }
+    for (int i = 0; i < n; ++i) {
+        P.jobs[size_t(j0 + i)] = jobs[size_t(i)];
+        P.job_bucket[size_t(j0 + i)] = bucket[size_t(i)];
+    }
+}
+
 }  // namespace
 
 void build_lds_program(TreePlan& t) {
@@ -255,6 +298,7 @@ void build_lds_program(TreePlan& t) {
                 P.job_bucket.push_back(sid);
             }
         }
+        order_level_jobs(P, P.level_job_off.back(), int32_t(P.jobs.size()), int(n_waves));
         P.level_job_off.push_back(int32_t(P.jobs.size()));
     }
     for (int f : t.finals) {

@@ -2,6 +2,7 @@
 semantics checked against the oracle through a CPU interpreter, slicing,
 open qubits, error handling and the exported C-ABI symbols."""
 import ctypes
+import itertools
 import os
 import re
 
@@ -678,6 +679,41 @@ def test_lds_program_limits():
     with pytest.raises(N.QgmError) as ei:
         Q.plan(big, ordering=1, tree_exec=3)
     assert ei.value.status == N.QGM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("wl", ["c2_5x5_d25", "c5_5x5_d24", "c5_6x6_d24", "c5_4x5_d20"])
+def test_lds_jobs_balanced_over_waves(wl):
+    """The kernel gives wave w the jobs w, w + W, ... of a level; the planner
+    orders each level's jobs so that the heaviest wave (cost: loads per lane
+    plus a fixed part) stays within the list-scheduling bound of the mean load
+    plus one job, and every level still covers each bucket's rows once."""
+    c, _ = C.workload(wl)
+    info = Q.plan(c, ordering=1).info(2)
+    L = info["lds"]
+    W = info["lds_threads"] // 64
+    off = L["level_job_off"]
+    cost = lambda j: 16 + (1 << j["rl"]) * (j["nin"] + 1) * (1 << j["k"])
+    for lv in range(len(off) - 1):
+        jobs = L["jobs"][off[lv]:off[lv + 1]]
+        load = [0] * W
+        for i, j in enumerate(jobs):
+            load[i % W] += cost(j)
+        if jobs:
+            assert max(load) <= sum(load) / W + max(cost(j) for j in jobs)
+        if W < len(jobs) <= 8:   # small levels: the best split the assignment allows, by brute force
+            n, full, extra = len(jobs), len(jobs) // W, len(jobs) % W
+            cap = [full + (w < extra) for w in range(W)]
+            best = None
+            for asg in itertools.product(range(W), repeat=n):
+                if all(asg.count(w) == cap[w] for w in range(W)):
+                    m = max(sum(cost(jobs[i]) for i in range(n) if asg[i] == w) for w in range(W))
+                    best = m if best is None else min(best, m)
+            assert max(load) == best, (wl, lv, load, best)
+        rows = {}
+        for j in jobs:   # rows per bucket: 64 << rl per job (fewer lanes for buckets under 64 rows)
+            rows[j["bucket"]] = rows.get(j["bucket"], 0) + j["lanes"] * (1 << j["rl"])
+        for b, n in rows.items():
+            assert n == 1 << info["buckets"][b]["r_out"], (wl, lv, b)
 
 
 # ---- slicing of bucket plans (Sec. V outlook: space-time tradeoffs) ----------

@@ -550,7 +550,8 @@ def _sec_xeb(Q, C, torch, np, stream, args, out):
                   "xeb_frac_of_hbm": round(8 * nx / (ms_x / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                   "sample_set_ms": round(ms_s, 4),
                   "note": "workspace and outputs allocated once, outside the timing; each call is timed from Python "
-                          "(its launches and the binding included); the XEB kernels are bound by the FP64 logarithm"}
+                          "(its launches and the binding included); the XEB partial kernel is bound by its FP64 logarithm "
+                          "chains (one round of 4 waves per SIMD), not by its reads"}
     print(f"# xeb: {ms_x:.3f} ms, sample_set: {ms_s:.3f} ms", file=sys.stderr, flush=True)
 
 

@@ -45,7 +45,7 @@ MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
     ("c2_5x5_d25", 1): {"bytes_per_launch": 12430049.3, "source": "tree.hip", "sha256_16": "50fd2ea026f0b985",
                         "plan": {"bytes_per_amp": 41096, "level_launches": 5}},
-    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 6717849.6, "source": "tree_lds.hip", "sha256_16": "37b2ea1941df5ce9",
+    ("c2_5x5_d25", "lds"): {"bytes_per_launch": 6717849.6, "source": "tree_lds.hip", "sha256_16": "371a4a84ae1b6d6a",
                             "plan": {"lds_entries": 3540, "lds_jobs": 16, "lds_threads": 256}},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"

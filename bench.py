@@ -40,13 +40,14 @@ LDS_HEADER = 4 * 256 + 16   # LDS bytes before the data of the LDS-resident laun
 # HBM bytes per dominant-kernel launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
 # plain 1 GiB copy gives), valid for the kernel source with this hash and the
-# plan with these figures.
+# plan with these figures; for the LDS launch also its SQ_INSTS_VALU per wave.
 MEASURED_TRAFFIC = {
     ("c2_5x5_d25", 0): {"bytes_per_launch": 226794653.4, "source": "kernels.hip", "sha256_16": "a72736aaae65f038"},
     ("c2_5x5_d25", 1): {"bytes_per_launch": 12430049.3, "source": "tree.hip", "sha256_16": "50fd2ea026f0b985",
                         "plan": {"bytes_per_amp": 41096, "level_launches": 5}},
     ("c2_5x5_d25", "lds"): {"bytes_per_launch": 6717849.6, "source": "tree_lds.hip", "sha256_16": "371a4a84ae1b6d6a",
-                            "plan": {"lds_entries": 3540, "lds_jobs": 16, "lds_threads": 256}},
+                            "plan": {"lds_entries": 3540, "lds_jobs": 16, "lds_threads": 256},
+                            "valu_per_wave": 694},
 }
 METRIC = "amplitudes/sec at max err vs FP64 oracle; % FP32-MFMA/HBM roofline; grad/sec"
 
@@ -292,6 +293,14 @@ def dominant_kernel(args, p, info, B, elim_ms, kernels, tree_exec=0):
                 roofline["traffic"] = round(rec["bytes_per_launch"] / t / 1e9, 2)
                 roofline["traffic_bytes_per_launch"] = rec["bytes_per_launch"]
                 roofline["traffic_unit"] = "GB/s of HBM"
+                vi = rec.get("valu_per_wave")
+                if vi:   # the vector-ALU issue floor from the same record's SQ_INSTS_VALU count
+                    waves_per_simd = B * (info["lds_threads"] // 64) / (4 * 256)
+                    floor_s = vi * 4 * waves_per_simd / 2.4e9
+                    roofline["valu_issue"] = {"instructions_per_wave": vi, "floor_ms": round(floor_s * 1e3, 5),
+                                              "frac": round(floor_s / t, 3),
+                                              "note": "4 cycles per wave64 instruction on a SIMD, 1024 SIMDs "
+                                                      "at 2.4 GHz, every wave of the launch"}
         return roofline, cfg
     if info["ordering"] == 1:
         kernel = ("k_tree_level + k_tree_tail (bucket elimination: one launch per elimination-tree level, "
